@@ -1,0 +1,377 @@
+"""Pins for the CPU oracle (brute force O1, elimination O2, plan following O3).
+
+Each pin comes from outside the oracle: values the paper prints (golden file,
+cited), closed forms from combinatorics, an independent transfer-matrix count,
+or agreement between the three independent oracle programs.
+"""
+import json
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+SEMIRINGS = ["tropical", "counting_tropical", "count", "partition"]
+
+
+def fib(n):
+    a, b = 0, 1
+    for _ in range(n):
+        a, b = b, a + b
+    return a
+
+
+def lucas(n):
+    a, b = 2, 1
+    for _ in range(n):
+        a, b = b, a + b
+    return a
+
+
+# ----------------------------------------------------------- paper pins ---
+
+def test_petersen_paper_values_brute_force():
+    g = gg.petersen()
+    p = GOLD["petersen"]
+    r = oracle.brute_force(g, [0.0], sets_cap=16)
+    assert r["size_max"] == p["size_max"]["value"]
+    assert [r["size_max"], r["count_max"]] == p["counting_max"]["value"]
+    assert r["count_all"] == p["counting_all"]["value"]
+    poly = p["independence_polynomial"]["value"]
+    assert r["poly"][: len(poly)] == poly and not any(r["poly"][len(poly):])
+    # CountingMax(2): the two largest sizes and their counts
+    c2 = p["counting_max_2"]["value"]
+    assert {str(k): r["poly"][k] for k in (3, 4)} == c2
+    # the five maximum sets, character k <-> vertex k-1
+    printed = {sum(1 << i for i, ch in enumerate(s) if ch == "1") for s in p["max_sets"]["value"]}
+    assert set(r["max_sets"]) == printed
+
+
+@pytest.mark.parametrize("sr", SEMIRINGS)
+def test_petersen_paper_values_elimination(sr):
+    g = gg.petersen()
+    p = GOLD["petersen"]
+    r = oracle.eliminate(g, sr, beta=0.7)
+    poly = p["independence_polynomial"]["value"]
+    if sr == "tropical":
+        assert r["size"] == p["size_max"]["value"]
+    elif sr == "counting_tropical":
+        assert [r["size"], r["count"]] == p["counting_max"]["value"]
+    elif sr == "count":
+        assert r["count"] == p["counting_all"]["value"]
+    else:
+        # unit weights: Z(beta) is the independence polynomial at x = e^beta
+        want = sum(c * math.exp(0.7 * k) for k, c in enumerate(poly))
+        assert r["z"] == pytest.approx(want, rel=1e-14)
+
+
+@pytest.mark.slow
+def test_square20_partition_function_matches_paper():
+    """Z(beta=0) of the 20x20 grid printed in Float64 in Sec. 5.1."""
+    want = GOLD["square20"]["partition_beta0"]["value"]
+    r = oracle.eliminate(gg.square_lattice(20), "partition", 0.0, max_width=21)
+    # the paper's Float64 contraction carries its own rounding; 1e-14 is ~50 ulp
+    assert abs(r["z"] - want) / want < 1e-14
+
+
+def _transfer_matrix_count(L):
+    """Independent sets of the L x L grid by rows: a row is a mask with no two
+    adjacent ones, consecutive rows must not share a one."""
+    rows = [s for s in range(1 << L) if s & (s >> 1) == 0]
+    v = {s: 1 for s in rows}
+    for _ in range(L - 1):
+        v = {t: sum(c for s, c in v.items() if s & t == 0) for t in rows}
+    return sum(v.values())
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 5, 8, 10])
+def test_square_lattice_counts_transfer_matrix(L):
+    g = gg.square_lattice(L)
+    assert oracle.eliminate(g, "count")["count"] == _transfer_matrix_count(L)
+
+
+def test_square2_label_invariant_facts():
+    # Sec. 3.2 example: the 4-cycle has 7 independent sets, 2 of size 2
+    g = gg.cycle(4)
+    r = oracle.brute_force(g)
+    assert r["count_all"] == GOLD["square2"]["count_all"]["value"]
+    assert (r["size_max"], r["count_max"]) == (2.0, 2)
+
+
+# --------------------------------------------------------- closed forms ---
+
+@pytest.mark.parametrize("n", list(range(1, 21)))
+def test_path_fibonacci(n):
+    g = gg.path(n)
+    r = oracle.brute_force(g)
+    assert r["count_all"] == fib(n + 2)
+    assert r["size_max"] == (n + 1) // 2
+    assert r["count_max"] == (n // 2 + 1 if n % 2 == 0 else 1)
+    assert oracle.eliminate(g, "count")["count"] == fib(n + 2)
+
+
+@pytest.mark.parametrize("n", list(range(3, 21)))
+def test_cycle_lucas(n):
+    g = gg.cycle(n)
+    r = oracle.brute_force(g)
+    assert r["count_all"] == lucas(n)
+    assert r["size_max"] == n // 2
+    assert r["count_max"] == (2 if n % 2 == 0 else n)
+    e = oracle.eliminate(g, "counting_tropical")
+    assert (e["size"], e["count"]) == (n // 2, 2 if n % 2 == 0 else n)
+
+
+def test_long_path_exact_count_beyond_int64():
+    # F_{302} needs ~208 bits: exercises the 256-bit counts of O2
+    g = gg.path(300)
+    assert oracle.eliminate(g, "count")["count"] == fib(302)
+
+
+def test_count_overflow_flagged():
+    # F_{402} needs ~278 bits > 256: must be reported, not wrapped silently
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.eliminate(gg.path(400), "count")
+    assert ei.value.code == oracle.ORC_EOVERFLOW
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_complete_graph(n):
+    r = oracle.brute_force(gg.complete(n))
+    assert (r["count_all"], r["size_max"], r["count_max"]) == (n + 1, 1.0, n)
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 16])
+def test_empty_graph(n):
+    g = gg.empty(n)
+    r = oracle.brute_force(g, [0.3])
+    assert (r["count_all"], r["size_max"], r["count_max"]) == (2 ** n, float(n), 1)
+    assert r["z"][0] == pytest.approx((1 + math.exp(0.3)) ** n, rel=1e-15)
+    for sr in SEMIRINGS:
+        oracle.eliminate(g, sr)  # nv = 0 and isolated vertices are valid
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (4, 4), (3, 7)])
+def test_complete_bipartite(a, b):
+    r = oracle.brute_force(gg.complete_bipartite(a, b))
+    assert r["count_all"] == 2 ** a + 2 ** b - 1
+    assert r["size_max"] == max(a, b)
+    assert r["count_max"] == (2 if a == b else 1)
+
+
+def test_weighted_closed_forms():
+    beta = 0.9
+    w = gg.dyadic_weights(12, seed=3)
+    # empty graph: Z = prod (1 + e^{beta w}), max = sum of weights
+    g = gg.empty(12).with_weights(w)
+    r = oracle.brute_force(g, [beta])
+    assert r["z"][0] == pytest.approx(np.prod(1 + np.exp(beta * w.astype(np.float64))), rel=1e-14)
+    assert r["size_max"] == pytest.approx(float(np.sum(w.astype(np.float64))), abs=0)
+    # complete graph: Z = 1 + sum e^{beta w}, max = max w
+    g = gg.complete(12).with_weights(w)
+    r = oracle.brute_force(g, [beta])
+    assert r["z"][0] == pytest.approx(1 + np.sum(np.exp(beta * w.astype(np.float64))), rel=1e-14)
+    assert r["size_max"] == float(w.max())
+    # star: centre alone, or any subset of the leaves
+    g = gg.star(9).with_weights(w[:10])
+    wd = w[:10].astype(np.float64)
+    for sr in ("partition",):
+        z = oracle.eliminate(g, sr, beta)["z"]
+        assert z == pytest.approx(math.exp(beta * wd[0]) + np.prod(1 + np.exp(beta * wd[1:])), rel=1e-14)
+    t = oracle.eliminate(g, "tropical")["size"]
+    assert t == max(wd[0], wd[1:].sum())
+
+
+def test_disjoint_union_multiplies_counts_and_adds_sizes():
+    g, h = gg.random_regular(10, 3, 1), gg.cycle(7)
+    u = gg.disjoint_union(g, h)
+    rg, rh, ru = (oracle.brute_force(x, [0.4]) for x in (g, h, u))
+    assert ru["count_all"] == rg["count_all"] * rh["count_all"]
+    assert ru["size_max"] == rg["size_max"] + rh["size_max"]
+    assert ru["count_max"] == rg["count_max"] * rh["count_max"]
+    assert ru["z"][0] == pytest.approx(rg["z"][0] * rh["z"][0], rel=1e-14)
+
+
+def test_tropical_is_zero_temperature_limit_of_log_z():
+    # reading of Sec. 5.2: ln Z(beta) - beta * SizeMax -> ln(count at max)
+    g = gg.random_regular(16, 3, 4).with_weights(gg.integer_weights(16, 4))
+    r = oracle.brute_force(g, [40.0])
+    assert r["log_z"][0] - 40.0 * r["size_max"] == pytest.approx(math.log(r["count_max"]), abs=1e-9)
+
+
+def test_partition_at_beta_zero_is_count():
+    g = gg.random_regular(18, 3, 9)
+    r = oracle.brute_force(g, [0.0])
+    assert r["z"][0] == r["count_all"]
+    assert oracle.eliminate(g, "partition", 0.0)["z"] == r["count_all"]
+
+
+# --------------------------------------------------- O2 against O1 -------
+
+def _random_graphs(count):
+    out = []
+    for s in range(count):
+        kind = s % 4
+        if kind == 0:
+            g = gg.random_regular(2 * (4 + s % 6), 3, s)
+        elif kind == 1:
+            g = gg.gnp(8 + s % 9, 0.15 + 0.05 * (s % 5), s)
+        elif kind == 2:
+            g = gg.kings_subgraph(4, 0.8, s)
+        else:
+            g = gg.gnp(6 + s % 10, 0.4, s)
+        if s % 3 == 1:
+            g = g.with_weights(gg.dyadic_weights(g.nv, s))
+        elif s % 3 == 2:
+            g = g.with_weights(gg.integer_weights(g.nv, s, 1, 3))
+        out.append(g)
+    return out
+
+
+def test_elimination_matches_brute_force_on_200_graphs():
+    beta = 1.3
+    for g in _random_graphs(200):
+        bf = oracle.brute_force(g, [beta])
+        t = oracle.eliminate(g, "tropical")
+        ct = oracle.eliminate(g, "counting_tropical")
+        c = oracle.eliminate(g, "count")
+        z = oracle.eliminate(g, "partition", beta)
+        assert t["size"] == bf["size_max"], g.name
+        assert (ct["size"], ct["count"]) == (bf["size_max"], bf["count_max"]), g.name
+        assert c["count"] == bf["count_all"], g.name
+        assert z["z"] == pytest.approx(bf["z"][0], rel=1e-13), g.name
+
+
+# --------------------------------------------------- O3 plan following ---
+
+def leaves_of(g, absorb):
+    """Leaf factor lists: one per edge, one per vertex (or vertex tensors
+    folded into the first incident edge when absorb is set)."""
+    leaves = [[e] for e in range(g.ne)]
+    first = {}
+    for e, (u, v) in enumerate(g.edges.tolist()):
+        first.setdefault(u, e)
+        first.setdefault(v, e)
+    for v in range(g.nv):
+        if absorb and v in first:
+            leaves[first[v]].append(-v - 1)
+        else:
+            leaves.append([-v - 1])
+    return leaves
+
+
+def random_tree(g, seed, absorb=False, nsliced=0):
+    """A random binary contraction tree in the oracle's plan format."""
+    rng = random.Random(seed)
+    leaves = leaves_of(g, absorb)
+    edges = g.edges.tolist()
+
+    def scope(fs):
+        s = set()
+        for f in fs:
+            s.update(edges[f] if f >= 0 else [-f - 1])
+        return s
+
+    counts = [dict.fromkeys(scope(fs), 1) for fs in leaves]
+    total = {}
+    for c in counts:
+        for k in c:
+            total[k] = total.get(k, 0) + 1
+
+    def open_of(c):
+        return sorted(k for k, n in c.items() if n < total[k])
+
+    indices = [open_of(c) for c in counts]
+    live = list(range(len(leaves)))
+    left, right = [], []
+    while len(live) > 1:
+        a, b = rng.sample(live, 2)
+        live.remove(a)
+        live.remove(b)
+        c = dict(counts[a])
+        for k, n in counts[b].items():
+            c[k] = c.get(k, 0) + n
+        counts.append(c)
+        indices.append(open_of(c))
+        left.append(a)
+        right.append(b)
+        live.append(len(counts) - 1)
+    sliced = rng.sample(range(g.nv), nsliced) if nsliced else []
+    return {"leaf_factors": leaves, "left": left, "right": right, "indices": indices, "sliced": sliced}
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_follow_plan_random_trees_match_brute_force(seed):
+    g = [gg.random_regular(12, 3, seed), gg.kings_subgraph(3, 0.9, seed), gg.gnp(11, 0.3, seed)][seed % 3]
+    if seed % 2:
+        g = g.with_weights(gg.dyadic_weights(g.nv, seed))
+    tree = random_tree(g, seed, absorb=bool(seed % 4 >= 2), nsliced=seed % 3)
+    bf = oracle.brute_force(g, [0.8])
+    assert oracle.follow_plan(g, tree, "tropical")["size"] == bf["size_max"]
+    ct = oracle.follow_plan(g, tree, "counting_tropical")
+    assert (ct["size"], ct["count"]) == (bf["size_max"], bf["count_max"])
+    assert oracle.follow_plan(g, tree, "count")["count"] == bf["count_all"]
+    assert oracle.follow_plan(g, tree, "partition", 0.8)["z"] == pytest.approx(bf["z"][0], rel=1e-13)
+
+
+def _paper_square_tree():
+    """The TreeSA tree printed in Sec. 4.1, in the oracle's plan format."""
+    t = GOLD["square2"]["tree"]
+    code = t["eincode"]
+    # graph vertices 1..4 -> 0..3; edges in the EinCode's order
+    edges = [tuple(sorted((a - 1, b - 1))) for a, b in code[:4]]
+    g = gg.Graph(4, np.array(edges, np.int32), None, "square2")
+    leaf_names = ["L:" + "∘".join(map(str, c)) for c in code]
+    leaf_factors = [[e] for e in range(4)] + [[-v - 1] for v in range(4)]
+    nodes = {n.get("id", "root"): n for n in t["nodes"]}
+    ids = {name: i for i, name in enumerate(leaf_names)}
+    order = ["N6", "N5", "N4", "N3", "N2", "N1", "root"]
+    for k, name in enumerate(order):
+        ids[name] = len(leaf_names) + k
+    left, right, inner_out = [], [], []
+    for name in order:
+        a, b = nodes[name]["children"]
+        left.append(ids[a])
+        right.append(ids[b])
+        inner_out.append(sorted(x - 1 for x in nodes[name]["out"]))
+    leaf_out = [sorted(x - 1 for x in c) for c in code]
+    tree = {"leaf_factors": leaf_factors, "left": left, "right": right,
+            "indices": leaf_out + inner_out, "sliced": []}
+    return g, tree
+
+
+def test_follow_plan_on_the_papers_printed_tree():
+    g, tree = _paper_square_tree()
+    assert oracle.follow_plan(g, tree, "count")["count"] == 7
+    ct = oracle.follow_plan(g, tree, "counting_tropical")
+    assert (ct["size"], ct["count"]) == (2.0, 2)
+
+
+def test_follow_plan_rejects_a_wrong_output_list():
+    # plant a mistake in the plan: keep an index open after its last use
+    g = gg.cycle(5)
+    tree = random_tree(g, 1)
+    bad = dict(tree)
+    bad["indices"] = [list(x) for x in tree["indices"]]
+    bad["indices"][-2] = sorted(set(bad["indices"][-2]) | {0, 1, 2, 3, 4})
+    with pytest.raises(oracle.OracleError):
+        oracle.follow_plan(g, bad, "count")
+    bad2 = dict(tree)
+    bad2["leaf_factors"] = tree["leaf_factors"][:-1] + [tree["leaf_factors"][0]]
+    with pytest.raises(oracle.OracleError):
+        oracle.follow_plan(g, bad2, "count")
+
+
+def test_follow_plan_slicing_every_subset_agrees():
+    g = gg.random_regular(10, 3, 5).with_weights(gg.dyadic_weights(10, 5))
+    base = random_tree(g, 3)
+    ref = oracle.follow_plan(g, base, "counting_tropical")
+    for k in range(1, 5):
+        t = dict(base)
+        t["sliced"] = list(range(k))
+        r = oracle.follow_plan(g, t, "counting_tropical")
+        assert r == ref
