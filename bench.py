@@ -1,0 +1,166 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = the three contractions of the 3-regular n=120 workload (seeded
+random 3-regular graph, unit weights, TreeSA order): max independent-set size
+in int32 max-plus, exact independent-set count (uint64 lane + residues mod
+three primes + a check prime, CRT), and the partition function at x = 1 in
+float32 with per-tensor power-of-two exponents.  Inputs (leaf data, plan
+tables) are resident on the device before timing; planning is host-side and
+untimed.
+
+Prints one JSON line:
+  value        semiring GOP/s = (3 x 2^tc) / seconds per step, tc the plan's
+               time complexity (Sec. 4.1: product of index dimensions summed
+               over the binary contractions)
+  roofline     the dominant kernel (largest share of measured device time),
+               its algorithmic ops or bytes per launch over its average
+               launch duration, against the MI355X peak of its bound
+  cpu_baseline the CPU oracle producing the same three results, timed on the
+               host cores
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the VALU issue model of each GEMM inner loop
+HBM_GBS = 8000.0
+CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
+LANE_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0  # 39.3 T 32-bit lane instructions/s
+# VALU instructions per semiring op in the register-tiled inner loop (from the
+# compiled gfx950 code: see DESIGN.md, "Kernels and their rooflines")
+INSTR_PER_OP = {0: 1.5, 1: 1.5, 2: 10.0, 3: 4.0, 4: 7.0, 5: 1.0, 6: 1.0}
+SR_NAME = {0: "tropical_i32", 1: "tropical_f32", 2: "counting_tropical", 3: "count_exact", 4: "partition_f32",
+           5: "partition_bf16"}
+
+
+def build_workload(seed: int = 0, n: int = 120):
+    import graphgen as gg
+    import paper_2501_00227_amd as tn
+
+    g = gg.random_regular(n, 3, seed)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, method="treesa", ntrials=8, niters=20, seed=seed)
+    return g, net, plan
+
+
+STEP = (("tropical_i32", 0.0), ("count_exact", 0.0), ("partition_f32", 0.0))
+
+
+def run_step(ctx, net, plan):
+    return [ctx.solve(net, plan, sr, beta=b) for sr, b in STEP]
+
+
+def dominant_kernel(recs):
+    """Group launch records by (kind, algebra); pick the group with most time."""
+    groups = {}
+    for r in recs:
+        key = (r["kind"], r["semiring"])
+        g = groups.setdefault(key, {"ms": 0.0, "n": 0, "ops": 0.0, "bytes": 0.0})
+        g["ms"] += r["ms"]
+        g["n"] += 1
+        g["ops"] += r["ops"]
+        g["bytes"] += r["alg_bytes"]
+    key = max(groups, key=lambda k: groups[k]["ms"])
+    return key, groups[key], groups
+
+
+def cpu_baseline(g, ops_per_step):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.eliminate(g, "tropical")
+    oracle.eliminate(g, "count")
+    oracle.eliminate(g, "partition", 0.0)
+    dt = time.perf_counter() - t0
+    return {"value": ops_per_step / dt / 1e9, "unit": "GOP/s", "cores": 1, "kind": "oracle",
+            "sample": "one full step (the same three results) by the oracle's variable elimination, "
+                      "single-threaded; work counted as the GPU plan's 3 x 2^tc semiring ops",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path shards by slices and jobs with one final "
+              "(+)-reduction of a scalar root, which this build does not run; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2501_00227_amd as tn
+
+    torch.cuda.set_device(0)
+    g, net, plan = build_workload(args.seed)
+    tc, sc, rwc = plan.complexity()
+    ctx = tn.Context(0)
+    for _ in range(args.warmup):
+        run_step(ctx, net, plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = run_step(ctx, net, plan)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ops_per_step = len(STEP) * 2.0 ** tc
+    value = ops_per_step / dt / 1e9
+
+    # one profiled step: HIP events around every launch on the context stream
+    ctx.set_profiling(True)
+    run_step(ctx, net, plan)
+    recs = ctx.profile(clear=True)
+    ctx.set_profiling(False)
+    (kind, sr), grp, groups = dominant_kernel(recs)
+    avg_ms = grp["ms"] / grp["n"]
+    if kind in ("gemm", "gemm_mfma"):
+        achieved = grp["ops"] / grp["n"] / (avg_ms * 1e-3) / 1e12
+        peak = LANE_TOPS / INSTR_PER_OP.get(sr, 1.0)
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                "frac": achieved / peak, "traffic": None}
+    else:
+        achieved = grp["bytes"] / grp["n"] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_GBS, "traffic": None}
+    roof["kernel"] = f"{kind}/{SR_NAME.get(sr, sr)}"
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches"] = grp["n"]
+    roof["share_of_device_time"] = grp["ms"] / sum(x["ms"] for x in groups.values())
+
+    out = {
+        "metric": "semiring GOP/s & % roofline at largest intermediate; batched solves/s + p50/p99",
+        "value": value,
+        "unit": "GOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+u64+u32+f32",
+        "data": "synthetic",
+        "config": {"workload": "3-regular n=120 seed %d, unit weights: tropical int32 + exact count (CRT) + "
+                               "Z(x=1) fp32" % args.seed,
+                   "tc_log2": tc, "sc_log2": sc, "rwc_log2": rwc},
+        "roofline": roof,
+        "results": {"size_max": res[0]["size"], "count_all": str(res[1]["count"]), "log_z": res[2]["log_z"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, ops_per_step)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,330 @@
+/*
+ * tn.h -- C ABI of the MI355X (gfx950) generic tensor-network library.
+ *
+ * The library solves the independent-set problem by contracting its tensor
+ * network over a semiring, following "Programming guide for solving
+ * constraint satisfaction problems with tensor networks" (arXiv 2501.00227):
+ *
+ *   graph + weights  --tn_net_independent_set-->  network      (Sec. 3.2)
+ *   network          --tn_plan_create-->          contraction tree, slicing
+ *                                                 (Sec. 4.1 complexity, Sec. 4.2 optimizers)
+ *   network + plan   --tn_solve-->                solution-space property
+ *                                                 (Sec. 5.1 solve, Sec. 5 property table)
+ *
+ * plus a batched form (many networks in one persistent launch) and a server
+ * form (continuous batching with HBM-budget admission).
+ *
+ * Conventions for every call:
+ *   - Every function that can fail returns tn_status; nothing aborts and no
+ *     C++ exception crosses this boundary.  tn_last_error() returns a
+ *     thread-local text for the last failure on the calling thread.
+ *   - Vertex ids are 0-based (the paper's Julia ids are 1-based).
+ *   - Input arrays are owned by the caller and copied during the call.
+ *     Handles (tn_ctx, tn_net, tn_plan, tn_server) are owned by the library
+ *     until the matching *_destroy.  Results are plain structs written into
+ *     caller memory.
+ *   - A tn_ctx is used by one thread at a time; tn_server_* calls are
+ *     thread-safe.
+ *   - Device memory comes from the context's allocator callbacks (for
+ *     example PyTorch's caching allocator), or from hipMallocAsync on the
+ *     context stream when no allocator is given.
+ */
+#ifndef TN_H_
+#define TN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TN_OK = 0,
+    TN_EINVAL = -1,     /* invalid argument (bad graph, options, handle) */
+    TN_ENOMEM = -2,     /* host or device allocation failed */
+    TN_EDEVICE = -3,    /* a HIP runtime call failed */
+    TN_EOVERFLOW = -4,  /* exact count exceeds the CRT range (check residue disagrees) */
+    TN_ETOOBIG = -5,    /* plan needs more device memory than allowed */
+    TN_EBUSY = -6,      /* server queue full */
+    TN_ECANCELED = -7   /* job cancelled or server shut down before it ran */
+} tn_status;
+
+/* Element algebra of the contraction (Sec. 5 property table).
+ *   TN_TROPICAL_I32      SizeMax     max-plus over int32, -inf = INT32_MIN with
+ *                                    saturating add; integer weights only
+ *   TN_TROPICAL_F32      SizeMax     max-plus over float32, -inf = -INFINITY
+ *   TN_COUNTING_TROPICAL CountingMax (int32 size, uint64 count): larger size wins,
+ *                                    equal sizes add counts; the count is exact
+ *                                    modulo 2^64; integer weights only
+ *   TN_COUNT_EXACT       CountingAll counts in Z/2^64 plus residues modulo primes
+ *                                    below 2^31, recombined by CRT into an exact
+ *                                    integer (Z(beta=0) of Sec. 3.1)
+ *   TN_PARTITION_F32     PartitionFunction(beta): float32 values, one power-of-two
+ *                                    exponent per intermediate tensor
+ *   TN_PARTITION_BF16    as above with bfloat16-rounded GEMM inputs, float32
+ *                                    accumulation (error reported, not bounded) */
+typedef enum {
+    TN_TROPICAL_I32 = 0,
+    TN_TROPICAL_F32 = 1,
+    TN_COUNTING_TROPICAL = 2,
+    TN_COUNT_EXACT = 3,
+    TN_PARTITION_F32 = 4,
+    TN_PARTITION_BF16 = 5
+} tn_semiring;
+
+typedef struct tn_ctx tn_ctx;
+typedef struct tn_net tn_net;
+typedef struct tn_plan tn_plan;
+typedef struct tn_server tn_server;
+
+/* Device allocator callbacks.  alloc returns a device pointer (256-byte
+ * aligned) or NULL; both are called on the thread that calls the library,
+ * with the context stream. */
+typedef void* (*tn_alloc_fn)(size_t bytes, void* user, void* stream);
+typedef void (*tn_free_fn)(void* ptr, size_t bytes, void* user, void* stream);
+typedef struct {
+    tn_alloc_fn alloc;
+    tn_free_fn free;
+    void* user;
+} tn_allocator;
+
+/* ------------------------------------------------------------- context --- */
+
+/* Create a context on HIP device `device`.  stream: a hipStream_t to run on
+ * (NULL: the context creates its own default-priority stream).  alloc: NULL
+ * uses hipMallocAsync/hipFreeAsync on that stream.  Errors: TN_EINVAL for a
+ * bad device, TN_EDEVICE if HIP fails. */
+tn_status tn_ctx_create(int device, void* stream, const tn_allocator* alloc, tn_ctx** out);
+void tn_ctx_destroy(tn_ctx* ctx);
+const char* tn_last_error(void);
+
+/* Per-launch profiling.  When enabled, every kernel the context launches is
+ * bracketed by HIP events recorded on the stream it runs on; records hold the
+ * kernel kind, the tree node, the measured duration and the algorithmic work
+ * of that launch (bytes of operands read + result written, and semiring ops
+ * = product of the node's index dimensions, Sec. 4.1 tc/rwc).  Records are
+ * kept until read or cleared. */
+typedef enum {
+    TN_K_LEAF = 0,      /* leaf tensor initialisation */
+    TN_K_PERMUTE = 1,   /* operand transpose into GEMM layout */
+    TN_K_GEMM = 2,      /* batched semiring GEMM (VALU) */
+    TN_K_GEMM_MFMA = 3, /* batched GEMM on matrix cores (partition function) */
+    TN_K_ACCUM = 4,     /* slice accumulation / root handling */
+    TN_K_BATCH = 5      /* persistent batched launch */
+} tn_kernel_kind;
+
+typedef struct {
+    int32_t kind;       /* tn_kernel_kind */
+    int32_t node;       /* inner-node index, -1 if none */
+    int32_t semiring;   /* tn_semiring */
+    int32_t shape[4];   /* GEMM: log2 batch, M, N, K; permute: rank, 0, 0, 0 */
+    float ms;           /* measured duration */
+    double alg_bytes;   /* algorithmic bytes of the launch */
+    double ops;         /* semiring ops of the launch (GEMM) */
+} tn_kernel_record;
+
+tn_status tn_ctx_set_profiling(tn_ctx* ctx, int enabled);
+/* Copy up to cap records; *n receives the number available.  Synchronises the
+ * context stream.  clear != 0 drops the records afterwards. */
+tn_status tn_ctx_profile(tn_ctx* ctx, tn_kernel_record* recs, int32_t cap, int32_t* n, int clear);
+tn_status tn_ctx_synchronize(tn_ctx* ctx);
+
+/* ------------------------------------------------------------- network --- */
+
+/* Independent-set network of a graph (Sec. 3.2): one index per vertex, an
+ * edge tensor B = [[1,1],[1,0]] per edge and a vertex tensor W = [1, x^w_v]
+ * per vertex, where 1 and 0 are the multiplicative and additive identities of
+ * the chosen algebra and x^w is w (tropical) or e^{beta w} (real).
+ *   nv      number of vertices (>= 0)
+ *   ne      number of edges (>= 0); edges: 2*ne vertex ids, pair e = (u, v)
+ *   weights nv floats, or NULL for unit weights
+ * Duplicate edges are merged (edge ids follow the first occurrence).  Errors: TN_EINVAL for self-loops, ids out of
+ * range, non-finite weights, nv > 4096. */
+tn_status tn_net_independent_set(int32_t nv, int32_t ne, const int32_t* edges,
+                                 const float* weights, tn_net** out);
+void tn_net_destroy(tn_net* net);
+/* Sizes after de-duplication. */
+tn_status tn_net_info(const tn_net* net, int32_t* nv, int32_t* ne);
+
+/* ---------------------------------------------------------------- plan --- */
+
+/* Options of the contraction-order optimizers (Sec. 4.2).
+ *   method 0 GreedyMethod: cost size(Ti*Tj) - alpha (size(Ti) + size(Tj));
+ *            temperature > 0 samples pairs by e^{-cost/T} (hyper-greedy);
+ *            best of nrepeat runs.
+ *   method 1 TreeSA: greedy start, then simulated annealing over the four
+ *            tree rotations with cost tc + sc_weight * max(0, sc - sc_target)
+ *            + rw_weight * rwc (all log2), Metropolis acceptance, inverse
+ *            temperatures beta_start:beta_step:beta_stop, niters sweeps per
+ *            temperature, best of ntrials (trials run on host threads).
+ *   nslices  upper bound on sliced indices; indices are sliced (Sec. 4.2)
+ *            while sc > sc_target.  0 = never slice.
+ *   absorb_vertices  fold each vertex tensor into one incident edge tensor
+ *            (same result, fewer leaves). */
+typedef struct {
+    int32_t method;
+    double alpha;
+    double temperature;
+    int32_t nrepeat;
+    uint64_t seed;
+    double sc_target;
+    double sc_weight;
+    double rw_weight;
+    double beta_start;
+    double beta_step;
+    double beta_stop;
+    int32_t ntrials;
+    int32_t niters;
+    int32_t nslices;
+    int32_t absorb_vertices;
+    int32_t nthreads; /* host threads for TreeSA trials; 0 = hardware count */
+} tn_plan_opts;
+
+/* Defaults: greedy alpha 0, T 0, nrepeat 10 (Sec. 4.2.1); TreeSA sc_target 20,
+ * betas 0.01:0.05:15, ntrials 10, niters 50, sc_weight 1, rw_weight 0.2
+ * (Sec. 4.2.2); no slicing; vertices absorbed. */
+void tn_plan_opts_default(tn_plan_opts* opts);
+
+tn_status tn_plan_create(const tn_net* net, const tn_plan_opts* opts, tn_plan** out);
+
+/* A plan from an explicit binary tree (e.g. the tree printed in Sec. 4.1).
+ * Leaves 0..nleaf-1 hold the factors fac[fac_off[l] .. fac_off[l+1]) where a
+ * code c >= 0 is edge c and c < 0 is the vertex tensor of vertex -c-1; every
+ * factor appears exactly once.  Inner node t (id nleaf+t) has children
+ * left[t], right[t] with smaller ids; the last node is the root.  Output
+ * indices follow the einsum rule (an index stays open while it occurs outside
+ * the subtree).  sliced: nsliced vertex ids fixed per slice.  TN_EINVAL if the
+ * tree is not a valid binary tree over all factors. */
+tn_status tn_plan_from_tree(const tn_net* net, int32_t nleaf, const int32_t* fac_off,
+                            const int32_t* fac, int32_t ninner, const int32_t* left,
+                            const int32_t* right, int32_t nsliced, const int32_t* sliced,
+                            tn_plan** out);
+
+/* Contraction complexity of the plan (Sec. 4.1): tc = log2 of the total
+ * number of semiring operations (product of all index dimensions at each
+ * binary contraction, times 2^nsliced), sc = log2 of the largest intermediate
+ * (entries, per slice), rwc = log2 of the total entries read and written. */
+tn_status tn_plan_complexity(const tn_plan* plan, double* tc_log2, double* sc_log2,
+                             double* rwc_log2);
+
+typedef struct {
+    int32_t nleaf;
+    int32_t ninner;
+    int32_t nsliced;
+    int32_t max_rank;        /* sc as an integer */
+    double tc_log2, sc_log2, rwc_log2;
+    uint64_t arena_entries;  /* live-entry peak of the memory plan, per slice */
+    int32_t npermutes;       /* operand permutes the executor will run per slice */
+} tn_plan_info_t;
+tn_status tn_plan_info(const tn_plan* plan, tn_plan_info_t* info);
+
+/* Device bytes one tn_solve of this plan needs in the given algebra (arena of
+ * live intermediates, permute scratch, leaves and bookkeeping). */
+tn_status tn_plan_peak_bytes(const tn_plan* plan, tn_semiring semiring, uint64_t* bytes);
+
+/* Export the tree in the format of tn_plan_from_tree, plus the ordered output
+ * indices of every node (leaves first).  Call with NULL arrays to get the
+ * sizes: *nfac, *nidx.  idx_off has nleaf+ninner+1 entries. */
+tn_status tn_plan_export(const tn_plan* plan, int32_t* nleaf, int32_t* ninner, int32_t* nfac,
+                         int32_t* nidx, int32_t* nsliced, int32_t* fac_off, int32_t* fac,
+                         int32_t* left, int32_t* right, int32_t* idx_off, int32_t* idx,
+                         int32_t* sliced);
+void tn_plan_destroy(tn_plan* plan);
+
+/* Complexity of the unordered (flat) einsum of a network: one node over all
+ * indices (Sec. 4.1, the EinCode before optimize_code). */
+tn_status tn_net_flat_complexity(const tn_net* net, double* tc_log2, double* sc_log2,
+                                 double* rwc_log2);
+
+/* --------------------------------------------------------------- solve --- */
+
+typedef struct {
+    int32_t semiring;          /* tn_semiring */
+    double beta;               /* inverse temperature for TN_PARTITION_* (x = e^beta) */
+    int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime
+                                  (0 = default 4: three CRT primes + one check) */
+    const uint32_t* primes;    /* NULL = default primes (largest primes below 2^31) */
+    int32_t slice_begin;       /* run slices [slice_begin, slice_end) only; */
+    int32_t slice_end;         /* 0,0 = all slices */
+} tn_solve_opts;
+
+void tn_solve_opts_default(tn_solve_opts* opts);
+
+/* Result of one contraction (a 0-dimensional tensor, Sec. 5.1).
+ *   Tropical:  size_i32 / size_f32; size_is_neg_inf when no configuration
+ *              exists (cannot happen for independent sets, kept for slices).
+ *   Counting tropical: size_i32 and count_mod_2_64.
+ *   Exact count: count_mod_2_64, residues[] (one per prime), count_limbs
+ *              (little-endian 32-bit limbs of the exact integer from CRT,
+ *              count_nlimbs of them); TN_EOVERFLOW if the check prime
+ *              disagrees with the CRT value.
+ *   Partition function: Z = z_mant * 2^z_exp2 (z_mant in [1,2) or 0),
+ *              log_z = ln Z, z = Z as a double (inf if above DBL_MAX). */
+typedef struct {
+    int32_t semiring;
+    int32_t size_i32;
+    float size_f32;
+    int32_t size_is_neg_inf;
+    uint64_t count_mod_2_64;
+    uint32_t residues[8];
+    uint32_t primes[8];
+    int32_t nresidues;
+    uint32_t count_limbs[16];
+    int32_t count_nlimbs;
+    double z_mant;
+    int64_t z_exp2;
+    double log_z;
+    double z;
+    double seconds;            /* wall time of the call */
+} tn_result;
+
+/* Contract the network along the plan on the context's stream and wait for
+ * the root.  Errors: TN_EINVAL (semiring needs integer weights, plan built
+ * for another network), TN_ENOMEM (allocator returned NULL), TN_EDEVICE,
+ * TN_EOVERFLOW (exact count). */
+tn_status tn_solve(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts,
+                   tn_result* out);
+
+/* Many networks in one persistent launch: a device task table of
+ * (job, node, tile) entries with dependency counters; workgroups pop ready
+ * tiles until every job's root is done.  Tile shapes come from the
+ * autotuner table keyed by each job's own shapes, so a job's result does not
+ * depend on the other jobs in the batch.  n jobs; opts and out have n
+ * entries.  Jobs must not be sliced.  Per-job failures are reported in
+ * out[i].semiring = -1 and the call returns the first failure. */
+tn_status tn_solve_batch(tn_ctx* ctx, int32_t n, const tn_net* const* nets,
+                         const tn_plan* const* plans, const tn_solve_opts* opts, tn_result* out);
+
+/* -------------------------------------------------------------- server --- */
+
+/* Continuous-batching server on one context.  Jobs are admitted while the sum
+ * of their device bytes (tn_plan_peak_bytes) stays within hbm_budget_bytes and
+ * fewer than max_slots run; admitted jobs are merged into the next persistent
+ * launch while earlier launches may still run; each job's latency is
+ * result-on-host minus submit time.  The server owns a scheduler thread. */
+tn_status tn_server_create(tn_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
+                           tn_server** out);
+/* Thread-safe.  The net and plan must stay alive until the job is done.
+ * TN_ETOOBIG if the job alone exceeds the budget. */
+tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
+                           const tn_solve_opts* opts, uint64_t* job_id);
+/* Thread-safe.  *done = 1 once the result is on the host. */
+tn_status tn_server_poll(tn_server* s, uint64_t job_id, tn_result* out, int32_t* done,
+                         double* latency_s);
+/* Block until all submitted jobs are done. */
+tn_status tn_server_drain(tn_server* s);
+
+typedef struct {
+    uint64_t submitted, completed, failed, launches;
+    uint64_t peak_admitted_bytes;   /* never above the budget */
+    int32_t peak_running;
+} tn_server_stats_t;
+tn_status tn_server_stats(tn_server* s, tn_server_stats_t* st);
+tn_status tn_server_destroy(tn_server* s); /* drains first */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H_ */

@@ -1,0 +1,354 @@
+// extern "C" entry points (include/tn.h).  No exception crosses this file:
+// every call is wrapped and reports a tn_status plus a thread-local message.
+#include <atomic>
+#include <new>
+
+#include "exec.h"
+
+namespace tn {
+const char* last_error_cstr();
+}
+
+using namespace tn;
+
+#define TN_GUARD_BEGIN try {
+#define TN_GUARD_END                                        \
+    }                                                       \
+    catch (const std::bad_alloc&) {                         \
+        return fail(TN_ENOMEM, "host allocation failed");   \
+    }                                                       \
+    catch (const std::exception& e) {                       \
+        return fail(TN_EINVAL, e.what());                   \
+    }                                                       \
+    catch (...) {                                           \
+        return fail(TN_EINVAL, "unexpected internal error"); \
+    }
+
+static std::atomic<uint64_t> g_plan_uid{1};
+
+extern "C" {
+
+const char* tn_last_error(void) { return last_error_cstr(); }
+
+tn_status tn_ctx_create(int device, void* stream, const tn_allocator* alloc, tn_ctx** out) {
+    TN_GUARD_BEGIN
+    if (!out) return fail(TN_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(TN_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(TN_EINVAL, "device id out of range");
+    if (hipSetDevice(device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    auto* c = new tn_ctx();
+    c->device = device;
+    if (alloc) {
+        if (!alloc->alloc || !alloc->free) {
+            delete c;
+            return fail(TN_EINVAL, "allocator needs alloc and free");
+        }
+        c->alloc = *alloc;
+        c->has_alloc = true;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(TN_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return TN_OK;
+    TN_GUARD_END
+}
+
+void tn_ctx_destroy(tn_ctx* c) {
+    if (!c) return;
+    try {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        for (auto& kv : c->progs) dev_free(c, kv.second.buf, kv.second.bytes);
+        (void)hipStreamSynchronize(c->stream);
+        for (auto& pr : c->pending) {
+            (void)hipEventDestroy(pr.start);
+            (void)hipEventDestroy(pr.stop);
+        }
+        for (auto e : c->event_pool) (void)hipEventDestroy(e);
+        if (c->pinned) (void)hipHostFree(c->pinned);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    } catch (...) {
+    }
+    delete c;
+}
+
+tn_status tn_ctx_set_profiling(tn_ctx* c, int enabled) {
+    if (!c) return fail(TN_EINVAL, "ctx is NULL");
+    c->profiling = enabled != 0;
+    return TN_OK;
+}
+
+tn_status tn_ctx_synchronize(tn_ctx* c) {
+    if (!c) return fail(TN_EINVAL, "ctx is NULL");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(TN_EDEVICE, "hipStreamSynchronize failed");
+    return TN_OK;
+}
+
+tn_status tn_ctx_profile(tn_ctx* c, tn_kernel_record* recs, int32_t cap, int32_t* n, int clear) {
+    TN_GUARD_BEGIN
+    if (!c || !n) return fail(TN_EINVAL, "ctx or n is NULL");
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(TN_EDEVICE, "hipStreamSynchronize failed");
+    for (auto& pr : c->pending) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, pr.start, pr.stop);
+        pr.rec.ms = ms;
+        c->records.push_back(pr.rec);
+        c->event_pool.push_back(pr.start);
+        c->event_pool.push_back(pr.stop);
+    }
+    c->pending.clear();
+    *n = (int32_t)c->records.size();
+    if (recs)
+        for (int32_t k = 0; k < cap && k < *n; k++) recs[k] = c->records[k];
+    if (clear) c->records.clear();
+    return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_net_independent_set(int32_t nv, int32_t ne, const int32_t* edges, const float* weights,
+                                 tn_net** out) {
+    TN_GUARD_BEGIN
+    if (!out) return fail(TN_EINVAL, "out is NULL");
+    *out = nullptr;
+    auto* n = new tn_net();
+    tn_status st = make_net(nv, ne, edges, weights, n->net);
+    if (st != TN_OK) {
+        delete n;
+        return st;
+    }
+    *out = n;
+    return TN_OK;
+    TN_GUARD_END
+}
+
+void tn_net_destroy(tn_net* n) { delete n; }
+
+tn_status tn_net_info(const tn_net* n, int32_t* nv, int32_t* ne) {
+    if (!n) return fail(TN_EINVAL, "net is NULL");
+    if (nv) *nv = n->net.nv;
+    if (ne) *ne = (int32_t)n->net.edges.size();
+    return TN_OK;
+}
+
+tn_status tn_net_flat_complexity(const tn_net* n, double* tc, double* sc, double* rwc) {
+    if (!n) return fail(TN_EINVAL, "net is NULL");
+    double a, b, c;
+    flat_complexity(n->net, a, b, c);
+    if (tc) *tc = a;
+    if (sc) *sc = b;
+    if (rwc) *rwc = c;
+    return TN_OK;
+}
+
+void tn_plan_opts_default(tn_plan_opts* o) {
+    if (!o) return;
+    PlanOptions d;
+    o->method = d.method;
+    o->alpha = d.alpha;
+    o->temperature = d.temperature;
+    o->nrepeat = d.nrepeat;
+    o->seed = d.seed;
+    o->sc_target = d.sc_target;
+    o->sc_weight = d.sc_weight;
+    o->rw_weight = d.rw_weight;
+    o->beta_start = d.beta_start;
+    o->beta_step = d.beta_step;
+    o->beta_stop = d.beta_stop;
+    o->ntrials = d.ntrials;
+    o->niters = d.niters;
+    o->nslices = d.nslices;
+    o->absorb_vertices = d.absorb ? 1 : 0;
+    o->nthreads = d.nthreads;
+}
+
+static tn_status to_options(const tn_plan_opts* o, PlanOptions& p) {
+    if (!o) return TN_OK;
+    p.method = o->method;
+    p.alpha = o->alpha;
+    p.temperature = o->temperature;
+    p.nrepeat = o->nrepeat;
+    p.seed = o->seed;
+    p.sc_target = o->sc_target;
+    p.sc_weight = o->sc_weight;
+    p.rw_weight = o->rw_weight;
+    p.beta_start = o->beta_start;
+    p.beta_step = o->beta_step;
+    p.beta_stop = o->beta_stop;
+    p.ntrials = o->ntrials;
+    p.niters = o->niters;
+    p.nslices = o->nslices;
+    p.absorb = o->absorb_vertices != 0;
+    p.nthreads = o->nthreads;
+    if (p.method != 0 && p.method != 1) return fail(TN_EINVAL, "method must be 0 (greedy) or 1 (TreeSA)");
+    if (p.temperature < 0 || p.nrepeat < 0 || p.ntrials < 0 || p.niters < 0 || p.nslices < 0)
+        return fail(TN_EINVAL, "negative optimizer parameter");
+    if (p.method == 1 && (p.beta_step <= 0 || p.beta_stop < p.beta_start))
+        return fail(TN_EINVAL, "TreeSA needs beta_step > 0 and beta_stop >= beta_start");
+    return TN_OK;
+}
+
+tn_status tn_plan_create(const tn_net* n, const tn_plan_opts* o, tn_plan** out) {
+    TN_GUARD_BEGIN
+    if (!n || !out) return fail(TN_EINVAL, "net or out is NULL");
+    *out = nullptr;
+    PlanOptions po;
+    tn_status st = to_options(o, po);
+    if (st != TN_OK) return st;
+    auto* p = new tn_plan();
+    st = plan_create(n->net, po, p->plan);
+    if (st != TN_OK) {
+        delete p;
+        return st;
+    }
+    p->plan.uid = g_plan_uid.fetch_add(1);
+    *out = p;
+    return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_plan_from_tree(const tn_net* n, int32_t nleaf, const int32_t* fac_off, const int32_t* fac,
+                            int32_t ninner, const int32_t* left, const int32_t* right, int32_t nsliced,
+                            const int32_t* sliced, tn_plan** out) {
+    TN_GUARD_BEGIN
+    if (!n || !out || nleaf < 1 || ninner < 0 || nsliced < 0 || !fac_off || !fac)
+        return fail(TN_EINVAL, "invalid tree arguments");
+    *out = nullptr;
+    std::vector<Leaf> leaves(nleaf);
+    for (int l = 0; l < nleaf; l++) {
+        if (fac_off[l + 1] < fac_off[l]) return fail(TN_EINVAL, "fac_off must be non-decreasing");
+        for (int q = fac_off[l]; q < fac_off[l + 1]; q++) leaves[l].factors.push_back(fac[q]);
+    }
+    std::vector<int> L(left, left + ninner), R(right, right + ninner), S;
+    if (nsliced) S.assign(sliced, sliced + nsliced);
+    auto* p = new tn_plan();
+    tn_status st = plan_from_tree(n->net, leaves, L, R, S, p->plan);
+    if (st != TN_OK) {
+        delete p;
+        return st;
+    }
+    p->plan.uid = g_plan_uid.fetch_add(1);
+    *out = p;
+    return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_plan_complexity(const tn_plan* p, double* tc, double* sc, double* rwc) {
+    if (!p) return fail(TN_EINVAL, "plan is NULL");
+    if (tc) *tc = p->plan.tc;
+    if (sc) *sc = p->plan.sc;
+    if (rwc) *rwc = p->plan.rwc;
+    return TN_OK;
+}
+
+tn_status tn_plan_info(const tn_plan* p, tn_plan_info_t* info) {
+    if (!p || !info) return fail(TN_EINVAL, "plan or info is NULL");
+    info->nleaf = p->plan.nleaf();
+    info->ninner = p->plan.ninner();
+    info->nsliced = (int32_t)p->plan.sliced.size();
+    info->max_rank = p->plan.max_rank;
+    info->tc_log2 = p->plan.tc;
+    info->sc_log2 = p->plan.sc;
+    info->rwc_log2 = p->plan.rwc;
+    info->arena_entries = (uint64_t)p->plan.arena_entries;
+    info->npermutes = p->plan.npermutes;
+    return TN_OK;
+}
+
+tn_status tn_plan_peak_bytes(const tn_plan* p, tn_semiring sr, uint64_t* bytes) {
+    TN_GUARD_BEGIN
+    if (!p || !bytes) return fail(TN_EINVAL, "plan or bytes is NULL");
+    int dsr;
+    switch (sr) {
+    case TN_TROPICAL_I32: dsr = DSR_TROP_I32; break;
+    case TN_TROPICAL_F32: dsr = DSR_TROP_F32; break;
+    case TN_COUNTING_TROPICAL: dsr = DSR_CTROP; break;
+    case TN_COUNT_EXACT: dsr = DSR_U64; break;
+    case TN_PARTITION_F32: dsr = DSR_Z_F32; break;
+    case TN_PARTITION_BF16: dsr = DSR_Z_BF16; break;
+    default: return fail(TN_EINVAL, "unknown semiring");
+    }
+    const Plan& pl = p->plan;
+    uint64_t eb = (uint64_t)plane_bytes(dsr, 0) + (uint64_t)plane_bytes(dsr, 1);
+    uint64_t part = 0;
+    for (auto& np : pl.prog) {
+        GemmShape g = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+        if (g.lsplit) part = std::max<uint64_t>(part, 1ull << (g.lsplit + np.lb + np.li + np.lj));
+    }
+    uint64_t e = (uint64_t)std::max<int64_t>(pl.arena_entries, 64);
+    *bytes = (e + part) * eb + sizeof(TensorMeta) * pl.nodes.size() + 4ull * pl.nv + 4096 + 8192;
+    return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_plan_export(const tn_plan* pp, int32_t* nleaf, int32_t* ninner, int32_t* nfac, int32_t* nidx,
+                         int32_t* nsliced, int32_t* fac_off, int32_t* fac, int32_t* left, int32_t* right,
+                         int32_t* idx_off, int32_t* idx, int32_t* sliced) {
+    TN_GUARD_BEGIN
+    if (!pp) return fail(TN_EINVAL, "plan is NULL");
+    const Plan& p = pp->plan;
+    int nl = p.nleaf(), ni = p.ninner();
+    int nf = 0, nx = 0;
+    for (auto& l : p.leaves) nf += (int)l.factors.size();
+    for (auto& n : p.nodes) nx += (int)n.out.size();
+    if (nleaf) *nleaf = nl;
+    if (ninner) *ninner = ni;
+    if (nfac) *nfac = nf;
+    if (nidx) *nidx = nx;
+    if (nsliced) *nsliced = (int32_t)p.sliced.size();
+    if (fac_off && fac) {
+        int q = 0;
+        for (int l = 0; l < nl; l++) {
+            fac_off[l] = q;
+            for (int f : p.leaves[l].factors) fac[q++] = f;
+        }
+        fac_off[nl] = q;
+    }
+    if (left && right)
+        for (int t = 0; t < ni; t++) {
+            left[t] = p.nodes[nl + t].left;
+            right[t] = p.nodes[nl + t].right;
+        }
+    if (idx_off && idx) {
+        int q = 0;
+        for (size_t x = 0; x < p.nodes.size(); x++) {
+            idx_off[x] = q;
+            for (int v : p.nodes[x].out) idx[q++] = v;
+        }
+        idx_off[p.nodes.size()] = q;
+    }
+    if (sliced)
+        for (size_t k = 0; k < p.sliced.size(); k++) sliced[k] = p.sliced[k];
+    return TN_OK;
+    TN_GUARD_END
+}
+
+void tn_plan_destroy(tn_plan* p) { delete p; }
+
+void tn_solve_opts_default(tn_solve_opts* o) {
+    if (!o) return;
+    o->semiring = TN_TROPICAL_I32;
+    o->beta = 0.0;
+    o->nprimes = 0;
+    o->primes = nullptr;
+    o->slice_begin = 0;
+    o->slice_end = 0;
+}
+
+tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_opts* o, tn_result* out) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    return solve_one(c, n->net, p->plan, *o, *out);
+    TN_GUARD_END
+}
+
+}  // extern "C"

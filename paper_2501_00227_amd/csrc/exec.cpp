@@ -1,0 +1,506 @@
+// Single-network executor: leaf initialisation, per-node permute + batched
+// semiring GEMM in execution order, slicing loop with root accumulation, and
+// root decoding (CRT for exact counts, mantissa/exponent for Z).
+#include "exec.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace tn {
+
+// ---------------------------------------------------------------- memory --
+void* dev_alloc(tn_ctx* ctx, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (ctx->has_alloc) return ctx->alloc.alloc(bytes, ctx->alloc.user, (void*)ctx->stream);
+    void* p = nullptr;
+    if (hipMallocAsync(&p, bytes, ctx->stream) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(tn_ctx* ctx, void* p, size_t bytes) {
+    if (!p) return;
+    bytes = std::max<size_t>(bytes, 256);
+    if (ctx->has_alloc)
+        ctx->alloc.free(p, bytes, ctx->alloc.user, (void*)ctx->stream);
+    else
+        (void)hipFreeAsync(p, ctx->stream);
+}
+
+tn_status ensure_pinned(tn_ctx* ctx, size_t bytes) {
+    if (ctx->pinned_bytes >= bytes) return TN_OK;
+    if (ctx->pinned) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+    }
+    size_t n = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&ctx->pinned, n, hipHostMallocDefault) != hipSuccess)
+        return fail(TN_ENOMEM, "hipHostMalloc of the staging buffer failed");
+    ctx->pinned_bytes = n;
+    return TN_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------- profiling --
+ProfScope::ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops)
+    : ctx(c), on(c->profiling) {
+    if (!on) return;
+    auto get = [&]() {
+        hipEvent_t e;
+        if (!ctx->event_pool.empty()) {
+            e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+        } else {
+            (void)hipEventCreate(&e);
+        }
+        return e;
+    };
+    pr.start = get();
+    pr.stop = get();
+    pr.rec.kind = kind;
+    pr.rec.node = node;
+    pr.rec.semiring = sr;
+    for (int k = 0; k < 4; k++) pr.rec.shape[k] = shape ? shape[k] : 0;
+    pr.rec.ms = 0;
+    pr.rec.alg_bytes = bytes;
+    pr.rec.ops = ops;
+    (void)hipEventRecord(pr.start, ctx->stream);
+}
+
+ProfScope::~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(pr.stop, ctx->stream);
+    ctx->pending.push_back(pr);
+}
+
+// -------------------------------------------------------- device program --
+tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
+    auto it = ctx->progs.find(p.uid);
+    if (it != ctx->progs.end()) {
+        out = &it->second;
+        return TN_OK;
+    }
+    DevProgram dp;
+    int nleaf = p.nleaf();
+    std::vector<LeafDev> leaves(nleaf);
+    for (int l = 0; l < nleaf; l++) {
+        const LeafProg& lp = p.leaf_prog[l];
+        LeafDev& d = leaves[l];
+        d.u = lp.u;
+        d.v = lp.has_edge ? lp.v : -1;
+        d.flags = (lp.has_edge ? 1 : 0) | (lp.wu ? 2 : 0) | (lp.wv ? 4 : 0);
+        d.rank = lp.rank;
+        d.var0 = lp.var[0];
+        d.var1 = lp.var[1];
+        d.off = lp.off;
+    }
+    std::vector<PermParams> perms;
+    dp.perm_slot_a.assign(p.prog.size(), -1);
+    dp.perm_slot_b.assign(p.prog.size(), -1);
+    for (size_t t = 0; t < p.prog.size(); t++) {
+        const NodeProg& np = p.prog[t];
+        if (np.perm_a) {
+            PermParams pp;
+            build_perm_params((int)np.perm_a_src.size(), np.perm_a_src.data(), pp);
+            dp.perm_slot_a[t] = (int)perms.size();
+            perms.push_back(pp);
+        }
+        if (np.perm_b) {
+            PermParams pp;
+            build_perm_params((int)np.perm_b_src.size(), np.perm_b_src.data(), pp);
+            dp.perm_slot_b[t] = (int)perms.size();
+            perms.push_back(pp);
+        }
+    }
+    std::vector<int> spos(std::max(p.nv, 1), -1);
+    for (size_t k = 0; k < p.sliced.size(); k++) spos[p.sliced[k]] = (int)k;
+    size_t o_leaf = 0;
+    size_t o_perm = align256(o_leaf + sizeof(LeafDev) * leaves.size());
+    size_t o_spos = align256(o_perm + sizeof(PermParams) * perms.size());
+    size_t total = align256(o_spos + sizeof(int) * spos.size());
+    dp.bytes = total;
+    dp.buf = dev_alloc(ctx, total);
+    if (!dp.buf) return fail(TN_ENOMEM, "device allocation of the plan program failed");
+    tn_status st = ensure_pinned(ctx, total);
+    if (st != TN_OK) return st;
+    (void)hipStreamSynchronize(ctx->stream);  // the staging buffer may still be in use
+    unsigned char* h = (unsigned char*)ctx->pinned;
+    std::memcpy(h + o_leaf, leaves.data(), sizeof(LeafDev) * leaves.size());
+    if (!perms.empty()) std::memcpy(h + o_perm, perms.data(), sizeof(PermParams) * perms.size());
+    std::memcpy(h + o_spos, spos.data(), sizeof(int) * spos.size());
+    if (hipMemcpyAsync(dp.buf, h, total, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return fail(TN_EDEVICE, "upload of the plan program failed");
+    unsigned char* d = (unsigned char*)dp.buf;
+    dp.leaves = (LeafDev*)(d + o_leaf);
+    dp.perms = (PermParams*)(d + o_perm);
+    dp.slice_pos = (int*)(d + o_spos);
+    auto ins = ctx->progs.emplace(p.uid, std::move(dp));
+    out = &ins.first->second;
+    return TN_OK;
+}
+
+const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr) {
+    auto it = dp.launches.find(dsr);
+    if (it != dp.launches.end()) return it->second;
+    std::vector<NodeLaunch> v(p.prog.size());
+    int64_t part = 0;
+    for (size_t t = 0; t < p.prog.size(); t++) {
+        const NodeProg& np = p.prog[t];
+        v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+        if (v[t].shape.lsplit > 0)
+            v[t].part_entries = (int64_t)1 << (v[t].shape.lsplit + np.lb + np.li + np.lj);
+        part = std::max(part, v[t].part_entries);
+    }
+    dp.part_entries[dsr] = part;
+    return dp.launches.emplace(dsr, std::move(v)).first->second;
+}
+
+// --------------------------------------------------------------- algebra --
+static uint32_t powmod(uint64_t b, uint64_t e, uint32_t m) {
+    uint64_t r = 1 % m;
+    b %= m;
+    while (e) {
+        if (e & 1) r = r * b % m;
+        b = b * b % m;
+        e >>= 1;
+    }
+    return (uint32_t)r;
+}
+
+AlgebraParams algebra_params(int dsr, uint32_t prime, double beta) {
+    AlgebraParams ap;
+    ap.beta = beta;
+    if (dsr == DSR_MODP) {
+        uint32_t inv = prime;  // Newton iteration for p^{-1} mod 2^32 (p odd)
+        for (int k = 0; k < 5; k++) inv *= 2u - prime * inv;
+        ap.p = prime;
+        ap.pinv = (uint32_t)(0u - inv);
+        ap.r1 = (uint32_t)((1ull << 32) % prime);
+    }
+    return ap;
+}
+
+static const uint32_t kDefaultPrimes[8] = {2147483647u, 2147483629u, 2147483587u, 2147483579u,
+                                           2147483563u, 2147483549u, 2147483543u, 2147483497u};
+
+static bool is_prime(uint32_t p) {
+    if (p < 2) return false;
+    for (uint64_t d = 2; d * d <= p; d++)
+        if (p % d == 0) return false;
+    return true;
+}
+
+tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes) {
+    passes.clear();
+    switch (o.semiring) {
+    case TN_TROPICAL_I32:
+        if (!net.integer_weights) return fail(TN_EINVAL, "TN_TROPICAL_I32 needs integer weights (|w| <= 65536)");
+        passes.push_back({DSR_TROP_I32, 0});
+        break;
+    case TN_TROPICAL_F32: passes.push_back({DSR_TROP_F32, 0}); break;
+    case TN_COUNTING_TROPICAL:
+        if (!net.integer_weights) return fail(TN_EINVAL, "TN_COUNTING_TROPICAL needs integer weights");
+        passes.push_back({DSR_CTROP, 0});
+        break;
+    case TN_COUNT_EXACT: {
+        int np = o.nprimes > 0 ? o.nprimes : 4;
+        if (np < 2 || np > 8) return fail(TN_EINVAL, "nprimes must be in [2, 8] (CRT primes + one check prime)");
+        passes.push_back({DSR_U64, 0});
+        for (int k = 0; k < np; k++) {
+            uint32_t p = o.primes ? o.primes[k] : kDefaultPrimes[k];
+            if (p >= (1u << 31) || p < 3 || !is_prime(p)) return fail(TN_EINVAL, "residue moduli must be odd primes below 2^31");
+            for (auto& q : passes)
+                if (q.prime == p) return fail(TN_EINVAL, "residue primes must be distinct");
+            passes.push_back({DSR_MODP, p});
+        }
+        break;
+    }
+    case TN_PARTITION_F32: passes.push_back({DSR_Z_F32, 0}); break;
+    case TN_PARTITION_BF16: passes.push_back({DSR_Z_BF16, 0}); break;
+    default: return fail(TN_EINVAL, "unknown semiring");
+    }
+    if ((o.semiring == TN_PARTITION_F32 || o.semiring == TN_PARTITION_BF16) && !std::isfinite(o.beta))
+        return fail(TN_EINVAL, "beta must be finite");
+    return TN_OK;
+}
+
+// little-endian 32-bit limb helpers for the CRT value
+struct BigU {
+    std::vector<uint32_t> d;
+    void mul_small(uint32_t m) {
+        uint64_t carry = 0;
+        for (auto& x : d) {
+            uint64_t t = (uint64_t)x * m + carry;
+            x = (uint32_t)t;
+            carry = t >> 32;
+        }
+        if (carry) d.push_back((uint32_t)carry);
+    }
+    void add(const BigU& o) {
+        if (o.d.size() > d.size()) d.resize(o.d.size(), 0);
+        uint64_t carry = 0;
+        for (size_t k = 0; k < d.size(); k++) {
+            uint64_t t = (uint64_t)d[k] + (k < o.d.size() ? o.d[k] : 0) + carry;
+            d[k] = (uint32_t)t;
+            carry = t >> 32;
+        }
+        if (carry) d.push_back((uint32_t)carry);
+    }
+    uint32_t mod_small(uint32_t m) const {
+        uint64_t r = 0;
+        for (size_t k = d.size(); k-- > 0;) r = ((r << 32) | d[k]) % m;
+        return (uint32_t)r;
+    }
+    void trim() {
+        while (!d.empty() && d.back() == 0) d.pop_back();
+    }
+};
+
+tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& passes,
+                        const std::vector<std::vector<unsigned char>>& acc, tn_result& res) {
+    std::memset(&res, 0, sizeof res);
+    res.semiring = o.semiring;
+    const unsigned char* a0 = acc[0].data();
+    switch (o.semiring) {
+    case TN_TROPICAL_I32: {
+        int v;
+        std::memcpy(&v, a0, 4);
+        res.size_i32 = v;
+        res.size_f32 = (float)v;
+        res.size_is_neg_inf = v <= -(1 << 30);
+        break;
+    }
+    case TN_TROPICAL_F32: {
+        float v;
+        std::memcpy(&v, a0, 4);
+        res.size_f32 = v;
+        res.size_i32 = std::isfinite(v) ? (int32_t)v : INT32_MIN;
+        res.size_is_neg_inf = std::isinf(v) && v < 0;
+        break;
+    }
+    case TN_COUNTING_TROPICAL: {
+        int n;
+        uint64_t c;
+        std::memcpy(&n, a0, 4);
+        std::memcpy(&c, a0 + 8, 8);
+        res.size_i32 = n;
+        res.size_f32 = (float)n;
+        res.size_is_neg_inf = n <= -(1 << 30);
+        res.count_mod_2_64 = res.size_is_neg_inf ? 0 : c;
+        break;
+    }
+    case TN_COUNT_EXACT: {
+        uint64_t c64;
+        std::memcpy(&c64, a0, 8);
+        res.count_mod_2_64 = c64;
+        int np = (int)passes.size() - 1;
+        res.nresidues = np;
+        for (int k = 0; k < np; k++) {
+            uint32_t p = passes[k + 1].prime, xm;
+            std::memcpy(&xm, acc[k + 1].data(), 4);
+            uint32_t rinv = powmod((1ull << 32) % p, p - 2, p);  // R^{-1} mod p
+            res.residues[k] = (uint32_t)((uint64_t)xm * rinv % p);
+            res.primes[k] = p;
+        }
+        // Garner over {2^64, p_1 .. p_{np-1}}; p_np checks the result
+        BigU x, M;
+        x.d = {(uint32_t)c64, (uint32_t)(c64 >> 32)};
+        M.d = {0u, 0u, 1u};  // 2^64
+        for (int k = 0; k < np - 1; k++) {
+            uint32_t p = res.primes[k];
+            uint32_t xm = x.mod_small(p), mm = M.mod_small(p);
+            uint32_t t = (uint32_t)((uint64_t)((res.residues[k] + (uint64_t)p - xm) % p) * powmod(mm, p - 2, p) % p);
+            BigU add = M;
+            add.mul_small(t);
+            x.add(add);
+            M.mul_small(p);
+        }
+        x.trim();
+        if (x.d.size() > 16) return fail(TN_EOVERFLOW, "exact count needs more than 512 bits");
+        res.count_nlimbs = (int)x.d.size();
+        for (size_t k = 0; k < x.d.size(); k++) res.count_limbs[k] = x.d[k];
+        uint32_t pc = res.primes[np - 1];
+        if (x.mod_small(pc) != res.residues[np - 1])
+            return fail(TN_EOVERFLOW, "exact count exceeds the CRT range: the check prime disagrees");
+        break;
+    }
+    case TN_PARTITION_F32:
+    case TN_PARTITION_BF16: {
+        double m;
+        int64_t e;
+        std::memcpy(&m, a0, 8);
+        std::memcpy(&e, a0 + 8, 8);
+        res.z_mant = m;
+        res.z_exp2 = m == 0.0 ? 0 : e;
+        res.log_z = m == 0.0 ? -INFINITY : std::log(m) + (double)e * std::log(2.0);
+        res.z = m == 0.0 ? 0.0 : (e > 1100 ? INFINITY : std::ldexp(m, (int)std::max<int64_t>(e, -2000)));
+        break;
+    }
+    default: return fail(TN_EINVAL, "unknown semiring");
+    }
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ solve --
+static int64_t node_entries(const Plan& p, int node) { return (int64_t)1 << p.order[node].size(); }
+
+tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (plan.fingerprint != net.fingerprint || plan.nv != net.nv)
+        return fail(TN_EINVAL, "plan was built for a different network");
+    std::vector<PassSpec> passes;
+    tn_status st = make_passes(net, o, passes);
+    if (st != TN_OK) return st;
+    hipStream_t s = ctx->stream;
+    const int nleaf = plan.nleaf();
+    const int nn = (int)plan.nodes.size();
+    int ns = (int)plan.sliced.size();
+    if (ns > 62) return fail(TN_EINVAL, "too many sliced indices");
+    int64_t nslices = (int64_t)1 << ns;
+    int64_t sb = o.slice_begin, se = o.slice_end;
+    if (sb == 0 && se == 0) se = nslices;
+    if (sb < 0 || se > nslices || sb >= se) return fail(TN_EINVAL, "slice range out of bounds");
+
+    DevProgram* dp = nullptr;
+    if (nleaf > 0) {
+        st = get_program(ctx, plan, dp);
+        if (st != TN_OK) return st;
+    }
+    // one allocation: arena planes, split partials, meta, weights, accumulator
+    size_t need = 0;
+    int64_t E = std::max<int64_t>(plan.arena_entries, 64);
+    int64_t Pe = 0;
+    for (auto& ps : passes) {
+        if (dp) {
+            node_launches(*dp, plan, ps.dsr);
+            Pe = std::max(Pe, dp->part_entries[ps.dsr]);
+        }
+    }
+    int pb0 = 0, pb1 = 0;
+    for (auto& ps : passes) {
+        pb0 = std::max(pb0, plane_bytes(ps.dsr, 0));
+        pb1 = std::max(pb1, plane_bytes(ps.dsr, 1));
+    }
+    size_t o_a0 = 0;
+    size_t o_a1 = align256(o_a0 + (size_t)E * pb0);
+    size_t o_p0 = align256(o_a1 + (size_t)E * pb1);
+    size_t o_p1 = align256(o_p0 + (size_t)Pe * pb0);
+    size_t o_meta = align256(o_p1 + (size_t)Pe * pb1);
+    size_t o_w = align256(o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
+    size_t o_acc = align256(o_w + sizeof(float) * (size_t)std::max(net.nv, 1));
+    need = align256(o_acc + 16 * passes.size());
+    unsigned char* base = (unsigned char*)dev_alloc(ctx, need);
+    if (!base) return fail(TN_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
+    Planes arena{base + o_a0, pb1 ? base + o_a1 : nullptr};
+    Planes part{base + o_p0, pb1 ? base + o_p1 : nullptr};
+    TensorMeta* meta = (TensorMeta*)(base + o_meta);
+    float* wdev = net.w.empty() ? nullptr : (float*)(base + o_w);
+    st = ensure_pinned(ctx, std::max<size_t>(16 * passes.size(), sizeof(float) * net.w.size()) + 64);
+    if (st != TN_OK) {
+        dev_free(ctx, base, need);
+        return st;
+    }
+    hipError_t herr = hipSuccess;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && herr == hipSuccess) herr = e;
+    };
+    if (wdev) {
+        chk(hipStreamSynchronize(s));
+        std::memcpy(ctx->pinned, net.w.data(), sizeof(float) * net.w.size());
+        chk(hipMemcpyAsync(wdev, ctx->pinned, sizeof(float) * net.w.size(), hipMemcpyHostToDevice, s));
+        chk(hipStreamSynchronize(s));  // staging is reused for the results below
+    }
+    auto plane_at = [&](Planes pl, int dsr, int64_t off) {
+        Planes r;
+        r.p0 = (unsigned char*)pl.p0 + off * plane_bytes(dsr, 0);
+        r.p1 = plane_bytes(dsr, 1) ? (unsigned char*)pl.p1 + off * plane_bytes(dsr, 1) : nullptr;
+        return r;
+    };
+    for (size_t pi = 0; pi < passes.size() && herr == hipSuccess; pi++) {
+        const int dsr = passes[pi].dsr;
+        const AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta);
+        void* acc = base + o_acc + 16 * pi;
+        const int eb = plane_bytes(dsr, 0) + plane_bytes(dsr, 1);
+        const bool is_z = dsr == DSR_Z_F32 || dsr == DSR_Z_BF16;
+        if (nleaf == 0) {
+            chk(launch_set_one(dsr, acc, ap, s));
+            continue;
+        }
+        const auto& launches = node_launches(*dp, plan, dsr);
+        for (int64_t sl = sb; sl < se && herr == hipSuccess; sl++) {
+            if (is_z) chk(launch_meta_init(meta, nn, s));
+            {
+                ProfScope ps(ctx, TN_K_LEAF, -1, o.semiring, nullptr, (double)plan.leaf_entries * eb, 0);
+                chk(launch_leaves(dsr, dp->leaves, nleaf, wdev, dp->slice_pos, (unsigned long long)sl, arena, ap,
+                                  meta, s));
+            }
+            for (size_t t = 0; t < plan.prog.size() && herr == hipSuccess; t++) {
+                const NodeProg& np = plan.prog[t];
+                const NodeLaunch& nl = launches[t];
+                Planes Ap = plane_at(arena, dsr, plan.node_off[np.a]);
+                Planes Bp = plane_at(arena, dsr, plan.node_off[np.b]);
+                for (int side = 0; side < 2; side++) {
+                    bool perm = side ? np.perm_b : np.perm_a;
+                    if (!perm) continue;
+                    int slot = side ? dp->perm_slot_b[t] : dp->perm_slot_a[t];
+                    int src_node = side ? np.b : np.a;
+                    int rank = (int)plan.order[src_node].size();
+                    Planes src = side ? Bp : Ap;
+                    Planes dst = plane_at(arena, dsr, side ? np.b_tmp_off : np.a_tmp_off);
+                    int tb = rank < 11 ? rank : 11;
+                    int shp[4] = {rank, 0, 0, 0};
+                    for (int pl = 0; pl < 2; pl++) {
+                        int pbytes = plane_bytes(dsr, pl);
+                        if (!pbytes) continue;
+                        ProfScope ps(ctx, TN_K_PERMUTE, np.node, o.semiring, shp,
+                                     2.0 * (double)node_entries(plan, src_node) * pbytes, 0);
+                        chk(launch_permute(pbytes, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms + slot, rank,
+                                           tb, s));
+                    }
+                    if (side)
+                        Bp = dst;
+                    else
+                        Ap = dst;
+                }
+                Planes Cp = plane_at(arena, dsr, np.c_off);
+                const GemmShape& g = nl.shape;
+                double ent = std::exp2((double)(g.lb + g.li + g.lk)) + std::exp2((double)(g.lb + g.lk + g.lj)) +
+                             std::exp2((double)(g.lb + g.li + g.lj));
+                int shp[4] = {g.lb, g.li, g.lj, g.lk};
+                {
+                    ProfScope ps(ctx, TN_K_GEMM, np.node, o.semiring, shp, ent * eb,
+                                 std::exp2((double)(g.lb + g.li + g.lj + g.lk)));
+                    chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s));
+                }
+                if (g.lsplit > 0) {
+                    int64_t nout = (int64_t)1 << (g.lb + g.li + g.lj);
+                    ProfScope ps(ctx, TN_K_ACCUM, np.node, o.semiring, shp,
+                                 (double)(nout << g.lsplit) * eb + (double)nout * eb, 0);
+                    chk(launch_split_reduce(dsr, part, Cp, nout, g.lsplit, ap, meta, np.node, s));
+                }
+            }
+            int root = nn - 1;
+            chk(launch_accumulate(dsr, plane_at(arena, dsr, plan.node_off[root]), root, meta, acc, sl == sb ? 1 : 0,
+                                  ap, s));
+        }
+    }
+    std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
+    if (herr == hipSuccess) {
+        chk(hipMemcpyAsync(ctx->pinned, base + o_acc, 16 * passes.size(), hipMemcpyDeviceToHost, s));
+        chk(hipStreamSynchronize(s));
+        for (size_t k = 0; k < passes.size(); k++)
+            std::memcpy(accs[k].data(), (unsigned char*)ctx->pinned + 16 * k, 16);
+    }
+    dev_free(ctx, base, need);
+    if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error: ") + hipGetErrorString(herr));
+    st = decode_result(o, passes, accs, res);
+    res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+}  // namespace tn

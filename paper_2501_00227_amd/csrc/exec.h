@@ -1,0 +1,96 @@
+// Executor: device contexts, per-plan device programs, and single-network
+// contraction on one HIP stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+struct tn_net {
+    tn::Net net;
+};
+
+struct tn_plan {
+    tn::Plan plan;
+};
+
+namespace tn {
+
+// Host copy of the executor program of one plan for one device algebra.
+struct NodeLaunch {
+    GemmShape shape;
+    int64_t part_entries = 0;  // split-K partial buffer entries (0 if none)
+};
+
+// Device-resident constant data of one plan: leaf descriptors, permute
+// tables and slice positions.  Uploaded once per (context, plan).
+struct DevProgram {
+    void* buf = nullptr;
+    size_t bytes = 0;
+    LeafDev* leaves = nullptr;
+    PermParams* perms = nullptr;  // indexed by permute slot
+    int* slice_pos = nullptr;     // nv entries: position in the sliced list or -1
+    std::vector<int> perm_slot_a, perm_slot_b;  // per inner node, -1 if none
+    std::map<int, std::vector<NodeLaunch>> launches;  // per device algebra
+    std::map<int, int64_t> part_entries;              // per device algebra
+};
+
+struct PendingRec {
+    hipEvent_t start, stop;
+    tn_kernel_record rec;
+};
+
+}  // namespace tn
+
+struct tn_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    tn_allocator alloc{};
+    bool has_alloc = false;
+    bool profiling = false;
+    std::vector<tn::PendingRec> pending;
+    std::vector<tn_kernel_record> records;
+    std::vector<hipEvent_t> event_pool;
+    void* pinned = nullptr;  // host staging (results, weights)
+    size_t pinned_bytes = 0;
+    std::map<uint64_t, tn::DevProgram> progs;  // keyed by plan uid
+};
+
+namespace tn {
+
+void* dev_alloc(tn_ctx* ctx, size_t bytes);
+void dev_free(tn_ctx* ctx, void* p, size_t bytes);
+tn_status ensure_pinned(tn_ctx* ctx, size_t bytes);
+tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out);
+const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr);
+
+// Profiling bracket around one launch (no-op unless profiling is on).
+struct ProfScope {
+    tn_ctx* ctx;
+    PendingRec pr;
+    bool on;
+    ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops);
+    ~ProfScope();
+};
+
+tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res);
+
+// Device algebras needed for a user algebra, and the lane primes.
+struct PassSpec {
+    int dsr;
+    uint32_t prime;
+};
+tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes);
+AlgebraParams algebra_params(int dsr, uint32_t prime, double beta);
+// Decode the accumulators of all passes into the result struct.
+tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& passes,
+                        const std::vector<std::vector<unsigned char>>& acc, tn_result& res);
+
+}  // namespace tn

@@ -1,0 +1,94 @@
+// Host-callable launchers of the gfx950 kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tn {
+
+// Device algebra of one contraction pass.  Exact counting runs one pass per
+// lane: DSR_U64 (counts mod 2^64) and DSR_MODP (counts mod a prime p).
+enum DevSemiring {
+    DSR_TROP_I32 = 0,
+    DSR_TROP_F32 = 1,
+    DSR_CTROP = 2,   // plane 0 int32 size, plane 1 uint64 count
+    DSR_U64 = 3,
+    DSR_MODP = 4,    // Montgomery form, R = 2^32
+    DSR_Z_F32 = 5,   // float32 with per-tensor power-of-two exponents
+    DSR_Z_BF16 = 6,  // as DSR_Z_F32, GEMM inputs rounded to bfloat16
+    DSR_COUNT_ = 7
+};
+
+// bytes per entry of plane 0 / plane 1 (0 = no such plane)
+int plane_bytes(int dsr, int plane);
+
+struct Planes {
+    void* p0 = nullptr;
+    void* p1 = nullptr;
+};
+
+// Per-tensor bookkeeping of the partition-function algebra: the true tensor
+// is stored * 2^exp; maxbits is the float bit pattern of max|stored|.
+struct TensorMeta {
+    long long exp;
+    unsigned int maxbits;
+    unsigned int pad;
+};
+
+struct AlgebraParams {
+    uint32_t p = 0, pinv = 0, r1 = 0;  // modulus, -p^{-1} mod 2^32, 2^32 mod p
+    double beta = 0;
+};
+
+// Leaf descriptor on the device (one per leaf tensor, rank <= 2).
+struct LeafDev {
+    int u, v;          // edge ends (u < v) or u = vertex of a vertex-only leaf, v = -1
+    int flags;         // 1: edge factor, 2: W_u, 4: W_v
+    int rank;          // unsliced output indices
+    int var0, var1;    // vertex at bit 0 / bit 1
+    long long off;     // arena offset (entries)
+};
+
+// Bit-permutation tables of one permute (see kernels.hip).
+struct PermParams {
+    long long in_lo[64], in_hi[64];
+    long long out_lo[64], out_hi[64];
+    int e_lo[64], e_hi[64];
+    signed char tin[48], tout[48];
+    int rank, tile_bits, ntile_bits, pad;
+};
+
+struct GemmShape {
+    int lb, li, lj, lk;    // log2 batch, M, N, K
+    int a_t, b_t;          // operand transposition flags
+    int tb, ti, tj, tk;    // log2 tile (batch, M, N, K-step)
+    int rm, rn;            // per-thread micro tile
+    int lsplit;            // log2 of K splits (partials then reduce)
+};
+
+void build_perm_params(int rank, const int* src, PermParams& pp);
+
+hipError_t launch_meta_init(TensorMeta* meta, int n, hipStream_t s);
+hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float* w, const int* slice_pos,
+                         unsigned long long slice_id, Planes arena, const AlgebraParams& ap,
+                         TensorMeta* meta, hipStream_t s);
+hipError_t launch_permute(int elem_bytes, const void* in, void* out, const PermParams* pp_dev, int rank,
+                          int tile_bits, hipStream_t s);
+hipError_t launch_gemm(int dsr, Planes A, Planes B, Planes C, Planes part, const GemmShape& g,
+                       const AlgebraParams& ap, TensorMeta* meta, int ma, int mb, int mc, hipStream_t s);
+hipError_t launch_split_reduce(int dsr, Planes part, Planes C, int64_t nout, int lsplit,
+                               const AlgebraParams& ap, TensorMeta* meta, int mc, hipStream_t s);
+// acc (+)= root; first != 0 copies.  For the partition function the
+// accumulator is {double mantissa, int64 exponent}.
+hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
+                             const AlgebraParams& ap, hipStream_t s);
+// The device-side identity element of a whole (empty) network.
+hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream_t s);
+int accumulator_bytes(int dsr);
+
+// Choose tile shape for a GEMM node (heuristic; the autotuner may override).
+GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);
+bool gemm_shape_valid(int dsr, const GemmShape& g);
+
+}  // namespace tn

@@ -1,0 +1,160 @@
+"""Host-side tests of the C-ABI library (no GPU needed): symbol exports,
+network validation, the contraction-complexity definitions of Sec. 4.1, and
+the planner's trees checked by the oracle's independent plan follower."""
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2501_00227_amd as tn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "tn.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    names = set(re.findall(r"\b(tn_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) >= 25
+    L = tn.lib()
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert names <= {s[0] for s in tn.SIGNATURES}
+
+
+def test_network_validation():
+    with pytest.raises(tn.TnError) as ei:
+        tn.Net(3, [[0, 0]])
+    assert ei.value.code == tn.TN_EINVAL
+    with pytest.raises(tn.TnError):
+        tn.Net(3, [[0, 3]])
+    with pytest.raises(tn.TnError):
+        tn.Net(2, [[0, 1]], np.array([1.0, np.nan], np.float32))
+    n = tn.Net(3, [[0, 1], [1, 0], [1, 2]])
+    nv, ne = np.zeros(1, np.int32), np.zeros(1, np.int32)
+    tn.lib().tn_net_info(n.h, tn._p32(nv), tn._p32(ne))
+    assert (nv[0], ne[0]) == (3, 2)  # duplicate edge merged
+
+
+def _square2_code():
+    # EinCode of Sec. 4.1: tensors [1,2],[2,3],[3,4],[4,1],[1],[2],[3],[4]
+    return tn.Net(4, np.array([[0, 1], [1, 2], [2, 3], [0, 3]], np.int32))
+
+
+def test_flat_complexity_matches_paper():
+    want = GOLD["square2"]["flat_complexity_log2"]["value"]
+    tc, sc, rw = _square2_code().flat_complexity()
+    assert (tc, sc) == (want["tc"], want["sc"])
+    assert rw == pytest.approx(want["rwc"], abs=1e-12)
+
+
+def _paper_tree_plan():
+    net = _square2_code()
+    leaves = [[0], [1], [2], [3], [-1], [-2], [-3], [-4]]
+    left = [2, 8, 5, 10, 11, 3, 13]
+    right = [6, 7, 1, 9, 0, 12, 4]
+    return net, tn.Plan.from_tree(net, leaves, left, right)
+
+
+def test_tree_complexity_matches_paper():
+    want = GOLD["square2"]["tree_complexity_log2"]["value"]
+    net, plan = _paper_tree_plan()
+    tc, sc, rw = plan.complexity()
+    assert tc == pytest.approx(want["tc"], abs=1e-12)
+    assert sc == want["sc"]
+    assert rw == pytest.approx(want["rwc"], abs=1e-12)
+
+
+def test_paper_tree_is_followed_by_the_oracle():
+    net, plan = _paper_tree_plan()
+    g = gg.Graph(4, np.array([[0, 1], [1, 2], [2, 3], [0, 3]], np.int32))
+    t = plan.export()
+    assert oracle.follow_plan(g, t, "count")["count"] == 7
+
+
+def test_invalid_trees_rejected():
+    net = _square2_code()
+    leaves = [[0], [1], [2], [3], [-1], [-2], [-3], [-4]]
+    with pytest.raises(tn.TnError):  # node used twice
+        tn.Plan.from_tree(net, leaves, [2, 2, 5, 10, 11, 3, 13], [6, 7, 1, 9, 0, 12, 4])
+    with pytest.raises(tn.TnError):  # a factor missing
+        tn.Plan.from_tree(net, leaves[:-1] + [[-3]], [2, 8, 5, 10, 11, 3, 13], [6, 7, 1, 9, 0, 12, 4])
+    with pytest.raises(tn.TnError):  # child after parent
+        tn.Plan.from_tree(net, leaves, [2, 8, 5, 10, 11, 3, 14], [6, 7, 1, 9, 0, 12, 4])
+
+
+def test_plan_option_validation():
+    net = tn.Net.from_graph(gg.cycle(5))
+    with pytest.raises(tn.TnError):
+        tn.Plan.create(net, method=7)
+    with pytest.raises(tn.TnError):
+        tn.Plan.create(net, method="treesa", beta_step=0.0)
+
+
+def _random_plans():
+    cases = []
+    for s in range(16):
+        g = [gg.random_regular(14, 3, s), gg.kings_subgraph(4, 0.8, s), gg.gnp(12, 0.3, s),
+             gg.disjoint_union(gg.path(4), gg.empty(3))][s % 4]
+        if s % 2:
+            g = g.with_weights(gg.dyadic_weights(g.nv, s))
+        kw = [dict(), dict(method="treesa", ntrials=2, niters=4), dict(absorb=False),
+              dict(sc_target=2, nslices=3), dict(temperature=2.0, nrepeat=3)][s % 5]
+        kw["seed"] = s
+        cases.append((g, kw))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(16))
+def test_planner_trees_evaluate_correctly_in_the_oracle(case):
+    g, kw = _random_plans()[case]
+    plan = tn.Plan.create(tn.Net.from_graph(g), **kw)
+    t = plan.export()
+    bf = oracle.brute_force(g, [0.5])
+    ct = oracle.follow_plan(g, t, "counting_tropical")
+    assert ct["size"] == bf["size_max"]
+    assert oracle.follow_plan(g, t, "count")["count"] == bf["count_all"]
+    assert oracle.follow_plan(g, t, "partition", 0.5)["z"] == pytest.approx(bf["z"][0], rel=1e-13)
+
+
+def test_greedy_meets_small_config_space_bound():
+    for s in range(20):
+        plan = tn.Plan.create(tn.Net.from_graph(gg.random_regular(20, 3, s)), seed=s)
+        assert plan.complexity()[1] <= 8
+
+
+def test_treesa_never_worse_than_its_greedy_start():
+    g = gg.random_regular(60, 3, 3)
+    net = tn.Net.from_graph(g)
+    gr = tn.Plan.create(net, nrepeat=1, seed=1)
+    sa = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=1, sc_target=30)
+    # cost = tc + 0.2 rwc (sc below target): annealing keeps its best tree
+    c = lambda p: p.complexity()[0] + 0.2 * p.complexity()[2]
+    assert c(sa) <= c(gr) + 1e-9
+
+
+def test_slicing_reaches_the_space_target():
+    g = gg.random_regular(40, 3, 2)
+    net = tn.Net.from_graph(g)
+    full = tn.Plan.create(net, seed=2)
+    sl = tn.Plan.create(net, seed=2, sc_target=full.complexity()[1] - 3, nslices=10)
+    info = sl.info()
+    assert info["nsliced"] >= 1
+    assert sl.complexity()[1] <= full.complexity()[1] - 3
+    # each sliced index doubles the work (Sec. 4.2): tc includes the 2^s factor
+    assert sl.complexity()[0] >= full.complexity()[0] - 3
+
+
+def test_peak_bytes_scale_with_element_size():
+    plan = tn.Plan.create(tn.Net.from_graph(gg.random_regular(40, 3, 1)))
+    b32 = plan.peak_bytes("tropical_i32")
+    bct = plan.peak_bytes("counting_tropical")
+    assert bct > 2.5 * b32 - 20000
+    assert plan.info()["arena_entries"] * 4 <= b32
