@@ -55,7 +55,8 @@ STEP = (("tropical_i32", 0.0), ("count_exact", 0.0), ("partition_f32", 0.0))
 
 
 def run_step(ctx, net, plan):
-    return [ctx.solve(net, plan, sr, beta=b) for sr, b in STEP]
+    """The three contractions of one step as one persistent launch."""
+    return ctx.solve_batch([net] * len(STEP), [plan] * len(STEP), [s for s, _ in STEP], [b for _, b in STEP])
 
 
 def dominant_kernel(recs):

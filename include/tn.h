@@ -130,6 +130,18 @@ tn_status tn_ctx_set_profiling(tn_ctx* ctx, int enabled);
 tn_status tn_ctx_profile(tn_ctx* ctx, tn_kernel_record* recs, int32_t cap, int32_t* n, int clear);
 tn_status tn_ctx_synchronize(tn_ctx* ctx);
 
+/* Per-task timeline of the persistent launches run while profiling was on:
+ * for each task its kind (0 leaves, 1 permute tile, 2 GEMM tile, 3 split
+ * reduction, 4 root accumulation), job, tree node, the hardware XCC (chiplet)
+ * that ran it, and its start (ticket taken), ready (dependencies met) and end
+ * times in microseconds since the launch's first ticket.  Copies up to cap
+ * records; *n receives the number available.  clear != 0 drops them. */
+typedef struct {
+    int32_t kind, job, node, xcc;
+    float t_start, t_ready, t_end;
+} tn_task_record;
+tn_status tn_ctx_task_trace(tn_ctx* ctx, tn_task_record* recs, int32_t cap, int32_t* n, int clear);
+
 /* ------------------------------------------------------------- network --- */
 
 /* Independent-set network of a graph (Sec. 3.2): one index per vertex, an
@@ -247,6 +259,10 @@ typedef struct {
     const uint32_t* primes;    /* NULL = default primes (largest primes below 2^31) */
     int32_t slice_begin;       /* run slices [slice_begin, slice_end) only; */
     int32_t slice_end;         /* 0,0 = all slices */
+    int32_t executor;          /* 0 auto: one persistent launch for unsliced trees with
+                                  sc <= 22, per-node stream launches otherwise;
+                                  1 per-node stream launches; 2 persistent launch
+                                  (unsliced plans only) */
 } tn_solve_opts;
 
 void tn_solve_opts_default(tn_solve_opts* opts);

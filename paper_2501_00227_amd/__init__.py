@@ -75,7 +75,7 @@ class tn_plan_info_t(ctypes.Structure):
 class tn_solve_opts(ctypes.Structure):
     _fields_ = [("semiring", ctypes.c_int32), ("beta", ctypes.c_double), ("nprimes", ctypes.c_int32),
                 ("primes", ctypes.POINTER(ctypes.c_uint32)), ("slice_begin", ctypes.c_int32),
-                ("slice_end", ctypes.c_int32)]
+                ("slice_end", ctypes.c_int32), ("executor", ctypes.c_int32)]
 
 
 class tn_result(ctypes.Structure):
@@ -91,6 +91,11 @@ class tn_kernel_record(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("node", ctypes.c_int32), ("semiring", ctypes.c_int32),
                 ("shape", ctypes.c_int32 * 4), ("ms", ctypes.c_float), ("alg_bytes", ctypes.c_double),
                 ("ops", ctypes.c_double)]
+
+
+class tn_task_record(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("job", ctypes.c_int32), ("node", ctypes.c_int32), ("xcc", ctypes.c_int32),
+                ("t_start", ctypes.c_float), ("t_ready", ctypes.c_float), ("t_end", ctypes.c_float)]
 
 
 class tn_server_stats_t(ctypes.Structure):
@@ -109,6 +114,7 @@ SIGNATURES = [
     ("tn_ctx_set_profiling", ctypes.c_int, [_VP, ctypes.c_int]),
     ("tn_ctx_profile", ctypes.c_int, [_VP, _P(tn_kernel_record), ctypes.c_int32, c_int32_p, ctypes.c_int]),
     ("tn_ctx_synchronize", ctypes.c_int, [_VP]),
+    ("tn_ctx_task_trace", ctypes.c_int, [_VP, _P(tn_task_record), ctypes.c_int32, c_int32_p, ctypes.c_int]),
     ("tn_net_independent_set", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, c_int32_p, _P(ctypes.c_float), _P(_VP)]),
     ("tn_net_destroy", None, [_VP]),
     ("tn_net_info", ctypes.c_int, [_VP, c_int32_p, c_int32_p]),
@@ -292,12 +298,16 @@ def _sr(semiring) -> int:
     return SEMIRING[semiring] if isinstance(semiring, str) else int(semiring)
 
 
+EXECUTOR = {"auto": 0, "stream": 1, "persistent": 2}
+
+
 def solve_opts(semiring, beta: float = 0.0, primes: Optional[Sequence[int]] = None,
-               slices: Optional[Sequence[int]] = None) -> tn_solve_opts:
+               slices: Optional[Sequence[int]] = None, executor="auto") -> tn_solve_opts:
     o = tn_solve_opts()
     lib().tn_solve_opts_default(ctypes.byref(o))
     o.semiring = _sr(semiring)
     o.beta = float(beta)
+    o.executor = EXECUTOR.get(executor, executor) if isinstance(executor, str) else int(executor)
     if primes is not None:
         arr = (ctypes.c_uint32 * len(primes))(*primes)
         o.nprimes = len(primes)
@@ -377,11 +387,22 @@ class Context:
                  "shape": list(r.shape), "ms": r.ms, "alg_bytes": r.alg_bytes, "ops": r.ops}
                 for r in recs[: n.value]]
 
+    def task_trace(self, clear: bool = True) -> np.ndarray:
+        """Per-task timeline of persistent launches (profiling on): structured array."""
+        n = ctypes.c_int32()
+        _check(lib().tn_ctx_task_trace(self.h, None, 0, ctypes.byref(n), 0))
+        recs = (tn_task_record * max(n.value, 1))()
+        _check(lib().tn_ctx_task_trace(self.h, recs, n.value, ctypes.byref(n), 1 if clear else 0))
+        dt = np.dtype([("kind", np.int32), ("job", np.int32), ("node", np.int32), ("xcc", np.int32),
+                       ("t_start", np.float32), ("t_ready", np.float32), ("t_end", np.float32)])
+        return np.frombuffer(bytes(recs)[: n.value * dt.itemsize], dtype=dt).copy()
+
     def synchronize(self) -> None:
         _check(lib().tn_ctx_synchronize(self.h))
 
-    def solve(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None) -> Dict:
-        o = solve_opts(semiring, beta, primes, slices)
+    def solve(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None,
+              executor="auto") -> Dict:
+        o = solve_opts(semiring, beta, primes, slices, executor)
         r = tn_result()
         _check(lib().tn_solve(self.h, net.h, plan.h, ctypes.byref(o), ctypes.byref(r)))
         return decode(r)

@@ -3,6 +3,7 @@
 #include <atomic>
 #include <new>
 
+#include "batch_host.h"
 #include "exec.h"
 
 namespace tn {
@@ -110,6 +111,17 @@ tn_status tn_ctx_profile(tn_ctx* c, tn_kernel_record* recs, int32_t cap, int32_t
     if (recs)
         for (int32_t k = 0; k < cap && k < *n; k++) recs[k] = c->records[k];
     if (clear) c->records.clear();
+    return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_ctx_task_trace(tn_ctx* c, tn_task_record* recs, int32_t cap, int32_t* n, int clear) {
+    TN_GUARD_BEGIN
+    if (!c || !n) return fail(TN_EINVAL, "ctx or n is NULL");
+    *n = (int32_t)c->task_trace.size();
+    if (recs)
+        for (int32_t k = 0; k < cap && k < *n; k++) recs[k] = c->task_trace[k];
+    if (clear) c->task_trace.clear();
     return TN_OK;
     TN_GUARD_END
 }
@@ -278,12 +290,15 @@ tn_status tn_plan_peak_bytes(const tn_plan* p, tn_semiring sr, uint64_t* bytes) 
     }
     const Plan& pl = p->plan;
     uint64_t eb = (uint64_t)plane_bytes(dsr, 0) + (uint64_t)plane_bytes(dsr, 1);
+    const bool dag = use_persistent(pl);  // the dependency-graph executor keeps every partial separate
     uint64_t part = 0;
     for (auto& np : pl.prog) {
         GemmShape g = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
-        if (g.lsplit) part = std::max<uint64_t>(part, 1ull << (g.lsplit + np.lb + np.li + np.lj));
+        if (!g.lsplit) continue;
+        uint64_t n = 1ull << (g.lsplit + np.lb + np.li + np.lj);
+        part = dag ? part + ((n + 63) & ~63ull) : std::max<uint64_t>(part, n);
     }
-    uint64_t e = (uint64_t)std::max<int64_t>(pl.arena_entries, 64);
+    uint64_t e = (uint64_t)std::max<int64_t>(dag ? pl.arena_entries_dag : pl.arena_entries, 64);
     *bytes = (e + part) * eb + sizeof(TensorMeta) * pl.nodes.size() + 4ull * pl.nv + 4096 + 8192;
     return TN_OK;
     TN_GUARD_END
@@ -341,13 +356,42 @@ void tn_solve_opts_default(tn_solve_opts* o) {
     o->primes = nullptr;
     o->slice_begin = 0;
     o->slice_end = 0;
+    o->executor = 0;
 }
 
 tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_opts* o, tn_result* out) {
     TN_GUARD_BEGIN
     if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");
     if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    if (o->executor < 0 || o->executor > 2) return fail(TN_EINVAL, "executor must be 0, 1 or 2");
+    bool persistent = o->executor == 2 || (o->executor == 0 && use_persistent(p->plan));
+    if (o->executor == 2 && (!p->plan.sliced.empty() || o->slice_begin || o->slice_end))
+        return fail(TN_EINVAL, "the persistent executor runs unsliced plans only");
+    if (persistent && o->slice_begin == 0 && o->slice_end == 0) {
+        std::vector<BatchItem> items{{&n->net, &p->plan, *o}};
+        std::vector<tn_result> res;
+        tn_status st = solve_batch_sync(c, items, res);
+        if (!res.empty()) *out = res[0];
+        return st;
+    }
     return solve_one(c, n->net, p->plan, *o, *out);
+    TN_GUARD_END
+}
+
+tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const tn_plan* const* plans,
+                         const tn_solve_opts* opts, tn_result* out) {
+    TN_GUARD_BEGIN
+    if (!c || n < 0 || (n > 0 && (!nets || !plans || !opts || !out))) return fail(TN_EINVAL, "NULL argument");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    std::vector<BatchItem> items;
+    for (int32_t i = 0; i < n; i++) {
+        if (!nets[i] || !plans[i]) return fail(TN_EINVAL, "NULL network or plan in the batch");
+        items.push_back({&nets[i]->net, &plans[i]->plan, opts[i]});
+    }
+    std::vector<tn_result> res;
+    tn_status st = solve_batch_sync(c, items, res);
+    for (int32_t i = 0; i < n && i < (int32_t)res.size(); i++) out[i] = res[i];
+    return st;
     TN_GUARD_END
 }
 

@@ -1,0 +1,493 @@
+// Host side of the persistent batched executor: builds the task table of a
+// set of contraction passes, uploads it with one copy, launches one
+// persistent kernel, and decodes the roots.
+#include "batch_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+namespace tn {
+
+namespace {
+
+struct Counter {
+    int id = -1;
+    int need = 0;
+    int level = 0;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// tensors of at most 2^small_rank() entries are contracted inside one task;
+// Fusing trades parallelism inside one job for fewer synchronisations: it
+// pays when a launch holds enough jobs to keep every chiplet busy.
+int small_rank(size_t njobs, int nworkgroups) {
+    static int env = -2;
+    if (env == -2) {
+        const char* e = std::getenv("TN_FUSE_RANK");
+        env = e ? std::atoi(e) : -1;
+    }
+    if (env >= 0) return env;
+    return (int)njobs >= nworkgroups / 4 ? 12 : 0;
+}
+// a large node is cut into at most this many tasks (each loops over tiles)
+constexpr int64_t kMaxTasksPerNode = 64;
+
+int64_t chunk(int64_t ntiles) {  // tiles per task (powers of two divide exactly)
+    int64_t per = 1;
+    while (ntiles / per > kMaxTasksPerNode) per *= 2;
+    return per;
+}
+
+}  // namespace
+
+int device_cu_count(tn_ctx* ctx) {
+    if (ctx->cu_count > 0) return ctx->cu_count;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || n <= 0) n = 256;
+    ctx->cu_count = n;
+    return n;
+}
+
+tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch& L, const DevAllocFn& alloc) {
+    L = BatchLaunch();
+    L.items.resize(items.size());
+    struct JobPlan {
+        int item, pass;
+        const Plan* plan;
+        int dsr;
+        uint32_t prime;
+        DevProgram* dp;
+        const std::vector<NodeLaunch>* nl;
+        int64_t E, Pe;
+        size_t o_arena0, o_arena1, o_part0, o_part1, o_meta, o_acc;
+    };
+    std::vector<JobPlan> jobs;
+    std::vector<size_t> item_w_off(items.size(), 0);
+    size_t data = 0;
+    // weights of every item first, so one contiguous copy uploads them
+    for (size_t i = 0; i < items.size(); i++) {
+        if (!items[i].net->w.empty()) {
+            item_w_off[i] = data;
+            data = a256(data + sizeof(float) * items[i].net->w.size());
+        }
+    }
+    const size_t weights_end = data;
+    // ---- per item: passes and device programs; lay out device memory
+    for (size_t i = 0; i < items.size(); i++) {
+        BatchItem& it = items[i];
+        ItemState& st = L.items[i];
+        st.opts = it.opts;
+        st.status = TN_OK;
+        if (it.plan->fingerprint != it.net->fingerprint || it.plan->nv != it.net->nv) {
+            st.status = fail(TN_EINVAL, "plan was built for a different network");
+            continue;
+        }
+        if (!it.plan->sliced.empty()) {
+            st.status = fail(TN_EINVAL, "batched jobs must not be sliced; use tn_solve for sliced plans");
+            continue;
+        }
+        tn_status s = make_passes(*it.net, it.opts, st.passes);
+        if (s != TN_OK) {
+            st.status = s;
+            continue;
+        }
+        DevProgram* dp = nullptr;
+        if (it.plan->nleaf() > 0) {
+            s = get_program(ctx, *it.plan, dp);
+            if (s != TN_OK) {
+                st.status = s;
+                continue;
+            }
+        }
+        for (size_t p = 0; p < st.passes.size(); p++) {
+            JobPlan jp{};
+            jp.item = (int)i;
+            jp.pass = (int)p;
+            jp.plan = it.plan;
+            jp.dsr = st.passes[p].dsr;
+            jp.prime = st.passes[p].prime;
+            jp.dp = dp;
+            jp.nl = dp ? &node_launches(*dp, *it.plan, jp.dsr) : nullptr;
+            jp.E = std::max<int64_t>(it.plan->arena_entries_dag, 64);
+            jp.Pe = dp ? dp->part_entries_dag[jp.dsr] : 0;
+            int pb0 = plane_bytes(jp.dsr, 0), pb1 = plane_bytes(jp.dsr, 1);
+            jp.o_arena0 = data;
+            data = a256(data + (size_t)jp.E * pb0);
+            jp.o_arena1 = data;
+            data = a256(data + (size_t)jp.E * pb1);
+            jp.o_part0 = data;
+            data = a256(data + (size_t)jp.Pe * pb0);
+            jp.o_part1 = data;
+            data = a256(data + (size_t)jp.Pe * pb1);
+            jp.o_meta = data;
+            data = a256(data + sizeof(TensorMeta) * (size_t)std::max<size_t>(it.plan->nodes.size(), 1));
+            jp.o_acc = data;
+            data = a256(data + 16);
+            st.job_ids.push_back((int)jobs.size());
+            jobs.push_back(jp);
+        }
+    }
+    L.njobs = (int)jobs.size();
+    if (jobs.empty()) return TN_OK;
+    L.data_bytes = std::max<size_t>(data, 256);
+    L.data = alloc.alloc(L.data_bytes);
+    if (!L.data) return fail(TN_ENOMEM, "device allocation of " + std::to_string(L.data_bytes) + " bytes failed");
+    L.free_fn = alloc.free;
+    unsigned char* dbase = (unsigned char*)L.data;
+
+    // ---- task table
+    std::vector<BJob> bj(jobs.size());
+    std::vector<BNode> bn;
+    std::vector<BTask> bt;
+    std::vector<int> level;
+    int ncounters = 0;
+    const int fuse_rank = small_rank(jobs.size(), device_cu_count(ctx) * 2);
+    for (size_t ji = 0; ji < jobs.size(); ji++) {
+        JobPlan& jp = jobs[ji];
+        const Plan& p = *jp.plan;
+        BJob& J = bj[ji];
+        J.dsr = jp.dsr;
+        J.nleaf = p.nleaf();
+        J.nnode = (int)p.nodes.size();
+        J.root = J.nnode - 1;
+        J.ap = algebra_params(jp.dsr, jp.prime, items[jp.item].opts.beta);
+        J.arena.p0 = dbase + jp.o_arena0;
+        J.arena.p1 = plane_bytes(jp.dsr, 1) ? dbase + jp.o_arena1 : nullptr;
+        J.part.p0 = dbase + jp.o_part0;
+        J.part.p1 = plane_bytes(jp.dsr, 1) ? dbase + jp.o_part1 : nullptr;
+        const bool isz = jp.dsr == DSR_Z_F32 || jp.dsr == DSR_Z_BF16;
+        J.meta = isz ? (TensorMeta*)(dbase + jp.o_meta) : nullptr;
+        J.acc = dbase + jp.o_acc;
+        J.leaves = jp.dp ? jp.dp->leaves : nullptr;
+        J.spos = jp.dp ? jp.dp->slice_pos : nullptr;
+        J.w = items[jp.item].net->w.empty() ? nullptr : (const float*)(dbase + item_w_off[jp.item]);
+        auto add = [&](int kind, int node, int aux, int64_t tile, Counter d0, Counter d1, int signal, int lvl,
+                       int count = 1) {
+            BTask t;
+            t.kind = kind;
+            t.job = (int)ji;
+            t.node = node;
+            t.aux = aux;
+            t.tile = tile;
+            t.dep0 = d0.id;
+            t.need0 = d0.need;
+            t.dep1 = d1.id;
+            t.need1 = d1.need;
+            t.signal = signal;
+            t.count = count;
+            bt.push_back(t);
+            level.push_back(lvl);
+        };
+        if (J.nleaf == 0) {
+            add(BT_ONE, -1, 0, 0, Counter(), Counter(), -1, 0);
+            continue;
+        }
+        const int nleaf = J.nleaf;
+        Counter leaves_done{ncounters++, 1, 0};
+        add(BT_LEAVES, -1, 0, 0, Counter(), Counter(), leaves_done.id, 0);
+        std::vector<Counter> final_of(p.nodes.size());
+        for (int l = 0; l < nleaf; l++) final_of[l] = leaves_done;
+        const int npl = plane_bytes(jp.dsr, 1) ? 2 : 1;
+        // small subtrees (every tensor <= 2^fuse_rank entries) run as one
+        // task each: one workgroup contracts the whole subtree in order
+        const int ninner = (int)p.prog.size();
+        std::vector<char> small(ninner, 0);
+        std::vector<int> parent_t(p.nodes.size(), -1);
+        for (int t = 0; t < ninner; t++) {
+            const NodeProg& np = p.prog[t];
+            parent_t[np.a] = parent_t[np.b] = t;
+            int r = std::max({(int)p.order[np.a].size(), (int)p.order[np.b].size(), (int)p.order[np.node].size()});
+            bool ok = r <= fuse_rank;
+            for (int ch : {np.a, np.b})
+                if (ch >= nleaf && !small[ch - nleaf]) ok = false;
+            small[t] = ok;
+        }
+        const int bn0 = (int)bn.size();
+        for (int t = 0; t < ninner; t++) {
+            const NodeProg& np = p.prog[t];
+            const NodeLaunch& nl = (*jp.nl)[t];
+            BNode N{};
+            N.g = nl.shape;
+            N.job = (int)ji;
+            N.ma = np.a;
+            N.mb = np.b;
+            N.mc = np.node;
+            N.a_off = np.perm_a ? np.dag_a_tmp : p.node_off_dag[np.a];
+            N.b_off = np.perm_b ? np.dag_b_tmp : p.node_off_dag[np.b];
+            N.c_off = np.dag_c_off;
+            N.nout = (int64_t)1 << (N.g.lb + N.g.li + N.g.lj);
+            N.reduce_per_block = N.nout < 1024 ? 1 : 0;
+            N.part_off = jp.dp->part_off_dag[jp.dsr][t];
+            for (int side = 0; side < 2; side++) {
+                int child = side ? np.b : np.a;
+                bool perm = side ? np.perm_b : np.perm_a;
+                N.pp[side] = nullptr;
+                if (!perm) continue;
+                int slot = side ? jp.dp->perm_slot_b[t] : jp.dp->perm_slot_a[t];
+                int rank = (int)p.order[child].size();
+                N.pp[side] = jp.dp->perms + slot;
+                N.psrc[side] = p.node_off_dag[child];
+                N.pdst[side] = side ? np.dag_b_tmp : np.dag_a_tmp;
+                N.prank[side] = rank;
+                N.ptile_bits[side] = rank < 11 ? rank : 11;
+            }
+            L.total_ops += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk));
+            L.total_bytes += (std::exp2((double)(N.g.lb + N.g.li + N.g.lk)) + std::exp2((double)(N.g.lb + N.g.lk + N.g.lj)) +
+                              std::exp2((double)(N.g.lb + N.g.li + N.g.lj))) *
+                             (plane_bytes(jp.dsr, 0) + plane_bytes(jp.dsr, 1));
+            bn.push_back(N);
+            if (small[t]) {
+                bool sub_root = parent_t[np.node] < 0 || !small[parent_t[np.node]];
+                if (!sub_root) continue;
+                // collect the subtree's inner nodes in execution order
+                std::vector<int> stack{t}, members;
+                while (!stack.empty()) {
+                    int u = stack.back();
+                    stack.pop_back();
+                    members.push_back(u);
+                    for (int ch : {p.prog[u].a, p.prog[u].b})
+                        if (ch >= nleaf) stack.push_back(ch - nleaf);
+                }
+                std::sort(members.begin(), members.end());
+                int off = (int)L.subtree_list.size();
+                for (int u : members) L.subtree_list.push_back(bn0 + u);
+                Counter done{ncounters++, 1, leaves_done.level + 1};
+                add(BT_SUBTREE, off, (int)members.size(), 0, leaves_done, Counter(), done.id, done.level);
+                final_of[np.node] = done;
+                continue;
+            }
+            const int nidx = bn0 + t;
+            Counter ready[2];
+            for (int side = 0; side < 2; side++) {
+                int child = side ? np.b : np.a;
+                if (!N.pp[side]) {
+                    ready[side] = final_of[child];
+                    continue;
+                }
+                int64_t ntiles = (int64_t)1 << (N.prank[side] - N.ptile_bits[side]);
+                int64_t per = chunk(ntiles);
+                int64_t ntask = ntiles / per;
+                Counter c{ncounters++, (int)(ntask * npl), final_of[child].level + 1};
+                for (int pl = 0; pl < npl; pl++)
+                    for (int64_t k = 0; k < ntask; k++)
+                        add(BT_PERM, nidx, side * 2 + pl, k * per, final_of[child], Counter(), c.id, c.level, (int)per);
+                ready[side] = c;
+            }
+            int64_t nblocks = (int64_t)1 << ((N.g.lb - N.g.tb) + (N.g.li - N.g.ti) + (N.g.lj - N.g.tj) + N.g.lsplit);
+            int64_t per = chunk(nblocks);
+            Counter gdone{ncounters++, (int)(nblocks / per), std::max(ready[0].level, ready[1].level) + 1};
+            for (int64_t k = 0; k < nblocks / per; k++)
+                add(BT_GEMM, nidx, 0, k * per, ready[0], ready[1], gdone.id, gdone.level, (int)per);
+            Counter fin = gdone;
+            if (N.g.lsplit > 0) {
+                int64_t nred = N.reduce_per_block ? N.nout : (N.nout + 255) / 256;
+                int64_t rper = 1;
+                while (nred / rper > kMaxTasksPerNode) rper *= 2;
+                int64_t nrt = (nred + rper - 1) / rper;
+                Counter rdone{ncounters++, (int)nrt, gdone.level + 1};
+                for (int64_t k = 0; k < nrt; k++)
+                    add(BT_REDUCE, nidx, 0, k * rper, gdone, Counter(), rdone.id, rdone.level,
+                        (int)std::min<int64_t>(rper, nred - k * rper));
+                fin = rdone;
+            }
+            final_of[np.node] = fin;
+        }
+        int root = (int)p.nodes.size() - 1;
+        add(BT_ACCUM, -1, 0, p.node_off_dag[root], final_of[root], Counter(), -1, final_of[root].level + 1);
+    }
+    // every job goes to one XCC queue (longest-processing-time first on the
+    // estimated work: semiring ops plus a fixed cost per task)
+    const int nq = std::max(1, std::min(16, device_cu_count(ctx) / 32));
+    std::vector<double> job_work(jobs.size(), 0.0);
+    for (size_t k = 0; k < bt.size(); k++) job_work[bt[k].job] += 2.0e4;
+    for (auto& N : bn)
+        job_work[N.job] += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk)) * (N.g.rm == 4 ? 0.5 : 1.0);
+    std::vector<int> jq(jobs.size(), 0), jorder(jobs.size());
+    for (size_t k = 0; k < jorder.size(); k++) jorder[k] = (int)k;
+    std::stable_sort(jorder.begin(), jorder.end(), [&](int a, int b) { return job_work[a] > job_work[b]; });
+    std::vector<double> qload(nq, 0.0);
+    for (int j : jorder) {
+        int best = (int)(std::min_element(qload.begin(), qload.end()) - qload.begin());
+        jq[j] = best;
+        qload[best] += job_work[j];
+    }
+    // ticket order inside a queue = dependency level order (stable: job / node / tile)
+    std::vector<int> order(bt.size());
+    for (size_t k = 0; k < order.size(); k++) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        int qa = jq[bt[a].job], qb = jq[bt[b].job];
+        return qa != qb ? qa < qb : level[a] < level[b];
+    });
+    std::vector<BTask> sorted(bt.size());
+    for (size_t k = 0; k < order.size(); k++) sorted[k] = bt[order[k]];
+    L.ntasks = (int)sorted.size();
+    L.nq = nq;
+    L.qbegin.assign(nq, 0);
+    L.qcount.assign(nq, 0);
+    for (auto& t : sorted) L.qcount[jq[t.job]]++;
+    for (int q = 1; q < nq; q++) L.qbegin[q] = L.qbegin[q - 1] + L.qcount[q - 1];
+    if (ctx->profiling) L.host_tasks = sorted;
+
+    // ---- one upload: jobs | nodes | tasks | counters + ticket | weights
+    size_t o_jobs = 0;
+    size_t o_nodes = a256(o_jobs + sizeof(BJob) * bj.size());
+    size_t o_tasks = a256(o_nodes + sizeof(BNode) * std::max<size_t>(bn.size(), 1));
+    size_t o_cnt = a256(o_tasks + sizeof(BTask) * sorted.size());
+    size_t o_sub = a256(o_cnt + sizeof(int) * (size_t)ncounters);
+    size_t o_q = a256(o_sub + sizeof(int) * std::max<size_t>(L.subtree_list.size(), 1));  // qbegin | qcount | tickets
+    size_t o_trace = a256(o_q + sizeof(int) * 3 * (size_t)nq);
+    size_t o_end = ctx->profiling ? a256(o_trace + 32 * sorted.size()) : o_trace;
+    L.table_bytes = o_end;
+    L.tables = alloc.alloc(L.table_bytes);
+    if (!L.tables) return fail(TN_ENOMEM, "device allocation of the task table failed");
+    size_t wbytes = weights_end;
+    L.host_bytes = o_end + wbytes + 16 * jobs.size() + sizeof(int) * nq + 1024;
+    if (hipHostMalloc(&L.host, L.host_bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(TN_ENOMEM, "pinned staging allocation failed");
+    unsigned char* h = (unsigned char*)L.host;
+    std::memset(h, 0, o_end);
+    std::memcpy(h + o_jobs, bj.data(), sizeof(BJob) * bj.size());
+    if (!bn.empty()) std::memcpy(h + o_nodes, bn.data(), sizeof(BNode) * bn.size());
+    std::memcpy(h + o_tasks, sorted.data(), sizeof(BTask) * sorted.size());
+    if (!L.subtree_list.empty()) std::memcpy(h + o_sub, L.subtree_list.data(), sizeof(int) * L.subtree_list.size());
+    std::memcpy(h + o_q, L.qbegin.data(), sizeof(int) * nq);
+    std::memcpy(h + o_q + sizeof(int) * nq, L.qcount.data(), sizeof(int) * nq);
+    unsigned char* d = (unsigned char*)L.tables;
+    L.d_jobs = (BJob*)(d + o_jobs);
+    L.d_nodes = (BNode*)(d + o_nodes);
+    L.d_tasks = (BTask*)(d + o_tasks);
+    L.d_counters = (int*)(d + o_cnt);
+    L.d_subtree = (int*)(d + o_sub);
+    L.d_qbegin = (int*)(d + o_q);
+    L.d_qcount = L.d_qbegin + nq;
+    L.d_ticket = L.d_qbegin + 2 * nq;
+    L.d_trace = ctx->profiling ? (unsigned long long*)(d + o_trace) : nullptr;
+    L.o_wstage = o_end;
+    for (size_t i = 0; i < items.size(); i++)
+        if (!items[i].net->w.empty())
+            std::memcpy(h + o_end + item_w_off[i], items[i].net->w.data(), sizeof(float) * items[i].net->w.size());
+    L.wbytes = wbytes;
+    L.o_hacc = o_end + wbytes;
+    L.o_hticket = a256(L.o_hacc + 16 * jobs.size());
+    L.accs.resize(jobs.size());
+    for (size_t ji = 0; ji < jobs.size(); ji++) L.accs[ji] = dbase + jobs[ji].o_acc;
+    return TN_OK;
+}
+
+tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
+    if (L.njobs == 0) return TN_OK;
+    hipError_t e = hipMemcpyAsync(L.tables, L.host, L.table_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && L.wbytes)
+        e = hipMemcpyAsync(L.data, (unsigned char*)L.host + L.o_wstage, L.wbytes, hipMemcpyHostToDevice, s);
+    // two workgroups per CU: every XCC serves its queue
+    int nwg = device_cu_count(ctx) * 2;
+    if (e == hipSuccess) {
+        int shape[4] = {0, 0, 0, 0};
+        ProfScope ps(ctx, TN_K_BATCH, -1, -1, shape, L.total_bytes, L.total_ops);
+        e = launch_batch(L.d_tasks, L.d_qbegin, L.d_qcount, L.nq, L.d_jobs, L.d_nodes, L.d_subtree, L.d_counters,
+                         L.d_ticket, nwg, L.d_trace, s);
+    }
+    // the tickets come back with the roots: a queue whose tickets did not all
+    // go out was not served, and its jobs' results are not valid
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((unsigned char*)L.host + L.o_hticket, L.d_ticket, sizeof(int) * L.nq, hipMemcpyDeviceToHost, s);
+    for (int j = 0; j < L.njobs && e == hipSuccess; j++)
+        e = hipMemcpyAsync((unsigned char*)L.host + L.o_hacc + 16 * j, L.accs[j], 16, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail(TN_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
+    return TN_OK;
+}
+
+tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out) {
+    out.assign(L.items.size(), tn_result{});
+    tn_status first = TN_OK;
+    for (int q = 0; q < L.nq && L.njobs > 0; q++) {
+        int served = ((const int*)((unsigned char*)L.host + L.o_hticket))[q];
+        if (L.qcount[q] > 0 && served < L.qcount[q]) {
+            for (auto& st : L.items)
+                if (st.status == TN_OK) st.status = fail(TN_EDEVICE, "a chiplet queue of the persistent launch was not served");
+        }
+    }
+    for (size_t i = 0; i < L.items.size(); i++) {
+        ItemState& st = L.items[i];
+        tn_status s = st.status;
+        if (s == TN_OK) {
+            std::vector<std::vector<unsigned char>> accs;
+            for (int j : st.job_ids) {
+                std::vector<unsigned char> a(16);
+                std::memcpy(a.data(), (unsigned char*)L.host + L.o_hacc + 16 * j, 16);
+                accs.push_back(a);
+            }
+            s = decode_result(st.opts, st.passes, accs, out[i]);
+        }
+        if (s != TN_OK) {
+            out[i].semiring = -1;
+            if (first == TN_OK) first = s;
+        }
+        st.status = s;
+    }
+    return first;
+}
+
+void batch_release(BatchLaunch& L) {
+    if (L.free_fn) {
+        if (L.data) L.free_fn(L.data, L.data_bytes);
+        if (L.tables) L.free_fn(L.tables, L.table_bytes);
+    }
+    if (L.host) (void)hipHostFree(L.host);
+    L.data = L.tables = L.host = nullptr;
+}
+
+void collect_trace(tn_ctx* ctx, BatchLaunch& L) {
+    std::vector<unsigned long long> tr(4 * (size_t)L.ntasks);
+    if (hipMemcpy(tr.data(), L.d_trace, 32 * (size_t)L.ntasks, hipMemcpyDeviceToHost) != hipSuccess) return;
+    unsigned long long t0 = ~0ull;
+    for (int k = 0; k < L.ntasks; k++) t0 = std::min(t0, tr[4 * k]);
+    const double us_per_tick = 0.01;  // wall_clock64 runs at 100 MHz
+    for (int k = 0; k < L.ntasks; k++) {
+        tn_task_record r;
+        r.kind = L.host_tasks[k].kind;
+        r.job = L.host_tasks[k].job;
+        r.node = L.host_tasks[k].node;
+        r.xcc = (int32_t)tr[4 * k + 3];
+        r.t_start = (float)((tr[4 * k] - t0) * us_per_tick);
+        r.t_ready = (float)((tr[4 * k + 1] - t0) * us_per_tick);
+        r.t_end = (float)((tr[4 * k + 2] - t0) * us_per_tick);
+        ctx->task_trace.push_back(r);
+    }
+}
+
+tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out) {
+    auto t0 = std::chrono::steady_clock::now();
+    DevAllocFn alloc;
+    alloc.alloc = [ctx](size_t n) { return dev_alloc(ctx, n); };
+    alloc.free = [ctx](void* p, size_t n) { dev_free(ctx, p, n); };
+    BatchLaunch L;
+    tn_status st = batch_prepare(ctx, items, L, alloc);
+    if (st == TN_OK) st = batch_launch(ctx, L, ctx->stream);
+    if (st == TN_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(TN_EDEVICE, "batch execution failed");
+    tn_status st2 = TN_OK;
+    if (st == TN_OK) st2 = batch_finish(L, out);
+    if (st == TN_OK && L.d_trace) collect_trace(ctx, L);
+    if (L.host) (void)hipStreamSynchronize(ctx->stream);
+    batch_release(L);
+    double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (auto& r : out) r.seconds = sec;
+    return st != TN_OK ? st : st2;
+}
+
+bool use_persistent(const Plan& p) {
+    static int mode = -2;
+    if (mode == -2) {
+        const char* e = std::getenv("TN_EXEC");
+        mode = !e ? -1 : (std::strcmp(e, "stream") == 0 ? 0 : (std::strcmp(e, "persistent") == 0 ? 1 : -1));
+    }
+    if (!p.sliced.empty()) return false;
+    if (mode >= 0) return mode == 1;
+    return p.max_rank <= 22;  // small trees: launch overhead dominates the per-node path
+}
+
+}  // namespace tn

@@ -1,0 +1,73 @@
+// Host interface of the persistent batched executor (batch.cpp), used by
+// tn_solve (small trees), tn_solve_batch and the server.
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "batch.h"
+#include "exec.h"
+
+namespace tn {
+
+struct BatchItem {
+    const Net* net;
+    const Plan* plan;
+    tn_solve_opts opts;
+};
+
+struct ItemState {
+    tn_solve_opts opts{};
+    std::vector<PassSpec> passes;
+    std::vector<int> job_ids;  // one job per pass
+    tn_status status = TN_OK;
+};
+
+struct DevAllocFn {
+    std::function<void*(size_t)> alloc;
+    std::function<void(void*, size_t)> free;
+};
+
+// Everything one persistent launch owns until it is finished and released.
+struct BatchLaunch {
+    std::vector<ItemState> items;
+    int njobs = 0, ntasks = 0;
+    void* data = nullptr;    // arenas, partials, meta, accumulators, weights
+    size_t data_bytes = 0;
+    void* tables = nullptr;  // jobs, nodes, tasks, counters
+    size_t table_bytes = 0;
+    void* host = nullptr;    // pinned staging: tables, weights, returned accumulators
+    size_t host_bytes = 0, o_wstage = 0, wbytes = 0, o_hacc = 0;
+    BJob* d_jobs = nullptr;
+    BNode* d_nodes = nullptr;
+    BTask* d_tasks = nullptr;
+    int* d_counters = nullptr;
+    int* d_ticket = nullptr;  // one ticket per XCC queue
+    int* d_qbegin = nullptr;
+    int* d_qcount = nullptr;
+    int* d_subtree = nullptr;  // BNode indices of the fused small subtrees
+    std::vector<int> subtree_list;
+    int nq = 1;
+    std::vector<int> qbegin, qcount;
+    size_t o_hticket = 0;
+    std::vector<void*> accs;  // device accumulator of every job
+    double total_ops = 0, total_bytes = 0;  // algorithmic work of the launch
+    unsigned long long* d_trace = nullptr;  // per-task timestamps (profiling)
+    std::vector<BTask> host_tasks;          // kept for the trace
+    std::function<void(void*, size_t)> free_fn;
+};
+
+int device_cu_count(tn_ctx* ctx);
+// Build and upload nothing yet: lay out memory, allocate, fill the staging.
+tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch& L, const DevAllocFn& alloc);
+// Enqueue upload, the persistent kernel and the root read-back on stream s.
+tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s);
+// After the stream has passed the launch: decode every item's result.
+tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out);
+void batch_release(BatchLaunch& L);
+void collect_trace(tn_ctx* ctx, BatchLaunch& L);
+tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out);
+// Route a single unsliced small tree through the persistent launch.
+bool use_persistent(const Plan& p);
+
+}  // namespace tn

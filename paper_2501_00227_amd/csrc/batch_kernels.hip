@@ -1,0 +1,258 @@
+// Persistent batched kernel: executes a task table of many contraction
+// passes in one launch (see batch.h for the task model).
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "kernels_dev.h"
+
+namespace tn {
+
+// bytes of dynamic LDS: the largest GEMM tile, a permute tile of 8-byte
+// entries with its tables, or a 256-entry reduction buffer
+constexpr size_t kBatchLds = 48 * 1024;
+
+size_t batch_lds_bytes() { return kBatchLds; }
+
+// All tasks of one job run on the same XCC (the host assigns every job to
+// one chiplet's queue and a workgroup serves the queue of the XCC it runs
+// on), so producer and consumer share that XCC's L2: a task's results are
+// visible to the next task once its stores have reached L2 (vmcnt drained)
+// and the consumer's CU has dropped its L1 lines.  The counters themselves
+// are device-scope atomics.
+__device__ inline void wait_counters(const int* counters, int d0, int n0, int d1, int n1) {
+    if (threadIdx.x == 0) {
+        if (d0 >= 0)
+            while (__hip_atomic_load(&counters[d0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n0)
+                __builtin_amdgcn_s_sleep(1);
+        if (d1 >= 0)
+            while (__hip_atomic_load(&counters[d1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n1)
+                __builtin_amdgcn_s_sleep(1);
+    }
+    __syncthreads();
+    asm volatile("buffer_inv sc0" ::: "memory");  // this CU's L1: refetch from the XCC's L2
+}
+
+__device__ inline void signal_counter(int* counters, int c) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached L2
+    __syncthreads();
+    if (threadIdx.x == 0 && c >= 0) __hip_atomic_fetch_add(&counters[c], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int D>
+__device__ void run_gemm(const BJob& j, const BNode& nd, i64 tile, unsigned char* smem) {
+    auto at = [&](int64_t off) {
+        Planes r;
+        r.p0 = (unsigned char*)j.arena.p0 + off * plane_bytes_dev<D>(0);
+        r.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.arena.p1 + off * plane_bytes_dev<D>(1) : nullptr;
+        return r;
+    };
+    GemmArgs g;
+    g.A = at(nd.a_off);
+    g.B = at(nd.b_off);
+    g.C = at(nd.c_off);
+    g.P.p0 = (unsigned char*)j.part.p0 + nd.part_off * plane_bytes_dev<D>(0);
+    g.P.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.part.p1 + nd.part_off * plane_bytes_dev<D>(1) : nullptr;
+    g.lb = nd.g.lb;
+    g.li = nd.g.li;
+    g.lj = nd.g.lj;
+    g.lk = nd.g.lk;
+    g.a_t = nd.g.a_t;
+    g.b_t = nd.g.b_t;
+    g.tb = nd.g.tb;
+    g.ti = nd.g.ti;
+    g.tj = nd.g.tj;
+    g.tk = nd.g.tk;
+    g.lsplit = nd.g.lsplit;
+    g.ap = j.ap;
+    g.meta = j.meta;
+    g.ma = nd.ma;
+    g.mb = nd.mb;
+    g.mc = nd.mc;
+    const int rm = nd.g.rm, rn = nd.g.rn;
+    if (rm == 2 && rn == 2)
+        gemm_tile<D, 2, 2>(g, (u64)tile, smem);
+    else if (rm == 4 && rn == 4)
+        gemm_tile<D, 4, 4>(g, (u64)tile, smem);
+    else if (rm == 1 && rn == 2)
+        gemm_tile<D, 1, 2>(g, (u64)tile, smem);
+    else if (rm == 2 && rn == 1)
+        gemm_tile<D, 2, 1>(g, (u64)tile, smem);
+    else
+        gemm_tile<D, 1, 1>(g, (u64)tile, smem);
+}
+
+// stores of this workgroup visible to its own later loads (same CU)
+__device__ inline void local_step_sync() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    asm volatile("buffer_inv sc0" ::: "memory");
+}
+
+template <int D>
+__device__ void run_perm(const BJob& j, const BNode& nd, int side, int plane, i64 first, int count,
+                         unsigned char* smem) {
+    PermLds* tabs = (PermLds*)smem;
+    perm_load_tables(tabs, nd.pp[side]);
+    __syncthreads();
+    const int pb = plane_bytes_dev<D>(plane);
+    unsigned char* base = (unsigned char*)(plane ? j.arena.p1 : j.arena.p0);
+    unsigned char* tile = smem + ((sizeof(PermLds) + 255) & ~(size_t)255);
+    const int nt = nd.prank[side] - nd.ptile_bits[side];
+    for (int k = 0; k < count; k++) {
+        if (pb == 4)
+            permute_tile<unsigned int>((const unsigned int*)(base + nd.psrc[side] * 4),
+                                       (unsigned int*)(base + nd.pdst[side] * 4), tabs, (unsigned int*)tile,
+                                       nd.ptile_bits[side], nt, first + k);
+        else
+            permute_tile<u64>((const u64*)(base + nd.psrc[side] * 8), (u64*)(base + nd.pdst[side] * 8), tabs,
+                              (u64*)tile, nd.ptile_bits[side], nt, first + k);
+    }
+}
+
+template <int D>
+__device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count, unsigned char* smem) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    Planes C, P;
+    C.p0 = (unsigned char*)j.arena.p0 + nd.c_off * plane_bytes_dev<D>(0);
+    C.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.arena.p1 + nd.c_off * plane_bytes_dev<D>(1) : nullptr;
+    P.p0 = (unsigned char*)j.part.p0 + nd.part_off * plane_bytes_dev<D>(0);
+    P.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.part.p1 + nd.part_off * plane_bytes_dev<D>(1) : nullptr;
+    for (int k = 0; k < count; k++) {
+        const i64 unit = first + k;
+        if (nd.reduce_per_block) {
+            split_reduce_one<D>(P, C, nd.nout, nd.g.lsplit, j.ap, j.meta, nd.mc, unit, (V*)smem);
+        } else {
+            i64 o = unit * 256 + threadIdx.x;
+            float lmax = 0.0f;
+            if (o < nd.nout) {
+                V acc = A::zero(j.ap);
+                for (int s = 0; s < (1 << nd.g.lsplit); s++) acc = A::add(acc, A::load(P, (i64)s * nd.nout + o), j.ap);
+                A::store(C, o, acc);
+                if constexpr (is_z<D>()) lmax = acc;
+            }
+            if constexpr (is_z<D>()) {
+                for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
+                if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(j.meta, nd.mc, __float_as_uint(lmax));
+            }
+        }
+    }
+}
+
+// one inner node, start to end, by this workgroup alone
+template <int D>
+__device__ void run_node_whole(const BJob& j, const BNode& nd, unsigned char* smem) {
+    const int npl = plane_bytes_dev<D>(1) ? 2 : 1;
+    bool any = false;
+    for (int side = 0; side < 2; side++) {
+        if (!nd.pp[side]) continue;
+        const int ntiles = 1 << (nd.prank[side] - nd.ptile_bits[side]);
+        for (int pl = 0; pl < npl; pl++) run_perm<D>(j, nd, side, pl, 0, ntiles, smem);
+        any = true;
+    }
+    if (any) local_step_sync();
+    const int nblocks = 1 << ((nd.g.lb - nd.g.tb) + (nd.g.li - nd.g.ti) + (nd.g.lj - nd.g.tj) + nd.g.lsplit);
+    for (int k = 0; k < nblocks; k++) run_gemm<D>(j, nd, k, smem);
+    local_step_sync();
+    if (nd.g.lsplit > 0) {
+        const i64 nred = nd.reduce_per_block ? nd.nout : (nd.nout + 255) / 256;
+        run_reduce<D>(j, nd, 0, (int)nred, smem);
+        local_step_sync();
+    }
+}
+
+template <int D>
+__device__ void run_task(const BTask& t, const BJob& j, const BNode* nodes, const int* subtree, unsigned char* smem) {
+    switch (t.kind) {
+    case BT_LEAVES: {
+        // fresh partition-function bookkeeping for every node, then the leaves
+        if (j.meta)
+            for (int i = threadIdx.x; i < j.nnode; i += blockDim.x) meta_set(j.meta, i, 0, 0u);
+        __syncthreads();
+        for (int l = threadIdx.x; l < j.nleaf; l += blockDim.x) leaf_dispatch<D>(j.leaves[l], l, j.w, j.spos, 0ull, j.arena, j.ap, j.meta);
+        break;
+    }
+    case BT_PERM: run_perm<D>(j, nodes[t.node], t.aux >> 1, t.aux & 1, t.tile, t.count, smem); break;
+    case BT_GEMM:
+        for (int k = 0; k < t.count; k++) run_gemm<D>(j, nodes[t.node], t.tile + k, smem);
+        break;
+    case BT_REDUCE: run_reduce<D>(j, nodes[t.node], t.tile, t.count, smem); break;
+    case BT_SUBTREE:
+        for (int k = 0; k < t.aux; k++) run_node_whole<D>(j, nodes[subtree[t.node + k]], smem);
+        break;
+    case BT_ACCUM: {
+        if (threadIdx.x == 0) {
+            // the root's tensor sits at the arena offset carried in the tile field
+            Planes r;
+            int64_t off = t.tile;
+            r.p0 = (unsigned char*)j.arena.p0 + off * plane_bytes_dev<D>(0);
+            r.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.arena.p1 + off * plane_bytes_dev<D>(1) : nullptr;
+            accumulate_one<D>(r, j.root, j.meta, j.acc, 1, j.ap);
+        }
+        break;
+    }
+    case BT_ONE: {
+        if (threadIdx.x == 0) set_one<D>(j.acc, j.ap);
+        break;
+    }
+    default: break;
+    }
+}
+
+__device__ inline unsigned int hw_xcc_id() {
+    unsigned int x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & 0xfu;
+}
+
+__global__ __launch_bounds__(256) void batch_kernel(const BTask* __restrict__ tasks, const int* __restrict__ qbegin,
+                                                    const int* __restrict__ qcount, int nq,
+                                                    const BJob* __restrict__ jobs, const BNode* __restrict__ nodes,
+                                                    const int* __restrict__ subtree, int* counters, int* tickets,
+                                                    unsigned long long* trace) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_task;
+    const int q = (int)(hw_xcc_id() % (unsigned)nq);
+    const int qb = qbegin[q], qn = qcount[q];
+    for (;;) {
+        if (threadIdx.x == 0) s_task = atomicAdd(&tickets[q], 1);
+        __syncthreads();
+        const int tq = s_task;
+        __syncthreads();
+        if (tq >= qn) break;  // every workgroup leaves once its queue's tickets run out
+        const int ti = qb + tq;
+        const unsigned long long t_start = trace ? wall_clock64() : 0ull;
+        const BTask t = tasks[ti];
+        wait_counters(counters, t.dep0, t.need0, t.dep1, t.need1);
+        const unsigned long long t_ready = trace ? wall_clock64() : 0ull;
+        const BJob& j = jobs[t.job];
+        switch (j.dsr) {
+        case DSR_TROP_I32: run_task<DSR_TROP_I32>(t, j, nodes, subtree, smem); break;
+        case DSR_TROP_F32: run_task<DSR_TROP_F32>(t, j, nodes, subtree, smem); break;
+        case DSR_CTROP: run_task<DSR_CTROP>(t, j, nodes, subtree, smem); break;
+        case DSR_U64: run_task<DSR_U64>(t, j, nodes, subtree, smem); break;
+        case DSR_MODP: run_task<DSR_MODP>(t, j, nodes, subtree, smem); break;
+        case DSR_Z_F32: run_task<DSR_Z_F32>(t, j, nodes, subtree, smem); break;
+        case DSR_Z_BF16: run_task<DSR_Z_BF16>(t, j, nodes, subtree, smem); break;
+        default: break;
+        }
+        signal_counter(counters, t.signal);
+        if (trace && threadIdx.x == 0) {
+            trace[4 * (size_t)ti + 0] = t_start;
+            trace[4 * (size_t)ti + 1] = t_ready;
+            trace[4 * (size_t)ti + 2] = wall_clock64();
+            trace[4 * (size_t)ti + 3] = hw_xcc_id();
+        }
+    }
+}
+
+hipError_t launch_batch(const BTask* tasks, const int* qbegin, const int* qcount, int nq, const BJob* jobs,
+                        const BNode* nodes, const int* subtree, int* counters, int* tickets, int nworkgroups,
+                        unsigned long long* trace, hipStream_t s) {
+    if (nworkgroups <= 0) return hipSuccess;
+    batch_kernel<<<nworkgroups, 256, kBatchLds, s>>>(tasks, qbegin, qcount, nq, jobs, nodes, subtree, counters,
+                                                     tickets, trace);
+    return hipGetLastError();
+}
+
+}  // namespace tn

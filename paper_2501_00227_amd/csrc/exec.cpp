@@ -148,15 +148,21 @@ const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int 
     auto it = dp.launches.find(dsr);
     if (it != dp.launches.end()) return it->second;
     std::vector<NodeLaunch> v(p.prog.size());
-    int64_t part = 0;
+    int64_t part = 0, part_dag = 0;
+    std::vector<int64_t> part_off(p.prog.size(), 0);
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
         v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
         if (v[t].shape.lsplit > 0)
             v[t].part_entries = (int64_t)1 << (v[t].shape.lsplit + np.lb + np.li + np.lj);
         part = std::max(part, v[t].part_entries);
+        // concurrent nodes of the dependency-graph executor need separate partials
+        part_off[t] = part_dag;
+        part_dag += (v[t].part_entries + 63) & ~(int64_t)63;
     }
     dp.part_entries[dsr] = part;
+    dp.part_off_dag[dsr] = part_off;
+    dp.part_entries_dag[dsr] = part_dag;
     return dp.launches.emplace(dsr, std::move(v)).first->second;
 }
 

@@ -38,7 +38,9 @@ struct DevProgram {
     int* slice_pos = nullptr;     // nv entries: position in the sliced list or -1
     std::vector<int> perm_slot_a, perm_slot_b;  // per inner node, -1 if none
     std::map<int, std::vector<NodeLaunch>> launches;  // per device algebra
-    std::map<int, int64_t> part_entries;              // per device algebra
+    std::map<int, int64_t> part_entries;              // per device algebra (largest node)
+    std::map<int, std::vector<int64_t>> part_off_dag; // per algebra: each split node's own partials
+    std::map<int, int64_t> part_entries_dag;          // per algebra: sum over split nodes
 };
 
 struct PendingRec {
@@ -61,6 +63,8 @@ struct tn_ctx {
     void* pinned = nullptr;  // host staging (results, weights)
     size_t pinned_bytes = 0;
     std::map<uint64_t, tn::DevProgram> progs;  // keyed by plan uid
+    int cu_count = 0;
+    std::vector<tn_task_record> task_trace;  // persistent-launch timelines (profiling)
 };
 
 namespace tn {

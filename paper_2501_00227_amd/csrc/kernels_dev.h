@@ -1,0 +1,559 @@
+// Device-side building blocks shared by the stream kernels (kernels.hip) and
+// the persistent batched kernel (batch_kernels.hip): the element algebras of
+// the Sec. 5 property table, leaf initialisation (Sec. 3.2 tensors), one tile
+// of the bit permute, one tile of the batched semiring GEMM, the split-K
+// reduction of one output and the slice accumulator.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace tn {
+
+typedef int64_t i64;
+typedef unsigned long long u64;
+
+struct CTv {  // counting-tropical value: (size, count)
+    int n;
+    u64 c;
+};
+
+// ----------------------------------------------------------- algebras ----
+// Each algebra provides zero (additive identity), one (multiplicative
+// identity), add, mul, global loads/stores over its planes, and prescale
+// (applied to GEMM inputs: the partition function's per-tensor exponent).
+template <int D>
+struct Alg;
+
+template <>
+struct Alg<DSR_TROP_I32> {  // max-plus, -inf = INT_MIN, saturating add
+    using V = int;
+    __device__ static V zero(const AlgebraParams&) { return INT_MIN; }
+    __device__ static V one(const AlgebraParams&) { return 0; }
+    __device__ static V add(V a, V b, const AlgebraParams&) { return max(a, b); }
+    __device__ static V mul(V a, V b, const AlgebraParams&) { return __builtin_elementwise_add_sat(a, b); }
+    __device__ static V weight(float w, const AlgebraParams&) { return (int)w; }
+    __device__ static V load(const Planes& p, i64 i) { return ((const int*)p.p0)[i]; }
+    __device__ static void store(const Planes& p, i64 i, V v) { ((int*)p.p0)[i] = v; }
+    __device__ static V prescale(V v, float) { return v; }
+};
+
+template <>
+struct Alg<DSR_TROP_F32> {  // max-plus over float32, -inf = -INFINITY
+    using V = float;
+    __device__ static V zero(const AlgebraParams&) { return -INFINITY; }
+    __device__ static V one(const AlgebraParams&) { return 0.0f; }
+    __device__ static V add(V a, V b, const AlgebraParams&) { return fmaxf(a, b); }
+    __device__ static V mul(V a, V b, const AlgebraParams&) { return a + b; }
+    __device__ static V weight(float w, const AlgebraParams&) { return w; }
+    __device__ static V load(const Planes& p, i64 i) { return ((const float*)p.p0)[i]; }
+    __device__ static void store(const Planes& p, i64 i, V v) { ((float*)p.p0)[i] = v; }
+    __device__ static V prescale(V v, float) { return v; }
+};
+
+template <>
+struct Alg<DSR_CTROP> {  // (size, count): larger size wins, equal sizes add counts
+    using V = CTv;
+    __device__ static V zero(const AlgebraParams&) { return CTv{INT_MIN, 0ull}; }
+    __device__ static V one(const AlgebraParams&) { return CTv{0, 1ull}; }
+    __device__ static V add(V a, V b, const AlgebraParams&) {
+        int n = max(a.n, b.n);
+        u64 c = (a.n == n ? a.c : 0ull) + (b.n == n ? b.c : 0ull);
+        return CTv{n, c};
+    }
+    __device__ static V mul(V a, V b, const AlgebraParams&) {
+        return CTv{__builtin_elementwise_add_sat(a.n, b.n), a.c * b.c};
+    }
+    __device__ static V weight(float w, const AlgebraParams&) { return CTv{(int)w, 1ull}; }
+    __device__ static V load(const Planes& p, i64 i) { return CTv{((const int*)p.p0)[i], ((const u64*)p.p1)[i]}; }
+    __device__ static void store(const Planes& p, i64 i, V v) {
+        ((int*)p.p0)[i] = v.n;
+        ((u64*)p.p1)[i] = v.c;
+    }
+    __device__ static V prescale(V v, float) { return v; }
+};
+
+template <>
+struct Alg<DSR_U64> {  // counting in Z / 2^64
+    using V = u64;
+    __device__ static V zero(const AlgebraParams&) { return 0ull; }
+    __device__ static V one(const AlgebraParams&) { return 1ull; }
+    __device__ static V add(V a, V b, const AlgebraParams&) { return a + b; }
+    __device__ static V mul(V a, V b, const AlgebraParams&) { return a * b; }
+    __device__ static V weight(float, const AlgebraParams&) { return 1ull; }
+    __device__ static V load(const Planes& p, i64 i) { return ((const u64*)p.p0)[i]; }
+    __device__ static void store(const Planes& p, i64 i, V v) { ((u64*)p.p0)[i] = v; }
+    __device__ static V prescale(V v, float) { return v; }
+};
+
+template <>
+struct Alg<DSR_MODP> {  // counting modulo p < 2^31, Montgomery form with R = 2^32
+    using V = unsigned int;
+    __device__ static V zero(const AlgebraParams&) { return 0u; }
+    __device__ static V one(const AlgebraParams& ap) { return ap.r1; }
+    __device__ static V add(V a, V b, const AlgebraParams& ap) {
+        V s = a + b;
+        return s >= ap.p ? s - ap.p : s;
+    }
+    __device__ static V mul(V a, V b, const AlgebraParams& ap) {
+        u64 t = (u64)a * b;                          // < p^2 < 2^62
+        unsigned int m = (unsigned int)t * ap.pinv;  // t + m p == 0 mod 2^32
+        u64 u = (t + (u64)m * ap.p) >> 32;           // < 2p
+        return (V)(u >= ap.p ? u - ap.p : u);
+    }
+    __device__ static V weight(float, const AlgebraParams& ap) { return ap.r1; }
+    __device__ static V load(const Planes& p, i64 i) { return ((const unsigned int*)p.p0)[i]; }
+    __device__ static void store(const Planes& p, i64 i, V v) { ((unsigned int*)p.p0)[i] = v; }
+    __device__ static V prescale(V v, float) { return v; }
+};
+
+template <>
+struct Alg<DSR_Z_F32> {  // real (+, x) over float32
+    using V = float;
+    __device__ static V zero(const AlgebraParams&) { return 0.0f; }
+    __device__ static V one(const AlgebraParams&) { return 1.0f; }
+    __device__ static V add(V a, V b, const AlgebraParams&) { return a + b; }
+    __device__ static V mul(V a, V b, const AlgebraParams&) { return a * b; }
+    __device__ static V load(const Planes& p, i64 i) { return ((const float*)p.p0)[i]; }
+    __device__ static void store(const Planes& p, i64 i, V v) { ((float*)p.p0)[i] = v; }
+    __device__ static V prescale(V v, float s) { return v * s; }
+};
+
+__device__ inline float round_bf16(float x) {  // round to nearest even on the top 16 bits
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+template <>
+struct Alg<DSR_Z_BF16> : Alg<DSR_Z_F32> {
+    __device__ static V prescale(V v, float s) { return round_bf16(v * s); }
+};
+
+template <int D>
+constexpr bool is_z() {
+    return D == DSR_Z_F32 || D == DSR_Z_BF16;
+}
+
+// bytes per entry of plane 0 / plane 1 of an algebra (0: no such plane)
+template <int D>
+__host__ __device__ constexpr int plane_bytes_dev(int plane) {
+    return D == DSR_CTROP ? (plane == 0 ? 4 : 8) : D == DSR_U64 ? (plane == 0 ? 8 : 0) : (plane == 0 ? 4 : 0);
+}
+
+// Partition-function bookkeeping is read and written with device-scope
+// atomics only, so it is coherent between workgroups on any chiplet.
+__device__ inline unsigned int meta_maxbits(const TensorMeta* m, int i) {
+    return __hip_atomic_load(&m[i].maxbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline long long meta_exp(const TensorMeta* m, int i) {
+    return __hip_atomic_load(&m[i].exp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void meta_set(TensorMeta* m, int i, long long e, unsigned int bits) {
+    __hip_atomic_store(&m[i].exp, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&m[i].maxbits, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void meta_set_exp(TensorMeta* m, int i, long long e) {
+    __hip_atomic_store(&m[i].exp, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void meta_max(TensorMeta* m, int i, unsigned int bits) {
+    __hip_atomic_fetch_max(&m[i].maxbits, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// exponent m with 2^m <= max < 2^(m+1) of a non-negative float given by its bits
+__device__ inline int max_exponent(unsigned int bits) {
+    if (bits == 0u) return 0;
+    int e = (int)((bits >> 23) & 0xffu);
+    return e == 0 ? -126 : e - 127;
+}
+
+// --------------------------------------------------------------- leaves --
+// A leaf is the product of its factors: the edge tensor B(n_u, n_v) =
+// [[1,1],[1,0]] and the vertex tensors W(n) = [1, x^w] folded into it
+// (Sec. 3.2), summed over its indices that occur nowhere else, with sliced
+// indices fixed to this slice's values.
+__device__ inline int leaf_var_value(int var, const LeafDev& d, int e, const int* spos, u64 sid) {
+    if (var == d.var0) return e & 1;
+    if (var == d.var1) return (e >> 1) & 1;
+    int sp = spos[var];
+    if (sp >= 0) return (int)((sid >> sp) & 1ull);
+    return -1;  // summed at the leaf
+}
+
+template <int D>
+__device__ void leaf_one(const LeafDev& d, int leaf_id, const float* w, const int* spos, u64 sid, Planes arena,
+                         const AlgebraParams& ap, TensorMeta* meta) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    int nent = 1 << d.rank;
+    for (int e = 0; e < nent; e++) {
+        int fu = leaf_var_value(d.u, d, e, spos, sid);
+        int fv = d.v >= 0 ? leaf_var_value(d.v, d, e, spos, sid) : 0;
+        V acc = A::zero(ap);
+        for (int a = 0; a < 4; a++) {
+            int nu = a & 1, nv = (a >> 1) & 1;
+            if (fu >= 0 && nu != fu) continue;
+            if (fv >= 0 && nv != fv) continue;
+            if (d.v < 0 && nv) continue;
+            V prod = A::one(ap);
+            if ((d.flags & 1) && nu && nv) prod = A::zero(ap);
+            if ((d.flags & 2) && nu) prod = A::mul(prod, A::weight(w ? w[d.u] : 1.0f, ap), ap);
+            if ((d.flags & 4) && nv) prod = A::mul(prod, A::weight(w ? w[d.v] : 1.0f, ap), ap);
+            acc = A::add(acc, prod, ap);
+        }
+        A::store(arena, d.off + e, acc);
+    }
+}
+
+// Partition function: leaf values in double, stored as float scaled by a
+// power of two so the largest entry lies in [1, 2).
+__device__ inline void leaf_one_z(const LeafDev& d, int leaf_id, const float* w, const int* spos, u64 sid,
+                                  Planes arena, const AlgebraParams& ap, TensorMeta* meta) {
+    int nent = 1 << d.rank;
+    double val[4] = {0, 0, 0, 0};
+    double mx = 0.0;
+    for (int e = 0; e < nent; e++) {
+        int fu = leaf_var_value(d.u, d, e, spos, sid);
+        int fv = d.v >= 0 ? leaf_var_value(d.v, d, e, spos, sid) : 0;
+        double acc = 0.0;
+        for (int a = 0; a < 4; a++) {
+            int nu = a & 1, nv = (a >> 1) & 1;
+            if (fu >= 0 && nu != fu) continue;
+            if (fv >= 0 && nv != fv) continue;
+            if (d.v < 0 && nv) continue;
+            double prod = 1.0;
+            if ((d.flags & 1) && nu && nv) prod = 0.0;
+            if ((d.flags & 2) && nu) prod *= exp(ap.beta * (double)(w ? w[d.u] : 1.0f));
+            if ((d.flags & 4) && nv) prod *= exp(ap.beta * (double)(w ? w[d.v] : 1.0f));
+            acc += prod;
+        }
+        val[e] = acc;
+        mx = fmax(mx, acc);
+    }
+    int ex = mx > 0.0 ? ilogb(mx) : 0;
+    float fmx = 0.0f;
+    for (int e = 0; e < nent; e++) {
+        float f = (float)ldexp(val[e], -ex);
+        fmx = fmaxf(fmx, f);
+        ((float*)arena.p0)[d.off + e] = f;
+    }
+    meta_set(meta, leaf_id, ex, __float_as_uint(fmx));
+}
+
+template <int D>
+__device__ inline void leaf_dispatch(const LeafDev& d, int leaf_id, const float* w, const int* spos, u64 sid,
+                                     Planes arena, const AlgebraParams& ap, TensorMeta* meta) {
+    if constexpr (is_z<D>())
+        leaf_one_z(d, leaf_id, w, spos, sid, arena, ap, meta);
+    else
+        leaf_one<D>(d, leaf_id, w, spos, sid, arena, ap, meta);
+}
+
+// -------------------------------------------------------------- permute --
+// out[pi(x)] = in[x], pi a permutation of the bits of x.  A workgroup moves a
+// tile of 2^u entries through LDS: read in input order (contiguous runs of
+// the input's low bits), write in output order (contiguous runs of the
+// output's low bits).  Tables (see build_perm_params): in_lo/in_hi give the
+// input offset of tile entry e from its low 6 / high bits, out_lo/out_hi the
+// output offset of write slot f, e_lo/e_hi map f to e, and tin/tout place
+// the tile index bits.
+struct PermLds {
+    i64 in_lo[64], in_hi[64], out_lo[64], out_hi[64];
+    int e_lo[64], e_hi[64];
+    signed char tin[48], tout[48];
+};
+constexpr int kPermTile = 2048;
+
+__device__ inline void perm_load_tables(PermLds* s, const PermParams* pp) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        s->in_lo[tid] = pp->in_lo[tid];
+        s->in_hi[tid] = pp->in_hi[tid];
+        s->out_lo[tid] = pp->out_lo[tid];
+        s->out_hi[tid] = pp->out_hi[tid];
+        s->e_lo[tid] = pp->e_lo[tid];
+        s->e_hi[tid] = pp->e_hi[tid];
+    }
+    if (tid < 48) {
+        s->tin[tid] = pp->tin[tid];
+        s->tout[tid] = pp->tout[tid];
+    }
+}
+
+// One tile; tables must already be in LDS (and a barrier passed).  Ends with
+// a barrier so the tile buffer can be reused.
+template <typename T>
+__device__ inline void permute_tile(const T* __restrict__ in, T* __restrict__ out, const PermLds* s, T* tile, int u,
+                                    int nt, i64 t) {
+    const int tid = threadIdx.x;
+    const int n = 1 << u;
+    i64 bin = 0, bout = 0;
+    for (int k = 0; k < nt; k++) {
+        i64 bit = (t >> k) & 1;
+        bin |= bit << s->tin[k];
+        bout |= bit << s->tout[k];
+    }
+    for (int e = tid; e < n; e += blockDim.x) tile[e + (e >> 5)] = in[bin + s->in_lo[e & 63] + s->in_hi[e >> 6]];
+    __syncthreads();
+    for (int f = tid; f < n; f += blockDim.x) {
+        int e = s->e_lo[f & 63] | s->e_hi[f >> 6];
+        out[bout + s->out_lo[f & 63] + s->out_hi[f >> 6]] = tile[e + (e >> 5)];
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- GEMM --
+// C[b][i][j] = (+)_k A[b][i][k] (*) B[b][k][j], all extents powers of two.
+// A is [b][i][k] (k fastest) or, with a_t, [b][k][i]; B is [b][k][j] or, with
+// b_t, [b][j][k]; C is [b][i][j].  A workgroup owns a tile of 2^tb batches x
+// 2^ti rows x 2^tj columns and walks K in steps of 2^tk: both operand tiles
+// are staged in LDS as [batch][k][row] and [batch][k][col], read from global
+// memory in memory order (contiguous runs), and each thread accumulates an
+// RM x RN register tile with rows y + r*TMt, columns x + c*TNt.  With
+// lsplit > 0 the K range is split over workgroups and partial results go to
+// `P` ([split][b][i][j]) for the split reduction.
+struct GemmArgs {
+    Planes A, B, C, P;
+    int lb, li, lj, lk, a_t, b_t, tb, ti, tj, tk, lsplit;
+    AlgebraParams ap;
+    TensorMeta* meta;
+    int ma, mb, mc;
+};
+
+template <int D>
+__device__ inline float input_scale(const GemmArgs& g, int m) {
+    if constexpr (is_z<D>()) {
+        return ldexpf(1.0f, -max_exponent(meta_maxbits(g.meta, m)));
+    } else {
+        return 1.0f;
+    }
+}
+
+__host__ __device__ inline int pad_dim(int t) { return t + (t >= 32 ? 1 : 0); }
+
+template <int D, int RM, int RN>
+__device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    const int TB = 1 << g.tb, TM = 1 << g.ti, TN = 1 << g.tj, TK = 1 << g.tk;
+    const int TMp = pad_dim(TM), TNp = pad_dim(TN);
+    V* As = (V*)smem;
+    V* Bs = As + (size_t)TB * TK * TMp;
+
+    const u64 first = tile;
+    const int split = (int)(tile & ((1u << g.lsplit) - 1));
+    tile >>= g.lsplit;
+    const int ntn = g.lj - g.tj, ntm = g.li - g.ti;
+    const i64 jt = (i64)(tile & ((1ull << ntn) - 1));
+    tile >>= ntn;
+    const i64 it = (i64)(tile & ((1ull << ntm) - 1));
+    tile >>= ntm;
+    const i64 b0 = (i64)tile << g.tb, i0 = it << g.ti, j0 = jt << g.tj;
+    const int lkc = g.lk - g.lsplit;
+    const i64 kbeg = (i64)split << lkc;
+    const int Kc = 1 << lkc;
+
+    const int TNt = TN / RN, TMt = TM / RM;
+    const int active = TB * TMt * TNt;
+    const int tid = threadIdx.x;
+    const int x = tid % TNt, y = (tid / TNt) % TMt, z = tid / (TNt * TMt);
+
+    const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+
+    V acc[RM][RN];
+#pragma unroll
+    for (int r = 0; r < RM; r++)
+#pragma unroll
+        for (int c = 0; c < RN; c++) acc[r][c] = A::zero(g.ap);
+
+    const int na = TB * TM * TK, nb = TB * TK * TN;
+    for (int kk = 0; kk < Kc; kk += TK) {
+        const i64 k0 = kbeg + kk;
+        for (int idx = tid; idx < na; idx += 256) {
+            int bb, i, k;
+            i64 addr;
+            if (!g.a_t) {  // memory order (b, i, k)
+                k = idx & (TK - 1);
+                i = (idx >> g.tk) & (TM - 1);
+                bb = idx >> (g.tk + g.ti);
+                addr = ((((b0 + bb) << g.li) | (i0 + i)) << g.lk) | (k0 + k);
+            } else {  // memory order (b, k, i)
+                i = idx & (TM - 1);
+                k = (idx >> g.ti) & (TK - 1);
+                bb = idx >> (g.tk + g.ti);
+                addr = ((((b0 + bb) << g.lk) | (k0 + k)) << g.li) | (i0 + i);
+            }
+            As[(bb * TK + k) * TMp + i] = A::prescale(A::load(g.A, addr), sA);
+        }
+        for (int idx = tid; idx < nb; idx += 256) {
+            int bb, j, k;
+            i64 addr;
+            if (!g.b_t) {  // memory order (b, k, j)
+                j = idx & (TN - 1);
+                k = (idx >> g.tj) & (TK - 1);
+                bb = idx >> (g.tk + g.tj);
+                addr = ((((b0 + bb) << g.lk) | (k0 + k)) << g.lj) | (j0 + j);
+            } else {  // memory order (b, j, k)
+                k = idx & (TK - 1);
+                j = (idx >> g.tk) & (TN - 1);
+                bb = idx >> (g.tk + g.tj);
+                addr = ((((b0 + bb) << g.lj) | (j0 + j)) << g.lk) | (k0 + k);
+            }
+            Bs[(bb * TK + k) * TNp + j] = A::prescale(A::load(g.B, addr), sB);
+        }
+        __syncthreads();
+        if (tid < active) {
+            const V* ap_ = As + (size_t)z * TK * TMp + y;
+            const V* bp_ = Bs + (size_t)z * TK * TNp + x;
+            for (int k = 0; k < TK; k++) {
+                V av[RM], bv[RN];
+#pragma unroll
+                for (int r = 0; r < RM; r++) av[r] = ap_[k * TMp + r * TMt];
+#pragma unroll
+                for (int c = 0; c < RN; c++) bv[c] = bp_[k * TNp + c * TNt];
+#pragma unroll
+                for (int r = 0; r < RM; r++)
+#pragma unroll
+                    for (int c = 0; c < RN; c++) acc[r][c] = A::add(acc[r][c], A::mul(av[r], bv[c], g.ap), g.ap);
+            }
+        }
+        __syncthreads();
+    }
+
+    if constexpr (is_z<D>()) {
+        if (first == 0 && tid == 0) {
+            meta_set_exp(g.meta, g.mc,
+                         meta_exp(g.meta, g.ma) + max_exponent(meta_maxbits(g.meta, g.ma)) + meta_exp(g.meta, g.mb) +
+                             max_exponent(meta_maxbits(g.meta, g.mb)));
+        }
+    }
+    float lmax = 0.0f;
+    if (tid < active) {
+        const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
+        const Planes dst = g.lsplit ? g.P : g.C;
+        const i64 base = g.lsplit ? (i64)split * nout : 0;
+#pragma unroll
+        for (int r = 0; r < RM; r++)
+#pragma unroll
+            for (int c = 0; c < RN; c++) {
+                i64 o = ((((b0 + z) << g.li) | (i0 + y + r * TMt)) << g.lj) | (j0 + x + c * TNt);
+                A::store(dst, base + o, acc[r][c]);
+                if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc[r][c]);
+            }
+    }
+    if constexpr (is_z<D>()) {
+        if (!g.lsplit) {
+            for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
+            if ((tid & 63) == 0 && lmax > 0.0f) meta_max(g.meta, g.mc, __float_as_uint(lmax));
+        }
+    }
+}
+
+// --------------------------------------------------------- split reduce --
+// C[o] = (+)_s part[s][o] for one output o, by the whole workgroup.
+template <int D>
+__device__ void split_reduce_one(Planes part, Planes C, i64 nout, int lsplit, const AlgebraParams& ap,
+                                 TensorMeta* meta, int mc, i64 o, typename Alg<D>::V* red) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    const int S = 1 << lsplit;
+    V acc = A::zero(ap);
+    for (int s = threadIdx.x; s < S; s += blockDim.x) acc = A::add(acc, A::load(part, (i64)s * nout + o), ap);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = A::add(red[threadIdx.x], red[threadIdx.x + w], ap);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A::store(C, o, red[0]);
+        if constexpr (is_z<D>()) {
+            if (red[0] > 0.0f) meta_max(meta, mc, __float_as_uint(red[0]));
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------- accumulate ---
+// Slice accumulation (Sec. 4.2): the per-slice roots are combined with the
+// algebra's addition.  The partition function keeps {mantissa, exponent}.
+struct ZAcc {
+    double m;
+    i64 e;
+};
+
+__device__ inline void zacc_add(ZAcc& a, double v, i64 e) {
+    if (v == 0.0) return;
+    int e2;
+    double fr = frexp(v, &e2);  // v = fr * 2^e2, fr in [0.5, 1)
+    double m = 2.0 * fr;
+    i64 E = e + e2 - 1;
+    if (a.m == 0.0) {
+        a.m = m;
+        a.e = E;
+        return;
+    }
+    if (E > a.e) {
+        double t = a.m;
+        i64 te = a.e;
+        a.m = m;
+        a.e = E;
+        m = t;
+        E = te;
+    }
+    i64 d = E - a.e;  // <= 0
+    if (d > -1100) a.m += ldexp(m, (int)d);
+    if (a.m >= 2.0) {
+        a.m *= 0.5;
+        a.e += 1;
+    }
+}
+
+template <int D>
+__device__ void accumulate_one(Planes root, int mroot, TensorMeta* meta, void* acc, int first,
+                               const AlgebraParams& ap) {
+    using A = Alg<D>;
+    if constexpr (is_z<D>()) {
+        ZAcc* z = (ZAcc*)acc;
+        if (first) {
+            z->m = 0.0;
+            z->e = 0;
+        }
+        zacc_add(*z, (double)((const float*)root.p0)[0], meta_exp(meta, mroot));
+    } else if constexpr (D == DSR_CTROP) {
+        CTv v = A::load(root, 0);
+        int* n = (int*)acc;
+        u64* c = (u64*)((char*)acc + 8);
+        CTv a = first ? A::zero(ap) : CTv{*n, *c};
+        a = A::add(a, v, ap);
+        *n = a.n;
+        *c = a.c;
+    } else {
+        using V = typename A::V;
+        V v = A::load(root, 0);
+        V* a = (V*)acc;
+        *a = first ? v : A::add(*a, v, ap);
+    }
+}
+
+template <int D>
+__device__ void set_one(void* acc, const AlgebraParams& ap) {
+    using A = Alg<D>;
+    if constexpr (is_z<D>()) {
+        ZAcc* z = (ZAcc*)acc;
+        z->m = 1.0;
+        z->e = 0;
+    } else if constexpr (D == DSR_CTROP) {
+        *(int*)acc = 0;
+        *(u64*)((char*)acc + 8) = 1ull;
+    } else {
+        *(typename A::V*)acc = A::one(ap);
+    }
+}
+
+}  // namespace tn

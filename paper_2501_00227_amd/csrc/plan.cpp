@@ -286,8 +286,9 @@ tn_status plan_program(Plan& p) {
 
     Arena arena;
     arena.end = arena.peak = Arena::align(p.leaf_entries);
-    std::vector<int64_t> off(nn, -1);
-    for (int l = 0; l < nleaf; l++) off[l] = p.leaf_prog[l].off;
+    std::vector<int64_t> off(nn, -1), dag_off(nn, -1);
+    for (int l = 0; l < nleaf; l++) off[l] = dag_off[l] = p.leaf_prog[l].off;
+    int64_t dag_end = Arena::align(p.leaf_entries);
 
     for (int x = nleaf; x < nn; x++) {
         const Node& nd = p.nodes[x];
@@ -406,6 +407,17 @@ tn_status plan_program(Plan& p) {
         if (best.perm_a) best.a_tmp_off = arena.alloc(sa);
         if (best.perm_b) best.b_tmp_off = arena.alloc(sb);
         best.c_off = arena.alloc(scn);
+        if (best.perm_a) {
+            best.dag_a_tmp = dag_end;
+            dag_end += Arena::align(sa);
+        }
+        if (best.perm_b) {
+            best.dag_b_tmp = dag_end;
+            dag_end += Arena::align(sb);
+        }
+        best.dag_c_off = dag_end;
+        dag_off[x] = dag_end;
+        dag_end += Arena::align(scn);
         off[x] = best.c_off;
         if (best.perm_a) arena.release(best.a_tmp_off, sa);
         if (best.perm_b) arena.release(best.b_tmp_off, sb);
@@ -420,6 +432,8 @@ tn_status plan_program(Plan& p) {
     }
     p.arena_entries = arena.peak;
     p.node_off = off;
+    p.node_off_dag = dag_off;
+    p.arena_entries_dag = dag_end;
     return TN_OK;
 }
 

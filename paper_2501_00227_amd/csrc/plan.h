@@ -51,6 +51,9 @@ struct NodeProg {
     bool b_t = false;              // B stored [b][j][k] (k fastest) instead of [b][k][j]
     int64_t c_off = 0;             // arena offsets (entries)
     int64_t a_tmp_off = -1, b_tmp_off = -1;
+    // the same tensors in the dependency-graph layout: every tensor has its
+    // own region, so nodes of independent subtrees may run concurrently
+    int64_t dag_c_off = 0, dag_a_tmp = -1, dag_b_tmp = -1;
 };
 
 struct LeafProg {
@@ -79,6 +82,8 @@ struct Plan {
     std::vector<LeafProg> leaf_prog;
     std::vector<NodeProg> prog;           // one per inner node, execution order
     std::vector<int64_t> node_off;        // arena offset of every node's tensor
+    std::vector<int64_t> node_off_dag;    // same, dependency-graph layout (no reuse)
+    int64_t arena_entries_dag = 0;
     int64_t arena_entries = 0;            // per plane, per slice
     int64_t leaf_entries = 0;
     int npermutes = 0;

@@ -1,0 +1,407 @@
+// Continuous-batching server.  A scheduler thread admits queued jobs while
+// the device bytes of the admitted jobs stay within the budget and fewer than
+// max_slots run, packs every admission round into one persistent launch on
+// one of a few streams (so a new launch overlaps launches still running),
+// and completes jobs as their launch's read-back event fires.  Device memory
+// comes from one pool of the budget's size, allocated once.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "batch_host.h"
+
+namespace tn {
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit sub-allocator over one device block.
+struct Pool {
+    unsigned char* base = nullptr;
+    uint64_t bytes = 0;
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    void init(void* b, uint64_t n) {
+        base = (unsigned char*)b;
+        bytes = n;
+        free_.clear();
+        free_[0] = n;
+    }
+    void* alloc(uint64_t n) {
+        n = (n + 255) & ~(uint64_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                uint64_t off = it->first, sz = it->second;
+                free_.erase(it);
+                if (sz > n) free_[off + n] = sz - n;
+                return base + off;
+            }
+        return nullptr;
+    }
+    void release(void* p, uint64_t n) {
+        n = (n + 255) & ~(uint64_t)255;
+        uint64_t off = (uint64_t)((unsigned char*)p - base);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+// Device bytes one job takes inside a persistent launch (all its passes).
+uint64_t job_device_bytes(const Net& net, const Plan& plan, const tn_solve_opts& o) {
+    std::vector<PassSpec> passes;
+    if (make_passes(net, o, passes) != TN_OK) return 0;
+    auto a = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    uint64_t total = a(sizeof(float) * net.w.size());
+    for (auto& ps : passes) {
+        uint64_t pb0 = plane_bytes(ps.dsr, 0), pb1 = plane_bytes(ps.dsr, 1);
+        uint64_t E = (uint64_t)std::max<int64_t>(plan.arena_entries_dag, 64);
+        uint64_t Pe = 0;  // every split node has its own partials in the dependency-graph executor
+        for (auto& np : plan.prog) {
+            GemmShape g = choose_gemm_shape(ps.dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+            if (g.lsplit) Pe += ((1ull << (g.lsplit + np.lb + np.li + np.lj)) + 63) & ~63ull;
+        }
+        total += a(E * pb0) + a(E * pb1) + a(Pe * pb0) + a(Pe * pb1) + a(sizeof(TensorMeta) * plan.nodes.size()) + a(16);
+    }
+    return total;
+}
+
+}  // namespace tn
+
+using namespace tn;
+
+struct ServerJob {
+    uint64_t id = 0;
+    const Net* net = nullptr;
+    const Plan* plan = nullptr;
+    tn_solve_opts opts{};
+    uint64_t bytes = 0;
+    double t_submit = 0;
+    int state = 0;  // 0 queued, 1 running, 2 done
+    tn_result res{};
+    tn_status st = TN_OK;
+    double latency = 0;
+};
+
+struct InFlight {
+    BatchLaunch L;
+    std::vector<uint64_t> ids;
+    hipEvent_t ev = nullptr;
+    uint64_t bytes = 0;
+};
+
+struct tn_server {
+    tn_ctx* ctx = nullptr;
+    uint64_t budget = 0;
+    int max_slots = 0;
+    std::mutex mu;   // jobs, queue, counters
+    std::mutex dev;  // context (device programs, staging)
+    std::condition_variable cv, done_cv;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, ServerJob> jobs;
+    uint64_t next_id = 1;
+    uint64_t admitted = 0;
+    int running = 0;
+    std::vector<hipStream_t> streams;
+    int next_stream = 0;
+    Pool pool;
+    void* pool_mem = nullptr;
+    uint64_t pool_bytes = 0;
+    std::list<InFlight> inflight;
+    std::thread th;
+    bool stop = false;
+    tn_server_stats_t stats{};
+};
+
+static const uint64_t kTableReserve = 64ull << 20;  // task tables of in-flight launches
+
+static void complete(tn_server* s, InFlight& f) {
+    std::vector<tn_result> res;
+    batch_finish(f.L, res);
+    double t = now_s();
+    {
+        std::lock_guard<std::mutex> g(s->dev);
+        batch_release(f.L);
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    for (size_t k = 0; k < f.ids.size(); k++) {
+        ServerJob& j = s->jobs[f.ids[k]];
+        j.res = res[k];
+        j.st = f.L.items[k].status;
+        j.res.seconds = t - j.t_submit;
+        j.latency = t - j.t_submit;
+        j.state = 2;
+        s->stats.completed++;
+        if (j.st != TN_OK) s->stats.failed++;
+    }
+    s->admitted -= f.bytes;
+    s->running -= (int)f.ids.size();
+    s->done_cv.notify_all();
+}
+
+static void scheduler(tn_server* s) {
+    (void)hipSetDevice(s->ctx->device);
+    for (;;) {
+        // 1. complete launches whose read-back has landed
+        for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+            if (hipEventQuery(it->ev) == hipSuccess) {
+                complete(s, *it);
+                (void)hipEventDestroy(it->ev);
+                it = s->inflight.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        // 2. admit: FIFO while the budget and the slots allow
+        std::vector<uint64_t> ids;
+        uint64_t bytes = 0;
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            if (s->stop && s->queue.empty() && s->inflight.empty()) break;
+            while (!s->queue.empty()) {
+                ServerJob& j = s->jobs[s->queue.front()];
+                if (s->running + (int)ids.size() >= s->max_slots) break;
+                if (s->admitted + bytes + j.bytes > s->budget) break;
+                bytes += j.bytes;
+                ids.push_back(j.id);
+                s->queue.pop_front();
+            }
+            if (ids.empty()) {
+                // nothing admissible: sleep until a submit or a completion poll
+                auto wait = s->inflight.empty() ? std::chrono::microseconds(2000) : std::chrono::microseconds(50);
+                s->cv.wait_for(g, wait);
+                continue;
+            }
+            s->admitted += bytes;
+            s->running += (int)ids.size();
+            if (s->admitted > s->stats.peak_admitted_bytes) s->stats.peak_admitted_bytes = s->admitted;
+            if (s->running > s->stats.peak_running) s->stats.peak_running = s->running;
+            for (auto id : ids) s->jobs[id].state = 1;
+        }
+        // 3. one persistent launch for this admission round
+        std::vector<BatchItem> items;
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            for (auto id : ids) {
+                ServerJob& j = s->jobs[id];
+                items.push_back({j.net, j.plan, j.opts});
+            }
+        }
+        InFlight f;
+        f.ids = ids;
+        f.bytes = bytes;
+        DevAllocFn alloc;
+        alloc.alloc = [s](size_t n) { return s->pool.alloc(n); };
+        alloc.free = [s](void* p, size_t n) { s->pool.release(p, n); };
+        tn_status st;
+        hipStream_t stream = s->streams[s->next_stream];
+        s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+        {
+            std::lock_guard<std::mutex> g(s->dev);
+            st = batch_prepare(s->ctx, items, f.L, alloc);
+            if (st == TN_OK) st = batch_launch(s->ctx, f.L, stream);
+        }
+        if (st == TN_ENOMEM) {  // pool fragmented: requeue at the front, retry after completions
+            std::lock_guard<std::mutex> g(s->dev);
+            batch_release(f.L);
+            std::lock_guard<std::mutex> g2(s->mu);
+            for (auto it = ids.rbegin(); it != ids.rend(); ++it) {
+                s->jobs[*it].state = 0;
+                s->queue.push_front(*it);
+            }
+            s->admitted -= bytes;
+            s->running -= (int)ids.size();
+            if (s->inflight.empty()) {  // nothing will free memory: fail the head job
+                ServerJob& j = s->jobs[s->queue.front()];
+                s->queue.pop_front();
+                j.st = TN_ENOMEM;
+                j.state = 2;
+                j.res.semiring = -1;
+                s->stats.completed++;
+                s->stats.failed++;
+                s->done_cv.notify_all();
+            }
+            continue;
+        }
+        if (st != TN_OK) {
+            {
+                std::lock_guard<std::mutex> g(s->dev);
+                (void)hipStreamSynchronize(stream);
+                batch_release(f.L);
+            }
+            std::lock_guard<std::mutex> g(s->mu);
+            for (auto id : ids) {
+                ServerJob& j = s->jobs[id];
+                j.st = st;
+                j.state = 2;
+                j.res.semiring = -1;
+                s->stats.completed++;
+                s->stats.failed++;
+            }
+            s->admitted -= bytes;
+            s->running -= (int)ids.size();
+            s->done_cv.notify_all();
+            continue;
+        }
+        (void)hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
+        (void)hipEventRecord(f.ev, stream);
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stats.launches++;
+        }
+        s->inflight.push_back(std::move(f));
+    }
+}
+
+extern "C" {
+
+tn_status tn_server_create(tn_ctx* ctx, uint64_t budget, int32_t max_slots, tn_server** out) {
+    try {
+        if (!ctx || !out || budget == 0 || max_slots <= 0) return fail(TN_EINVAL, "invalid server arguments");
+        *out = nullptr;
+        auto* s = new tn_server();
+        s->ctx = ctx;
+        s->budget = budget;
+        s->max_slots = max_slots;
+        s->pool_bytes = budget + kTableReserve;
+        s->pool_mem = dev_alloc(ctx, s->pool_bytes);
+        if (!s->pool_mem) {
+            delete s;
+            return fail(TN_ENOMEM, "server pool allocation failed");
+        }
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+            dev_free(ctx, s->pool_mem, s->pool_bytes);
+            delete s;
+            return fail(TN_EDEVICE, "stream synchronisation failed");
+        }
+        s->pool.init(s->pool_mem, s->pool_bytes);
+        for (int k = 0; k < 3; k++) {  // default-priority streams
+            hipStream_t st;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) break;
+            s->streams.push_back(st);
+        }
+        if (s->streams.empty()) {
+            dev_free(ctx, s->pool_mem, s->pool_bytes);
+            delete s;
+            return fail(TN_EDEVICE, "stream creation failed");
+        }
+        s->th = std::thread(scheduler, s);
+        *out = s;
+        return TN_OK;
+    } catch (...) {
+        return fail(TN_ENOMEM, "server creation failed");
+    }
+}
+
+tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan, const tn_solve_opts* o,
+                           uint64_t* job_id) {
+    try {
+        if (!s || !net || !plan || !o || !job_id) return fail(TN_EINVAL, "NULL argument");
+        if (plan->plan.fingerprint != net->net.fingerprint) return fail(TN_EINVAL, "plan was built for a different network");
+        if (!plan->plan.sliced.empty()) return fail(TN_EINVAL, "served jobs must not be sliced");
+        std::vector<PassSpec> passes;
+        tn_status st = make_passes(net->net, *o, passes);
+        if (st != TN_OK) return st;
+        uint64_t bytes = job_device_bytes(net->net, plan->plan, *o);
+        if (bytes > s->budget) return fail(TN_ETOOBIG, "job needs " + std::to_string(bytes) + " device bytes, above the budget");
+        {
+            // upload the plan's device program now, on the caller's thread
+            std::lock_guard<std::mutex> g(s->dev);
+            DevProgram* dp = nullptr;
+            if (plan->plan.nleaf() > 0) {
+                st = get_program(s->ctx, plan->plan, dp);
+                if (st != TN_OK) return st;
+                for (auto& ps : passes) node_launches(*dp, plan->plan, ps.dsr);
+            }
+        }
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) return fail(TN_ECANCELED, "server is shutting down");
+        ServerJob j;
+        j.id = s->next_id++;
+        j.net = &net->net;
+        j.plan = &plan->plan;
+        j.opts = *o;
+        j.opts.primes = nullptr;  // the default primes; caller arrays may not outlive the call
+        if (o->primes) return fail(TN_EINVAL, "served jobs use the default primes");
+        j.bytes = bytes;
+        j.t_submit = now_s();
+        s->jobs[j.id] = j;
+        s->queue.push_back(j.id);
+        s->stats.submitted++;
+        *job_id = j.id;
+        s->cv.notify_one();
+        return TN_OK;
+    } catch (...) {
+        return fail(TN_ENOMEM, "submit failed");
+    }
+}
+
+tn_status tn_server_poll(tn_server* s, uint64_t job_id, tn_result* out, int32_t* done, double* latency_s) {
+    if (!s || !done) return fail(TN_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return fail(TN_EINVAL, "unknown job id");
+    *done = it->second.state == 2 ? 1 : 0;
+    if (*done) {
+        if (out) *out = it->second.res;
+        if (latency_s) *latency_s = it->second.latency;
+        tn_status st = it->second.st;
+        s->jobs.erase(it);
+        if (st != TN_OK) return fail(st, "job failed");
+    }
+    return TN_OK;
+}
+
+tn_status tn_server_drain(tn_server* s) {
+    if (!s) return fail(TN_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> g(s->mu);
+    s->done_cv.wait(g, [&] { return s->queue.empty() && s->running == 0; });
+    return TN_OK;
+}
+
+tn_status tn_server_stats(tn_server* s, tn_server_stats_t* st) {
+    if (!s || !st) return fail(TN_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    *st = s->stats;
+    return TN_OK;
+}
+
+tn_status tn_server_destroy(tn_server* s) {
+    if (!s) return TN_OK;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    for (auto st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    dev_free(s->ctx, s->pool_mem, s->pool_bytes);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    delete s;
+    return TN_OK;
+}
+
+}  // extern "C"

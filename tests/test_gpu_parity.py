@@ -47,32 +47,34 @@ def _weighted(g, s):
     return g
 
 
-def _check_all(ctx, g, plan_kw, beta=0.7, label=""):
+def _check_all(ctx, g, plan_kw, beta=0.7, label="", executor="auto"):
     ref = oracle.brute_force(g, [beta])
     net = tn.Net.from_graph(g)
     plan = tn.Plan.create(net, **plan_kw)
     integer = g.weights is None or np.all(g.weights == np.round(g.weights))
-    print(f"case {label} {g.name} nv={g.nv} ne={g.ne} plan={plan_kw}", flush=True)
+    print(f"case {label} {g.name} nv={g.nv} ne={g.ne} plan={plan_kw} executor={executor}", flush=True)
+    ex = {"executor": executor}
     if integer:
-        r = ctx.solve(net, plan, "tropical_i32")
+        r = ctx.solve(net, plan, "tropical_i32", **ex)
         assert r["size"] == ref["size_max"], (label, r, ref)
-        r = ctx.solve(net, plan, "counting_tropical")
+        r = ctx.solve(net, plan, "counting_tropical", **ex)
         assert (r["size"], r["count_mod_2_64"]) == (ref["size_max"], ref["count_max"]), (label, r, ref)
-    r = ctx.solve(net, plan, "tropical_f32")
+    r = ctx.solve(net, plan, "tropical_f32", **ex)
     assert r["size"] == pytest.approx(ref["size_max"], abs=0), (label, r, ref)
-    r = ctx.solve(net, plan, "count_exact")
+    r = ctx.solve(net, plan, "count_exact", **ex)
     assert r["count"] == ref["count_all"], (label, r, ref)
     assert r["count_mod_2_64"] == ref["count_all"] % (1 << 64)
-    r = ctx.solve(net, plan, "partition_f32", beta=beta)
+    r = ctx.solve(net, plan, "partition_f32", beta=beta, **ex)
     assert abs(r["z"] - ref["z"][0]) <= Z_RTOL * ref["z"][0], (label, r, ref)
-    r = ctx.solve(net, plan, "partition_bf16", beta=beta)
+    r = ctx.solve(net, plan, "partition_bf16", beta=beta, **ex)
     assert abs(r["z"] - ref["z"][0]) <= 5e-2 * ref["z"][0], (label, r, ref)
 
 
 @pytest.mark.parametrize("absorb", [True, False])
-def test_small_graphs_every_algebra(ctx, absorb):
+@pytest.mark.parametrize("executor", ["stream", "persistent"])
+def test_small_graphs_every_algebra(ctx, absorb, executor):
     for s, g in enumerate(_small_graphs()):
-        _check_all(ctx, _weighted(g, s), {"absorb": absorb, "seed": s}, label=f"s{s}")
+        _check_all(ctx, _weighted(g, s), {"absorb": absorb, "seed": s}, label=f"s{s}", executor=executor)
 
 
 def test_empty_network(ctx):
@@ -83,10 +85,12 @@ def test_empty_network(ctx):
     assert ctx.solve(net, plan, "partition_f32", beta=1.0)["z"] == 1.0
 
 
-def test_treesa_plans(ctx):
+@pytest.mark.parametrize("executor", ["stream", "persistent"])
+def test_treesa_plans(ctx, executor):
     for s in range(4):
         g = _weighted(gg.random_regular(16, 3, 100 + s), s)
-        _check_all(ctx, g, {"method": "treesa", "ntrials": 2, "niters": 5, "seed": s}, label=f"sa{s}")
+        _check_all(ctx, g, {"method": "treesa", "ntrials": 2, "niters": 5, "seed": s}, label=f"sa{s}",
+                   executor=executor)
 
 
 def test_sliced_plans_match(ctx):
@@ -121,8 +125,8 @@ def test_k1_counting_tropical_twenty_seeds(ctx):
         assert (r["size"], r["count_mod_2_64"]) == (case["size_max"], case["count_max"]), case
 
 
-@pytest.mark.parametrize("method", ["greedy", "treesa"])
-def test_k2_three_contractions(ctx, method):
+@pytest.mark.parametrize("method,executor", [("greedy", "stream"), ("treesa", "stream"), ("treesa", "persistent")])
+def test_k2_three_contractions(ctx, method, executor):
     gold = json.load(open(os.path.join(GOLD, "k2.json")))["cases"]
     for case in gold:
         g = gg.random_regular(120, 3, case["seed"])
@@ -131,15 +135,15 @@ def test_k2_three_contractions(ctx, method):
         if method == "treesa":
             kw.update(method="treesa", ntrials=4, niters=10)
         plan = tn.Plan.create(net, **kw)
-        print(f"k2 seed {case['seed']} {method} complexity {plan.complexity()}", flush=True)
-        r = ctx.solve(net, plan, "tropical_i32")
+        print(f"k2 seed {case['seed']} {method} {executor} complexity {plan.complexity()}", flush=True)
+        r = ctx.solve(net, plan, "tropical_i32", executor=executor)
         assert r["size"] == case["size_max"]
-        r = ctx.solve(net, plan, "count_exact")
+        r = ctx.solve(net, plan, "count_exact", executor=executor)
         assert r["count"] == int(case["count_all"])
         assert r["count"] > 2 ** 64  # exercises the CRT beyond the uint64 lane
-        r = ctx.solve(net, plan, "counting_tropical")
+        r = ctx.solve(net, plan, "counting_tropical", executor=executor)
         assert r["count_mod_2_64"] == int(case["count_max"])
-        r = ctx.solve(net, plan, "partition_f32", beta=0.0)
+        r = ctx.solve(net, plan, "partition_f32", beta=0.0, executor=executor)
         assert abs(r["log_z"] - case["log_z_beta0"]) <= Z_RTOL, (r, case)
 
 
