@@ -257,8 +257,8 @@ typedef struct {
     int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime
                                   (0 = default 4: three CRT primes + one check) */
     const uint32_t* primes;    /* NULL = default primes (largest primes below 2^31) */
-    int32_t slice_begin;       /* run slices [slice_begin, slice_end) only; */
-    int32_t slice_end;         /* 0,0 = all slices */
+    int64_t slice_begin;       /* run slices [slice_begin, slice_end) only; slice s */
+    int64_t slice_end;         /* fixes sliced index k to bit k of s; 0,0 = all */
     int32_t executor;          /* 0 auto: one persistent launch for unsliced trees with
                                   sc <= 22, per-node stream launches otherwise;
                                   1 per-node stream launches; 2 persistent launch

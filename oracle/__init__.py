@@ -62,8 +62,8 @@ def _load():
                                       ctypes.c_double, ctypes.c_int, f64p, u64p, f64p, f64p, ip]
         lib.orc_follow_plan.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, i32p, i32p,
-                                        i32p, i32p, i32p, i32p, ctypes.c_int, i32p, ctypes.c_int,
-                                        f64p, u64p, f64p, f64p]
+                                        i32p, i32p, i32p, i32p, ctypes.c_int, i32p, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int, f64p, u64p, f64p, f64p]
         for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_follow_plan):
             f.restype = ctypes.c_int
         _lib = lib
@@ -150,13 +150,15 @@ def eliminate(graph, semiring: str, beta: float = 0.0, max_width: int = 26) -> D
     return out
 
 
-def follow_plan(graph, tree: Dict, semiring: str, beta: float = 0.0, max_rank: int = 26) -> Dict:
+def follow_plan(graph, tree: Dict, semiring: str, beta: float = 0.0, max_rank: int = 26,
+                slices: Optional[Sequence[int]] = None) -> Dict:
     """O3: evaluate a given contraction tree with literal einsum loops.
 
     ``tree`` holds plain lists: ``leaf_factors`` (per leaf, factor codes: an
     edge id e >= 0 or a vertex v as -v-1), ``left``/``right`` (children of the
     inner nodes, numbered after the leaves), ``indices`` (output indices of
-    every node, leaves first) and ``sliced`` (indices fixed per slice).
+    every node, leaves first) and ``sliced`` (indices fixed per slice; slice s
+    sets sliced[k] to bit k of s).  ``slices=(a, b)`` sums slices a..b-1 only.
     """
     lib = _load()
     sr = SEMIRINGS[semiring]
@@ -181,7 +183,8 @@ def follow_plan(graph, tree: Dict, semiring: str, beta: float = 0.0, max_rank: i
     rc = lib.orc_follow_plan(graph.nv, graph.ne, _ptr(edges, I32), _ptr(w, ctypes.c_double), sr,
                              float(beta), nleaf, ninner, _ptr(fac_off, I32), _ptr(fac, I32),
                              _ptr(left, I32), _ptr(right, I32), _ptr(idx_off, I32), _ptr(idx, I32),
-                             nsl, _ptr(sl, I32), int(max_rank), _ptr(size, ctypes.c_double),
+                             nsl, _ptr(sl, I32), int(slices[0]) if slices else 0, int(slices[1]) if slices else 0,
+                             int(max_rank), _ptr(size, ctypes.c_double),
                              _ptr(limbs, ctypes.c_uint64), _ptr(z, ctypes.c_double),
                              _ptr(lz, ctypes.c_double))
     if rc != ORC_OK:

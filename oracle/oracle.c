@@ -549,7 +549,10 @@ int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr,
  *   idx[idx_off[x] .. idx_off[x+1])  the output indices of node x (vertex ids)
  *   sliced[0 .. nsliced)           indices fixed per slice (Sec. 4.2: slicing
  *                                 loops over a subset of indices and combines
- *                                 the slice results at the end)
+ *                                 the slice results at the end); slice s sets
+ *                                 sliced[k] to bit k of s.  A range
+ *                                 [slice_begin, slice_end) sums those slices
+ *                                 only (0, 0: all)
  *
  * The root (last node) must have no output indices.  Before evaluating, the
  * tree is checked against the einsum rule: an index stays open at a node iff
@@ -570,8 +573,9 @@ static int iset_has(const iset* s, int x) { return contains(s->v, s->n, x); }
 int orc_follow_plan(int nv, int ne, const int32_t* edges, const double* w, int sr, double beta,
                     int nleaf, int ninner, const int32_t* fac_off, const int32_t* fac,
                     const int32_t* left, const int32_t* right, const int32_t* idx_off,
-                    const int32_t* idx, int nsliced, const int32_t* sliced, int max_rank,
-                    double* size, uint64_t* limbs, double* zval, double* logz) {
+                    const int32_t* idx, int nsliced, const int32_t* sliced, int64_t slice_begin,
+                    int64_t slice_end, int max_rank, double* size, uint64_t* limbs, double* zval,
+                    double* logz) {
     if (nv < 0 || ne < 0 || nleaf < 1 || ninner < 0 || sr < 0 || sr > 3) return ORC_EINVAL;
     int nn = nleaf + ninner;
     g_overflow = 0;
@@ -678,7 +682,14 @@ int orc_follow_plan(int nv, int ne, const int32_t* edges, const double* w, int s
     int* free_idx = malloc(sizeof(int) * (size_t)(nv + 1));
     elem total = e_zero(sr);
     uint64_t nslices = (uint64_t)1 << nsliced;
-    for (uint64_t sl = 0; sl < nslices && status == ORC_OK; sl++) {
+    /* slices [slice_begin, slice_end) only; 0, 0 means all of them */
+    uint64_t sl_lo = 0, sl_hi = nslices;
+    if (slice_begin != 0 || slice_end != 0) {
+        if (slice_begin < 0 || slice_end <= slice_begin || (uint64_t)slice_end > nslices) status = ORC_EINVAL;
+        sl_lo = (uint64_t)slice_begin;
+        sl_hi = (uint64_t)slice_end;
+    }
+    for (uint64_t sl = sl_lo; sl < sl_hi && status == ORC_OK; sl++) {
         for (int u = 0; u < nv; u++) value[u] = -1;
         for (int s = 0; s < nsliced; s++) value[sliced[s]] = (int)((sl >> s) & 1);
         for (int x = 0; x < nn && status == ORC_OK; x++) {

@@ -74,8 +74,8 @@ class tn_plan_info_t(ctypes.Structure):
 
 class tn_solve_opts(ctypes.Structure):
     _fields_ = [("semiring", ctypes.c_int32), ("beta", ctypes.c_double), ("nprimes", ctypes.c_int32),
-                ("primes", ctypes.POINTER(ctypes.c_uint32)), ("slice_begin", ctypes.c_int32),
-                ("slice_end", ctypes.c_int32), ("executor", ctypes.c_int32)]
+                ("primes", ctypes.POINTER(ctypes.c_uint32)), ("slice_begin", ctypes.c_int64),
+                ("slice_end", ctypes.c_int64), ("executor", ctypes.c_int32)]
 
 
 class tn_result(ctypes.Structure):

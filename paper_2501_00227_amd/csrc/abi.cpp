@@ -76,6 +76,10 @@ void tn_ctx_destroy(tn_ctx* c) {
         }
         for (auto e : c->event_pool) (void)hipEventDestroy(e);
         if (c->pinned) (void)hipHostFree(c->pinned);
+        for (auto& b : c->pinned_pool) (void)hipHostFree(b.p);
+        for (auto& b : c->batch_overflow) dev_free(c, b.first, b.second);
+        if (c->batch_dev) dev_free(c, c->batch_dev, c->batch_dev_cap);
+        (void)hipStreamSynchronize(c->stream);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     } catch (...) {
     }

@@ -346,8 +346,9 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     if (!L.tables) return fail(TN_ENOMEM, "device allocation of the task table failed");
     size_t wbytes = weights_end;
     L.host_bytes = o_end + wbytes + 16 * jobs.size() + sizeof(int) * nq + 1024;
-    if (hipHostMalloc(&L.host, L.host_bytes, hipHostMallocDefault) != hipSuccess)
-        return fail(TN_ENOMEM, "pinned staging allocation failed");
+    L.host = pinned_acquire(ctx, L.host_bytes);
+    L.ctx = ctx;
+    if (!L.host) return fail(TN_ENOMEM, "pinned staging allocation failed");
     unsigned char* h = (unsigned char*)L.host;
     std::memset(h, 0, o_end);
     std::memcpy(h + o_jobs, bj.data(), sizeof(BJob) * bj.size());
@@ -437,7 +438,7 @@ void batch_release(BatchLaunch& L) {
         if (L.data) L.free_fn(L.data, L.data_bytes);
         if (L.tables) L.free_fn(L.tables, L.table_bytes);
     }
-    if (L.host) (void)hipHostFree(L.host);
+    if (L.host) pinned_release(L.ctx, L.host);
     L.data = L.tables = L.host = nullptr;
 }
 
@@ -462,9 +463,24 @@ void collect_trace(tn_ctx* ctx, BatchLaunch& L) {
 
 tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out) {
     auto t0 = std::chrono::steady_clock::now();
+    // bump allocation in the context's grow-only scratch; what does not fit
+    // is allocated separately and the scratch grows for the next call
     DevAllocFn alloc;
-    alloc.alloc = [ctx](size_t n) { return dev_alloc(ctx, n); };
-    alloc.free = [ctx](void* p, size_t n) { dev_free(ctx, p, n); };
+    ctx->batch_dev_used = 0;
+    alloc.alloc = [ctx](size_t n) -> void* {
+        n = (n + 255) & ~(size_t)255;
+        ctx->batch_dev_peak = std::max(ctx->batch_dev_peak, ctx->batch_dev_used + n);
+        if (ctx->batch_dev && ctx->batch_dev_used + n <= ctx->batch_dev_cap) {
+            void* p = (unsigned char*)ctx->batch_dev + ctx->batch_dev_used;
+            ctx->batch_dev_used += n;
+            return p;
+        }
+        ctx->batch_dev_used += n;
+        void* p = dev_alloc(ctx, n);
+        if (p) ctx->batch_overflow.push_back({p, n});
+        return p;
+    };
+    alloc.free = [](void*, size_t) {};
     BatchLaunch L;
     tn_status st = batch_prepare(ctx, items, L, alloc);
     if (st == TN_OK) st = batch_launch(ctx, L, ctx->stream);
@@ -474,6 +490,14 @@ tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vect
     if (st == TN_OK && L.d_trace) collect_trace(ctx, L);
     if (L.host) (void)hipStreamSynchronize(ctx->stream);
     batch_release(L);
+    if (!ctx->batch_overflow.empty()) {  // grow the scratch to this call's need
+        for (auto& b : ctx->batch_overflow) dev_free(ctx, b.first, b.second);
+        ctx->batch_overflow.clear();
+        if (ctx->batch_dev) dev_free(ctx, ctx->batch_dev, ctx->batch_dev_cap);
+        ctx->batch_dev_cap = ctx->batch_dev_peak + (ctx->batch_dev_peak >> 3);
+        ctx->batch_dev = dev_alloc(ctx, ctx->batch_dev_cap);
+        if (!ctx->batch_dev) ctx->batch_dev_cap = 0;
+    }
     double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (auto& r : out) r.seconds = sec;
     return st != TN_OK ? st : st2;

@@ -55,6 +55,7 @@ struct BatchLaunch {
     unsigned long long* d_trace = nullptr;  // per-task timestamps (profiling)
     std::vector<BTask> host_tasks;          // kept for the trace
     std::function<void(void*, size_t)> free_fn;
+    tn_ctx* ctx = nullptr;  // owner of the pinned staging buffer
 };
 
 int device_cu_count(tn_ctx* ctx);

@@ -69,6 +69,12 @@ __device__ void run_gemm(const BJob& j, const BNode& nd, i64 tile, unsigned char
     g.mb = nd.mb;
     g.mc = nd.mc;
     const int rm = nd.g.rm, rn = nd.g.rn;
+    if constexpr (is_z<D>()) {
+        if (nd.g.mfma) {
+            gemm_tile_mfma<D>(g, (u64)tile, smem);
+            return;
+        }
+    }
     if (rm == 2 && rn == 2)
         gemm_tile<D, 2, 2>(g, (u64)tile, smem);
     else if (rm == 4 && rn == 4)

@@ -45,6 +45,28 @@ tn_status ensure_pinned(tn_ctx* ctx, size_t bytes) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+void* pinned_acquire(tn_ctx* ctx, size_t bytes) {
+    std::lock_guard<std::mutex> g(ctx->pinned_mu);
+    tn_ctx::PinnedBuf* best = nullptr;
+    for (auto& b : ctx->pinned_pool)
+        if (!b.busy && b.bytes >= bytes && (!best || b.bytes < best->bytes)) best = &b;
+    if (best) {
+        best->busy = true;
+        return best->p;
+    }
+    void* p = nullptr;
+    size_t n = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) return nullptr;
+    ctx->pinned_pool.push_back({p, n, true});
+    return p;
+}
+
+void pinned_release(tn_ctx* ctx, void* p) {
+    std::lock_guard<std::mutex> g(ctx->pinned_mu);
+    for (auto& b : ctx->pinned_pool)
+        if (b.p == p) b.busy = false;
+}
+
 // ------------------------------------------------------------- profiling --
 ProfScope::ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops)
     : ctx(c), on(c->profiling) {
@@ -479,7 +501,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                              std::exp2((double)(g.lb + g.li + g.lj));
                 int shp[4] = {g.lb, g.li, g.lj, g.lk};
                 {
-                    ProfScope ps(ctx, TN_K_GEMM, np.node, o.semiring, shp, ent * eb,
+                    ProfScope ps(ctx, g.mfma ? TN_K_GEMM_MFMA : TN_K_GEMM, np.node, o.semiring, shp, ent * eb,
                                  std::exp2((double)(g.lb + g.li + g.lj + g.lk)));
                     chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s));
                 }

@@ -64,11 +64,25 @@ struct tn_ctx {
     size_t pinned_bytes = 0;
     std::map<uint64_t, tn::DevProgram> progs;  // keyed by plan uid
     int cu_count = 0;
+    // grow-only device scratch reused by synchronous persistent launches
+    void* batch_dev = nullptr;
+    size_t batch_dev_cap = 0, batch_dev_used = 0, batch_dev_peak = 0;
+    std::vector<std::pair<void*, size_t>> batch_overflow;
+    // pinned staging buffers handed to persistent launches
+    struct PinnedBuf {
+        void* p;
+        size_t bytes;
+        bool busy;
+    };
+    std::vector<PinnedBuf> pinned_pool;
+    std::mutex pinned_mu;
     std::vector<tn_task_record> task_trace;  // persistent-launch timelines (profiling)
 };
 
 namespace tn {
 
+void* pinned_acquire(tn_ctx* ctx, size_t bytes);
+void pinned_release(tn_ctx* ctx, void* p);
 void* dev_alloc(tn_ctx* ctx, size_t bytes);
 void dev_free(tn_ctx* ctx, void* p, size_t bytes);
 tn_status ensure_pinned(tn_ctx* ctx, size_t bytes);

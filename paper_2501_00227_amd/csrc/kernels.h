@@ -65,6 +65,7 @@ struct GemmShape {
     int tb, ti, tj, tk;    // log2 tile (batch, M, N, K-step)
     int rm, rn;            // per-thread micro tile
     int lsplit;            // log2 of K splits (partials then reduce)
+    int mfma;              // partition function on matrix cores (64 x 64 tile, 4 waves)
 };
 
 void build_perm_params(int rank, const int* src, PermParams& pp);

@@ -182,6 +182,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     gemm_tile<D, RM, RN>(g, blockIdx.x, smem);
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gemm_tile_mfma<D>(g, blockIdx.x, smem);
+}
+
 GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
     GemmShape g{};
     g.lb = lb;
@@ -192,13 +198,16 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     g.b_t = b_t;
     const int eb = lds_elem_bytes(dsr);
     const int lds_cap = 40 * 1024;
+    g.mfma = 0;
     if (li >= 6 && lj >= 6 && lk >= 4) {
-        // contraction-heavy node: 64x64 tile, 4x4 per thread
+        // contraction-heavy node: 64x64 tile, 4x4 per thread (or one 32x32
+        // matrix-core block per wave for the partition function)
         g.rm = g.rn = 4;
         g.ti = g.tj = 6;
         g.tb = 0;
         g.tk = lk < 5 ? lk : 5;
         while (g.tk > 0 && (1 << g.tk) * 128 * eb > lds_cap) g.tk--;
+        g.mfma = (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) ? 1 : 0;
     } else {
         g.rm = li >= 1 ? 2 : 1;
         g.rn = lj >= 1 ? 2 : 1;
@@ -241,6 +250,11 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
+    if (g.mfma) {
+        if (dsr != DSR_Z_F32 && dsr != DSR_Z_BF16) return false;
+        if (g.ti != 6 || g.tj != 6 || g.tb != 0) return false;
+        if (g.tk < (dsr == DSR_Z_BF16 ? 4 : 1)) return false;
+    }
     if (g.tb < 0 || g.ti < 0 || g.tj < 0 || g.tk < 0 || g.lsplit < 0) return false;
     if (g.tb > g.lb || g.ti > g.li || g.tj > g.lj || g.tk + g.lsplit > g.lk) return false;
     if (g.rm != 1 && g.rm != 2 && g.rm != 4) return false;
@@ -304,6 +318,13 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
     GemmArgs a = make_gemm_args(Ap, Bp, Cp, part, g, ap, meta, ma, mb, mc);
     size_t lds = gemm_lds_bytes(dsr, g);
     u64 blocks = 1ull << ((g.lb - g.tb) + (g.li - g.ti) + (g.lj - g.tj) + g.lsplit);
+    if (g.mfma) {
+        if (dsr == DSR_Z_F32)
+            gemm_mfma_kernel<DSR_Z_F32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        else
+            gemm_mfma_kernel<DSR_Z_BF16><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        return hipGetLastError();
+    }
 #define TN_GM(D) \
     case D: return gemm_dispatch<D>(a, g.rm, g.rn, lds, blocks, s);
     switch (dsr) {

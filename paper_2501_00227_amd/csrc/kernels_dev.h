@@ -336,6 +336,93 @@ __device__ inline float input_scale(const GemmArgs& g, int m) {
 
 __host__ __device__ inline int pad_dim(int t) { return t + (t >= 32 ? 1 : 0); }
 
+// Position of one workgroup tile: split index, first batch / row / column,
+// first k of its K range and the length of that range.
+struct TilePos {
+    int split;
+    i64 b0, i0, j0, kbeg;
+    int Kc;
+};
+
+__device__ inline TilePos tile_pos(const GemmArgs& g, u64 tile) {
+    TilePos p;
+    p.split = (int)(tile & ((1u << g.lsplit) - 1));
+    tile >>= g.lsplit;
+    const int ntn = g.lj - g.tj, ntm = g.li - g.ti;
+    const i64 jt = (i64)(tile & ((1ull << ntn) - 1));
+    tile >>= ntn;
+    const i64 it = (i64)(tile & ((1ull << ntm) - 1));
+    tile >>= ntm;
+    p.b0 = (i64)tile << g.tb;
+    p.i0 = it << g.ti;
+    p.j0 = jt << g.tj;
+    const int lkc = g.lk - g.lsplit;
+    p.kbeg = (i64)p.split << lkc;
+    p.Kc = 1 << lkc;
+    return p;
+}
+
+// Stage the A tile as As[batch][k][row] and the B tile as Bs[batch][k][col]
+// for k in [k0, k0 + TK), reading global memory in its own order.
+template <int D>
+__device__ inline void gemm_stage(const GemmArgs& g, const TilePos& p, i64 k0, typename Alg<D>::V* As,
+                                  typename Alg<D>::V* Bs, float sA, float sB) {
+    using A = Alg<D>;
+    const int TB = 1 << g.tb, TM = 1 << g.ti, TN = 1 << g.tj, TK = 1 << g.tk;
+    const int TMp = pad_dim(TM), TNp = pad_dim(TN);
+    const int tid = threadIdx.x;
+    const int na = TB * TM * TK, nb = TB * TK * TN;
+    for (int idx = tid; idx < na; idx += 256) {
+        int bb, i, k;
+        i64 addr;
+        if (!g.a_t) {  // memory order (b, i, k)
+            k = idx & (TK - 1);
+            i = (idx >> g.tk) & (TM - 1);
+            bb = idx >> (g.tk + g.ti);
+            addr = ((((p.b0 + bb) << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
+        } else {  // memory order (b, k, i)
+            i = idx & (TM - 1);
+            k = (idx >> g.ti) & (TK - 1);
+            bb = idx >> (g.tk + g.ti);
+            addr = ((((p.b0 + bb) << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
+        }
+        As[(bb * TK + k) * TMp + i] = A::prescale(A::load(g.A, addr), sA);
+    }
+    for (int idx = tid; idx < nb; idx += 256) {
+        int bb, j, k;
+        i64 addr;
+        if (!g.b_t) {  // memory order (b, k, j)
+            j = idx & (TN - 1);
+            k = (idx >> g.tj) & (TK - 1);
+            bb = idx >> (g.tk + g.tj);
+            addr = ((((p.b0 + bb) << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
+        } else {  // memory order (b, j, k)
+            k = idx & (TK - 1);
+            j = (idx >> g.tk) & (TN - 1);
+            bb = idx >> (g.tk + g.tj);
+            addr = ((((p.b0 + bb) << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
+        }
+        Bs[(bb * TK + k) * TNp + j] = A::prescale(A::load(g.B, addr), sB);
+    }
+}
+
+// Partition function: the exponent of C (first tile only) and the running
+// maximum of the stored entries (one atomic per wave).
+template <int D>
+__device__ inline void z_epilogue(const GemmArgs& g, u64 first_tile, float lmax) {
+    if constexpr (is_z<D>()) {
+        if (first_tile == 0 && threadIdx.x == 0) {
+            meta_set_exp(g.meta, g.mc,
+                         meta_exp(g.meta, g.ma) + max_exponent(meta_maxbits(g.meta, g.ma)) + meta_exp(g.meta, g.mb) +
+                             max_exponent(meta_maxbits(g.meta, g.mb)));
+        }
+        if (!g.lsplit) {
+            for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
+            if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(g.meta, g.mc, __float_as_uint(lmax));
+        }
+    }
+}
+
 template <int D, int RM, int RN>
 __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
     using A = Alg<D>;
@@ -344,19 +431,7 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
     const int TMp = pad_dim(TM), TNp = pad_dim(TN);
     V* As = (V*)smem;
     V* Bs = As + (size_t)TB * TK * TMp;
-
-    const u64 first = tile;
-    const int split = (int)(tile & ((1u << g.lsplit) - 1));
-    tile >>= g.lsplit;
-    const int ntn = g.lj - g.tj, ntm = g.li - g.ti;
-    const i64 jt = (i64)(tile & ((1ull << ntn) - 1));
-    tile >>= ntn;
-    const i64 it = (i64)(tile & ((1ull << ntm) - 1));
-    tile >>= ntm;
-    const i64 b0 = (i64)tile << g.tb, i0 = it << g.ti, j0 = jt << g.tj;
-    const int lkc = g.lk - g.lsplit;
-    const i64 kbeg = (i64)split << lkc;
-    const int Kc = 1 << lkc;
+    const TilePos p = tile_pos(g, tile);
 
     const int TNt = TN / RN, TMt = TM / RM;
     const int active = TB * TMt * TNt;
@@ -371,41 +446,8 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
 #pragma unroll
         for (int c = 0; c < RN; c++) acc[r][c] = A::zero(g.ap);
 
-    const int na = TB * TM * TK, nb = TB * TK * TN;
-    for (int kk = 0; kk < Kc; kk += TK) {
-        const i64 k0 = kbeg + kk;
-        for (int idx = tid; idx < na; idx += 256) {
-            int bb, i, k;
-            i64 addr;
-            if (!g.a_t) {  // memory order (b, i, k)
-                k = idx & (TK - 1);
-                i = (idx >> g.tk) & (TM - 1);
-                bb = idx >> (g.tk + g.ti);
-                addr = ((((b0 + bb) << g.li) | (i0 + i)) << g.lk) | (k0 + k);
-            } else {  // memory order (b, k, i)
-                i = idx & (TM - 1);
-                k = (idx >> g.ti) & (TK - 1);
-                bb = idx >> (g.tk + g.ti);
-                addr = ((((b0 + bb) << g.lk) | (k0 + k)) << g.li) | (i0 + i);
-            }
-            As[(bb * TK + k) * TMp + i] = A::prescale(A::load(g.A, addr), sA);
-        }
-        for (int idx = tid; idx < nb; idx += 256) {
-            int bb, j, k;
-            i64 addr;
-            if (!g.b_t) {  // memory order (b, k, j)
-                j = idx & (TN - 1);
-                k = (idx >> g.tj) & (TK - 1);
-                bb = idx >> (g.tk + g.tj);
-                addr = ((((b0 + bb) << g.lk) | (k0 + k)) << g.lj) | (j0 + j);
-            } else {  // memory order (b, j, k)
-                k = idx & (TK - 1);
-                j = (idx >> g.tk) & (TN - 1);
-                bb = idx >> (g.tk + g.tj);
-                addr = ((((b0 + bb) << g.lj) | (j0 + j)) << g.lk) | (k0 + k);
-            }
-            Bs[(bb * TK + k) * TNp + j] = A::prescale(A::load(g.B, addr), sB);
-        }
+    for (int kk = 0; kk < p.Kc; kk += TK) {
+        gemm_stage<D>(g, p, p.kbeg + kk, As, Bs, sA, sB);
         __syncthreads();
         if (tid < active) {
             const V* ap_ = As + (size_t)z * TK * TMp + y;
@@ -425,33 +467,82 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
         __syncthreads();
     }
 
-    if constexpr (is_z<D>()) {
-        if (first == 0 && tid == 0) {
-            meta_set_exp(g.meta, g.mc,
-                         meta_exp(g.meta, g.ma) + max_exponent(meta_maxbits(g.meta, g.ma)) + meta_exp(g.meta, g.mb) +
-                             max_exponent(meta_maxbits(g.meta, g.mb)));
-        }
-    }
     float lmax = 0.0f;
     if (tid < active) {
         const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
         const Planes dst = g.lsplit ? g.P : g.C;
-        const i64 base = g.lsplit ? (i64)split * nout : 0;
+        const i64 base = g.lsplit ? (i64)p.split * nout : 0;
 #pragma unroll
         for (int r = 0; r < RM; r++)
 #pragma unroll
             for (int c = 0; c < RN; c++) {
-                i64 o = ((((b0 + z) << g.li) | (i0 + y + r * TMt)) << g.lj) | (j0 + x + c * TNt);
+                i64 o = ((((p.b0 + z) << g.li) | (p.i0 + y + r * TMt)) << g.lj) | (p.j0 + x + c * TNt);
                 A::store(dst, base + o, acc[r][c]);
                 if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc[r][c]);
             }
     }
-    if constexpr (is_z<D>()) {
-        if (!g.lsplit) {
-            for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
-            if ((tid & 63) == 0 && lmax > 0.0f) meta_max(g.meta, g.mc, __float_as_uint(lmax));
+    z_epilogue<D>(g, tile, lmax);
+}
+
+// Partition function on the matrix cores: a 64 x 64 tile (tb = 0), four
+// waves in a 2 x 2 grid, each accumulating a 32 x 32 block with
+// v_mfma_f32_32x32x2f32 (float32 inputs) or v_mfma_f32_32x32x16_bf16
+// (bfloat16 inputs, the staged values are already rounded), float32
+// accumulation.  Lane l holds A[l%32][k + l/32] (x2f32; for x16_bf16 eight
+// consecutive k starting at 8*(l/32)), B likewise by column, and result
+// register r is row 8*(r/4) + 4*(l/32) + r%4, column l%32.
+typedef float tn_v16f __attribute__((ext_vector_type(16)));
+typedef short tn_v8s __attribute__((ext_vector_type(8)));
+
+template <int D>
+__device__ void gemm_tile_mfma(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    static_assert(is_z<D>(), "matrix cores serve the real algebra only");
+    const int TK = 1 << g.tk;
+    const int TMp = pad_dim(64), TNp = pad_dim(64);
+    float* As = (float*)smem;
+    float* Bs = As + (size_t)TK * TMp;
+    const TilePos p = tile_pos(g, tile);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int half = lane >> 5, l32 = lane & 31;
+    const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    tn_v16f acc;
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0.0f;
+    for (int kk = 0; kk < p.Kc; kk += TK) {
+        gemm_stage<D>(g, p, p.kbeg + kk, As, Bs, sA, sB);
+        __syncthreads();
+        const float* ap_ = As + wr * 32 + l32;
+        const float* bp_ = Bs + wc * 32 + l32;
+        if constexpr (D == DSR_Z_BF16) {
+            for (int k = 0; k < TK; k += 16) {
+                tn_v8s a, b;
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    a[t] = (short)(__float_as_uint(ap_[(k + 8 * half + t) * TMp]) >> 16);
+                    b[t] = (short)(__float_as_uint(bp_[(k + 8 * half + t) * TNp]) >> 16);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+        } else {
+            for (int k = 0; k < TK; k += 2) {
+                float a = ap_[(k + half) * TMp], b = bp_[(k + half) * TNp];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            }
         }
+        __syncthreads();
     }
+    const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
+    float* dst = (float*)(g.lsplit ? g.P.p0 : g.C.p0) + (g.lsplit ? (i64)p.split * nout : 0);
+    float lmax = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+        const i64 o = (((p.b0 << g.li) | (p.i0 + wr * 32 + row)) << g.lj) | (p.j0 + wc * 32 + l32);
+        dst[o] = acc[r];
+        lmax = fmaxf(lmax, acc[r]);
+    }
+    z_epilogue<D>(g, tile, lmax);
 }
 
 // --------------------------------------------------------- split reduce --
