@@ -1,66 +1,93 @@
 """Benchmark of the hot path on one MI355X.
 
-One step = the three contractions of the 3-regular n=120 workload (seeded
-random 3-regular graph, unit weights, TreeSA order): max independent-set size
-in int32 max-plus, exact independent-set count (uint64 lane + residues mod
-three primes + a check prime, CRT), and the partition function at x = 1 in
-float32 with per-tensor power-of-two exponents.  Inputs (leaf data, plan
-tables) are resident on the device before timing; planning is host-side and
-untimed.
+Headline (``value``): one step = the three contractions of the seeded
+3-regular n=120 network (unit weights, TreeSA order), run as one persistent
+launch: max independent-set size (int32 max-plus), exact independent-set
+count (uint64 lane + residues mod three primes + a check prime, CRT) and the
+partition function at x = 1 (float32, per-tensor power-of-two exponents).
+Leaf data and plan tables are resident on the device before timing; planning
+is host-side and untimed.  value = 3 x 2^tc semiring ops / seconds per step,
+tc the plan's time complexity (Sec. 4.1).
 
-Prints one JSON line:
-  value        semiring GOP/s = (3 x 2^tc) / seconds per step, tc the plan's
-               time complexity (Sec. 4.1: product of index dimensions summed
-               over the binary contractions)
-  roofline     the dominant kernel (largest share of measured device time),
-               its algorithmic ops or bytes per launch over its average
-               launch duration, against the MI355X peak of its bound
-  cpu_baseline the CPU oracle producing the same three results, timed on the
-               host cores
+Also reported in the same JSON line:
+  roofline              the dominant kernel of the timed step (HIP events on
+                        the context stream), algorithmic bytes per launch over
+                        its average launch duration, against HBM peak
+  largest_intermediate  one slice of the 240-vertex 3-regular network planned
+                        to a largest intermediate of 2^30 entries: the GEMM
+                        node with the most semiring ops and the largest permute,
+                        against the VALU peak of their algebra / HBM peak
+  batched / served      a stream of 3-regular jobs (n even in [40, 120],
+                        algebra uniform over tropical int32, counting tropical,
+                        float32 partition function): one-at-a-time, batched
+                        (persistent launches of 256 jobs) and served
+                        (Poisson arrivals at 0.5, 1 and 2 x the one-at-a-time
+                        rate; p50/p99 latency submit -> result on the host)
+  cpu_baseline          the CPU oracle producing the step's three results
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the VALU issue model of each GEMM inner loop
 HBM_GBS = 8000.0
 CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
-LANE_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0  # 39.3 T 32-bit lane instructions/s
-# VALU instructions per semiring op in the register-tiled inner loop (from the
-# compiled gfx950 code: see DESIGN.md, "Kernels and their rooflines")
-INSTR_PER_OP = {0: 1.5, 1: 1.5, 2: 10.0, 3: 4.0, 4: 7.0, 5: 1.0, 6: 1.0}
+LANE_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0  # 39.3 T 32-bit lane instructions / s
+# VALU instructions per semiring op of the register-tiled GEMM inner loop,
+# counted in the compiled gfx950 code (max-plus: v_add clamp + v_max3 per two
+# ops; counting tropical: add-sat, 64-bit multiply, compare/select, 64-bit add)
+INSTR_PER_OP = {"tropical_i32": 1.5, "tropical_f32": 1.5, "counting_tropical": 12.0}
 SR_NAME = {0: "tropical_i32", 1: "tropical_f32", 2: "counting_tropical", 3: "count_exact", 4: "partition_f32",
-           5: "partition_bf16"}
+           5: "partition_bf16", -1: "mixed"}
+MFMA_F32_TFLOPS = 157.3
+
+STEP = (("tropical_i32", 0.0), ("count_exact", 0.0), ("partition_f32", 0.0))
 
 
-def build_workload(seed: int = 0, n: int = 120):
+def build_k2(seed):
     import graphgen as gg
     import paper_2501_00227_amd as tn
 
-    g = gg.random_regular(n, 3, seed)
+    g = gg.random_regular(120, 3, seed)
     net = tn.Net.from_graph(g)
     plan = tn.Plan.create(net, method="treesa", ntrials=8, niters=20, seed=seed)
     return g, net, plan
 
 
-STEP = (("tropical_i32", 0.0), ("count_exact", 0.0), ("partition_f32", 0.0))
-
-
-def run_step(ctx, net, plan):
-    """The three contractions of one step as one persistent launch."""
+def run_step(ctx, net, plan, executor="persistent"):
+    """The three contractions of one step: one persistent launch, or (for
+    comparison) per-node stream launches, one contraction after the other."""
+    if executor == "stream":
+        return [ctx.solve(net, plan, s, beta=b, executor="stream") for s, b in STEP]
     return ctx.solve_batch([net] * len(STEP), [plan] * len(STEP), [s for s, _ in STEP], [b for _, b in STEP])
 
 
-def dominant_kernel(recs):
-    """Group launch records by (kind, algebra); pick the group with most time."""
+def measured_traffic():
+    """HBM bytes per launch of the persistent kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if the kernel is unchanged since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k2_step_persistent_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    srcs = ["paper_2501_00227_amd/csrc/batch_kernels.hip", "paper_2501_00227_amd/csrc/kernels_dev.h"]
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in srcs)).hexdigest()[:16]
+    if h != rec.get("kernel_source_sha256_16"):
+        return None
+    return rec["batch_kernel"]["traffic_bytes_per_launch"]
+
+
+def group(recs):
     groups = {}
     for r in recs:
         key = (r["kind"], r["semiring"])
@@ -69,8 +96,7 @@ def dominant_kernel(recs):
         g["n"] += 1
         g["ops"] += r["ops"]
         g["bytes"] += r["alg_bytes"]
-    key = max(groups, key=lambda k: groups[k]["ms"])
-    return key, groups[key], groups
+    return groups
 
 
 def cpu_baseline(g, ops_per_step):
@@ -87,16 +113,125 @@ def cpu_baseline(g, ops_per_step):
             "seconds": dt}
 
 
+def largest_intermediate(ctx):
+    """One slice of the n=240 network planned to sc = 30, per-node timings."""
+    import graphgen as gg
+    import paper_2501_00227_amd as tn
+
+    g = gg.random_regular(240, 3, 0)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, method="treesa", ntrials=8, niters=10, sc_target=30, nslices=30, seed=0)
+    tc, sc, rwc = plan.complexity()
+    info = plan.info()
+    out = {"workload": "3-regular n=240 seed 0, TreeSA sc_target 30: slice 0 of %d" % (1 << info["nsliced"]),
+           "tc_log2_per_slice": tc - info["nsliced"], "sc_log2": sc, "nsliced": info["nsliced"]}
+    for sr in ("tropical_f32", "counting_tropical"):
+        ctx.solve(net, plan, sr, slices=(0, 1))  # warm
+        ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        ctx.solve(net, plan, sr, slices=(0, 1))
+        dt = time.perf_counter() - t0
+        recs = ctx.profile()
+        ctx.set_profiling(False)
+        gem = max((r for r in recs if r["kind"] == "gemm"), key=lambda r: r["ops"])
+        perm = max((r for r in recs if r["kind"] == "permute"), key=lambda r: r["alg_bytes"])
+        peak = LANE_TOPS / INSTR_PER_OP[sr]
+        tops = gem["ops"] / gem["ms"] / 1e9
+        gbs = perm["alg_bytes"] / perm["ms"] / 1e6
+        out[sr] = {
+            "slice_seconds": dt,
+            "slice_GOPs": 2.0 ** (tc - info["nsliced"]) / dt / 1e9,
+            "largest_gemm": {"shape_log2_bikj": gem["shape"], "ms": gem["ms"], "achieved": tops, "unit": "TOP/s",
+                             "peak": peak, "bound": "alu", "frac": tops / peak},
+            "largest_permute": {"rank": perm["shape"][0], "ms": perm["ms"], "achieved": gbs, "unit": "GB/s",
+                                "peak": HBM_GBS, "bound": "hbm", "frac": gbs / HBM_GBS},
+        }
+    return out
+
+
+def job_stream(ctx, njobs, seed=0):
+    """Batched and served throughput on a stream of small 3-regular jobs."""
+    import numpy as np
+
+    import graphgen as gg
+    import paper_2501_00227_amd as tn
+
+    mix = gg.job_mix(njobs, seed, 40, 120)
+
+    def mk(j):
+        n, gseed, sr = j
+        net = tn.Net.from_graph(gg.random_regular(n, 3, gseed))
+        return net, tn.Plan.create(net, seed=gseed), sr
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(8) as ex:
+        jobs = list(ex.map(mk, mix))
+    plan_s = time.perf_counter() - t0
+    res = {"jobs": njobs, "n_range": [40, 120], "planning_seconds_8_threads": plan_s}
+    # one at a time (a sample), each tn_solve synchronous
+    sample = jobs[: min(300, njobs)]
+    for net, plan, sr in sample[:20]:
+        ctx.solve(net, plan, sr)
+    t0 = time.perf_counter()
+    for net, plan, sr in sample:
+        ctx.solve(net, plan, sr)
+    plain = len(sample) / (time.perf_counter() - t0)
+    res["plain_solves_per_s"] = plain
+    # batched: persistent launches of 256 jobs
+    t0 = time.perf_counter()
+    for k in range(0, njobs, 256):
+        chunk = jobs[k:k + 256]
+        ctx.solve_batch([c[0] for c in chunk], [c[1] for c in chunk], [c[2] for c in chunk])
+    res["batched_solves_per_s"] = njobs / (time.perf_counter() - t0)
+    # served: Poisson arrivals at 0.5, 1 and 2 x the one-at-a-time rate
+    res["served"] = []
+    for mult in (0.5, 1.0, 2.0):
+        rate = mult * plain
+        arrivals = gg.poisson_arrivals(njobs, rate, seed + 1)
+        srv = tn.Server(ctx, 16 << 30, max_slots=512)
+        ids = [None] * njobs
+        t_start = time.perf_counter()
+
+        def producer():
+            for i, (net, plan, sr) in enumerate(jobs):
+                dt = arrivals[i] - (time.perf_counter() - t_start)
+                if dt > 0:
+                    time.sleep(dt)
+                ids[i] = srv.submit(net, plan, sr)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        srv.drain()
+        t_end = time.perf_counter()
+        lat = np.array([srv.poll(i)["latency_s"] for i in ids])
+        st = srv.stats()
+        srv.close()
+        res["served"].append({"arrival_rate_per_s": rate, "rate_over_plain": mult,
+                              "solves_per_s": njobs / (t_end - t_start),
+                              "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                              "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                              "launches": st["launches"], "peak_running": st["peak_running"],
+                              "peak_admitted_bytes": st["peak_admitted_bytes"], "budget_bytes": 16 << 30})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--jobs", type=int, default=2000, help="jobs in the batched / served stream")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline step only")
+    ap.add_argument("--executor", default="persistent", choices=["persistent", "stream"],
+                    help="persistent launch per step (default) or per-node stream launches")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 256 MiB device copy (for scaling hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the path shards by slices and jobs with one final "
+        print("bench.py measures one GPU only: the path would shard by slices and jobs with one final "
               "(+)-reduction of a scalar root, which this build does not run; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -104,40 +239,45 @@ def main():
     import paper_2501_00227_amd as tn
 
     torch.cuda.set_device(0)
-    g, net, plan = build_workload(args.seed)
+    if args.calibrate_copy:
+        x = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "copies": 3}))
+        return
+    g, net, plan = build_k2(args.seed)
     tc, sc, rwc = plan.complexity()
     ctx = tn.Context(0)
     for _ in range(args.warmup):
-        run_step(ctx, net, plan)
+        run_step(ctx, net, plan, args.executor)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res = run_step(ctx, net, plan)
+        res = run_step(ctx, net, plan, args.executor)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     ops_per_step = len(STEP) * 2.0 ** tc
     value = ops_per_step / dt / 1e9
 
-    # one profiled step: HIP events around every launch on the context stream
+    # profiled steps: HIP events around every launch on the context stream
     ctx.set_profiling(True)
-    run_step(ctx, net, plan)
+    for _ in range(5):
+        run_step(ctx, net, plan, args.executor)
     recs = ctx.profile(clear=True)
     ctx.set_profiling(False)
-    (kind, sr), grp, groups = dominant_kernel(recs)
+    groups = group(recs)
+    (kind, sr) = max(groups, key=lambda k: groups[k]["ms"])
+    grp = groups[(kind, sr)]
     avg_ms = grp["ms"] / grp["n"]
-    if kind in ("gemm", "gemm_mfma"):
-        achieved = grp["ops"] / grp["n"] / (avg_ms * 1e-3) / 1e12
-        peak = LANE_TOPS / INSTR_PER_OP.get(sr, 1.0)
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                "frac": achieved / peak, "traffic": None}
-    else:
-        achieved = grp["bytes"] / grp["n"] / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_GBS, "traffic": None}
-    roof["kernel"] = f"{kind}/{SR_NAME.get(sr, sr)}"
-    roof["avg_launch_ms"] = avg_ms
-    roof["launches"] = grp["n"]
-    roof["share_of_device_time"] = grp["ms"] / sum(x["ms"] for x in groups.values())
+    achieved = grp["bytes"] / grp["n"] / (avg_ms * 1e-3) / 1e9
+    kname = "batch_kernel (persistent: %s)" % SR_NAME.get(sr, sr) if kind == "batch" else "%s/%s" % (kind, SR_NAME.get(sr, sr))
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s", "frac": achieved / HBM_GBS,
+            "traffic": measured_traffic() if kind == "batch" else None, "kernel": kname,
+            "avg_launch_ms": avg_ms, "launches": grp["n"],
+            "alg_bytes_per_launch": grp["bytes"] / grp["n"], "ops_per_launch": grp["ops"] / grp["n"],
+            "share_of_device_time": grp["ms"] / sum(x["ms"] for x in groups.values())}
 
     out = {
         "metric": "semiring GOP/s & % roofline at largest intermediate; batched solves/s + p50/p99",
@@ -152,12 +292,17 @@ def main():
         "vs_baseline": None,
         "dtype": "i32+u64+u32+f32",
         "data": "synthetic",
-        "config": {"workload": "3-regular n=120 seed %d, unit weights: tropical int32 + exact count (CRT) + "
-                               "Z(x=1) fp32" % args.seed,
+        "config": {"workload": "3-regular n=120 seed %d, unit weights: tropical int32 + exact count (uint64 + 4 "
+                               "primes, CRT) + Z(x=1) fp32, %s" % (args.seed, "one persistent launch per step"
+                                                                   if args.executor == "persistent"
+                                                                   else "per-node stream launches"),
                    "tc_log2": tc, "sc_log2": sc, "rwc_log2": rwc},
         "roofline": roof,
         "results": {"size_max": res[0]["size"], "count_all": str(res[1]["count"]), "log_z": res[2]["log_z"]},
     }
+    if not args.quick:
+        out["largest_intermediate"] = largest_intermediate(ctx)
+        out["batched"] = job_stream(ctx, args.jobs, args.seed)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, ops_per_step)
     print(json.dumps(out))
