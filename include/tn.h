@@ -111,7 +111,8 @@ typedef enum {
     TN_K_GEMM = 2,      /* batched semiring GEMM (VALU) */
     TN_K_GEMM_MFMA = 3, /* batched GEMM on matrix cores (partition function) */
     TN_K_ACCUM = 4,     /* slice accumulation / root handling */
-    TN_K_BATCH = 5      /* persistent batched launch */
+    TN_K_BATCH = 5,     /* persistent batched launch */
+    TN_K_GEMM_BIG = 6   /* batched semiring GEMM, 128 x 128 register-tiled VALU kernel */
 } tn_kernel_kind;
 
 typedef struct {

@@ -33,7 +33,7 @@ SEMIRING = {
     "partition_f32": TN_PARTITION_F32,
     "partition_bf16": TN_PARTITION_BF16,
 }
-KERNEL_KIND = {0: "leaf", 1: "permute", 2: "gemm", 3: "gemm_mfma", 4: "accum", 5: "batch"}
+KERNEL_KIND = {0: "leaf", 1: "permute", 2: "gemm", 3: "gemm_mfma", 4: "accum", 5: "batch", 6: "gemm_big"}
 
 
 class LibraryMissing(RuntimeError):

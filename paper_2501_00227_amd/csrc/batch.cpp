@@ -111,9 +111,9 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             jp.dsr = st.passes[p].dsr;
             jp.prime = st.passes[p].prime;
             jp.dp = dp;
-            jp.nl = dp ? &node_launches(*dp, *it.plan, jp.dsr) : nullptr;
+            jp.nl = dp ? &node_launches(*dp, *it.plan, jp.dsr, false) : nullptr;
             jp.E = std::max<int64_t>(it.plan->arena_entries_dag, 64);
-            jp.Pe = dp ? dp->part_entries_dag[jp.dsr] : 0;
+            jp.Pe = dp ? dp->part_entries_dag[launch_key(jp.dsr, false)] : 0;
             int pb0 = plane_bytes(jp.dsr, 0), pb1 = plane_bytes(jp.dsr, 1);
             jp.o_arena0 = data;
             data = a256(data + (size_t)jp.E * pb0);
@@ -221,7 +221,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             N.c_off = np.dag_c_off;
             N.nout = (int64_t)1 << (N.g.lb + N.g.li + N.g.lj);
             N.reduce_per_block = N.nout < 1024 ? 1 : 0;
-            N.part_off = jp.dp->part_off_dag[jp.dsr][t];
+            N.part_off = jp.dp->part_off_dag[launch_key(jp.dsr, false)][t];
             for (int side = 0; side < 2; side++) {
                 int child = side ? np.b : np.a;
                 bool perm = side ? np.perm_b : np.perm_a;

@@ -166,15 +166,16 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     return TN_OK;
 }
 
-const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr) {
-    auto it = dp.launches.find(dsr);
+const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr, bool big) {
+    const int key = launch_key(dsr, big);
+    auto it = dp.launches.find(key);
     if (it != dp.launches.end()) return it->second;
     std::vector<NodeLaunch> v(p.prog.size());
     int64_t part = 0, part_dag = 0;
     std::vector<int64_t> part_off(p.prog.size(), 0);
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
-        v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+        v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t, big ? 1 : 0);
         if (v[t].shape.lsplit > 0)
             v[t].part_entries = (int64_t)1 << (v[t].shape.lsplit + np.lb + np.li + np.lj);
         part = std::max(part, v[t].part_entries);
@@ -182,10 +183,10 @@ const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int 
         part_off[t] = part_dag;
         part_dag += (v[t].part_entries + 63) & ~(int64_t)63;
     }
-    dp.part_entries[dsr] = part;
-    dp.part_off_dag[dsr] = part_off;
-    dp.part_entries_dag[dsr] = part_dag;
-    return dp.launches.emplace(dsr, std::move(v)).first->second;
+    dp.part_entries[key] = part;
+    dp.part_off_dag[key] = part_off;
+    dp.part_entries_dag[key] = part_dag;
+    return dp.launches.emplace(key, std::move(v)).first->second;
 }
 
 // --------------------------------------------------------------- algebra --
@@ -405,8 +406,8 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     int64_t Pe = 0;
     for (auto& ps : passes) {
         if (dp) {
-            node_launches(*dp, plan, ps.dsr);
-            Pe = std::max(Pe, dp->part_entries[ps.dsr]);
+            node_launches(*dp, plan, ps.dsr, true);
+            Pe = std::max(Pe, dp->part_entries[launch_key(ps.dsr, true)]);
         }
     }
     int pb0 = 0, pb1 = 0;
@@ -459,7 +460,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
             chk(launch_set_one(dsr, acc, ap, s));
             continue;
         }
-        const auto& launches = node_launches(*dp, plan, dsr);
+        const auto& launches = node_launches(*dp, plan, dsr, true);
         for (int64_t sl = sb; sl < se && herr == hipSuccess; sl++) {
             if (is_z) chk(launch_meta_init(meta, nn, s));
             {
@@ -501,7 +502,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                              std::exp2((double)(g.lb + g.li + g.lj));
                 int shp[4] = {g.lb, g.li, g.lj, g.lk};
                 {
-                    ProfScope ps(ctx, g.mfma ? TN_K_GEMM_MFMA : TN_K_GEMM, np.node, o.semiring, shp, ent * eb,
+                    ProfScope ps(ctx, g.mfma ? TN_K_GEMM_MFMA : (g.rm == 8 ? TN_K_GEMM_BIG : TN_K_GEMM), np.node, o.semiring, shp, ent * eb,
                                  std::exp2((double)(g.lb + g.li + g.lj + g.lk)));
                     chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s));
                 }

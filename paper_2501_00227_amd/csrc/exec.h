@@ -87,7 +87,11 @@ void* dev_alloc(tn_ctx* ctx, size_t bytes);
 void dev_free(tn_ctx* ctx, void* p, size_t bytes);
 tn_status ensure_pinned(tn_ctx* ctx, size_t bytes);
 tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out);
-const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr);
+// Tile shapes of every node for one device algebra; big selects the shapes of
+// the per-node stream executor (1) or of the persistent executor (0).  The
+// per-algebra maps of DevProgram are keyed by launch_key(dsr, big).
+inline int launch_key(int dsr, bool big) { return dsr + (big ? 16 : 0); }
+const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr, bool big);
 
 // Profiling bracket around one launch (no-op unless profiling is on).
 struct ProfScope {

@@ -183,12 +183,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 }
 
 template <int D>
+__global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gemm_tile_big<D>(g, blockIdx.x, smem);
+}
+
+template <int D>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
     extern __shared__ __align__(16) unsigned char smem[];
     gemm_tile_mfma<D>(g, blockIdx.x, smem);
 }
 
-GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
+GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, int big) {
     GemmShape g{};
     g.lb = lb;
     g.li = li;
@@ -199,7 +205,14 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     const int eb = lds_elem_bytes(dsr);
     const int lds_cap = 40 * 1024;
     g.mfma = 0;
-    if (li >= 6 && lj >= 6 && lk >= 4) {
+    const bool four_byte_valu = dsr == DSR_TROP_I32 || dsr == DSR_TROP_F32 || dsr == DSR_MODP;
+    if (big && four_byte_valu && li >= 7 && lj >= 7 && lk >= 4) {
+        // contraction-heavy node: 128x128 tile, 8x8 per thread
+        g.rm = g.rn = 8;
+        g.ti = g.tj = 7;
+        g.tb = 0;
+        g.tk = lk < 5 ? lk : 5;
+    } else if (li >= 6 && lj >= 6 && lk >= 4) {
         // contraction-heavy node: 64x64 tile, 4x4 per thread (or one 32x32
         // matrix-core block per wave for the partition function)
         g.rm = g.rn = 4;
@@ -250,6 +263,12 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
+    if (g.rm == 8 || g.rn == 8) {
+        if (dsr != DSR_TROP_I32 && dsr != DSR_TROP_F32 && dsr != DSR_MODP) return false;
+        if (g.rm != 8 || g.rn != 8 || g.ti != 7 || g.tj != 7 || g.tb != 0 || g.mfma) return false;
+        if (g.tk < 0 || g.tk > 5 || g.tk + g.lsplit > g.lk || g.li < 7 || g.lj < 7) return false;
+        return true;
+    }
     if (g.mfma) {
         if (dsr != DSR_Z_F32 && dsr != DSR_Z_BF16) return false;
         if (g.ti != 6 || g.tj != 6 || g.tb != 0) return false;
@@ -267,6 +286,7 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
 }
 
 size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
+    if (g.rm == 8) return (size_t)(1 << g.tk) * 2 * kBigPad * 4;
     return (size_t)(1 << (g.tb + g.tk)) * (pad_dim(1 << g.ti) + pad_dim(1 << g.tj)) * lds_elem_bytes(dsr);
 }
 
@@ -318,6 +338,15 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
     GemmArgs a = make_gemm_args(Ap, Bp, Cp, part, g, ap, meta, ma, mb, mc);
     size_t lds = gemm_lds_bytes(dsr, g);
     u64 blocks = 1ull << ((g.lb - g.tb) + (g.li - g.ti) + (g.lj - g.tj) + g.lsplit);
+    if (g.rm == 8) {
+        if (dsr == DSR_TROP_I32)
+            gemm_big_kernel<DSR_TROP_I32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        else if (dsr == DSR_TROP_F32)
+            gemm_big_kernel<DSR_TROP_F32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        else
+            gemm_big_kernel<DSR_MODP><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        return hipGetLastError();
+    }
     if (g.mfma) {
         if (dsr == DSR_Z_F32)
             gemm_mfma_kernel<DSR_Z_F32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);

@@ -484,6 +484,138 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
     z_epilogue<D>(g, tile, lmax);
 }
 
+// Contraction-heavy nodes of the 4-byte VALU algebras (max-plus int32/f32,
+// counts mod p): a 128 x 128 tile, 8 x 8 outputs per thread arranged as two
+// groups of 4 rows (ty*4 + r, 64 + ty*4 + r) and two groups of 4 columns
+// (tx*4 + c, 64 + tx*4 + c), so every LDS operand read is one 16-byte load and
+// every k step does 64 ops from 4 such loads.
+template <int D>
+constexpr bool big_tile_ok() {
+    return D == DSR_TROP_I32 || D == DSR_TROP_F32 || D == DSR_MODP;
+}
+
+template <typename V>
+__device__ inline void lds_load4(const V* p, V* out) {
+    const uint4 u = *(const uint4*)p;
+    out[0] = __builtin_bit_cast(V, u.x);
+    out[1] = __builtin_bit_cast(V, u.y);
+    out[2] = __builtin_bit_cast(V, u.z);
+    out[3] = __builtin_bit_cast(V, u.w);
+}
+
+template <typename V>
+__device__ inline void global_store4(V* p, const V* v) {
+    uint4 u;
+    u.x = __builtin_bit_cast(unsigned int, v[0]);
+    u.y = __builtin_bit_cast(unsigned int, v[1]);
+    u.z = __builtin_bit_cast(unsigned int, v[2]);
+    u.w = __builtin_bit_cast(unsigned int, v[3]);
+    *(uint4*)p = u;
+}
+
+// acc + a0 b0 + a1 b1 (mod p) in Montgomery form with one reduction for the two
+// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^31), so REDC(t) < 2p and
+// REDC(t) = a0 b0 R^-1 + a1 b1 R^-1 (mod p).  min(x, x - p) reduces x < 2p.
+__device__ inline unsigned int modp_mac2(unsigned int acc, unsigned int a0, unsigned int b0, unsigned int a1,
+                                         unsigned int b1, const AlgebraParams& ap) {
+    const u64 t = (u64)a0 * b0 + (u64)a1 * b1;
+    const unsigned int m = (unsigned int)t * ap.pinv;
+    unsigned int u = (unsigned int)((t + (u64)m * ap.p) >> 32);
+    u = min(u, u - ap.p);
+    const unsigned int s2 = acc + u;
+    return min(s2, s2 - ap.p);
+}
+
+template <int D>
+__device__ inline typename Alg<D>::V big_mac2(typename Alg<D>::V acc, typename Alg<D>::V a0, typename Alg<D>::V b0,
+                                              typename Alg<D>::V a1, typename Alg<D>::V b1, const AlgebraParams& ap) {
+    using A = Alg<D>;
+    if constexpr (D == DSR_MODP)
+        return modp_mac2(acc, a0, b0, a1, b1, ap);
+    else
+        return A::add(acc, A::add(A::mul(a0, b0, ap), A::mul(a1, b1, ap), ap), ap);
+}
+
+constexpr int kBigTile = 128, kBigPad = 132;  // padded LDS row keeps 16-byte alignment
+
+template <int D>
+__device__ void gemm_tile_big(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    static_assert(big_tile_ok<D>(), "4-byte VALU algebras only");
+    using A = Alg<D>;
+    using V = typename A::V;
+    const int TK = 1 << g.tk;
+    V* As = (V*)smem;  // [TK][kBigPad]
+    V* Bs = As + (size_t)TK * kBigPad;
+    const TilePos p = tile_pos(g, tile);
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    V acc[8][8];
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+#pragma unroll
+        for (int c = 0; c < 8; c++) acc[r][c] = A::zero(g.ap);
+    const int n = kBigTile * TK;
+    for (int kk = 0; kk < p.Kc; kk += TK) {
+        const i64 k0 = p.kbeg + kk;
+        for (int idx = tid; idx < n; idx += 256) {
+            int i, k;
+            i64 addr;
+            if (!g.a_t) {
+                k = idx & (TK - 1);
+                i = idx >> g.tk;
+                addr = (((p.b0 << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
+            } else {
+                i = idx & (kBigTile - 1);
+                k = idx >> 7;
+                addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
+            }
+            As[k * kBigPad + i] = A::load(g.A, addr);
+        }
+        for (int idx = tid; idx < n; idx += 256) {
+            int j, k;
+            i64 addr;
+            if (!g.b_t) {
+                j = idx & (kBigTile - 1);
+                k = idx >> 7;
+                addr = (((p.b0 << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
+            } else {
+                k = idx & (TK - 1);
+                j = idx >> g.tk;
+                addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
+            }
+            Bs[k * kBigPad + j] = A::load(g.B, addr);
+        }
+        __syncthreads();
+        // two k steps per iteration: acc (+)= (a0 b0 (+) a1 b1), which max-plus
+        // compiles to one three-input max per two products (TK >= 16)
+        for (int k = 0; k < TK; k += 2) {
+            V a0[8], b0[8], a1[8], b1[8];
+            lds_load4(As + k * kBigPad + ty * 4, a0);
+            lds_load4(As + k * kBigPad + 64 + ty * 4, a0 + 4);
+            lds_load4(Bs + k * kBigPad + tx * 4, b0);
+            lds_load4(Bs + k * kBigPad + 64 + tx * 4, b0 + 4);
+            lds_load4(As + (k + 1) * kBigPad + ty * 4, a1);
+            lds_load4(As + (k + 1) * kBigPad + 64 + ty * 4, a1 + 4);
+            lds_load4(Bs + (k + 1) * kBigPad + tx * 4, b1);
+            lds_load4(Bs + (k + 1) * kBigPad + 64 + tx * 4, b1 + 4);
+#pragma unroll
+            for (int r = 0; r < 8; r++)
+#pragma unroll
+                for (int c = 0; c < 8; c++)
+                    acc[r][c] = big_mac2<D>(acc[r][c], a0[r], b0[c], a1[r], b1[c], g.ap);
+        }
+        __syncthreads();
+    }
+    const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
+    V* dst = (V*)(g.lsplit ? g.P.p0 : g.C.p0) + (g.lsplit ? (i64)p.split * nout : 0);
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+        const int row = r < 4 ? ty * 4 + r : 64 + ty * 4 + (r - 4);
+        const i64 base = ((p.b0 << g.li) | (p.i0 + row)) << g.lj;
+        global_store4(dst + base + p.j0 + tx * 4, &acc[r][0]);
+        global_store4(dst + base + p.j0 + 64 + tx * 4, &acc[r][4]);
+    }
+}
+
 // Partition function on the matrix cores: a 64 x 64 tile (tb = 0), four
 // waves in a 2 x 2 grid, each accumulating a 32 x 32 block with
 // v_mfma_f32_32x32x2f32 (float32 inputs) or v_mfma_f32_32x32x16_bf16
