@@ -233,7 +233,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
                 N.psrc[side] = p.node_off_dag[child];
                 N.pdst[side] = side ? np.dag_b_tmp : np.dag_a_tmp;
                 N.prank[side] = rank;
-                N.ptile_bits[side] = rank < 11 ? rank : 11;
+                N.ptile_bits[side] = perm_tile_bits(rank);
             }
             L.total_ops += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk));
             L.total_bytes += (std::exp2((double)(N.g.lb + N.g.li + N.g.lk)) + std::exp2((double)(N.g.lb + N.g.lk + N.g.lj)) +

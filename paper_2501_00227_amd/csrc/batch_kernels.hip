@@ -12,6 +12,7 @@ namespace tn {
 constexpr size_t kBatchLds = 48 * 1024;
 
 size_t batch_lds_bytes() { return kBatchLds; }
+static_assert(((sizeof(PermLds) + 255) & ~(size_t)255) + kPermTile * 8 <= kBatchLds, "permute tile fits");
 
 // All tasks of one job run on the same XCC (the host assigns every job to
 // one chiplet's queue and a workgroup serves the queue of the XCC it runs

@@ -481,7 +481,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                     int rank = (int)plan.order[src_node].size();
                     Planes src = side ? Bp : Ap;
                     Planes dst = plane_at(arena, dsr, side ? np.b_tmp_off : np.a_tmp_off);
-                    int tb = rank < 11 ? rank : 11;
+                    int tb = perm_tile_bits(rank);
                     int shp[4] = {rank, 0, 0, 0};
                     for (int pl = 0; pl < 2; pl++) {
                         int pbytes = plane_bytes(dsr, pl);

@@ -68,6 +68,10 @@ struct GemmShape {
     int mfma;              // partition function on matrix cores (64 x 64 tile, 4 waves)
 };
 
+// log2 entries of one permute tile for a tensor of the given rank
+constexpr int kPermTileBits = 12;
+inline int perm_tile_bits(int rank) { return rank < kPermTileBits ? rank : kPermTileBits; }
+
 void build_perm_params(int rank, const int* src, PermParams& pp);
 
 hipError_t launch_meta_init(TensorMeta* meta, int n, hipStream_t s);

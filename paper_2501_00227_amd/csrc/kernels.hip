@@ -94,7 +94,7 @@ hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float*
 void build_perm_params(int rank, const int* src, PermParams& pp) {
     std::memset(&pp, 0, sizeof pp);
     int r = rank;
-    int u = r < 11 ? r : 11;
+    int u = perm_tile_bits(r);
     int inv[64];
     for (int q = 0; q < r; q++) inv[src[q]] = q;
     bool inU[64] = {false};
@@ -151,11 +151,13 @@ void build_perm_params(int rank, const int* src, PermParams& pp) {
     pp.ntile_bits = nt;
 }
 
+static_assert(kPermTile == 1 << kPermTileBits, "permute tile size");
+
 template <typename T>
 __global__ __launch_bounds__(256) void permute_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                       const PermParams* __restrict__ pp, i64 ntiles) {
     __shared__ PermLds tabs;
-    __shared__ T tile[kPermTile + kPermTile / 32];
+    __shared__ __align__(16) T tile[kPermTile];
     perm_load_tables(&tabs, pp);
     const int u = pp->tile_bits, nt = pp->ntile_bits;
     __syncthreads();
@@ -182,10 +184,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     gemm_tile<D, RM, RN>(g, blockIdx.x, smem);
 }
 
-template <int D>
+template <int D, int LTM, int LTN>
 __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs g) {
     extern __shared__ __align__(16) unsigned char smem[];
-    gemm_tile_big<D>(g, blockIdx.x, smem);
+    gemm_tile_big<D, LTM, LTN>(g, blockIdx.x, smem);
+}
+
+template <int D>
+static hipError_t gemm_big_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t s) {
+    const dim3 grid((unsigned)blocks), block(256);
+    if (a.ti == 7 && a.tj == 7) gemm_big_kernel<D, 7, 7><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 8 && a.tj == 6) gemm_big_kernel<D, 8, 6><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 8 && a.tj == 5) gemm_big_kernel<D, 8, 5><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 6 && a.tj == 8) gemm_big_kernel<D, 6, 8><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 5 && a.tj == 8) gemm_big_kernel<D, 5, 8><<<grid, block, lds, s>>>(a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 template <int D>
@@ -206,12 +220,21 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     const int lds_cap = 40 * 1024;
     g.mfma = 0;
     const bool four_byte_valu = dsr == DSR_TROP_I32 || dsr == DSR_TROP_F32 || dsr == DSR_MODP;
-    if (big && four_byte_valu && li >= 7 && lj >= 7 && lk >= 4) {
-        // contraction-heavy node: 128x128 tile, 8x8 per thread
+    // register-tiled family: 128 x 128 for large M and N; 256 x 64 / 256 x 32
+    // (or mirrored) when one side is large and the other 2^5 or 2^6
+    int bti = 0, btj = 0;
+    if (li >= 7 && lj >= 7 && lk >= 4) bti = btj = 7;
+    else if (li >= 8 && (lj == 5 || lj == 6) && lk >= 2) bti = 8, btj = lj;
+    else if (lj >= 8 && (li == 5 || li == 6) && lk >= 2) bti = li, btj = 8;
+    if (big && four_byte_valu && bti) {
         g.rm = g.rn = 8;
-        g.ti = g.tj = 7;
+        g.ti = bti;
+        g.tj = btj;
         g.tb = 0;
-        g.tk = lk < 5 ? lk : 5;
+        // K step: 32 for the square tile, 16 for the 256-wide ones, so that
+        // four workgroups' operand tiles fit in one CU's LDS
+        const int tkmax = (bti == 8 || btj == 8) ? 4 : 5;
+        g.tk = lk < tkmax ? lk : tkmax;
     } else if (li >= 6 && lj >= 6 && lk >= 4) {
         // contraction-heavy node: 64x64 tile, 4x4 per thread (or one 32x32
         // matrix-core block per wave for the partition function)
@@ -263,10 +286,10 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
-    if (g.rm == 8 || g.rn == 8) {
+    if (g.rm == 8 || g.rn == 8) {  // the register-tiled family; ti, tj give the tile
         if (dsr != DSR_TROP_I32 && dsr != DSR_TROP_F32 && dsr != DSR_MODP) return false;
-        if (g.rm != 8 || g.rn != 8 || g.ti != 7 || g.tj != 7 || g.tb != 0 || g.mfma) return false;
-        if (g.tk < 0 || g.tk > 5 || g.tk + g.lsplit > g.lk || g.li < 7 || g.lj < 7) return false;
+        if (g.rm != 8 || g.rn != 8 || !big_tile_shape(g.ti, g.tj) || g.tb != 0 || g.mfma) return false;
+        if (g.tk < 1 || g.tk > 5 || g.tk + g.lsplit > g.lk || g.li < g.ti || g.lj < g.tj) return false;
         return true;
     }
     if (g.mfma) {
@@ -286,7 +309,7 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
 }
 
 size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
-    if (g.rm == 8) return (size_t)(1 << g.tk) * 2 * kBigPad * 4;
+    if (g.rm == 8) return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * 4;
     return (size_t)(1 << (g.tb + g.tk)) * (pad_dim(1 << g.ti) + pad_dim(1 << g.tj)) * lds_elem_bytes(dsr);
 }
 
@@ -339,13 +362,9 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
     size_t lds = gemm_lds_bytes(dsr, g);
     u64 blocks = 1ull << ((g.lb - g.tb) + (g.li - g.ti) + (g.lj - g.tj) + g.lsplit);
     if (g.rm == 8) {
-        if (dsr == DSR_TROP_I32)
-            gemm_big_kernel<DSR_TROP_I32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
-        else if (dsr == DSR_TROP_F32)
-            gemm_big_kernel<DSR_TROP_F32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
-        else
-            gemm_big_kernel<DSR_MODP><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
-        return hipGetLastError();
+        if (dsr == DSR_TROP_I32) return gemm_big_go<DSR_TROP_I32>(a, lds, blocks, s);
+        if (dsr == DSR_TROP_F32) return gemm_big_go<DSR_TROP_F32>(a, lds, blocks, s);
+        return gemm_big_go<DSR_MODP>(a, lds, blocks, s);
     }
     if (g.mfma) {
         if (dsr == DSR_Z_F32)

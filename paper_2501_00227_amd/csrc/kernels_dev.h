@@ -262,12 +262,20 @@ __device__ inline void leaf_dispatch(const LeafDev& d, int leaf_id, const float*
 // input offset of tile entry e from its low 6 / high bits, out_lo/out_hi the
 // output offset of write slot f, e_lo/e_hi map f to e, and tin/tout place
 // the tile index bits.
+//
+// The tile's low entry bits are the input's lowest bits and its low slot bits
+// the output's lowest bits, so once u >= 4 every 16-byte group of entries is
+// 16 contiguous input bytes and every group of slots 16 contiguous output
+// bytes: both global passes move whole 16-byte vectors.  In LDS, entry e sits
+// at perm_lds_pos(e): the 16-byte group index within a 256-byte row is XORed
+// with a fold of the row number, so the gathers of the write pass spread over
+// the banks instead of stacking up on one.
 struct PermLds {
     i64 in_lo[64], in_hi[64], out_lo[64], out_hi[64];
     int e_lo[64], e_hi[64];
     signed char tin[48], tout[48];
 };
-constexpr int kPermTile = 2048;
+constexpr int kPermTile = 4096;  // entries; must equal 1 << the tile bits the host plans with
 
 __device__ inline void perm_load_tables(PermLds* s, const PermParams* pp) {
     const int tid = threadIdx.x;
@@ -285,11 +293,20 @@ __device__ inline void perm_load_tables(PermLds* s, const PermParams* pp) {
     }
 }
 
+template <typename T>
+__device__ inline int perm_lds_pos(int e) {
+    constexpr int LG = sizeof(T) == 4 ? 2 : 1;  // log2 entries per 16 bytes
+    constexpr int R = LG + 4;                   // log2 entries per 256-byte row
+    const int row = e >> R;
+    return e ^ (((row ^ (row >> 4) ^ (row >> 8)) & 15) << LG);
+}
+
 // One tile; tables must already be in LDS (and a barrier passed).  Ends with
 // a barrier so the tile buffer can be reused.
 template <typename T>
 __device__ inline void permute_tile(const T* __restrict__ in, T* __restrict__ out, const PermLds* s, T* tile, int u,
                                     int nt, i64 t) {
+    constexpr int G = 16 / sizeof(T);  // entries per 16-byte vector
     const int tid = threadIdx.x;
     const int n = 1 << u;
     i64 bin = 0, bout = 0;
@@ -298,11 +315,28 @@ __device__ inline void permute_tile(const T* __restrict__ in, T* __restrict__ ou
         bin |= bit << s->tin[k];
         bout |= bit << s->tout[k];
     }
-    for (int e = tid; e < n; e += blockDim.x) tile[e + (e >> 5)] = in[bin + s->in_lo[e & 63] + s->in_hi[e >> 6]];
-    __syncthreads();
-    for (int f = tid; f < n; f += blockDim.x) {
-        int e = s->e_lo[f & 63] | s->e_hi[f >> 6];
-        out[bout + s->out_lo[f & 63] + s->out_hi[f >> 6]] = tile[e + (e >> 5)];
+    if (u >= 4) {
+        for (int e = tid * G; e < n; e += 256 * G) {
+            const uint4 v = *(const uint4*)(in + bin + s->in_lo[e & 63] + s->in_hi[e >> 6]);
+            *(uint4*)(tile + perm_lds_pos<T>(e)) = v;
+        }
+        __syncthreads();
+        for (int f = tid * G; f < n; f += 256 * G) {
+            T v[G];
+#pragma unroll
+            for (int c = 0; c < G; c++) {
+                const int e = s->e_lo[(f + c) & 63] | s->e_hi[(f + c) >> 6];
+                v[c] = tile[perm_lds_pos<T>(e)];
+            }
+            *(uint4*)(out + bout + s->out_lo[f & 63] + s->out_hi[f >> 6]) = *(const uint4*)v;
+        }
+    } else {
+        for (int e = tid; e < n; e += blockDim.x) tile[e] = in[bin + s->in_lo[e & 63] + s->in_hi[e >> 6]];
+        __syncthreads();
+        for (int f = tid; f < n; f += blockDim.x) {
+            const int e = s->e_lo[f & 63] | s->e_hi[f >> 6];
+            out[bout + s->out_lo[f & 63] + s->out_hi[f >> 6]] = tile[e];
+        }
     }
     __syncthreads();
 }
@@ -484,11 +518,13 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
     z_epilogue<D>(g, tile, lmax);
 }
 
-// Contraction-heavy nodes of the 4-byte VALU algebras (max-plus int32/f32,
-// counts mod p): a 128 x 128 tile, 8 x 8 outputs per thread arranged as two
-// groups of 4 rows (ty*4 + r, 64 + ty*4 + r) and two groups of 4 columns
-// (tx*4 + c, 64 + tx*4 + c), so every LDS operand read is one 16-byte load and
-// every k step does 64 ops from 4 such loads.
+// Register-tiled GEMM of the 4-byte VALU algebras (max-plus int32/f32, counts
+// mod p) for nodes with large M and N (128 x 128 tile) or one large and one
+// small side (256 x 64, 256 x 32 and the mirrored 64 x 256, 32 x 256).  Each
+// of the 256 threads owns RMT x RNT outputs: rows in groups of four
+// (ty*4 + r, and TM/2 + ty*4 + r when RMT = 8), columns likewise, so every LDS
+// operand read is one 16-byte load; two k steps per iteration fold into one
+// three-input max.
 template <int D>
 constexpr bool big_tile_ok() {
     return D == DSR_TROP_I32 || D == DSR_TROP_F32 || D == DSR_MODP;
@@ -536,84 +572,109 @@ __device__ inline typename Alg<D>::V big_mac2(typename Alg<D>::V acc, typename A
         return A::add(acc, A::add(A::mul(a0, b0, ap), A::mul(a1, b1, ap), ap), ap);
 }
 
-constexpr int kBigTile = 128, kBigPad = 132;  // padded LDS row keeps 16-byte alignment
+template <int LTM, int LTN>
+struct BigTile {
+    static constexpr int TM = 1 << LTM, TN = 1 << LTN;
+    static constexpr int RMT = TM >= 64 ? 8 : 4, RNT = TN >= 64 ? 8 : 4;  // outputs per thread
+    static constexpr int CT = TN / RNT;                                   // column threads
+    static constexpr int TMP = TM + 4, TNP = TN + 4;                      // padded LDS rows, 16-byte aligned
+    static_assert((TM / RMT) * CT == 256, "256 threads per tile");
+};
 
-template <int D>
+// the tile shapes of the family, (log2 TM, log2 TN)
+__host__ __device__ constexpr bool big_tile_shape(int ti, int tj) {
+    return (ti == 7 && tj == 7) || (ti == 8 && (tj == 5 || tj == 6)) || (tj == 8 && (ti == 5 || ti == 6));
+}
+
+template <int D, int LTM, int LTN>
 __device__ void gemm_tile_big(const GemmArgs& g, u64 tile, unsigned char* smem) {
     static_assert(big_tile_ok<D>(), "4-byte VALU algebras only");
     using A = Alg<D>;
     using V = typename A::V;
+    using T = BigTile<LTM, LTN>;
+    constexpr int RMT = T::RMT, RNT = T::RNT, TM = T::TM, TN = T::TN, TMP = T::TMP, TNP = T::TNP;
     const int TK = 1 << g.tk;
-    V* As = (V*)smem;  // [TK][kBigPad]
-    V* Bs = As + (size_t)TK * kBigPad;
+    V* As = (V*)smem;  // [TK][TMP]
+    V* Bs = As + (size_t)TK * TMP;  // [TK][TNP]
     const TilePos p = tile_pos(g, tile);
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    V acc[8][8];
+    const int tid = threadIdx.x, tx = tid % T::CT, ty = tid / T::CT;
+    V acc[RMT][RNT];
 #pragma unroll
-    for (int r = 0; r < 8; r++)
+    for (int r = 0; r < RMT; r++)
 #pragma unroll
-        for (int c = 0; c < 8; c++) acc[r][c] = A::zero(g.ap);
-    const int n = kBigTile * TK;
+        for (int c = 0; c < RNT; c++) acc[r][c] = A::zero(g.ap);
+    const int na = TM * TK, nb = TN * TK;
     for (int kk = 0; kk < p.Kc; kk += TK) {
         const i64 k0 = p.kbeg + kk;
-        for (int idx = tid; idx < n; idx += 256) {
+        for (int idx = tid; idx < na; idx += 256) {
             int i, k;
             i64 addr;
-            if (!g.a_t) {
+            if (!g.a_t) {  // memory order (b, i, k)
                 k = idx & (TK - 1);
                 i = idx >> g.tk;
                 addr = (((p.b0 << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
-            } else {
-                i = idx & (kBigTile - 1);
-                k = idx >> 7;
+            } else {  // (b, k, i)
+                i = idx & (TM - 1);
+                k = idx >> LTM;
                 addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
             }
-            As[k * kBigPad + i] = A::load(g.A, addr);
+            As[k * TMP + i] = A::load(g.A, addr);
         }
-        for (int idx = tid; idx < n; idx += 256) {
+        for (int idx = tid; idx < nb; idx += 256) {
             int j, k;
             i64 addr;
-            if (!g.b_t) {
-                j = idx & (kBigTile - 1);
-                k = idx >> 7;
+            if (!g.b_t) {  // (b, k, j)
+                j = idx & (TN - 1);
+                k = idx >> LTN;
                 addr = (((p.b0 << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
-            } else {
+            } else {  // (b, j, k)
                 k = idx & (TK - 1);
                 j = idx >> g.tk;
                 addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
             }
-            Bs[k * kBigPad + j] = A::load(g.B, addr);
+            Bs[k * TNP + j] = A::load(g.B, addr);
         }
         __syncthreads();
-        // two k steps per iteration: acc (+)= (a0 b0 (+) a1 b1), which max-plus
-        // compiles to one three-input max per two products (TK >= 16)
-        for (int k = 0; k < TK; k += 2) {
-            V a0[8], b0[8], a1[8], b1[8];
-            lds_load4(As + k * kBigPad + ty * 4, a0);
-            lds_load4(As + k * kBigPad + 64 + ty * 4, a0 + 4);
-            lds_load4(Bs + k * kBigPad + tx * 4, b0);
-            lds_load4(Bs + k * kBigPad + 64 + tx * 4, b0 + 4);
-            lds_load4(As + (k + 1) * kBigPad + ty * 4, a1);
-            lds_load4(As + (k + 1) * kBigPad + 64 + ty * 4, a1 + 4);
-            lds_load4(Bs + (k + 1) * kBigPad + tx * 4, b1);
-            lds_load4(Bs + (k + 1) * kBigPad + 64 + tx * 4, b1 + 4);
+        for (int k = 0; k < TK; k += 2) {  // TK >= 2
+            V a0[RMT], b0[RNT], a1[RMT], b1[RNT];
 #pragma unroll
-            for (int r = 0; r < 8; r++)
+            for (int h = 0; h < RMT / 4; h++) {
+                lds_load4(As + k * TMP + h * (TM / 2) + ty * 4, a0 + 4 * h);
+                lds_load4(As + (k + 1) * TMP + h * (TM / 2) + ty * 4, a1 + 4 * h);
+            }
 #pragma unroll
-                for (int c = 0; c < 8; c++)
-                    acc[r][c] = big_mac2<D>(acc[r][c], a0[r], b0[c], a1[r], b1[c], g.ap);
+            for (int h = 0; h < RNT / 4; h++) {
+                lds_load4(Bs + k * TNP + h * (TN / 2) + tx * 4, b0 + 4 * h);
+                lds_load4(Bs + (k + 1) * TNP + h * (TN / 2) + tx * 4, b1 + 4 * h);
+            }
+#pragma unroll
+            for (int r = 0; r < RMT; r++)
+#pragma unroll
+                for (int c = 0; c < RNT; c++) acc[r][c] = big_mac2<D>(acc[r][c], a0[r], b0[c], a1[r], b1[c], g.ap);
         }
         __syncthreads();
     }
     const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
     V* dst = (V*)(g.lsplit ? g.P.p0 : g.C.p0) + (g.lsplit ? (i64)p.split * nout : 0);
 #pragma unroll
-    for (int r = 0; r < 8; r++) {
-        const int row = r < 4 ? ty * 4 + r : 64 + ty * 4 + (r - 4);
+    for (int r = 0; r < RMT; r++) {
+        const int row = (r / 4) * (TM / 2) + ty * 4 + (r & 3);
         const i64 base = ((p.b0 << g.li) | (p.i0 + row)) << g.lj;
-        global_store4(dst + base + p.j0 + tx * 4, &acc[r][0]);
-        global_store4(dst + base + p.j0 + 64 + tx * 4, &acc[r][4]);
+#pragma unroll
+        for (int h = 0; h < RNT / 4; h++) global_store4(dst + base + p.j0 + h * (TN / 2) + tx * 4, &acc[r][4 * h]);
     }
+}
+
+// Launch the family member for (ti, tj); false if (ti, tj) is not one.
+template <int D>
+__device__ inline bool gemm_tile_big_any(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    if (g.ti == 7 && g.tj == 7) gemm_tile_big<D, 7, 7>(g, tile, smem);
+    else if (g.ti == 8 && g.tj == 6) gemm_tile_big<D, 8, 6>(g, tile, smem);
+    else if (g.ti == 8 && g.tj == 5) gemm_tile_big<D, 8, 5>(g, tile, smem);
+    else if (g.ti == 6 && g.tj == 8) gemm_tile_big<D, 6, 8>(g, tile, smem);
+    else if (g.ti == 5 && g.tj == 8) gemm_tile_big<D, 5, 8>(g, tile, smem);
+    else return false;
+    return true;
 }
 
 // Partition function on the matrix cores: a 64 x 64 tile (tb = 0), four

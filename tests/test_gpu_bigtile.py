@@ -1,11 +1,13 @@
 """GPU parity of the 128 x 128 register-tiled VALU GEMM.
 
-The per-node executor sends nodes with M, N >= 2^7 and K >= 2^4 of the
-4-byte VALU algebras (max-plus int32 and float32, counts mod p) to the
-big-tile kernel.  Square lattices of side 14 and 16 and finely sliced plans
-of the 240-vertex 3-regular network have such nodes (with and without batch
-indices, with split K, and with both operand orders); each case asserts that
-the big-tile kernel actually ran and compares the result with the oracle.
+The per-node executor sends nodes of the 4-byte VALU algebras (max-plus
+int32 and float32, counts mod p) with M, N >= 2^7 and K >= 2^4 to a 128 x 128
+tile, and nodes with one side >= 2^8 and the other 2^5 or 2^6 to the 256 x 32,
+256 x 64 tiles (or their mirror images).  Square lattices of side 14 and 16,
+a King's subgraph of side 15 and a finely sliced plan of the 240-vertex
+3-regular network have such nodes (with and without batch indices, with
+split K); each case asserts which tiles ran and compares the result with the
+oracle.
 """
 import numpy as np
 import pytest
@@ -35,30 +37,58 @@ def _solve_profiled(ctx, net, plan, sr, **kw):
     return r, recs
 
 
-def _plan(net, method):
+def _plan(net, method, seed=0):
     if method == "greedy":
-        return tn.Plan.create(net, seed=0)
-    return tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=0)
+        return tn.Plan.create(net, seed=seed)
+    return tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=seed)
 
 
 def _nbig(recs):
     return sum(1 for x in recs if x["kind"] == "gemm_big")
 
 
-@pytest.mark.parametrize("side,method", [(14, "greedy"), (14, "treesa"), (16, "greedy")])
-def test_lattice_big_tiles_vs_oracle(ctx, side, method):
-    gu = gg.square_lattice(side)
-    gw = gu.with_weights(gg.dyadic_weights(gu.nv, side))
+def _tile(shape):
+    """(log2 TM, log2 TN) of the register-tiled kernel for a GEMM shape (b, i, j, k)."""
+    _, i, j, k = shape
+    if i >= 7 and j >= 7 and k >= 4:
+        return (7, 7)
+    if i >= 8 and j in (5, 6):
+        return (8, j)
+    if j >= 8 and i in (5, 6):
+        return (i, 8)
+    return None
+
+
+# (graph, planner, planner seed, tiles the plan must exercise)
+CASES = [
+    ("lattice14", "greedy", 0, {(7, 7), (8, 6), (8, 5)}),
+    ("lattice14", "treesa", 0, {(7, 7)}),
+    ("lattice16", "greedy", 0, {(7, 7), (6, 8)}),
+    ("ksg15", "treesa", 2, {(7, 7), (8, 6), (8, 5), (5, 8)}),
+]
+
+
+def _graph(name):
+    if name.startswith("lattice"):
+        return gg.square_lattice(int(name[7:]))
+    return gg.kings_subgraph(15, 0.8, 1)
+
+
+@pytest.mark.parametrize("name,method,seed,tiles", CASES)
+def test_big_tiles_vs_oracle(ctx, name, method, seed, tiles):
+    gu = _graph(name)
+    gw = gu.with_weights(gg.dyadic_weights(gu.nv, 7))
     net_u, net_w = tn.Net.from_graph(gu), tn.Net.from_graph(gw)
-    plan_u, plan_w = _plan(net_u, method), _plan(net_w, method)
-    print(f"lattice {side} {method} complexity {plan_u.complexity()}", flush=True)
+    plan_u, plan_w = _plan(net_u, method, seed), _plan(net_w, method, seed)
+    print(f"{name} {method} complexity {plan_u.complexity()}", flush=True)
     cases = [("tropical_f32", net_w, plan_w, "size", oracle.eliminate(gw, "tropical")["size"]),
              ("tropical_i32", net_u, plan_u, "size", oracle.eliminate(gu, "tropical")["size"]),
              ("count_exact", net_u, plan_u, "count", oracle.eliminate(gu, "count")["count"])]
     for sr, net, plan, key, want in cases:
         r, recs = _solve_profiled(ctx, net, plan, sr)
-        print(f"  {sr}: {r[key]} vs {want}, big-tile launches {_nbig(recs)}", flush=True)
-        assert _nbig(recs) > 0  # count_exact: the residue lanes mod p
+        ran = {_tile(x["shape"]) for x in recs if x["kind"] == "gemm_big"}
+        print(f"  {sr}: {r[key]} vs {want}, big-tile launches {_nbig(recs)}, tiles {sorted(ran)}", flush=True)
+        assert tiles <= ran  # count_exact: the residue lanes mod p
         # dyadic weights: every partial sum is exact in float32
         assert r[key] == want
 
