@@ -26,6 +26,7 @@ using namespace tn;
     }
 
 static std::atomic<uint64_t> g_plan_uid{1};
+static std::atomic<uint64_t> g_net_uid{1};
 
 extern "C" {
 
@@ -68,6 +69,7 @@ void tn_ctx_destroy(tn_ctx* c) {
     try {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
+        batch_cache_drop(c);
         for (auto& kv : c->progs) dev_free(c, kv.second.buf, kv.second.bytes);
         (void)hipStreamSynchronize(c->stream);
         for (auto& pr : c->pending) {
@@ -141,6 +143,7 @@ tn_status tn_net_independent_set(int32_t nv, int32_t ne, const int32_t* edges, c
         delete n;
         return st;
     }
+    n->net.uid = g_net_uid.fetch_add(1);
     *out = n;
     return TN_OK;
     TN_GUARD_END
@@ -297,7 +300,7 @@ tn_status tn_plan_peak_bytes(const tn_plan* p, tn_semiring sr, uint64_t* bytes) 
     const bool dag = use_persistent(pl);  // the dependency-graph executor keeps every partial separate
     uint64_t part = 0;
     for (auto& np : pl.prog) {
-        GemmShape g = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t, dag ? 0 : 1);
+        GemmShape g = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
         if (!g.lsplit) continue;
         uint64_t n = 1ull << (g.lsplit + np.lb + np.li + np.lj);
         part = dag ? part + ((n + 63) & ~63ull) : std::max<uint64_t>(part, n);

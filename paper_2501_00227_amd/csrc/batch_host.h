@@ -50,7 +50,9 @@ struct BatchLaunch {
     int nq = 1;
     std::vector<int> qbegin, qcount;
     size_t o_hticket = 0;
-    std::vector<void*> accs;  // device accumulator of every job
+    void* d_accs = nullptr;   // the jobs' root accumulators, 16 bytes each
+    size_t o_reset = 0, reset_bytes = 0;  // counters and tickets within the tables
+    bool uploaded = false;    // tables and weights are on the device
     double total_ops = 0, total_bytes = 0;  // algorithmic work of the launch
     unsigned long long* d_trace = nullptr;  // per-task timestamps (profiling)
     std::vector<BTask> host_tasks;          // kept for the trace
@@ -68,6 +70,8 @@ tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out);
 void batch_release(BatchLaunch& L);
 void collect_trace(tn_ctx* ctx, BatchLaunch& L);
 tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out);
+// Release the launch a synchronous batch keeps for an identical next call.
+void batch_cache_drop(tn_ctx* ctx);
 // Route a single unsliced small tree through the persistent launch.
 bool use_persistent(const Plan& p);
 

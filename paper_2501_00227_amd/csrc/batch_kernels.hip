@@ -76,6 +76,12 @@ __device__ void run_gemm(const BJob& j, const BNode& nd, i64 tile, unsigned char
             return;
         }
     }
+    if constexpr (big_tile_ok<D>()) {
+        if (rm == 8) {
+            gemm_tile_big_any<D>(g, (u64)tile, smem);
+            return;
+        }
+    }
     if (rm == 2 && rn == 2)
         gemm_tile<D, 2, 2>(g, (u64)tile, smem);
     else if (rm == 4 && rn == 4)
@@ -212,7 +218,9 @@ __device__ inline unsigned int hw_xcc_id() {
     return x & 0xfu;
 }
 
-__global__ __launch_bounds__(256) void batch_kernel(const BTask* __restrict__ tasks, const int* __restrict__ qbegin,
+// At least two waves per SIMD (registers capped at 256 per lane): the grid of
+// two workgroups per CU is then resident at once.
+__global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__ tasks, const int* __restrict__ qbegin,
                                                     const int* __restrict__ qcount, int nq,
                                                     const BJob* __restrict__ jobs, const BNode* __restrict__ nodes,
                                                     const int* __restrict__ subtree, int* counters, int* tickets,

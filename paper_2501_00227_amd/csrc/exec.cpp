@@ -166,8 +166,8 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     return TN_OK;
 }
 
-const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr, bool big) {
-    const int key = launch_key(dsr, big);
+const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr) {
+    const int key = dsr;
     auto it = dp.launches.find(key);
     if (it != dp.launches.end()) return it->second;
     std::vector<NodeLaunch> v(p.prog.size());
@@ -175,7 +175,7 @@ const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int 
     std::vector<int64_t> part_off(p.prog.size(), 0);
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
-        v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t, big ? 1 : 0);
+        v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
         if (v[t].shape.lsplit > 0)
             v[t].part_entries = (int64_t)1 << (v[t].shape.lsplit + np.lb + np.li + np.lj);
         part = std::max(part, v[t].part_entries);
@@ -406,8 +406,8 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     int64_t Pe = 0;
     for (auto& ps : passes) {
         if (dp) {
-            node_launches(*dp, plan, ps.dsr, true);
-            Pe = std::max(Pe, dp->part_entries[launch_key(ps.dsr, true)]);
+            node_launches(*dp, plan, ps.dsr);
+            Pe = std::max(Pe, dp->part_entries[ps.dsr]);
         }
     }
     int pb0 = 0, pb1 = 0;
@@ -460,7 +460,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
             chk(launch_set_one(dsr, acc, ap, s));
             continue;
         }
-        const auto& launches = node_launches(*dp, plan, dsr, true);
+        const auto& launches = node_launches(*dp, plan, dsr);
         for (int64_t sl = sb; sl < se && herr == hipSuccess; sl++) {
             if (is_z) chk(launch_meta_init(meta, nn, s));
             {

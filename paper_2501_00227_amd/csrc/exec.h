@@ -50,6 +50,10 @@ struct PendingRec {
 
 }  // namespace tn
 
+namespace tn {
+struct BatchLaunch;
+}
+
 struct tn_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -77,6 +81,9 @@ struct tn_ctx {
     std::vector<PinnedBuf> pinned_pool;
     std::mutex pinned_mu;
     std::vector<tn_task_record> task_trace;  // persistent-launch timelines (profiling)
+    // the last synchronous persistent launch, kept for an identical next call
+    tn::BatchLaunch* batch_cache = nullptr;
+    std::vector<uint64_t> batch_cache_key;
 };
 
 namespace tn {
@@ -87,11 +94,8 @@ void* dev_alloc(tn_ctx* ctx, size_t bytes);
 void dev_free(tn_ctx* ctx, void* p, size_t bytes);
 tn_status ensure_pinned(tn_ctx* ctx, size_t bytes);
 tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out);
-// Tile shapes of every node for one device algebra; big selects the shapes of
-// the per-node stream executor (1) or of the persistent executor (0).  The
-// per-algebra maps of DevProgram are keyed by launch_key(dsr, big).
-inline int launch_key(int dsr, bool big) { return dsr + (big ? 16 : 0); }
-const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr, bool big);
+// Tile shapes of every node for one device algebra (cached in dp).
+const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr);
 
 // Profiling bracket around one launch (no-op unless profiling is on).
 struct ProfScope {

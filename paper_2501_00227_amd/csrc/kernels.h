@@ -93,10 +93,7 @@ hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream
 int accumulator_bytes(int dsr);
 
 // Choose tile shape for a GEMM node (heuristic; the autotuner may override).
-// big != 0 admits the 128 x 128 register-tiled kernel of the 4-byte VALU
-// algebras; the persistent executor passes 0 (its one kernel would otherwise
-// need that kernel's register budget for every task).
-GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, int big = 1);
+GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);
 bool gemm_shape_valid(int dsr, const GemmShape& g);
 
 }  // namespace tn

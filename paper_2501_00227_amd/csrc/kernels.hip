@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
     gemm_tile_mfma<D>(g, blockIdx.x, smem);
 }
 
-GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, int big) {
+GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
     GemmShape g{};
     g.lb = lb;
     g.li = li;
@@ -226,7 +226,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     if (li >= 7 && lj >= 7 && lk >= 4) bti = btj = 7;
     else if (li >= 8 && (lj == 5 || lj == 6) && lk >= 2) bti = 8, btj = lj;
     else if (lj >= 8 && (li == 5 || li == 6) && lk >= 2) bti = li, btj = 8;
-    if (big && four_byte_valu && bti) {
+    if (four_byte_valu && bti) {
         g.rm = g.rn = 8;
         g.ti = bti;
         g.tj = btj;

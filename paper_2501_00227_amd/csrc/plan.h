@@ -18,6 +18,7 @@ struct Net {
     std::vector<float> w;                   // empty = unit weights
     bool integer_weights = true;            // every weight is an exact integer
     uint64_t fingerprint = 0;
+    uint64_t uid = 0;  // unique per created network (cache keys)
 };
 
 tn_status make_net(int nv, int ne, const int32_t* edges, const float* weights, Net& out);

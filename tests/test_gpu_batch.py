@@ -42,6 +42,51 @@ def _key(r):
     return r
 
 
+def _oracle_check(g, sr, b, m):
+    ref = oracle.brute_force(g, [b])
+    if sr in ("tropical_i32", "tropical_f32"):
+        assert m["size"] == ref["size_max"]
+    elif sr == "counting_tropical":
+        assert (m["size"], m["count_mod_2_64"]) == (ref["size_max"], ref["count_max"])
+    elif sr == "count_exact":
+        assert m["count"] == ref["count_all"]
+    else:
+        assert abs(m["z"] - ref["z"][0]) <= 1e-5 * ref["z"][0]
+
+
+def test_repeated_batch_reuses_launch(ctx):
+    """An identical batch again reuses the previous launch's task table; a
+    different batch in between, a single solve and a network with the same
+    structure but new weights must all still give their own results."""
+    a = _jobs(10, seed=3, n_lo=12, n_hi=22)
+    b = _jobs(6, seed=4, n_lo=12, n_hi=22)
+
+    def run(jobs):
+        return [_key(r) for r in ctx.solve_batch([j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs],
+                                                 [j[4] for j in jobs])]
+
+    first = run(a)
+    for (g, net, plan, sr, beta), m in zip(a, first):
+        _oracle_check(g, sr, beta, m)
+    assert run(a) == first and run(a) == first
+    rb = run(b)
+    for (g, net, plan, sr, beta), m in zip(b, rb):
+        _oracle_check(g, sr, beta, m)
+    assert run(a) == first
+    g0, net0, plan0, sr0, beta0 = a[0]
+    ctx.solve(net0, plan0, sr0, beta=beta0, executor="persistent")
+    assert run(a) == first
+    # same structure, other weights: a new network, a new result
+    gw = g0.with_weights(gg.integer_weights(g0.nv, 5, 1, 4))
+    netw = tn.Net.from_graph(gw)
+    planw = tn.Plan.create(netw, seed=0)
+    jobs_w = [(gw, netw, planw, "tropical_i32", 0.0)] + list(a[1:])
+    rw = run(jobs_w)
+    assert rw[0]["size"] == oracle.brute_force(gw)["size_max"]
+    assert rw[1:] == first[1:]
+    assert run(a) == first
+
+
 def test_batch_matches_alone_and_oracle(ctx):
     jobs = _jobs(24)
     alone = [ctx.solve(net, plan, sr, beta=b, executor="persistent") for g, net, plan, sr, b in jobs]
