@@ -82,6 +82,12 @@ __device__ void run_gemm(const BJob& j, const BNode& nd, i64 tile, unsigned char
             return;
         }
     }
+    if constexpr (D == DSR_CTROP) {
+        if (rm == 8) {
+            gemm_tile_ct_big_any<D>(g, (u64)tile, smem);
+            return;
+        }
+    }
     if (rm == 2 && rn == 2)
         gemm_tile<D, 2, 2>(g, (u64)tile, smem);
     else if (rm == 4 && rn == 4)

@@ -190,6 +190,22 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs g) {
     gemm_tile_big<D, LTM, LTN>(g, blockIdx.x, smem);
 }
 
+template <int LTM, int LTN>
+__global__ __launch_bounds__(256) void gemm_ct_big_kernel(GemmArgs g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gemm_tile_ct_big<LTM, LTN>(g, blockIdx.x, smem);
+}
+
+static hipError_t gemm_ct_big_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t s) {
+    const dim3 grid((unsigned)blocks), block(256);
+    if (a.ti == 7 && a.tj == 6) gemm_ct_big_kernel<7, 6><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 6 && a.tj == 7) gemm_ct_big_kernel<6, 7><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 8 && a.tj == 5) gemm_ct_big_kernel<8, 5><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 5 && a.tj == 8) gemm_ct_big_kernel<5, 8><<<grid, block, lds, s>>>(a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int D>
 static hipError_t gemm_big_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t s) {
     const dim3 grid((unsigned)blocks), block(256);
@@ -226,7 +242,20 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     if (li >= 7 && lj >= 7 && lk >= 4) bti = btj = 7;
     else if (li >= 8 && (lj == 5 || lj == 6) && lk >= 2) bti = 8, btj = lj;
     else if (lj >= 8 && (li == 5 || li == 6) && lk >= 2) bti = li, btj = 8;
-    if (four_byte_valu && bti) {
+    // counting tropical: 128 x 64 / 64 x 128, or 256 x 32 / 32 x 256
+    int cti = 0, ctj = 0;
+    if (li >= 7 && lj >= 6 && lk >= 2) cti = 7, ctj = 6;
+    else if (li >= 6 && lj >= 7 && lk >= 2) cti = 6, ctj = 7;
+    else if (li >= 8 && lj == 5 && lk >= 2) cti = 8, ctj = 5;
+    else if (lj >= 8 && li == 5 && lk >= 2) cti = 5, ctj = 8;
+    if (dsr == DSR_CTROP && cti) {
+        g.rm = g.rn = 8;
+        g.ti = cti;
+        g.tj = ctj;
+        g.tb = 0;
+        const int tkmax = (cti == 8 || ctj == 8) ? 3 : 4;  // operand tiles <= 40 KB of LDS
+        g.tk = lk < tkmax ? lk : tkmax;
+    } else if (four_byte_valu && bti) {
         g.rm = g.rn = 8;
         g.ti = bti;
         g.tj = btj;
@@ -286,6 +315,11 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
+    if ((g.rm == 8 || g.rn == 8) && dsr == DSR_CTROP) {  // counting-tropical register tiles
+        if (g.rm != 8 || g.rn != 8 || !ct_tile_shape(g.ti, g.tj) || g.tb != 0 || g.mfma) return false;
+        if (g.tk < 0 || g.tk > 4 || g.tk + g.lsplit > g.lk || g.li < g.ti || g.lj < g.tj) return false;
+        return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * 12 <= 40 * 1024;
+    }
     if (g.rm == 8 || g.rn == 8) {  // the register-tiled family; ti, tj give the tile
         if (dsr != DSR_TROP_I32 && dsr != DSR_TROP_F32 && dsr != DSR_MODP) return false;
         if (g.rm != 8 || g.rn != 8 || !big_tile_shape(g.ti, g.tj) || g.tb != 0 || g.mfma) return false;
@@ -309,7 +343,8 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
 }
 
 size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
-    if (g.rm == 8) return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * 4;
+    if (g.rm == 8)
+        return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * (dsr == DSR_CTROP ? 12 : 4);
     return (size_t)(1 << (g.tb + g.tk)) * (pad_dim(1 << g.ti) + pad_dim(1 << g.tj)) * lds_elem_bytes(dsr);
 }
 
@@ -362,6 +397,7 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
     size_t lds = gemm_lds_bytes(dsr, g);
     u64 blocks = 1ull << ((g.lb - g.tb) + (g.li - g.ti) + (g.lj - g.tj) + g.lsplit);
     if (g.rm == 8) {
+        if (dsr == DSR_CTROP) return gemm_ct_big_go(a, lds, blocks, s);
         if (dsr == DSR_TROP_I32) return gemm_big_go<DSR_TROP_I32>(a, lds, blocks, s);
         if (dsr == DSR_TROP_F32) return gemm_big_go<DSR_TROP_F32>(a, lds, blocks, s);
         return gemm_big_go<DSR_MODP>(a, lds, blocks, s);

@@ -135,6 +135,19 @@ struct Alg<DSR_Z_BF16> : Alg<DSR_Z_F32> {
     __device__ static V prescale(V v, float s) { return round_bf16(v * s); }
 };
 
+// acc + a0 b0 + a1 b1 (mod p) in Montgomery form with one reduction for the two
+// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^31), so REDC(t) < 2p and
+// REDC(t) = a0 b0 R^-1 + a1 b1 R^-1 (mod p).  min(x, x - p) reduces x < 2p.
+__device__ inline unsigned int modp_mac2(unsigned int acc, unsigned int a0, unsigned int b0, unsigned int a1,
+                                         unsigned int b1, const AlgebraParams& ap) {
+    const u64 t = (u64)a0 * b0 + (u64)a1 * b1;
+    const unsigned int m = (unsigned int)t * ap.pinv;
+    unsigned int u = (unsigned int)((t + (u64)m * ap.p) >> 32);
+    u = min(u, u - ap.p);
+    const unsigned int s2 = acc + u;
+    return min(s2, s2 - ap.p);
+}
+
 template <int D>
 constexpr bool is_z() {
     return D == DSR_Z_F32 || D == DSR_Z_BF16;
@@ -486,7 +499,27 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
         if (tid < active) {
             const V* ap_ = As + (size_t)z * TK * TMp + y;
             const V* bp_ = Bs + (size_t)z * TK * TNp + x;
-            for (int k = 0; k < TK; k++) {
+            int k = 0;
+            if constexpr (D == DSR_MODP) {  // two k steps per Montgomery reduction
+                for (; k + 1 < TK; k += 2) {
+                    V av0[RM], bv0[RN], av1[RM], bv1[RN];
+#pragma unroll
+                    for (int r = 0; r < RM; r++) {
+                        av0[r] = ap_[k * TMp + r * TMt];
+                        av1[r] = ap_[(k + 1) * TMp + r * TMt];
+                    }
+#pragma unroll
+                    for (int c = 0; c < RN; c++) {
+                        bv0[c] = bp_[k * TNp + c * TNt];
+                        bv1[c] = bp_[(k + 1) * TNp + c * TNt];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RM; r++)
+#pragma unroll
+                        for (int c = 0; c < RN; c++) acc[r][c] = modp_mac2(acc[r][c], av0[r], bv0[c], av1[r], bv1[c], g.ap);
+                }
+            }
+            for (; k < TK; k++) {
                 V av[RM], bv[RN];
 #pragma unroll
                 for (int r = 0; r < RM; r++) av[r] = ap_[k * TMp + r * TMt];
@@ -547,19 +580,6 @@ __device__ inline void global_store4(V* p, const V* v) {
     u.z = __builtin_bit_cast(unsigned int, v[2]);
     u.w = __builtin_bit_cast(unsigned int, v[3]);
     *(uint4*)p = u;
-}
-
-// acc + a0 b0 + a1 b1 (mod p) in Montgomery form with one reduction for the two
-// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^31), so REDC(t) < 2p and
-// REDC(t) = a0 b0 R^-1 + a1 b1 R^-1 (mod p).  min(x, x - p) reduces x < 2p.
-__device__ inline unsigned int modp_mac2(unsigned int acc, unsigned int a0, unsigned int b0, unsigned int a1,
-                                         unsigned int b1, const AlgebraParams& ap) {
-    const u64 t = (u64)a0 * b0 + (u64)a1 * b1;
-    const unsigned int m = (unsigned int)t * ap.pinv;
-    unsigned int u = (unsigned int)((t + (u64)m * ap.p) >> 32);
-    u = min(u, u - ap.p);
-    const unsigned int s2 = acc + u;
-    return min(s2, s2 - ap.p);
 }
 
 template <int D>
@@ -673,6 +693,148 @@ __device__ inline bool gemm_tile_big_any(const GemmArgs& g, u64 tile, unsigned c
     else if (g.ti == 8 && g.tj == 5) gemm_tile_big<D, 8, 5>(g, tile, smem);
     else if (g.ti == 6 && g.tj == 8) gemm_tile_big<D, 6, 8>(g, tile, smem);
     else if (g.ti == 5 && g.tj == 8) gemm_tile_big<D, 5, 8>(g, tile, smem);
+    else return false;
+    return true;
+}
+
+// Counting tropical, register-tiled: (size, count) planes staged separately
+// in LDS (counts first for 8-byte alignment), each thread owning 8 x 4 (or
+// 4 x 8) outputs in groups of four rows / columns as above.  Tiles 128 x 64,
+// 64 x 128, 256 x 32, 32 x 256.
+__host__ __device__ constexpr bool ct_tile_shape(int ti, int tj) {
+    return (ti == 7 && tj == 6) || (ti == 6 && tj == 7) || (ti == 8 && tj == 5) || (ti == 5 && tj == 8);
+}
+
+// acc (+)= (an + bn, ac * bc): the larger size wins, equal sizes add counts
+__device__ inline void ct_mac(int& n, u64& c, int an, u64 ac, int bn, u64 bc) {
+    const int s = __builtin_elementwise_add_sat(an, bn);
+    const u64 p = ac * bc;
+    const u64 keep = n >= s ? c : 0ull;
+    const u64 add = s >= n ? p : 0ull;
+    c = keep + add;
+    n = max(n, s);
+}
+
+template <int LTM, int LTN>
+__device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    constexpr int TM = 1 << LTM, TN = 1 << LTN;
+    constexpr int RMT = LTM >= LTN ? 8 : 4, RNT = LTM >= LTN ? 4 : 8;
+    constexpr int CTH = TN / RNT, TMP = TM + 4, TNP = TN + 4;
+    static_assert((TM / RMT) * CTH == 256, "256 threads per tile");
+    const int TK = 1 << g.tk;
+    u64* Ac = (u64*)smem;                    // [TK][TMP]
+    u64* Bc = Ac + (size_t)TK * TMP;         // [TK][TNP]
+    int* An = (int*)(Bc + (size_t)TK * TNP);  // [TK][TMP]
+    int* Bn = An + (size_t)TK * TMP;          // [TK][TNP]
+    const TilePos p = tile_pos(g, tile);
+    const int tid = threadIdx.x, tx = tid % CTH, ty = tid / CTH;
+    int accn[RMT][RNT];
+    u64 accc[RMT][RNT];
+#pragma unroll
+    for (int r = 0; r < RMT; r++)
+#pragma unroll
+        for (int c = 0; c < RNT; c++) {
+            accn[r][c] = INT_MIN;
+            accc[r][c] = 0ull;
+        }
+    const int na = TM * TK, nb = TN * TK;
+    for (int kk = 0; kk < p.Kc; kk += TK) {
+        const i64 k0 = p.kbeg + kk;
+        for (int idx = tid; idx < na; idx += 256) {
+            int i, k;
+            i64 addr;
+            if (!g.a_t) {
+                k = idx & (TK - 1);
+                i = idx >> g.tk;
+                addr = (((p.b0 << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
+            } else {
+                i = idx & (TM - 1);
+                k = idx >> LTM;
+                addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
+            }
+            An[k * TMP + i] = ((const int*)g.A.p0)[addr];
+            Ac[k * TMP + i] = ((const u64*)g.A.p1)[addr];
+        }
+        for (int idx = tid; idx < nb; idx += 256) {
+            int j, k;
+            i64 addr;
+            if (!g.b_t) {
+                j = idx & (TN - 1);
+                k = idx >> LTN;
+                addr = (((p.b0 << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
+            } else {
+                k = idx & (TK - 1);
+                j = idx >> g.tk;
+                addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
+            }
+            Bn[k * TNP + j] = ((const int*)g.B.p0)[addr];
+            Bc[k * TNP + j] = ((const u64*)g.B.p1)[addr];
+        }
+        __syncthreads();
+        for (int k = 0; k < TK; k++) {
+            int an[RMT], bn[RNT];
+            u64 ac[RMT], bc[RNT];
+#pragma unroll
+            for (int h = 0; h < RMT / 4; h++) {
+                lds_load4(An + k * TMP + h * (TM / 2) + ty * 4, an + 4 * h);
+                const uint4 u0 = *(const uint4*)(Ac + k * TMP + h * (TM / 2) + ty * 4);
+                const uint4 u1 = *(const uint4*)(Ac + k * TMP + h * (TM / 2) + ty * 4 + 2);
+                ac[4 * h + 0] = ((u64)u0.y << 32) | u0.x;
+                ac[4 * h + 1] = ((u64)u0.w << 32) | u0.z;
+                ac[4 * h + 2] = ((u64)u1.y << 32) | u1.x;
+                ac[4 * h + 3] = ((u64)u1.w << 32) | u1.z;
+            }
+#pragma unroll
+            for (int h = 0; h < RNT / 4; h++) {
+                lds_load4(Bn + k * TNP + h * (TN / 2) + tx * 4, bn + 4 * h);
+                const uint4 u0 = *(const uint4*)(Bc + k * TNP + h * (TN / 2) + tx * 4);
+                const uint4 u1 = *(const uint4*)(Bc + k * TNP + h * (TN / 2) + tx * 4 + 2);
+                bc[4 * h + 0] = ((u64)u0.y << 32) | u0.x;
+                bc[4 * h + 1] = ((u64)u0.w << 32) | u0.z;
+                bc[4 * h + 2] = ((u64)u1.y << 32) | u1.x;
+                bc[4 * h + 3] = ((u64)u1.w << 32) | u1.z;
+            }
+#pragma unroll
+            for (int r = 0; r < RMT; r++)
+#pragma unroll
+                for (int c = 0; c < RNT; c++) ct_mac(accn[r][c], accc[r][c], an[r], ac[r], bn[c], bc[c]);
+        }
+        __syncthreads();
+    }
+    const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
+    const Planes dst = g.lsplit ? g.P : g.C;
+    const i64 sbase = g.lsplit ? (i64)p.split * nout : 0;
+    int* dn = (int*)dst.p0 + sbase;
+    u64* dc = (u64*)dst.p1 + sbase;
+#pragma unroll
+    for (int r = 0; r < RMT; r++) {
+        const int row = (r / 4) * (TM / 2) + ty * 4 + (r & 3);
+        const i64 base = ((p.b0 << g.li) | (p.i0 + row)) << g.lj;
+#pragma unroll
+        for (int h = 0; h < RNT / 4; h++) {
+            const i64 o = base + p.j0 + h * (TN / 2) + tx * 4;
+            global_store4(dn + o, &accn[r][4 * h]);
+            uint4 u0, u1;
+            u0.x = (unsigned)accc[r][4 * h + 0];
+            u0.y = (unsigned)(accc[r][4 * h + 0] >> 32);
+            u0.z = (unsigned)accc[r][4 * h + 1];
+            u0.w = (unsigned)(accc[r][4 * h + 1] >> 32);
+            u1.x = (unsigned)accc[r][4 * h + 2];
+            u1.y = (unsigned)(accc[r][4 * h + 2] >> 32);
+            u1.z = (unsigned)accc[r][4 * h + 3];
+            u1.w = (unsigned)(accc[r][4 * h + 3] >> 32);
+            *(uint4*)(dc + o) = u0;
+            *(uint4*)(dc + o + 2) = u1;
+        }
+    }
+}
+
+template <int D>
+__device__ inline bool gemm_tile_ct_big_any(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    if (g.ti == 7 && g.tj == 6) gemm_tile_ct_big<7, 6>(g, tile, smem);
+    else if (g.ti == 6 && g.tj == 7) gemm_tile_ct_big<6, 7>(g, tile, smem);
+    else if (g.ti == 8 && g.tj == 5) gemm_tile_ct_big<8, 5>(g, tile, smem);
+    else if (g.ti == 5 && g.tj == 8) gemm_tile_ct_big<5, 8>(g, tile, smem);
     else return false;
     return true;
 }

@@ -3,7 +3,8 @@
 The per-node executor sends nodes of the 4-byte VALU algebras (max-plus
 int32 and float32, counts mod p) with M, N >= 2^7 and K >= 2^4 to a 128 x 128
 tile, and nodes with one side >= 2^8 and the other 2^5 or 2^6 to the 256 x 32,
-256 x 64 tiles (or their mirror images).  Square lattices of side 14 and 16,
+256 x 64 tiles (or their mirror images); counting-tropical nodes go to
+128 x 64, 64 x 128, 256 x 32 and 32 x 256 tiles.  Square lattices of side 14 and 16,
 a King's subgraph of side 15 and a finely sliced plan of the 240-vertex
 3-regular network have such nodes (with and without batch indices, with
 split K); each case asserts which tiles ran and compares the result with the
@@ -59,12 +60,28 @@ def _tile(shape):
     return None
 
 
-# (graph, planner, planner seed, tiles the plan must exercise)
+def _ct_tile(shape):
+    """(log2 TM, log2 TN) of the counting-tropical register-tiled kernel."""
+    _, i, j, k = shape
+    if k < 2:
+        return None
+    if i >= 7 and j >= 6:
+        return (7, 6)
+    if i >= 6 and j >= 7:
+        return (6, 7)
+    if i >= 8 and j == 5:
+        return (8, 5)
+    if j >= 8 and i == 5:
+        return (5, 8)
+    return None
+
+
+# (graph, planner, planner seed, 4-byte tiles, counting-tropical tiles the plan must exercise)
 CASES = [
-    ("lattice14", "greedy", 0, {(7, 7), (8, 6), (8, 5)}),
-    ("lattice14", "treesa", 0, {(7, 7)}),
-    ("lattice16", "greedy", 0, {(7, 7), (6, 8)}),
-    ("ksg15", "treesa", 2, {(7, 7), (8, 6), (8, 5), (5, 8)}),
+    ("lattice14", "greedy", 0, {(7, 7), (8, 6), (8, 5)}, {(7, 6), (8, 5)}),
+    ("lattice14", "treesa", 0, {(7, 7)}, {(7, 6)}),
+    ("lattice16", "greedy", 0, {(7, 7), (6, 8)}, {(7, 6), (6, 7)}),
+    ("ksg15", "treesa", 2, {(7, 7), (8, 6), (8, 5), (5, 8)}, {(7, 6), (6, 7), (8, 5), (5, 8)}),
 ]
 
 
@@ -74,8 +91,8 @@ def _graph(name):
     return gg.kings_subgraph(15, 0.8, 1)
 
 
-@pytest.mark.parametrize("name,method,seed,tiles", CASES)
-def test_big_tiles_vs_oracle(ctx, name, method, seed, tiles):
+@pytest.mark.parametrize("name,method,seed,tiles,ct_tiles", CASES)
+def test_big_tiles_vs_oracle(ctx, name, method, seed, tiles, ct_tiles):
     gu = _graph(name)
     gw = gu.with_weights(gg.dyadic_weights(gu.nv, 7))
     net_u, net_w = tn.Net.from_graph(gu), tn.Net.from_graph(gw)
@@ -91,6 +108,12 @@ def test_big_tiles_vs_oracle(ctx, name, method, seed, tiles):
         assert tiles <= ran  # count_exact: the residue lanes mod p
         # dyadic weights: every partial sum is exact in float32
         assert r[key] == want
+    want = oracle.eliminate(gu, "counting_tropical")
+    r, recs = _solve_profiled(ctx, net_u, plan_u, "counting_tropical")
+    ran = {_ct_tile(x["shape"]) for x in recs if x["kind"] == "gemm_big"}
+    print(f"  counting_tropical: {r['size']}, {r['count_mod_2_64']} vs {want}, tiles {sorted(ran, key=str)}", flush=True)
+    assert ct_tiles <= ran
+    assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count"] % 2 ** 64)
 
 
 def test_k5_slice_big_tiles_vs_plan_follower(ctx):
@@ -113,3 +136,20 @@ def test_k5_slice_big_tiles_vs_plan_follower(ctx):
     b = ctx.solve(net, plan, "tropical_f32", slices=(s, s + 1), executor="stream")
     c = ctx.solve(net, plan, "counting_tropical", slices=(s, s + 1), executor="stream")
     assert a["size"] == b["size"] == c["size"]
+
+
+@pytest.mark.parametrize("name,method,seed", [("lattice14", "greedy", 0), ("ksg15", "treesa", 2)])
+def test_persistent_big_tiles_vs_oracle(ctx, name, method, seed):
+    """The persistent kernel runs the same tile shapes (they depend on the
+    node only), so the networks above cover its register-tiled paths too."""
+    gu = _graph(name)
+    gw = gu.with_weights(gg.dyadic_weights(gu.nv, 7))
+    net_u, net_w = tn.Net.from_graph(gu), tn.Net.from_graph(gw)
+    plan_u, plan_w = _plan(net_u, method, seed), _plan(net_w, method, seed)
+    ct = oracle.eliminate(gu, "counting_tropical")
+    r = ctx.solve(net_u, plan_u, "counting_tropical", executor="persistent")
+    assert (r["size"], r["count_mod_2_64"]) == (ct["size"], ct["count"] % 2 ** 64)
+    assert ctx.solve(net_u, plan_u, "tropical_i32", executor="persistent")["size"] == ct["size"]
+    assert ctx.solve(net_u, plan_u, "count_exact", executor="persistent")["count"] == oracle.eliminate(gu, "count")["count"]
+    want = oracle.eliminate(gw, "tropical")["size"]
+    assert ctx.solve(net_w, plan_w, "tropical_f32", executor="persistent")["size"] == want
