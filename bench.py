@@ -133,7 +133,7 @@ def largest_intermediate(ctx):
         dt = time.perf_counter() - t0
         recs = ctx.profile()
         ctx.set_profiling(False)
-        gem = max((r for r in recs if r["kind"] in ("gemm", "gemm_big")), key=lambda r: r["ops"])
+        gem = max((r for r in recs if r["kind"].startswith("gemm")), key=lambda r: r["ops"])
         perm = max((r for r in recs if r["kind"] == "permute"), key=lambda r: r["alg_bytes"])
         peak = LANE_TOPS / INSTR_PER_OP[sr]
         tops = gem["ops"] / gem["ms"] / 1e9

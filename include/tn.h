@@ -112,7 +112,9 @@ typedef enum {
     TN_K_GEMM_MFMA = 3, /* batched GEMM on matrix cores (partition function) */
     TN_K_ACCUM = 4,     /* slice accumulation / root handling */
     TN_K_BATCH = 5,     /* persistent batched launch */
-    TN_K_GEMM_BIG = 6   /* batched semiring GEMM, 128 x 128 register-tiled VALU kernel */
+    TN_K_GEMM_BIG = 6,  /* batched semiring GEMM, register-tiled VALU kernels (large M, N) */
+    TN_K_GEMM_THIN = 7, /* batched semiring GEMM, row streaming for N * K <= 32 */
+    TN_K_GEMM_DOT = 8   /* batched semiring GEMM with M = N = 1: long-K reduction */
 } tn_kernel_kind;
 
 typedef struct {

@@ -33,7 +33,8 @@ SEMIRING = {
     "partition_f32": TN_PARTITION_F32,
     "partition_bf16": TN_PARTITION_BF16,
 }
-KERNEL_KIND = {0: "leaf", 1: "permute", 2: "gemm", 3: "gemm_mfma", 4: "accum", 5: "batch", 6: "gemm_big"}
+KERNEL_KIND = {0: "leaf", 1: "permute", 2: "gemm", 3: "gemm_mfma", 4: "accum", 5: "batch", 6: "gemm_big", 7: "gemm_thin",
+               8: "gemm_dot"}
 
 
 class LibraryMissing(RuntimeError):

@@ -70,6 +70,14 @@ __device__ void run_gemm(const BJob& j, const BNode& nd, i64 tile, unsigned char
     g.mb = nd.mb;
     g.mc = nd.mc;
     const int rm = nd.g.rm, rn = nd.g.rn;
+    if (nd.g.mode == GEMM_THIN) {
+        gemm_tile_thin<D>(g, (u64)tile, smem);
+        return;
+    }
+    if (nd.g.mode == GEMM_DOT) {
+        gemm_tile_dot<D>(g, (u64)tile, smem);
+        return;
+    }
     if constexpr (is_z<D>()) {
         if (nd.g.mfma) {
             gemm_tile_mfma<D>(g, (u64)tile, smem);

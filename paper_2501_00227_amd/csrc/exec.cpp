@@ -502,7 +502,12 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                              std::exp2((double)(g.lb + g.li + g.lj));
                 int shp[4] = {g.lb, g.li, g.lj, g.lk};
                 {
-                    ProfScope ps(ctx, g.mfma ? TN_K_GEMM_MFMA : (g.rm == 8 ? TN_K_GEMM_BIG : TN_K_GEMM), np.node, o.semiring, shp, ent * eb,
+                    const int kind = g.mode == GEMM_THIN  ? TN_K_GEMM_THIN
+                                     : g.mode == GEMM_DOT ? TN_K_GEMM_DOT
+                                     : g.mfma             ? TN_K_GEMM_MFMA
+                                     : g.rm == 8          ? TN_K_GEMM_BIG
+                                                          : TN_K_GEMM;
+                    ProfScope ps(ctx, kind, np.node, o.semiring, shp, ent * eb,
                                  std::exp2((double)(g.lb + g.li + g.lj + g.lk)));
                     chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s));
                 }

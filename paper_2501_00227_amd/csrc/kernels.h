@@ -66,7 +66,14 @@ struct GemmShape {
     int rm, rn;            // per-thread micro tile
     int lsplit;            // log2 of K splits (partials then reduce)
     int mfma;              // partition function on matrix cores (64 x 64 tile, 4 waves)
+    int mode;              // GEMM_TILED, GEMM_THIN or GEMM_DOT
 };
+
+// GEMM kernel modes: LDS-staged tiles (the 4x4 / register-tiled families),
+// row streaming for thin nodes (N * K <= 32: each thread owns whole output
+// rows, B sits in LDS), and a long-K reduction for nodes with one output per
+// batch (M = N = 1).
+enum GemmMode { GEMM_TILED = 0, GEMM_THIN = 1, GEMM_DOT = 2 };
 
 // log2 entries of one permute tile for a tensor of the given rank
 constexpr int kPermTileBits = 12;

@@ -190,6 +190,27 @@ __global__ __launch_bounds__(256) void gemm_big_kernel(GemmArgs g) {
     gemm_tile_big<D, LTM, LTN>(g, blockIdx.x, smem);
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void gemm_thin_kernel(GemmArgs g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gemm_tile_thin<D>(g, blockIdx.x, smem);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void gemm_dot_kernel(GemmArgs g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gemm_tile_dot<D>(g, blockIdx.x, smem);
+}
+
+template <int D>
+static hipError_t gemm_mode_go(const GemmArgs& a, int mode, size_t lds, u64 blocks, hipStream_t s) {
+    if (mode == GEMM_THIN)
+        gemm_thin_kernel<D><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+    else
+        gemm_dot_kernel<D><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+    return hipGetLastError();
+}
+
 template <int LTM, int LTN>
 __global__ __launch_bounds__(256) void gemm_ct_big_kernel(GemmArgs g) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -235,6 +256,25 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     const int eb = lds_elem_bytes(dsr);
     const int lds_cap = 40 * 1024;
     g.mfma = 0;
+    g.mode = GEMM_TILED;
+    if (li == 0 && lj == 0 && lk >= 12) {  // one output per batch, long K
+        g.mode = GEMM_DOT;
+        g.rm = g.rn = 1;
+        int ls = 9 - lb;  // about 512 workgroups, each over >= 2^12 of K
+        if (ls > lk - 12) ls = lk - 12;
+        if (ls > 10) ls = 10;
+        g.lsplit = ls < 0 ? 0 : ls;
+        return g;
+    }
+    const int kthin = (dsr == DSR_CTROP || dsr == DSR_U64) ? 1 : 2;  // K entries of <= 16 bytes per row
+    if (li >= 10 && lj <= 4 && lk <= kthin && lj + lk <= 5) {  // thin: N * K <= 32
+        g.mode = GEMM_THIN;
+        g.rm = g.rn = 1;
+        g.ti = li < 12 ? li : 12;
+        g.tj = lj;
+        g.tk = lk;
+        return g;
+    }
     const bool four_byte_valu = dsr == DSR_TROP_I32 || dsr == DSR_TROP_F32 || dsr == DSR_MODP;
     // register-tiled family: 128 x 128 for large M and N; 256 x 64 / 256 x 32
     // (or mirrored) when one side is large and the other 2^5 or 2^6
@@ -315,6 +355,13 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
+    if (g.mode == GEMM_DOT)
+        return g.li == 0 && g.lj == 0 && g.ti == 0 && g.tj == 0 && g.tb == 0 && !g.mfma && g.lsplit >= 0 &&
+               g.lsplit <= 10 && g.lsplit <= g.lk;
+    if (g.mode == GEMM_THIN)
+        return g.tb == 0 && g.tj == g.lj && g.tk == g.lk && g.lj <= 4 && g.lk <= 2 && g.lj + g.lk <= 5 &&
+               g.ti >= 10 && g.ti <= g.li && g.lsplit == 0 && !g.mfma;
+    if (g.mode != GEMM_TILED) return false;
     if ((g.rm == 8 || g.rn == 8) && dsr == DSR_CTROP) {  // counting-tropical register tiles
         if (g.rm != 8 || g.rn != 8 || !ct_tile_shape(g.ti, g.tj) || g.tb != 0 || g.mfma) return false;
         if (g.tk < 0 || g.tk > 4 || g.tk + g.lsplit > g.lk || g.li < g.ti || g.lj < g.tj) return false;
@@ -343,6 +390,8 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
 }
 
 size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
+    if (g.mode == GEMM_DOT) return 256 * (size_t)lds_elem_bytes(dsr);
+    if (g.mode == GEMM_THIN) return ((size_t)1 << (g.lk + g.lj)) * lds_elem_bytes(dsr);
     if (g.rm == 8)
         return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * (dsr == DSR_CTROP ? 12 : 4);
     return (size_t)(1 << (g.tb + g.tk)) * (pad_dim(1 << g.ti) + pad_dim(1 << g.tj)) * lds_elem_bytes(dsr);
@@ -396,6 +445,18 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
     GemmArgs a = make_gemm_args(Ap, Bp, Cp, part, g, ap, meta, ma, mb, mc);
     size_t lds = gemm_lds_bytes(dsr, g);
     u64 blocks = 1ull << ((g.lb - g.tb) + (g.li - g.ti) + (g.lj - g.tj) + g.lsplit);
+    if (g.mode != GEMM_TILED) {
+        switch (dsr) {
+        case DSR_TROP_I32: return gemm_mode_go<DSR_TROP_I32>(a, g.mode, lds, blocks, s);
+        case DSR_TROP_F32: return gemm_mode_go<DSR_TROP_F32>(a, g.mode, lds, blocks, s);
+        case DSR_CTROP: return gemm_mode_go<DSR_CTROP>(a, g.mode, lds, blocks, s);
+        case DSR_U64: return gemm_mode_go<DSR_U64>(a, g.mode, lds, blocks, s);
+        case DSR_MODP: return gemm_mode_go<DSR_MODP>(a, g.mode, lds, blocks, s);
+        case DSR_Z_F32: return gemm_mode_go<DSR_Z_F32>(a, g.mode, lds, blocks, s);
+        case DSR_Z_BF16: return gemm_mode_go<DSR_Z_BF16>(a, g.mode, lds, blocks, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (g.rm == 8) {
         if (dsr == DSR_CTROP) return gemm_ct_big_go(a, lds, blocks, s);
         if (dsr == DSR_TROP_I32) return gemm_big_go<DSR_TROP_I32>(a, lds, blocks, s);

@@ -900,6 +900,92 @@ __device__ void gemm_tile_mfma(const GemmArgs& g, u64 tile, unsigned char* smem)
     z_epilogue<D>(g, tile, lmax);
 }
 
+// ----------------------------------------------------- thin / dot GEMM --
+// Thin node (GEMM_THIN): a tile is 2^ti (>= 1024) consecutive rows of one
+// batch; B (K x N <= 32 entries) is staged in LDS.  Each thread takes four
+// rows per step (tid + 256 q) and issues all their loads (K <= 4 entries of
+// at most 4 bytes, or K <= 2 of 8) before computing, so a wave keeps
+// 4 x 64 row loads in flight; neighbouring lanes touch neighbouring rows, so
+// loads and stores are contiguous across a wave in either operand order.
+template <int D>
+__device__ void gemm_tile_thin(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    constexpr int RQ = 4, KMAX = 4;
+    V* Bs = (V*)smem;  // [k][j]
+    const TilePos p = tile_pos(g, tile);
+    const int K = 1 << g.lk, N = 1 << g.lj;
+    const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    for (int q = threadIdx.x; q < K * N; q += 256) {
+        const int k = q >> g.lj, j = q & (N - 1);
+        const i64 addr = g.b_t ? (((p.b0 << g.lj) | j) << g.lk) | k : (((p.b0 << g.lk) | k) << g.lj) | j;
+        Bs[q] = A::prescale(A::load(g.B, addr), sB);
+    }
+    __syncthreads();
+    float lmax = 0.0f;
+    const int rows = 1 << g.ti;
+    for (int r0 = 0; r0 < rows; r0 += 256 * RQ) {
+        V av[RQ][KMAX];
+#pragma unroll
+        for (int q = 0; q < RQ; q++) {
+            const i64 i = p.i0 + r0 + q * 256 + threadIdx.x;
+#pragma unroll
+            for (int k = 0; k < KMAX; k++)
+                if (k < K) {
+                    const i64 addr = g.a_t ? (((p.b0 << g.lk) | k) << g.li) | i : (((p.b0 << g.li) | i) << g.lk) | k;
+                    av[q][k] = A::load(g.A, addr);
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < RQ; q++) {
+            const i64 obase = ((p.b0 << g.li) | (p.i0 + r0 + q * 256 + threadIdx.x)) << g.lj;
+            for (int j = 0; j < N; j++) {
+                V acc = A::zero(g.ap);
+#pragma unroll
+                for (int k = 0; k < KMAX; k++)
+                    if (k < K) acc = A::add(acc, A::mul(A::prescale(av[q][k], sA), Bs[(k << g.lj) | j], g.ap), g.ap);
+                A::store(g.C, obase | j, acc);
+                if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc);
+            }
+        }
+    }
+    z_epilogue<D>(g, tile, lmax);
+}
+
+// One output per batch (GEMM_DOT): a tile is one (batch, K-split) pair; the
+// workgroup's threads stride over the K range (A and B are both contiguous in
+// k when M = N = 1), then reduce through LDS.
+template <int D>
+__device__ void gemm_tile_dot(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    V* red = (V*)smem;
+    const TilePos p = tile_pos(g, tile);
+    const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    V acc = A::zero(g.ap);
+    const i64 base = p.b0 << g.lk;
+    for (i64 k = p.kbeg + threadIdx.x; k < p.kbeg + p.Kc; k += 256)
+        acc = A::add(acc, A::mul(A::prescale(A::load(g.A, base | k), sA), A::prescale(A::load(g.B, base | k), sB), g.ap),
+                     g.ap);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = A::add(red[threadIdx.x], red[threadIdx.x + w], g.ap);
+        __syncthreads();
+    }
+    float lmax = 0.0f;
+    if (threadIdx.x == 0) {
+        const i64 nout = (i64)1 << g.lb;
+        if (g.lsplit)
+            A::store(g.P, (i64)p.split * nout + p.b0, red[0]);
+        else
+            A::store(g.C, p.b0, red[0]);
+        if constexpr (is_z<D>()) lmax = red[0];
+    }
+    z_epilogue<D>(g, tile, lmax);
+    __syncthreads();
+}
+
 // --------------------------------------------------------- split reduce --
 // C[o] = (+)_s part[s][o] for one output o, by the whole workgroup.
 template <int D>

@@ -131,9 +131,14 @@ def test_k5_slice_big_tiles_vs_plan_follower(ctx):
     assert r["count"] == want
     # the max-plus lanes on the same slice agree with each other and with the
     # counting-tropical size (which runs on the 4 x 4 kernel)
+    kinds = {x["kind"] for x in recs}
+    print("  kernel kinds", sorted(kinds), flush=True)
+    assert {"gemm_thin", "gemm_dot"} <= kinds  # sliced plans have thin nodes (N * K <= 32, M >= 2^10)
     a, recs = _solve_profiled(ctx, net, plan, "tropical_i32", slices=(s, s + 1))
     assert _nbig(recs) > 0
     b = ctx.solve(net, plan, "tropical_f32", slices=(s, s + 1), executor="stream")
+    z = oracle.follow_plan(g, tree, "partition", beta=0.25, slices=(s, s + 1))["log_z"]
+    assert abs(ctx.solve(net, plan, "partition_f32", beta=0.25, slices=(s, s + 1), executor="stream")["log_z"] - z) <= 1e-5
     c = ctx.solve(net, plan, "counting_tropical", slices=(s, s + 1), executor="stream")
     assert a["size"] == b["size"] == c["size"]
 
@@ -153,3 +158,40 @@ def test_persistent_big_tiles_vs_oracle(ctx, name, method, seed):
     assert ctx.solve(net_u, plan_u, "count_exact", executor="persistent")["count"] == oracle.eliminate(gu, "count")["count"]
     want = oracle.eliminate(gw, "tropical")["size"]
     assert ctx.solve(net_w, plan_w, "tropical_f32", executor="persistent")["size"] == want
+
+
+@pytest.mark.parametrize("side", [14, 16])
+@pytest.mark.parametrize("executor", ["stream", "persistent"])
+def test_thin_and_dot_modes_vs_oracle(ctx, side, executor):
+    """The root of a lattice plan contracts two tensors over all their indices
+    (M = N = 1, K >= 2^12) and runs as a long-K reduction; every algebra
+    against the oracle.  (Thin nodes come with slicing: see the sliced
+    240-vertex test.)"""
+    gu = gg.square_lattice(side)
+    gw = gu.with_weights(gg.dyadic_weights(gu.nv, 3))
+    net_u, net_w = tn.Net.from_graph(gu), tn.Net.from_graph(gw)
+    plan_u, plan_w = _plan(net_u, "greedy"), _plan(net_w, "greedy")
+    ct = oracle.eliminate(gu, "counting_tropical")
+    cnt = oracle.eliminate(gu, "count")["count"]
+    trw = oracle.eliminate(gw, "tropical")["size"]
+    kinds = set()
+
+    def run(net, plan, sr, **kw):
+        if executor == "stream":
+            r, recs = _solve_profiled(ctx, net, plan, sr, **kw)
+            kinds.update(x["kind"] for x in recs)
+            return r
+        return ctx.solve(net, plan, sr, executor="persistent", **kw)
+
+    r = run(net_u, plan_u, "counting_tropical")
+    assert (r["size"], r["count_mod_2_64"]) == (ct["size"], ct["count"] % 2 ** 64)
+    assert run(net_u, plan_u, "tropical_i32")["size"] == ct["size"]
+    assert run(net_w, plan_w, "tropical_f32")["size"] == trw
+    assert run(net_u, plan_u, "count_exact")["count"] == cnt
+    for beta in (0.5, 2.0):
+        want = oracle.eliminate(gw, "partition", beta=beta)["log_z"]
+        assert abs(run(net_w, plan_w, "partition_f32", beta=beta)["log_z"] - want) <= 1e-5
+        assert abs(run(net_w, plan_w, "partition_bf16", beta=beta)["log_z"] - want) <= 0.05
+    if executor == "stream":
+        print("kernel kinds", sorted(kinds), flush=True)
+        assert "gemm_dot" in kinds
