@@ -40,12 +40,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_GBS = 8000.0
-CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
-LANE_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0  # 39.3 T 32-bit lane instructions / s
-# VALU instructions per semiring op of the register-tiled GEMM inner loop,
-# counted in the compiled gfx950 code (max-plus: v_add clamp + v_max3 per two
-# ops; counting tropical: add-sat, 64-bit multiply, compare/select, 64-bit add)
-INSTR_PER_OP = {"tropical_i32": 1.5, "tropical_f32": 1.5, "counting_tropical": 12.0}
+# VALU peak from the published FP32 vector rate: 157.3 TFLOP/s = 78.6 T lane
+# FMAs / s, i.e. 78.6 T 32-bit lane instructions / s (256 CUs x 2.4 GHz x 128
+# lanes per clock).
+LANE_TOPS = 157.3 / 2.0
+# Fewest VALU instructions one semiring op can take on gfx950: max-plus is one
+# add per product plus one three-input max per two products; counting
+# tropical is a saturating add, a 64-bit product (one 32x32->64 multiply-add,
+# two 32-bit multiplies, one three-input add), two compares, four selects, a
+# 64-bit add and a max.
+INSTR_PER_OP = {"tropical_i32": 1.5, "tropical_f32": 1.5, "counting_tropical": 13.0}
 SR_NAME = {0: "tropical_i32", 1: "tropical_f32", 2: "counting_tropical", 3: "count_exact", 4: "partition_f32",
            5: "partition_bf16", -1: "mixed"}
 MFMA_F32_TFLOPS = 157.3

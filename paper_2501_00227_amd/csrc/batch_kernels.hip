@@ -40,7 +40,8 @@ __device__ inline void signal_counter(int* counters, int c) {
 }
 
 template <int D>
-__device__ void run_gemm(const BJob& j, const BNode& nd, i64 tile, unsigned char* smem) {
+__device__ __attribute__((always_inline)) void run_gemm(const BJob& j, const BNode& nd, i64 tile,
+                                                        unsigned char* smem) {
     auto at = [&](int64_t off) {
         Planes r;
         r.p0 = (unsigned char*)j.arena.p0 + off * plane_bytes_dev<D>(0);
@@ -188,8 +189,16 @@ __device__ void run_node_whole(const BJob& j, const BNode& nd, unsigned char* sm
     }
 }
 
+// One task of an algebra-D job.  Kept out of line, one function per algebra,
+// with everything it runs inlined: registers are then allocated per algebra
+// (each fits the two-waves-per-SIMD budget; only counting tropical spills a
+// few) rather than over the union of all algebras in the task loop, and the call
+// costs one register save per task.  (Inlining all algebras into the task
+// loop spills heavily; calling a GEMM routine per tile saves registers to
+// scratch on every tile.)
 template <int D>
-__device__ void run_task(const BTask& t, const BJob& j, const BNode* nodes, const int* subtree, unsigned char* smem) {
+__attribute__((noinline)) __device__ void run_task(const BTask& t, const BJob& j, const BNode* nodes,
+                                                   const int* subtree, unsigned char* smem) {
     switch (t.kind) {
     case BT_LEAVES: {
         // fresh partition-function bookkeeping for every node, then the leaves
