@@ -60,11 +60,12 @@ def _load():
                                         f64p, u64p, u64p, u64p, f64p, f64p, ctypes.c_int, u64p, ip]
         lib.orc_eliminate.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                       ctypes.c_double, ctypes.c_int, f64p, u64p, f64p, f64p, ip]
+        lib.orc_eliminate_poly.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int, u64p, ip, ip]
         lib.orc_follow_plan.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, i32p, i32p,
                                         i32p, i32p, i32p, i32p, ctypes.c_int, i32p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int, f64p, u64p, f64p, f64p]
-        for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_follow_plan):
+        for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_eliminate_poly, lib.orc_follow_plan):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -148,6 +149,22 @@ def eliminate(graph, semiring: str, beta: float = 0.0, max_width: int = 26) -> D
     out = _result(sr, size, limbs, z, lz)
     out["width"] = width.value
     return out
+
+
+def eliminate_polynomial(graph, max_width: int = 16) -> Dict:
+    """O2 over polynomials: the independence polynomial's coefficients
+    (c_k = number of independent sets of size k), unit weights, exact."""
+    lib = _load()
+    edges, _ = _graph_arrays(graph)
+    coeffs = np.zeros(4 * (graph.nv + 1), np.uint64)
+    degree = ctypes.c_int(0)
+    width = ctypes.c_int(0)
+    rc = lib.orc_eliminate_poly(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), int(max_width),
+                                _ptr(coeffs, ctypes.c_uint64), ctypes.byref(degree), ctypes.byref(width))
+    if rc != ORC_OK:
+        raise OracleError(rc, f"eliminate_polynomial(width={width.value})")
+    poly = [_limbs_to_int(coeffs[4 * k: 4 * k + 4]) for k in range(degree.value + 1)]
+    return {"poly": poly, "degree": degree.value, "width": width.value}
 
 
 def follow_plan(graph, tree: Dict, semiring: str, beta: float = 0.0, max_rank: int = 26,

@@ -19,7 +19,9 @@
  * Three programs, each independent of the others:
  *   O1  orc_brute_force   enumerate all 2^n subsets (the definitions above)
  *   O2  orc_eliminate     variable elimination with its own heuristic order,
- *                         over dense factor tables in exact semiring arithmetic
+ *                         over dense factor tables in exact semiring arithmetic;
+ *       orc_eliminate_poly  the same over polynomial-valued tables: the
+ *                         independence polynomial (Sec. 5.3 GraphPolynomial)
  *   O3  orc_follow_plan   evaluate a given binary contraction tree (Sec. 4.1),
  *                         one literal einsum loop per node, with optional
  *                         sliced indices (Sec. 4.2, TreeSA slicing)
@@ -533,6 +535,186 @@ int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr,
     free(order);
     if (status != ORC_OK) return status;
     put_result(sr, root, size, limbs, zval, logz);
+    return g_overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+/* --------------------------------------------------- O2 over polynomials --- */
+/*
+ * The independence polynomial I(G, x) = sum_k c_k x^k, c_k = #{S independent :
+ * |S| = k} (Sec. 5.3, GraphPolynomial; Sec. 6.2).  Same elimination as above,
+ * but every table entry is a polynomial in x with exact 256-bit coefficients:
+ * the vertex tensor is [1, x], the edge tensor [[1,1],[1,0]], "+" adds
+ * polynomials and "*" multiplies them.  Unit weights only.  Each factor keeps
+ * the largest degree any of its entries can have (the number of vertex
+ * tensors absorbed into it, at most nv).
+ */
+typedef struct {
+    int nvars;
+    int* vars;
+    int deg;   /* entries are polynomials of degree <= deg */
+    u256* tab; /* 2^nvars entries of deg+1 coefficients each */
+    int alive;
+} pfactor;
+
+static void poly_mul_into(const u256* a, int da, const u256* b, int db, u256* out, int dout) {
+    for (int k = 0; k <= dout; k++) out[k] = u256_from(0);
+    for (int i = 0; i <= da; i++) {
+        if (!(a[i].w[0] | a[i].w[1] | a[i].w[2] | a[i].w[3])) continue;
+        for (int j = 0; j <= db && i + j <= dout; j++) out[i + j] = u256_add(out[i + j], u256_mul(a[i], b[j]));
+    }
+}
+
+int orc_eliminate_poly(int nv, int ne, const int32_t* edges, int max_width, uint64_t* coeffs, int* degree,
+                       int* width_out) {
+    if (nv < 0 || ne < 0) return ORC_EINVAL;
+    for (int e = 0; e < ne; e++) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= nv || v >= nv || u == v) return ORC_EINVAL;
+    }
+    g_overflow = 0;
+    int* order = malloc(sizeof(int) * (size_t)(nv + 1));
+    pfactor* fs = calloc((size_t)(ne + 2 * nv + 1), sizeof(pfactor));
+    if (!order || !fs) {
+        free(order);
+        free(fs);
+        return ORC_ENOMEM;
+    }
+    int width = 0;
+    if (nv > 0 && elimination_order(nv, ne, edges, order, &width) != ORC_OK) {
+        free(order);
+        free(fs);
+        return ORC_ENOMEM;
+    }
+    if (width_out) *width_out = width;
+    if (width > max_width) {
+        free(order);
+        free(fs);
+        return ORC_ETOOBIG;
+    }
+    int nfac = 0;
+    for (int e = 0; e < ne; e++) { /* [[1,1],[1,0]] */
+        pfactor* f = &fs[nfac++];
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        f->nvars = 2;
+        f->vars = malloc(2 * sizeof(int));
+        f->vars[0] = u < v ? u : v;
+        f->vars[1] = u < v ? v : u;
+        f->deg = 0;
+        f->tab = malloc(4 * sizeof(u256));
+        for (int a = 0; a < 4; a++) f->tab[a] = u256_from(a == 3 ? 0 : 1);
+        f->alive = 1;
+    }
+    for (int v = 0; v < nv; v++) { /* [1, x] */
+        pfactor* f = &fs[nfac++];
+        f->nvars = 1;
+        f->vars = malloc(sizeof(int));
+        f->vars[0] = v;
+        f->deg = 1;
+        f->tab = malloc(4 * sizeof(u256)); /* entry 0: 1 + 0x, entry 1: 0 + 1x */
+        f->tab[0] = u256_from(1);
+        f->tab[1] = u256_from(0);
+        f->tab[2] = u256_from(0);
+        f->tab[3] = u256_from(1);
+        f->alive = 1;
+    }
+    int status = ORC_OK;
+    int* scope = malloc(sizeof(int) * (size_t)(nv + 1));
+    int* bucket = malloc(sizeof(int) * (size_t)(nfac + nv + 1));
+    int* pos = malloc(sizeof(int) * (size_t)(nfac + nv + 1) * (size_t)(nv + 1));
+    u256* prod = malloc(sizeof(u256) * (size_t)(nv + 1));
+    u256* tmp = malloc(sizeof(u256) * (size_t)(nv + 1));
+    for (int step = 0; step < nv && status == ORC_OK; step++) {
+        int v = order[step];
+        int nb = 0, ns = 0, dg = 0;
+        for (int i = 0; i < nfac; i++) {
+            if (!fs[i].alive || !contains(fs[i].vars, fs[i].nvars, v)) continue;
+            bucket[nb++] = i;
+            dg += fs[i].deg;
+            for (int t = 0; t < fs[i].nvars; t++)
+                if (!contains(scope, ns, fs[i].vars[t])) scope[ns++] = fs[i].vars[t];
+        }
+        if (dg > nv) dg = nv;
+        qsort(scope, (size_t)ns, sizeof(int), cmp_int);
+        int vpos = 0;
+        while (scope[vpos] != v) vpos++;
+        pfactor* g = &fs[nfac];
+        g->nvars = ns - 1;
+        g->deg = dg;
+        g->vars = malloc(sizeof(int) * (size_t)(ns > 1 ? ns - 1 : 1));
+        for (int s = 0, t = 0; s < ns; s++)
+            if (s != vpos) g->vars[t++] = scope[s];
+        size_t nout = (size_t)1 << g->nvars;
+        g->tab = calloc(nout * (size_t)(dg + 1), sizeof(u256));
+        if (!g->tab) {
+            status = ORC_ENOMEM;
+            break;
+        }
+        for (int b = 0; b < nb; b++) { /* positions of each bucket factor's variables in the scope */
+            pfactor* f = &fs[bucket[b]];
+            for (int t = 0; t < f->nvars; t++)
+                for (int s2 = 0; s2 < ns; s2++)
+                    if (scope[s2] == f->vars[t]) pos[(size_t)b * (size_t)(nv + 1) + t] = s2;
+        }
+        for (size_t y = 0; y < nout; y++) {
+            uint64_t lo = y & (((uint64_t)1 << vpos) - 1), hi = (y >> vpos) << (vpos + 1);
+            u256* acc = g->tab + y * (size_t)(dg + 1);
+            for (int xv = 0; xv < 2; xv++) {
+                uint64_t x = hi | ((uint64_t)xv << vpos) | lo;
+                int dp = 0;
+                prod[0] = u256_from(1);
+                for (int b = 0; b < nb; b++) {
+                    pfactor* f = &fs[bucket[b]];
+                    size_t idx = 0;
+                    for (int t = 0; t < f->nvars; t++)
+                        idx |= (size_t)((x >> pos[(size_t)b * (size_t)(nv + 1) + t]) & 1) << t;
+                    int dn = dp + f->deg > dg ? dg : dp + f->deg;
+                    poly_mul_into(prod, dp, f->tab + idx * (size_t)(f->deg + 1), f->deg, tmp, dn);
+                    memcpy(prod, tmp, sizeof(u256) * (size_t)(dn + 1));
+                    dp = dn;
+                }
+                for (int k = 0; k <= dp; k++) acc[k] = u256_add(acc[k], prod[k]);
+            }
+        }
+        for (int b = 0; b < nb; b++) {
+            pfactor* f = &fs[bucket[b]];
+            f->alive = 0;
+            free(f->tab);
+            free(f->vars);
+            f->tab = NULL;
+            f->vars = NULL;
+        }
+        g->alive = 1;
+        nfac++;
+    }
+    /* product of the remaining scalars (empty scopes) */
+    int dr = 0;
+    prod[0] = u256_from(1);
+    for (int i = 0; i < nfac; i++) {
+        if (!fs[i].alive) continue;
+        if (status == ORC_OK) {
+            int dn = dr + fs[i].deg > nv ? nv : dr + fs[i].deg;
+            poly_mul_into(prod, dr, fs[i].tab, fs[i].deg, tmp, dn);
+            memcpy(prod, tmp, sizeof(u256) * (size_t)(dn + 1));
+            dr = dn;
+        }
+        free(fs[i].tab);
+        free(fs[i].vars);
+    }
+    if (status == ORC_OK) {
+        int d = dr;
+        while (d > 0 && !(prod[d].w[0] | prod[d].w[1] | prod[d].w[2] | prod[d].w[3])) d--;
+        for (int k = 0; k <= nv; k++)
+            for (int l = 0; l < 4; l++) coeffs[4 * k + l] = k <= dr ? prod[k].w[l] : 0;
+        if (degree) *degree = d;
+    }
+    free(prod);
+    free(tmp);
+    free(scope);
+    free(bucket);
+    free(pos);
+    free(fs);
+    free(order);
+    if (status != ORC_OK) return status;
     return g_overflow ? ORC_EOVERFLOW : ORC_OK;
 }
 

@@ -375,3 +375,57 @@ def test_follow_plan_slicing_every_subset_agrees():
         t["sliced"] = list(range(k))
         r = oracle.follow_plan(g, t, "counting_tropical")
         assert r == ref
+
+
+# ---------------------------------------------------- independence polynomial
+# O2 over polynomial-valued tables (Sec. 5.3 GraphPolynomial; Sec. 6.2).
+
+def test_polynomial_petersen_matches_paper():
+    want = GOLD["petersen"]["independence_polynomial"]["value"]
+    r = oracle.eliminate_polynomial(gg.petersen())
+    assert r["poly"] == want and r["degree"] == len(want) - 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 12, 30, 60])
+def test_polynomial_path_and_cycle_closed_forms(n):
+    # paths: c_k = C(n - k + 1, k); cycles (n >= 3): c_k = n / (n - k) * C(n - k, k)
+    p = oracle.eliminate_polynomial(gg.path(n))["poly"]
+    assert p == [math.comb(n - k + 1, k) for k in range((n + 1) // 2 + 1)]
+    if n >= 3:
+        c = oracle.eliminate_polynomial(gg.cycle(n))["poly"]
+        assert c == [1] + [n * math.comb(n - k, k) // (n - k) for k in range(1, n // 2 + 1)]
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 5), (6, 6), (3, 9)])
+def test_polynomial_complete_bipartite_star_complete_empty(a, b):
+    # K_{a,b}: (1+x)^a + (1+x)^b - 1 (independent sets lie on one side)
+    want = [math.comb(a, k) + math.comb(b, k) - (k == 0) for k in range(max(a, b) + 1)]
+    assert oracle.eliminate_polynomial(gg.complete_bipartite(a, b))["poly"] == want
+    assert oracle.eliminate_polynomial(gg.complete(a + b))["poly"] == [1, a + b]
+    assert oracle.eliminate_polynomial(gg.empty(b))["poly"] == [math.comb(b, k) for k in range(b + 1)]
+
+
+def test_polynomial_matches_brute_force_histogram():
+    rng = random.Random(11)
+    for t in range(80):
+        n = rng.randint(1, 16)
+        g = gg.gnp(n, rng.uniform(0.05, 0.7), t) if t % 2 else gg.random_regular(n - n % 2 or 2, 3 if n > 4 else 1, t)
+        bf = oracle.brute_force(g)["poly"]
+        while len(bf) > 1 and bf[-1] == 0:
+            bf.pop()
+        assert oracle.eliminate_polynomial(g)["poly"] == bf, (t, g.nv)
+
+
+def test_polynomial_multiplies_over_disjoint_union_and_agrees_with_other_algebras():
+    g1, g2 = gg.random_regular(14, 3, 1), gg.cycle(9)
+    p1 = oracle.eliminate_polynomial(g1)["poly"]
+    p2 = oracle.eliminate_polynomial(g2)["poly"]
+    prod = [sum(p1[i] * p2[k - i] for i in range(len(p1)) if 0 <= k - i < len(p2)) for k in range(len(p1) + len(p2) - 1)]
+    assert oracle.eliminate_polynomial(gg.disjoint_union(g1, g2))["poly"] == prod
+    for seed in range(3):  # larger graphs: sum = total count, top coefficient = count at the maximum size
+        g = gg.random_regular(50, 3, seed)
+        p = oracle.eliminate_polynomial(g)["poly"]
+        ct = oracle.eliminate(g, "counting_tropical")
+        assert sum(p) == oracle.eliminate(g, "count")["count"]
+        assert (len(p) - 1, p[-1]) == (ct["size"], ct["count"])
+        assert p[1] == g.nv and p[2] == math.comb(g.nv, 2) - g.ne
