@@ -315,6 +315,27 @@ tn_status tn_solve(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn
 tn_status tn_solve_batch(tn_ctx* ctx, int32_t n, const tn_net* const* nets,
                          const tn_plan* const* plans, const tn_solve_opts* opts, tn_result* out);
 
+/* Independence polynomial I(G, x) = sum_k c_k x^k, c_k = the number of
+ * independent sets of size k: the GraphPolynomial property of the Sec. 5
+ * table, computed by the finite-field method of Sec. 6.2.  The network is
+ * contracted with vertex tensors [1, t] for t = 0 .. alpha (alpha = the
+ * largest independent-set size, from one max-plus contraction) modulo primes
+ * below 2^31 whose product exceeds the total count (from one exact-count
+ * contraction), every evaluation one mod-p pass of the persistent launch;
+ * the values are interpolated mod each prime and the coefficients
+ * recombined by CRT, with one more prime as a check.
+ *   limbs   32-bit limbs per coefficient (>= 1)
+ *   coeffs  caller memory of (nv + 1) * limbs uint32: coefficient k, little
+ *           endian, at coeffs[k * limbs]; entries above the degree are 0
+ *   degree  receives alpha (NULL allowed)
+ * Unit weights only; the plan must not be sliced.  Errors: TN_EINVAL
+ * (weighted network, sliced plan, bad arguments), TN_ETOOBIG (nv > 512),
+ * TN_EOVERFLOW (a coefficient needs more than limbs limbs, or the check
+ * prime disagrees), TN_EDEVICE (device failure, or the coefficients do not
+ * sum to the exact count). */
+tn_status tn_solve_polynomial(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t limbs, uint32_t* coeffs,
+                              int32_t* degree);
+
 /* -------------------------------------------------------------- server --- */
 
 /* Continuous-batching server on one context.  Jobs are admitted while the sum

@@ -132,6 +132,7 @@ SIGNATURES = [
     ("tn_solve_opts_default", None, [_P(tn_solve_opts)]),
     ("tn_solve", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_batch", ctypes.c_int, [_VP, ctypes.c_int32, _P(_VP), _P(_VP), _P(tn_solve_opts), _P(tn_result)]),
+    ("tn_solve_polynomial", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_uint32), _P(ctypes.c_int32)]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
     ("tn_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _P(tn_result), c_int32_p, _P(ctypes.c_double)]),
@@ -419,6 +420,14 @@ class Context:
         R = (tn_result * n)()
         _check(lib().tn_solve_batch(self.h, n, NH, PH, O, R))
         return [decode(R[i]) for i in range(n)]
+
+    def solve_polynomial(self, net: Net, plan: Plan) -> List[int]:
+        """Independence polynomial coefficients c_0 .. c_alpha (exact ints)."""
+        limbs = net.nv // 32 + 2
+        buf = (ctypes.c_uint32 * ((net.nv + 1) * limbs))()
+        deg = ctypes.c_int32(0)
+        _check(lib().tn_solve_polynomial(self.h, net.h, plan.h, limbs, buf, ctypes.byref(deg)))
+        return [sum(int(buf[k * limbs + l]) << (32 * l) for l in range(limbs)) for k in range(deg.value + 1)]
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

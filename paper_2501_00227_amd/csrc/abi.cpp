@@ -402,4 +402,18 @@ tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const 
     TN_GUARD_END
 }
 
+tn_status tn_solve_polynomial(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t limbs, uint32_t* coeffs,
+                              int32_t* degree) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p) return fail(TN_EINVAL, "NULL argument");
+    if (p->plan.fingerprint != n->net.fingerprint || p->plan.nv != n->net.nv)
+        return fail(TN_EINVAL, "plan was built for a different network");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    int deg = 0;
+    tn_status st = solve_polynomial(c, n->net, p->plan, limbs, coeffs, &deg);
+    if (degree) *degree = st == TN_OK ? deg : 0;
+    return st;
+    TN_GUARD_END
+}
+
 }  // extern "C"

@@ -59,7 +59,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         int item, pass;
         const Plan* plan;
         int dsr;
-        uint32_t prime;
+        uint32_t prime, xval;
         DevProgram* dp;
         const std::vector<NodeLaunch>* nl;
         int64_t E, Pe;
@@ -90,7 +90,12 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             st.status = fail(TN_EINVAL, "batched jobs must not be sliced; use tn_solve for sliced plans");
             continue;
         }
-        tn_status s = make_passes(*it.net, it.opts, st.passes);
+        tn_status s = TN_OK;
+        st.raw = it.passes != nullptr;
+        if (it.passes)
+            st.passes = *it.passes;
+        else
+            s = make_passes(*it.net, it.opts, st.passes);
         if (s != TN_OK) {
             st.status = s;
             continue;
@@ -110,6 +115,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             jp.plan = it.plan;
             jp.dsr = st.passes[p].dsr;
             jp.prime = st.passes[p].prime;
+            jp.xval = st.passes[p].xval;
             jp.dp = dp;
             jp.nl = dp ? &node_launches(*dp, *it.plan, jp.dsr) : nullptr;
             jp.E = std::max<int64_t>(it.plan->arena_entries_dag, 64);
@@ -156,7 +162,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         J.nleaf = p.nleaf();
         J.nnode = (int)p.nodes.size();
         J.root = J.nnode - 1;
-        J.ap = algebra_params(jp.dsr, jp.prime, items[jp.item].opts.beta);
+        J.ap = algebra_params(jp.dsr, jp.prime, items[jp.item].opts.beta, jp.xval);
         J.arena.p0 = dbase + jp.o_arena0;
         J.arena.p1 = plane_bytes(jp.dsr, 1) ? dbase + jp.o_arena1 : nullptr;
         J.part.p0 = dbase + jp.o_part0;
@@ -426,6 +432,10 @@ tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out) {
     for (size_t i = 0; i < L.items.size(); i++) {
         ItemState& st = L.items[i];
         tn_status s = st.status;
+        if (s == TN_OK && st.raw) {
+            out[i].semiring = -1;
+            continue;
+        }
         if (s == TN_OK) {
             std::vector<std::vector<unsigned char>> accs;
             for (int j : st.job_ids) {
@@ -495,6 +505,39 @@ void batch_cache_drop(tn_ctx* ctx) {
     ctx->batch_cache_key.clear();
 }
 
+// Bump allocation in the context's grow-only scratch; what does not fit is
+// allocated separately (and freed by scratch_regrow, which grows the scratch
+// to the last call's need).
+static DevAllocFn scratch_alloc(tn_ctx* ctx) {
+    DevAllocFn alloc;
+    ctx->batch_dev_used = 0;
+    alloc.alloc = [ctx](size_t n) -> void* {
+        n = (n + 255) & ~(size_t)255;
+        ctx->batch_dev_peak = std::max(ctx->batch_dev_peak, ctx->batch_dev_used + n);
+        if (ctx->batch_dev && ctx->batch_dev_used + n <= ctx->batch_dev_cap) {
+            void* p = (unsigned char*)ctx->batch_dev + ctx->batch_dev_used;
+            ctx->batch_dev_used += n;
+            return p;
+        }
+        ctx->batch_dev_used += n;
+        void* p = dev_alloc(ctx, n);
+        if (p) ctx->batch_overflow.push_back({p, n});
+        return p;
+    };
+    alloc.free = [](void*, size_t) {};
+    return alloc;
+}
+
+static void scratch_regrow(tn_ctx* ctx) {
+    if (ctx->batch_overflow.empty()) return;
+    for (auto& b : ctx->batch_overflow) dev_free(ctx, b.first, b.second);
+    ctx->batch_overflow.clear();
+    if (ctx->batch_dev) dev_free(ctx, ctx->batch_dev, ctx->batch_dev_cap);
+    ctx->batch_dev_cap = ctx->batch_dev_peak + (ctx->batch_dev_peak >> 3);
+    ctx->batch_dev = dev_alloc(ctx, ctx->batch_dev_cap);
+    if (!ctx->batch_dev) ctx->batch_dev_cap = 0;
+}
+
 tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out) {
     auto t0 = std::chrono::steady_clock::now();
     // The same batch again (same networks, plans and options) reuses the last
@@ -512,24 +555,7 @@ tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vect
         return st;
     }
     batch_cache_drop(ctx);  // this call overwrites the scratch the cached launch lives in
-    // bump allocation in the context's grow-only scratch; what does not fit
-    // is allocated separately and the scratch grows for the next call
-    DevAllocFn alloc;
-    ctx->batch_dev_used = 0;
-    alloc.alloc = [ctx](size_t n) -> void* {
-        n = (n + 255) & ~(size_t)255;
-        ctx->batch_dev_peak = std::max(ctx->batch_dev_peak, ctx->batch_dev_used + n);
-        if (ctx->batch_dev && ctx->batch_dev_used + n <= ctx->batch_dev_cap) {
-            void* p = (unsigned char*)ctx->batch_dev + ctx->batch_dev_used;
-            ctx->batch_dev_used += n;
-            return p;
-        }
-        ctx->batch_dev_used += n;
-        void* p = dev_alloc(ctx, n);
-        if (p) ctx->batch_overflow.push_back({p, n});
-        return p;
-    };
-    alloc.free = [](void*, size_t) {};
+    DevAllocFn alloc = scratch_alloc(ctx);
     BatchLaunch L;
     tn_status st = batch_prepare(ctx, items, L, alloc);
     if (st == TN_OK) st = batch_launch(ctx, L, ctx->stream);
@@ -544,17 +570,38 @@ tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vect
     } else {
         batch_release(L);
     }
-    if (!ctx->batch_overflow.empty()) {  // grow the scratch to this call's need
-        for (auto& b : ctx->batch_overflow) dev_free(ctx, b.first, b.second);
-        ctx->batch_overflow.clear();
-        if (ctx->batch_dev) dev_free(ctx, ctx->batch_dev, ctx->batch_dev_cap);
-        ctx->batch_dev_cap = ctx->batch_dev_peak + (ctx->batch_dev_peak >> 3);
-        ctx->batch_dev = dev_alloc(ctx, ctx->batch_dev_cap);
-        if (!ctx->batch_dev) ctx->batch_dev_cap = 0;
-    }
+    scratch_regrow(ctx);
     double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (auto& r : out) r.seconds = sec;
     return st != TN_OK ? st : st2;
+}
+
+tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
+                          std::vector<std::array<unsigned char, 16>>& accs) {
+    std::vector<BatchItem> items(1);
+    items[0].net = &net;
+    items[0].plan = &plan;
+    items[0].opts = tn_solve_opts{};
+    items[0].passes = &passes;
+    batch_cache_drop(ctx);
+    DevAllocFn alloc = scratch_alloc(ctx);
+    BatchLaunch L;
+    tn_status st = batch_prepare(ctx, items, L, alloc);
+    if (st == TN_OK) st = L.items[0].status;
+    if (st == TN_OK) st = batch_launch(ctx, L, ctx->stream);
+    if (st == TN_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(TN_EDEVICE, "batch execution failed");
+    std::vector<tn_result> out;
+    if (st == TN_OK) st = batch_finish(L, out);
+    if (st == TN_OK) {
+        accs.assign(passes.size(), {});
+        const std::vector<int>& ids = L.items[0].job_ids;
+        for (size_t k = 0; k < ids.size() && k < accs.size(); k++)
+            std::memcpy(accs[k].data(), (unsigned char*)L.host + L.o_hacc + 16 * (size_t)ids[k], 16);
+    }
+    if (L.host) (void)hipStreamSynchronize(ctx->stream);
+    batch_release(L);
+    scratch_regrow(ctx);
+    return st;
 }
 
 bool use_persistent(const Plan& p) {

@@ -2,6 +2,7 @@
 // tn_solve (small trees), tn_solve_batch and the server.
 #pragma once
 
+#include <array>
 #include <functional>
 #include <vector>
 
@@ -14,6 +15,9 @@ struct BatchItem {
     const Net* net;
     const Plan* plan;
     tn_solve_opts opts;
+    // explicit passes (their roots are returned raw, not decoded); null: the
+    // passes of opts.semiring
+    const std::vector<PassSpec>* passes = nullptr;
 };
 
 struct ItemState {
@@ -21,6 +25,7 @@ struct ItemState {
     std::vector<PassSpec> passes;
     std::vector<int> job_ids;  // one job per pass
     tn_status status = TN_OK;
+    bool raw = false;          // explicit passes: no decoding
 };
 
 struct DevAllocFn {
@@ -70,6 +75,12 @@ tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out);
 void batch_release(BatchLaunch& L);
 void collect_trace(tn_ctx* ctx, BatchLaunch& L);
 tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out);
+// One synchronous persistent launch of explicit passes of one unsliced
+// network; accs receives the 16-byte root accumulator of every pass, in order.
+tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
+                          std::vector<std::array<unsigned char, 16>>& accs);
+// Independence polynomial (finite-field method); coeffs: (nv + 1) * limbs.
+tn_status solve_polynomial(tn_ctx* ctx, const Net& net, const Plan& plan, int limbs, uint32_t* coeffs, int* degree);
 // Release the launch a synchronous batch keeps for an identical next call.
 void batch_cache_drop(tn_ctx* ctx);
 // Route a single unsliced small tree through the persistent launch.

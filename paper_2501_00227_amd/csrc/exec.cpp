@@ -201,7 +201,7 @@ static uint32_t powmod(uint64_t b, uint64_t e, uint32_t m) {
     return (uint32_t)r;
 }
 
-AlgebraParams algebra_params(int dsr, uint32_t prime, double beta) {
+AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval) {
     AlgebraParams ap;
     ap.beta = beta;
     if (dsr == DSR_MODP) {
@@ -210,6 +210,7 @@ AlgebraParams algebra_params(int dsr, uint32_t prime, double beta) {
         ap.p = prime;
         ap.pinv = (uint32_t)(0u - inv);
         ap.r1 = (uint32_t)((1ull << 32) % prime);
+        ap.xv = (uint32_t)(((uint64_t)(xval % prime) << 32) % prime);
     }
     return ap;
 }
@@ -452,7 +453,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     };
     for (size_t pi = 0; pi < passes.size() && herr == hipSuccess; pi++) {
         const int dsr = passes[pi].dsr;
-        const AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta);
+        const AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta, passes[pi].xval);
         void* acc = base + o_acc + 16 * pi;
         const int eb = plane_bytes(dsr, 0) + plane_bytes(dsr, 1);
         const bool is_z = dsr == DSR_Z_F32 || dsr == DSR_Z_BF16;

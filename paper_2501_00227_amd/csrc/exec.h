@@ -112,9 +112,10 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
 struct PassSpec {
     int dsr;
     uint32_t prime;
+    uint32_t xval = 1;  // mod p: value of x in the vertex tensors [1, x] (1: counting)
 };
 tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes);
-AlgebraParams algebra_params(int dsr, uint32_t prime, double beta);
+AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval = 1);
 // Decode the accumulators of all passes into the result struct.
 tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& passes,
                         const std::vector<std::vector<unsigned char>>& acc, tn_result& res);

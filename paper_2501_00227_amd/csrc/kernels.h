@@ -38,6 +38,7 @@ struct TensorMeta {
 
 struct AlgebraParams {
     uint32_t p = 0, pinv = 0, r1 = 0;  // modulus, -p^{-1} mod 2^32, 2^32 mod p
+    uint32_t xv = 0;                   // mod p: the vertex tensor's x (Montgomery form; 1 = r1 counts)
     double beta = 0;
 };
 

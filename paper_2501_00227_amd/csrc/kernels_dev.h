@@ -106,7 +106,7 @@ struct Alg<DSR_MODP> {  // counting modulo p < 2^31, Montgomery form with R = 2^
         u64 u = (t + (u64)m * ap.p) >> 32;           // < 2p
         return (V)(u >= ap.p ? u - ap.p : u);
     }
-    __device__ static V weight(float, const AlgebraParams& ap) { return ap.r1; }
+    __device__ static V weight(float, const AlgebraParams& ap) { return ap.xv; }
     __device__ static V load(const Planes& p, i64 i) { return ((const unsigned int*)p.p0)[i]; }
     __device__ static void store(const Planes& p, i64 i, V v) { ((unsigned int*)p.p0)[i] = v; }
     __device__ static V prescale(V v, float) { return v; }
