@@ -163,10 +163,10 @@ def independence_polynomial(ctx, net, plan, tc):
     for _ in range(reps):
         p = ctx.solve_polynomial(net, plan)
     dt = (time.perf_counter() - t0) / reps
-    nprimes = 1
-    while 2 ** (30 * nprimes) <= sum(p) * 2:
-        nprimes += 1
-    passes = 6 + (len(p)) * (nprimes + 1)  # first two contractions: 1 + 5 passes
+    # the library's choice: CRT primes (> 2^30 each) until 30 bits per prime
+    # cover the total count's bits + 1 (at least two), plus one check prime
+    nprimes = max(2, -(-(sum(p).bit_length() + 1) // 30)) + 1
+    passes = 6 + len(p) * nprimes  # first two contractions: 1 + 5 passes
     return {"workload": "3-regular n=120 seed 0: independence polynomial, Sec. 6.2 finite-field method",
             "seconds": dt, "degree": len(p) - 1, "evaluation_passes": passes,
             "GOP_per_s": passes * 2.0 ** tc / dt / 1e9, "max_coefficient_bits": max(c.bit_length() for c in p)}
