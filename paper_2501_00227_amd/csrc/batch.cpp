@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <queue>
 
 namespace tn {
 
@@ -40,6 +41,79 @@ int64_t chunk(int64_t ntiles) {  // tiles per task (powers of two divide exactly
     int64_t per = 1;
     while (ntiles / per > kMaxTasksPerNode) per *= 2;
     return per;
+}
+
+// Estimated microseconds one workgroup spends on a task (a rough model: a
+// fixed cost per task, permutes at ~20 GB/s and GEMMs at ~50 G semiring ops/s
+// per workgroup); only the relative order matters.
+double task_cost(const BTask& t, const std::vector<BNode>& bn, const std::vector<int>& subtree) {
+    auto gemm_ops = [&](const BNode& N, double tiles) {
+        return tiles * std::exp2((double)(N.g.tb + N.g.ti + N.g.tj + N.g.lk - N.g.lsplit));
+    };
+    switch (t.kind) {
+    case BT_PERM: {
+        const BNode& N = bn[t.node];
+        const double bytes = (double)t.count * std::exp2((double)N.ptile_bits[t.aux >> 1]) * 8.0;
+        return 3.0 + bytes / 2.0e4;
+    }
+    case BT_GEMM: return 3.0 + gemm_ops(bn[t.node], (double)t.count) / 5.0e4;
+    case BT_REDUCE: return 3.0 + (double)t.count * 0.5;
+    case BT_SUBTREE: {
+        double c = 3.0;
+        for (int k = 0; k < t.aux; k++) {
+            const BNode& N = bn[subtree[t.node + k]];
+            c += 1.0 + gemm_ops(N, std::exp2((double)((N.g.lb - N.g.tb) + (N.g.li - N.g.ti) + (N.g.lj - N.g.tj) +
+                                                      N.g.lsplit))) / 5.0e4;
+        }
+        return c;
+    }
+    default: return 2.0;
+    }
+}
+
+// Rank of every task in a critical-path-first topological order (tasks are
+// created in a topological order: every producer before its consumers).
+std::vector<int> critical_path_order(const std::vector<BTask>& bt, const std::vector<BNode>& bn,
+                                     const std::vector<int>& subtree, int ncounters) {
+    const int n = (int)bt.size();
+    std::vector<double> blevel(n, 0.0), cblevel(ncounters, 0.0);
+    for (int k = n - 1; k >= 0; k--) {  // consumers first
+        const BTask& t = bt[k];
+        blevel[k] = task_cost(t, bn, subtree) + (t.signal >= 0 ? cblevel[t.signal] : 0.0);
+        for (int d : {t.dep0, t.dep1})
+            if (d >= 0) cblevel[d] = std::max(cblevel[d], blevel[k]);
+    }
+    // Kahn's algorithm over counters: a task is ready once each of its
+    // counters has had all its producers emitted
+    std::vector<int> producers_left(ncounters, 0), waiting(n, 0);
+    std::vector<std::vector<int>> waiters(ncounters);
+    for (int k = 0; k < n; k++) {
+        const BTask& t = bt[k];
+        if (t.signal >= 0) producers_left[t.signal]++;
+        for (int d : {t.dep0, t.dep1})
+            if (d >= 0) {
+                waiters[d].push_back(k);
+                waiting[k]++;
+            }
+    }
+    auto cmp = [&](int a, int b) { return blevel[a] != blevel[b] ? blevel[a] < blevel[b] : a > b; };
+    std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
+    for (int k = 0; k < n; k++)
+        if (!waiting[k]) ready.push(k);
+    std::vector<int> rank(n, 0);
+    int next = 0;
+    while (!ready.empty()) {
+        const int k = ready.top();
+        ready.pop();
+        rank[k] = next++;
+        const int c = bt[k].signal;
+        if (c >= 0 && --producers_left[c] == 0)
+            for (int w : waiters[c])
+                if (--waiting[w] == 0) ready.push(w);
+    }
+    for (int k = 0; k < n; k++)  // unreachable with a well-formed table; keep every task in a valid place
+        if (waiting[k]) rank[k] = next++;
+    return rank;
 }
 
 }  // namespace
@@ -323,12 +397,18 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         jq[j] = best;
         qload[best] += job_work[j];
     }
-    // ticket order inside a queue = dependency level order (stable: job / node / tile)
+    // ticket order inside a queue: critical path first.  Every task gets a
+    // rough cost (per-workgroup rates) and its bottom level (its cost plus the
+    // longest chain of dependent tasks after it); tasks are then emitted in a
+    // topological order that always takes the ready task with the largest
+    // bottom level.  Every producer precedes its consumers, so a waiting
+    // workgroup only waits on smaller tickets of its queue.
+    const std::vector<int> rank = critical_path_order(bt, bn, L.subtree_list, ncounters);
     std::vector<int> order(bt.size());
     for (size_t k = 0; k < order.size(); k++) order[k] = (int)k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         int qa = jq[bt[a].job], qb = jq[bt[b].job];
-        return qa != qb ? qa < qb : level[a] < level[b];
+        return qa != qb ? qa < qb : rank[a] < rank[b];
     });
     std::vector<BTask> sorted(bt.size());
     for (size_t k = 0; k < order.size(); k++) sorted[k] = bt[order[k]];
