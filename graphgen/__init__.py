@@ -166,6 +166,29 @@ def square_lattice(L: int) -> Graph:
     return _make(L * L, pairs, f"square{L}")
 
 
+def fullerene() -> Graph:
+    """The C60 buckyball of the Sec. 6.4 example: the 60 vertices of a truncated
+    icosahedron (all cyclic coordinate rotations and sign changes of
+    (0, 1, 3phi), (1, 2 + phi, 2 phi), (phi, 2, 2 phi + 1), phi the golden
+    ratio), joined when at most sqrt(5) apart (its 90 edges, all of length 2)."""
+    import math
+
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    pts = []
+    for base in ((0.0, 1.0, 3 * phi), (1.0, 2 + phi, 2 * phi), (phi, 2.0, 2 * phi + 1)):
+        for r in range(3):
+            a, b, c = base[r % 3], base[(r + 1) % 3], base[(r + 2) % 3]
+            for sa in (1, -1):
+                for sb in (1, -1):
+                    for sc in (1, -1):
+                        q = (sa * a, sb * b, sc * c)
+                        if not any(max(abs(x - y) for x, y in zip(q, o)) < 1e-9 for o in pts):
+                            pts.append(q)
+    edges = [(i, j) for i in range(len(pts)) for j in range(i + 1, len(pts))
+             if math.dist(pts[i], pts[j]) <= math.sqrt(5.0) + 1e-9]
+    return _make(len(pts), edges, "fullerene")
+
+
 def kings_subgraph(L: int, p: float, seed: int) -> Graph:
     """King's subgraph: keep each site of an L x L grid with probability p.
 

@@ -61,11 +61,16 @@ def _load():
         lib.orc_eliminate.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                       ctypes.c_double, ctypes.c_int, f64p, u64p, f64p, f64p, ip]
         lib.orc_eliminate_poly.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int, u64p, ip, ip]
+        lib.orc_eliminate_sg.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_int, f64p, u64p, f64p, f64p, ip]
+        lib.orc_brute_force_sg.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, f64p, f64p,
+                                           u64p, f64p, f64p]
         lib.orc_follow_plan.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, i32p, i32p,
                                         i32p, i32p, i32p, i32p, ctypes.c_int, i32p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int, f64p, u64p, f64p, f64p]
-        for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_eliminate_poly, lib.orc_follow_plan):
+        for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_eliminate_poly, lib.orc_eliminate_sg,
+                  lib.orc_brute_force_sg, lib.orc_follow_plan):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -165,6 +170,54 @@ def eliminate_polynomial(graph, max_width: int = 16) -> Dict:
         raise OracleError(rc, f"eliminate_polynomial(width={width.value})")
     poly = [_limbs_to_int(coeffs[4 * k: 4 * k + 4]) for k in range(degree.value + 1)]
     return {"poly": poly, "degree": degree.value, "width": width.value}
+
+
+def _sg_arrays(graph, J, h):
+    Ja = None if J is None else np.ascontiguousarray(J, dtype=np.float64)
+    ha = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+    return Ja, ha
+
+
+def spin_glass_brute_force(graph, J=None, h=None, betas: Sequence[float] = ()) -> Dict:
+    """O1 for the spin glass H = sum_(u,v) J_uv s_u s_v + sum_v h_v s_v, s = +-1
+    (J per edge in edge order, default 1; h per vertex, default 0); n <= 24."""
+    lib = _load()
+    edges, _ = _graph_arrays(graph)
+    Ja, ha = _sg_arrays(graph, J, h)
+    nb = len(betas)
+    b = np.ascontiguousarray(betas, dtype=np.float64) if nb else np.zeros(1)
+    emin = np.zeros(1)
+    cnt = np.zeros(1, np.uint64)
+    z, lz = np.zeros(max(nb, 1)), np.zeros(max(nb, 1))
+    rc = lib.orc_brute_force_sg(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(Ja, ctypes.c_double),
+                                _ptr(ha, ctypes.c_double), nb, _ptr(b, ctypes.c_double), _ptr(emin, ctypes.c_double),
+                                _ptr(cnt, ctypes.c_uint64), _ptr(z, ctypes.c_double), _ptr(lz, ctypes.c_double))
+    if rc != ORC_OK:
+        raise OracleError(rc, "spin_glass_brute_force")
+    return {"energy_min": float(emin[0]), "count_min": int(cnt[0]), "z": [float(x) for x in z[:nb]],
+            "log_z": [float(x) for x in lz[:nb]]}
+
+
+def spin_glass_eliminate(graph, semiring: str, J=None, h=None, beta: float = 0.0, max_width: int = 26) -> Dict:
+    """O2 for the spin glass.  tropical / counting_tropical maximise -H:
+    "size" is -min H and "count" the number of ground states; "partition"
+    gives Z(beta) = sum exp(-beta H); "count" gives 2^n."""
+    lib = _load()
+    sr = SEMIRINGS[semiring]
+    edges, _ = _graph_arrays(graph)
+    Ja, ha = _sg_arrays(graph, J, h)
+    size, z, lz = np.zeros(1), np.zeros(1), np.zeros(1)
+    limbs = np.zeros(4, np.uint64)
+    width = ctypes.c_int(0)
+    rc = lib.orc_eliminate_sg(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(Ja, ctypes.c_double),
+                              _ptr(ha, ctypes.c_double), sr, float(beta), int(max_width), _ptr(size, ctypes.c_double),
+                              _ptr(limbs, ctypes.c_uint64), _ptr(z, ctypes.c_double), _ptr(lz, ctypes.c_double),
+                              ctypes.byref(width))
+    if rc != ORC_OK:
+        raise OracleError(rc, f"spin_glass_eliminate(width={width.value})")
+    out = _result(sr, size, limbs, z, lz)
+    out["width"] = width.value
+    return out
 
 
 def follow_plan(graph, tree: Dict, semiring: str, beta: float = 0.0, max_rank: int = 26,

@@ -22,6 +22,8 @@
  *                         over dense factor tables in exact semiring arithmetic;
  *       orc_eliminate_poly  the same over polynomial-valued tables: the
  *                         independence polynomial (Sec. 5.3 GraphPolynomial)
+ *       orc_eliminate_sg, orc_brute_force_sg  the spin glass of Sec. 2
+ *                         (energy H = sum J s s + sum h s, Sec. 6.4 buckyball)
  *   O3  orc_follow_plan   evaluate a given binary contraction tree (Sec. 4.1),
  *                         one literal einsum loop per node, with optional
  *                         sliced indices (Sec. 4.2, TreeSA slicing)
@@ -426,9 +428,9 @@ static int cmp_int(const void* a, const void* b) {
  * sr (beta used by SR_PARTITION only).  max_width bounds the largest
  * intermediate scope (the table has 2^(width+1) entries while being built).
  */
-int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr, double beta,
-                  int max_width, double* size, uint64_t* limbs, double* zval, double* logz,
-                  int* width_out) {
+static int eliminate_impl(int nv, int ne, const int32_t* edges, const double* w, const double* J,
+                          const double* hf, int model, int sr, double beta, int max_width, double* size,
+                          uint64_t* limbs, double* zval, double* logz, int* width_out) {
     if (nv < 0 || ne < 0 || sr < 0 || sr > 3) return ORC_EINVAL;
     for (int e = 0; e < ne; e++) {
         int u = edges[2 * e], v = edges[2 * e + 1];
@@ -464,7 +466,14 @@ int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr,
         f->vars[0] = u < v ? u : v;
         f->vars[1] = u < v ? v : u;
         f->tab = malloc(4 * sizeof(elem));
-        for (int a = 0; a < 4; a++) f->tab[a] = e_edge(sr, a & 1, (a >> 1) & 1);
+        for (int a = 0; a < 4; a++) {
+            if (model == 0) {
+                f->tab[a] = e_edge(sr, a & 1, (a >> 1) & 1);
+            } else { /* spin glass: x^(-J s_u s_v), s = 2n - 1 */
+                int su = 2 * (a & 1) - 1, sv = 2 * ((a >> 1) & 1) - 1;
+                f->tab[a] = e_weight(sr, -(J ? J[e] : 1.0) * su * sv, beta);
+            }
+        }
         f->alive = 1;
     }
     for (int v = 0; v < nv; v++) { /* vertex tensors */
@@ -473,7 +482,9 @@ int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr,
         f->vars = malloc(sizeof(int));
         f->vars[0] = v;
         f->tab = malloc(2 * sizeof(elem));
-        for (int a = 0; a < 2; a++) f->tab[a] = e_vertex(sr, a, w ? w[v] : 1.0, beta);
+        for (int a = 0; a < 2; a++) /* spin glass: x^(-h s_v) */
+            f->tab[a] = model == 0 ? e_vertex(sr, a, w ? w[v] : 1.0, beta)
+                                   : e_weight(sr, -(hf ? hf[v] : 0.0) * (2 * a - 1), beta);
         f->alive = 1;
     }
     int status = ORC_OK;
@@ -536,6 +547,68 @@ int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr,
     if (status != ORC_OK) return status;
     put_result(sr, root, size, limbs, zval, logz);
     return g_overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+int orc_eliminate(int nv, int ne, const int32_t* edges, const double* w, int sr, double beta,
+                  int max_width, double* size, uint64_t* limbs, double* zval, double* logz,
+                  int* width_out) {
+    return eliminate_impl(nv, ne, edges, w, NULL, NULL, 0, sr, beta, max_width, size, limbs, zval, logz,
+                          width_out);
+}
+
+/*
+ * O2 for the spin glass of Sec. 2 (H(sigma) = sum_(i,j) J_ij s_i s_j +
+ * sum_i h_i s_i, s in {-1, 1}; index value n = (s + 1) / 2): edge tensors
+ * x^(-J s_u s_v), vertex tensors x^(-h s).  The tropical algebras maximise
+ * -H (size = -min H, count = number of ground states); the real algebra gives
+ * Z(beta) = sum_sigma e^(-beta H).  J, h may be NULL (all 1 / all 0).
+ */
+int orc_eliminate_sg(int nv, int ne, const int32_t* edges, const double* J, const double* h, int sr,
+                     double beta, int max_width, double* size, uint64_t* limbs, double* zval, double* logz,
+                     int* width_out) {
+    return eliminate_impl(nv, ne, edges, NULL, J, h, 1, sr, beta, max_width, size, limbs, zval, logz,
+                          width_out);
+}
+
+/* O1 for the spin glass: every configuration s in {-1,1}^n (bit v of the mask
+ * is n_v, s_v = 2 n_v - 1); the minimum energy, its multiplicity and
+ * Z(beta) = sum e^(-beta H) for each beta (Kahan sums). */
+int orc_brute_force_sg(int nv, int ne, const int32_t* edges, const double* J, const double* h, int nbeta,
+                       const double* betas, double* emin, uint64_t* count_min, double* z, double* logz) {
+    if (nv < 0 || nv > 30 || ne < 0 || nbeta < 0 || nbeta > 64) return ORC_EINVAL;
+    for (int e = 0; e < ne; e++) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= nv || v >= nv || u == v) return ORC_EINVAL;
+    }
+    long double best = INFINITY, zs[64], zc[64];
+    uint64_t nbest = 0;
+    for (int b = 0; b < nbeta; b++) zs[b] = zc[b] = 0.0L;
+    for (uint64_t m = 0; m < (1ull << nv); m++) {
+        long double H = 0.0L;
+        for (int e = 0; e < ne; e++) {
+            int su = (int)((m >> edges[2 * e]) & 1) * 2 - 1, sv = (int)((m >> edges[2 * e + 1]) & 1) * 2 - 1;
+            H += (long double)(J ? J[e] : 1.0) * su * sv;
+        }
+        for (int v = 0; v < nv; v++) H += (long double)(h ? h[v] : 0.0) * (int)(((m >> v) & 1) * 2 - 1);
+        if (H < best) {
+            best = H;
+            nbest = 0;
+        }
+        if (H == best) nbest++;
+        for (int b = 0; b < nbeta; b++) {
+            long double term = expl(-(long double)betas[b] * H) - zc[b];
+            long double t = zs[b] + term;
+            zc[b] = (t - zs[b]) - term;
+            zs[b] = t;
+        }
+    }
+    if (emin) *emin = (double)best;
+    if (count_min) *count_min = nbest;
+    for (int b = 0; b < nbeta; b++) {
+        if (z) z[b] = (double)zs[b];
+        if (logz) logz[b] = (double)logl(zs[b]);
+    }
+    return ORC_OK;
 }
 
 /* --------------------------------------------------- O2 over polynomials --- */

@@ -429,3 +429,73 @@ def test_polynomial_multiplies_over_disjoint_union_and_agrees_with_other_algebra
         assert sum(p) == oracle.eliminate(g, "count")["count"]
         assert (len(p) - 1, p[-1]) == (ct["size"], ct["count"])
         assert p[1] == g.nv and p[2] == math.comb(g.nv, 2) - g.ne
+
+
+# ---------------------------------------------------------------- spin glass
+# H(s) = sum_(u,v) J_uv s_u s_v + sum_v h_v s_v, s = +-1 (Sec. 2); the
+# tropical algebras maximise -H (Sec. 6.4 CountingMin).
+
+def test_spin_glass_fullerene_matches_paper():
+    g = gg.fullerene()
+    fp = GOLD["fullerene"]
+    assert [g.nv, g.ne] == fp["size"]["value"]
+    lz = oracle.spin_glass_eliminate(g, "partition", beta=1.0)["log_z"]
+    assert abs(lz / g.nv - fp["log_z_per_vertex_beta1"]["value"]) <= 1e-14
+    ct = oracle.spin_glass_eliminate(g, "counting_tropical")
+    assert [-ct["size"], ct["count"]] == fp["counting_min"]["value"]
+
+
+def test_spin_glass_petersen_printed_energy_and_brute_force():
+    g = gg.petersen()
+    spins = GOLD["petersen"]["spin_glass_energy"]["value"]["spins"]
+    # the energy of one configuration: a field-free spin glass on the graph
+    # with each vertex's spin pinned by a huge field, minus the pinning
+    big = 1000.0
+    h = [-big * s for s in spins]
+    bf = oracle.spin_glass_brute_force(g, h=h)
+    assert bf["count_min"] == 1
+    assert bf["energy_min"] + big * len(spins) == GOLD["petersen"]["spin_glass_energy"]["value"]["energy"]
+
+
+@pytest.mark.parametrize("n", [2, 5, 8, 13])
+def test_ising_chain_and_ring_closed_forms(n):
+    for beta in (0.3, 1.0):
+        c, s = 2 * math.cosh(beta), 2 * math.sinh(beta)
+        zp = oracle.spin_glass_eliminate(gg.path(n), "partition", beta=beta)["z"]
+        assert abs(zp - 2 * c ** (n - 1)) <= 1e-12 * zp
+        if n >= 3:
+            zr = oracle.spin_glass_eliminate(gg.cycle(n), "partition", beta=beta)["z"]
+            # transfer matrix [[e^-b, e^b], [e^b, e^-b]]: eigenvalues 2 cosh b, -2 sinh b
+            assert abs(zr - (c ** n + (-s) ** n)) <= 1e-12 * zr
+    if n >= 3:  # antiferromagnetic ring: frustrated when n is odd
+        ct = oracle.spin_glass_eliminate(gg.cycle(n), "counting_tropical")
+        assert (-ct["size"], ct["count"]) == ((-(n - 2), 2 * n) if n % 2 else (-n, 2))
+    fm = oracle.spin_glass_eliminate(gg.path(n), "counting_tropical", J=[-1.0] * (n - 1))  # ferromagnet
+    assert (-fm["size"], fm["count"]) == (-(n - 1), 2)
+
+
+def test_spin_glass_fields_only_and_counts():
+    g = gg.empty(7)
+    h = [0.5, -1.0, 0.0, 2.0, 0.0, -0.25, 1.5]
+    z = oracle.spin_glass_eliminate(g, "partition", h=h, beta=0.7)["z"]
+    assert abs(z - math.prod(2 * math.cosh(0.7 * x) for x in h)) <= 1e-12 * z
+    ct = oracle.spin_glass_eliminate(g, "counting_tropical", h=h)
+    assert (ct["size"], ct["count"]) == (sum(abs(x) for x in h), 4)
+    g2 = gg.random_regular(30, 3, 2)
+    assert oracle.spin_glass_eliminate(g2, "count")["count"] == 2 ** 30
+    assert abs(oracle.spin_glass_eliminate(g2, "partition", beta=0.0)["z"] - 2.0 ** 30) <= 1e-6
+
+
+def test_spin_glass_elimination_matches_brute_force():
+    rng = random.Random(5)
+    for t in range(60):
+        n = rng.randint(1, 14)
+        g = gg.gnp(n, rng.uniform(0.1, 0.8), 100 + t)
+        J = [float(rng.randint(-2, 2)) for _ in range(g.ne)]
+        h = [float(rng.randint(-1, 1)) for _ in range(n)] if t % 2 else None
+        bf = oracle.spin_glass_brute_force(g, J, h, betas=[0.4])
+        ct = oracle.spin_glass_eliminate(g, "counting_tropical", J=J, h=h)
+        assert (-ct["size"], ct["count"]) == (bf["energy_min"], bf["count_min"]), t
+        z = oracle.spin_glass_eliminate(g, "partition", J=J, h=h, beta=0.4)["z"]
+        assert abs(z - bf["z"][0]) <= 1e-12 * bf["z"][0], t
+        assert oracle.spin_glass_eliminate(g, "tropical", J=J, h=h)["size"] == -bf["energy_min"]
