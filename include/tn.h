@@ -158,6 +158,22 @@ tn_status tn_ctx_task_trace(tn_ctx* ctx, tn_task_record* recs, int32_t cap, int3
  * range, non-finite weights, nv > 4096. */
 tn_status tn_net_independent_set(int32_t nv, int32_t ne, const int32_t* edges,
                                  const float* weights, tn_net** out);
+
+/* Spin-glass network of a graph (Sec. 2: H(s) = sum_(u,v) J_uv s_u s_v +
+ * sum_v h_v s_v, s_v in {-1, 1}; index value n_v = (s_v + 1) / 2): an edge
+ * tensor x^(-J_uv s_u s_v) per edge and a vertex tensor x^(-h_v s_v) per
+ * vertex.  Every algebra then solves for -H: the tropical ones give
+ * max(-H) = -(ground-state energy), counting tropical also the ground-state
+ * degeneracy (CountingMin of the Sec. 6.4 buckyball example), the real one
+ * Z(beta) = sum_s e^(-beta H), exact counting 2^nv.
+ *   J  ne floats in edge order (NULL: all 1, antiferromagnetic unit
+ *      coupling); duplicate edges add their couplings
+ *   h  nv floats (NULL: all 0)
+ * Tropical int32 and counting tropical need integer J and h.  The
+ * independence polynomial is not defined for it (TN_EINVAL).  Errors as
+ * tn_net_independent_set, plus non-finite J or h. */
+tn_status tn_net_spin_glass(int32_t nv, int32_t ne, const int32_t* edges, const float* J, const float* h,
+                            tn_net** out);
 void tn_net_destroy(tn_net* net);
 /* Sizes after de-duplication. */
 tn_status tn_net_info(const tn_net* net, int32_t* nv, int32_t* ne);

@@ -117,6 +117,8 @@ SIGNATURES = [
     ("tn_ctx_synchronize", ctypes.c_int, [_VP]),
     ("tn_ctx_task_trace", ctypes.c_int, [_VP, _P(tn_task_record), ctypes.c_int32, c_int32_p, ctypes.c_int]),
     ("tn_net_independent_set", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, c_int32_p, _P(ctypes.c_float), _P(_VP)]),
+    ("tn_net_spin_glass", ctypes.c_int,
+     [ctypes.c_int32, ctypes.c_int32, c_int32_p, _P(ctypes.c_float), _P(ctypes.c_float), _P(_VP)]),
     ("tn_net_destroy", None, [_VP]),
     ("tn_net_info", ctypes.c_int, [_VP, c_int32_p, c_int32_p]),
     ("tn_plan_opts_default", None, [_P(tn_plan_opts)]),
@@ -198,6 +200,25 @@ class Net:
     @classmethod
     def from_graph(cls, g) -> "Net":
         return cls(g.nv, g.edges, g.weights)
+
+    @classmethod
+    def spin_glass(cls, g, J=None, h=None) -> "Net":
+        """Spin glass H = sum J_uv s_u s_v + sum h_v s_v on graph g (J per edge,
+        default 1; h per vertex, default 0).  Tropical results are -H's maximum
+        (minus the ground-state energy)."""
+        self = cls.__new__(cls)
+        e = _i32(np.asarray(g.edges).reshape(-1, 2)).reshape(-1)
+        self._J = None if J is None else np.ascontiguousarray(J, dtype=np.float32)
+        self._h = None if h is None else np.ascontiguousarray(h, dtype=np.float32)
+        self._w = None
+        hdl = ctypes.c_void_p()
+        fp = _P(ctypes.c_float)
+        _check(lib().tn_net_spin_glass(int(g.nv), int(e.size // 2), _p32(e) if e.size else None,
+                                       None if self._J is None else self._J.ctypes.data_as(fp),
+                                       None if self._h is None else self._h.ctypes.data_as(fp), ctypes.byref(hdl)))
+        self.h = hdl
+        self.nv = int(g.nv)
+        return self
 
     def flat_complexity(self):
         tc, sc, rw = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -132,6 +132,23 @@ tn_status tn_ctx_task_trace(tn_ctx* c, tn_task_record* recs, int32_t cap, int32_
     TN_GUARD_END
 }
 
+tn_status tn_net_spin_glass(int32_t nv, int32_t ne, const int32_t* edges, const float* J, const float* h,
+                            tn_net** out) {
+    TN_GUARD_BEGIN
+    if (!out) return fail(TN_EINVAL, "out is NULL");
+    *out = nullptr;
+    auto* n = new tn_net();
+    tn_status st = make_spin_glass(nv, ne, edges, J, h, n->net);
+    if (st != TN_OK) {
+        delete n;
+        return st;
+    }
+    n->net.uid = g_net_uid.fetch_add(1);
+    *out = n;
+    return TN_OK;
+    TN_GUARD_END
+}
+
 tn_status tn_net_independent_set(int32_t nv, int32_t ne, const int32_t* edges, const float* weights,
                                  tn_net** out) {
     TN_GUARD_BEGIN

@@ -114,7 +114,9 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
         LeafDev& d = leaves[l];
         d.u = lp.u;
         d.v = lp.has_edge ? lp.v : -1;
-        d.flags = (lp.has_edge ? 1 : 0) | (lp.wu ? 2 : 0) | (lp.wv ? 4 : 0);
+        d.flags = (lp.has_edge ? 1 : 0) | (lp.wu ? 2 : 0) | (lp.wv ? 4 : 0) | (p.kind == 1 ? 8 : 0);
+        d.jidx = (p.kind == 1 && lp.has_edge) ? p.nv + lp.edge : -1;
+        d.pad = 0;
         d.rank = lp.rank;
         d.var0 = lp.var[0];
         d.var1 = lp.var[1];
@@ -422,7 +424,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     size_t o_p1 = align256(o_p0 + (size_t)Pe * pb0);
     size_t o_meta = align256(o_p1 + (size_t)Pe * pb1);
     size_t o_w = align256(o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
-    size_t o_acc = align256(o_w + sizeof(float) * (size_t)std::max(net.nv, 1));
+    size_t o_acc = align256(o_w + sizeof(float) * std::max<size_t>(net.w.size(), 1));
     need = align256(o_acc + 16 * passes.size());
     unsigned char* base = (unsigned char*)dev_alloc(ctx, need);
     if (!base) return fail(TN_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");

@@ -45,7 +45,9 @@ struct AlgebraParams {
 // Leaf descriptor on the device (one per leaf tensor, rank <= 2).
 struct LeafDev {
     int u, v;          // edge ends (u < v) or u = vertex of a vertex-only leaf, v = -1
-    int flags;         // 1: edge factor, 2: W_u, 4: W_v
+    int flags;         // 1: edge factor, 2: W_u, 4: W_v, 8: spin-glass factors
+    int jidx;          // spin glass: index of the edge's coupling in the weight array (-1: none)
+    int pad;
     int rank;          // unsliced output indices
     int var0, var1;    // vertex at bit 0 / bit 1
     long long off;     // arena offset (entries)

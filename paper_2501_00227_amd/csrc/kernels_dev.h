@@ -214,9 +214,15 @@ __device__ void leaf_one(const LeafDev& d, int leaf_id, const float* w, const in
             if (fv >= 0 && nv != fv) continue;
             if (d.v < 0 && nv) continue;
             V prod = A::one(ap);
-            if ((d.flags & 1) && nu && nv) prod = A::zero(ap);
-            if ((d.flags & 2) && nu) prod = A::mul(prod, A::weight(w ? w[d.u] : 1.0f, ap), ap);
-            if ((d.flags & 4) && nv) prod = A::mul(prod, A::weight(w ? w[d.v] : 1.0f, ap), ap);
+            if (d.flags & 8) {  // spin glass: x^(-J s_u s_v), x^(-h s), s = 2n - 1
+                if (d.flags & 1) prod = A::weight(nu == nv ? -w[d.jidx] : w[d.jidx], ap);
+                if (d.flags & 2) prod = A::mul(prod, A::weight(nu ? -w[d.u] : w[d.u], ap), ap);
+                if (d.flags & 4) prod = A::mul(prod, A::weight(nv ? -w[d.v] : w[d.v], ap), ap);
+            } else {  // independent set: B = [[1, 1], [1, 0]], W = [1, x^w]
+                if ((d.flags & 1) && nu && nv) prod = A::zero(ap);
+                if ((d.flags & 2) && nu) prod = A::mul(prod, A::weight(w ? w[d.u] : 1.0f, ap), ap);
+                if ((d.flags & 4) && nv) prod = A::mul(prod, A::weight(w ? w[d.v] : 1.0f, ap), ap);
+            }
             acc = A::add(acc, prod, ap);
         }
         A::store(arena, d.off + e, acc);
@@ -240,9 +246,17 @@ __device__ inline void leaf_one_z(const LeafDev& d, int leaf_id, const float* w,
             if (fv >= 0 && nv != fv) continue;
             if (d.v < 0 && nv) continue;
             double prod = 1.0;
-            if ((d.flags & 1) && nu && nv) prod = 0.0;
-            if ((d.flags & 2) && nu) prod *= exp(ap.beta * (double)(w ? w[d.u] : 1.0f));
-            if ((d.flags & 4) && nv) prod *= exp(ap.beta * (double)(w ? w[d.v] : 1.0f));
+            if (d.flags & 8) {  // spin glass: e^(-beta J s_u s_v), e^(-beta h s)
+                double ex = 0.0;
+                if (d.flags & 1) ex += nu == nv ? -(double)w[d.jidx] : (double)w[d.jidx];
+                if (d.flags & 2) ex += nu ? -(double)w[d.u] : (double)w[d.u];
+                if (d.flags & 4) ex += nv ? -(double)w[d.v] : (double)w[d.v];
+                prod = exp(ap.beta * ex);
+            } else {
+                if ((d.flags & 1) && nu && nv) prod = 0.0;
+                if ((d.flags & 2) && nu) prod *= exp(ap.beta * (double)(w ? w[d.u] : 1.0f));
+                if ((d.flags & 4) && nv) prod *= exp(ap.beta * (double)(w ? w[d.v] : 1.0f));
+            }
             acc += prod;
         }
         val[e] = acc;

@@ -64,6 +64,31 @@ tn_status make_net(int nv, int ne, const int32_t* edges, const float* weights, N
     return TN_OK;
 }
 
+tn_status make_spin_glass(int nv, int ne, const int32_t* edges, const float* J, const float* h, Net& out) {
+    tn_status st = make_net(nv, ne, edges, nullptr, out);
+    if (st != TN_OK) return st;
+    out.kind = 1;
+    out.w.assign((size_t)nv + out.edges.size(), 0.0f);
+    for (int v = 0; v < nv; v++) out.w[v] = h ? h[v] : 0.0f;
+    std::vector<std::array<int, 2>> sorted = out.edges;  // kept edge id of every input edge
+    std::vector<int> id(sorted.size());
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t k = 0; k < out.edges.size(); k++)
+        id[(size_t)(std::lower_bound(sorted.begin(), sorted.end(), out.edges[k]) - sorted.begin())] = (int)k;
+    for (int e = 0; e < ne; e++) {
+        std::array<int, 2> key{std::min(edges[2 * e], edges[2 * e + 1]), std::max(edges[2 * e], edges[2 * e + 1])};
+        int k = id[(size_t)(std::lower_bound(sorted.begin(), sorted.end(), key) - sorted.begin())];
+        out.w[(size_t)nv + k] += J ? J[e] : 1.0f;
+    }
+    out.integer_weights = true;
+    for (float x : out.w) {
+        if (!std::isfinite(x)) return fail(TN_EINVAL, "non-finite coupling or field");
+        if (x != std::nearbyint(x) || std::fabs(x) > 65536.0f) out.integer_weights = false;
+    }
+    out.fingerprint = out.fingerprint * 1099511628211ull ^ 0x5397u;  // a spin glass differs from an IS network
+    return TN_OK;
+}
+
 std::vector<Leaf> make_leaves(const Net& net, bool absorb) {
     std::vector<Leaf> leaves;
     std::vector<int> first(net.nv, -1);

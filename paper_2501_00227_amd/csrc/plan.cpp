@@ -263,6 +263,7 @@ tn_status plan_program(Plan& p) {
         for (int f : p.leaves[l].factors) {
             if (f >= 0) {
                 lp.has_edge = 1;
+                lp.edge = f;
                 lp.u = p.edges[f][0];
                 lp.v = p.edges[f][1];
             }
@@ -451,6 +452,7 @@ tn_status plan_create(const Net& net, const PlanOptions& o, Plan& out) {
     out.nv = net.nv;
     out.edges = net.edges;
     out.fingerprint = net.fingerprint;
+    out.kind = net.kind;
     out.leaves = make_leaves(net, o.absorb);
     if (out.leaves.empty()) {  // nv = 0: the empty network, result is the identity
         return TN_OK;
@@ -471,6 +473,7 @@ tn_status plan_from_tree(const Net& net, const std::vector<Leaf>& leaves0, const
     out.nv = net.nv;
     out.edges = net.edges;
     out.fingerprint = net.fingerprint;
+    out.kind = net.kind;
     out.leaves = leaves0;
     for (auto& l : out.leaves) {
         l.scope.clear();

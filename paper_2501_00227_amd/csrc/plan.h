@@ -19,9 +19,15 @@ struct Net {
     bool integer_weights = true;            // every weight is an exact integer
     uint64_t fingerprint = 0;
     uint64_t uid = 0;  // unique per created network (cache keys)
+    // 0: independent set (w = vertex weights, or empty for unit weights);
+    // 1: spin glass H = sum J s_u s_v + sum h s_v (w = h[nv] then J[edges])
+    int kind = 0;
 };
 
 tn_status make_net(int nv, int ne, const int32_t* edges, const float* weights, Net& out);
+// Spin glass on the graph: J per input edge (NULL: all 1; duplicates add up),
+// h per vertex (NULL: all 0).
+tn_status make_spin_glass(int nv, int ne, const int32_t* edges, const float* J, const float* h, Net& out);
 
 // One leaf tensor: the product of some edge / vertex factors of the network.
 struct Leaf {
@@ -60,6 +66,7 @@ struct NodeProg {
 struct LeafProg {
     int u = -1, v = -1;     // the leaf's edge (u < v) or u = the vertex of a vertex-only leaf
     int has_edge = 0;
+    int edge = -1;          // the edge factor's edge id
     int wu = 0, wv = 0;     // vertex factors of u / v folded into this leaf
     int rank = 0;           // unsliced output indices
     int var[2] = {-1, -1};  // vertex at bit 0 / bit 1 of the leaf tensor
@@ -71,6 +78,7 @@ struct Plan {
     int nv = 0;
     std::vector<std::array<int, 2>> edges;
     uint64_t fingerprint = 0;
+    int kind = 0;  // the network kind (Net::kind)
     // tree
     std::vector<Leaf> leaves;
     std::vector<Node> nodes;

@@ -98,6 +98,7 @@ std::vector<uint32_t> interpolate(const std::vector<uint32_t>& y, uint32_t p) {
 
 tn_status solve_polynomial(tn_ctx* ctx, const Net& net, const Plan& plan, int limbs, uint32_t* coeffs, int* degree) {
     if (limbs < 1 || !coeffs) return fail(TN_EINVAL, "coeffs and limbs >= 1 are required");
+    if (net.kind != 0) return fail(TN_EINVAL, "the independence polynomial needs an independent-set network");
     for (float w : net.w)
         if (w != 1.0f) return fail(TN_EINVAL, "the independence polynomial needs unit weights");
     if (!plan.sliced.empty()) return fail(TN_EINVAL, "the independence polynomial needs an unsliced plan");

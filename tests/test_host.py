@@ -158,3 +158,19 @@ def test_peak_bytes_scale_with_element_size():
     bct = plan.peak_bytes("counting_tropical")
     assert bct > 2.5 * b32 - 20000
     assert plan.info()["arena_entries"] * 4 <= b32
+
+
+def test_spin_glass_network_validation_and_structure():
+    g = gg.fullerene()
+    assert (g.nv, g.ne) == (60, 90)
+    with pytest.raises(tn.TnError) as ei:
+        tn.Net.spin_glass(g, J=[float("nan")] + [1.0] * (g.ne - 1))
+    assert ei.value.code == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as ei:
+        tn.Net.spin_glass(g, h=[float("inf")] * g.nv)
+    assert ei.value.code == tn.TN_EINVAL
+    sg, isn = tn.Net.spin_glass(g), tn.Net.from_graph(g)
+    # same structure, same planner result; the plans are not interchangeable
+    a = tn.Plan.create(sg, seed=3).complexity()
+    b = tn.Plan.create(isn, seed=3).complexity()
+    assert a == b
