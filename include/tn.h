@@ -352,6 +352,20 @@ tn_status tn_solve_batch(tn_ctx* ctx, int32_t n, const tn_net* const* nets,
 tn_status tn_solve_polynomial(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t limbs, uint32_t* coeffs,
                               int32_t* degree);
 
+/* The k largest independent-set sizes and their counts (SizeMax(k) and
+ * CountingMax(k) of the Sec. 5 table, Sec. 5.3 examples), for unit weights:
+ * both are read off the independence polynomial (tn_solve_polynomial).
+ *   sizes   k int32: the k largest sizes of independent sets, with
+ *           multiplicity, largest first (SizeMax(k); fewer than k sets:
+ *           the rest is INT32_MIN)
+ *   counts  k * limbs uint32 (NULL allowed): the numbers of independent sets
+ *           of sizes alpha, alpha - 1, ..., alpha - k + 1 (CountingMax(k),
+ *           the coefficients of the k highest orders; 0 below size 0)
+ *   k       1 .. 64
+ * Errors as tn_solve_polynomial. */
+tn_status tn_solve_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t* sizes,
+                         int32_t limbs, uint32_t* counts);
+
 /* -------------------------------------------------------------- server --- */
 
 /* Continuous-batching server on one context.  Jobs are admitted while the sum

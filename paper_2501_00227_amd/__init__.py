@@ -135,6 +135,8 @@ SIGNATURES = [
     ("tn_solve", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_batch", ctypes.c_int, [_VP, ctypes.c_int32, _P(_VP), _P(_VP), _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_polynomial", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_uint32), _P(ctypes.c_int32)]),
+    ("tn_solve_max_k", ctypes.c_int,
+     [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_uint32)]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
     ("tn_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _P(tn_result), c_int32_p, _P(ctypes.c_double)]),
@@ -449,6 +451,19 @@ class Context:
         deg = ctypes.c_int32(0)
         _check(lib().tn_solve_polynomial(self.h, net.h, plan.h, limbs, buf, ctypes.byref(deg)))
         return [sum(int(buf[k * limbs + l]) << (32 * l) for l in range(limbs)) for k in range(deg.value + 1)]
+
+    def solve_max_k(self, net: Net, plan: Plan, k: int) -> Dict:
+        """SizeMax(k) (the k largest sizes, with multiplicity) and CountingMax(k)
+        ({size: count} for the k largest sizes), unit weights."""
+        limbs = net.nv // 32 + 2
+        sizes = (ctypes.c_int32 * k)()
+        counts = (ctypes.c_uint32 * (k * limbs))()
+        _check(lib().tn_solve_max_k(self.h, net.h, plan.h, int(k), sizes, limbs, counts))
+        top = [int(s) for s in sizes]
+        alpha = top[0]
+        cm = {alpha - d: sum(int(counts[d * limbs + l]) << (32 * l) for l in range(limbs)) for d in range(k)
+              if alpha - d >= 0}
+        return {"size_max_k": [s if s != -2 ** 31 else float("-inf") for s in top], "counting_max_k": cm}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

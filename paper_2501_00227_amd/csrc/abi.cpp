@@ -419,6 +419,44 @@ tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const 
     TN_GUARD_END
 }
 
+tn_status tn_solve_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, int32_t* sizes, int32_t limbs,
+                         uint32_t* counts) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p || !sizes || k < 1 || k > 64 || (counts && limbs < 1))
+        return fail(TN_EINVAL, "invalid arguments (k in 1..64, sizes required, limbs >= 1 with counts)");
+    if (p->plan.fingerprint != n->net.fingerprint || p->plan.nv != n->net.nv)
+        return fail(TN_EINVAL, "plan was built for a different network");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    const int nv = n->net.nv, L = nv / 32 + 2;
+    std::vector<uint32_t> poly((size_t)(nv + 1) * L);
+    int deg = 0;
+    tn_status st = solve_polynomial(c, n->net, p->plan, L, poly.data(), &deg);
+    if (st != TN_OK) return st;
+    auto coeff_small = [&](int s) -> uint64_t {  // saturating: only compared with k <= 64
+        if (s < 0 || s > deg) return 0;
+        for (int l = 2; l < L; l++)
+            if (poly[(size_t)s * L + l]) return ~0ull;
+        return (uint64_t)poly[(size_t)s * L] | ((uint64_t)poly[(size_t)s * L + 1] << 32);
+    };
+    int filled = 0;
+    for (int s = deg; s >= 0 && filled < k; s--)
+        for (uint64_t m = coeff_small(s); m > 0 && filled < k; m--) sizes[filled++] = s;
+    for (; filled < k; filled++) sizes[filled] = INT32_MIN;
+    if (counts) {
+        std::memset(counts, 0, sizeof(uint32_t) * (size_t)k * limbs);
+        for (int d = 0; d < k; d++) {
+            const int s = deg - d;
+            if (s < 0) break;
+            int used = L;
+            while (used > 0 && !poly[(size_t)s * L + used - 1]) used--;
+            if (used > limbs) return fail(TN_EOVERFLOW, "a count needs more limbs than given");
+            for (int l = 0; l < used; l++) counts[(size_t)d * limbs + l] = poly[(size_t)s * L + l];
+        }
+    }
+    return TN_OK;
+    TN_GUARD_END
+}
+
 tn_status tn_solve_polynomial(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t limbs, uint32_t* coeffs,
                               int32_t* degree) {
     TN_GUARD_BEGIN

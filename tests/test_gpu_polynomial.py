@@ -102,3 +102,22 @@ def test_rejected_inputs(ctx):
     with pytest.raises(tn.TnError) as ei:
         ctx.solve_polynomial(hnet, tn.Plan.create(hnet))
     assert ei.value.code == tn.TN_ETOOBIG
+
+
+def test_size_max_k_and_counting_max_k(ctx):
+    """SizeMax(k) / CountingMax(k) (Sec. 5.3): the paper's Petersen values, then
+    the brute-force size histogram of random graphs."""
+    net = tn.Net.from_graph(gg.petersen())
+    r = ctx.solve_max_k(net, tn.Plan.create(net), 2)
+    assert r["size_max_k"] == GOLD["petersen"]["size_max_2"]["value"]
+    assert r["counting_max_k"] == {int(s): c for s, c in GOLD["petersen"]["counting_max_2"]["value"].items()}
+    for seed in range(4):
+        g = gg.random_regular(20, 3, seed)
+        hist = _trim(oracle.brute_force(g)["poly"])
+        net = tn.Net.from_graph(g)
+        for k in (1, 3, 7):
+            r = ctx.solve_max_k(net, tn.Plan.create(net, seed=seed), k)
+            alpha = len(hist) - 1
+            want_sizes = [s for s in range(alpha, -1, -1) for _ in range(hist[s])][:k]
+            assert r["size_max_k"] == want_sizes
+            assert r["counting_max_k"] == {alpha - d: hist[alpha - d] for d in range(k) if alpha - d >= 0}
