@@ -153,6 +153,17 @@ def disjoint_union(g: Graph, h: Graph) -> Graph:
     return out
 
 
+def induced(g: Graph, keep: Sequence[int]) -> Graph:
+    """The subgraph induced by the vertices in keep, relabelled 0.. in keep's
+    order (weights follow their vertices)."""
+    pos = {int(v): k for k, v in enumerate(keep)}
+    pairs = [(pos[u], pos[v]) for u, v in g.edges.tolist() if u in pos and v in pos]
+    out = _make(len(pos), pairs, f"{g.name}[{len(pos)}]")
+    if g.weights is not None:
+        out = out.with_weights(np.asarray([g.weights[int(v)] for v in keep], np.float32))
+    return out
+
+
 def square_lattice(L: int) -> Graph:
     """Full L x L grid, vertex (r, c) -> r*L + c, 4-neighbour edges."""
     pairs = []

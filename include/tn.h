@@ -178,6 +178,18 @@ void tn_net_destroy(tn_net* net);
 /* Sizes after de-duplication. */
 tn_status tn_net_info(const tn_net* net, int32_t* nv, int32_t* ne);
 
+/* A conditioned copy of a network (the fixed vertices of the Sec. 5 network
+ * object): vertices[k] is fixed to values[k] (0 = not in the set / spin
+ * down, 1 = in the set / spin up), on top of any fixings src already has.
+ * Every leaf tensor that holds a fixed vertex is multiplied by the indicator
+ * of its value, so every property (sizes, counts, Z, polynomial, maximum
+ * configuration) becomes the property of the configurations that agree with
+ * the fixings.  The copy has src's structure: plans of src fit it.  Errors:
+ * TN_EINVAL (vertex out of range, value not 0/1, a vertex fixed to both
+ * values, NULL arguments).  Release with tn_net_destroy. */
+tn_status tn_net_condition(const tn_net* src, int32_t n, const int32_t* vertices, const int32_t* values,
+                           tn_net** out);
+
 /* ---------------------------------------------------------------- plan --- */
 
 /* Options of the contraction-order optimizers (Sec. 4.2).
@@ -365,6 +377,27 @@ tn_status tn_solve_polynomial(tn_ctx* ctx, const tn_net* net, const tn_plan* pla
  * Errors as tn_solve_polynomial. */
 tn_status tn_solve_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t* sizes,
                          int32_t limbs, uint32_t* counts);
+
+/* One maximum configuration (SingleConfigMax of the Sec. 5 table): an
+ * independent set of largest total weight, or for a spin-glass network a
+ * ground state (a configuration of smallest energy H, Sec. 2).  The max-plus
+ * float32 contraction runs once on the persistent executor with every tensor
+ * of the tree kept; a one-workgroup kernel then traces the maximum back from
+ * the root (at each inner node the summed indices take the first values whose
+ * operand entries add up to the node's entry), and the host sets the
+ * vertices that a single leaf sums by itself.
+ *   config  caller memory of nv int32: config[v] = 1 if vertex v is in the
+ *           set (spin glass: spin s_v = 2 config[v] - 1)
+ *   value   receives the float32 maximum: the set's weight, or -H of the
+ *           ground state (NULL allowed)
+ * Among several maxima any one may be returned.  The plan must not be
+ * sliced.  Errors: TN_EINVAL (sliced or foreign plan, no configuration
+ * satisfies the fixed vertices, NULL config with
+ * nv > 0), TN_ETOOBIG (an inner node sums more than 30 indices, or a tensor
+ * of rank > 62), TN_ENOMEM, TN_EDEVICE (device failure, or no assignment
+ * reproduces a node's value). */
+tn_status tn_solve_single_config_max(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t* config,
+                                     float* value);
 
 /* -------------------------------------------------------------- server --- */
 

@@ -57,14 +57,15 @@ def _load():
         i32p, f64p, u64p = P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_uint64)
         ip = P(ctypes.c_int)
         lib.orc_brute_force.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int, f64p,
-                                        f64p, u64p, u64p, u64p, f64p, f64p, ctypes.c_int, u64p, ip]
+                                        f64p, u64p, u64p, u64p, f64p, f64p, ctypes.c_int, u64p, ip,
+                                        ctypes.c_uint64, ctypes.c_uint64]
         lib.orc_eliminate.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                       ctypes.c_double, ctypes.c_int, f64p, u64p, f64p, f64p, ip]
         lib.orc_eliminate_poly.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int, u64p, ip, ip]
         lib.orc_eliminate_sg.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, ctypes.c_double,
                                          ctypes.c_int, f64p, u64p, f64p, f64p, ip]
         lib.orc_brute_force_sg.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, f64p, f64p,
-                                           u64p, f64p, f64p]
+                                           u64p, f64p, f64p, ctypes.c_uint64, ctypes.c_uint64]
         lib.orc_follow_plan.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, i32p, i32p,
                                         i32p, i32p, i32p, i32p, ctypes.c_int, i32p, ctypes.c_int64,
@@ -92,9 +93,19 @@ def _limbs_to_int(limbs: np.ndarray) -> int:
     return sum(int(x) << (64 * i) for i, x in enumerate(limbs.tolist()))
 
 
-def brute_force(graph, betas: Sequence[float] = (), sets_cap: int = 0) -> Dict:
-    """O1: enumerate all 2^n subsets (n <= 30; n <= 24 takes about a second)."""
+def _fix_masks(fixed) -> tuple:
+    mask = val = 0
+    for v, x in (fixed or {}).items():
+        mask |= 1 << int(v)
+        val |= (int(x) & 1) << int(v)
+    return mask, val
+
+
+def brute_force(graph, betas: Sequence[float] = (), sets_cap: int = 0, fixed=None) -> Dict:
+    """O1: enumerate all 2^n subsets (n <= 30; n <= 24 takes about a second).
+    fixed: {vertex: 0 or 1}, only subsets that agree with it count."""
     lib = _load()
+    fmask, fval = _fix_masks(fixed)
     edges, w = _graph_arrays(graph)
     nb = len(betas)
     b = np.ascontiguousarray(betas, dtype=np.float64) if nb else np.zeros(1)
@@ -111,7 +122,7 @@ def brute_force(graph, betas: Sequence[float] = (), sets_cap: int = 0) -> Dict:
                              _ptr(cmax, ctypes.c_uint64), _ptr(tot, ctypes.c_uint64),
                              _ptr(hist, ctypes.c_uint64), _ptr(z, ctypes.c_double),
                              _ptr(lz, ctypes.c_double), sets_cap, _ptr(sets, ctypes.c_uint64),
-                             ctypes.byref(nsets))
+                             ctypes.byref(nsets), fmask, fval)
     if rc != ORC_OK:
         raise OracleError(rc, "brute_force")
     return {
@@ -178,10 +189,12 @@ def _sg_arrays(graph, J, h):
     return Ja, ha
 
 
-def spin_glass_brute_force(graph, J=None, h=None, betas: Sequence[float] = ()) -> Dict:
+def spin_glass_brute_force(graph, J=None, h=None, betas: Sequence[float] = (), fixed=None) -> Dict:
     """O1 for the spin glass H = sum_(u,v) J_uv s_u s_v + sum_v h_v s_v, s = +-1
-    (J per edge in edge order, default 1; h per vertex, default 0); n <= 24."""
+    (J per edge in edge order, default 1; h per vertex, default 0); n <= 24.
+    fixed: {vertex: 0 (spin down) or 1 (spin up)}."""
     lib = _load()
+    fmask, fval = _fix_masks(fixed)
     edges, _ = _graph_arrays(graph)
     Ja, ha = _sg_arrays(graph, J, h)
     nb = len(betas)
@@ -191,7 +204,8 @@ def spin_glass_brute_force(graph, J=None, h=None, betas: Sequence[float] = ()) -
     z, lz = np.zeros(max(nb, 1)), np.zeros(max(nb, 1))
     rc = lib.orc_brute_force_sg(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(Ja, ctypes.c_double),
                                 _ptr(ha, ctypes.c_double), nb, _ptr(b, ctypes.c_double), _ptr(emin, ctypes.c_double),
-                                _ptr(cnt, ctypes.c_uint64), _ptr(z, ctypes.c_double), _ptr(lz, ctypes.c_double))
+                                _ptr(cnt, ctypes.c_uint64), _ptr(z, ctypes.c_double), _ptr(lz, ctypes.c_double),
+                                fmask, fval)
     if rc != ORC_OK:
         raise OracleError(rc, "spin_glass_brute_force")
     return {"energy_min": float(emin[0]), "count_min": int(cnt[0]), "z": [float(x) for x in z[:nb]],

@@ -199,6 +199,8 @@ static void put_result(int sr, elem e, double* size, uint64_t* limbs, double* zv
 /*
  * Brute force, straight from the definitions: every subset S of V (bit v of
  * the mask = n_v) is independent iff no edge has both ends in S.
+ * Conditioning (fixed vertices of the Sec. 5 network object): only subsets
+ * with (S & fix_mask) == fix_val are counted.
  *
  * Outputs (NULL to skip): maximum weight, number of subsets reaching it,
  * total number of independent sets, per-cardinality histogram (the
@@ -209,7 +211,7 @@ static void put_result(int sr, elem e, double* size, uint64_t* limbs, double* zv
 int orc_brute_force(int nv, int ne, const int32_t* edges, const double* w, int nbeta,
                     const double* betas, double* max_size, uint64_t* count_at_max,
                     uint64_t* total, uint64_t* size_hist, double* z, double* logz,
-                    int sets_cap, uint64_t* sets, int* n_sets) {
+                    int sets_cap, uint64_t* sets, int* n_sets, uint64_t fix_mask, uint64_t fix_val) {
     if (nv < 0 || nv > 30 || ne < 0) return ORC_EINVAL;
     uint64_t* nbr = calloc((size_t)(nv > 0 ? nv : 1), sizeof(uint64_t));
     if (!nbr) return ORC_ENOMEM;
@@ -235,6 +237,7 @@ int orc_brute_force(int nv, int ne, const int32_t* edges, const double* w, int n
     int nfound = 0;
     uint64_t nsub = 1ull << nv;
     for (uint64_t S = 0; S < nsub; S++) {
+        if ((S & fix_mask) != fix_val) continue;
         int ok = 1;
         for (int v = 0; v < nv && ok; v++)
             if (((S >> v) & 1) && (S & nbr[v])) ok = 0;
@@ -572,9 +575,11 @@ int orc_eliminate_sg(int nv, int ne, const int32_t* edges, const double* J, cons
 
 /* O1 for the spin glass: every configuration s in {-1,1}^n (bit v of the mask
  * is n_v, s_v = 2 n_v - 1); the minimum energy, its multiplicity and
- * Z(beta) = sum e^(-beta H) for each beta (Kahan sums). */
+ * Z(beta) = sum e^(-beta H) for each beta (Kahan sums); with fixed spins,
+ * only configurations with (m & fix_mask) == fix_val. */
 int orc_brute_force_sg(int nv, int ne, const int32_t* edges, const double* J, const double* h, int nbeta,
-                       const double* betas, double* emin, uint64_t* count_min, double* z, double* logz) {
+                       const double* betas, double* emin, uint64_t* count_min, double* z, double* logz,
+                       uint64_t fix_mask, uint64_t fix_val) {
     if (nv < 0 || nv > 30 || ne < 0 || nbeta < 0 || nbeta > 64) return ORC_EINVAL;
     for (int e = 0; e < ne; e++) {
         int u = edges[2 * e], v = edges[2 * e + 1];
@@ -584,6 +589,7 @@ int orc_brute_force_sg(int nv, int ne, const int32_t* edges, const double* J, co
     uint64_t nbest = 0;
     for (int b = 0; b < nbeta; b++) zs[b] = zc[b] = 0.0L;
     for (uint64_t m = 0; m < (1ull << nv); m++) {
+        if ((m & fix_mask) != fix_val) continue;
         long double H = 0.0L;
         for (int e = 0; e < ne; e++) {
             int su = (int)((m >> edges[2 * e]) & 1) * 2 - 1, sv = (int)((m >> edges[2 * e + 1]) & 1) * 2 - 1;

@@ -137,6 +137,8 @@ SIGNATURES = [
     ("tn_solve_polynomial", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_uint32), _P(ctypes.c_int32)]),
     ("tn_solve_max_k", ctypes.c_int,
      [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_uint32)]),
+    ("tn_net_condition", ctypes.c_int, [_VP, ctypes.c_int32, c_int32_p, c_int32_p, _P(_VP)]),
+    ("tn_solve_single_config_max", ctypes.c_int, [_VP, _VP, _VP, c_int32_p, _P(ctypes.c_float)]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
     ("tn_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _P(tn_result), c_int32_p, _P(ctypes.c_double)]),
@@ -221,6 +223,20 @@ class Net:
         self.h = hdl
         self.nv = int(g.nv)
         return self
+
+    def condition(self, fixed) -> "Net":
+        """A copy with vertices fixed ({vertex: 0 or 1}); plans of this network
+        fit the copy."""
+        items = sorted((int(v), int(x)) for v, x in dict(fixed).items())
+        vs = np.ascontiguousarray([v for v, _ in items], dtype=np.int32)
+        xs = np.ascontiguousarray([x for _, x in items], dtype=np.int32)
+        out = Net.__new__(Net)
+        hdl = ctypes.c_void_p()
+        _check(lib().tn_net_condition(self.h, len(items), _p32(vs) if len(items) else None,
+                                      _p32(xs) if len(items) else None, ctypes.byref(hdl)))
+        out.h = hdl
+        out.nv = self.nv
+        return out
 
     def flat_complexity(self):
         tc, sc, rw = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -464,6 +480,14 @@ class Context:
         cm = {alpha - d: sum(int(counts[d * limbs + l]) << (32 * l) for l in range(limbs)) for d in range(k)
               if alpha - d >= 0}
         return {"size_max_k": [s if s != -2 ** 31 else float("-inf") for s in top], "counting_max_k": cm}
+
+    def solve_single_config_max(self, net: Net, plan: Plan) -> Dict:
+        """One maximum configuration (SingleConfigMax): {"config": [0/1 per
+        vertex], "value": float32 maximum (set weight, or -H for a spin glass)}."""
+        cfg = (ctypes.c_int32 * max(1, net.nv))()
+        val = ctypes.c_float(0.0)
+        _check(lib().tn_solve_single_config_max(self.h, net.h, plan.h, cfg, ctypes.byref(val)))
+        return {"config": [int(cfg[v]) for v in range(net.nv)], "value": float(val.value)}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

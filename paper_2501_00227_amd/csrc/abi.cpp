@@ -166,6 +166,23 @@ tn_status tn_net_independent_set(int32_t nv, int32_t ne, const int32_t* edges, c
     TN_GUARD_END
 }
 
+tn_status tn_net_condition(const tn_net* src, int32_t n, const int32_t* vertices, const int32_t* values,
+                           tn_net** out) {
+    TN_GUARD_BEGIN
+    if (!src || !out) return fail(TN_EINVAL, "NULL argument");
+    *out = nullptr;
+    auto* c = new tn_net();
+    tn_status st = condition_net(src->net, n, vertices, values, c->net);
+    if (st != TN_OK) {
+        delete c;
+        return st;
+    }
+    c->net.uid = g_net_uid.fetch_add(1);
+    *out = c;
+    return TN_OK;
+    TN_GUARD_END
+}
+
 void tn_net_destroy(tn_net* n) { delete n; }
 
 tn_status tn_net_info(const tn_net* n, int32_t* nv, int32_t* ne) {
@@ -454,6 +471,14 @@ tn_status tn_solve_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k
         }
     }
     return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_solve_single_config_max(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t* config, float* value) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p) return fail(TN_EINVAL, "NULL argument");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    return single_config_max(c, n->net, p->plan, config, value);
     TN_GUARD_END
 }
 

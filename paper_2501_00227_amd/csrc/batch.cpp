@@ -144,9 +144,9 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     size_t data = 0;
     // weights of every item first, so one contiguous copy uploads them
     for (size_t i = 0; i < items.size(); i++) {
-        if (!items[i].net->w.empty()) {
+        if (!items[i].net->wdev.empty()) {
             item_w_off[i] = data;
-            data = a256(data + sizeof(float) * items[i].net->w.size());
+            data = a256(data + sizeof(float) * items[i].net->wdev.size());
         }
     }
     const size_t weights_end = data;
@@ -237,7 +237,9 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         J.nnode = (int)p.nodes.size();
         J.root = J.nnode - 1;
         J.ap = algebra_params(jp.dsr, jp.prime, items[jp.item].opts.beta, jp.xval);
+        J.ap.fix_off = items[jp.item].net->fix_off;
         J.arena.p0 = dbase + jp.o_arena0;
+        L.job_arena0.push_back(J.arena.p0);
         J.arena.p1 = plane_bytes(jp.dsr, 1) ? dbase + jp.o_arena1 : nullptr;
         J.part.p0 = dbase + jp.o_part0;
         J.part.p1 = plane_bytes(jp.dsr, 1) ? dbase + jp.o_part1 : nullptr;
@@ -246,7 +248,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         J.acc = dbase + jp.o_acc;
         J.leaves = jp.dp ? jp.dp->leaves : nullptr;
         J.spos = jp.dp ? jp.dp->slice_pos : nullptr;
-        J.w = items[jp.item].net->w.empty() ? nullptr : (const float*)(dbase + item_w_off[jp.item]);
+        J.w = items[jp.item].net->wdev.empty() ? nullptr : (const float*)(dbase + item_w_off[jp.item]);
         auto add = [&](int kind, int node, int aux, int64_t tile, Counter d0, Counter d1, int signal, int lvl,
                        int count = 1) {
             BTask t;
@@ -461,8 +463,8 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     L.d_trace = ctx->profiling ? (unsigned long long*)(d + o_trace) : nullptr;
     L.o_wstage = o_end;
     for (size_t i = 0; i < items.size(); i++)
-        if (!items[i].net->w.empty())
-            std::memcpy(h + o_end + item_w_off[i], items[i].net->w.data(), sizeof(float) * items[i].net->w.size());
+        if (!items[i].net->wdev.empty())
+            std::memcpy(h + o_end + item_w_off[i], items[i].net->wdev.data(), sizeof(float) * items[i].net->wdev.size());
     L.wbytes = wbytes;
     L.o_hacc = o_end + wbytes;
     L.o_hticket = a256(L.o_hacc + 16 * jobs.size());
@@ -658,6 +660,20 @@ tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vect
 
 tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
                           std::vector<std::array<unsigned char, 16>>& accs) {
+    BatchLaunch L;
+    tn_status st = run_passes_keep(ctx, net, plan, passes, accs, L);
+    batch_done(ctx, L);
+    return st;
+}
+
+void batch_done(tn_ctx* ctx, BatchLaunch& L) {
+    if (L.host) (void)hipStreamSynchronize(ctx->stream);
+    batch_release(L);
+    scratch_regrow(ctx);
+}
+
+tn_status run_passes_keep(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
+                          std::vector<std::array<unsigned char, 16>>& accs, BatchLaunch& L) {
     std::vector<BatchItem> items(1);
     items[0].net = &net;
     items[0].plan = &plan;
@@ -665,7 +681,6 @@ tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const s
     items[0].passes = &passes;
     batch_cache_drop(ctx);
     DevAllocFn alloc = scratch_alloc(ctx);
-    BatchLaunch L;
     tn_status st = batch_prepare(ctx, items, L, alloc);
     if (st == TN_OK) st = L.items[0].status;
     if (st == TN_OK) st = batch_launch(ctx, L, ctx->stream);
@@ -678,9 +693,6 @@ tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const s
         for (size_t k = 0; k < ids.size() && k < accs.size(); k++)
             std::memcpy(accs[k].data(), (unsigned char*)L.host + L.o_hacc + 16 * (size_t)ids[k], 16);
     }
-    if (L.host) (void)hipStreamSynchronize(ctx->stream);
-    batch_release(L);
-    scratch_regrow(ctx);
     return st;
 }
 

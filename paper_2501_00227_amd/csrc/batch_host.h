@@ -58,6 +58,7 @@ struct BatchLaunch {
     void* d_accs = nullptr;   // the jobs' root accumulators, 16 bytes each
     size_t o_reset = 0, reset_bytes = 0;  // counters and tickets within the tables
     bool uploaded = false;    // tables and weights are on the device
+    std::vector<void*> job_arena0;  // plane 0 of every job's arena (dependency-graph layout)
     double total_ops = 0, total_bytes = 0;  // algorithmic work of the launch
     unsigned long long* d_trace = nullptr;  // per-task timestamps (profiling)
     std::vector<BTask> host_tasks;          // kept for the trace
@@ -79,6 +80,13 @@ tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vect
 // network; accs receives the 16-byte root accumulator of every pass, in order.
 tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
                           std::vector<std::array<unsigned char, 16>>& accs);
+// As run_passes_sync, but the launch stays alive (its arenas hold every
+// tensor of the contraction) until batch_done.
+tn_status run_passes_keep(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
+                          std::vector<std::array<unsigned char, 16>>& accs, BatchLaunch& L);
+void batch_done(tn_ctx* ctx, BatchLaunch& L);
+// One maximum configuration (SingleConfigMax): config[v] in {0, 1}.
+tn_status single_config_max(tn_ctx* ctx, const Net& net, const Plan& plan, int32_t* config, float* value);
 // Independence polynomial (finite-field method); coeffs: (nv + 1) * limbs.
 tn_status solve_polynomial(tn_ctx* ctx, const Net& net, const Plan& plan, int limbs, uint32_t* coeffs, int* degree);
 // Release the launch a synchronous batch keeps for an identical next call.

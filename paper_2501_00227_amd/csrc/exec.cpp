@@ -424,28 +424,32 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     size_t o_p1 = align256(o_p0 + (size_t)Pe * pb0);
     size_t o_meta = align256(o_p1 + (size_t)Pe * pb1);
     size_t o_w = align256(o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
-    size_t o_acc = align256(o_w + sizeof(float) * std::max<size_t>(net.w.size(), 1));
+    size_t o_acc = align256(o_w + sizeof(float) * std::max<size_t>(net.wdev.size(), 1));
     need = align256(o_acc + 16 * passes.size());
     unsigned char* base = (unsigned char*)dev_alloc(ctx, need);
     if (!base) return fail(TN_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
     Planes arena{base + o_a0, pb1 ? base + o_a1 : nullptr};
     Planes part{base + o_p0, pb1 ? base + o_p1 : nullptr};
     TensorMeta* meta = (TensorMeta*)(base + o_meta);
-    float* wdev = net.w.empty() ? nullptr : (float*)(base + o_w);
-    st = ensure_pinned(ctx, std::max<size_t>(16 * passes.size(), sizeof(float) * net.w.size()) + 64);
+    float* wdev = net.wdev.empty() ? nullptr : (float*)(base + o_w);
+    st = ensure_pinned(ctx, std::max<size_t>(16 * passes.size(), sizeof(float) * net.wdev.size()) + 64);
     if (st != TN_OK) {
         dev_free(ctx, base, need);
         return st;
     }
     hipError_t herr = hipSuccess;
-    auto chk = [&](hipError_t e) {
-        if (e != hipSuccess && herr == hipSuccess) herr = e;
+    const char* herr_at = "";
+    auto chk = [&](hipError_t e, const char* at) {
+        if (e != hipSuccess && herr == hipSuccess) {
+            herr = e;
+            herr_at = at;
+        }
     };
     if (wdev) {
-        chk(hipStreamSynchronize(s));
-        std::memcpy(ctx->pinned, net.w.data(), sizeof(float) * net.w.size());
-        chk(hipMemcpyAsync(wdev, ctx->pinned, sizeof(float) * net.w.size(), hipMemcpyHostToDevice, s));
-        chk(hipStreamSynchronize(s));  // staging is reused for the results below
+        chk(hipStreamSynchronize(s), "sync before weights");
+        std::memcpy(ctx->pinned, net.wdev.data(), sizeof(float) * net.wdev.size());
+        chk(hipMemcpyAsync(wdev, ctx->pinned, sizeof(float) * net.wdev.size(), hipMemcpyHostToDevice, s), "weights upload");
+        chk(hipStreamSynchronize(s), "weights sync");  // staging is reused for the results below
     }
     auto plane_at = [&](Planes pl, int dsr, int64_t off) {
         Planes r;
@@ -455,21 +459,23 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     };
     for (size_t pi = 0; pi < passes.size() && herr == hipSuccess; pi++) {
         const int dsr = passes[pi].dsr;
-        const AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta, passes[pi].xval);
+        AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta, passes[pi].xval);
+        ap.fix_off = net.fix_off;
         void* acc = base + o_acc + 16 * pi;
         const int eb = plane_bytes(dsr, 0) + plane_bytes(dsr, 1);
         const bool is_z = dsr == DSR_Z_F32 || dsr == DSR_Z_BF16;
         if (nleaf == 0) {
-            chk(launch_set_one(dsr, acc, ap, s));
+            chk(launch_set_one(dsr, acc, ap, s), "set one");
             continue;
         }
         const auto& launches = node_launches(*dp, plan, dsr);
         for (int64_t sl = sb; sl < se && herr == hipSuccess; sl++) {
-            if (is_z) chk(launch_meta_init(meta, nn, s));
+            if (is_z) chk(launch_meta_init(meta, nn, s), "meta init");
             {
                 ProfScope ps(ctx, TN_K_LEAF, -1, o.semiring, nullptr, (double)plan.leaf_entries * eb, 0);
                 chk(launch_leaves(dsr, dp->leaves, nleaf, wdev, dp->slice_pos, (unsigned long long)sl, arena, ap,
-                                  meta, s));
+                                  meta, s),
+                    "leaves");
             }
             for (size_t t = 0; t < plan.prog.size() && herr == hipSuccess; t++) {
                 const NodeProg& np = plan.prog[t];
@@ -492,7 +498,8 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                         ProfScope ps(ctx, TN_K_PERMUTE, np.node, o.semiring, shp,
                                      2.0 * (double)node_entries(plan, src_node) * pbytes, 0);
                         chk(launch_permute(pbytes, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms + slot, rank,
-                                           tb, s));
+                                           tb, s),
+                            "permute");
                     }
                     if (side)
                         Bp = dst;
@@ -512,29 +519,30 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                                                           : TN_K_GEMM;
                     ProfScope ps(ctx, kind, np.node, o.semiring, shp, ent * eb,
                                  std::exp2((double)(g.lb + g.li + g.lj + g.lk)));
-                    chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s));
+                    chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s), "gemm");
                 }
                 if (g.lsplit > 0) {
                     int64_t nout = (int64_t)1 << (g.lb + g.li + g.lj);
                     ProfScope ps(ctx, TN_K_ACCUM, np.node, o.semiring, shp,
                                  (double)(nout << g.lsplit) * eb + (double)nout * eb, 0);
-                    chk(launch_split_reduce(dsr, part, Cp, nout, g.lsplit, ap, meta, np.node, s));
+                    chk(launch_split_reduce(dsr, part, Cp, nout, g.lsplit, ap, meta, np.node, s), "split reduce");
                 }
             }
             int root = nn - 1;
             chk(launch_accumulate(dsr, plane_at(arena, dsr, plan.node_off[root]), root, meta, acc, sl == sb ? 1 : 0,
-                                  ap, s));
+                                  ap, s),
+                "root accumulate");
         }
     }
     std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
     if (herr == hipSuccess) {
-        chk(hipMemcpyAsync(ctx->pinned, base + o_acc, 16 * passes.size(), hipMemcpyDeviceToHost, s));
-        chk(hipStreamSynchronize(s));
+        chk(hipMemcpyAsync(ctx->pinned, base + o_acc, 16 * passes.size(), hipMemcpyDeviceToHost, s), "result copy");
+        chk(hipStreamSynchronize(s), "result sync");
         for (size_t k = 0; k < passes.size(); k++)
             std::memcpy(accs[k].data(), (unsigned char*)ctx->pinned + 16 * k, 16);
     }
     dev_free(ctx, base, need);
-    if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error: ") + hipGetErrorString(herr));
+    if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error at ") + herr_at + ": " + hipGetErrorString(herr));
     st = decode_result(o, passes, accs, res);
     res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;

@@ -39,6 +39,8 @@ struct TensorMeta {
 struct AlgebraParams {
     uint32_t p = 0, pinv = 0, r1 = 0;  // modulus, -p^{-1} mod 2^32, 2^32 mod p
     uint32_t xv = 0;                   // mod p: the vertex tensor's x (Montgomery form; 1 = r1 counts)
+    int fix_off = -1;                  // fixed vertices: w[fix_off + v] = -1 (free), 0 or 1; -1: none
+    int pad = 0;
     double beta = 0;
 };
 
@@ -101,6 +103,17 @@ hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, 
 // The device-side identity element of a whole (empty) network.
 hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream_t s);
 int accumulator_bytes(int dsr);
+
+// Back-trace of a max-plus float32 contraction kept in the dependency-graph
+// layout (every tensor at arena + off[x] in its storage order): from the root
+// down, each inner node's summed indices are set to the first assignment
+// whose A + B reproduces the node's stored value.  nodes: 3 ints (node,
+// left, right) per inner node in execution order; the storage order of node
+// x is ord_ids[ord_off[x] .. ord_off[x+1]) (index ids = vertex ids).  assign
+// (nv ints, -1 = unset) receives every index value; status: 0 ok, 1 no
+// matching assignment, 2 too many summed indices.
+hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, const int* ord_off, const int* ord_ids,
+                            const long long* off, int* assign, int* status, hipStream_t s);
 
 // Choose tile shape for a GEMM node (heuristic; the autotuner may override).
 GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);

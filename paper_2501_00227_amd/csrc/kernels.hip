@@ -513,6 +513,115 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(Planes part, Planes C
     }
 }
 
+// ---------------------------------------------------------- back-trace --
+// One workgroup walks the tree from the root: thread 0 reads the node's value
+// at its (already assigned) output indices and lists the summed indices; all
+// threads then scan the assignments of the summed indices, in chunks, for the
+// smallest one whose A + B equals that value.  The GEMM formed the value as
+// the maximum of exactly these float sums, so the equality is exact.
+__global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, const int* nodes, int ninner,
+                                                        const int* ord_off, const int* ord_ids, const long long* off,
+                                                        int* assign, int* status) {
+    constexpr int kMaxFree = 30, kMaxRank = 62;
+    constexpr unsigned long long kChunk = 1ull << 16;
+    __shared__ int sfree[kMaxFree];
+    __shared__ int nfree;
+    __shared__ float target;
+    __shared__ unsigned long long best;
+    __shared__ int mapA[kMaxRank], mapB[kMaxRank];  // >= 0: position in sfree; < 0: -1 - fixed value
+    __shared__ int rankA, rankB;
+    __shared__ int stop;
+    if (threadIdx.x == 0) stop = 0;
+    __syncthreads();
+    // Shared state is written by thread 0 only between the barrier pairs that
+    // separate it from every read by the other threads.
+    for (int t = ninner - 1; t >= 0; t--) {
+        const int x = nodes[3 * t], a = nodes[3 * t + 1], b = nodes[3 * t + 2];
+        if (threadIdx.x == 0 && !stop) {
+            long long addr = 0;
+            const int rc = ord_off[x + 1] - ord_off[x];
+            if (rc > kMaxRank) stop = 2;
+            for (int q = 0; q < rc && !stop; q++) {
+                const int v = assign[ord_ids[ord_off[x] + q]];
+                if (v < 0) stop = 3;  // an output index left unset
+                addr |= (long long)(v & 1) << q;
+            }
+            if (!stop) target = arena[off[x] + addr];
+            nfree = 0;
+            for (int side = 0; side < 2 && !stop; side++) {
+                const int y = side ? b : a;
+                int* map = side ? mapB : mapA;
+                const int r = ord_off[y + 1] - ord_off[y];
+                if (side) rankB = r;
+                else rankA = r;
+                if (r > kMaxRank) {
+                    stop = 2;
+                    break;
+                }
+                for (int q = 0; q < r; q++) {
+                    const int id = ord_ids[ord_off[y] + q];
+                    if (assign[id] >= 0) {
+                        map[q] = -1 - (assign[id] & 1);
+                        continue;
+                    }
+                    int pos = -1;
+                    for (int f = 0; f < nfree; f++)
+                        if (sfree[f] == id) pos = f;
+                    if (pos < 0) {
+                        if (nfree == kMaxFree) {
+                            stop = 2;
+                            break;
+                        }
+                        pos = nfree;
+                        sfree[nfree++] = id;
+                    }
+                    map[q] = pos;
+                }
+            }
+            if (stop) *status = stop;
+            best = ~0ull;
+        }
+        __syncthreads();
+        const int halt = stop;
+        const unsigned long long total = 1ull << nfree;
+        __syncthreads();
+        if (halt) break;
+        for (unsigned long long c0 = 0; c0 < total; c0 += kChunk) {
+            const unsigned long long c1 = c0 + kChunk < total ? c0 + kChunk : total;
+            for (unsigned long long s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
+                long long addrA = 0, addrB = 0;
+                for (int q = 0; q < rankA; q++) {
+                    const int m = mapA[q];
+                    addrA |= (long long)(m >= 0 ? (int)((s >> m) & 1) : -1 - m) << q;
+                }
+                for (int q = 0; q < rankB; q++) {
+                    const int m = mapB[q];
+                    addrB |= (long long)(m >= 0 ? (int)((s >> m) & 1) : -1 - m) << q;
+                }
+                if (arena[off[a] + addrA] + arena[off[b] + addrB] == target) atomicMin(&best, s);
+            }
+            __syncthreads();
+            const bool found = best != ~0ull;
+            __syncthreads();
+            if (found) break;
+        }
+        if (threadIdx.x == 0) {
+            if (best == ~0ull) {
+                *status = 1;
+                stop = 1;
+            } else {
+                for (int f = 0; f < nfree; f++) assign[sfree[f]] = (int)((best >> f) & 1);
+            }
+        }
+    }
+}
+
+hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, const int* ord_off, const int* ord_ids,
+                            const long long* off, int* assign, int* status, hipStream_t s) {
+    backtrace_kernel<<<1, 256, 0, s>>>(arena, nodes, ninner, ord_off, ord_ids, off, assign, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_reduce(int dsr, Planes part, Planes C, i64 nout, int lsplit, const AlgebraParams& ap,
                                TensorMeta* meta, int mc, hipStream_t s) {
     int per_block = nout < 1024 ? 1 : 0;

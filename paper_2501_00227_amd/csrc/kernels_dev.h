@@ -189,7 +189,14 @@ __device__ inline int max_exponent(unsigned int bits) {
 // A leaf is the product of its factors: the edge tensor B(n_u, n_v) =
 // [[1,1],[1,0]] and the vertex tensors W(n) = [1, x^w] folded into it
 // (Sec. 3.2), summed over its indices that occur nowhere else, with sliced
-// indices fixed to this slice's values.
+// indices fixed to this slice's values.  A fixed vertex (conditioning, the
+// fixed vertices of the Sec. 5 network object) multiplies every leaf it
+// occurs in by the indicator of its value; the indicator is idempotent, so
+// applying it in several leaves changes nothing.
+__device__ inline int leaf_fixed(int v, const float* w, const AlgebraParams& ap) {
+    return (ap.fix_off >= 0 && v >= 0) ? (int)w[ap.fix_off + v] : -1;
+}
+
 __device__ inline int leaf_var_value(int var, const LeafDev& d, int e, const int* spos, u64 sid) {
     if (var == d.var0) return e & 1;
     if (var == d.var1) return (e >> 1) & 1;
@@ -204,6 +211,7 @@ __device__ void leaf_one(const LeafDev& d, int leaf_id, const float* w, const in
     using A = Alg<D>;
     using V = typename A::V;
     int nent = 1 << d.rank;
+    const int xu = leaf_fixed(d.u, w, ap), xv = leaf_fixed(d.v, w, ap);
     for (int e = 0; e < nent; e++) {
         int fu = leaf_var_value(d.u, d, e, spos, sid);
         int fv = d.v >= 0 ? leaf_var_value(d.v, d, e, spos, sid) : 0;
@@ -213,6 +221,7 @@ __device__ void leaf_one(const LeafDev& d, int leaf_id, const float* w, const in
             if (fu >= 0 && nu != fu) continue;
             if (fv >= 0 && nv != fv) continue;
             if (d.v < 0 && nv) continue;
+            if ((xu >= 0 && nu != xu) || (xv >= 0 && nv != xv)) continue;
             V prod = A::one(ap);
             if (d.flags & 8) {  // spin glass: x^(-J s_u s_v), x^(-h s), s = 2n - 1
                 if (d.flags & 1) prod = A::weight(nu == nv ? -w[d.jidx] : w[d.jidx], ap);
@@ -236,6 +245,7 @@ __device__ inline void leaf_one_z(const LeafDev& d, int leaf_id, const float* w,
     int nent = 1 << d.rank;
     double val[4] = {0, 0, 0, 0};
     double mx = 0.0;
+    const int xu = leaf_fixed(d.u, w, ap), xv = leaf_fixed(d.v, w, ap);
     for (int e = 0; e < nent; e++) {
         int fu = leaf_var_value(d.u, d, e, spos, sid);
         int fv = d.v >= 0 ? leaf_var_value(d.v, d, e, spos, sid) : 0;
@@ -245,6 +255,7 @@ __device__ inline void leaf_one_z(const LeafDev& d, int leaf_id, const float* w,
             if (fu >= 0 && nu != fu) continue;
             if (fv >= 0 && nv != fv) continue;
             if (d.v < 0 && nv) continue;
+            if ((xu >= 0 && nu != xu) || (xv >= 0 && nv != xv)) continue;
             double prod = 1.0;
             if (d.flags & 8) {  // spin glass: e^(-beta J s_u s_v), e^(-beta h s)
                 double ex = 0.0;

@@ -61,6 +61,33 @@ tn_status make_net(int nv, int ne, const int32_t* edges, const float* weights, N
     mix((uint64_t)nv);
     for (auto& e : out.edges) mix(((uint64_t)e[0] << 32) | (uint32_t)e[1]);
     out.fingerprint = h;
+    set_dev_weights(out);
+    return TN_OK;
+}
+
+void set_dev_weights(Net& net) {
+    net.wdev = net.w;
+    net.fix_off = -1;
+    if (net.fix.empty()) return;
+    if (net.wdev.empty()) net.wdev.assign((size_t)net.nv, 1.0f);
+    net.fix_off = (int)net.wdev.size();
+    for (int v = 0; v < net.nv; v++) net.wdev.push_back((float)net.fix[v]);
+}
+
+tn_status condition_net(const Net& src, int n, const int32_t* vertices, const int32_t* values, Net& out) {
+    if (n < 0 || (n > 0 && (!vertices || !values))) return fail(TN_EINVAL, "vertices and values are required");
+    std::vector<signed char> fix = src.fix.empty() ? std::vector<signed char>((size_t)src.nv, -1) : src.fix;
+    for (int k = 0; k < n; k++) {
+        const int v = vertices[k], x = values[k];
+        if (v < 0 || v >= src.nv) return fail(TN_EINVAL, "fixed vertex " + std::to_string(v) + " out of range");
+        if (x != 0 && x != 1) return fail(TN_EINVAL, "a fixed vertex takes the value 0 or 1");
+        if (fix[v] >= 0 && fix[v] != x)
+            return fail(TN_EINVAL, "vertex " + std::to_string(v) + " is fixed to both values");
+        fix[v] = (signed char)x;
+    }
+    out = src;
+    out.fix = fix;
+    set_dev_weights(out);
     return TN_OK;
 }
 
@@ -86,6 +113,7 @@ tn_status make_spin_glass(int nv, int ne, const int32_t* edges, const float* J, 
         if (x != std::nearbyint(x) || std::fabs(x) > 65536.0f) out.integer_weights = false;
     }
     out.fingerprint = out.fingerprint * 1099511628211ull ^ 0x5397u;  // a spin glass differs from an IS network
+    set_dev_weights(out);
     return TN_OK;
 }
 

@@ -22,12 +22,22 @@ struct Net {
     // 0: independent set (w = vertex weights, or empty for unit weights);
     // 1: spin glass H = sum J s_u s_v + sum h s_v (w = h[nv] then J[edges])
     int kind = 0;
+    // fixed vertices (conditioning): fix[v] = -1 free, 0 or 1; empty = none
+    std::vector<signed char> fix;
+    // the array the leaf kernels read: w (unit weights written out when
+    // vertices are fixed), then the fix codes as floats from fix_off on
+    std::vector<float> wdev;
+    int fix_off = -1;
 };
 
 tn_status make_net(int nv, int ne, const int32_t* edges, const float* weights, Net& out);
 // Spin glass on the graph: J per input edge (NULL: all 1; duplicates add up),
 // h per vertex (NULL: all 0).
 tn_status make_spin_glass(int nv, int ne, const int32_t* edges, const float* J, const float* h, Net& out);
+// A copy of src with vertices[k] fixed to values[k] (0 or 1), on top of the
+// fixings src already has; same structure, so src's plans fit it.
+tn_status condition_net(const Net& src, int n, const int32_t* vertices, const int32_t* values, Net& out);
+void set_dev_weights(Net& net);
 
 // One leaf tensor: the product of some edge / vertex factors of the network.
 struct Leaf {

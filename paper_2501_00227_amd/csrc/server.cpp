@@ -72,7 +72,7 @@ uint64_t job_device_bytes(const Net& net, const Plan& plan, const tn_solve_opts&
     std::vector<PassSpec> passes;
     if (make_passes(net, o, passes) != TN_OK) return 0;
     auto a = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
-    uint64_t total = a(sizeof(float) * net.w.size());
+    uint64_t total = a(sizeof(float) * net.wdev.size());
     for (auto& ps : passes) {
         uint64_t pb0 = plane_bytes(ps.dsr, 0), pb1 = plane_bytes(ps.dsr, 1);
         uint64_t E = (uint64_t)std::max<int64_t>(plan.arena_entries_dag, 64);

@@ -499,3 +499,70 @@ def test_spin_glass_elimination_matches_brute_force():
         z = oracle.spin_glass_eliminate(g, "partition", J=J, h=h, beta=0.4)["z"]
         assert abs(z - bf["z"][0]) <= 1e-12 * bf["z"][0], t
         assert oracle.spin_glass_eliminate(g, "tropical", J=J, h=h)["size"] == -bf["energy_min"]
+
+
+# ----------------------------------------------------- fixed vertices ----
+# Conditioning on n_v (the fixed vertices of the Sec. 5 network object) is
+# pinned by graph identities the oracle computes on other graphs: n_v = 0
+# is the graph without v; n_v = 1 is the graph without v's closed
+# neighbourhood, plus v's weight (Z times e^(beta w_v), the polynomial times
+# x); the two conditionings add up to the unconditioned result.
+
+def _without(g, drop):
+    return gg.induced(g, [v for v in range(g.nv) if v not in set(drop)])
+
+
+def test_fixed_vertex_identities_brute_force():
+    rng = random.Random(17)
+    for t in range(30):
+        n = rng.randint(2, 14)
+        g = gg.gnp(n, rng.uniform(0.1, 0.6), 900 + t)
+        if t % 2:
+            g = g.with_weights(gg.integer_weights(n, 900 + t, 1, 5))
+        w = g.weights if g.weights is not None else np.ones(n, np.float32)
+        v = rng.randrange(n)
+        beta = 0.3
+        full = oracle.brute_force(g, betas=[beta])
+        f0 = oracle.brute_force(g, betas=[beta], fixed={v: 0}, sets_cap=50)
+        f1 = oracle.brute_force(g, betas=[beta], fixed={v: 1}, sets_cap=50)
+        g0 = oracle.brute_force(_without(g, [v]), betas=[beta])
+        nb = [u for u in g.adjacency()[v]]
+        g1 = oracle.brute_force(_without(g, [v] + nb), betas=[beta])
+        assert (f0["size_max"], f0["count_all"], f0["count_max"]) == (g0["size_max"], g0["count_all"], g0["count_max"])
+        assert f0["poly"][: n] == g0["poly"] + [0] * (n - len(g0["poly"]))
+        assert f1["size_max"] == g1["size_max"] + float(w[v]) and f1["count_all"] == g1["count_all"]
+        assert f1["poly"] == [0] + g1["poly"] + [0] * (n - len(g1["poly"]))
+        assert math.isclose(f1["z"][0], g1["z"][0] * math.exp(beta * float(w[v])), rel_tol=1e-12)
+        assert f0["count_all"] + f1["count_all"] == full["count_all"]
+        assert [a + b for a, b in zip(f0["poly"], f1["poly"])] == full["poly"]
+        assert math.isclose(f0["z"][0] + f1["z"][0], full["z"][0], rel_tol=1e-12)
+        for S in f0["max_sets"]:
+            assert not (S >> v) & 1
+        for S in f1["max_sets"]:
+            assert (S >> v) & 1
+    # conflicting fixings leave nothing: an edge with both ends fixed to 1
+    g = gg.path(3)
+    r = oracle.brute_force(g, fixed={0: 1, 1: 1})
+    assert r["count_all"] == 0 and r["size_max"] == float("-inf")
+
+
+def test_fixed_spin_identities_brute_force():
+    rng = random.Random(19)
+    for t in range(12):
+        n = rng.randint(2, 12)
+        g = gg.gnp(n, rng.uniform(0.2, 0.7), 950 + t)
+        J = [float(rng.randint(-3, 3)) for _ in range(g.ne)]
+        v = rng.randrange(n)
+        full = oracle.spin_glass_brute_force(g, J, betas=[0.4])
+        up = oracle.spin_glass_brute_force(g, J, betas=[0.4], fixed={v: 1})
+        dn = oracle.spin_glass_brute_force(g, J, betas=[0.4], fixed={v: 0})
+        # without fields H is even under flipping every spin
+        assert (up["energy_min"], up["count_min"]) == (dn["energy_min"], dn["count_min"])
+        assert up["count_min"] + dn["count_min"] == full["count_min"] and up["energy_min"] == full["energy_min"]
+        assert math.isclose(up["z"][0], full["z"][0] / 2, rel_tol=1e-12)
+        # a field on v alone: fixing s_v = +1 adds h_v to every energy
+        h = [0.0] * n
+        h[v] = 2.0
+        upf = oracle.spin_glass_brute_force(g, J, h, betas=[0.4], fixed={v: 1})
+        assert upf["energy_min"] == up["energy_min"] + 2.0
+        assert math.isclose(upf["z"][0], up["z"][0] * math.exp(-0.8), rel_tol=1e-12)
