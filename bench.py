@@ -172,6 +172,49 @@ def independence_polynomial(ctx, net, plan, tc):
             "GOP_per_s": passes * 2.0 ** tc / dt / 1e9, "max_coefficient_bits": max(c.bit_length() for c in p)}
 
 
+def single_config(ctx, net, plan):
+    """One maximum independent set of the n=120 network (SingleConfigMax):
+    one float32 max-plus pass kept on the device, then the back-trace
+    kernel; and SizeMax(k)/CountingMax(k) at k = 4 (read off the
+    independence polynomial)."""
+    r = ctx.solve_single_config_max(net, plan)  # warm
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        r = ctx.solve_single_config_max(net, plan)
+    dt = (time.perf_counter() - t0) / reps
+    mk = ctx.solve_max_k(net, plan, 4)
+    return {"workload": "3-regular n=120 seed 0: one maximum independent set (Sec. 5 SingleConfigMax)",
+            "ms": dt * 1e3, "value": r["value"], "set_size": sum(r["config"]),
+            "size_max_4": mk["size_max_k"], "counting_max_4": {str(k): v for k, v in mk["counting_max_k"].items()}}
+
+
+def conditioned_batch(ctx, g, plan, nfix=8, njobs=64, seed=0):
+    """Conditioning: njobs copies of the network, each with nfix random
+    vertices fixed, counted (counting tropical) in one persistent launch."""
+    import random
+
+    import paper_2501_00227_amd as tn
+
+    base = tn.Net.from_graph(g)
+    rng = random.Random(seed)
+    adj = g.adjacency()
+    nets = []
+    for _ in range(njobs):
+        fixed = {}
+        for v in rng.sample(range(g.nv), nfix):
+            fixed[v] = 0 if any(fixed.get(u) == 1 for u in adj[v]) else rng.randint(0, 1)
+        nets.append(base.condition(fixed))
+    ctx.solve_batch(nets, [plan] * njobs, "counting_tropical")  # warm
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        ctx.solve_batch(nets, [plan] * njobs, "counting_tropical")
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "3-regular n=120 seed 0: %d conditionings (%d fixed vertices each), counting tropical, "
+                        "one persistent launch" % (njobs, nfix), "ms": dt * 1e3, "solves_per_s": njobs / dt}
+
+
 def buckyball(ctx):
     """The Sec. 6.4 example: antiferromagnetic unit-coupling spin glass on
     the C60 graph, ln Z / N at beta = 1 (float32 on matrix cores) and the
@@ -351,6 +394,8 @@ def main():
         out["largest_intermediate"] = largest_intermediate(ctx)
         out["independence_polynomial"] = independence_polynomial(ctx, net, plan, tc)
         out["spin_glass_buckyball"] = buckyball(ctx)
+        out["single_config_max"] = single_config(ctx, net, plan)
+        out["conditioned"] = conditioned_batch(ctx, g, plan)
         out["batched"] = job_stream(ctx, args.jobs, args.seed)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, ops_per_step)

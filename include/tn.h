@@ -204,7 +204,11 @@ tn_status tn_net_condition(const tn_net* src, int32_t n, const int32_t* vertices
  *   nslices  upper bound on sliced indices; indices are sliced (Sec. 4.2)
  *            while sc > sc_target.  0 = never slice.
  *   absorb_vertices  fold each vertex tensor into one incident edge tensor
- *            (same result, fewer leaves). */
+ *            (same result, fewer leaves).
+ *   open     open vertices (the open vertices of the Sec. 5 network object):
+ *            never summed, so the root is a tensor over them (at most 16);
+ *            they are never sliced.  Such a plan is solved by tn_solve_open
+ *            only. */
 typedef struct {
     int32_t method;
     double alpha;
@@ -222,6 +226,8 @@ typedef struct {
     int32_t nslices;
     int32_t absorb_vertices;
     int32_t nthreads; /* host threads for TreeSA trials; 0 = hardware count */
+    int32_t nopen;       /* open vertices: indices the contraction keeps to the root */
+    const int32_t* open; /* nopen distinct vertex ids (copied); see tn_solve_open */
 } tn_plan_opts;
 
 /* Defaults: greedy alpha 0, T 0, nrepeat 10 (Sec. 4.2.1); TreeSA sc_target 20,
@@ -265,6 +271,19 @@ tn_status tn_plan_info(const tn_plan* plan, tn_plan_info_t* info);
 /* Device bytes one tn_solve of this plan needs in the given algebra (arena of
  * live intermediates, permute scratch, leaves and bookkeeping). */
 tn_status tn_plan_peak_bytes(const tn_plan* plan, tn_semiring semiring, uint64_t* bytes);
+
+/* The GEMM launch shape of every inner node for one semiring (introspection:
+ * which kernel family and tile each contraction step of Sec. 4.1 runs on).
+ * One row of TN_SHAPE_ROW int32 per (device algebra, inner node), inner nodes
+ * in execution order; TN_COUNT_EXACT has two device algebras (counts mod 2^64,
+ * then mod p), the others one.  Row: algebra index, node id, log2 batch / M /
+ * N / K, A and B transposition flags, log2 tile batch / M / N / K step, micro
+ * tile rows / columns, log2 K splits, kernel kind (tn_kernel_kind), 1 if the
+ * shape is one the kernels accept, 0.  Writes at most cap rows (rows may be
+ * NULL with cap 0); *nrows receives the full count. */
+#define TN_SHAPE_ROW 18
+tn_status tn_plan_gemm_shapes(const tn_plan* plan, tn_semiring semiring, int32_t cap, int32_t* rows,
+                              int32_t* nrows);
 
 /* Export the tree in the format of tn_plan_from_tree, plus the ordered output
  * indices of every node (leaves first).  Call with NULL arrays to get the
@@ -377,6 +396,18 @@ tn_status tn_solve_polynomial(tn_ctx* ctx, const tn_net* net, const tn_plan* pla
  * Errors as tn_solve_polynomial. */
 tn_status tn_solve_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t* sizes,
                          int32_t limbs, uint32_t* counts);
+
+/* Solve a plan with open vertices (tn_plan_opts.open): the result is the
+ * tensor over the open vertices, one tn_result per assignment (marginals in
+ * the chosen algebra: the property of the configurations that agree with
+ * that assignment).  out[e] holds the assignment whose bit q is the value of
+ * open vertex q in the order given at plan creation; cap >= 2^nopen.  Runs
+ * on the stream executor (sliced plans too: open vertices are never
+ * sliced); opts.executor 2 (persistent) is refused.  Errors as tn_solve, and
+ * TN_EINVAL for cap too small.  A plan without open vertices gives one
+ * result. */
+tn_status tn_solve_open(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts, int64_t cap,
+                        tn_result* out);
 
 /* One maximum configuration (SingleConfigMax of the Sec. 5 table): an
  * independent set of largest total weight, or for a spin-glass network a

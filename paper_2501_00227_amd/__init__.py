@@ -64,7 +64,7 @@ class tn_plan_opts(ctypes.Structure):
                 ("sc_weight", ctypes.c_double), ("rw_weight", ctypes.c_double), ("beta_start", ctypes.c_double),
                 ("beta_step", ctypes.c_double), ("beta_stop", ctypes.c_double), ("ntrials", ctypes.c_int32),
                 ("niters", ctypes.c_int32), ("nslices", ctypes.c_int32), ("absorb_vertices", ctypes.c_int32),
-                ("nthreads", ctypes.c_int32)]
+                ("nthreads", ctypes.c_int32), ("nopen", ctypes.c_int32), ("open", ctypes.POINTER(ctypes.c_int32))]
 
 
 class tn_plan_info_t(ctypes.Structure):
@@ -137,7 +137,9 @@ SIGNATURES = [
     ("tn_solve_polynomial", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_uint32), _P(ctypes.c_int32)]),
     ("tn_solve_max_k", ctypes.c_int,
      [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_uint32)]),
+    ("tn_plan_gemm_shapes", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int32, c_int32_p, c_int32_p]),
     ("tn_net_condition", ctypes.c_int, [_VP, ctypes.c_int32, c_int32_p, c_int32_p, _P(_VP)]),
+    ("tn_solve_open", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), ctypes.c_int64, _P(tn_result)]),
     ("tn_solve_single_config_max", ctypes.c_int, [_VP, _VP, _VP, c_int32_p, _P(ctypes.c_float)]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
@@ -252,11 +254,18 @@ class Net:
 # --------------------------------------------------------------------- plan --
 
 def plan_opts(**kw) -> tn_plan_opts:
+    """Plan options; open=[vertices] keeps those vertices to the root (the
+    array is attached to the returned struct, which must outlive the call)."""
     o = tn_plan_opts()
     lib().tn_plan_opts_default(ctypes.byref(o))
     method = kw.pop("method", None)
     if method is not None:
         o.method = {"greedy": 0, "treesa": 1}.get(method, method)
+    opn = kw.pop("open", None)
+    if opn:
+        o._open_buf = _i32(list(opn))
+        o.nopen = len(opn)
+        o.open = _p32(o._open_buf)
     for k, v in kw.items():
         if k == "absorb":
             k = "absorb_vertices"
@@ -273,10 +282,14 @@ class Plan:
 
     @classmethod
     def create(cls, net: Net, **kw) -> "Plan":
+        """Plan options as keywords (method="greedy" | "treesa", seed, ntrials,
+        niters, sc_target, nslices, ..., open=[vertices])."""
         o = plan_opts(**kw)
         h = ctypes.c_void_p()
         _check(lib().tn_plan_create(net.h, ctypes.byref(o), ctypes.byref(h)))
-        return cls(net, h)
+        p = cls(net, h)
+        p.open = [int(v) for v in kw.get("open") or []]
+        return p
 
     @classmethod
     def from_tree(cls, net: Net, leaf_factors: Sequence[Sequence[int]], left: Sequence[int],
@@ -305,6 +318,26 @@ class Plan:
         b = ctypes.c_uint64()
         _check(lib().tn_plan_peak_bytes(self.h, _sr(semiring), ctypes.byref(b)))
         return b.value
+
+    SHAPE_FIELDS = ("algebra", "node", "lb", "li", "lj", "lk", "a_t", "b_t", "tb", "ti", "tj", "tk", "rm", "rn",
+                    "lsplit", "kind", "valid")
+
+    def gemm_shapes(self, semiring) -> List[Dict]:
+        """The GEMM launch shape of every inner node (one dict per device
+        algebra and node): sizes, tile, kernel kind, and whether the kernels
+        accept it."""
+        n = ctypes.c_int32()
+        _check(lib().tn_plan_gemm_shapes(self.h, _sr(semiring), 0, None, ctypes.byref(n)))
+        width = 18
+        buf = (ctypes.c_int32 * max(1, n.value * width))()
+        _check(lib().tn_plan_gemm_shapes(self.h, _sr(semiring), n.value, buf, ctypes.byref(n)))
+        out = []
+        for r in range(n.value):
+            row = buf[r * width:(r + 1) * width]
+            d = dict(zip(self.SHAPE_FIELDS, row))
+            d["kind"] = KERNEL_KIND.get(d["kind"], d["kind"])
+            out.append(d)
+        return out
 
     def export(self) -> Dict:
         """The tree as plain lists, in the oracle's plan format."""
@@ -447,6 +480,15 @@ class Context:
         r = tn_result()
         _check(lib().tn_solve(self.h, net.h, plan.h, ctypes.byref(o), ctypes.byref(r)))
         return decode(r)
+
+    def solve_open(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None) -> List[Dict]:
+        """The result tensor of a plan with open vertices: one dict per
+        assignment, entry e has bit q = value of plan.open[q]."""
+        o = solve_opts(semiring, beta, primes, slices, "stream")
+        n = 1 << len(getattr(plan, "open", []))
+        R = (tn_result * n)()
+        _check(lib().tn_solve_open(self.h, net.h, plan.h, ctypes.byref(o), n, R))
+        return [decode(R[i]) for i in range(n)]
 
     def solve_batch(self, nets: Sequence[Net], plans: Sequence[Plan], semirings, betas=None) -> List[Dict]:
         n = len(nets)

@@ -221,6 +221,8 @@ void tn_plan_opts_default(tn_plan_opts* o) {
     o->nslices = d.nslices;
     o->absorb_vertices = d.absorb ? 1 : 0;
     o->nthreads = d.nthreads;
+    o->nopen = 0;
+    o->open = nullptr;
 }
 
 static tn_status to_options(const tn_plan_opts* o, PlanOptions& p) {
@@ -241,6 +243,9 @@ static tn_status to_options(const tn_plan_opts* o, PlanOptions& p) {
     p.nslices = o->nslices;
     p.absorb = o->absorb_vertices != 0;
     p.nthreads = o->nthreads;
+    if (o->nopen < 0 || o->nopen > kMaxOpen || (o->nopen > 0 && !o->open))
+        return fail(TN_EINVAL, "nopen must be 0 .. 16, with open given");
+    p.open.assign(o->open, o->open + o->nopen);
     if (p.method != 0 && p.method != 1) return fail(TN_EINVAL, "method must be 0 (greedy) or 1 (TreeSA)");
     if (p.temperature < 0 || p.nrepeat < 0 || p.ntrials < 0 || p.niters < 0 || p.nslices < 0)
         return fail(TN_EINVAL, "negative optimizer parameter");
@@ -314,6 +319,40 @@ tn_status tn_plan_info(const tn_plan* p, tn_plan_info_t* info) {
     info->arena_entries = (uint64_t)p->plan.arena_entries;
     info->npermutes = p->plan.npermutes;
     return TN_OK;
+}
+
+tn_status tn_plan_gemm_shapes(const tn_plan* p, tn_semiring sr, int32_t cap, int32_t* rows, int32_t* nrows) {
+    TN_GUARD_BEGIN
+    if (!p || !nrows || cap < 0 || (cap > 0 && !rows)) return fail(TN_EINVAL, "invalid arguments");
+    std::vector<int> dsrs;
+    switch (sr) {
+    case TN_TROPICAL_I32: dsrs = {DSR_TROP_I32}; break;
+    case TN_TROPICAL_F32: dsrs = {DSR_TROP_F32}; break;
+    case TN_COUNTING_TROPICAL: dsrs = {DSR_CTROP}; break;
+    case TN_COUNT_EXACT: dsrs = {DSR_U64, DSR_MODP}; break;
+    case TN_PARTITION_F32: dsrs = {DSR_Z_F32}; break;
+    case TN_PARTITION_BF16: dsrs = {DSR_Z_BF16}; break;
+    default: return fail(TN_EINVAL, "unknown semiring");
+    }
+    const Plan& pl = p->plan;
+    int32_t n = 0;
+    for (size_t a = 0; a < dsrs.size(); a++)
+        for (const NodeProg& np : pl.prog) {
+            GemmShape g = choose_gemm_shape(dsrs[a], np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+            const int kind = g.mode == GEMM_THIN  ? TN_K_GEMM_THIN
+                             : g.mode == GEMM_DOT ? TN_K_GEMM_DOT
+                             : g.mfma             ? TN_K_GEMM_MFMA
+                             : g.rm == 8          ? TN_K_GEMM_BIG
+                                                  : TN_K_GEMM;
+            const int32_t row[TN_SHAPE_ROW] = {(int32_t)a, np.node, g.lb, g.li, g.lj, g.lk, g.a_t, g.b_t, g.tb,
+                                               g.ti, g.tj, g.tk, g.rm, g.rn, g.lsplit, kind,
+                                               gemm_shape_valid(dsrs[a], g) ? 1 : 0, 0};
+            if (n < cap) std::memcpy(rows + (size_t)n * TN_SHAPE_ROW, row, sizeof row);
+            n++;
+        }
+    *nrows = n;
+    return TN_OK;
+    TN_GUARD_END
 }
 
 tn_status tn_plan_peak_bytes(const tn_plan* p, tn_semiring sr, uint64_t* bytes) {
@@ -471,6 +510,23 @@ tn_status tn_solve_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k
         }
     }
     return TN_OK;
+    TN_GUARD_END
+}
+
+tn_status tn_solve_open(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_opts* o, int64_t cap,
+                        tn_result* out) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");
+    const int64_t need = (int64_t)1 << p->plan.open.size();
+    if (cap < need) return fail(TN_EINVAL, "out must hold 2^nopen results");
+    if (o->executor == 2) return fail(TN_EINVAL, "open plans run on the stream executor");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    std::vector<tn_result> t;
+    tn_result first;
+    tn_status st = solve_one(c, n->net, p->plan, *o, first, &t);
+    if (st == TN_OK)
+        for (int64_t e = 0; e < need; e++) out[e] = t[(size_t)e];
+    return st;
     TN_GUARD_END
 }
 

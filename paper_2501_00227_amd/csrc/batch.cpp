@@ -164,6 +164,10 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             st.status = fail(TN_EINVAL, "batched jobs must not be sliced; use tn_solve for sliced plans");
             continue;
         }
+        if (!it.plan->open.empty()) {
+            st.status = fail(TN_EINVAL, "the plan has open vertices: use tn_solve_open");
+            continue;
+        }
         tn_status s = TN_OK;
         st.raw = it.passes != nullptr;
         if (it.passes)

@@ -381,10 +381,12 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
 // ------------------------------------------------------------------ solve --
 static int64_t node_entries(const Plan& p, int node) { return (int64_t)1 << p.order[node].size(); }
 
-tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res) {
+tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res,
+                    std::vector<tn_result>* tensor) {
     auto t0 = std::chrono::steady_clock::now();
     if (plan.fingerprint != net.fingerprint || plan.nv != net.nv)
         return fail(TN_EINVAL, "plan was built for a different network");
+    if (!plan.open.empty() && !tensor) return fail(TN_EINVAL, "the plan has open vertices: use tn_solve_open");
     std::vector<PassSpec> passes;
     tn_status st = make_passes(net, o, passes);
     if (st != TN_OK) return st;
@@ -424,15 +426,18 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     size_t o_p1 = align256(o_p0 + (size_t)Pe * pb0);
     size_t o_meta = align256(o_p1 + (size_t)Pe * pb1);
     size_t o_w = align256(o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
+    // root entries: 2^|open| for plans with open vertices, else one
+    const int64_t nent = (nleaf > 0 && tensor) ? (int64_t)1 << plan.order[nn - 1].size() : 1;
+    const size_t acc_bytes = 16 * (size_t)nent * passes.size();
     size_t o_acc = align256(o_w + sizeof(float) * std::max<size_t>(net.wdev.size(), 1));
-    need = align256(o_acc + 16 * passes.size());
+    need = align256(o_acc + acc_bytes);
     unsigned char* base = (unsigned char*)dev_alloc(ctx, need);
     if (!base) return fail(TN_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
     Planes arena{base + o_a0, pb1 ? base + o_a1 : nullptr};
     Planes part{base + o_p0, pb1 ? base + o_p1 : nullptr};
     TensorMeta* meta = (TensorMeta*)(base + o_meta);
     float* wdev = net.wdev.empty() ? nullptr : (float*)(base + o_w);
-    st = ensure_pinned(ctx, std::max<size_t>(16 * passes.size(), sizeof(float) * net.wdev.size()) + 64);
+    st = ensure_pinned(ctx, std::max<size_t>(acc_bytes, sizeof(float) * net.wdev.size()) + 64);
     if (st != TN_OK) {
         dev_free(ctx, base, need);
         return st;
@@ -461,7 +466,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
         const int dsr = passes[pi].dsr;
         AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta, passes[pi].xval);
         ap.fix_off = net.fix_off;
-        void* acc = base + o_acc + 16 * pi;
+        void* acc = base + o_acc + 16 * (size_t)nent * pi;
         const int eb = plane_bytes(dsr, 0) + plane_bytes(dsr, 1);
         const bool is_z = dsr == DSR_Z_F32 || dsr == DSR_Z_BF16;
         if (nleaf == 0) {
@@ -530,21 +535,48 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
             }
             int root = nn - 1;
             chk(launch_accumulate(dsr, plane_at(arena, dsr, plan.node_off[root]), root, meta, acc, sl == sb ? 1 : 0,
-                                  ap, s),
+                                  ap, s, nent),
                 "root accumulate");
         }
     }
-    std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
+    std::vector<unsigned char> all(acc_bytes);
     if (herr == hipSuccess) {
-        chk(hipMemcpyAsync(ctx->pinned, base + o_acc, 16 * passes.size(), hipMemcpyDeviceToHost, s), "result copy");
+        chk(hipMemcpyAsync(ctx->pinned, base + o_acc, acc_bytes, hipMemcpyDeviceToHost, s), "result copy");
         chk(hipStreamSynchronize(s), "result sync");
-        for (size_t k = 0; k < passes.size(); k++)
-            std::memcpy(accs[k].data(), (unsigned char*)ctx->pinned + 16 * k, 16);
+        std::memcpy(all.data(), ctx->pinned, acc_bytes);
     }
     dev_free(ctx, base, need);
     if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error at ") + herr_at + ": " + hipGetErrorString(herr));
-    st = decode_result(o, passes, accs, res);
-    res.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    // decode root entry addr (storage order of the root) from every pass
+    auto decode_entry = [&](int64_t addr, tn_result& r) {
+        std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
+        for (size_t k = 0; k < passes.size(); k++)
+            std::memcpy(accs[k].data(), all.data() + 16 * ((size_t)nent * k + (size_t)addr), 16);
+        return decode_result(o, passes, accs, r);
+    };
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (tensor) {
+        // result entry bit q = open vertex plan.open[q]; find its bit in the root
+        const int k = (int)plan.open.size();
+        std::vector<int> pos(k, 0);
+        if (nleaf > 0)
+            for (int q = 0; q < k; q++) {
+                const auto& ord = plan.order[nn - 1];
+                pos[q] = (int)(std::find(ord.begin(), ord.end(), plan.open[q]) - ord.begin());
+            }
+        tensor->assign((size_t)1 << k, tn_result{});
+        for (int64_t e = 0; e < ((int64_t)1 << k); e++) {
+            int64_t addr = 0;
+            for (int q = 0; q < k; q++) addr |= ((e >> q) & 1) << pos[q];
+            tn_status s2 = decode_entry(addr, (*tensor)[e]);
+            if (s2 != TN_OK) return s2;
+            (*tensor)[e].seconds = sec;
+        }
+        res = (*tensor)[0];
+        return TN_OK;
+    }
+    st = decode_entry(0, res);
+    res.seconds = sec;
     return st;
 }
 

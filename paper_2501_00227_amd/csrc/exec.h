@@ -106,7 +106,10 @@ struct ProfScope {
     ~ProfScope();
 };
 
-tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res);
+// tensor: for plans with open vertices, receives the 2^nopen results (entry
+// bits = open vertices in the plan's order); res then holds entry 0.
+tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res,
+                    std::vector<tn_result>* tensor = nullptr);
 
 // Device algebras needed for a user algebra, and the lane primes.
 struct PassSpec {

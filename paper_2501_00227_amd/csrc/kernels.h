@@ -96,10 +96,11 @@ hipError_t launch_gemm(int dsr, Planes A, Planes B, Planes C, Planes part, const
                        const AlgebraParams& ap, TensorMeta* meta, int ma, int mb, int mc, hipStream_t s);
 hipError_t launch_split_reduce(int dsr, Planes part, Planes C, int64_t nout, int lsplit,
                                const AlgebraParams& ap, TensorMeta* meta, int mc, hipStream_t s);
-// acc (+)= root; first != 0 copies.  For the partition function the
-// accumulator is {double mantissa, int64 exponent}.
+// acc[e] (+)= root[e] for the nent root entries, 16-byte slots; first != 0
+// copies.  For the partition function a slot is {double mantissa, int64
+// exponent}.
 hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
-                             const AlgebraParams& ap, hipStream_t s);
+                             const AlgebraParams& ap, hipStream_t s, long long nent = 1);
 // The device-side identity element of a whole (empty) network.
 hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream_t s);
 int accumulator_bytes(int dsr);

@@ -245,6 +245,12 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
     gemm_tile_mfma<D>(g, blockIdx.x, smem);
 }
 
+// Dynamic LDS of the LDS-staged tile kernel: the A and B tiles of one K step
+// (rows padded as the kernel pads them).
+static long long tiled_lds_bytes(int dsr, int tb, int ti, int tj, int tk) {
+    return (1ll << (tb + tk)) * (pad_dim(1 << ti) + pad_dim(1 << tj)) * lds_elem_bytes(dsr);
+}
+
 GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
     GemmShape g{};
     g.lb = lb;
@@ -253,7 +259,6 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     g.lk = lk;
     g.a_t = a_t;
     g.b_t = b_t;
-    const int eb = lds_elem_bytes(dsr);
     const int lds_cap = 40 * 1024;
     g.mfma = 0;
     g.mode = GEMM_TILED;
@@ -311,7 +316,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
         g.ti = g.tj = 6;
         g.tb = 0;
         g.tk = lk < 5 ? lk : 5;
-        while (g.tk > 0 && (1 << g.tk) * 128 * eb > lds_cap) g.tk--;
+        while (g.tk > 0 && tiled_lds_bytes(dsr, 0, 6, 6, g.tk) > lds_cap) g.tk--;
         g.mfma = (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) ? 1 : 0;
     } else {
         g.rm = li >= 1 ? 2 : 1;
@@ -337,7 +342,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
             rest--;
         }
         g.tk = lk < 5 ? lk : 5;
-        while (g.tk > 0 && (1ll << (g.tb + g.tk)) * ((1 << g.ti) + (1 << g.tj)) * eb > lds_cap) g.tk--;
+        while (g.tk > 0 && tiled_lds_bytes(dsr, g.tb, g.ti, g.tj, g.tk) > lds_cap) g.tk--;
         // a tile needs at least RM rows / RN columns per thread
         if ((1 << g.ti) < g.rm) g.rm = 1;
         if ((1 << g.tj) < g.rn) g.rn = 1;
@@ -385,8 +390,7 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
     if ((1 << g.ti) < g.rm || (1 << g.tj) < g.rn) return false;
     long long threads = (1ll << (g.tb + g.ti + g.tj)) / (g.rm * g.rn);
     if (threads > 256 || threads < 1) return false;
-    long long lds = (1ll << (g.tb + g.tk)) * ((1 << g.ti) + 1 + (1 << g.tj) + 1) * lds_elem_bytes(dsr);
-    return lds <= 48 * 1024;
+    return tiled_lds_bytes(dsr, g.tb, g.ti, g.tj, g.tk) <= 48 * 1024;
 }
 
 size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
@@ -394,7 +398,7 @@ size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
     if (g.mode == GEMM_THIN) return ((size_t)1 << (g.lk + g.lj)) * lds_elem_bytes(dsr);
     if (g.rm == 8)
         return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * (dsr == DSR_CTROP ? 12 : 4);
-    return (size_t)(1 << (g.tb + g.tk)) * (pad_dim(1 << g.ti) + pad_dim(1 << g.tj)) * lds_elem_bytes(dsr);
+    return (size_t)tiled_lds_bytes(dsr, g.tb, g.ti, g.tj, g.tk);
 }
 
 template <int D, int RM, int RN>
@@ -645,16 +649,26 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, i64 nout, int lsp
 }
 
 // ---------------------------------------------------------- accumulate ---
+// Entry e of the root (a scalar, or the tensor over the open vertices) is
+// folded into the 16-byte accumulator slot e.
 template <int D>
-__global__ void accumulate_kernel(Planes root, int mroot, TensorMeta* meta, void* acc, int first, AlgebraParams ap) {
-    accumulate_one<D>(root, mroot, meta, acc, first, ap);
+__global__ void accumulate_kernel(Planes root, int mroot, TensorMeta* meta, void* acc, int first, AlgebraParams ap,
+                                  long long nent) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nent) return;
+    Planes r;
+    r.p0 = (unsigned char*)root.p0 + e * plane_bytes_dev<D>(0);
+    r.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)root.p1 + e * plane_bytes_dev<D>(1) : nullptr;
+    accumulate_one<D>(r, mroot, meta, (unsigned char*)acc + 16 * e, first, ap);
 }
 
 hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
-                             const AlgebraParams& ap, hipStream_t s) {
-#define TN_AC(D)                                                                  \
-    case D:                                                                       \
-        accumulate_kernel<D><<<1, 1, 0, s>>>(root, mroot, meta, acc, first, ap); \
+                             const AlgebraParams& ap, hipStream_t s, long long nent) {
+    if (nent < 1) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((nent + 255) / 256), threads = nent < 256 ? (unsigned)nent : 256u;
+#define TN_AC(D)                                                                                        \
+    case D:                                                                                             \
+        accumulate_kernel<D><<<blocks, threads, 0, s>>>(root, mroot, meta, acc, first, ap, nent); \
         break;
     switch (dsr) {
         TN_AC(DSR_TROP_I32)

@@ -30,7 +30,7 @@ struct Cost {
 // leaf indices below N and O the union of leaf indices outside N's subtree
 // (an index stays open while it is still needed elsewhere, Sec. 3.2 einsum).
 template <int W>
-void outputs(const Tree& t, const std::vector<Bits<W>>& leaf_ix, std::vector<Bits<W>>& out) {
+void outputs(const Tree& t, const std::vector<Bits<W>>& leaf_ix, std::vector<Bits<W>>& out, const Bits<W>& open) {
     int nn = 2 * t.nleaf - 1;
     std::vector<Bits<W>> U(nn), O(nn);
     std::vector<int> post;
@@ -50,7 +50,7 @@ void outputs(const Tree& t, const std::vector<Bits<W>>& leaf_ix, std::vector<Bit
     }
     for (int n : post)
         U[n] = n < t.nleaf ? leaf_ix[n] : U[t.L[n - t.nleaf]] | U[t.R[n - t.nleaf]];
-    O[t.root] = Bits<W>();
+    O[t.root] = open;  // open vertices are held by the output
     for (int k = (int)post.size() - 1; k >= 0; k--) {
         int n = post[k];
         if (n < t.nleaf) continue;
@@ -81,7 +81,8 @@ Cost<W> tree_cost(const Tree& t, const std::vector<Bits<W>>& out) {
 // L = size(Ti*Tj) - alpha (size(Ti) + size(Tj)); with temperature T > 0 the
 // pair is sampled with probability proportional to e^{-L/T}.
 template <int W>
-Tree greedy_once(const std::vector<Bits<W>>& leaf_ix, int nv, double alpha, double T, Rng& rng) {
+Tree greedy_once(const std::vector<Bits<W>>& leaf_ix, int nv, double alpha, double T, Rng& rng,
+                 const Bits<W>& open) {
     int n = (int)leaf_ix.size();
     Tree t;
     t.nleaf = n;
@@ -101,6 +102,7 @@ Tree greedy_once(const std::vector<Bits<W>>& leaf_ix, int nv, double alpha, doub
             holders[x].push_back(i);
         });
     }
+    open.for_each([&](int x) { cnt[x]++; });  // held by the output: never summed
     int next = n, nalive = n;
     std::vector<uint64_t> pairs;
     std::vector<double> costs;
@@ -199,14 +201,14 @@ bool better(const Cost<W>& a, const Cost<W>& b) {
 
 template <int W>
 Tree greedy(const std::vector<Bits<W>>& leaf_ix, int nv, double alpha, double T, int nrepeat,
-            uint64_t seed) {
+            uint64_t seed, const Bits<W>& open) {
     Tree best;
     Cost<W> bc;
     std::vector<Bits<W>> out;
     for (int r = 0; r < std::max(1, nrepeat); r++) {
         Rng rng(seed * 1000003ull + (uint64_t)r);
-        Tree t = greedy_once<W>(leaf_ix, nv, alpha, T, rng);
-        outputs<W>(t, leaf_ix, out);
+        Tree t = greedy_once<W>(leaf_ix, nv, alpha, T, rng, open);
+        outputs<W>(t, leaf_ix, out, open);
         Cost<W> c = tree_cost<W>(t, out);
         if (r == 0 || better<W>(c, bc)) {
             best = t;
@@ -230,6 +232,7 @@ struct Annealer {
     std::vector<int> hist;             // number of inner nodes of each rank
     double TC = 0, RW = 0;
     double sc_target, ws, wrw;
+    Bits<W> open;  // open vertices: kept to the root, never sliced
 
     void load(const Tree& t, const std::vector<Bits<W>>& leaf_ix) {
         nleaf = t.nleaf;
@@ -242,7 +245,7 @@ struct Annealer {
             R[n] = t.R[n - nleaf];
             P[L[n]] = P[R[n]] = n;
         }
-        outputs<W>(t, leaf_ix, out);
+        outputs<W>(t, leaf_ix, out, open);
         refresh();
     }
     int root() const {
@@ -405,7 +408,7 @@ int choose_slice(const Annealer<W>& a) {
     }
     int best = -1;
     for (int x = 0; x < W * 64; x++) {
-        if (!hits[x]) continue;
+        if (!hits[x] || a.open.has(x)) continue;
         if (best < 0 || hits[x] > hits[best] || (hits[x] == hits[best] && gain[x] > gain[best])) best = x;
     }
     return best;
@@ -413,10 +416,10 @@ int choose_slice(const Annealer<W>& a) {
 
 template <int W>
 SAResult<W> treesa_trial(const std::vector<Bits<W>>& leaf_ix0, int nv, const PlanOptions& o,
-                         uint64_t seed) {
+                         uint64_t seed, const Bits<W>& open) {
     Rng rng(seed);
     std::vector<Bits<W>> leaf_ix = leaf_ix0;
-    Tree t0 = greedy<W>(leaf_ix, nv, 0.0, 0.0, 1, seed);
+    Tree t0 = greedy<W>(leaf_ix, nv, 0.0, 0.0, 1, seed, open);
     SAResult<W> res;
     if ((int)leaf_ix.size() < 3) {
         res.tree = t0;
@@ -430,6 +433,7 @@ SAResult<W> treesa_trial(const std::vector<Bits<W>>& leaf_ix0, int nv, const Pla
     a.sc_target = o.sc_target;
     a.ws = o.sc_weight;
     a.wrw = o.rw_weight;
+    a.open = open;
     a.load(t0, leaf_ix);
     a.anneal(betas, o.niters, rng);
     // slicing: fix one index at a time while the largest intermediate is
@@ -462,20 +466,23 @@ tn_status optimize_w(const Net& net, const std::vector<Leaf>& leaves, const Plan
     std::vector<int> occ(net.nv, 0);
     for (auto& l : leaves)
         for (int x : l.scope) occ[x]++;
+    Bits<W> open;
+    for (int x : o.open) open.set(x);
     std::vector<Bits<W>> leaf_ix(nleaf);
     for (int i = 0; i < nleaf; i++)
         for (int x : leaves[i].scope)
-            if (occ[x] > 1) leaf_ix[i].set(x);
+            if (occ[x] > 1 || open.has(x)) leaf_ix[i].set(x);
     Tree best;
     sliced.clear();
     if (o.method == 0) {
-        best = greedy<W>(leaf_ix, net.nv, o.alpha, o.temperature, o.nrepeat, o.seed);
+        best = greedy<W>(leaf_ix, net.nv, o.alpha, o.temperature, o.nrepeat, o.seed, open);
         // optional slicing on a greedy tree
         if (o.nslices > 0) {
             Annealer<W> a;
             a.sc_target = o.sc_target;
             a.ws = o.sc_weight;
             a.wrw = o.rw_weight;
+            a.open = open;
             a.load(best, leaf_ix);
             while ((int)sliced.size() < o.nslices && a.sc() > (int)o.sc_target) {
                 int x = choose_slice<W>(a);
@@ -497,7 +504,7 @@ tn_status optimize_w(const Net& net, const std::vector<Leaf>& leaves, const Plan
         for (int th = 0; th < nth; th++)
             pool.emplace_back([&]() {
                 for (int k; (k = next.fetch_add(1)) < nt;)
-                    res[k] = treesa_trial<W>(leaf_ix, net.nv, o, o.seed * 7919ull + (uint64_t)k);
+                    res[k] = treesa_trial<W>(leaf_ix, net.nv, o, o.seed * 7919ull + (uint64_t)k, open);
             });
         for (auto& th : pool) th.join();
         int bi = 0;

@@ -32,9 +32,10 @@ std::vector<int> set_minus(const std::vector<int>& a, const std::vector<int>& b)
 bool has(const std::vector<int>& a, int x) { return std::binary_search(a.begin(), a.end(), x); }
 
 // Validate a tree and fill node outputs by the einsum rule.  Nodes are given
-// with leaves first and inner nodes whose children have smaller ids.
+// with leaves first and inner nodes whose children have smaller ids.  Open
+// vertices count as held by the output as well, so they stay to the root.
 tn_status build_nodes(const Net& net, const std::vector<Leaf>& leaves, const std::vector<int>& left,
-                      const std::vector<int>& right, std::vector<Node>& nodes) {
+                      const std::vector<int>& right, std::vector<Node>& nodes, const std::vector<int>& open = {}) {
     int nleaf = (int)leaves.size();
     int ninner = (int)left.size();
     if (nleaf < 1) return fail(TN_EINVAL, "a plan needs at least one leaf");
@@ -66,6 +67,7 @@ tn_status build_nodes(const Net& net, const std::vector<Leaf>& leaves, const std
     std::vector<int> total(net.nv, 0);
     for (auto& l : leaves)
         for (int x : l.scope) total[x]++;
+    for (int v : open) total[v]++;
     nodes.assign(nn, Node());
     std::vector<std::map<int, int>> cnt(nn);
     for (int x = 0; x < nn; x++) {
@@ -83,7 +85,9 @@ tn_status build_nodes(const Net& net, const std::vector<Leaf>& leaves, const std
         for (auto& [v, c] : cnt[x])
             if (c < total[v]) nodes[x].out.push_back(v);
     }
-    if (!nodes.back().out.empty()) return fail(TN_EINVAL, "root keeps open indices");
+    std::vector<int> want = open;
+    std::sort(want.begin(), want.end());
+    if (nodes.back().out != want) return fail(TN_EINVAL, "root keeps open indices");
     return TN_OK;
 }
 
@@ -454,13 +458,22 @@ tn_status plan_create(const Net& net, const PlanOptions& o, Plan& out) {
     out.fingerprint = net.fingerprint;
     out.kind = net.kind;
     out.leaves = make_leaves(net, o.absorb);
+    {
+        std::vector<char> seen(net.nv, 0);
+        for (int v : o.open) {
+            if (v < 0 || v >= net.nv) return fail(TN_EINVAL, "open vertex out of range");
+            if (seen[v]++) return fail(TN_EINVAL, "open vertex listed twice");
+        }
+        if ((int)o.open.size() > kMaxOpen) return fail(TN_EINVAL, "at most 16 open vertices");
+    }
+    out.open = o.open;
     if (out.leaves.empty()) {  // nv = 0: the empty network, result is the identity
         return TN_OK;
     }
     std::vector<int> L, R, sliced;
     tn_status st = optimize_tree(net, out.leaves, o, L, R, sliced);
     if (st != TN_OK) return st;
-    st = build_nodes(net, out.leaves, L, R, out.nodes);
+    st = build_nodes(net, out.leaves, L, R, out.nodes, o.open);
     if (st != TN_OK) return st;
     out.sliced = sliced;
     std::sort(out.sliced.begin(), out.sliced.end());

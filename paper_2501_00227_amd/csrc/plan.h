@@ -93,6 +93,7 @@ struct Plan {
     std::vector<Leaf> leaves;
     std::vector<Node> nodes;
     std::vector<int> sliced;
+    std::vector<int> open;  // open vertices in the caller's order: bit q of a result entry is open[q]
     // complexity (log2), Sec. 4.1; tc includes the 2^nsliced factor
     double tc = 0, sc = 0, rwc = 0;
     int max_rank = 0;
@@ -122,7 +123,10 @@ struct PlanOptions {
     int ntrials = 10, niters = 50, nslices = 0;
     bool absorb = true;
     int nthreads = 0;
+    std::vector<int> open;  // open vertices (kept to the root), in the caller's order
 };
+
+constexpr int kMaxOpen = 16;
 
 // Leaves of the network: one per edge, plus one per vertex unless the
 // vertex tensor is folded into its first incident edge.

@@ -174,3 +174,50 @@ def test_spin_glass_network_validation_and_structure():
     a = tn.Plan.create(sg, seed=3).complexity()
     b = tn.Plan.create(isn, seed=3).complexity()
     assert a == b
+
+
+SEMIRINGS = ["tropical_i32", "tropical_f32", "counting_tropical", "count_exact", "partition_f32", "partition_bf16"]
+
+
+def test_every_planned_gemm_shape_is_accepted_by_the_kernels():
+    """Dense small graphs give nodes with wide batch groups (b up to 2^8) and
+    narrow M / N; sparse and lattice graphs give the wide tiles.  Every node of
+    every algebra must get a launch shape the kernels accept."""
+    graphs = [gg.gnp(n, p, 700 + n) for n in (10, 16, 20, 24) for p in (0.3, 0.6, 0.9)]
+    graphs += [gg.complete(12), gg.complete_bipartite(8, 9), gg.square_lattice(10), gg.kings_subgraph(10, 0.8, 1),
+               gg.random_regular(120, 3, 0)]
+    seen = set()
+    for g in graphs:
+        net = tn.Net.from_graph(g)
+        for kw in ({"seed": 0}, {"method": "treesa", "ntrials": 1, "niters": 2, "seed": 1}):
+            plan = tn.Plan.create(net, **kw)
+            for sr in SEMIRINGS:
+                for row in plan.gemm_shapes(sr):
+                    seen.add((sr, row["kind"]))
+                    assert row["valid"] == 1, (g.name, kw, sr, row)
+    # the sweep reaches the small-tile, register-tiled and long-K families
+    kinds = {k for _, k in seen}
+    assert {"gemm", "gemm_big", "gemm_dot", "gemm_mfma"} <= kinds, kinds
+
+
+def test_open_vertices_stay_to_the_root_and_are_never_sliced():
+    g = gg.random_regular(40, 3, 0)
+    net = tn.Net.from_graph(g)
+    opn = [5, 3, 17]
+    for kw in ({"seed": 0}, {"method": "treesa", "ntrials": 1, "niters": 3, "seed": 0},
+               {"method": "treesa", "ntrials": 1, "niters": 3, "seed": 0, "sc_target": 6, "nslices": 4}):
+        plan = tn.Plan.create(net, open=opn, **kw)
+        e = plan.export()
+        assert e["indices"][-1] == sorted(opn)  # the root's indices
+        assert not set(e["sliced"]) & set(opn)
+        for sr in SEMIRINGS:
+            assert all(r["valid"] for r in plan.gemm_shapes(sr))
+    assert tn.Plan.create(net, method="treesa", ntrials=1, niters=3, seed=0, sc_target=6, nslices=4,
+                          open=opn).info()["nsliced"] > 0
+    # an isolated open vertex (its only tensor is its own leaf) stays open too
+    iso = tn.Net.from_graph(gg.disjoint_union(gg.path(3), gg.empty(1)))
+    assert tn.Plan.create(iso, open=[3]).export()["indices"][-1] == [3]
+    for bad in ([40], [1, 1], list(range(17)), [-1]):
+        with pytest.raises(tn.TnError) as ei:
+            tn.Plan.create(net, open=bad)
+        assert ei.value.code == tn.TN_EINVAL
