@@ -317,12 +317,14 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline step only")
     ap.add_argument("--executor", default="persistent", choices=["persistent", "stream"],
                     help="persistent launch per step (default) or per-node stream launches")
+    ap.add_argument("--widened", action="store_true",
+                    help="only the polynomial, spin-glass, maximum-configuration and conditioning lines")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (for scaling hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the path would shard by slices and jobs with one final "
-              "(+)-reduction of a scalar root, which this build does not run; use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: several GPUs would share slices and jobs with one final "
+              "(+)-reduction of a scalar root, which is not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -340,6 +342,11 @@ def main():
     g, net, plan = build_k2(args.seed)
     tc, sc, rwc = plan.complexity()
     ctx = tn.Context(0)
+    if args.widened:
+        print(json.dumps({"independence_polynomial": independence_polynomial(ctx, net, plan, tc),
+                          "spin_glass_buckyball": buckyball(ctx), "single_config_max": single_config(ctx, net, plan),
+                          "conditioned": conditioned_batch(ctx, g, plan)}))
+        return
     for _ in range(args.warmup):
         run_step(ctx, net, plan, args.executor)
     torch.cuda.synchronize()

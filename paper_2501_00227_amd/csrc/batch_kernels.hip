@@ -154,8 +154,7 @@ __device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count,
             i64 o = unit * 256 + threadIdx.x;
             float lmax = 0.0f;
             if (o < nd.nout) {
-                V acc = A::zero(j.ap);
-                for (int s = 0; s < (1 << nd.g.lsplit); s++) acc = A::add(acc, A::load(P, (i64)s * nd.nout + o), j.ap);
+                const V acc = split_sum<D>(P, nd.nout, o, 1 << nd.g.lsplit, j.ap);
                 A::store(C, o, acc);
                 if constexpr (is_z<D>()) lmax = acc;
             }

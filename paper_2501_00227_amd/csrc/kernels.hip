@@ -319,9 +319,13 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
         while (g.tk > 0 && tiled_lds_bytes(dsr, 0, 6, 6, g.tk) > lds_cap) g.tk--;
         g.mfma = (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) ? 1 : 0;
     } else {
-        g.rm = li >= 1 ? 2 : 1;
-        g.rn = lj >= 1 ? 2 : 1;
-        const int lr = (g.rm == 2) + (g.rn == 2);
+        // little reuse per output (K <= 8) and many outputs: 4 x 4 per
+        // thread, 4096 outputs per workgroup, so fewer and larger tiles
+        // carry the output traffic (each tile pays one load round trip)
+        const bool wide = lk <= 3 && li >= 2 && lj >= 2 && lb + li + lj >= 14;
+        g.rm = wide ? 4 : (li >= 1 ? 2 : 1);
+        g.rn = wide ? 4 : (lj >= 1 ? 2 : 1);
+        const int lr = (g.rm == 4 ? 2 : g.rm == 2 ? 1 : 0) + (g.rn == 4 ? 2 : g.rn == 2 ? 1 : 0);
         const int tot = 8 + lr;  // log2 outputs per workgroup
         g.ti = li < 5 ? li : 5;
         g.tj = lj < 5 ? lj : 5;
@@ -506,8 +510,7 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(Planes part, Planes C
     float lmax = 0.0f;
     i64 o = (i64)blockIdx.x * 256 + threadIdx.x;
     if (o < nout) {
-        V acc = A::zero(ap);
-        for (int s = 0; s < S; s++) acc = A::add(acc, A::load(part, (i64)s * nout + o), ap);
+        const V acc = split_sum<D>(part, nout, o, S, ap);
         A::store(C, o, acc);
         if constexpr (is_z<D>()) lmax = acc;
     }

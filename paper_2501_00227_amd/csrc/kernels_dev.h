@@ -1013,6 +1013,25 @@ __device__ void gemm_tile_dot(const GemmArgs& g, u64 tile, unsigned char* smem) 
 
 // --------------------------------------------------------- split reduce --
 // C[o] = (+)_s part[s][o] for one output o, by the whole workgroup.
+// (+) of the S partials of output o, folded in split order; the loads are
+// issued eight at a time so their latencies overlap.
+template <int D>
+__device__ inline typename Alg<D>::V split_sum(Planes part, i64 nout, i64 o, int S, const AlgebraParams& ap) {
+    using A = Alg<D>;
+    using V = typename A::V;
+    V acc = A::zero(ap);
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+        V v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = A::load(part, (i64)(s + u) * nout + o);
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc = A::add(acc, v[u], ap);
+    }
+    for (; s < S; s++) acc = A::add(acc, A::load(part, (i64)s * nout + o), ap);
+    return acc;
+}
+
 template <int D>
 __device__ void split_reduce_one(Planes part, Planes C, i64 nout, int lsplit, const AlgebraParams& ap,
                                  TensorMeta* meta, int mc, i64 o, typename Alg<D>::V* red) {
