@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <queue>
 
 namespace tn {
@@ -116,6 +117,168 @@ std::vector<int> critical_path_order(const std::vector<BTask>& bt, const std::ve
     return rank;
 }
 
+struct JobPlan {
+    int item, pass;
+    const Plan* plan;
+    int dsr;
+    uint32_t prime, xval;
+    DevProgram* dp;
+    const std::vector<NodeLaunch>* nl;
+    int64_t E, Pe;
+    size_t o_arena0, o_arena1, o_part0, o_part1, o_meta, o_acc;
+};
+
+// The tasks, nodes and fused-subtree lists of one job, built once per (plan,
+// algebra) in a launch and copied for every job that shares them (many
+// passes of one network differ only in their prime or evaluation point):
+// node ids, subtree offsets and counter ids are relative to the job's own
+// first entries, the job index is 0.
+struct JobTemplate {
+    std::vector<BNode> bn;
+    std::vector<BTask> bt;
+    std::vector<int> subtree;
+    int ncounters = 0;
+    double ops = 0, bytes = 0, work = 0;
+    std::vector<int> order;  // task indices in critical-path-first order
+    int bn0 = -1, sub0 = 0;  // where the launch holds its nodes and subtree lists (shared by its jobs)
+};
+
+void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
+    const Plan& p = *jp.plan;
+    auto add = [&](int kind, int node, int aux, int64_t tile, Counter d0, Counter d1, int signal, int lvl,
+                   int count = 1) {
+        BTask t;
+        t.kind = kind;
+        t.job = 0;
+        t.node = node;
+        t.aux = aux;
+        t.tile = tile;
+        t.dep0 = d0.id;
+        t.need0 = d0.need;
+        t.dep1 = d1.id;
+        t.need1 = d1.need;
+        t.signal = signal;
+        t.count = count;
+        T.bt.push_back(t);
+        (void)lvl;
+    };
+    if (p.nleaf() == 0) {
+        add(BT_ONE, -1, 0, 0, Counter(), Counter(), -1, 0);
+        return;
+    }
+    const int nleaf = p.nleaf();
+    Counter leaves_done{T.ncounters++, 1, 0};
+    add(BT_LEAVES, -1, 0, 0, Counter(), Counter(), leaves_done.id, 0);
+    std::vector<Counter> final_of(p.nodes.size());
+    for (int l = 0; l < nleaf; l++) final_of[l] = leaves_done;
+    const int npl = plane_bytes(jp.dsr, 1) ? 2 : 1;
+    // small subtrees (every tensor <= 2^fuse_rank entries) run as one
+    // task each: one workgroup contracts the whole subtree in order
+    const int ninner = (int)p.prog.size();
+    std::vector<char> small(ninner, 0);
+    std::vector<int> parent_t(p.nodes.size(), -1);
+    for (int t = 0; t < ninner; t++) {
+        const NodeProg& np = p.prog[t];
+        parent_t[np.a] = parent_t[np.b] = t;
+        int r = std::max({(int)p.order[np.a].size(), (int)p.order[np.b].size(), (int)p.order[np.node].size()});
+        bool ok = r <= fuse_rank;
+        for (int ch : {np.a, np.b})
+            if (ch >= nleaf && !small[ch - nleaf]) ok = false;
+        small[t] = ok;
+    }
+    const int bn0 = 0;
+    for (int t = 0; t < ninner; t++) {
+        const NodeProg& np = p.prog[t];
+        const NodeLaunch& nl = (*jp.nl)[t];
+        BNode N{};
+        N.g = nl.shape;
+        N.ma = np.a;
+        N.mb = np.b;
+        N.mc = np.node;
+        N.a_off = np.perm_a ? np.dag_a_tmp : p.node_off_dag[np.a];
+        N.b_off = np.perm_b ? np.dag_b_tmp : p.node_off_dag[np.b];
+        N.c_off = np.dag_c_off;
+        N.nout = (int64_t)1 << (N.g.lb + N.g.li + N.g.lj);
+        N.reduce_per_block = N.nout < 1024 ? 1 : 0;
+        N.part_off = jp.dp->part_off_dag[jp.dsr][t];
+        for (int side = 0; side < 2; side++) {
+            int child = side ? np.b : np.a;
+            bool perm = side ? np.perm_b : np.perm_a;
+            N.pp[side] = nullptr;
+            if (!perm) continue;
+            int slot = side ? jp.dp->perm_slot_b[t] : jp.dp->perm_slot_a[t];
+            int rank = (int)p.order[child].size();
+            N.pp[side] = jp.dp->perms + slot;
+            N.psrc[side] = p.node_off_dag[child];
+            N.pdst[side] = side ? np.dag_b_tmp : np.dag_a_tmp;
+            N.prank[side] = rank;
+            N.ptile_bits[side] = perm_tile_bits(rank);
+        }
+        T.ops += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk));
+        T.bytes += (std::exp2((double)(N.g.lb + N.g.li + N.g.lk)) + std::exp2((double)(N.g.lb + N.g.lk + N.g.lj)) +
+                          std::exp2((double)(N.g.lb + N.g.li + N.g.lj))) *
+                         (plane_bytes(jp.dsr, 0) + plane_bytes(jp.dsr, 1));
+        T.bn.push_back(N);
+        if (small[t]) {
+            bool sub_root = parent_t[np.node] < 0 || !small[parent_t[np.node]];
+            if (!sub_root) continue;
+            // collect the subtree's inner nodes in execution order
+            std::vector<int> stack{t}, members;
+            while (!stack.empty()) {
+                int u = stack.back();
+                stack.pop_back();
+                members.push_back(u);
+                for (int ch : {p.prog[u].a, p.prog[u].b})
+                    if (ch >= nleaf) stack.push_back(ch - nleaf);
+            }
+            std::sort(members.begin(), members.end());
+            int off = (int)T.subtree.size();
+            for (int u : members) T.subtree.push_back(bn0 + u);
+            Counter done{T.ncounters++, 1, leaves_done.level + 1};
+            add(BT_SUBTREE, off, (int)members.size(), 0, leaves_done, Counter(), done.id, done.level);
+            final_of[np.node] = done;
+            continue;
+        }
+        const int nidx = bn0 + t;
+        Counter ready[2];
+        for (int side = 0; side < 2; side++) {
+            int child = side ? np.b : np.a;
+            if (!N.pp[side]) {
+                ready[side] = final_of[child];
+                continue;
+            }
+            int64_t ntiles = (int64_t)1 << (N.prank[side] - N.ptile_bits[side]);
+            int64_t per = chunk(ntiles);
+            int64_t ntask = ntiles / per;
+            Counter c{T.ncounters++, (int)(ntask * npl), final_of[child].level + 1};
+            for (int pl = 0; pl < npl; pl++)
+                for (int64_t k = 0; k < ntask; k++)
+                    add(BT_PERM, nidx, side * 2 + pl, k * per, final_of[child], Counter(), c.id, c.level, (int)per);
+            ready[side] = c;
+        }
+        int64_t nblocks = (int64_t)1 << ((N.g.lb - N.g.tb) + (N.g.li - N.g.ti) + (N.g.lj - N.g.tj) + N.g.lsplit);
+        int64_t per = chunk(nblocks);
+        Counter gdone{T.ncounters++, (int)(nblocks / per), std::max(ready[0].level, ready[1].level) + 1};
+        for (int64_t k = 0; k < nblocks / per; k++)
+            add(BT_GEMM, nidx, 0, k * per, ready[0], ready[1], gdone.id, gdone.level, (int)per);
+        Counter fin = gdone;
+        if (N.g.lsplit > 0) {
+            int64_t nred = N.reduce_per_block ? N.nout : (N.nout + 255) / 256;
+            int64_t rper = 1;
+            while (nred / rper > kMaxTasksPerNode) rper *= 2;
+            int64_t nrt = (nred + rper - 1) / rper;
+            Counter rdone{T.ncounters++, (int)nrt, gdone.level + 1};
+            for (int64_t k = 0; k < nrt; k++)
+                add(BT_REDUCE, nidx, 0, k * rper, gdone, Counter(), rdone.id, rdone.level,
+                    (int)std::min<int64_t>(rper, nred - k * rper));
+            fin = rdone;
+        }
+        final_of[np.node] = fin;
+    }
+    int root = (int)p.nodes.size() - 1;
+    add(BT_ACCUM, -1, 0, p.node_off_dag[root], final_of[root], Counter(), -1, final_of[root].level + 1);
+}
+
 }  // namespace
 
 int device_cu_count(tn_ctx* ctx) {
@@ -129,16 +292,6 @@ int device_cu_count(tn_ctx* ctx) {
 tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch& L, const DevAllocFn& alloc) {
     L = BatchLaunch();
     L.items.resize(items.size());
-    struct JobPlan {
-        int item, pass;
-        const Plan* plan;
-        int dsr;
-        uint32_t prime, xval;
-        DevProgram* dp;
-        const std::vector<NodeLaunch>* nl;
-        int64_t E, Pe;
-        size_t o_arena0, o_arena1, o_part0, o_part1, o_meta, o_acc;
-    };
     std::vector<JobPlan> jobs;
     std::vector<size_t> item_w_off(items.size(), 0);
     size_t data = 0;
@@ -229,9 +382,11 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     std::vector<BJob> bj(jobs.size());
     std::vector<BNode> bn;
     std::vector<BTask> bt;
-    std::vector<int> level;
     int ncounters = 0;
     const int fuse_rank = small_rank(jobs.size(), device_cu_count(ctx) * 2);
+    std::map<std::pair<const Plan*, int>, JobTemplate> templates;
+    std::vector<const JobTemplate*> job_tmpl(jobs.size(), nullptr);
+    std::vector<int> job_task0(jobs.size(), 0);
     for (size_t ji = 0; ji < jobs.size(); ji++) {
         JobPlan& jp = jobs[ji];
         const Plan& p = *jp.plan;
@@ -253,171 +408,92 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         J.leaves = jp.dp ? jp.dp->leaves : nullptr;
         J.spos = jp.dp ? jp.dp->slice_pos : nullptr;
         J.w = items[jp.item].net->wdev.empty() ? nullptr : (const float*)(dbase + item_w_off[jp.item]);
-        auto add = [&](int kind, int node, int aux, int64_t tile, Counter d0, Counter d1, int signal, int lvl,
-                       int count = 1) {
-            BTask t;
-            t.kind = kind;
+        // the job's tasks: a copy of its template with ids shifted
+        const auto key = std::make_pair(jp.plan, jp.dsr);
+        auto ti = templates.find(key);
+        if (ti == templates.end()) {
+            ti = templates.emplace(key, JobTemplate()).first;
+            JobTemplate& T = ti->second;
+            build_template(jp, fuse_rank, T);
+            const std::vector<int> rank = critical_path_order(T.bt, T.bn, T.subtree, T.ncounters);
+            T.order.assign(T.bt.size(), 0);
+            for (size_t k = 0; k < rank.size(); k++) T.order[(size_t)rank[k]] = (int)k;
+            T.work = 2.0e4 * (double)T.bt.size();
+            for (auto& N : T.bn)
+                T.work += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk)) * (N.g.rm == 4 ? 0.5 : 1.0);
+        }
+        JobTemplate& T = ti->second;
+        if (T.bn0 < 0) {  // nodes and subtree lists: once per template, shared by its jobs
+            T.bn0 = (int)bn.size();
+            T.sub0 = (int)L.subtree_list.size();
+            bn.insert(bn.end(), T.bn.begin(), T.bn.end());
+            for (int x : T.subtree) L.subtree_list.push_back(T.bn0 + x);
+        }
+        job_tmpl[ji] = &T;
+        job_task0[ji] = (int)bt.size();
+        const int bn0 = T.bn0, sub0 = T.sub0, c0 = ncounters;
+        for (const BTask& t0 : T.bt) {
+            BTask t = t0;
             t.job = (int)ji;
-            t.node = node;
-            t.aux = aux;
-            t.tile = tile;
-            t.dep0 = d0.id;
-            t.need0 = d0.need;
-            t.dep1 = d1.id;
-            t.need1 = d1.need;
-            t.signal = signal;
-            t.count = count;
+            if (t.kind == BT_PERM || t.kind == BT_GEMM || t.kind == BT_REDUCE) t.node += bn0;
+            if (t.kind == BT_SUBTREE) t.node += sub0;
+            if (t.dep0 >= 0) t.dep0 += c0;
+            if (t.dep1 >= 0) t.dep1 += c0;
+            if (t.signal >= 0) t.signal += c0;
             bt.push_back(t);
-            level.push_back(lvl);
-        };
-        if (J.nleaf == 0) {
-            add(BT_ONE, -1, 0, 0, Counter(), Counter(), -1, 0);
-            continue;
         }
-        const int nleaf = J.nleaf;
-        Counter leaves_done{ncounters++, 1, 0};
-        add(BT_LEAVES, -1, 0, 0, Counter(), Counter(), leaves_done.id, 0);
-        std::vector<Counter> final_of(p.nodes.size());
-        for (int l = 0; l < nleaf; l++) final_of[l] = leaves_done;
-        const int npl = plane_bytes(jp.dsr, 1) ? 2 : 1;
-        // small subtrees (every tensor <= 2^fuse_rank entries) run as one
-        // task each: one workgroup contracts the whole subtree in order
-        const int ninner = (int)p.prog.size();
-        std::vector<char> small(ninner, 0);
-        std::vector<int> parent_t(p.nodes.size(), -1);
-        for (int t = 0; t < ninner; t++) {
-            const NodeProg& np = p.prog[t];
-            parent_t[np.a] = parent_t[np.b] = t;
-            int r = std::max({(int)p.order[np.a].size(), (int)p.order[np.b].size(), (int)p.order[np.node].size()});
-            bool ok = r <= fuse_rank;
-            for (int ch : {np.a, np.b})
-                if (ch >= nleaf && !small[ch - nleaf]) ok = false;
-            small[t] = ok;
-        }
-        const int bn0 = (int)bn.size();
-        for (int t = 0; t < ninner; t++) {
-            const NodeProg& np = p.prog[t];
-            const NodeLaunch& nl = (*jp.nl)[t];
-            BNode N{};
-            N.g = nl.shape;
-            N.job = (int)ji;
-            N.ma = np.a;
-            N.mb = np.b;
-            N.mc = np.node;
-            N.a_off = np.perm_a ? np.dag_a_tmp : p.node_off_dag[np.a];
-            N.b_off = np.perm_b ? np.dag_b_tmp : p.node_off_dag[np.b];
-            N.c_off = np.dag_c_off;
-            N.nout = (int64_t)1 << (N.g.lb + N.g.li + N.g.lj);
-            N.reduce_per_block = N.nout < 1024 ? 1 : 0;
-            N.part_off = jp.dp->part_off_dag[jp.dsr][t];
-            for (int side = 0; side < 2; side++) {
-                int child = side ? np.b : np.a;
-                bool perm = side ? np.perm_b : np.perm_a;
-                N.pp[side] = nullptr;
-                if (!perm) continue;
-                int slot = side ? jp.dp->perm_slot_b[t] : jp.dp->perm_slot_a[t];
-                int rank = (int)p.order[child].size();
-                N.pp[side] = jp.dp->perms + slot;
-                N.psrc[side] = p.node_off_dag[child];
-                N.pdst[side] = side ? np.dag_b_tmp : np.dag_a_tmp;
-                N.prank[side] = rank;
-                N.ptile_bits[side] = perm_tile_bits(rank);
-            }
-            L.total_ops += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk));
-            L.total_bytes += (std::exp2((double)(N.g.lb + N.g.li + N.g.lk)) + std::exp2((double)(N.g.lb + N.g.lk + N.g.lj)) +
-                              std::exp2((double)(N.g.lb + N.g.li + N.g.lj))) *
-                             (plane_bytes(jp.dsr, 0) + plane_bytes(jp.dsr, 1));
-            bn.push_back(N);
-            if (small[t]) {
-                bool sub_root = parent_t[np.node] < 0 || !small[parent_t[np.node]];
-                if (!sub_root) continue;
-                // collect the subtree's inner nodes in execution order
-                std::vector<int> stack{t}, members;
-                while (!stack.empty()) {
-                    int u = stack.back();
-                    stack.pop_back();
-                    members.push_back(u);
-                    for (int ch : {p.prog[u].a, p.prog[u].b})
-                        if (ch >= nleaf) stack.push_back(ch - nleaf);
-                }
-                std::sort(members.begin(), members.end());
-                int off = (int)L.subtree_list.size();
-                for (int u : members) L.subtree_list.push_back(bn0 + u);
-                Counter done{ncounters++, 1, leaves_done.level + 1};
-                add(BT_SUBTREE, off, (int)members.size(), 0, leaves_done, Counter(), done.id, done.level);
-                final_of[np.node] = done;
-                continue;
-            }
-            const int nidx = bn0 + t;
-            Counter ready[2];
-            for (int side = 0; side < 2; side++) {
-                int child = side ? np.b : np.a;
-                if (!N.pp[side]) {
-                    ready[side] = final_of[child];
-                    continue;
-                }
-                int64_t ntiles = (int64_t)1 << (N.prank[side] - N.ptile_bits[side]);
-                int64_t per = chunk(ntiles);
-                int64_t ntask = ntiles / per;
-                Counter c{ncounters++, (int)(ntask * npl), final_of[child].level + 1};
-                for (int pl = 0; pl < npl; pl++)
-                    for (int64_t k = 0; k < ntask; k++)
-                        add(BT_PERM, nidx, side * 2 + pl, k * per, final_of[child], Counter(), c.id, c.level, (int)per);
-                ready[side] = c;
-            }
-            int64_t nblocks = (int64_t)1 << ((N.g.lb - N.g.tb) + (N.g.li - N.g.ti) + (N.g.lj - N.g.tj) + N.g.lsplit);
-            int64_t per = chunk(nblocks);
-            Counter gdone{ncounters++, (int)(nblocks / per), std::max(ready[0].level, ready[1].level) + 1};
-            for (int64_t k = 0; k < nblocks / per; k++)
-                add(BT_GEMM, nidx, 0, k * per, ready[0], ready[1], gdone.id, gdone.level, (int)per);
-            Counter fin = gdone;
-            if (N.g.lsplit > 0) {
-                int64_t nred = N.reduce_per_block ? N.nout : (N.nout + 255) / 256;
-                int64_t rper = 1;
-                while (nred / rper > kMaxTasksPerNode) rper *= 2;
-                int64_t nrt = (nred + rper - 1) / rper;
-                Counter rdone{ncounters++, (int)nrt, gdone.level + 1};
-                for (int64_t k = 0; k < nrt; k++)
-                    add(BT_REDUCE, nidx, 0, k * rper, gdone, Counter(), rdone.id, rdone.level,
-                        (int)std::min<int64_t>(rper, nred - k * rper));
-                fin = rdone;
-            }
-            final_of[np.node] = fin;
-        }
-        int root = (int)p.nodes.size() - 1;
-        add(BT_ACCUM, -1, 0, p.node_off_dag[root], final_of[root], Counter(), -1, final_of[root].level + 1);
+        ncounters += T.ncounters;
+        L.total_ops += T.ops;
+        L.total_bytes += T.bytes;
     }
     // every job goes to one XCC queue (longest-processing-time first on the
     // estimated work: semiring ops plus a fixed cost per task)
     const int nq = std::max(1, std::min(16, device_cu_count(ctx) / 32));
-    std::vector<double> job_work(jobs.size(), 0.0);
-    for (size_t k = 0; k < bt.size(); k++) job_work[bt[k].job] += 2.0e4;
-    for (auto& N : bn)
-        job_work[N.job] += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk)) * (N.g.rm == 4 ? 0.5 : 1.0);
     std::vector<int> jq(jobs.size(), 0), jorder(jobs.size());
     for (size_t k = 0; k < jorder.size(); k++) jorder[k] = (int)k;
-    std::stable_sort(jorder.begin(), jorder.end(), [&](int a, int b) { return job_work[a] > job_work[b]; });
+    std::stable_sort(jorder.begin(), jorder.end(),
+                     [&](int a, int b) { return job_tmpl[a]->work > job_tmpl[b]->work; });
     std::vector<double> qload(nq, 0.0);
     for (int j : jorder) {
         int best = (int)(std::min_element(qload.begin(), qload.end()) - qload.begin());
         jq[j] = best;
-        qload[best] += job_work[j];
+        qload[best] += job_tmpl[j]->work;
     }
-    // ticket order inside a queue: critical path first.  Every task gets a
-    // rough cost (per-workgroup rates) and its bottom level (its cost plus the
-    // longest chain of dependent tasks after it); tasks are then emitted in a
-    // topological order that always takes the ready task with the largest
-    // bottom level.  Every producer precedes its consumers, so a waiting
-    // workgroup only waits on smaller tickets of its queue.
-    const std::vector<int> rank = critical_path_order(bt, bn, L.subtree_list, ncounters);
-    std::vector<int> order(bt.size());
-    for (size_t k = 0; k < order.size(); k++) order[k] = (int)k;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        int qa = jq[bt[a].job], qb = jq[bt[b].job];
-        return qa != qb ? qa < qb : rank[a] < rank[b];
-    });
-    std::vector<BTask> sorted(bt.size());
-    for (size_t k = 0; k < order.size(); k++) sorted[k] = bt[order[k]];
+    // ticket order inside a queue.  Each job's tasks follow its template's
+    // critical-path-first order: every task has a rough cost (per-workgroup
+    // rates) and a bottom level (its cost plus the longest chain of dependent
+    // tasks after it), and the order always takes the ready task with the
+    // largest bottom level.  The jobs of a queue are interleaved position by
+    // position in proportion to their lengths, so every producer precedes its
+    // consumers and a waiting workgroup only waits on smaller tickets of its
+    // queue.
+    std::vector<BTask> sorted;
+    sorted.reserve(bt.size());
+    std::vector<std::vector<int>> qjobs(nq);
+    for (size_t j = 0; j < jobs.size(); j++) qjobs[jq[j]].push_back((int)j);
+    for (int q = 0; q < nq; q++) {
+        const std::vector<int>& J = qjobs[q];
+        if (J.empty()) continue;
+        bool same = true;
+        for (int j : J) same = same && job_tmpl[j] == job_tmpl[J[0]];
+        if (same) {
+            const std::vector<int>& ord = job_tmpl[J[0]]->order;
+            for (size_t k = 0; k < ord.size(); k++)
+                for (int j : J) sorted.push_back(bt[(size_t)job_task0[j] + (size_t)ord[k]]);
+            continue;
+        }
+        using Item = std::pair<double, std::pair<int, int>>;  // (relative position, (job, next index))
+        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+        for (int j : J) heap.push({0.5 / (double)job_tmpl[j]->order.size(), {j, 0}});
+        while (!heap.empty()) {
+            const Item it = heap.top();
+            heap.pop();
+            const int j = it.second.first, k = it.second.second;
+            const std::vector<int>& ord = job_tmpl[j]->order;
+            sorted.push_back(bt[(size_t)job_task0[j] + (size_t)ord[k]]);
+            if (k + 1 < (int)ord.size()) heap.push({(k + 1.5) / (double)ord.size(), {j, k + 1}});
+        }
+    }
     L.ntasks = (int)sorted.size();
     L.nq = nq;
     L.qbegin.assign(nq, 0);

@@ -33,11 +33,10 @@ struct BJob {  // one contraction pass of one network
     const int* spos;
 };
 
-struct BNode {  // one inner node of one job
+struct BNode {  // one inner node; jobs of the same plan and algebra share it (offsets are job-relative)
     GemmShape g;
     int64_t a_off, b_off, c_off;  // effective operand offsets (after permutes)
     int ma, mb, mc;
-    int job;
     const PermParams* pp[2];
     int64_t psrc[2], pdst[2];
     int prank[2], ptile_bits[2];

@@ -146,23 +146,52 @@ __device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count,
     C.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.arena.p1 + nd.c_off * plane_bytes_dev<D>(1) : nullptr;
     P.p0 = (unsigned char*)j.part.p0 + nd.part_off * plane_bytes_dev<D>(0);
     P.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.part.p1 + nd.part_off * plane_bytes_dev<D>(1) : nullptr;
-    for (int k = 0; k < count; k++) {
-        const i64 unit = first + k;
-        if (nd.reduce_per_block) {
-            split_reduce_one<D>(P, C, nd.nout, nd.g.lsplit, j.ap, j.meta, nd.mc, unit, (V*)smem);
-        } else {
-            i64 o = unit * 256 + threadIdx.x;
-            float lmax = 0.0f;
-            if (o < nd.nout) {
-                const V acc = split_sum<D>(P, nd.nout, o, 1 << nd.g.lsplit, j.ap);
-                A::store(C, o, acc);
-                if constexpr (is_z<D>()) lmax = acc;
-            }
-            if constexpr (is_z<D>()) {
-                for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
-                if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(j.meta, nd.mc, __float_as_uint(lmax));
-            }
+    if (nd.reduce_per_block) {
+        for (int k = 0; k < count; k++)
+            split_reduce_one<D>(P, C, nd.nout, nd.g.lsplit, j.ap, j.meta, nd.mc, first + k, (V*)smem);
+        return;
+    }
+    const int S = 1 << nd.g.lsplit;
+    float lmax = 0.0f;
+    for (int k = 0; k < count; k += 4) {
+        // four units per pass: with at most 4 splits all their loads are in
+        // flight together (a unit is one output per thread)
+        i64 o[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            o[u] = (first + k + u) * 256 + threadIdx.x;
+            ok[u] = k + u < count && o[u] < nd.nout;
         }
+        V acc[4];
+        if (D != DSR_CTROP && S <= 4) {  // counting tropical: registers are tight
+            V v[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int s = 0; s < 4; s++)
+                    if (ok[u] && s < S) v[u][s] = A::load(P, (i64)s * nd.nout + o[u]);
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                acc[u] = A::zero(j.ap);
+#pragma unroll
+                for (int s = 0; s < 4; s++)
+                    if (ok[u] && s < S) acc[u] = A::add(acc[u], v[u][s], j.ap);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++) acc[u] = ok[u] ? split_sum<D>(P, nd.nout, o[u], S, j.ap) : A::zero(j.ap);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (ok[u]) {
+                A::store(C, o[u], acc[u]);
+                if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc[u]);
+            }
+    }
+    if constexpr (is_z<D>()) {
+        for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
+        if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(j.meta, nd.mc, __float_as_uint(lmax));
     }
 }
 

@@ -97,7 +97,7 @@ tn_status single_config_max(tn_ctx* ctx, const Net& net, const Plan& plan, int32
                 if (hipMemcpyAsync(d, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess ||
                     launch_backtrace((const float*)L.job_arena0[0], (const int*)d, ninner, (const int*)(d + o_ooff),
                                      (const int*)(d + o_oids), (const long long*)(d + o_off), (int*)(d + o_asg),
-                                     (int*)(d + o_stat), s) != hipSuccess ||
+                                     (int*)(d + o_stat), nn, (int)ord_ids.size(), net.nv, s) != hipSuccess ||
                     hipMemcpyAsync(host.data() + o_asg, d + o_asg, total - o_asg, hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess) {
                     st = fail(TN_EDEVICE, "back-trace kernel failed");

@@ -526,14 +526,40 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(Planes part, Planes C
 // threads then scan the assignments of the summed indices, in chunks, for the
 // smallest one whose A + B equals that value.  The GEMM formed the value as
 // the maximum of exactly these float sums, so the equality is exact.
-__global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, const int* nodes, int ninner,
-                                                        const int* ord_off, const int* ord_ids, const long long* off,
-                                                        int* assign, int* status) {
+__global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, const int* g_nodes, int ninner,
+                                                        const int* g_ord_off, const int* g_ord_ids,
+                                                        const long long* g_off, int* g_assign, int* status, int nn,
+                                                        int nids, int nv, int use_lds) {
+    // the tables and the assignment live in LDS when they fit (the walk is
+    // serial in thread 0, so their latency is on the critical path)
+    extern __shared__ __align__(16) unsigned char bt_lds[];
+    const int* nodes = g_nodes;
+    const int* ord_off = g_ord_off;
+    const int* ord_ids = g_ord_ids;
+    const long long* off = g_off;
+    int* assign = g_assign;
+    if (use_lds) {
+        long long* s_off = (long long*)bt_lds;
+        int* s_nodes = (int*)(s_off + nn);
+        int* s_oo = s_nodes + 3 * ninner;
+        int* s_oi = s_oo + nn + 1;
+        int* s_as = s_oi + nids;
+        for (int i = threadIdx.x; i < nn; i += blockDim.x) s_off[i] = g_off[i];
+        for (int i = threadIdx.x; i < 3 * ninner; i += blockDim.x) s_nodes[i] = g_nodes[i];
+        for (int i = threadIdx.x; i <= nn; i += blockDim.x) s_oo[i] = g_ord_off[i];
+        for (int i = threadIdx.x; i < nids; i += blockDim.x) s_oi[i] = g_ord_ids[i];
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) s_as[i] = g_assign[i];
+        nodes = s_nodes;
+        ord_off = s_oo;
+        ord_ids = s_oi;
+        off = s_off;
+        assign = s_as;
+    }
     constexpr int kMaxFree = 30, kMaxRank = 62;
     constexpr unsigned long long kChunk = 1ull << 16;
     __shared__ int sfree[kMaxFree];
     __shared__ int nfree;
-    __shared__ float target;
+    __shared__ long long taddr;  // the node's entry at its assigned output indices
     __shared__ unsigned long long best;
     __shared__ int mapA[kMaxRank], mapB[kMaxRank];  // >= 0: position in sfree; < 0: -1 - fixed value
     __shared__ int rankA, rankB;
@@ -553,7 +579,7 @@ __global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, cons
                 if (v < 0) stop = 3;  // an output index left unset
                 addr |= (long long)(v & 1) << q;
             }
-            if (!stop) target = arena[off[x] + addr];
+            if (!stop) taddr = off[x] + addr;
             nfree = 0;
             for (int side = 0; side < 2 && !stop; side++) {
                 const int y = side ? b : a;
@@ -567,13 +593,14 @@ __global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, cons
                 }
                 for (int q = 0; q < r; q++) {
                     const int id = ord_ids[ord_off[y] + q];
-                    if (assign[id] >= 0) {
-                        map[q] = -1 - (assign[id] & 1);
+                    const int cur = assign[id];
+                    if (cur >= 0) {
+                        map[q] = -1 - (cur & 1);
                         continue;
                     }
-                    int pos = -1;
-                    for (int f = 0; f < nfree; f++)
-                        if (sfree[f] == id) pos = f;
+                    // a summed index already listed for this node is marked
+                    // -2 - position until the node's values are written
+                    int pos = cur <= -2 ? -2 - cur : -1;
                     if (pos < 0) {
                         if (nfree == kMaxFree) {
                             stop = 2;
@@ -581,6 +608,7 @@ __global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, cons
                         }
                         pos = nfree;
                         sfree[nfree++] = id;
+                        assign[id] = -2 - pos;
                     }
                     map[q] = pos;
                 }
@@ -593,6 +621,7 @@ __global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, cons
         const unsigned long long total = 1ull << nfree;
         __syncthreads();
         if (halt) break;
+        const float target = arena[taddr];  // every thread: one round trip with the scan's loads
         for (unsigned long long c0 = 0; c0 < total; c0 += kChunk) {
             const unsigned long long c1 = c0 + kChunk < total ? c0 + kChunk : total;
             for (unsigned long long s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
@@ -621,11 +650,18 @@ __global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, cons
             }
         }
     }
+    if (use_lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) g_assign[i] = assign[i];
+    }
 }
 
 hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, const int* ord_off, const int* ord_ids,
-                            const long long* off, int* assign, int* status, hipStream_t s) {
-    backtrace_kernel<<<1, 256, 0, s>>>(arena, nodes, ninner, ord_off, ord_ids, off, assign, status);
+                            const long long* off, int* assign, int* status, int nn, int nids, int nv, hipStream_t s) {
+    const size_t bytes = 8 * (size_t)nn + 4 * (3 * (size_t)ninner + (size_t)nn + 1 + (size_t)nids + (size_t)nv);
+    const int use_lds = bytes <= 48 * 1024 ? 1 : 0;
+    backtrace_kernel<<<1, 256, use_lds ? bytes : 0, s>>>(arena, nodes, ninner, ord_off, ord_ids, off, assign, status,
+                                                         nn, nids, nv, use_lds);
     return hipGetLastError();
 }
 
