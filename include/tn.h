@@ -58,7 +58,7 @@ typedef enum {
  *                                    equal sizes add counts; the count is exact
  *                                    modulo 2^64; integer weights only
  *   TN_COUNT_EXACT       CountingAll counts in Z/2^64 plus residues modulo primes
- *                                    below 2^31, recombined by CRT into an exact
+ *                                    below 2^30, recombined by CRT into an exact
  *                                    integer (Z(beta=0) of Sec. 3.1)
  *   TN_PARTITION_F32     PartitionFunction(beta): float32 values, one power-of-two
  *                                    exponent per intermediate tensor
@@ -306,7 +306,7 @@ typedef struct {
     double beta;               /* inverse temperature for TN_PARTITION_* (x = e^beta) */
     int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime
                                   (0 = default 4: three CRT primes + one check) */
-    const uint32_t* primes;    /* NULL = default primes (largest primes below 2^31) */
+    const uint32_t* primes;    /* NULL = default primes (largest primes below 2^30) */
     int64_t slice_begin;       /* run slices [slice_begin, slice_end) only; slice s */
     int64_t slice_end;         /* fixes sliced index k to bit k of s; 0,0 = all */
     int32_t executor;          /* 0 auto: one persistent launch for unsliced trees with
@@ -367,7 +367,7 @@ tn_status tn_solve_batch(tn_ctx* ctx, int32_t n, const tn_net* const* nets,
  * table, computed by the finite-field method of Sec. 6.2.  The network is
  * contracted with vertex tensors [1, t] for t = 0 .. alpha (alpha = the
  * largest independent-set size, from one max-plus contraction) modulo primes
- * below 2^31 whose product exceeds the total count (from one exact-count
+ * below 2^30 whose product exceeds the total count (from one exact-count
  * contraction), every evaluation one mod-p pass of the persistent launch;
  * the values are interpolated mod each prime and the coefficients
  * recombined by CRT, with one more prime as a check.

@@ -217,8 +217,10 @@ AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval
     return ap;
 }
 
-static const uint32_t kDefaultPrimes[8] = {2147483647u, 2147483629u, 2147483587u, 2147483579u,
-                                           2147483563u, 2147483549u, 2147483543u, 2147483497u};
+// the largest primes below 2^30 (residues then admit one Montgomery
+// reduction per four products: 4 p^2 < p 2^32)
+static const uint32_t kDefaultPrimes[8] = {1073741789u, 1073741783u, 1073741741u, 1073741723u,
+                                           1073741719u, 1073741717u, 1073741689u, 1073741671u};
 
 static bool is_prime(uint32_t p) {
     if (p < 2) return false;
@@ -245,7 +247,7 @@ tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSp
         passes.push_back({DSR_U64, 0});
         for (int k = 0; k < np; k++) {
             uint32_t p = o.primes ? o.primes[k] : kDefaultPrimes[k];
-            if (p >= (1u << 31) || p < 3 || !is_prime(p)) return fail(TN_EINVAL, "residue moduli must be odd primes below 2^31");
+            if (p >= (1u << 30) || p < 3 || !is_prime(p)) return fail(TN_EINVAL, "residue moduli must be odd primes below 2^30");
             for (auto& q : passes)
                 if (q.prime == p) return fail(TN_EINVAL, "residue primes must be distinct");
             passes.push_back({DSR_MODP, p});

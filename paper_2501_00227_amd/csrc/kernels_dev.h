@@ -92,7 +92,7 @@ struct Alg<DSR_U64> {  // counting in Z / 2^64
 };
 
 template <>
-struct Alg<DSR_MODP> {  // counting modulo p < 2^31, Montgomery form with R = 2^32
+struct Alg<DSR_MODP> {  // counting modulo p < 2^30, Montgomery form with R = 2^32
     using V = unsigned int;
     __device__ static V zero(const AlgebraParams&) { return 0u; }
     __device__ static V one(const AlgebraParams& ap) { return ap.r1; }
@@ -136,8 +136,21 @@ struct Alg<DSR_Z_BF16> : Alg<DSR_Z_F32> {
 };
 
 // acc + a0 b0 + a1 b1 (mod p) in Montgomery form with one reduction for the two
-// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^31), so REDC(t) < 2p and
+// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^30), so REDC(t) < 2p and
 // REDC(t) = a0 b0 R^-1 + a1 b1 R^-1 (mod p).  min(x, x - p) reduces x < 2p.
+// acc + a0 b0 + a1 b1 + a2 b2 + a3 b3 (Montgomery form), one reduction:
+// the sum of four products is below 4 p^2 < p 2^32 for p < 2^30, so the
+// reduced value is below 2p.
+__device__ inline unsigned int modp_mac4(unsigned int acc, const unsigned int* a, const unsigned int* b,
+                                         const AlgebraParams& ap) {
+    const u64 t = (u64)a[0] * b[0] + (u64)a[1] * b[1] + (u64)a[2] * b[2] + (u64)a[3] * b[3];
+    const unsigned int m = (unsigned int)t * ap.pinv;
+    unsigned int u = (unsigned int)((t + (u64)m * ap.p) >> 32);
+    u = min(u, u - ap.p);
+    const unsigned int s2 = acc + u;
+    return min(s2, s2 - ap.p);
+}
+
 __device__ inline unsigned int modp_mac2(unsigned int acc, unsigned int a0, unsigned int b0, unsigned int a1,
                                          unsigned int b1, const AlgebraParams& ap) {
     const u64 t = (u64)a0 * b0 + (u64)a1 * b1;
@@ -525,7 +538,25 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
             const V* ap_ = As + (size_t)z * TK * TMp + y;
             const V* bp_ = Bs + (size_t)z * TK * TNp + x;
             int k = 0;
-            if constexpr (D == DSR_MODP) {  // two k steps per Montgomery reduction
+            if constexpr (D == DSR_MODP) {  // four k steps per Montgomery reduction, then two
+                for (; k + 3 < TK; k += 4) {
+                    V av[4][RM], bv[4][RN];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+#pragma unroll
+                        for (int r = 0; r < RM; r++) av[u][r] = ap_[(k + u) * TMp + r * TMt];
+#pragma unroll
+                        for (int c = 0; c < RN; c++) bv[u][c] = bp_[(k + u) * TNp + c * TNt];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RM; r++)
+#pragma unroll
+                        for (int c = 0; c < RN; c++) {
+                            const V a4[4] = {av[0][r], av[1][r], av[2][r], av[3][r]};
+                            const V b4[4] = {bv[0][c], bv[1][c], bv[2][c], bv[3][c]};
+                            acc[r][c] = modp_mac4(acc[r][c], a4, b4, g.ap);
+                        }
+                }
                 for (; k + 1 < TK; k += 2) {
                     V av0[RM], bv0[RN], av1[RM], bv1[RN];
 #pragma unroll
@@ -680,7 +711,31 @@ __device__ void gemm_tile_big(const GemmArgs& g, u64 tile, unsigned char* smem) 
             Bs[k * TNP + j] = A::load(g.B, addr);
         }
         __syncthreads();
-        for (int k = 0; k < TK; k += 2) {  // TK >= 2
+        int k0s = 0;
+        if constexpr (D == DSR_MODP) {  // four k steps per Montgomery reduction
+            for (; k0s + 3 < TK; k0s += 4) {
+                V a[4][RMT];
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+#pragma unroll
+                    for (int h = 0; h < RMT / 4; h++) lds_load4(As + (k0s + u) * TMP + h * (TM / 2) + ty * 4, a[u] + 4 * h);
+#pragma unroll
+                for (int h = 0; h < RNT / 4; h++) {  // four columns at a time keeps the operands in registers
+                    V b[4][4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) lds_load4(Bs + (k0s + u) * TNP + h * (TN / 2) + tx * 4, b[u]);
+#pragma unroll
+                    for (int r = 0; r < RMT; r++)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) {
+                            const V a4[4] = {a[0][r], a[1][r], a[2][r], a[3][r]};
+                            const V b4[4] = {b[0][c], b[1][c], b[2][c], b[3][c]};
+                            acc[r][4 * h + c] = modp_mac4(acc[r][4 * h + c], a4, b4, g.ap);
+                        }
+                }
+            }
+        }
+        for (int k = k0s; k < TK; k += 2) {  // TK >= 2
             V a0[RMT], b0[RNT], a1[RMT], b1[RNT];
 #pragma unroll
             for (int h = 0; h < RMT / 4; h++) {

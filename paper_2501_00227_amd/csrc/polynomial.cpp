@@ -124,12 +124,12 @@ tn_status solve_polynomial(tn_ctx* ctx, const Net& net, const Plan& plan, int li
     // count, hence every coefficient
     std::vector<uint32_t> primes;
     int need = total.bits() + 1, have = 0;
-    for (uint32_t p = 2147483647u; (have < need || primes.size() < 2) && p > (1u << 30); p -= 2)
+    for (uint32_t p = (1u << 30) - 1; (have < need || primes.size() < 2) && p > (1u << 29); p -= 2)
         if (prime32(p)) {
             primes.push_back(p);
-            have += 30;
+            have += 29;
         }
-    for (uint32_t p = primes.back() - 2; p > (1u << 30); p -= 2)
+    for (uint32_t p = primes.back() - 2; p > (1u << 29); p -= 2)
         if (prime32(p)) {  // the check prime
             primes.push_back(p);
             break;
