@@ -735,8 +735,8 @@ __device__ void gemm_tile_big(const GemmArgs& g, u64 tile, unsigned char* smem) 
                 }
             }
         }
-        for (int k = k0s; k < TK; k += 2) {  // TK >= 2
-            V a0[RMT], b0[RNT], a1[RMT], b1[RNT];
+        // two k per step
+        auto load2 = [&](int k, V* a0, V* a1, V* b0, V* b1) {
 #pragma unroll
             for (int h = 0; h < RMT / 4; h++) {
                 lds_load4(As + k * TMP + h * (TM / 2) + ty * 4, a0 + 4 * h);
@@ -747,6 +747,10 @@ __device__ void gemm_tile_big(const GemmArgs& g, u64 tile, unsigned char* smem) 
                 lds_load4(Bs + k * TNP + h * (TN / 2) + tx * 4, b0 + 4 * h);
                 lds_load4(Bs + (k + 1) * TNP + h * (TN / 2) + tx * 4, b1 + 4 * h);
             }
+        };
+        for (int k = k0s; k < TK; k += 2) {  // TK >= 2
+            V a0[RMT], b0[RNT], a1[RMT], b1[RNT];
+            load2(k, a0, a1, b0, b1);
 #pragma unroll
             for (int r = 0; r < RMT; r++)
 #pragma unroll
