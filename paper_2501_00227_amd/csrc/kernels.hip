@@ -231,6 +231,8 @@ template <int D>
 static hipError_t gemm_big_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t s) {
     const dim3 grid((unsigned)blocks), block(256);
     if (a.ti == 7 && a.tj == 7) gemm_big_kernel<D, 7, 7><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 7 && a.tj == 6) gemm_big_kernel<D, 7, 6><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 6 && a.tj == 7) gemm_big_kernel<D, 6, 7><<<grid, block, lds, s>>>(a);
     else if (a.ti == 8 && a.tj == 6) gemm_big_kernel<D, 8, 6><<<grid, block, lds, s>>>(a);
     else if (a.ti == 8 && a.tj == 5) gemm_big_kernel<D, 8, 5><<<grid, block, lds, s>>>(a);
     else if (a.ti == 6 && a.tj == 8) gemm_big_kernel<D, 6, 8><<<grid, block, lds, s>>>(a);
@@ -284,7 +286,15 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     // register-tiled family: 128 x 128 for large M and N; 256 x 64 / 256 x 32
     // (or mirrored) when one side is large and the other 2^5 or 2^6
     int bti = 0, btj = 0;
-    if (li >= 7 && lj >= 7 && lk >= 4) bti = btj = 7;
+    if (li >= 7 && lj >= 7 && lk >= 4) {
+        bti = btj = 7;
+        // at most 32 output tiles: halve the tile so that two workgroups per
+        // CU of a 32-CU chiplet each get one (instead of some CUs two tiles)
+        if (lb + (li - 7) + (lj - 7) <= 5) {
+            if (lj >= li) btj = 6;
+            else bti = 6;
+        }
+    }
     else if (li >= 8 && (lj == 5 || lj == 6) && lk >= 2) bti = 8, btj = lj;
     else if (lj >= 8 && (li == 5 || li == 6) && lk >= 2) bti = li, btj = 8;
     // counting tropical: 128 x 64 / 64 x 128, or 256 x 32 / 32 x 256

@@ -651,7 +651,9 @@ __device__ inline typename Alg<D>::V big_mac2(typename Alg<D>::V acc, typename A
 template <int LTM, int LTN>
 struct BigTile {
     static constexpr int TM = 1 << LTM, TN = 1 << LTN;
-    static constexpr int RMT = TM >= 64 ? 8 : 4, RNT = TN >= 64 ? 8 : 4;  // outputs per thread
+    // outputs per thread: 8 x 8, or 8 x 4 / 4 x 8 on the 32- and 64-wide sides
+    static constexpr int RMT = (LTM == 6 && LTN == 7) ? 4 : (TM >= 64 ? 8 : 4);
+    static constexpr int RNT = (LTM == 7 && LTN == 6) ? 4 : (TN >= 64 ? 8 : 4);
     static constexpr int CT = TN / RNT;                                   // column threads
     static constexpr int TMP = TM + 4, TNP = TN + 4;                      // padded LDS rows, 16-byte aligned
     static_assert((TM / RMT) * CT == 256, "256 threads per tile");
@@ -659,7 +661,8 @@ struct BigTile {
 
 // the tile shapes of the family, (log2 TM, log2 TN)
 __host__ __device__ constexpr bool big_tile_shape(int ti, int tj) {
-    return (ti == 7 && tj == 7) || (ti == 8 && (tj == 5 || tj == 6)) || (tj == 8 && (ti == 5 || ti == 6));
+    return (ti == 7 && (tj == 6 || tj == 7)) || (ti == 6 && tj == 7) || (ti == 8 && (tj == 5 || tj == 6)) ||
+           (tj == 8 && (ti == 5 || ti == 6));
 }
 
 template <int D, int LTM, int LTN>
@@ -773,6 +776,8 @@ __device__ void gemm_tile_big(const GemmArgs& g, u64 tile, unsigned char* smem) 
 template <int D>
 __device__ inline bool gemm_tile_big_any(const GemmArgs& g, u64 tile, unsigned char* smem) {
     if (g.ti == 7 && g.tj == 7) gemm_tile_big<D, 7, 7>(g, tile, smem);
+    else if (g.ti == 7 && g.tj == 6) gemm_tile_big<D, 7, 6>(g, tile, smem);
+    else if (g.ti == 6 && g.tj == 7) gemm_tile_big<D, 6, 7>(g, tile, smem);
     else if (g.ti == 8 && g.tj == 6) gemm_tile_big<D, 8, 6>(g, tile, smem);
     else if (g.ti == 8 && g.tj == 5) gemm_tile_big<D, 8, 5>(g, tile, smem);
     else if (g.ti == 6 && g.tj == 8) gemm_tile_big<D, 6, 8>(g, tile, smem);

@@ -2,13 +2,15 @@
 
 The per-node executor sends nodes of the 4-byte VALU algebras (max-plus
 int32 and float32, counts mod p) with M, N >= 2^7 and K >= 2^4 to a 128 x 128
-tile, and nodes with one side >= 2^8 and the other 2^5 or 2^6 to the 256 x 32,
-256 x 64 tiles (or their mirror images); counting-tropical nodes go to
-128 x 64, 64 x 128, 256 x 32 and 32 x 256 tiles.  Square lattices of side 14 and 16,
-a King's subgraph of side 15 and a finely sliced plan of the 240-vertex
-3-regular network have such nodes (with and without batch indices, with
-split K); each case asserts which tiles ran and compares the result with the
-oracle.
+tile (halved to 128 x 64 or 64 x 128 when that gives at most 32 output
+tiles), and nodes with one side >= 2^8 and the other 2^5 or 2^6 to the
+256 x 32, 256 x 64 tiles (or their mirror images); counting-tropical nodes go
+to 128 x 64, 64 x 128, 256 x 32 and 32 x 256 tiles.  Square lattices of side
+14 and 16, a King's subgraph of side 15, a finely sliced plan of the
+240-vertex 3-regular network and a hand-made tree whose middle node is a
+1024 x 1024 x 16 product have such nodes (with and without batch indices,
+with split K); each case asserts which tiles ran and compares the result with
+the oracle.
 """
 import numpy as np
 import pytest
@@ -50,8 +52,10 @@ def _nbig(recs):
 
 def _tile(shape):
     """(log2 TM, log2 TN) of the register-tiled kernel for a GEMM shape (b, i, j, k)."""
-    _, i, j, k = shape
+    b, i, j, k = shape
     if i >= 7 and j >= 7 and k >= 4:
+        if b + (i - 7) + (j - 7) <= 5:  # at most 32 square tiles: half tiles
+            return (7, 6) if j >= i else (6, 7)
         return (7, 7)
     if i >= 8 and j in (5, 6):
         return (8, j)
@@ -78,10 +82,10 @@ def _ct_tile(shape):
 
 # (graph, planner, planner seed, 4-byte tiles, counting-tropical tiles the plan must exercise)
 CASES = [
-    ("lattice14", "greedy", 0, {(7, 7), (8, 6), (8, 5)}, {(7, 6), (8, 5)}),
-    ("lattice14", "treesa", 0, {(7, 7)}, {(7, 6)}),
-    ("lattice16", "greedy", 0, {(7, 7), (6, 8)}, {(7, 6), (6, 7)}),
-    ("ksg15", "treesa", 2, {(7, 7), (8, 6), (8, 5), (5, 8)}, {(7, 6), (6, 7), (8, 5), (5, 8)}),
+    ("lattice14", "greedy", 0, {(7, 6), (8, 6), (8, 5), (6, 8)}, {(7, 6), (8, 5)}),
+    ("lattice14", "treesa", 0, {(6, 7), (8, 6)}, {(7, 6)}),
+    ("lattice16", "greedy", 0, {(6, 7), (7, 6), (6, 8)}, {(7, 6), (6, 7)}),
+    ("ksg15", "treesa", 2, {(7, 6), (8, 6), (8, 5), (5, 8)}, {(7, 6), (6, 7), (8, 5), (5, 8)}),
 ]
 
 
@@ -195,3 +199,68 @@ def test_thin_and_dot_modes_vs_oracle(ctx, side, executor):
     if executor == "stream":
         print("kernel kinds", sorted(kinds), flush=True)
         assert "gemm_dot" in kinds
+
+
+def test_square_tile_on_a_hand_made_tree(ctx):
+    """Vertex groups I, J (10 each) and K (4): I-K and J-K complete bipartite,
+    I-J a perfect matching.  The tree contracts the I-K edges into A(I, K),
+    the J-K edges into B(J, K), the matching into C(I, J), then A x B -> (I, J)
+    (M = N = 2^10, K = 2^4: 64 tiles of 128 x 128) and finally with C.  The
+    oracle is the brute force over the 24 vertices."""
+    I, J, K = list(range(10)), list(range(10, 20)), list(range(20, 24))
+    edges = [(i, k) for i in I for k in K] + [(j, k) for j in J for k in K] + [(i, i + 10) for i in I]
+    g = gg.Graph(24, np.asarray(sorted(edges), np.int32), None, "ijk")
+    eid = {tuple(e): n for n, e in enumerate(g.edges.tolist())}
+    def chain(es, verts):
+        leaves = []
+        placed = set()
+        for (u, v) in es:
+            f = [eid[(u, v)]]
+            for x in (u, v):
+                if x in verts and x not in placed:
+                    placed.add(x)
+                    f.append(-x - 1)
+            leaves.append(f)
+        return leaves
+    la = chain([(i, k) for i in I for k in K], set(I) | set(K))
+    lb = chain([(j, k) for j in J for k in K], set(J))
+    lc = chain([(i, i + 10) for i in I], set())
+    leaves = la + lb + lc
+    left, right = [], []
+    nl = len(leaves)
+    def fold(first, count):
+        node = first
+        for t in range(1, count):
+            left.append(node)
+            right.append(first + t)
+            node = nl + len(left) - 1
+        return node
+    a = fold(0, len(la))
+    b = fold(len(la), len(lb))
+    c = fold(len(la) + len(lb), len(lc))
+    left.append(a); right.append(b)
+    ab = nl + len(left) - 1
+    left.append(ab); right.append(c)
+    gw = g.with_weights(gg.dyadic_weights(24, 11))
+    bf_u = oracle.brute_force(g, betas=[0.5])
+    bf_w = oracle.brute_force(gw, betas=[0.5])
+    for graph, bf in ((g, bf_u), (gw, bf_w)):
+        net = tn.Net.from_graph(graph)
+        plan = tn.Plan.from_tree(net, leaves, left, right)
+        sr = "tropical_i32" if graph is g else "tropical_f32"
+        r, recs = _solve_profiled(ctx, net, plan, sr)
+        ran = {(x["shape"][1], x["shape"][2]) for x in recs if x["kind"] == "gemm_big"}
+        print(f"{sr}: big-tile shapes (log2 M, N) {sorted(ran)}", flush=True)
+        assert (10, 10) in ran and _tile([0, 10, 10, 4]) == (7, 7)
+        assert r["size"] == bf["size_max"]
+        z, _ = _solve_profiled(ctx, net, plan, "partition_f32", beta=0.5)
+        assert abs(z["log_z"] - bf["log_z"][0]) <= 1e-5
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.from_tree(net, leaves, left, right)
+    r, recs = _solve_profiled(ctx, net, plan, "count_exact")
+    assert (10, 10) in {(x["shape"][1], x["shape"][2]) for x in recs if x["kind"] == "gemm_big"}
+    assert r["count"] == bf_u["count_all"]
+    r = ctx.solve(net, plan, "counting_tropical", executor="stream")
+    assert (r["size"], r["count_mod_2_64"]) == (bf_u["size_max"], bf_u["count_max"])
+    r = ctx.solve(net, plan, "tropical_i32", executor="persistent")
+    assert r["size"] == bf_u["size_max"]
