@@ -57,9 +57,10 @@ typedef enum {
  *   TN_COUNTING_TROPICAL CountingMax (int32 size, uint64 count): larger size wins,
  *                                    equal sizes add counts; the count is exact
  *                                    modulo 2^64; integer weights only
- *   TN_COUNT_EXACT       CountingAll counts in Z/2^64 plus residues modulo primes
- *                                    below 2^30, recombined by CRT into an exact
- *                                    integer (Z(beta=0) of Sec. 3.1)
+ *   TN_COUNT_EXACT       CountingAll: counts modulo primes below 2^30 (one
+ *                                    contraction per prime), recombined by CRT
+ *                                    into an exact integer and checked modulo
+ *                                    one more prime (Z(beta=0) of Sec. 3.1)
  *   TN_PARTITION_F32     PartitionFunction(beta): float32 values, one power-of-two
  *                                    exponent per intermediate tensor
  *   TN_PARTITION_BF16    as above with bfloat16-rounded GEMM inputs, float32
@@ -275,8 +276,7 @@ tn_status tn_plan_peak_bytes(const tn_plan* plan, tn_semiring semiring, uint64_t
 /* The GEMM launch shape of every inner node for one semiring (introspection:
  * which kernel family and tile each contraction step of Sec. 4.1 runs on).
  * One row of TN_SHAPE_ROW int32 per (device algebra, inner node), inner nodes
- * in execution order; TN_COUNT_EXACT has two device algebras (counts mod 2^64,
- * then mod p), the others one.  Row: algebra index, node id, log2 batch / M /
+ * in execution order; one device algebra per semiring.  Row: algebra index, node id, log2 batch / M /
  * N / K, A and B transposition flags, log2 tile batch / M / N / K step, micro
  * tile rows / columns, log2 K splits, kernel kind (tn_kernel_kind), 1 if the
  * shape is one the kernels accept, 0.  Writes at most cap rows (rows may be
@@ -305,7 +305,8 @@ typedef struct {
     int32_t semiring;          /* tn_semiring */
     double beta;               /* inverse temperature for TN_PARTITION_* (x = e^beta) */
     int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime
-                                  (0 = default 4: three CRT primes + one check) */
+                                  (0 = default 6: five CRT primes, range 2^149,
+                                  + one check) */
     const uint32_t* primes;    /* NULL = default primes (largest primes below 2^30) */
     int64_t slice_begin;       /* run slices [slice_begin, slice_end) only; slice s */
     int64_t slice_end;         /* fixes sliced index k to bit k of s; 0,0 = all */

@@ -329,7 +329,7 @@ tn_status tn_plan_gemm_shapes(const tn_plan* p, tn_semiring sr, int32_t cap, int
     case TN_TROPICAL_I32: dsrs = {DSR_TROP_I32}; break;
     case TN_TROPICAL_F32: dsrs = {DSR_TROP_F32}; break;
     case TN_COUNTING_TROPICAL: dsrs = {DSR_CTROP}; break;
-    case TN_COUNT_EXACT: dsrs = {DSR_U64, DSR_MODP}; break;
+    case TN_COUNT_EXACT: dsrs = {DSR_MODP}; break;
     case TN_PARTITION_F32: dsrs = {DSR_Z_F32}; break;
     case TN_PARTITION_BF16: dsrs = {DSR_Z_BF16}; break;
     default: return fail(TN_EINVAL, "unknown semiring");
@@ -363,7 +363,7 @@ tn_status tn_plan_peak_bytes(const tn_plan* p, tn_semiring sr, uint64_t* bytes) 
     case TN_TROPICAL_I32: dsr = DSR_TROP_I32; break;
     case TN_TROPICAL_F32: dsr = DSR_TROP_F32; break;
     case TN_COUNTING_TROPICAL: dsr = DSR_CTROP; break;
-    case TN_COUNT_EXACT: dsr = DSR_U64; break;
+    case TN_COUNT_EXACT: dsr = DSR_MODP; break;
     case TN_PARTITION_F32: dsr = DSR_Z_F32; break;
     case TN_PARTITION_BF16: dsr = DSR_Z_BF16; break;
     default: return fail(TN_EINVAL, "unknown semiring");

@@ -296,7 +296,6 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
         case DSR_TROP_I32: run_task<DSR_TROP_I32>(t, j, nodes, subtree, smem); break;
         case DSR_TROP_F32: run_task<DSR_TROP_F32>(t, j, nodes, subtree, smem); break;
         case DSR_CTROP: run_task<DSR_CTROP>(t, j, nodes, subtree, smem); break;
-        case DSR_U64: run_task<DSR_U64>(t, j, nodes, subtree, smem); break;
         case DSR_MODP: run_task<DSR_MODP>(t, j, nodes, subtree, smem); break;
         case DSR_Z_F32: run_task<DSR_Z_F32>(t, j, nodes, subtree, smem); break;
         case DSR_Z_BF16: run_task<DSR_Z_BF16>(t, j, nodes, subtree, smem); break;

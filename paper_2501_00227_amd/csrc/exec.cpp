@@ -229,6 +229,29 @@ static bool is_prime(uint32_t p) {
     return true;
 }
 
+// log2 of an upper bound on the number of configurations the exact count can
+// reach: 2^n for a spin glass; for independent sets the bound of Sah,
+// Sawhney, Stoner and Zhao (the number of independent sets is at most the
+// product over edges uv of i(K_{d_u, d_v})^(1 / (d_u d_v)), with
+// i(K_{a,b}) = 2^a + 2^b - 1), times 2 per isolated vertex.
+double count_bound_bits(const Net& net) {
+    if (net.kind != 0) return (double)net.nv;
+    std::vector<int> deg(net.nv, 0);
+    for (auto& e : net.edges) {
+        deg[e[0]]++;
+        deg[e[1]]++;
+    }
+    double b = 0;
+    for (int v = 0; v < net.nv; v++)
+        if (deg[v] == 0) b += 1.0;
+    for (auto& e : net.edges) {
+        const double du = deg[e[0]], dv = deg[e[1]], m = std::max(du, dv);
+        const double l = m + std::log2(std::exp2(du - m) + std::exp2(dv - m) - std::exp2(-m));
+        b += l / (du * dv);
+    }
+    return b;
+}
+
 tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes) {
     passes.clear();
     switch (o.semiring) {
@@ -242,9 +265,11 @@ tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSp
         passes.push_back({DSR_CTROP, 0});
         break;
     case TN_COUNT_EXACT: {
-        int np = o.nprimes > 0 ? o.nprimes : 4;
+        // default: enough CRT primes (each above 2^29.99) for the bound on the
+        // count, plus one check prime
+        int np = o.nprimes;
+        if (np <= 0) np = std::min(8, std::max(2, (int)std::ceil((count_bound_bits(net) + 2.0) / 29.0) + 1));
         if (np < 2 || np > 8) return fail(TN_EINVAL, "nprimes must be in [2, 8] (CRT primes + one check prime)");
-        passes.push_back({DSR_U64, 0});
         for (int k = 0; k < np; k++) {
             uint32_t p = o.primes ? o.primes[k] : kDefaultPrimes[k];
             if (p >= (1u << 30) || p < 3 || !is_prime(p)) return fail(TN_EINVAL, "residue moduli must be odd primes below 2^30");
@@ -329,23 +354,20 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
         break;
     }
     case TN_COUNT_EXACT: {
-        uint64_t c64;
-        std::memcpy(&c64, a0, 8);
-        res.count_mod_2_64 = c64;
-        int np = (int)passes.size() - 1;
+        const int np = (int)passes.size();
         res.nresidues = np;
         for (int k = 0; k < np; k++) {
-            uint32_t p = passes[k + 1].prime, xm;
-            std::memcpy(&xm, acc[k + 1].data(), 4);
+            uint32_t p = passes[k].prime, xm;
+            std::memcpy(&xm, acc[k].data(), 4);
             uint32_t rinv = powmod((1ull << 32) % p, p - 2, p);  // R^{-1} mod p
             res.residues[k] = (uint32_t)((uint64_t)xm * rinv % p);
             res.primes[k] = p;
         }
-        // Garner over {2^64, p_1 .. p_{np-1}}; p_np checks the result
+        // Garner over p_1 .. p_{np-1}; p_np checks the result
         BigU x, M;
-        x.d = {(uint32_t)c64, (uint32_t)(c64 >> 32)};
-        M.d = {0u, 0u, 1u};  // 2^64
-        for (int k = 0; k < np - 1; k++) {
+        x.d = {res.residues[0]};
+        M.d = {res.primes[0]};
+        for (int k = 1; k < np - 1; k++) {
             uint32_t p = res.primes[k];
             uint32_t xm = x.mod_small(p), mm = M.mod_small(p);
             uint32_t t = (uint32_t)((uint64_t)((res.residues[k] + (uint64_t)p - xm) % p) * powmod(mm, p - 2, p) % p);
@@ -358,6 +380,7 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
         if (x.d.size() > 16) return fail(TN_EOVERFLOW, "exact count needs more than 512 bits");
         res.count_nlimbs = (int)x.d.size();
         for (size_t k = 0; k < x.d.size(); k++) res.count_limbs[k] = x.d[k];
+        res.count_mod_2_64 = (x.d.size() > 0 ? (uint64_t)x.d[0] : 0) | (x.d.size() > 1 ? (uint64_t)x.d[1] << 32 : 0);
         uint32_t pc = res.primes[np - 1];
         if (x.mod_small(pc) != res.residues[np - 1])
             return fail(TN_EOVERFLOW, "exact count exceeds the CRT range: the check prime disagrees");

@@ -8,16 +8,15 @@
 namespace tn {
 
 // Device algebra of one contraction pass.  Exact counting runs one pass per
-// lane: DSR_U64 (counts mod 2^64) and DSR_MODP (counts mod a prime p).
+// prime: DSR_MODP (counts mod p), recombined by CRT on the host.
 enum DevSemiring {
     DSR_TROP_I32 = 0,
     DSR_TROP_F32 = 1,
     DSR_CTROP = 2,   // plane 0 int32 size, plane 1 uint64 count
-    DSR_U64 = 3,
-    DSR_MODP = 4,    // Montgomery form, R = 2^32
-    DSR_Z_F32 = 5,   // float32 with per-tensor power-of-two exponents
-    DSR_Z_BF16 = 6,  // as DSR_Z_F32, GEMM inputs rounded to bfloat16
-    DSR_COUNT_ = 7
+    DSR_MODP = 3,    // Montgomery form, R = 2^32
+    DSR_Z_F32 = 4,   // float32 with per-tensor power-of-two exponents
+    DSR_Z_BF16 = 5,  // as DSR_Z_F32, GEMM inputs rounded to bfloat16
+    DSR_COUNT_ = 6
 };
 
 // bytes per entry of plane 0 / plane 1 (0 = no such plane)

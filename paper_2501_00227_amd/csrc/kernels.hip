@@ -25,7 +25,6 @@ namespace tn {
 int plane_bytes(int dsr, int plane) {
     switch (dsr) {
     case DSR_CTROP: return plane == 0 ? 4 : 8;
-    case DSR_U64: return plane == 0 ? 8 : 0;
     default: return plane == 0 ? 4 : 0;
     }
 }
@@ -33,7 +32,6 @@ int plane_bytes(int dsr, int plane) {
 static int lds_elem_bytes(int dsr) {
     switch (dsr) {
     case DSR_CTROP: return 16;
-    case DSR_U64: return 8;
     default: return 4;
     }
 }
@@ -71,7 +69,6 @@ hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float*
         TN_LF(DSR_TROP_I32)
         TN_LF(DSR_TROP_F32)
         TN_LF(DSR_CTROP)
-        TN_LF(DSR_U64)
         TN_LF(DSR_MODP)
         TN_LF(DSR_Z_F32)
         TN_LF(DSR_Z_BF16)
@@ -273,7 +270,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
         g.lsplit = ls < 0 ? 0 : ls;
         return g;
     }
-    const int kthin = (dsr == DSR_CTROP || dsr == DSR_U64) ? 1 : 2;  // K entries of <= 16 bytes per row
+    const int kthin = dsr == DSR_CTROP ? 1 : 2;  // K entries of <= 16 bytes per row
     if (li >= 10 && lj <= 4 && lk <= kthin && lj + lk <= 5) {  // thin: N * K <= 32
         g.mode = GEMM_THIN;
         g.rm = g.rn = 1;
@@ -468,7 +465,6 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         case DSR_TROP_I32: return gemm_mode_go<DSR_TROP_I32>(a, g.mode, lds, blocks, s);
         case DSR_TROP_F32: return gemm_mode_go<DSR_TROP_F32>(a, g.mode, lds, blocks, s);
         case DSR_CTROP: return gemm_mode_go<DSR_CTROP>(a, g.mode, lds, blocks, s);
-        case DSR_U64: return gemm_mode_go<DSR_U64>(a, g.mode, lds, blocks, s);
         case DSR_MODP: return gemm_mode_go<DSR_MODP>(a, g.mode, lds, blocks, s);
         case DSR_Z_F32: return gemm_mode_go<DSR_Z_F32>(a, g.mode, lds, blocks, s);
         case DSR_Z_BF16: return gemm_mode_go<DSR_Z_BF16>(a, g.mode, lds, blocks, s);
@@ -494,7 +490,6 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         TN_GM(DSR_TROP_I32)
         TN_GM(DSR_TROP_F32)
         TN_GM(DSR_CTROP)
-        TN_GM(DSR_U64)
         TN_GM(DSR_MODP)
         TN_GM(DSR_Z_F32)
         TN_GM(DSR_Z_BF16)
@@ -687,7 +682,6 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, i64 nout, int lsp
         TN_SR(DSR_TROP_I32)
         TN_SR(DSR_TROP_F32)
         TN_SR(DSR_CTROP)
-        TN_SR(DSR_U64)
         TN_SR(DSR_MODP)
         TN_SR(DSR_Z_F32)
         TN_SR(DSR_Z_BF16)
@@ -723,7 +717,6 @@ hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, 
         TN_AC(DSR_TROP_I32)
         TN_AC(DSR_TROP_F32)
         TN_AC(DSR_CTROP)
-        TN_AC(DSR_U64)
         TN_AC(DSR_MODP)
         TN_AC(DSR_Z_F32)
         TN_AC(DSR_Z_BF16)
@@ -747,7 +740,6 @@ hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream
         TN_SO(DSR_TROP_I32)
         TN_SO(DSR_TROP_F32)
         TN_SO(DSR_CTROP)
-        TN_SO(DSR_U64)
         TN_SO(DSR_MODP)
         TN_SO(DSR_Z_F32)
         TN_SO(DSR_Z_BF16)

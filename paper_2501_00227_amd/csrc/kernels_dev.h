@@ -79,19 +79,6 @@ struct Alg<DSR_CTROP> {  // (size, count): larger size wins, equal sizes add cou
 };
 
 template <>
-struct Alg<DSR_U64> {  // counting in Z / 2^64
-    using V = u64;
-    __device__ static V zero(const AlgebraParams&) { return 0ull; }
-    __device__ static V one(const AlgebraParams&) { return 1ull; }
-    __device__ static V add(V a, V b, const AlgebraParams&) { return a + b; }
-    __device__ static V mul(V a, V b, const AlgebraParams&) { return a * b; }
-    __device__ static V weight(float, const AlgebraParams&) { return 1ull; }
-    __device__ static V load(const Planes& p, i64 i) { return ((const u64*)p.p0)[i]; }
-    __device__ static void store(const Planes& p, i64 i, V v) { ((u64*)p.p0)[i] = v; }
-    __device__ static V prescale(V v, float) { return v; }
-};
-
-template <>
 struct Alg<DSR_MODP> {  // counting modulo p < 2^30, Montgomery form with R = 2^32
     using V = unsigned int;
     __device__ static V zero(const AlgebraParams&) { return 0u; }
@@ -169,7 +156,7 @@ constexpr bool is_z() {
 // bytes per entry of plane 0 / plane 1 of an algebra (0: no such plane)
 template <int D>
 __host__ __device__ constexpr int plane_bytes_dev(int plane) {
-    return D == DSR_CTROP ? (plane == 0 ? 4 : 8) : D == DSR_U64 ? (plane == 0 ? 8 : 0) : (plane == 0 ? 4 : 0);
+    return D == DSR_CTROP ? (plane == 0 ? 4 : 8) : (plane == 0 ? 4 : 0);
 }
 
 // Partition-function bookkeeping is read and written with device-scope

@@ -140,7 +140,7 @@ def test_k2_three_contractions(ctx, method, executor):
         assert r["size"] == case["size_max"]
         r = ctx.solve(net, plan, "count_exact", executor=executor)
         assert r["count"] == int(case["count_all"])
-        assert r["count"] > 2 ** 64  # exercises the CRT beyond the uint64 lane
+        assert r["count"] > 2 ** 64  # the CRT result needs more than 64 bits
         r = ctx.solve(net, plan, "counting_tropical", executor=executor)
         assert r["count_mod_2_64"] == int(case["count_max"])
         r = ctx.solve(net, plan, "partition_f32", beta=0.0, executor=executor)
@@ -175,3 +175,29 @@ def test_integer_algebra_rejects_fractional_weights(ctx):
     with pytest.raises(tn.TnError):
         ctx.solve(net, plan, "tropical_i32")
     assert ctx.solve(net, plan, "tropical_f32")["size"] == oracle.brute_force(g)["size_max"]
+
+
+def test_exact_count_range_and_overflow(ctx):
+    """Counts are exact below the product of the CRT primes and flagged above
+    it by the check prime.  By default the number of primes follows an upper
+    bound on the count (at most eight primes, seven of them for CRT, about
+    2^209); given primes set the range.  The empty graph on n vertices has
+    2^n independent sets."""
+    for n in (140, 160, 200):
+        net = tn.Net.from_graph(gg.empty(n))
+        r = ctx.solve(net, tn.Plan.create(net), "count_exact")
+        assert r["count"] == 2 ** n and r["count_mod_2_64"] == 0
+        assert len(r["primes"]) >= (n + 29) // 30 + 1
+    net = tn.Net.from_graph(gg.empty(300))
+    with pytest.raises(tn.TnError) as ei:
+        ctx.solve(net, tn.Plan.create(net), "count_exact")
+    assert ei.value.code == tn.TN_EOVERFLOW
+    net = tn.Net.from_graph(gg.empty(40))
+    plan = tn.Plan.create(net)
+    with pytest.raises(tn.TnError) as ei:  # one CRT prime: range below 2^30
+        ctx.solve(net, plan, "count_exact", primes=[1073741789, 1073741783])
+    assert ei.value.code == tn.TN_EOVERFLOW
+    primes = [1073741789, 1073741783, 1073741741]
+    r = ctx.solve(net, plan, "count_exact", primes=primes)
+    assert r["count"] == 2 ** 40
+    assert r["primes"] == primes and all(res == pow(2, 40, p) for res, p in zip(r["residues"], primes))
