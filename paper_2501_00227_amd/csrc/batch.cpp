@@ -482,17 +482,24 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
                 for (int j : J) sorted.push_back(bt[(size_t)job_task0[j] + (size_t)ord[k]]);
             continue;
         }
-        using Item = std::pair<double, std::pair<int, int>>;  // (relative position, (job, next index))
-        std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-        for (int j : J) heap.push({0.5 / (double)job_tmpl[j]->order.size(), {j, 0}});
-        while (!heap.empty()) {
-            const Item it = heap.top();
-            heap.pop();
-            const int j = it.second.first, k = it.second.second;
-            const std::vector<int>& ord = job_tmpl[j]->order;
-            sorted.push_back(bt[(size_t)job_task0[j] + (size_t)ord[k]]);
-            if (k + 1 < (int)ord.size()) heap.push({(k + 1.5) / (double)ord.size(), {j, k + 1}});
+        // different templates: a stable counting sort on the relative
+        // position (k + 1/2) / length keeps every job's own order
+        size_t nq_tasks = 0;
+        for (int j : J) nq_tasks += job_tmpl[j]->order.size();
+        std::vector<size_t> start(nq_tasks + 1, 0);
+        auto bucket = [&](size_t k, size_t len) { return (size_t)(((double)k + 0.5) / (double)len * (double)nq_tasks); };
+        for (int j : J) {
+            const size_t len = job_tmpl[j]->order.size();
+            for (size_t k = 0; k < len; k++) start[std::min(bucket(k, len), nq_tasks - 1) + 1]++;
         }
+        for (size_t b = 0; b < nq_tasks; b++) start[b + 1] += start[b];
+        std::vector<const BTask*> slot(nq_tasks);
+        for (int j : J) {
+            const std::vector<int>& ord = job_tmpl[j]->order;
+            for (size_t k = 0; k < ord.size(); k++)
+                slot[start[std::min(bucket(k, ord.size()), nq_tasks - 1)]++] = &bt[(size_t)job_task0[j] + (size_t)ord[k]];
+        }
+        for (const BTask* t : slot) sorted.push_back(*t);
     }
     L.ntasks = (int)sorted.size();
     L.nq = nq;
