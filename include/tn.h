@@ -304,9 +304,10 @@ tn_status tn_net_flat_complexity(const tn_net* net, double* tc_log2, double* sc_
 typedef struct {
     int32_t semiring;          /* tn_semiring */
     double beta;               /* inverse temperature for TN_PARTITION_* (x = e^beta) */
-    int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime
-                                  (0 = default 6: five CRT primes, range 2^149,
-                                  + one check) */
+    int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime,
+                                  2..8 (0 = default: enough CRT primes for an
+                                  upper bound on the count, at least two, plus
+                                  one check; at most 7 CRT primes, range 2^209) */
     const uint32_t* primes;    /* NULL = default primes (largest primes below 2^30) */
     int64_t slice_begin;       /* run slices [slice_begin, slice_end) only; slice s */
     int64_t slice_end;         /* fixes sliced index k to bit k of s; 0,0 = all */
@@ -409,6 +410,19 @@ tn_status tn_solve_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, in
  * result. */
 tn_status tn_solve_open(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts, int64_t cap,
                         tn_result* out);
+
+/* SizeMax(k) of the Sec. 5 table for any weights (and for spin glasses: the
+ * k largest values of -H, i.e. minus the k lowest energies): the k largest
+ * total weights over all independent sets, with multiplicity, largest first.
+ * Computed in max-plus over sorted lists of the eight largest values (float32
+ * weights; the (x) of two lists keeps the eight largest pairwise sums) on the
+ * per-node executor, sliced plans included.
+ *   k      1 .. 8
+ *   sizes  caller memory of k floats; fewer than k configurations: the rest
+ *          is -INFINITY
+ * Errors: TN_EINVAL (k out of range, plan with open vertices or built for
+ * another network), TN_ENOMEM, TN_EDEVICE. */
+tn_status tn_solve_size_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, float* sizes);
 
 /* One maximum configuration (SingleConfigMax of the Sec. 5 table): an
  * independent set of largest total weight, or for a spin-glass network a

@@ -70,8 +70,12 @@ def _load():
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, i32p, i32p,
                                         i32p, i32p, i32p, i32p, ctypes.c_int, i32p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int, f64p, u64p, f64p, f64p]
+        lib.orc_brute_force_topk.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int, f64p,
+                                             ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_brute_force_sg_topk.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, f64p,
+                                                ctypes.c_uint64, ctypes.c_uint64]
         for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_eliminate_poly, lib.orc_eliminate_sg,
-                  lib.orc_brute_force_sg, lib.orc_follow_plan):
+                  lib.orc_brute_force_sg, lib.orc_follow_plan, lib.orc_brute_force_topk, lib.orc_brute_force_sg_topk):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -210,6 +214,35 @@ def spin_glass_brute_force(graph, J=None, h=None, betas: Sequence[float] = (), f
         raise OracleError(rc, "spin_glass_brute_force")
     return {"energy_min": float(emin[0]), "count_min": int(cnt[0]), "z": [float(x) for x in z[:nb]],
             "log_z": [float(x) for x in lz[:nb]]}
+
+
+def brute_force_topk(graph, k: int, fixed=None) -> List[float]:
+    """The k largest independent-set weights with multiplicity (SizeMax(k)),
+    by enumeration (n <= 30)."""
+    lib = _load()
+    edges, w = _graph_arrays(graph)
+    fmask, fval = _fix_masks(fixed)
+    out = np.zeros(k)
+    rc = lib.orc_brute_force_topk(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(w, ctypes.c_double), k,
+                                  _ptr(out, ctypes.c_double), fmask, fval)
+    if rc != ORC_OK:
+        raise OracleError(rc, "brute_force_topk")
+    return [float(x) for x in out]
+
+
+def spin_glass_topk(graph, k: int, J=None, h=None, fixed=None) -> List[float]:
+    """The k largest values of -H over all spin configurations, with
+    multiplicity (minus the k lowest energies), by enumeration (n <= 30)."""
+    lib = _load()
+    edges, _ = _graph_arrays(graph)
+    Ja, ha = _sg_arrays(graph, J, h)
+    fmask, fval = _fix_masks(fixed)
+    out = np.zeros(k)
+    rc = lib.orc_brute_force_sg_topk(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(Ja, ctypes.c_double),
+                                     _ptr(ha, ctypes.c_double), k, _ptr(out, ctypes.c_double), fmask, fval)
+    if rc != ORC_OK:
+        raise OracleError(rc, "spin_glass_topk")
+    return [float(x) for x in out]
 
 
 def spin_glass_eliminate(graph, semiring: str, J=None, h=None, beta: float = 0.0, max_width: int = 26) -> Dict:

@@ -24,6 +24,8 @@
  *                         independence polynomial (Sec. 5.3 GraphPolynomial)
  *       orc_eliminate_sg, orc_brute_force_sg  the spin glass of Sec. 2
  *                         (energy H = sum J s s + sum h s, Sec. 6.4 buckyball)
+ *       orc_brute_force_topk, orc_brute_force_sg_topk  the k largest values
+ *                         with multiplicity (SizeMax(k)) by enumeration
  *   O3  orc_follow_plan   evaluate a given binary contraction tree (Sec. 4.1),
  *                         one literal einsum loop per node, with optional
  *                         sliced indices (Sec. 4.2, TreeSA slicing)
@@ -613,6 +615,67 @@ int orc_brute_force_sg(int nv, int ne, const int32_t* edges, const double* J, co
     for (int b = 0; b < nbeta; b++) {
         if (z) z[b] = (double)zs[b];
         if (logz) logz[b] = (double)logl(zs[b]);
+    }
+    return ORC_OK;
+}
+
+/* The k largest values over all configurations, with multiplicity (SizeMax(k)
+ * of the Sec. 5 table), by enumeration: independent sets and their total
+ * weight, or spin configurations and -H.  Subsets that disagree with the
+ * fixings are skipped.  out: k values, largest first, -INFINITY where fewer
+ * than k configurations exist. */
+static void topk_insert(double* top, int k, double v) {
+    if (v <= top[k - 1]) return;
+    int i = k - 1;
+    while (i > 0 && top[i - 1] < v) {
+        top[i] = top[i - 1];
+        i--;
+    }
+    top[i] = v;
+}
+
+int orc_brute_force_topk(int nv, int ne, const int32_t* edges, const double* w, int k, double* out,
+                         uint64_t fix_mask, uint64_t fix_val) {
+    if (nv < 0 || nv > 30 || ne < 0 || k < 1 || k > 64) return ORC_EINVAL;
+    uint64_t nbr[64] = {0};
+    for (int e = 0; e < ne; e++) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= nv || v >= nv || u == v) return ORC_EINVAL;
+        nbr[u] |= 1ull << v;
+        nbr[v] |= 1ull << u;
+    }
+    for (int i = 0; i < k; i++) out[i] = -INFINITY;
+    for (uint64_t S = 0; S < (1ull << nv); S++) {
+        if ((S & fix_mask) != fix_val) continue;
+        int ok = 1;
+        for (int v = 0; v < nv && ok; v++)
+            if (((S >> v) & 1) && (S & nbr[v])) ok = 0;
+        if (!ok) continue;
+        long double ws = 0.0L;
+        for (int v = 0; v < nv; v++)
+            if ((S >> v) & 1) ws += w ? (long double)w[v] : 1.0L;
+        topk_insert(out, k, (double)ws);
+    }
+    return ORC_OK;
+}
+
+int orc_brute_force_sg_topk(int nv, int ne, const int32_t* edges, const double* J, const double* h, int k,
+                            double* out, uint64_t fix_mask, uint64_t fix_val) {
+    if (nv < 0 || nv > 30 || ne < 0 || k < 1 || k > 64) return ORC_EINVAL;
+    for (int e = 0; e < ne; e++) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= nv || v >= nv || u == v) return ORC_EINVAL;
+    }
+    for (int i = 0; i < k; i++) out[i] = -INFINITY;
+    for (uint64_t m = 0; m < (1ull << nv); m++) {
+        if ((m & fix_mask) != fix_val) continue;
+        long double H = 0.0L;
+        for (int e = 0; e < ne; e++) {
+            int su = (int)((m >> edges[2 * e]) & 1) * 2 - 1, sv = (int)((m >> edges[2 * e + 1]) & 1) * 2 - 1;
+            H += (long double)(J ? J[e] : 1.0) * su * sv;
+        }
+        for (int v = 0; v < nv; v++) H += (long double)(h ? h[v] : 0.0) * (int)(((m >> v) & 1) * 2 - 1);
+        topk_insert(out, k, (double)-H);
     }
     return ORC_OK;
 }

@@ -439,9 +439,12 @@ void tn_solve_opts_default(tn_solve_opts* o) {
     o->executor = 0;
 }
 
+static bool public_semiring(int s) { return s >= TN_TROPICAL_I32 && s <= TN_PARTITION_BF16; }
+
 tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_opts* o, tn_result* out) {
     TN_GUARD_BEGIN
     if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");
+    if (!public_semiring(o->semiring)) return fail(TN_EINVAL, "unknown semiring");
     if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
     if (o->executor < 0 || o->executor > 2) return fail(TN_EINVAL, "executor must be 0, 1 or 2");
     bool persistent = o->executor == 2 || (o->executor == 0 && use_persistent(p->plan));
@@ -466,6 +469,7 @@ tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const 
     std::vector<BatchItem> items;
     for (int32_t i = 0; i < n; i++) {
         if (!nets[i] || !plans[i]) return fail(TN_EINVAL, "NULL network or plan in the batch");
+        if (!public_semiring(opts[i].semiring)) return fail(TN_EINVAL, "unknown semiring");
         items.push_back({&nets[i]->net, &plans[i]->plan, opts[i]});
     }
     std::vector<tn_result> res;
@@ -517,6 +521,7 @@ tn_status tn_solve_open(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_s
                         tn_result* out) {
     TN_GUARD_BEGIN
     if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");
+    if (!public_semiring(o->semiring)) return fail(TN_EINVAL, "unknown semiring");
     const int64_t need = (int64_t)1 << p->plan.open.size();
     if (cap < need) return fail(TN_EINVAL, "out must hold 2^nopen results");
     if (o->executor == 2) return fail(TN_EINVAL, "open plans run on the stream executor");
@@ -527,6 +532,28 @@ tn_status tn_solve_open(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_s
     if (st == TN_OK)
         for (int64_t e = 0; e < need; e++) out[e] = t[(size_t)e];
     return st;
+    TN_GUARD_END
+}
+
+tn_status tn_solve_size_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, float* sizes) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p || !sizes || k < 1 || k > 8) return fail(TN_EINVAL, "invalid arguments (k in 1..8, sizes required)");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    tn_solve_opts o;
+    tn_solve_opts_default(&o);
+    o.semiring = kSemiringTop8;
+    o.executor = 1;
+    tn_result r;
+    std::vector<unsigned char> raw;
+    tn_status st = solve_one(c, n->net, p->plan, o, r, nullptr, &raw);
+    if (st != TN_OK) return st;
+    if (p->plan.nleaf() == 0) {  // the empty network: one configuration of value 0
+        sizes[0] = 0.0f;
+        for (int t = 1; t < k; t++) sizes[t] = -INFINITY;
+        return TN_OK;
+    }
+    std::memcpy(sizes, raw.data(), sizeof(float) * (size_t)k);
+    return TN_OK;
     TN_GUARD_END
 }
 

@@ -122,29 +122,30 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
         d.var1 = lp.var[1];
         d.off = lp.off;
     }
-    std::vector<PermParams> perms;
+    std::vector<PermParams> perms, perms_wide;
     dp.perm_slot_a.assign(p.prog.size(), -1);
     dp.perm_slot_b.assign(p.prog.size(), -1);
+    auto add_perm = [&](const std::vector<int>& src) {
+        PermParams pp;
+        build_perm_params((int)src.size(), src.data(), pp);
+        perms.push_back(pp);
+        std::vector<int> wide{0, 1, 2};  // 32-byte entries: eight 4-byte words each
+        for (int x : src) wide.push_back(x + 3);
+        build_perm_params((int)wide.size(), wide.data(), pp);
+        perms_wide.push_back(pp);
+        return (int)perms.size() - 1;
+    };
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
-        if (np.perm_a) {
-            PermParams pp;
-            build_perm_params((int)np.perm_a_src.size(), np.perm_a_src.data(), pp);
-            dp.perm_slot_a[t] = (int)perms.size();
-            perms.push_back(pp);
-        }
-        if (np.perm_b) {
-            PermParams pp;
-            build_perm_params((int)np.perm_b_src.size(), np.perm_b_src.data(), pp);
-            dp.perm_slot_b[t] = (int)perms.size();
-            perms.push_back(pp);
-        }
+        if (np.perm_a) dp.perm_slot_a[t] = add_perm(np.perm_a_src);
+        if (np.perm_b) dp.perm_slot_b[t] = add_perm(np.perm_b_src);
     }
     std::vector<int> spos(std::max(p.nv, 1), -1);
     for (size_t k = 0; k < p.sliced.size(); k++) spos[p.sliced[k]] = (int)k;
     size_t o_leaf = 0;
     size_t o_perm = align256(o_leaf + sizeof(LeafDev) * leaves.size());
-    size_t o_spos = align256(o_perm + sizeof(PermParams) * perms.size());
+    size_t o_permw = align256(o_perm + sizeof(PermParams) * perms.size());
+    size_t o_spos = align256(o_permw + sizeof(PermParams) * perms_wide.size());
     size_t total = align256(o_spos + sizeof(int) * spos.size());
     dp.bytes = total;
     dp.buf = dev_alloc(ctx, total);
@@ -155,6 +156,7 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     unsigned char* h = (unsigned char*)ctx->pinned;
     std::memcpy(h + o_leaf, leaves.data(), sizeof(LeafDev) * leaves.size());
     if (!perms.empty()) std::memcpy(h + o_perm, perms.data(), sizeof(PermParams) * perms.size());
+    if (!perms_wide.empty()) std::memcpy(h + o_permw, perms_wide.data(), sizeof(PermParams) * perms_wide.size());
     std::memcpy(h + o_spos, spos.data(), sizeof(int) * spos.size());
     if (hipMemcpyAsync(dp.buf, h, total, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
@@ -162,6 +164,7 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     unsigned char* d = (unsigned char*)dp.buf;
     dp.leaves = (LeafDev*)(d + o_leaf);
     dp.perms = (PermParams*)(d + o_perm);
+    dp.perms_wide = (PermParams*)(d + o_permw);
     dp.slice_pos = (int*)(d + o_spos);
     auto ins = ctx->progs.emplace(p.uid, std::move(dp));
     out = &ins.first->second;
@@ -281,6 +284,7 @@ tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSp
     }
     case TN_PARTITION_F32: passes.push_back({DSR_Z_F32, 0}); break;
     case TN_PARTITION_BF16: passes.push_back({DSR_Z_BF16, 0}); break;
+    case kSemiringTop8: passes.push_back({DSR_TOPK, 0}); break;
     default: return fail(TN_EINVAL, "unknown semiring");
     }
     if ((o.semiring == TN_PARTITION_F32 || o.semiring == TN_PARTITION_BF16) && !std::isfinite(o.beta))
@@ -398,6 +402,7 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
         res.z = m == 0.0 ? 0.0 : (e > 1100 ? INFINITY : std::ldexp(m, (int)std::max<int64_t>(e, -2000)));
         break;
     }
+    case kSemiringTop8: break;  // the caller reads the raw accumulator
     default: return fail(TN_EINVAL, "unknown semiring");
     }
     return TN_OK;
@@ -407,7 +412,7 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
 static int64_t node_entries(const Plan& p, int node) { return (int64_t)1 << p.order[node].size(); }
 
 tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res,
-                    std::vector<tn_result>* tensor) {
+                    std::vector<tn_result>* tensor, std::vector<unsigned char>* raw) {
     auto t0 = std::chrono::steady_clock::now();
     if (plan.fingerprint != net.fingerprint || plan.nv != net.nv)
         return fail(TN_EINVAL, "plan was built for a different network");
@@ -453,7 +458,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     size_t o_w = align256(o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
     // root entries: 2^|open| for plans with open vertices, else one
     const int64_t nent = (nleaf > 0 && tensor) ? (int64_t)1 << plan.order[nn - 1].size() : 1;
-    const size_t acc_bytes = 16 * (size_t)nent * passes.size();
+    const size_t acc_bytes = kAccSlotBytes * (size_t)nent * passes.size();
     size_t o_acc = align256(o_w + sizeof(float) * std::max<size_t>(net.wdev.size(), 1));
     need = align256(o_acc + acc_bytes);
     unsigned char* base = (unsigned char*)dev_alloc(ctx, need);
@@ -491,7 +496,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
         const int dsr = passes[pi].dsr;
         AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta, passes[pi].xval);
         ap.fix_off = net.fix_off;
-        void* acc = base + o_acc + 16 * (size_t)nent * pi;
+        void* acc = base + o_acc + kAccSlotBytes * (size_t)nent * pi;
         const int eb = plane_bytes(dsr, 0) + plane_bytes(dsr, 1);
         const bool is_z = dsr == DSR_Z_F32 || dsr == DSR_Z_BF16;
         if (nleaf == 0) {
@@ -527,9 +532,14 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                         if (!pbytes) continue;
                         ProfScope ps(ctx, TN_K_PERMUTE, np.node, o.semiring, shp,
                                      2.0 * (double)node_entries(plan, src_node) * pbytes, 0);
-                        chk(launch_permute(pbytes, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms + slot, rank,
-                                           tb, s),
-                            "permute");
+                        if (pbytes == 32)  // 32-byte entries: 4-byte words, the three lowest bits in place
+                            chk(launch_permute(4, src.p0, dst.p0, dp->perms_wide + slot, rank + 3,
+                                               perm_tile_bits(rank + 3), s),
+                                "permute");
+                        else
+                            chk(launch_permute(pbytes, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms + slot,
+                                               rank, tb, s),
+                                "permute");
                     }
                     if (side)
                         Bp = dst;
@@ -572,11 +582,12 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     }
     dev_free(ctx, base, need);
     if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error at ") + herr_at + ": " + hipGetErrorString(herr));
+    if (raw) raw->assign(all.begin(), all.begin() + kAccSlotBytes);
     // decode root entry addr (storage order of the root) from every pass
     auto decode_entry = [&](int64_t addr, tn_result& r) {
         std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
         for (size_t k = 0; k < passes.size(); k++)
-            std::memcpy(accs[k].data(), all.data() + 16 * ((size_t)nent * k + (size_t)addr), 16);
+            std::memcpy(accs[k].data(), all.data() + kAccSlotBytes * ((size_t)nent * k + (size_t)addr), 16);
         return decode_result(o, passes, accs, r);
     };
     const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -35,6 +35,9 @@ struct DevProgram {
     size_t bytes = 0;
     LeafDev* leaves = nullptr;
     PermParams* perms = nullptr;  // indexed by permute slot
+    // the same permutes for 32-byte entries, as 4-byte permutes of rank + 3
+    // whose three lowest bits stay in place
+    PermParams* perms_wide = nullptr;
     int* slice_pos = nullptr;     // nv entries: position in the sliced list or -1
     std::vector<int> perm_slot_a, perm_slot_b;  // per inner node, -1 if none
     std::map<int, std::vector<NodeLaunch>> launches;  // per device algebra
@@ -108,8 +111,9 @@ struct ProfScope {
 
 // tensor: for plans with open vertices, receives the 2^nopen results (entry
 // bits = open vertices in the plan's order); res then holds entry 0.
+// raw: receives the first pass's accumulator slot (kAccSlotBytes).
 tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res,
-                    std::vector<tn_result>* tensor = nullptr);
+                    std::vector<tn_result>* tensor = nullptr, std::vector<unsigned char>* raw = nullptr);
 
 // Device algebras needed for a user algebra, and the lane primes.
 struct PassSpec {
@@ -117,6 +121,9 @@ struct PassSpec {
     uint32_t prime;
     uint32_t xval = 1;  // mod p: value of x in the vertex tensors [1, x] (1: counting)
 };
+// Internal semiring code (not part of tn_semiring): the eight largest values
+// (SizeMax(k), k <= 8); per-node executor only, raw accumulator result.
+constexpr int kSemiringTop8 = 100;
 tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes);
 AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval = 1);
 // Decode the accumulators of all passes into the result struct.

@@ -16,7 +16,8 @@ enum DevSemiring {
     DSR_MODP = 3,    // Montgomery form, R = 2^32
     DSR_Z_F32 = 4,   // float32 with per-tensor power-of-two exponents
     DSR_Z_BF16 = 5,  // as DSR_Z_F32, GEMM inputs rounded to bfloat16
-    DSR_COUNT_ = 6
+    DSR_TOPK = 6,    // the eight largest values with multiplicity (32-byte entries; per-node executor only)
+    DSR_COUNT_ = 7
 };
 
 // bytes per entry of plane 0 / plane 1 (0 = no such plane)
@@ -95,9 +96,10 @@ hipError_t launch_gemm(int dsr, Planes A, Planes B, Planes C, Planes part, const
                        const AlgebraParams& ap, TensorMeta* meta, int ma, int mb, int mc, hipStream_t s);
 hipError_t launch_split_reduce(int dsr, Planes part, Planes C, int64_t nout, int lsplit,
                                const AlgebraParams& ap, TensorMeta* meta, int mc, hipStream_t s);
-// acc[e] (+)= root[e] for the nent root entries, 16-byte slots; first != 0
-// copies.  For the partition function a slot is {double mantissa, int64
+// acc[e] (+)= root[e] for the nent root entries, kAccSlotBytes apart; first
+// != 0 copies.  For the partition function a slot is {double mantissa, int64
 // exponent}.
+constexpr int kAccSlotBytes = 32;
 hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
                              const AlgebraParams& ap, hipStream_t s, long long nent = 1);
 // The device-side identity element of a whole (empty) network.

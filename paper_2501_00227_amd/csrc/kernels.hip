@@ -25,6 +25,7 @@ namespace tn {
 int plane_bytes(int dsr, int plane) {
     switch (dsr) {
     case DSR_CTROP: return plane == 0 ? 4 : 8;
+    case DSR_TOPK: return plane == 0 ? 32 : 0;
     default: return plane == 0 ? 4 : 0;
     }
 }
@@ -32,6 +33,7 @@ int plane_bytes(int dsr, int plane) {
 static int lds_elem_bytes(int dsr) {
     switch (dsr) {
     case DSR_CTROP: return 16;
+    case DSR_TOPK: return 32;
     default: return 4;
     }
 }
@@ -72,6 +74,7 @@ hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float*
         TN_LF(DSR_MODP)
         TN_LF(DSR_Z_F32)
         TN_LF(DSR_Z_BF16)
+        TN_LF(DSR_TOPK)
     default: return hipErrorInvalidValue;
     }
 #undef TN_LF
@@ -261,7 +264,8 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     const int lds_cap = 40 * 1024;
     g.mfma = 0;
     g.mode = GEMM_TILED;
-    if (li == 0 && lj == 0 && lk >= 12) {  // one output per batch, long K
+    const bool topk = dsr == DSR_TOPK;  // 32-byte entries: LDS-staged tiles, one output per thread
+    if (!topk && li == 0 && lj == 0 && lk >= 12) {  // one output per batch, long K
         g.mode = GEMM_DOT;
         g.rm = g.rn = 1;
         int ls = 9 - lb;  // about 512 workgroups, each over >= 2^12 of K
@@ -271,7 +275,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
         return g;
     }
     const int kthin = dsr == DSR_CTROP ? 1 : 2;  // K entries of <= 16 bytes per row
-    if (li >= 10 && lj <= 4 && lk <= kthin && lj + lk <= 5) {  // thin: N * K <= 32
+    if (!topk && li >= 10 && lj <= 4 && lk <= kthin && lj + lk <= 5) {  // thin: N * K <= 32
         g.mode = GEMM_THIN;
         g.rm = g.rn = 1;
         g.ti = li < 12 ? li : 12;
@@ -300,6 +304,10 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     else if (li >= 6 && lj >= 7 && lk >= 2) cti = 6, ctj = 7;
     else if (li >= 8 && lj == 5 && lk >= 2) cti = 8, ctj = 5;
     else if (lj >= 8 && li == 5 && lk >= 2) cti = 5, ctj = 8;
+    if (topk) {
+        cti = 0;
+        bti = 0;
+    }
     if (dsr == DSR_CTROP && cti) {
         g.rm = g.rn = 8;
         g.ti = cti;
@@ -316,7 +324,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
         // four workgroups' operand tiles fit in one CU's LDS
         const int tkmax = (bti == 8 || btj == 8) ? 4 : 5;
         g.tk = lk < tkmax ? lk : tkmax;
-    } else if (li >= 6 && lj >= 6 && lk >= 4) {
+    } else if (!topk && li >= 6 && lj >= 6 && lk >= 4) {
         // contraction-heavy node: 64x64 tile, 4x4 per thread (or one 32x32
         // matrix-core block per wave for the partition function)
         g.rm = g.rn = 4;
@@ -329,9 +337,9 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
         // little reuse per output (K <= 8) and many outputs: 4 x 4 per
         // thread, 4096 outputs per workgroup, so fewer and larger tiles
         // carry the output traffic (each tile pays one load round trip)
-        const bool wide = lk <= 3 && li >= 2 && lj >= 2 && lb + li + lj >= 14;
-        g.rm = wide ? 4 : (li >= 1 ? 2 : 1);
-        g.rn = wide ? 4 : (lj >= 1 ? 2 : 1);
+        const bool wide = !topk && lk <= 3 && li >= 2 && lj >= 2 && lb + li + lj >= 14;
+        g.rm = topk ? 1 : wide ? 4 : (li >= 1 ? 2 : 1);
+        g.rn = topk ? 1 : wide ? 4 : (lj >= 1 ? 2 : 1);
         const int lr = (g.rm == 4 ? 2 : g.rm == 2 ? 1 : 0) + (g.rn == 4 ? 2 : g.rn == 2 ? 1 : 0);
         const int tot = 8 + lr;  // log2 outputs per workgroup
         g.ti = li < 5 ? li : 5;
@@ -371,6 +379,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
+    if (dsr == DSR_TOPK && (g.mode != GEMM_TILED || g.rm != 1 || g.rn != 1 || g.mfma)) return false;
     if (g.mode == GEMM_DOT)
         return g.li == 0 && g.lj == 0 && g.ti == 0 && g.tj == 0 && g.tb == 0 && !g.mfma && g.lsplit >= 0 &&
                g.lsplit <= 10 && g.lsplit <= g.lk;
@@ -420,6 +429,10 @@ static hipError_t gemm_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t
 
 template <int D>
 static hipError_t gemm_dispatch(const GemmArgs& a, int rm, int rn, size_t lds, u64 blocks, hipStream_t s) {
+    if constexpr (D == DSR_TOPK) {  // 32-byte entries: one output per thread
+        if (rm == 1 && rn == 1) return gemm_go<D, 1, 1>(a, lds, blocks, s);
+        return hipErrorInvalidValue;
+    }
     if (rm == 1 && rn == 1) return gemm_go<D, 1, 1>(a, lds, blocks, s);
     if (rm == 1 && rn == 2) return gemm_go<D, 1, 2>(a, lds, blocks, s);
     if (rm == 2 && rn == 1) return gemm_go<D, 2, 1>(a, lds, blocks, s);
@@ -468,6 +481,7 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         case DSR_MODP: return gemm_mode_go<DSR_MODP>(a, g.mode, lds, blocks, s);
         case DSR_Z_F32: return gemm_mode_go<DSR_Z_F32>(a, g.mode, lds, blocks, s);
         case DSR_Z_BF16: return gemm_mode_go<DSR_Z_BF16>(a, g.mode, lds, blocks, s);
+        case DSR_TOPK: return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }
     }
@@ -493,6 +507,7 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         TN_GM(DSR_MODP)
         TN_GM(DSR_Z_F32)
         TN_GM(DSR_Z_BF16)
+        TN_GM(DSR_TOPK)
     default: return hipErrorInvalidValue;
     }
 #undef TN_GM
@@ -685,6 +700,7 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, i64 nout, int lsp
         TN_SR(DSR_MODP)
         TN_SR(DSR_Z_F32)
         TN_SR(DSR_Z_BF16)
+        TN_SR(DSR_TOPK)
     default: return hipErrorInvalidValue;
     }
 #undef TN_SR
@@ -693,7 +709,7 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, i64 nout, int lsp
 
 // ---------------------------------------------------------- accumulate ---
 // Entry e of the root (a scalar, or the tensor over the open vertices) is
-// folded into the 16-byte accumulator slot e.
+// folded into accumulator slot e (kAccSlotBytes apart).
 template <int D>
 __global__ void accumulate_kernel(Planes root, int mroot, TensorMeta* meta, void* acc, int first, AlgebraParams ap,
                                   long long nent) {
@@ -702,7 +718,7 @@ __global__ void accumulate_kernel(Planes root, int mroot, TensorMeta* meta, void
     Planes r;
     r.p0 = (unsigned char*)root.p0 + e * plane_bytes_dev<D>(0);
     r.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)root.p1 + e * plane_bytes_dev<D>(1) : nullptr;
-    accumulate_one<D>(r, mroot, meta, (unsigned char*)acc + 16 * e, first, ap);
+    accumulate_one<D>(r, mroot, meta, (unsigned char*)acc + kAccSlotBytes * e, first, ap);
 }
 
 hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
@@ -720,6 +736,7 @@ hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, 
         TN_AC(DSR_MODP)
         TN_AC(DSR_Z_F32)
         TN_AC(DSR_Z_BF16)
+        TN_AC(DSR_TOPK)
     default: return hipErrorInvalidValue;
     }
 #undef TN_AC
@@ -743,6 +760,7 @@ hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream
         TN_SO(DSR_MODP)
         TN_SO(DSR_Z_F32)
         TN_SO(DSR_Z_BF16)
+        TN_SO(DSR_TOPK)
     default: return hipErrorInvalidValue;
     }
 #undef TN_SO

@@ -122,9 +122,90 @@ struct Alg<DSR_Z_BF16> : Alg<DSR_Z_F32> {
     __device__ static V prescale(V v, float s) { return round_bf16(v * s); }
 };
 
-// acc + a0 b0 + a1 b1 (mod p) in Montgomery form with one reduction for the two
-// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^30), so REDC(t) < 2p and
-// REDC(t) = a0 b0 R^-1 + a1 b1 R^-1 (mod p).  min(x, x - p) reduces x < 2p.
+// The eight largest values with multiplicity (SizeMax(k), k <= 8, of the
+// Sec. 5 table: max-plus over sorted lists).  v[0] >= v[1] >= ... >= v[7],
+// missing values -inf.  (+) keeps the eight largest of the union of two
+// lists, (x) the eight largest pairwise sums.
+struct Top8 {
+    float v[8];
+};
+
+// the eight largest of two sorted lists: max(a[t], b[7 - t]) keeps them as
+// a bitonic sequence, which three compare-exchange stages sort
+__device__ inline Top8 top8_merge(const Top8& a, const Top8& b) {
+    Top8 r;
+#pragma unroll
+    for (int t = 0; t < 8; t++) r.v[t] = fmaxf(a.v[t], b.v[7 - t]);
+#pragma unroll
+    for (int d = 4; d >= 1; d >>= 1)
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+            if ((t & d) == 0) {
+                const float hi = fmaxf(r.v[t], r.v[t + d]), lo = fminf(r.v[t], r.v[t + d]);
+                r.v[t] = hi;
+                r.v[t + d] = lo;
+            }
+    return r;
+}
+
+template <>
+struct Alg<DSR_TOPK> {
+    using V = Top8;
+    __device__ static V zero(const AlgebraParams&) {
+        V r;
+#pragma unroll
+        for (int t = 0; t < 8; t++) r.v[t] = -INFINITY;
+        return r;
+    }
+    __device__ static V one(const AlgebraParams& ap) {
+        V r = zero(ap);
+        r.v[0] = 0.0f;
+        return r;
+    }
+    __device__ static V add(const V& a, const V& b, const AlgebraParams&) { return top8_merge(a, b); }
+    // a[i] + b[j] can be among the eight largest sums only if (i+1)(j+1) <= 8
+    __device__ static V mul(const V& a, const V& b, const AlgebraParams&) {
+        V r;
+#pragma unroll
+        for (int i = 0; i < 8; i++) r.v[i] = a.v[i] + b.v[0];
+#pragma unroll
+        for (int j = 1; j < 8; j++) {
+            V c;
+#pragma unroll
+            for (int i = 0; i < 8; i++) c.v[i] = (i + 1) * (j + 1) <= 8 ? a.v[i] + b.v[j] : -INFINITY;
+            r = top8_merge(r, c);
+        }
+        return r;
+    }
+    __device__ static V weight(float w, const AlgebraParams& ap) {
+        V r = zero(ap);
+        r.v[0] = w;
+        return r;
+    }
+    __device__ static V load(const Planes& p, i64 i) {
+        const uint4* s = (const uint4*)((const unsigned char*)p.p0 + 32 * i);
+        const uint4 x = s[0], y = s[1];
+        V r;
+        r.v[0] = __uint_as_float(x.x);
+        r.v[1] = __uint_as_float(x.y);
+        r.v[2] = __uint_as_float(x.z);
+        r.v[3] = __uint_as_float(x.w);
+        r.v[4] = __uint_as_float(y.x);
+        r.v[5] = __uint_as_float(y.y);
+        r.v[6] = __uint_as_float(y.z);
+        r.v[7] = __uint_as_float(y.w);
+        return r;
+    }
+    __device__ static void store(const Planes& p, i64 i, const V& v) {
+        uint4* d = (uint4*)((unsigned char*)p.p0 + 32 * i);
+        d[0] = make_uint4(__float_as_uint(v.v[0]), __float_as_uint(v.v[1]), __float_as_uint(v.v[2]),
+                          __float_as_uint(v.v[3]));
+        d[1] = make_uint4(__float_as_uint(v.v[4]), __float_as_uint(v.v[5]), __float_as_uint(v.v[6]),
+                          __float_as_uint(v.v[7]));
+    }
+    __device__ static V prescale(const V& v, float) { return v; }
+};
+
 // acc + a0 b0 + a1 b1 + a2 b2 + a3 b3 (Montgomery form), one reduction:
 // the sum of four products is below 4 p^2 < p 2^32 for p < 2^30, so the
 // reduced value is below 2p.
@@ -138,6 +219,9 @@ __device__ inline unsigned int modp_mac4(unsigned int acc, const unsigned int* a
     return min(s2, s2 - ap.p);
 }
 
+// acc + a0 b0 + a1 b1 (mod p) in Montgomery form with one reduction for the two
+// products: t = a0 b0 + a1 b1 < 2 p^2 < p 2^32 (p < 2^30), so REDC(t) < 2p and
+// REDC(t) = a0 b0 R^-1 + a1 b1 R^-1 (mod p).  min(x, x - p) reduces x < 2p.
 __device__ inline unsigned int modp_mac2(unsigned int acc, unsigned int a0, unsigned int b0, unsigned int a1,
                                          unsigned int b1, const AlgebraParams& ap) {
     const u64 t = (u64)a0 * b0 + (u64)a1 * b1;
@@ -156,7 +240,7 @@ constexpr bool is_z() {
 // bytes per entry of plane 0 / plane 1 of an algebra (0: no such plane)
 template <int D>
 __host__ __device__ constexpr int plane_bytes_dev(int plane) {
-    return D == DSR_CTROP ? (plane == 0 ? 4 : 8) : (plane == 0 ? 4 : 0);
+    return D == DSR_CTROP ? (plane == 0 ? 4 : 8) : D == DSR_TOPK ? (plane == 0 ? 32 : 0) : (plane == 0 ? 4 : 0);
 }
 
 // Partition-function bookkeeping is read and written with device-scope

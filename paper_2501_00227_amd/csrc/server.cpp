@@ -319,6 +319,7 @@ tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
         if (!s || !net || !plan || !o || !job_id) return fail(TN_EINVAL, "NULL argument");
         if (plan->plan.fingerprint != net->net.fingerprint) return fail(TN_EINVAL, "plan was built for a different network");
         if (!plan->plan.sliced.empty()) return fail(TN_EINVAL, "served jobs must not be sliced");
+        if (o->semiring < TN_TROPICAL_I32 || o->semiring > TN_PARTITION_BF16) return fail(TN_EINVAL, "unknown semiring");
         std::vector<PassSpec> passes;
         tn_status st = make_passes(net->net, *o, passes);
         if (st != TN_OK) return st;

@@ -566,3 +566,37 @@ def test_fixed_spin_identities_brute_force():
         upf = oracle.spin_glass_brute_force(g, J, h, betas=[0.4], fixed={v: 1})
         assert upf["energy_min"] == up["energy_min"] + 2.0
         assert math.isclose(upf["z"][0], up["z"][0] * math.exp(-0.8), rel_tol=1e-12)
+
+
+# ----------------------------------------------------------- SizeMax(k) ----
+
+def test_topk_unit_weights_is_the_size_histogram_expanded():
+    for t in range(20):
+        g = gg.gnp(10 + t % 6, 0.3, 1000 + t)
+        hist = oracle.brute_force(g)["poly"]
+        expanded = [float(s) for s in range(len(hist) - 1, -1, -1) for _ in range(hist[s])]
+        for k in (1, 3, 8):
+            want = (expanded + [float("-inf")] * k)[:k]
+            assert oracle.brute_force_topk(g, k) == want
+
+
+def test_topk_petersen_matches_paper():
+    assert oracle.brute_force_topk(gg.petersen(), 2) == [float(x) for x in GOLD["petersen"]["size_max_2"]["value"]]
+
+
+def test_topk_weighted_empty_graph_is_the_largest_subset_sums():
+    import itertools
+    for t in range(6):
+        n = 4 + t
+        w = gg.integer_weights(n, 1100 + t, 1, 9)
+        g = gg.empty(n).with_weights(w)
+        sums = sorted((sum(float(w[i]) for i in c) for r in range(n + 1) for c in itertools.combinations(range(n), r)),
+                      reverse=True)
+        assert oracle.brute_force_topk(g, 8) == (sums + [float("-inf")] * 8)[:8]
+
+
+def test_topk_antiferromagnetic_ring():
+    """-H of the even ring with J = 1: two ground states at n, then the
+    states with two domain walls at n - 4."""
+    for n in (6, 8, 10):
+        assert oracle.spin_glass_topk(gg.cycle(n), 3) == [float(n), float(n), float(n - 4)]
