@@ -415,14 +415,20 @@ tn_status tn_solve_open(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, con
  * k largest values of -H, i.e. minus the k lowest energies): the k largest
  * total weights over all independent sets, with multiplicity, largest first.
  * Computed in max-plus over sorted lists of the eight largest values (float32
- * weights; the (x) of two lists keeps the eight largest pairwise sums) on the
- * per-node executor, sliced plans included.
- *   k      1 .. 8
- *   sizes  caller memory of k floats; fewer than k configurations: the rest
- *          is -INFINITY
- * Errors: TN_EINVAL (k out of range, plan with open vertices or built for
- * another network), TN_ENOMEM, TN_EDEVICE. */
-tn_status tn_solve_size_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, float* sizes);
+ * weights, 32-byte tensor entries; the (x) of two lists keeps the eight
+ * largest pairwise sums).
+ *   k         1 .. 8
+ *   executor  0 auto: one persistent launch for unsliced trees with
+ *             sc <= 14 (a persistent launch runs one job on one chiplet),
+ *             per-node launches otherwise; 1 per-node launches (sliced plans
+ *             too); 2 persistent (unsliced plans only)
+ *   sizes     caller memory of k floats; fewer than k configurations: the
+ *             rest is -INFINITY
+ * Synchronous.  Errors: TN_EINVAL (k or executor out of range, plan with open
+ * vertices or built for another network, executor 2 with a sliced plan),
+ * TN_ENOMEM, TN_EDEVICE. */
+tn_status tn_solve_size_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t executor,
+                              float* sizes);
 
 /* One maximum configuration (SingleConfigMax of the Sec. 5 table): an
  * independent set of largest total weight, or for a spin-glass network a

@@ -140,7 +140,7 @@ SIGNATURES = [
     ("tn_plan_gemm_shapes", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int32, c_int32_p, c_int32_p]),
     ("tn_net_condition", ctypes.c_int, [_VP, ctypes.c_int32, c_int32_p, c_int32_p, _P(_VP)]),
     ("tn_solve_open", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), ctypes.c_int64, _P(tn_result)]),
-    ("tn_solve_size_max_k", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_float)]),
+    ("tn_solve_size_max_k", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_float)]),
     ("tn_solve_single_config_max", ctypes.c_int, [_VP, _VP, _VP, c_int32_p, _P(ctypes.c_float)]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
@@ -524,11 +524,12 @@ class Context:
               if alpha - d >= 0}
         return {"size_max_k": [s if s != -2 ** 31 else float("-inf") for s in top], "counting_max_k": cm}
 
-    def solve_size_max_k(self, net: Net, plan: Plan, k: int) -> List[float]:
+    def solve_size_max_k(self, net: Net, plan: Plan, k: int, executor="auto") -> List[float]:
         """SizeMax(k) for any weights (k <= 8): the k largest total weights of
         independent sets with multiplicity (spin glass: the k largest -H)."""
         out = (ctypes.c_float * int(k))()
-        _check(lib().tn_solve_size_max_k(self.h, net.h, plan.h, int(k), out))
+        ex = EXECUTOR.get(executor, executor) if isinstance(executor, str) else int(executor)
+        _check(lib().tn_solve_size_max_k(self.h, net.h, plan.h, int(k), int(ex), out))
         return [float(x) for x in out]
 
     def solve_single_config_max(self, net: Net, plan: Plan) -> Dict:

@@ -535,24 +535,47 @@ tn_status tn_solve_open(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_s
     TN_GUARD_END
 }
 
-tn_status tn_solve_size_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, float* sizes) {
+tn_status tn_solve_size_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, int32_t executor,
+                              float* sizes) {
     TN_GUARD_BEGIN
     if (!c || !n || !p || !sizes || k < 1 || k > 8) return fail(TN_EINVAL, "invalid arguments (k in 1..8, sizes required)");
+    if (executor < 0 || executor > 2) return fail(TN_EINVAL, "executor must be 0, 1 or 2");
+    if (executor == 2 && !p->plan.sliced.empty())
+        return fail(TN_EINVAL, "the persistent executor runs unsliced plans only");
+    if (p->plan.fingerprint != n->net.fingerprint || p->plan.nv != n->net.nv)
+        return fail(TN_EINVAL, "plan was built for a different network");
     if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
-    tn_solve_opts o;
-    tn_solve_opts_default(&o);
-    o.semiring = kSemiringTop8;
-    o.executor = 1;
-    tn_result r;
-    std::vector<unsigned char> raw;
-    tn_status st = solve_one(c, n->net, p->plan, o, r, nullptr, &raw);
-    if (st != TN_OK) return st;
     if (p->plan.nleaf() == 0) {  // the empty network: one configuration of value 0
         sizes[0] = 0.0f;
         for (int t = 1; t < k; t++) sizes[t] = -INFINITY;
         return TN_OK;
     }
-    std::memcpy(sizes, raw.data(), sizeof(float) * (size_t)k);
+    float top[8];
+    // auto: one persistent launch only for small trees.  A persistent launch
+    // keeps a job on one chiplet (an eighth of the CUs); an eight-list op
+    // costs some twenty 4-byte ops, so larger trees fill the whole chip
+    // better through per-node launches.
+    const bool small = p->plan.sliced.empty() && p->plan.max_rank <= 14;
+    if (executor == 2 || (executor == 0 && small)) {
+        if (!p->plan.open.empty()) return fail(TN_EINVAL, "the plan has open vertices");
+        std::vector<PassSpec> passes(1);
+        passes[0].dsr = DSR_TOPK;
+        std::vector<std::array<unsigned char, kAccSlotBytes>> accs;
+        tn_status st = run_passes_sync(c, n->net, p->plan, passes, accs);
+        if (st != TN_OK) return st;
+        std::memcpy(top, accs[0].data(), sizeof top);
+    } else {
+        tn_solve_opts o;
+        tn_solve_opts_default(&o);
+        o.semiring = kSemiringTop8;
+        o.executor = 1;
+        tn_result r;
+        std::vector<unsigned char> raw;
+        tn_status st = solve_one(c, n->net, p->plan, o, r, nullptr, &raw);
+        if (st != TN_OK) return st;
+        std::memcpy(top, raw.data(), sizeof top);
+    }
+    std::memcpy(sizes, top, sizeof(float) * (size_t)k);
     return TN_OK;
     TN_GUARD_END
 }

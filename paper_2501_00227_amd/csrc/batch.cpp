@@ -35,12 +35,15 @@ int small_rank(size_t njobs, int nworkgroups) {
     if (env >= 0) return env;
     return (int)njobs >= nworkgroups / 4 ? 12 : 0;
 }
-// a large node is cut into at most this many tasks (each loops over tiles)
+// a large node is cut into at most this many tasks (each loops over tiles);
+// the eight-largest algebra's GEMM tiles cost some twenty times a 4-byte
+// tile, so its GEMMs get one task per resident workgroup (two per CU)
 constexpr int64_t kMaxTasksPerNode = 64;
+constexpr int64_t kMaxTasksPerNodeTop8 = 512;
 
-int64_t chunk(int64_t ntiles) {  // tiles per task (powers of two divide exactly)
+int64_t chunk(int64_t ntiles, int64_t max_tasks = kMaxTasksPerNode) {  // tiles per task (powers of two divide exactly)
     int64_t per = 1;
-    while (ntiles / per > kMaxTasksPerNode) per *= 2;
+    while (ntiles / per > max_tasks) per *= 2;
     return per;
 }
 
@@ -208,11 +211,13 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
             if (!perm) continue;
             int slot = side ? jp.dp->perm_slot_b[t] : jp.dp->perm_slot_a[t];
             int rank = (int)p.order[child].size();
-            N.pp[side] = jp.dp->perms + slot;
+            // 32-byte entries move as eight 4-byte words: three more bits, kept lowest
+            const int wide = jp.dsr == DSR_TOPK ? 3 : 0;
+            N.pp[side] = (wide ? jp.dp->perms_wide : jp.dp->perms) + slot;
             N.psrc[side] = p.node_off_dag[child];
             N.pdst[side] = side ? np.dag_b_tmp : np.dag_a_tmp;
-            N.prank[side] = rank;
-            N.ptile_bits[side] = perm_tile_bits(rank);
+            N.prank[side] = rank + wide;
+            N.ptile_bits[side] = perm_tile_bits(rank + wide);
         }
         T.ops += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk));
         T.bytes += (std::exp2((double)(N.g.lb + N.g.li + N.g.lk)) + std::exp2((double)(N.g.lb + N.g.lk + N.g.lj)) +
@@ -257,7 +262,7 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
             ready[side] = c;
         }
         int64_t nblocks = (int64_t)1 << ((N.g.lb - N.g.tb) + (N.g.li - N.g.ti) + (N.g.lj - N.g.tj) + N.g.lsplit);
-        int64_t per = chunk(nblocks);
+        int64_t per = chunk(nblocks, jp.dsr == DSR_TOPK ? kMaxTasksPerNodeTop8 : kMaxTasksPerNode);
         Counter gdone{T.ncounters++, (int)(nblocks / per), std::max(ready[0].level, ready[1].level) + 1};
         for (int64_t k = 0; k < nblocks / per; k++)
             add(BT_GEMM, nidx, 0, k * per, ready[0], ready[1], gdone.id, gdone.level, (int)per);
@@ -327,8 +332,6 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             st.passes = *it.passes;
         else
             s = make_passes(*it.net, it.opts, st.passes);
-        for (const PassSpec& ps : st.passes)
-            if (ps.dsr == DSR_TOPK) s = fail(TN_EINVAL, "the eight-largest algebra runs on the per-node executor only");
         if (s != TN_OK) {
             st.status = s;
             continue;
@@ -370,10 +373,10 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     }
     L.njobs = (int)jobs.size();
     if (jobs.empty()) return TN_OK;
-    // every job's 16-byte root accumulator, side by side: one read-back
+    // every job's root accumulator slot, side by side: one read-back
     const size_t o_accs = data;
-    for (size_t ji = 0; ji < jobs.size(); ji++) jobs[ji].o_acc = o_accs + 16 * ji;
-    data = a256(data + 16 * jobs.size());
+    for (size_t ji = 0; ji < jobs.size(); ji++) jobs[ji].o_acc = o_accs + kAccSlotBytes * ji;
+    data = a256(data + kAccSlotBytes * jobs.size());
     L.data_bytes = std::max<size_t>(data, 256);
     L.data = alloc.alloc(L.data_bytes);
     if (!L.data) return fail(TN_ENOMEM, "device allocation of " + std::to_string(L.data_bytes) + " bytes failed");
@@ -526,7 +529,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     L.tables = alloc.alloc(L.table_bytes);
     if (!L.tables) return fail(TN_ENOMEM, "device allocation of the task table failed");
     size_t wbytes = weights_end;
-    L.host_bytes = o_end + wbytes + 16 * jobs.size() + sizeof(int) * nq + 1024;
+    L.host_bytes = o_end + wbytes + kAccSlotBytes * jobs.size() + sizeof(int) * nq + 1024;
     L.o_reset = o_cnt;
     L.reset_bytes = o_tick + sizeof(int) * (size_t)nq - o_cnt;
     L.host = pinned_acquire(ctx, L.host_bytes);
@@ -556,7 +559,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             std::memcpy(h + o_end + item_w_off[i], items[i].net->wdev.data(), sizeof(float) * items[i].net->wdev.size());
     L.wbytes = wbytes;
     L.o_hacc = o_end + wbytes;
-    L.o_hticket = a256(L.o_hacc + 16 * jobs.size());
+    L.o_hticket = a256(L.o_hacc + kAccSlotBytes * jobs.size());
     L.d_accs = dbase + o_accs;
     return TN_OK;
 }
@@ -585,7 +588,7 @@ tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
     if (e == hipSuccess)
         e = hipMemcpyAsync((unsigned char*)L.host + L.o_hticket, L.d_ticket, sizeof(int) * L.nq, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync((unsigned char*)L.host + L.o_hacc, L.d_accs, 16 * (size_t)L.njobs, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync((unsigned char*)L.host + L.o_hacc, L.d_accs, kAccSlotBytes * (size_t)L.njobs, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return fail(TN_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
     return TN_OK;
 }
@@ -611,7 +614,7 @@ tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out) {
             std::vector<std::vector<unsigned char>> accs;
             for (int j : st.job_ids) {
                 std::vector<unsigned char> a(16);
-                std::memcpy(a.data(), (unsigned char*)L.host + L.o_hacc + 16 * j, 16);
+                std::memcpy(a.data(), (unsigned char*)L.host + L.o_hacc + kAccSlotBytes * j, 16);
                 accs.push_back(a);
             }
             s = decode_result(st.opts, st.passes, accs, out[i]);
@@ -748,7 +751,7 @@ tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vect
 }
 
 tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
-                          std::vector<std::array<unsigned char, 16>>& accs) {
+                          std::vector<std::array<unsigned char, kAccSlotBytes>>& accs) {
     BatchLaunch L;
     tn_status st = run_passes_keep(ctx, net, plan, passes, accs, L);
     batch_done(ctx, L);
@@ -762,7 +765,7 @@ void batch_done(tn_ctx* ctx, BatchLaunch& L) {
 }
 
 tn_status run_passes_keep(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
-                          std::vector<std::array<unsigned char, 16>>& accs, BatchLaunch& L) {
+                          std::vector<std::array<unsigned char, kAccSlotBytes>>& accs, BatchLaunch& L) {
     std::vector<BatchItem> items(1);
     items[0].net = &net;
     items[0].plan = &plan;
@@ -776,11 +779,12 @@ tn_status run_passes_keep(tn_ctx* ctx, const Net& net, const Plan& plan, const s
     if (st == TN_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(TN_EDEVICE, "batch execution failed");
     std::vector<tn_result> out;
     if (st == TN_OK) st = batch_finish(L, out);
+    if (st == TN_OK && L.d_trace) collect_trace(ctx, L);
     if (st == TN_OK) {
         accs.assign(passes.size(), {});
         const std::vector<int>& ids = L.items[0].job_ids;
         for (size_t k = 0; k < ids.size() && k < accs.size(); k++)
-            std::memcpy(accs[k].data(), (unsigned char*)L.host + L.o_hacc + 16 * (size_t)ids[k], 16);
+            std::memcpy(accs[k].data(), (unsigned char*)L.host + L.o_hacc + kAccSlotBytes * (size_t)ids[k], kAccSlotBytes);
     }
     return st;
 }

@@ -55,7 +55,7 @@ struct BatchLaunch {
     int nq = 1;
     std::vector<int> qbegin, qcount;
     size_t o_hticket = 0;
-    void* d_accs = nullptr;   // the jobs' root accumulators, 16 bytes each
+    void* d_accs = nullptr;   // the jobs' root accumulator slots, kAccSlotBytes each
     size_t o_reset = 0, reset_bytes = 0;  // counters and tickets within the tables
     bool uploaded = false;    // tables and weights are on the device
     std::vector<void*> job_arena0;  // plane 0 of every job's arena (dependency-graph layout)
@@ -77,13 +77,13 @@ void batch_release(BatchLaunch& L);
 void collect_trace(tn_ctx* ctx, BatchLaunch& L);
 tn_status solve_batch_sync(tn_ctx* ctx, std::vector<BatchItem>& items, std::vector<tn_result>& out);
 // One synchronous persistent launch of explicit passes of one unsliced
-// network; accs receives the 16-byte root accumulator of every pass, in order.
+// network; accs receives the root accumulator slot of every pass, in order.
 tn_status run_passes_sync(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
-                          std::vector<std::array<unsigned char, 16>>& accs);
+                          std::vector<std::array<unsigned char, kAccSlotBytes>>& accs);
 // As run_passes_sync, but the launch stays alive (its arenas hold every
 // tensor of the contraction) until batch_done.
 tn_status run_passes_keep(tn_ctx* ctx, const Net& net, const Plan& plan, const std::vector<PassSpec>& passes,
-                          std::vector<std::array<unsigned char, 16>>& accs, BatchLaunch& L);
+                          std::vector<std::array<unsigned char, kAccSlotBytes>>& accs, BatchLaunch& L);
 void batch_done(tn_ctx* ctx, BatchLaunch& L);
 // One maximum configuration (SingleConfigMax): config[v] in {0, 1}.
 tn_status single_config_max(tn_ctx* ctx, const Net& net, const Plan& plan, int32_t* config, float* value);

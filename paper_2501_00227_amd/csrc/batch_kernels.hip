@@ -71,6 +71,10 @@ __device__ __attribute__((always_inline)) void run_gemm(const BJob& j, const BNo
     g.mb = nd.mb;
     g.mc = nd.mc;
     const int rm = nd.g.rm, rn = nd.g.rn;
+    if constexpr (D == DSR_TOPK) {  // 32-byte entries: one output per thread only
+        gemm_tile<D, 1, 1>(g, (u64)tile, smem);
+        return;
+    }
     if (nd.g.mode == GEMM_THIN) {
         gemm_tile_thin<D>(g, (u64)tile, smem);
         return;
@@ -127,9 +131,9 @@ __device__ void run_perm(const BJob& j, const BNode& nd, int side, int plane, i6
     unsigned char* tile = smem + ((sizeof(PermLds) + 255) & ~(size_t)255);
     const int nt = nd.prank[side] - nd.ptile_bits[side];
     for (int k = 0; k < count; k++) {
-        if (pb == 4)
-            permute_tile<unsigned int>((const unsigned int*)(base + nd.psrc[side] * 4),
-                                       (unsigned int*)(base + nd.pdst[side] * 4), tabs, (unsigned int*)tile,
+        if (pb == 4 || pb == 32)  // 32-byte entries: their 4-byte words, by the host's widened tables
+            permute_tile<unsigned int>((const unsigned int*)(base + nd.psrc[side] * pb),
+                                       (unsigned int*)(base + nd.pdst[side] * pb), tabs, (unsigned int*)tile,
                                        nd.ptile_bits[side], nt, first + k);
         else
             permute_tile<u64>((const u64*)(base + nd.psrc[side] * 8), (u64*)(base + nd.pdst[side] * 8), tabs,
@@ -152,6 +156,13 @@ __device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count,
         return;
     }
     const int S = 1 << nd.g.lsplit;
+    if constexpr (D == DSR_TOPK) {  // 32-byte entries: one unit at a time
+        for (int k = 0; k < count; k++) {
+            const i64 o = (first + k) * 256 + threadIdx.x;
+            if (o < nd.nout) A::store(C, o, split_sum<D>(P, nd.nout, o, S, j.ap));
+        }
+        return;
+    }
     float lmax = 0.0f;
     for (int k = 0; k < count; k += 4) {
         // four units per pass: with at most 4 splits all their loads are in
@@ -299,6 +310,7 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
         case DSR_MODP: run_task<DSR_MODP>(t, j, nodes, subtree, smem); break;
         case DSR_Z_F32: run_task<DSR_Z_F32>(t, j, nodes, subtree, smem); break;
         case DSR_Z_BF16: run_task<DSR_Z_BF16>(t, j, nodes, subtree, smem); break;
+        case DSR_TOPK: run_task<DSR_TOPK>(t, j, nodes, subtree, smem); break;
         default: break;
         }
         signal_counter(counters, t.signal);

@@ -56,7 +56,7 @@ tn_status single_config_max(tn_ctx* ctx, const Net& net, const Plan& plan, int32
     if (nleaf > 0) {
         std::vector<PassSpec> passes(1);
         passes[0].dsr = DSR_TROP_F32;
-        std::vector<std::array<unsigned char, 16>> accs;
+        std::vector<std::array<unsigned char, kAccSlotBytes>> accs;
         BatchLaunch L;
         tn_status st = run_passes_keep(ctx, net, plan, passes, accs, L);
         if (st == TN_OK) std::memcpy(&root, accs[0].data(), 4);

@@ -148,6 +148,17 @@ __device__ inline Top8 top8_merge(const Top8& a, const Top8& b) {
     return r;
 }
 
+// x joins the sorted list r, keeping the eight largest, when at least F
+// entries of r are known to be >= x: entry t > F becomes the median of
+// r[t], r[t-1] and x (x clamped into [r[t], r[t-1]]), entry F max(r[F], x).
+// Lists hold no NaN (entries are finite or -inf), so the median is exact.
+template <int F>
+__device__ inline void top8_insert(Top8& r, float x) {
+#pragma unroll
+    for (int t = 7; t > F; t--) r.v[t] = __builtin_amdgcn_fmed3f(r.v[t], r.v[t - 1], x);
+    r.v[F] = fmaxf(r.v[F], x);
+}
+
 template <>
 struct Alg<DSR_TOPK> {
     using V = Top8;
@@ -163,18 +174,27 @@ struct Alg<DSR_TOPK> {
         return r;
     }
     __device__ static V add(const V& a, const V& b, const AlgebraParams&) { return top8_merge(a, b); }
-    // a[i] + b[j] can be among the eight largest sums only if (i+1)(j+1) <= 8
+    // The candidates a[i] + b[j] with (i+1)(j+1) <= 8 (twenty; no other pair
+    // can be among the eight largest).  Start from column j = 0 (sorted), then
+    // insert the rest in an order where every pair (i', j') <= (i, j) is
+    // already in: then (i+1)(j+1) - 1 entries are known to be >= a[i] + b[j],
+    // and its insertion touches only the list's tail.
     __device__ static V mul(const V& a, const V& b, const AlgebraParams&) {
         V r;
 #pragma unroll
         for (int i = 0; i < 8; i++) r.v[i] = a.v[i] + b.v[0];
-#pragma unroll
-        for (int j = 1; j < 8; j++) {
-            V c;
-#pragma unroll
-            for (int i = 0; i < 8; i++) c.v[i] = (i + 1) * (j + 1) <= 8 ? a.v[i] + b.v[j] : -INFINITY;
-            r = top8_merge(r, c);
-        }
+        top8_insert<1>(r, a.v[0] + b.v[1]);
+        top8_insert<2>(r, a.v[0] + b.v[2]);
+        top8_insert<3>(r, a.v[0] + b.v[3]);
+        top8_insert<4>(r, a.v[0] + b.v[4]);
+        top8_insert<5>(r, a.v[0] + b.v[5]);
+        top8_insert<6>(r, a.v[0] + b.v[6]);
+        top8_insert<7>(r, a.v[0] + b.v[7]);
+        top8_insert<3>(r, a.v[1] + b.v[1]);
+        top8_insert<5>(r, a.v[2] + b.v[1]);
+        top8_insert<5>(r, a.v[1] + b.v[2]);
+        top8_insert<7>(r, a.v[3] + b.v[1]);
+        top8_insert<7>(r, a.v[1] + b.v[3]);
         return r;
     }
     __device__ static V weight(float w, const AlgebraParams& ap) {

@@ -148,7 +148,7 @@ tn_status solve_polynomial(tn_ctx* ctx, const Net& net, const Plan& plan, int li
     std::vector<uint32_t> vals(all.size());
     for (size_t b = 0; b < all.size(); b += 256) {
         std::vector<PassSpec> chunk(all.begin() + b, all.begin() + std::min(all.size(), b + 256));
-        std::vector<std::array<unsigned char, 16>> accs;
+        std::vector<std::array<unsigned char, kAccSlotBytes>> accs;
         st = run_passes_sync(ctx, net, plan, chunk, accs);
         if (st != TN_OK) return st;
         for (size_t k = 0; k < chunk.size(); k++) {
