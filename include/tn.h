@@ -430,6 +430,26 @@ tn_status tn_solve_open(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, con
 tn_status tn_solve_size_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t executor,
                               float* sizes);
 
+/* CountingMax(k) of the Sec. 5 table for integer weights (and for spin
+ * glasses with integer J and h: values of -H): the number of configurations
+ * at each of the k values top, top - 1, ..., top - k + 1, where top is the
+ * largest value.  Computed in one contraction over truncated polynomials
+ * (per tensor entry the four highest-order terms c_d x^(m - d) of the
+ * polynomial whose exponents are configuration values; (+) aligns two such
+ * lists by their top exponent, (x) adds exponents and convolves the counts)
+ * on the per-node executor, sliced plans included.  Counts are modulo 2^64
+ * (as TN_COUNTING_TROPICAL); a value in between that no configuration takes
+ * has count 0.
+ *   k       1 .. 4
+ *   top     out: the largest value; INT32_MIN if no configuration satisfies
+ *           the fixed vertices (then every count is 0)
+ *   counts  caller memory of k uint64: counts[d] at value top - d
+ * Synchronous.  Errors: TN_EINVAL (k out of range, non-integer weights,
+ * plan with open vertices or built for another network), TN_ENOMEM,
+ * TN_EDEVICE. */
+tn_status tn_solve_counting_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t* top,
+                                  uint64_t* counts);
+
 /* One maximum configuration (SingleConfigMax of the Sec. 5 table): an
  * independent set of largest total weight, or for a spin-glass network a
  * ground state (a configuration of smallest energy H, Sec. 2).  The max-plus

@@ -74,8 +74,14 @@ def _load():
                                              ctypes.c_uint64, ctypes.c_uint64]
         lib.orc_brute_force_sg_topk.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, f64p,
                                                 ctypes.c_uint64, ctypes.c_uint64]
+        i64p = P(ctypes.c_int64)
+        lib.orc_brute_force_count_top.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, ctypes.c_int, i64p, u64p,
+                                                  ip, ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_brute_force_sg_count_top.argtypes = [ctypes.c_int, ctypes.c_int, i32p, f64p, f64p, ctypes.c_int, i64p,
+                                                     u64p, ip, ctypes.c_uint64, ctypes.c_uint64]
         for f in (lib.orc_brute_force, lib.orc_eliminate, lib.orc_eliminate_poly, lib.orc_eliminate_sg,
-                  lib.orc_brute_force_sg, lib.orc_follow_plan, lib.orc_brute_force_topk, lib.orc_brute_force_sg_topk):
+                  lib.orc_brute_force_sg, lib.orc_follow_plan, lib.orc_brute_force_topk, lib.orc_brute_force_sg_topk,
+                  lib.orc_brute_force_count_top, lib.orc_brute_force_sg_count_top):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -243,6 +249,44 @@ def spin_glass_topk(graph, k: int, J=None, h=None, fixed=None) -> List[float]:
     if rc != ORC_OK:
         raise OracleError(rc, "spin_glass_topk")
     return [float(x) for x in out]
+
+
+def _count_top_result(rc, name, top, cnt, found, k):
+    if rc != ORC_OK:
+        raise OracleError(rc, name)
+    if not found.value:
+        return {"top": float("-inf"), "counts": {}}
+    t = int(top.value)
+    return {"top": t, "counts": {t - d: int(cnt[d]) for d in range(k)}}
+
+
+def brute_force_counting_max_k(graph, k: int, fixed=None) -> Dict:
+    """CountingMax(k) by enumeration (integer weights, n <= 24): {"top": the
+    largest set weight, "counts": {top - d: number of independent sets of
+    that weight}} (exact; {"top": -inf} if no set meets the fixings)."""
+    lib = _load()
+    edges, w = _graph_arrays(graph)
+    fmask, fval = _fix_masks(fixed)
+    top, found = ctypes.c_int64(0), ctypes.c_int(0)
+    cnt = np.zeros(k, np.uint64)
+    rc = lib.orc_brute_force_count_top(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(w, ctypes.c_double), k,
+                                       ctypes.byref(top), _ptr(cnt, ctypes.c_uint64), ctypes.byref(found), fmask, fval)
+    return _count_top_result(rc, "brute_force_counting_max_k", top, cnt, found, k)
+
+
+def spin_glass_counting_max_k(graph, k: int, J=None, h=None, fixed=None) -> Dict:
+    """CountingMax(k) of a spin glass with integer J, h by enumeration: the
+    largest -H and the number of spin configurations at -H = top - d."""
+    lib = _load()
+    edges, _ = _graph_arrays(graph)
+    Ja, ha = _sg_arrays(graph, J, h)
+    fmask, fval = _fix_masks(fixed)
+    top, found = ctypes.c_int64(0), ctypes.c_int(0)
+    cnt = np.zeros(k, np.uint64)
+    rc = lib.orc_brute_force_sg_count_top(graph.nv, graph.ne, _ptr(edges, ctypes.c_int32), _ptr(Ja, ctypes.c_double),
+                                          _ptr(ha, ctypes.c_double), k, ctypes.byref(top), _ptr(cnt, ctypes.c_uint64),
+                                          ctypes.byref(found), fmask, fval)
+    return _count_top_result(rc, "spin_glass_counting_max_k", top, cnt, found, k)
 
 
 def spin_glass_eliminate(graph, semiring: str, J=None, h=None, beta: float = 0.0, max_width: int = 26) -> Dict:

@@ -26,6 +26,9 @@
  *                         (energy H = sum J s s + sum h s, Sec. 6.4 buckyball)
  *       orc_brute_force_topk, orc_brute_force_sg_topk  the k largest values
  *                         with multiplicity (SizeMax(k)) by enumeration
+ *       orc_brute_force_count_top, orc_brute_force_sg_count_top  the number
+ *                         of configurations at the k highest integer values
+ *                         top, top - 1, ... (CountingMax(k)) by enumeration
  *   O3  orc_follow_plan   evaluate a given binary contraction tree (Sec. 4.1),
  *                         one literal einsum loop per node, with optional
  *                         sliced indices (Sec. 4.2, TreeSA slicing)
@@ -1096,4 +1099,101 @@ int orc_follow_plan(int nv, int ne, const int32_t* edges, const double* w, int s
     if (status != ORC_OK) return status;
     put_result(sr, total, size, limbs, zval, logz);
     return g_overflow ? ORC_EOVERFLOW : ORC_OK;
+}
+
+/* CountingMax(k) of the Sec. 5 table by enumeration: the largest value over
+ * all configurations (independent sets: total weight; spin glass: -H) and the
+ * number of configurations at each value top - d, d < k.  Integer weights
+ * only (the values are then integers); counts are exact (n <= 30). */
+static int count_top_values(const long long* vals, const unsigned char* ok, uint64_t nconf, int k, long long* top,
+                            uint64_t* counts) {
+    int any = 0;
+    long long best = 0;
+    for (uint64_t m = 0; m < nconf; m++)
+        if (ok[m] && (!any || vals[m] > best)) {
+            best = vals[m];
+            any = 1;
+        }
+    for (int d = 0; d < k; d++) counts[d] = 0;
+    if (!any) return 0;
+    for (uint64_t m = 0; m < nconf; m++)
+        if (ok[m] && best - vals[m] < k) counts[best - vals[m]]++;
+    *top = best;
+    return 1;
+}
+
+static int is_integral(const double* x, int n) {
+    for (int i = 0; x && i < n; i++)
+        if (x[i] != floor(x[i]) || fabs(x[i]) > 65536.0) return 0;
+    return 1;
+}
+
+int orc_brute_force_count_top(int nv, int ne, const int32_t* edges, const double* w, int k, int64_t* top,
+                              uint64_t* counts, int* found, uint64_t fix_mask, uint64_t fix_val) {
+    if (nv < 0 || nv > 24 || ne < 0 || k < 1 || k > 64 || !is_integral(w, nv)) return ORC_EINVAL;
+    uint64_t nbr[64] = {0};
+    for (int e = 0; e < ne; e++) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= nv || v >= nv || u == v) return ORC_EINVAL;
+        nbr[u] |= 1ull << v;
+        nbr[v] |= 1ull << u;
+    }
+    const uint64_t nconf = 1ull << nv;
+    long long* vals = (long long*)malloc(sizeof(long long) * nconf);
+    unsigned char* ok = (unsigned char*)malloc(nconf);
+    if (!vals || !ok) {
+        free(vals);
+        free(ok);
+        return ORC_EINVAL;
+    }
+    for (uint64_t S = 0; S < nconf; S++) {
+        int good = (S & fix_mask) == fix_val;
+        for (int v = 0; v < nv && good; v++)
+            if (((S >> v) & 1) && (S & nbr[v])) good = 0;
+        long long ws = 0;
+        for (int v = 0; v < nv; v++)
+            if ((S >> v) & 1) ws += w ? (long long)w[v] : 1;
+        ok[S] = (unsigned char)good;
+        vals[S] = ws;
+    }
+    long long t = 0;
+    *found = count_top_values(vals, ok, nconf, k, &t, counts);
+    *top = t;
+    free(vals);
+    free(ok);
+    return ORC_OK;
+}
+
+int orc_brute_force_sg_count_top(int nv, int ne, const int32_t* edges, const double* J, const double* h, int k,
+                                 int64_t* top, uint64_t* counts, int* found, uint64_t fix_mask, uint64_t fix_val) {
+    if (nv < 0 || nv > 24 || ne < 0 || k < 1 || k > 64 || !is_integral(J, ne) || !is_integral(h, nv))
+        return ORC_EINVAL;
+    for (int e = 0; e < ne; e++) {
+        int u = edges[2 * e], v = edges[2 * e + 1];
+        if (u < 0 || v < 0 || u >= nv || v >= nv || u == v) return ORC_EINVAL;
+    }
+    const uint64_t nconf = 1ull << nv;
+    long long* vals = (long long*)malloc(sizeof(long long) * nconf);
+    unsigned char* ok = (unsigned char*)malloc(nconf);
+    if (!vals || !ok) {
+        free(vals);
+        free(ok);
+        return ORC_EINVAL;
+    }
+    for (uint64_t m = 0; m < nconf; m++) {
+        long long H = 0;
+        for (int e = 0; e < ne; e++) {
+            int su = (int)((m >> edges[2 * e]) & 1) * 2 - 1, sv = (int)((m >> edges[2 * e + 1]) & 1) * 2 - 1;
+            H += (long long)(J ? J[e] : 1.0) * su * sv;
+        }
+        for (int v = 0; v < nv; v++) H += (long long)(h ? h[v] : 0.0) * (int)(((m >> v) & 1) * 2 - 1);
+        ok[m] = (unsigned char)((m & fix_mask) == fix_val);
+        vals[m] = -H;
+    }
+    long long t = 0;
+    *found = count_top_values(vals, ok, nconf, k, &t, counts);
+    *top = t;
+    free(vals);
+    free(ok);
+    return ORC_OK;
 }

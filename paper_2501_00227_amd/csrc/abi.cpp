@@ -580,6 +580,39 @@ tn_status tn_solve_size_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int3
     TN_GUARD_END
 }
 
+tn_status tn_solve_counting_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, int32_t* top,
+                                  uint64_t* counts) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p || !top || !counts || k < 1 || k > 4)
+        return fail(TN_EINVAL, "invalid arguments (k in 1..4, top and counts required)");
+    if (p->plan.fingerprint != n->net.fingerprint || p->plan.nv != n->net.nv)
+        return fail(TN_EINVAL, "plan was built for a different network");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    tn_solve_opts o;
+    tn_solve_opts_default(&o);
+    o.semiring = kSemiringTPoly4;
+    o.executor = 1;
+    tn_result r;
+    std::vector<unsigned char> raw;
+    tn_status st = solve_one(c, n->net, p->plan, o, r, nullptr, &raw);
+    if (st != TN_OK) return st;
+    if (p->plan.nleaf() == 0) {  // the empty network: one configuration of value 0
+        *top = 0;
+        counts[0] = 1;
+        for (int d = 1; d < k; d++) counts[d] = 0;
+        return TN_OK;
+    }
+    int32_t m;
+    uint64_t cnt[4];
+    std::memcpy(&m, raw.data(), 4);
+    std::memcpy(cnt, raw.data() + 8, sizeof cnt);
+    const bool none = m <= -(1 << 30);  // no configuration at all
+    *top = none ? INT32_MIN : m;
+    for (int d = 0; d < k; d++) counts[d] = none ? 0 : cnt[d];
+    return TN_OK;
+    TN_GUARD_END
+}
+
 tn_status tn_solve_single_config_max(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t* config, float* value) {
     TN_GUARD_BEGIN
     if (!c || !n || !p) return fail(TN_EINVAL, "NULL argument");

@@ -332,6 +332,8 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             st.passes = *it.passes;
         else
             s = make_passes(*it.net, it.opts, st.passes);
+        for (const PassSpec& ps : st.passes)
+            if (ps.dsr == DSR_TPOLY) s = fail(TN_EINVAL, "the truncated-polynomial algebra runs on the per-node executor only");
         if (s != TN_OK) {
             st.status = s;
             continue;

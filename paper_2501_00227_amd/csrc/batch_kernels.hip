@@ -73,44 +73,44 @@ __device__ __attribute__((always_inline)) void run_gemm(const BJob& j, const BNo
     const int rm = nd.g.rm, rn = nd.g.rn;
     if constexpr (D == DSR_TOPK) {  // 32-byte entries: one output per thread only
         gemm_tile<D, 1, 1>(g, (u64)tile, smem);
-        return;
-    }
-    if (nd.g.mode == GEMM_THIN) {
-        gemm_tile_thin<D>(g, (u64)tile, smem);
-        return;
-    }
-    if (nd.g.mode == GEMM_DOT) {
-        gemm_tile_dot<D>(g, (u64)tile, smem);
-        return;
-    }
-    if constexpr (is_z<D>()) {
-        if (nd.g.mfma) {
-            gemm_tile_mfma<D>(g, (u64)tile, smem);
+    } else {
+        if (nd.g.mode == GEMM_THIN) {
+            gemm_tile_thin<D>(g, (u64)tile, smem);
             return;
         }
-    }
-    if constexpr (big_tile_ok<D>()) {
-        if (rm == 8) {
-            gemm_tile_big_any<D>(g, (u64)tile, smem);
+        if (nd.g.mode == GEMM_DOT) {
+            gemm_tile_dot<D>(g, (u64)tile, smem);
             return;
         }
-    }
-    if constexpr (D == DSR_CTROP) {
-        if (rm == 8) {
-            gemm_tile_ct_big_any<D>(g, (u64)tile, smem);
-            return;
+        if constexpr (is_z<D>()) {
+            if (nd.g.mfma) {
+                gemm_tile_mfma<D>(g, (u64)tile, smem);
+                return;
+            }
         }
+        if constexpr (big_tile_ok<D>()) {
+            if (rm == 8) {
+                gemm_tile_big_any<D>(g, (u64)tile, smem);
+                return;
+            }
+        }
+        if constexpr (D == DSR_CTROP) {
+            if (rm == 8) {
+                gemm_tile_ct_big_any<D>(g, (u64)tile, smem);
+                return;
+            }
+        }
+        if (rm == 2 && rn == 2)
+            gemm_tile<D, 2, 2>(g, (u64)tile, smem);
+        else if (rm == 4 && rn == 4)
+            gemm_tile<D, 4, 4>(g, (u64)tile, smem);
+        else if (rm == 1 && rn == 2)
+            gemm_tile<D, 1, 2>(g, (u64)tile, smem);
+        else if (rm == 2 && rn == 1)
+            gemm_tile<D, 2, 1>(g, (u64)tile, smem);
+        else
+            gemm_tile<D, 1, 1>(g, (u64)tile, smem);
     }
-    if (rm == 2 && rn == 2)
-        gemm_tile<D, 2, 2>(g, (u64)tile, smem);
-    else if (rm == 4 && rn == 4)
-        gemm_tile<D, 4, 4>(g, (u64)tile, smem);
-    else if (rm == 1 && rn == 2)
-        gemm_tile<D, 1, 2>(g, (u64)tile, smem);
-    else if (rm == 2 && rn == 1)
-        gemm_tile<D, 2, 1>(g, (u64)tile, smem);
-    else
-        gemm_tile<D, 1, 1>(g, (u64)tile, smem);
 }
 
 // stores of this workgroup visible to its own later loads (same CU)

@@ -285,6 +285,10 @@ tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSp
     case TN_PARTITION_F32: passes.push_back({DSR_Z_F32, 0}); break;
     case TN_PARTITION_BF16: passes.push_back({DSR_Z_BF16, 0}); break;
     case kSemiringTop8: passes.push_back({DSR_TOPK, 0}); break;
+    case kSemiringTPoly4:
+        if (!net.integer_weights) return fail(TN_EINVAL, "CountingMax(k) needs integer weights (|w| <= 65536)");
+        passes.push_back({DSR_TPOLY, 0});
+        break;
     default: return fail(TN_EINVAL, "unknown semiring");
     }
     if ((o.semiring == TN_PARTITION_F32 || o.semiring == TN_PARTITION_BF16) && !std::isfinite(o.beta))
@@ -402,7 +406,8 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
         res.z = m == 0.0 ? 0.0 : (e > 1100 ? INFINITY : std::ldexp(m, (int)std::max<int64_t>(e, -2000)));
         break;
     }
-    case kSemiringTop8: break;  // the caller reads the raw accumulator
+    case kSemiringTop8:
+    case kSemiringTPoly4: break;  // the caller reads the raw accumulator
     default: return fail(TN_EINVAL, "unknown semiring");
     }
     return TN_OK;
@@ -533,8 +538,8 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                         ProfScope ps(ctx, TN_K_PERMUTE, np.node, o.semiring, shp,
                                      2.0 * (double)node_entries(plan, src_node) * pbytes, 0);
                         if (pbytes == 32)  // 32-byte entries: 4-byte words, the three lowest bits in place
-                            chk(launch_permute(4, src.p0, dst.p0, dp->perms_wide + slot, rank + 3,
-                                               perm_tile_bits(rank + 3), s),
+                            chk(launch_permute(4, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms_wide + slot,
+                                               rank + 3, perm_tile_bits(rank + 3), s),
                                 "permute");
                         else
                             chk(launch_permute(pbytes, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms + slot,

@@ -121,9 +121,11 @@ struct PassSpec {
     uint32_t prime;
     uint32_t xval = 1;  // mod p: value of x in the vertex tensors [1, x] (1: counting)
 };
-// Internal semiring code (not part of tn_semiring): the eight largest values
-// (SizeMax(k), k <= 8); per-node executor only, raw accumulator result.
+// Internal semiring codes (not part of tn_semiring), raw accumulator results:
+// the eight largest values (SizeMax(k), k <= 8) and the truncated polynomial
+// of the four highest orders (CountingMax(k), k <= 4; per-node executor).
 constexpr int kSemiringTop8 = 100;
+constexpr int kSemiringTPoly4 = 101;
 tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes);
 AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval = 1);
 // Decode the accumulators of all passes into the result struct.

@@ -16,8 +16,9 @@ enum DevSemiring {
     DSR_MODP = 3,    // Montgomery form, R = 2^32
     DSR_Z_F32 = 4,   // float32 with per-tensor power-of-two exponents
     DSR_Z_BF16 = 5,  // as DSR_Z_F32, GEMM inputs rounded to bfloat16
-    DSR_TOPK = 6,    // the eight largest values with multiplicity (32-byte entries; per-node executor only)
-    DSR_COUNT_ = 7
+    DSR_TOPK = 6,    // the eight largest values with multiplicity (32-byte entries)
+    DSR_TPOLY = 7,   // truncated polynomial: plane 0 int32 top exponent, plane 1 four uint64 counts
+    DSR_COUNT_ = 8
 };
 
 // bytes per entry of plane 0 / plane 1 (0 = no such plane)
@@ -99,7 +100,7 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, int64_t nout, int
 // acc[e] (+)= root[e] for the nent root entries, kAccSlotBytes apart; first
 // != 0 copies.  For the partition function a slot is {double mantissa, int64
 // exponent}.
-constexpr int kAccSlotBytes = 32;
+constexpr int kAccSlotBytes = 48;
 hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
                              const AlgebraParams& ap, hipStream_t s, long long nent = 1);
 // The device-side identity element of a whole (empty) network.

@@ -26,6 +26,7 @@ int plane_bytes(int dsr, int plane) {
     switch (dsr) {
     case DSR_CTROP: return plane == 0 ? 4 : 8;
     case DSR_TOPK: return plane == 0 ? 32 : 0;
+    case DSR_TPOLY: return plane == 0 ? 4 : 32;
     default: return plane == 0 ? 4 : 0;
     }
 }
@@ -34,6 +35,7 @@ static int lds_elem_bytes(int dsr) {
     switch (dsr) {
     case DSR_CTROP: return 16;
     case DSR_TOPK: return 32;
+    case DSR_TPOLY: return (int)sizeof(TP4);
     default: return 4;
     }
 }
@@ -75,6 +77,7 @@ hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float*
         TN_LF(DSR_Z_F32)
         TN_LF(DSR_Z_BF16)
         TN_LF(DSR_TOPK)
+        TN_LF(DSR_TPOLY)
     default: return hipErrorInvalidValue;
     }
 #undef TN_LF
@@ -264,7 +267,8 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
     const int lds_cap = 40 * 1024;
     g.mfma = 0;
     g.mode = GEMM_TILED;
-    const bool topk = dsr == DSR_TOPK;  // 32-byte entries: LDS-staged tiles, one output per thread
+    // 32- and 40-byte entries: LDS-staged tiles, one output per thread
+    const bool topk = dsr == DSR_TOPK || dsr == DSR_TPOLY;
     if (!topk && li == 0 && lj == 0 && lk >= 12) {  // one output per batch, long K
         g.mode = GEMM_DOT;
         g.rm = g.rn = 1;
@@ -379,7 +383,8 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 }
 
 bool gemm_shape_valid(int dsr, const GemmShape& g) {
-    if (dsr == DSR_TOPK && (g.mode != GEMM_TILED || g.rm != 1 || g.rn != 1 || g.mfma)) return false;
+    if ((dsr == DSR_TOPK || dsr == DSR_TPOLY) && (g.mode != GEMM_TILED || g.rm != 1 || g.rn != 1 || g.mfma))
+        return false;
     if (g.mode == GEMM_DOT)
         return g.li == 0 && g.lj == 0 && g.ti == 0 && g.tj == 0 && g.tb == 0 && !g.mfma && g.lsplit >= 0 &&
                g.lsplit <= 10 && g.lsplit <= g.lk;
@@ -429,16 +434,17 @@ static hipError_t gemm_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t
 
 template <int D>
 static hipError_t gemm_dispatch(const GemmArgs& a, int rm, int rn, size_t lds, u64 blocks, hipStream_t s) {
-    if constexpr (D == DSR_TOPK) {  // 32-byte entries: one output per thread
+    if constexpr (D == DSR_TOPK || D == DSR_TPOLY) {  // wide entries: one output per thread
         if (rm == 1 && rn == 1) return gemm_go<D, 1, 1>(a, lds, blocks, s);
         return hipErrorInvalidValue;
+    } else {
+        if (rm == 1 && rn == 1) return gemm_go<D, 1, 1>(a, lds, blocks, s);
+        if (rm == 1 && rn == 2) return gemm_go<D, 1, 2>(a, lds, blocks, s);
+        if (rm == 2 && rn == 1) return gemm_go<D, 2, 1>(a, lds, blocks, s);
+        if (rm == 2 && rn == 2) return gemm_go<D, 2, 2>(a, lds, blocks, s);
+        if (rm == 4 && rn == 4) return gemm_go<D, 4, 4>(a, lds, blocks, s);
+        return hipErrorInvalidValue;
     }
-    if (rm == 1 && rn == 1) return gemm_go<D, 1, 1>(a, lds, blocks, s);
-    if (rm == 1 && rn == 2) return gemm_go<D, 1, 2>(a, lds, blocks, s);
-    if (rm == 2 && rn == 1) return gemm_go<D, 2, 1>(a, lds, blocks, s);
-    if (rm == 2 && rn == 2) return gemm_go<D, 2, 2>(a, lds, blocks, s);
-    if (rm == 4 && rn == 4) return gemm_go<D, 4, 4>(a, lds, blocks, s);
-    return hipErrorInvalidValue;
 }
 
 GemmArgs make_gemm_args(Planes Ap, Planes Bp, Planes Cp, Planes part, const GemmShape& g, const AlgebraParams& ap,
@@ -481,7 +487,8 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         case DSR_MODP: return gemm_mode_go<DSR_MODP>(a, g.mode, lds, blocks, s);
         case DSR_Z_F32: return gemm_mode_go<DSR_Z_F32>(a, g.mode, lds, blocks, s);
         case DSR_Z_BF16: return gemm_mode_go<DSR_Z_BF16>(a, g.mode, lds, blocks, s);
-        case DSR_TOPK: return hipErrorInvalidValue;
+        case DSR_TOPK:
+        case DSR_TPOLY: return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
         }
     }
@@ -508,6 +515,7 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         TN_GM(DSR_Z_F32)
         TN_GM(DSR_Z_BF16)
         TN_GM(DSR_TOPK)
+        TN_GM(DSR_TPOLY)
     default: return hipErrorInvalidValue;
     }
 #undef TN_GM
@@ -701,6 +709,7 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, i64 nout, int lsp
         TN_SR(DSR_Z_F32)
         TN_SR(DSR_Z_BF16)
         TN_SR(DSR_TOPK)
+        TN_SR(DSR_TPOLY)
     default: return hipErrorInvalidValue;
     }
 #undef TN_SR
@@ -737,6 +746,7 @@ hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, 
         TN_AC(DSR_Z_F32)
         TN_AC(DSR_Z_BF16)
         TN_AC(DSR_TOPK)
+        TN_AC(DSR_TPOLY)
     default: return hipErrorInvalidValue;
     }
 #undef TN_AC
@@ -761,6 +771,7 @@ hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream
         TN_SO(DSR_Z_F32)
         TN_SO(DSR_Z_BF16)
         TN_SO(DSR_TOPK)
+        TN_SO(DSR_TPOLY)
     default: return hipErrorInvalidValue;
     }
 #undef TN_SO

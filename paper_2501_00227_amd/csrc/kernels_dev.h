@@ -78,6 +78,75 @@ struct Alg<DSR_CTROP> {  // (size, count): larger size wins, equal sizes add cou
     __device__ static V prescale(V v, float) { return v; }
 };
 
+// Truncated polynomial (CountingMax(k), k <= 4, of the Sec. 5 table): the
+// four highest-order terms c[0] x^m + c[1] x^(m-1) + c[2] x^(m-2) +
+// c[3] x^(m-3) of a polynomial in x whose exponents are integer set weights
+// (or -H), counts modulo 2^64.  (+) aligns the two by their top exponent and
+// keeps the higher four orders; (x) adds top exponents and multiplies the
+// coefficient lists, truncated.  Zero: m = INT_MIN, no counts (as the
+// counting tropical algebra, exponents at or below -2^30 mean no term).
+struct TP4 {
+    int m;
+    u64 c[4];
+};
+
+template <>
+struct Alg<DSR_TPOLY> {
+    using V = TP4;
+    __device__ static V zero(const AlgebraParams&) { return TP4{INT_MIN, {0ull, 0ull, 0ull, 0ull}}; }
+    __device__ static V one(const AlgebraParams&) { return TP4{0, {1ull, 0ull, 0ull, 0ull}}; }
+    __device__ static V add(const V& a, const V& b, const AlgebraParams&) {
+        const bool sw = b.m > a.m;
+        const V& hi = sw ? b : a;
+        const V& lo = sw ? a : b;
+        // orders below the top: lo's term c[t] lands at hi's c[t + s]
+        const long long s = (long long)hi.m - (long long)lo.m;
+        V r;
+        r.m = hi.m;
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            u64 x = 0ull;
+#pragma unroll
+            for (int t = 0; t <= d; t++) x = s == d - t ? lo.c[t] : x;
+            r.c[d] = hi.c[d] + x;
+        }
+        return r;
+    }
+    __device__ static V mul(const V& a, const V& b, const AlgebraParams&) {
+        V r;
+        r.m = __builtin_elementwise_add_sat(a.m, b.m);
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            u64 x = 0ull;
+#pragma unroll
+            for (int t = 0; t <= d; t++) x += a.c[t] * b.c[d - t];
+            r.c[d] = x;
+        }
+        return r;
+    }
+    __device__ static V weight(float w, const AlgebraParams&) { return TP4{(int)w, {1ull, 0ull, 0ull, 0ull}}; }
+    __device__ static V load(const Planes& p, i64 i) {
+        const uint4* s = (const uint4*)((const unsigned char*)p.p1 + 32 * i);
+        const uint4 x = s[0], y = s[1];
+        V r;
+        r.m = ((const int*)p.p0)[i];
+        r.c[0] = (u64)x.x | ((u64)x.y << 32);
+        r.c[1] = (u64)x.z | ((u64)x.w << 32);
+        r.c[2] = (u64)y.x | ((u64)y.y << 32);
+        r.c[3] = (u64)y.z | ((u64)y.w << 32);
+        return r;
+    }
+    __device__ static void store(const Planes& p, i64 i, const V& v) {
+        ((int*)p.p0)[i] = v.m;
+        uint4* d = (uint4*)((unsigned char*)p.p1 + 32 * i);
+        d[0] = make_uint4((unsigned int)v.c[0], (unsigned int)(v.c[0] >> 32), (unsigned int)v.c[1],
+                          (unsigned int)(v.c[1] >> 32));
+        d[1] = make_uint4((unsigned int)v.c[2], (unsigned int)(v.c[2] >> 32), (unsigned int)v.c[3],
+                          (unsigned int)(v.c[3] >> 32));
+    }
+    __device__ static V prescale(const V& v, float) { return v; }
+};
+
 template <>
 struct Alg<DSR_MODP> {  // counting modulo p < 2^30, Montgomery form with R = 2^32
     using V = unsigned int;
@@ -260,7 +329,10 @@ constexpr bool is_z() {
 // bytes per entry of plane 0 / plane 1 of an algebra (0: no such plane)
 template <int D>
 __host__ __device__ constexpr int plane_bytes_dev(int plane) {
-    return D == DSR_CTROP ? (plane == 0 ? 4 : 8) : D == DSR_TOPK ? (plane == 0 ? 32 : 0) : (plane == 0 ? 4 : 0);
+    return D == DSR_CTROP   ? (plane == 0 ? 4 : 8)
+           : D == DSR_TOPK  ? (plane == 0 ? 32 : 0)
+           : D == DSR_TPOLY ? (plane == 0 ? 4 : 32)
+                            : (plane == 0 ? 4 : 0);
 }
 
 // Partition-function bookkeeping is read and written with device-scope
@@ -1264,6 +1336,15 @@ __device__ void accumulate_one(Planes root, int mroot, TensorMeta* meta, void* a
         a = A::add(a, v, ap);
         *n = a.n;
         *c = a.c;
+    } else if constexpr (D == DSR_TPOLY) {  // slot: int32 top exponent, then four counts from byte 8
+        TP4 v = A::load(root, 0);
+        int* m = (int*)acc;
+        u64* c = (u64*)((char*)acc + 8);
+        TP4 a = A::zero(ap);
+        if (!first) a = TP4{*m, {c[0], c[1], c[2], c[3]}};
+        a = A::add(a, v, ap);
+        *m = a.m;
+        for (int d = 0; d < 4; d++) c[d] = a.c[d];
     } else {
         using V = typename A::V;
         V v = A::load(root, 0);
@@ -1282,6 +1363,11 @@ __device__ void set_one(void* acc, const AlgebraParams& ap) {
     } else if constexpr (D == DSR_CTROP) {
         *(int*)acc = 0;
         *(u64*)((char*)acc + 8) = 1ull;
+    } else if constexpr (D == DSR_TPOLY) {
+        *(int*)acc = 0;
+        u64* c = (u64*)((char*)acc + 8);
+        c[0] = 1ull;
+        c[1] = c[2] = c[3] = 0ull;
     } else {
         *(typename A::V*)acc = A::one(ap);
     }

@@ -1,0 +1,125 @@
+"""GPU tests of CountingMax(k) for integer weights (Sec. 5 table; Sec. 5.3
+prints the Petersen value): one contraction over truncated polynomials (the
+four highest-order terms per tensor entry) on the per-node executor.  Checked
+against the paper's Petersen and buckyball values, the oracle's enumeration
+(weighted independent sets, spin glasses, fixed vertices, a sliced plan) and,
+for unit weights at n = 60 and 100, the oracle's independence polynomial."""
+import json
+import os
+import random
+
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2501_00227_amd as tn
+
+pytestmark = pytest.mark.gpu
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+M64 = 2 ** 64
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    tn.lib()
+    c = tn.Context(0)
+    yield c
+    c.synchronize()
+
+
+def _mod(r):
+    return {"top": r["top"], "counts": {s: c % M64 for s, c in r["counts"].items()}}
+
+
+def test_paper_values(ctx):
+    net = tn.Net.from_graph(gg.petersen())
+    want = {int(s): c for s, c in GOLD["petersen"]["counting_max_2"]["value"].items()}
+    assert ctx.solve_counting_max_k(net, tn.Plan.create(net), 2) == {"top": 4, "counts": want}
+    g = gg.fullerene()  # Sec. 6.4: CountingMin of the antiferromagnetic buckyball
+    net = tn.Net.spin_glass(g)
+    plan = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=0)
+    e, deg = GOLD["fullerene"]["counting_min"]["value"]
+    r = ctx.solve_counting_max_k(net, plan, 4)
+    assert r["top"] == -e and r["counts"][-e] == deg
+    # H is a sum of 90 terms +-1, so every value of -H is even
+    assert r["counts"][-e - 1] == r["counts"][-e - 3] == 0
+
+
+@pytest.mark.parametrize("weights", ["unit", "integer"])
+def test_random_graphs_vs_enumeration(ctx, weights):
+    rng = random.Random({"unit": 11, "integer": 12}[weights])
+    for t in range(12):
+        n = rng.randint(1, 18)
+        g = gg.gnp(n, rng.uniform(0.1, 0.6), 1500 + t)
+        if weights == "integer":
+            g = g.with_weights(gg.integer_weights(n, 1500 + t, 1, 5))
+        net = tn.Net.from_graph(g)
+        plan = tn.Plan.create(net, seed=t)
+        for k in (1, 2, 4):
+            assert ctx.solve_counting_max_k(net, plan, k) == _mod(oracle.brute_force_counting_max_k(g, k)), (t, k)
+
+
+def test_spin_glasses_and_fixed_vertices(ctx):
+    rng = random.Random(13)
+    for t in range(8):
+        n = rng.randint(3, 16)
+        g = gg.gnp(n, rng.uniform(0.2, 0.6), 1600 + t)
+        J = [float(rng.randint(-2, 2)) for _ in range(g.ne)]
+        h = [float(rng.randint(-1, 1)) for _ in range(n)]
+        net = tn.Net.spin_glass(g, J, h)
+        plan = tn.Plan.create(net, seed=t)
+        assert ctx.solve_counting_max_k(net, plan, 4) == _mod(oracle.spin_glass_counting_max_k(g, 4, J, h)), t
+        fixed = {v: rng.randint(0, 1) for v in rng.sample(range(n), 2)}
+        got = ctx.solve_counting_max_k(net.condition(fixed), plan, 3)
+        assert got == _mod(oracle.spin_glass_counting_max_k(g, 3, J, h, fixed)), t
+        gw = g.with_weights(gg.integer_weights(n, 1600 + t, 1, 4))
+        wnet = tn.Net.from_graph(gw)
+        wplan = tn.Plan.create(wnet, seed=t)
+        fixed = {v: 0 for v in rng.sample(range(n), 2)}
+        got = ctx.solve_counting_max_k(wnet.condition(fixed), wplan, 4)
+        assert got == _mod(oracle.brute_force_counting_max_k(gw, 4, fixed)), t
+
+
+def test_sliced_plan(ctx):
+    g = gg.random_regular(20, 3, 5).with_weights(gg.integer_weights(20, 5, 1, 6))
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, method="treesa", ntrials=1, niters=3, sc_target=3, nslices=4, seed=5)
+    assert plan.info()["nsliced"] > 0
+    assert ctx.solve_counting_max_k(net, plan, 4) == _mod(oracle.brute_force_counting_max_k(g, 4))
+
+
+@pytest.mark.parametrize("n,seed", [(60, 0), (100, 1)])
+def test_unit_weights_agree_with_the_polynomial(ctx, n, seed):
+    g = gg.random_regular(n, 3, seed)
+    poly = oracle.eliminate_polynomial(g, max_width=20)["poly"]
+    alpha = len(poly) - 1
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=seed)
+    r = ctx.solve_counting_max_k(net, plan, 4)
+    assert r == {"top": alpha, "counts": {alpha - d: poly[alpha - d] % M64 for d in range(4)}}
+    assert ctx.solve_max_k(net, plan, 4)["counting_max_k"] == {alpha - d: poly[alpha - d] for d in range(4)}
+
+
+def test_rejections_and_edge_cases(ctx):
+    net = tn.Net.from_graph(gg.path(5))
+    plan = tn.Plan.create(net)
+    for k in (0, 5):
+        with pytest.raises(tn.TnError) as ei:
+            ctx.solve_counting_max_k(net, plan, k)
+        assert ei.value.code == tn.TN_EINVAL
+    frac = tn.Net.from_graph(gg.path(5).with_weights(gg.dyadic_weights(5, 0)))
+    with pytest.raises(tn.TnError) as ei:
+        ctx.solve_counting_max_k(frac, tn.Plan.create(frac), 2)
+    assert ei.value.code == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as ei:
+        ctx.solve_counting_max_k(net, tn.Plan.create(net, open=[1]), 2)
+    assert ei.value.code == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as ei:
+        ctx.solve_counting_max_k(net, tn.Plan.create(tn.Net.from_graph(gg.path(6))), 2)
+    assert ei.value.code == tn.TN_EINVAL
+    e = tn.Net.from_graph(gg.empty(0))
+    assert ctx.solve_counting_max_k(e, tn.Plan.create(e), 3) == {"top": 0, "counts": {0: 1, -1: 0, -2: 0}}
+    bad = net.condition({1: 1, 2: 1})  # both ends of an edge in the set
+    assert ctx.solve_counting_max_k(bad, plan, 2) == {"top": float("-inf"), "counts": {}}
+    iso = tn.Net.from_graph(gg.empty(7))  # 2^7 sets: C(7, s) at size s
+    assert ctx.solve_counting_max_k(iso, tn.Plan.create(iso), 4) == {"top": 7, "counts": {7: 1, 6: 7, 5: 21, 4: 35}}

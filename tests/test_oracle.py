@@ -600,3 +600,87 @@ def test_topk_antiferromagnetic_ring():
     states with two domain walls at n - 4."""
     for n in (6, 8, 10):
         assert oracle.spin_glass_topk(gg.cycle(n), 3) == [float(n), float(n), float(n - 4)]
+
+
+# --- CountingMax(k) by enumeration: counts at the k highest integer values ---
+
+def test_count_top_petersen_matches_paper():
+    want = {int(s): c for s, c in GOLD["petersen"]["counting_max_2"]["value"].items()}
+    assert oracle.brute_force_counting_max_k(gg.petersen(), 2) == {"top": 4, "counts": want}
+
+
+def test_count_top_unit_weights_is_the_eliminated_polynomial():
+    """Unit weights: the top coefficients of the independence polynomial,
+    which the oracle's elimination over polynomial tables computes
+    independently of the enumeration."""
+    for t in range(20):
+        g = gg.gnp(8 + t % 10, 0.3, 1200 + t)
+        poly = oracle.eliminate_polynomial(g)["poly"]
+        alpha = len(poly) - 1
+        for k in (1, 2, 4, 6):
+            want = {alpha - d: (poly[alpha - d] if alpha - d >= 0 else 0) for d in range(k)}
+            assert oracle.brute_force_counting_max_k(g, k) == {"top": alpha, "counts": want}
+
+
+def test_count_top_weighted_graphs_by_plain_enumeration():
+    """Integer weights on small graphs: every subset listed with itertools,
+    independence checked edge by edge."""
+    import itertools
+    for t in range(12):
+        n = 3 + t % 8
+        g = gg.gnp(n, 0.35, 1300 + t).with_weights(gg.integer_weights(n, 1300 + t, 1, 6))
+        edges = [tuple(e) for e in g.edges.tolist()]
+        vals = [sum(int(g.weights[v]) for v in c) for r in range(n + 1) for c in itertools.combinations(range(n), r)
+                if not any(u in c and v in c for u, v in edges)]
+        top = max(vals)
+        want = {top - d: vals.count(top - d) for d in range(4)}
+        assert oracle.brute_force_counting_max_k(g, 4) == {"top": top, "counts": want}
+
+
+def test_count_top_fixed_vertices_are_deletions():
+    """n_v = 0 counts the sets of G - v; n_v = 1 those of G - N[v], each
+    shifted by w_v."""
+    for t in range(10):
+        n = 6 + t % 8
+        g = gg.gnp(n, 0.3, 1400 + t).with_weights(gg.integer_weights(n, 1400 + t, 1, 5))
+        v = t % n
+        adj = g.adjacency()
+        out = oracle.brute_force_counting_max_k(g, 3, fixed={v: 0})
+        assert out == oracle.brute_force_counting_max_k(gg.induced(g, [u for u in range(n) if u != v]), 3)
+        rest = gg.induced(g, [u for u in range(n) if u != v and u not in adj[v]])
+        sub = oracle.brute_force_counting_max_k(rest, 3)
+        wv = int(g.weights[v])
+        got = oracle.brute_force_counting_max_k(g, 3, fixed={v: 1})
+        assert got == {"top": sub["top"] + wv, "counts": {s + wv: c for s, c in sub["counts"].items()}}
+
+
+def test_count_top_spin_glass_closed_forms():
+    """Fields only: -H = -sum h_v s_v, whose value counts are the
+    coefficients of prod_v (x^h_v + x^-h_v); the ferromagnetic ring (J = -1)
+    has its two ground states at -H = n and nothing until n - 4."""
+    rng = np.random.default_rng(5)
+    for t in range(6):
+        n = 5 + t
+        h = [float(x) for x in rng.integers(-3, 4, n)]
+        coeff = {0: 1}
+        for hv in h:
+            nxt = {}
+            for e, c in coeff.items():
+                for s in (hv, -hv):
+                    nxt[e + int(s)] = nxt.get(e + int(s), 0) + c
+            coeff = nxt
+        top = max(coeff)
+        want = {top - d: coeff.get(top - d, 0) for d in range(4)}
+        assert oracle.spin_glass_counting_max_k(gg.empty(n), 4, h=h) == {"top": top, "counts": want}
+    for n in (6, 8):
+        got = oracle.spin_glass_counting_max_k(gg.cycle(n), 4, J=[-1.0] * n)
+        assert got == {"top": n, "counts": {n: 2, n - 1: 0, n - 2: 0, n - 3: 0}}
+        got = oracle.spin_glass_counting_max_k(gg.cycle(n), 1, J=[-1.0] * n, fixed={0: 1, 3: 0})
+        assert got["top"] == n - 4  # two domain walls forced
+
+
+def test_count_top_rejects_fractional_weights_and_reports_infeasible():
+    g = gg.path(3).with_weights(np.array([1.0, 0.5, 2.0]))
+    with pytest.raises(oracle.OracleError):
+        oracle.brute_force_counting_max_k(g, 2)
+    assert oracle.brute_force_counting_max_k(gg.path(2), 2, fixed={0: 1, 1: 1}) == {"top": float("-inf"), "counts": {}}
