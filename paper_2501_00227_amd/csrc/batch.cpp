@@ -341,6 +341,8 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         DevProgram* dp = nullptr;
         if (it.plan->nleaf() > 0) {
             s = get_program(ctx, *it.plan, dp);
+            for (const PassSpec& ps : st.passes)
+                if (s == TN_OK && ps.dsr == DSR_TOPK) s = ensure_wide_perms(ctx, *it.plan, *dp);
             if (s != TN_OK) {
                 st.status = s;
                 continue;

@@ -122,17 +122,13 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
         d.var1 = lp.var[1];
         d.off = lp.off;
     }
-    std::vector<PermParams> perms, perms_wide;
+    std::vector<PermParams> perms;
     dp.perm_slot_a.assign(p.prog.size(), -1);
     dp.perm_slot_b.assign(p.prog.size(), -1);
     auto add_perm = [&](const std::vector<int>& src) {
         PermParams pp;
         build_perm_params((int)src.size(), src.data(), pp);
         perms.push_back(pp);
-        std::vector<int> wide{0, 1, 2};  // 32-byte entries: eight 4-byte words each
-        for (int x : src) wide.push_back(x + 3);
-        build_perm_params((int)wide.size(), wide.data(), pp);
-        perms_wide.push_back(pp);
         return (int)perms.size() - 1;
     };
     for (size_t t = 0; t < p.prog.size(); t++) {
@@ -144,8 +140,7 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     for (size_t k = 0; k < p.sliced.size(); k++) spos[p.sliced[k]] = (int)k;
     size_t o_leaf = 0;
     size_t o_perm = align256(o_leaf + sizeof(LeafDev) * leaves.size());
-    size_t o_permw = align256(o_perm + sizeof(PermParams) * perms.size());
-    size_t o_spos = align256(o_permw + sizeof(PermParams) * perms_wide.size());
+    size_t o_spos = align256(o_perm + sizeof(PermParams) * perms.size());
     size_t total = align256(o_spos + sizeof(int) * spos.size());
     dp.bytes = total;
     dp.buf = dev_alloc(ctx, total);
@@ -156,7 +151,6 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     unsigned char* h = (unsigned char*)ctx->pinned;
     std::memcpy(h + o_leaf, leaves.data(), sizeof(LeafDev) * leaves.size());
     if (!perms.empty()) std::memcpy(h + o_perm, perms.data(), sizeof(PermParams) * perms.size());
-    if (!perms_wide.empty()) std::memcpy(h + o_permw, perms_wide.data(), sizeof(PermParams) * perms_wide.size());
     std::memcpy(h + o_spos, spos.data(), sizeof(int) * spos.size());
     if (hipMemcpyAsync(dp.buf, h, total, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
@@ -164,10 +158,43 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     unsigned char* d = (unsigned char*)dp.buf;
     dp.leaves = (LeafDev*)(d + o_leaf);
     dp.perms = (PermParams*)(d + o_perm);
-    dp.perms_wide = (PermParams*)(d + o_permw);
+    dp.nperms = (int)perms.size();
     dp.slice_pos = (int*)(d + o_spos);
     auto ins = ctx->progs.emplace(p.uid, std::move(dp));
     out = &ins.first->second;
+    return TN_OK;
+}
+
+tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp) {
+    if (dp.perms_wide || dp.nperms == 0) return TN_OK;
+    std::vector<PermParams> wide(dp.nperms);
+    auto build = [&](const std::vector<int>& src, int slot) {
+        std::vector<int> w{0, 1, 2};  // 32-byte entries: eight 4-byte words each
+        for (int x : src) w.push_back(x + 3);
+        build_perm_params((int)w.size(), w.data(), wide[slot]);
+    };
+    for (size_t t = 0; t < p.prog.size(); t++) {
+        if (dp.perm_slot_a[t] >= 0) build(p.prog[t].perm_a_src, dp.perm_slot_a[t]);
+        if (dp.perm_slot_b[t] >= 0) build(p.prog[t].perm_b_src, dp.perm_slot_b[t]);
+    }
+    const size_t bytes = sizeof(PermParams) * wide.size();
+    void* buf = dev_alloc(ctx, bytes);
+    if (!buf) return fail(TN_ENOMEM, "device allocation of the widened permute tables failed");
+    tn_status st = ensure_pinned(ctx, bytes);
+    if (st != TN_OK) {
+        dev_free(ctx, buf, bytes);
+        return st;
+    }
+    (void)hipStreamSynchronize(ctx->stream);  // the staging buffer may still be in use
+    std::memcpy(ctx->pinned, wide.data(), bytes);
+    if (hipMemcpyAsync(buf, ctx->pinned, bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        dev_free(ctx, buf, bytes);
+        return fail(TN_EDEVICE, "upload of the widened permute tables failed");
+    }
+    dp.wide_buf = buf;
+    dp.wide_bytes = bytes;
+    dp.perms_wide = (PermParams*)buf;
     return TN_OK;
 }
 
@@ -439,6 +466,11 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     if (nleaf > 0) {
         st = get_program(ctx, plan, dp);
         if (st != TN_OK) return st;
+        for (auto& ps : passes)
+            if (plane_bytes(ps.dsr, 0) == 32 || plane_bytes(ps.dsr, 1) == 32) {
+                st = ensure_wide_perms(ctx, plan, *dp);
+                if (st != TN_OK) return st;
+            }
     }
     // one allocation: arena planes, split partials, meta, weights, accumulator
     size_t need = 0;

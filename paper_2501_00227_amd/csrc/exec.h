@@ -35,9 +35,13 @@ struct DevProgram {
     size_t bytes = 0;
     LeafDev* leaves = nullptr;
     PermParams* perms = nullptr;  // indexed by permute slot
+    int nperms = 0;
     // the same permutes for 32-byte entries, as 4-byte permutes of rank + 3
-    // whose three lowest bits stay in place
+    // whose three lowest bits stay in place: built and uploaded (own buffer)
+    // the first time an algebra with such entries runs the plan
     PermParams* perms_wide = nullptr;
+    void* wide_buf = nullptr;
+    size_t wide_bytes = 0;
     int* slice_pos = nullptr;     // nv entries: position in the sliced list or -1
     std::vector<int> perm_slot_a, perm_slot_b;  // per inner node, -1 if none
     std::map<int, std::vector<NodeLaunch>> launches;  // per device algebra
@@ -97,6 +101,8 @@ void* dev_alloc(tn_ctx* ctx, size_t bytes);
 void dev_free(tn_ctx* ctx, void* p, size_t bytes);
 tn_status ensure_pinned(tn_ctx* ctx, size_t bytes);
 tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out);
+// The widened permute tables of a program (no-op once built).
+tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp);
 // Tile shapes of every node for one device algebra (cached in dp).
 const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr);
 
