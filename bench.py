@@ -350,8 +350,8 @@ def job_stream(ctx, njobs, seed=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=2000, help="jobs in the batched / served stream")
     ap.add_argument("--no-cpu", action="store_true")

@@ -37,7 +37,7 @@ struct BNode {  // one inner node; jobs of the same plan and algebra share it (o
     GemmShape g;
     int64_t a_off, b_off, c_off;  // effective operand offsets (after permutes)
     int ma, mb, mc;
-    const PermParams* pp[2];
+    const PermTables* pp[2];
     int64_t psrc[2], pdst[2];
     int prank[2], ptile_bits[2];
     int64_t part_off;     // this node's split-K partials inside the job's partial buffer

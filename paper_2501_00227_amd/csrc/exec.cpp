@@ -138,26 +138,36 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     }
     std::vector<int> spos(std::max(p.nv, 1), -1);
     for (size_t k = 0; k < p.sliced.size(); k++) spos[p.sliced[k]] = (int)k;
+    // one buffer: leaves, compact permutes, slice positions (uploaded), then
+    // the permute tables, expanded on the device from the compact permutes
     size_t o_leaf = 0;
     size_t o_perm = align256(o_leaf + sizeof(LeafDev) * leaves.size());
     size_t o_spos = align256(o_perm + sizeof(PermParams) * perms.size());
-    size_t total = align256(o_spos + sizeof(int) * spos.size());
+    size_t o_tab = align256(o_spos + sizeof(int) * spos.size());
+    size_t total = align256(o_tab + sizeof(PermTables) * perms.size());
     dp.bytes = total;
     dp.buf = dev_alloc(ctx, total);
     if (!dp.buf) return fail(TN_ENOMEM, "device allocation of the plan program failed");
-    tn_status st = ensure_pinned(ctx, total);
-    if (st != TN_OK) return st;
+    tn_status st = ensure_pinned(ctx, o_tab);
+    if (st != TN_OK) {
+        dev_free(ctx, dp.buf, dp.bytes);
+        return st;
+    }
     (void)hipStreamSynchronize(ctx->stream);  // the staging buffer may still be in use
     unsigned char* h = (unsigned char*)ctx->pinned;
     std::memcpy(h + o_leaf, leaves.data(), sizeof(LeafDev) * leaves.size());
     if (!perms.empty()) std::memcpy(h + o_perm, perms.data(), sizeof(PermParams) * perms.size());
     std::memcpy(h + o_spos, spos.data(), sizeof(int) * spos.size());
-    if (hipMemcpyAsync(dp.buf, h, total, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-        return fail(TN_EDEVICE, "upload of the plan program failed");
     unsigned char* d = (unsigned char*)dp.buf;
+    if (hipMemcpyAsync(dp.buf, h, o_tab, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        launch_expand_perms((const PermParams*)(d + o_perm), (PermTables*)(d + o_tab), (int)perms.size(),
+                            ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        dev_free(ctx, dp.buf, dp.bytes);
+        return fail(TN_EDEVICE, "upload of the plan program failed");
+    }
     dp.leaves = (LeafDev*)(d + o_leaf);
-    dp.perms = (PermParams*)(d + o_perm);
+    dp.perms = (PermTables*)(d + o_tab);
     dp.nperms = (int)perms.size();
     dp.slice_pos = (int*)(d + o_spos);
     auto ins = ctx->progs.emplace(p.uid, std::move(dp));
@@ -177,24 +187,30 @@ tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp) {
         if (dp.perm_slot_a[t] >= 0) build(p.prog[t].perm_a_src, dp.perm_slot_a[t]);
         if (dp.perm_slot_b[t] >= 0) build(p.prog[t].perm_b_src, dp.perm_slot_b[t]);
     }
-    const size_t bytes = sizeof(PermParams) * wide.size();
+    // compact permutes (uploaded), then their expanded tables
+    const size_t o_tab = align256(sizeof(PermParams) * wide.size());
+    const size_t bytes = o_tab + sizeof(PermTables) * wide.size();
     void* buf = dev_alloc(ctx, bytes);
     if (!buf) return fail(TN_ENOMEM, "device allocation of the widened permute tables failed");
-    tn_status st = ensure_pinned(ctx, bytes);
+    tn_status st = ensure_pinned(ctx, o_tab);
     if (st != TN_OK) {
         dev_free(ctx, buf, bytes);
         return st;
     }
     (void)hipStreamSynchronize(ctx->stream);  // the staging buffer may still be in use
-    std::memcpy(ctx->pinned, wide.data(), bytes);
-    if (hipMemcpyAsync(buf, ctx->pinned, bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+    std::memcpy(ctx->pinned, wide.data(), sizeof(PermParams) * wide.size());
+    unsigned char* d = (unsigned char*)buf;
+    if (hipMemcpyAsync(buf, ctx->pinned, sizeof(PermParams) * wide.size(), hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        launch_expand_perms((const PermParams*)d, (PermTables*)(d + o_tab), (int)wide.size(), ctx->stream) !=
+            hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         dev_free(ctx, buf, bytes);
         return fail(TN_EDEVICE, "upload of the widened permute tables failed");
     }
     dp.wide_buf = buf;
     dp.wide_bytes = bytes;
-    dp.perms_wide = (PermParams*)buf;
+    dp.perms_wide = (PermTables*)(d + o_tab);
     return TN_OK;
 }
 

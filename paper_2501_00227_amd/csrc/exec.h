@@ -34,12 +34,12 @@ struct DevProgram {
     void* buf = nullptr;
     size_t bytes = 0;
     LeafDev* leaves = nullptr;
-    PermParams* perms = nullptr;  // indexed by permute slot
+    PermTables* perms = nullptr;  // indexed by permute slot
     int nperms = 0;
     // the same permutes for 32-byte entries, as 4-byte permutes of rank + 3
     // whose three lowest bits stay in place: built and uploaded (own buffer)
     // the first time an algebra with such entries runs the plan
-    PermParams* perms_wide = nullptr;
+    PermTables* perms_wide = nullptr;
     void* wide_buf = nullptr;
     size_t wide_bytes = 0;
     int* slice_pos = nullptr;     // nv entries: position in the sliced list or -1

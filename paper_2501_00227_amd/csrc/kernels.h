@@ -56,8 +56,21 @@ struct LeafDev {
     long long off;     // arena offset (entries)
 };
 
-// Bit-permutation tables of one permute (see kernels.hip).
+// One permute of the bits of a linear offset, compact (see kernels.hip): the
+// tile bits (input bit u[t] and output bit vo[t] of tile bit t; ef[t]: the
+// read-order bit that feeds output tile bit t) and the bits that enumerate
+// tiles.  Built on the host and uploaded; a kernel expands it into
+// PermTables once per program.
 struct PermParams {
+    signed char u[12], vo[12], ef[12];
+    signed char tin[48], tout[48];
+    int rank, tile_bits, ntile_bits, pad;
+};
+
+// The same permute as the permute kernels read it: 64-entry lookup tables of
+// six tile bits each (input and output offsets, read-order index) and the
+// tile-enumeration bits, device-resident.
+struct PermTables {
     long long in_lo[64], in_hi[64];
     long long out_lo[64], out_hi[64];
     int e_lo[64], e_hi[64];
@@ -91,7 +104,9 @@ hipError_t launch_meta_init(TensorMeta* meta, int n, hipStream_t s);
 hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float* w, const int* slice_pos,
                          unsigned long long slice_id, Planes arena, const AlgebraParams& ap,
                          TensorMeta* meta, hipStream_t s);
-hipError_t launch_permute(int elem_bytes, const void* in, void* out, const PermParams* pp_dev, int rank,
+// tables[i] = the expansion of perms[i], i < n (device pointers)
+hipError_t launch_expand_perms(const PermParams* perms, PermTables* tables, int n, hipStream_t s);
+hipError_t launch_permute(int elem_bytes, const void* in, void* out, const PermTables* pp_dev, int rank,
                           int tile_bits, hipStream_t s);
 hipError_t launch_gemm(int dsr, Planes A, Planes B, Planes C, Planes part, const GemmShape& g,
                        const AlgebraParams& ap, TensorMeta* meta, int ma, int mb, int mc, hipStream_t s);

@@ -96,10 +96,12 @@ hipError_t launch_leaves(int dsr, const LeafDev* leaves, int nleaf, const float*
 // The remaining rank-u bits enumerate tiles (tin/tout: their positions).
 void build_perm_params(int rank, const int* src, PermParams& pp) {
     std::memset(&pp, 0, sizeof pp);
-    int r = rank;
-    int u = perm_tile_bits(r);
+    const int r = rank;
+    const int u = perm_tile_bits(r);
     int inv[64];
     for (int q = 0; q < r; q++) inv[src[q]] = q;
+    // tile bits: input bits 0, 1, ... interleaved with the input bits that
+    // feed output bits 0, 1, ..., until there are u of them
     bool inU[64] = {false};
     int nU = 0;
     for (int k = 0; k < r && nU < u; k++) {
@@ -112,36 +114,17 @@ void build_perm_params(int rank, const int* src, PermParams& pp) {
             nU++;
         }
     }
-    int U[64], nu = 0, Vo[64], nvo = 0;
+    int posU[64], nu = 0, nvo = 0;
     for (int b = 0; b < r; b++)
-        if (inU[b]) U[nu++] = b;  // e bit t <-> input bit U[t]
-    for (int q = 0; q < r; q++)
-        if (inU[src[q]]) Vo[nvo++] = q;  // f bit t <-> output bit Vo[t]
-    int posU[64];
-    for (int t = 0; t < nu; t++) posU[U[t]] = t;
-    for (int x = 0; x < 64; x++) {
-        long long il = 0, ih = 0, ol = 0, oh = 0;
-        int el = 0, eh = 0;
-        for (int t = 0; t < 6; t++) {
-            if (!((x >> t) & 1)) continue;
-            if (t < nu) il |= 1ll << U[t];
-            if (t + 6 < nu) ih |= 1ll << U[t + 6];
-            if (t < nvo) {
-                ol |= 1ll << Vo[t];
-                el |= 1 << posU[src[Vo[t]]];
-            }
-            if (t + 6 < nvo) {
-                oh |= 1ll << Vo[t + 6];
-                eh |= 1 << posU[src[Vo[t + 6]]];
-            }
+        if (inU[b]) {
+            posU[b] = nu;
+            pp.u[nu++] = (signed char)b;  // read-order bit t <-> input bit b
         }
-        pp.in_lo[x] = il;
-        pp.in_hi[x] = ih;
-        pp.out_lo[x] = ol;
-        pp.out_hi[x] = oh;
-        pp.e_lo[x] = el;
-        pp.e_hi[x] = eh;
-    }
+    for (int q = 0; q < r; q++)
+        if (inU[src[q]]) {
+            pp.vo[nvo] = (signed char)q;              // write-order bit t <-> output bit q
+            pp.ef[nvo++] = (signed char)posU[src[q]];  // fed by read-order bit posU[src[q]]
+        }
     int nt = 0;
     for (int b = 0; b < r; b++)
         if (!inU[b]) {
@@ -156,9 +139,43 @@ void build_perm_params(int rank, const int* src, PermParams& pp) {
 
 static_assert(kPermTile == 1 << kPermTileBits, "permute tile size");
 
+// one workgroup of 64 threads per permute, one table entry per thread
+__global__ __launch_bounds__(64) void expand_perms_kernel(const PermParams* __restrict__ perms,
+                                                          PermTables* __restrict__ tables, int n) {
+    const int i = blockIdx.x, x = threadIdx.x;
+    if (i >= n || x >= 64) return;
+    const PermParams& p = perms[i];
+    PermTables& t = tables[i];
+    long long il, ih, ol, oh;
+    int el, eh;
+    perm_table_entry(p, x, il, ih, ol, oh, el, eh);
+    t.in_lo[x] = il;
+    t.in_hi[x] = ih;
+    t.out_lo[x] = ol;
+    t.out_hi[x] = oh;
+    t.e_lo[x] = el;
+    t.e_hi[x] = eh;
+    if (x < 48) {
+        t.tin[x] = p.tin[x];
+        t.tout[x] = p.tout[x];
+    }
+    if (x == 0) {
+        t.rank = p.rank;
+        t.tile_bits = p.tile_bits;
+        t.ntile_bits = p.ntile_bits;
+        t.pad = 0;
+    }
+}
+
+hipError_t launch_expand_perms(const PermParams* perms, PermTables* tables, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    expand_perms_kernel<<<n, 64, 0, s>>>(perms, tables, n);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void permute_kernel(const T* __restrict__ in, T* __restrict__ out,
-                                                      const PermParams* __restrict__ pp, i64 ntiles) {
+                                                      const PermTables* __restrict__ pp, i64 ntiles) {
     __shared__ PermLds tabs;
     __shared__ __align__(16) T tile[kPermTile];
     perm_load_tables(&tabs, pp);
@@ -167,7 +184,7 @@ __global__ __launch_bounds__(256) void permute_kernel(const T* __restrict__ in, 
     for (i64 t = blockIdx.x; t < ntiles; t += gridDim.x) permute_tile<T>(in, out, &tabs, tile, u, nt, t);
 }
 
-hipError_t launch_permute(int elem_bytes, const void* in, void* out, const PermParams* pp_dev, int rank,
+hipError_t launch_permute(int elem_bytes, const void* in, void* out, const PermTables* pp_dev, int rank,
                           int tile_bits, hipStream_t s) {
     i64 ntiles = (i64)1 << (rank - tile_bits);
     int grid = (int)(ntiles < 4096 ? ntiles : 4096);

@@ -491,7 +491,31 @@ struct PermLds {
 };
 constexpr int kPermTile = 4096;  // entries; must equal 1 << the tile bits the host plans with
 
-__device__ inline void perm_load_tables(PermLds* s, const PermParams* pp) {
+// Entry x (six bits) of the lookup tables: the input offset of read-order
+// bits t (in_lo) and t + 6 (in_hi) set in x, likewise the output offset of
+// write-order bits (out_lo, out_hi) and the read-order index feeding them
+// (e_lo, e_hi).  Tile bits beyond tile_bits contribute nothing.
+__host__ __device__ inline void perm_table_entry(const PermParams& pp, int x, long long& il, long long& ih,
+                                                 long long& ol, long long& oh, int& el, int& eh) {
+    const int nu = pp.tile_bits;
+    il = ih = ol = oh = 0;
+    el = eh = 0;
+    for (int t = 0; t < 6; t++) {
+        if (!((x >> t) & 1)) continue;
+        if (t < nu) {
+            il |= 1ll << pp.u[t];
+            ol |= 1ll << pp.vo[t];
+            el |= 1 << pp.ef[t];
+        }
+        if (t + 6 < nu) {
+            ih |= 1ll << pp.u[t + 6];
+            oh |= 1ll << pp.vo[t + 6];
+            eh |= 1 << pp.ef[t + 6];
+        }
+    }
+}
+
+__device__ inline void perm_load_tables(PermLds* s, const PermTables* pp) {
     const int tid = threadIdx.x;
     if (tid < 64) {
         s->in_lo[tid] = pp->in_lo[tid];
