@@ -70,10 +70,9 @@ void tn_ctx_destroy(tn_ctx* c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
         batch_cache_drop(c);
-        for (auto& kv : c->progs) {
-            dev_free(c, kv.second.buf, kv.second.bytes);
+        for (auto& kv : c->progs)
             if (kv.second.wide_buf) dev_free(c, kv.second.wide_buf, kv.second.wide_bytes);
-        }
+        for (auto& b : c->prog_bufs) dev_free(c, b.first, b.second);
         (void)hipStreamSynchronize(c->stream);
         for (auto& pr : c->pending) {
             (void)hipEventDestroy(pr.start);

@@ -308,6 +308,15 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         }
     }
     const size_t weights_end = data;
+    // programs of every plan new to the device, with one upload (a failure
+    // here is reported per item by get_program below)
+    {
+        std::vector<const Plan*> plans;
+        plans.reserve(items.size());
+        for (const BatchItem& it : items)
+            if (it.plan && it.plan->fingerprint == it.net->fingerprint) plans.push_back(it.plan);
+        (void)get_programs(ctx, plans);
+    }
     // ---- per item: passes and device programs; lay out device memory
     for (size_t i = 0; i < items.size(); i++) {
         BatchItem& it = items[i];

@@ -100,18 +100,25 @@ ProfScope::~ProfScope() {
 }
 
 // -------------------------------------------------------- device program --
-tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
-    auto it = ctx->progs.find(p.uid);
-    if (it != ctx->progs.end()) {
-        out = &it->second;
-        return TN_OK;
-    }
+namespace {
+
+// Host side of one program: leaf records, compact permutes, slice positions.
+struct ProgramHost {
+    const Plan* plan;
     DevProgram dp;
-    int nleaf = p.nleaf();
-    std::vector<LeafDev> leaves(nleaf);
+    std::vector<LeafDev> leaves;
+    std::vector<PermParams> perms;
+    std::vector<int> spos;
+    size_t o_leaf = 0, o_spos = 0, perm_first = 0;
+};
+
+void build_program_host(const Plan& p, ProgramHost& h) {
+    h.plan = &p;
+    const int nleaf = p.nleaf();
+    h.leaves.resize(nleaf);
     for (int l = 0; l < nleaf; l++) {
         const LeafProg& lp = p.leaf_prog[l];
-        LeafDev& d = leaves[l];
+        LeafDev& d = h.leaves[l];
         d.u = lp.u;
         d.v = lp.has_edge ? lp.v : -1;
         d.flags = (lp.has_edge ? 1 : 0) | (lp.wu ? 2 : 0) | (lp.wv ? 4 : 0) | (p.kind == 1 ? 8 : 0);
@@ -122,56 +129,96 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
         d.var1 = lp.var[1];
         d.off = lp.off;
     }
-    std::vector<PermParams> perms;
-    dp.perm_slot_a.assign(p.prog.size(), -1);
-    dp.perm_slot_b.assign(p.prog.size(), -1);
+    h.dp.perm_slot_a.assign(p.prog.size(), -1);
+    h.dp.perm_slot_b.assign(p.prog.size(), -1);
     auto add_perm = [&](const std::vector<int>& src) {
         PermParams pp;
         build_perm_params((int)src.size(), src.data(), pp);
-        perms.push_back(pp);
-        return (int)perms.size() - 1;
+        h.perms.push_back(pp);
+        return (int)h.perms.size() - 1;
     };
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
-        if (np.perm_a) dp.perm_slot_a[t] = add_perm(np.perm_a_src);
-        if (np.perm_b) dp.perm_slot_b[t] = add_perm(np.perm_b_src);
+        if (np.perm_a) h.dp.perm_slot_a[t] = add_perm(np.perm_a_src);
+        if (np.perm_b) h.dp.perm_slot_b[t] = add_perm(np.perm_b_src);
     }
-    std::vector<int> spos(std::max(p.nv, 1), -1);
-    for (size_t k = 0; k < p.sliced.size(); k++) spos[p.sliced[k]] = (int)k;
-    // one buffer: leaves, compact permutes, slice positions (uploaded), then
-    // the permute tables, expanded on the device from the compact permutes
-    size_t o_leaf = 0;
-    size_t o_perm = align256(o_leaf + sizeof(LeafDev) * leaves.size());
-    size_t o_spos = align256(o_perm + sizeof(PermParams) * perms.size());
-    size_t o_tab = align256(o_spos + sizeof(int) * spos.size());
-    size_t total = align256(o_tab + sizeof(PermTables) * perms.size());
-    dp.bytes = total;
-    dp.buf = dev_alloc(ctx, total);
-    if (!dp.buf) return fail(TN_ENOMEM, "device allocation of the plan program failed");
+    h.spos.assign(std::max(p.nv, 1), -1);
+    for (size_t k = 0; k < p.sliced.size(); k++) h.spos[p.sliced[k]] = (int)k;
+}
+
+}  // namespace
+
+// Programs for every plan not yet on the device, in one buffer: each plan's
+// leaves and slice positions, then all compact permutes (uploaded in one
+// copy), then all permute tables, expanded on the device by one launch.
+tn_status get_programs(tn_ctx* ctx, const std::vector<const Plan*>& plans) {
+    std::vector<ProgramHost> todo;
+    std::vector<uint64_t> seen;
+    for (const Plan* p : plans) {
+        if (!p || p->nleaf() == 0 || ctx->progs.count(p->uid)) continue;
+        if (std::find(seen.begin(), seen.end(), p->uid) != seen.end()) continue;
+        seen.push_back(p->uid);
+        todo.emplace_back();
+        build_program_host(*p, todo.back());
+    }
+    if (todo.empty()) return TN_OK;
+    size_t off = 0, nperm = 0;
+    for (ProgramHost& h : todo) {
+        h.o_leaf = off;
+        off = align256(off + sizeof(LeafDev) * h.leaves.size());
+        h.o_spos = off;
+        off = align256(off + sizeof(int) * h.spos.size());
+        h.perm_first = nperm;
+        nperm += h.perms.size();
+    }
+    const size_t o_perm = off;
+    const size_t o_tab = align256(o_perm + sizeof(PermParams) * nperm);
+    const size_t total = align256(o_tab + sizeof(PermTables) * nperm);
+    unsigned char* d = (unsigned char*)dev_alloc(ctx, total);
+    if (!d) return fail(TN_ENOMEM, "device allocation of the plan programs failed");
     tn_status st = ensure_pinned(ctx, o_tab);
     if (st != TN_OK) {
-        dev_free(ctx, dp.buf, dp.bytes);
+        dev_free(ctx, d, total);
         return st;
     }
     (void)hipStreamSynchronize(ctx->stream);  // the staging buffer may still be in use
-    unsigned char* h = (unsigned char*)ctx->pinned;
-    std::memcpy(h + o_leaf, leaves.data(), sizeof(LeafDev) * leaves.size());
-    if (!perms.empty()) std::memcpy(h + o_perm, perms.data(), sizeof(PermParams) * perms.size());
-    std::memcpy(h + o_spos, spos.data(), sizeof(int) * spos.size());
-    unsigned char* d = (unsigned char*)dp.buf;
-    if (hipMemcpyAsync(dp.buf, h, o_tab, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        launch_expand_perms((const PermParams*)(d + o_perm), (PermTables*)(d + o_tab), (int)perms.size(),
-                            ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-        dev_free(ctx, dp.buf, dp.bytes);
-        return fail(TN_EDEVICE, "upload of the plan program failed");
+    unsigned char* hb = (unsigned char*)ctx->pinned;
+    for (const ProgramHost& h : todo) {
+        std::memcpy(hb + h.o_leaf, h.leaves.data(), sizeof(LeafDev) * h.leaves.size());
+        std::memcpy(hb + h.o_spos, h.spos.data(), sizeof(int) * h.spos.size());
+        if (!h.perms.empty())
+            std::memcpy(hb + o_perm + sizeof(PermParams) * h.perm_first, h.perms.data(),
+                        sizeof(PermParams) * h.perms.size());
     }
-    dp.leaves = (LeafDev*)(d + o_leaf);
-    dp.perms = (PermTables*)(d + o_tab);
-    dp.nperms = (int)perms.size();
-    dp.slice_pos = (int*)(d + o_spos);
-    auto ins = ctx->progs.emplace(p.uid, std::move(dp));
-    out = &ins.first->second;
+    if (hipMemcpyAsync(d, hb, o_tab, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        launch_expand_perms((const PermParams*)(d + o_perm), (PermTables*)(d + o_tab), (int)nperm, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        dev_free(ctx, d, total);
+        return fail(TN_EDEVICE, "upload of the plan programs failed");
+    }
+    ctx->prog_bufs.push_back({d, total});
+    PermTables* tabs = (PermTables*)(d + o_tab);
+    for (ProgramHost& h : todo) {
+        DevProgram& dp = h.dp;
+        dp.leaves = (LeafDev*)(d + h.o_leaf);
+        dp.slice_pos = (int*)(d + h.o_spos);
+        dp.perms = tabs + h.perm_first;
+        dp.nperms = (int)h.perms.size();
+        ctx->progs.emplace(h.plan->uid, std::move(dp));
+    }
+    return TN_OK;
+}
+
+tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
+    auto it = ctx->progs.find(p.uid);
+    if (it == ctx->progs.end()) {
+        tn_status st = get_programs(ctx, {&p});
+        if (st != TN_OK) return st;
+        it = ctx->progs.find(p.uid);
+        if (it == ctx->progs.end()) return fail(TN_EINVAL, "a plan without leaves has no program");
+    }
+    out = &it->second;
     return TN_OK;
 }
 

@@ -30,9 +30,7 @@ struct NodeLaunch {
 
 // Device-resident constant data of one plan: leaf descriptors, permute
 // tables and slice positions.  Uploaded once per (context, plan).
-struct DevProgram {
-    void* buf = nullptr;
-    size_t bytes = 0;
+struct DevProgram {  // device tables of one plan (in a buffer that ctx->prog_bufs owns)
     LeafDev* leaves = nullptr;
     PermTables* perms = nullptr;  // indexed by permute slot
     int nperms = 0;
@@ -74,6 +72,7 @@ struct tn_ctx {
     void* pinned = nullptr;  // host staging (results, weights)
     size_t pinned_bytes = 0;
     std::map<uint64_t, tn::DevProgram> progs;  // keyed by plan uid
+    std::vector<std::pair<void*, size_t>> prog_bufs;  // device buffers holding the programs
     int cu_count = 0;
     // grow-only device scratch reused by synchronous persistent launches
     void* batch_dev = nullptr;
@@ -101,6 +100,8 @@ void* dev_alloc(tn_ctx* ctx, size_t bytes);
 void dev_free(tn_ctx* ctx, void* p, size_t bytes);
 tn_status ensure_pinned(tn_ctx* ctx, size_t bytes);
 tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out);
+// Programs of every plan in the list not yet on the device, with one upload.
+tn_status get_programs(tn_ctx* ctx, const std::vector<const Plan*>& plans);
 // The widened permute tables of a program (no-op once built).
 tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp);
 // Tile shapes of every node for one device algebra (cached in dp).
