@@ -4,12 +4,15 @@
 #include "batch_host.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <queue>
+#include <thread>
 
 namespace tn {
 
@@ -203,7 +206,7 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
         N.c_off = np.dag_c_off;
         N.nout = (int64_t)1 << (N.g.lb + N.g.li + N.g.lj);
         N.reduce_per_block = N.nout < 1024 ? 1 : 0;
-        N.part_off = jp.dp->part_off_dag[jp.dsr][t];
+        N.part_off = jp.dp->part_off_dag.at(jp.dsr)[t];  // a lookup: templates build concurrently
         for (int side = 0; side < 2; side++) {
             int child = side ? np.b : np.a;
             bool perm = side ? np.perm_b : np.perm_a;
@@ -294,7 +297,25 @@ int device_cu_count(tn_ctx* ctx) {
     return n;
 }
 
+// Host-side phase timing of batch_prepare on stderr when TN_HOST_TIMING is
+// set (diagnostics only).
+namespace {
+struct PhaseClock {
+    bool on;
+    std::chrono::steady_clock::time_point t;
+    PhaseClock() : on(std::getenv("TN_HOST_TIMING") != nullptr), t(std::chrono::steady_clock::now()) {}
+    void mark(const char* what, size_t njobs) {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[tn host] %-10s %8.3f ms (%zu jobs)\n", what,
+                     std::chrono::duration<double, std::milli>(now - t).count(), njobs);
+        t = now;
+    }
+};
+}  // namespace
+
 tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch& L, const DevAllocFn& alloc) {
+    PhaseClock clk;
     L = BatchLaunch();
     L.items.resize(items.size());
     std::vector<JobPlan> jobs;
@@ -317,6 +338,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             if (it.plan && it.plan->fingerprint == it.net->fingerprint) plans.push_back(it.plan);
         (void)get_programs(ctx, plans);
     }
+    clk.mark("programs", items.size());
     // ---- per item: passes and device programs; lay out device memory
     for (size_t i = 0; i < items.size(); i++) {
         BatchItem& it = items[i];
@@ -402,7 +424,39 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     std::vector<BTask> bt;
     int ncounters = 0;
     const int fuse_rank = small_rank(jobs.size(), device_cu_count(ctx) * 2);
+    // one template per (plan, algebra); the templates are independent of each
+    // other, so a large launch builds them on several host threads
     std::map<std::pair<const Plan*, int>, JobTemplate> templates;
+    {
+        std::vector<std::pair<JobTemplate*, size_t>> todo;  // template, its first job
+        for (size_t ji = 0; ji < jobs.size(); ji++) {
+            auto ins = templates.emplace(std::make_pair(jobs[ji].plan, jobs[ji].dsr), JobTemplate());
+            if (ins.second) todo.push_back({&ins.first->second, ji});
+        }
+        auto build = [&](size_t u) {
+            JobTemplate& T = *todo[u].first;
+            build_template(jobs[todo[u].second], fuse_rank, T);
+            const std::vector<int> rank = critical_path_order(T.bt, T.bn, T.subtree, T.ncounters);
+            T.order.assign(T.bt.size(), 0);
+            for (size_t k = 0; k < rank.size(); k++) T.order[(size_t)rank[k]] = (int)k;
+            T.work = 2.0e4 * (double)T.bt.size();
+            for (auto& N : T.bn)
+                T.work += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk)) * (N.g.rm == 4 ? 0.5 : 1.0);
+        };
+        const size_t nthreads =
+            todo.size() >= 32 ? std::min<size_t>(8, std::max(1u, std::thread::hardware_concurrency())) : 1;
+        if (nthreads > 1) {
+            std::atomic<size_t> next{0};
+            std::vector<std::thread> pool;
+            for (size_t w = 0; w < nthreads; w++)
+                pool.emplace_back([&] {
+                    for (size_t u = next++; u < todo.size(); u = next++) build(u);
+                });
+            for (auto& th : pool) th.join();
+        } else {
+            for (size_t u = 0; u < todo.size(); u++) build(u);
+        }
+    }
     std::vector<const JobTemplate*> job_tmpl(jobs.size(), nullptr);
     std::vector<int> job_task0(jobs.size(), 0);
     for (size_t ji = 0; ji < jobs.size(); ji++) {
@@ -427,19 +481,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         J.spos = jp.dp ? jp.dp->slice_pos : nullptr;
         J.w = items[jp.item].net->wdev.empty() ? nullptr : (const float*)(dbase + item_w_off[jp.item]);
         // the job's tasks: a copy of its template with ids shifted
-        const auto key = std::make_pair(jp.plan, jp.dsr);
-        auto ti = templates.find(key);
-        if (ti == templates.end()) {
-            ti = templates.emplace(key, JobTemplate()).first;
-            JobTemplate& T = ti->second;
-            build_template(jp, fuse_rank, T);
-            const std::vector<int> rank = critical_path_order(T.bt, T.bn, T.subtree, T.ncounters);
-            T.order.assign(T.bt.size(), 0);
-            for (size_t k = 0; k < rank.size(); k++) T.order[(size_t)rank[k]] = (int)k;
-            T.work = 2.0e4 * (double)T.bt.size();
-            for (auto& N : T.bn)
-                T.work += std::exp2((double)(N.g.lb + N.g.li + N.g.lj + N.g.lk)) * (N.g.rm == 4 ? 0.5 : 1.0);
-        }
+        auto ti = templates.find(std::make_pair(jp.plan, jp.dsr));
         JobTemplate& T = ti->second;
         if (T.bn0 < 0) {  // nodes and subtree lists: once per template, shared by its jobs
             T.bn0 = (int)bn.size();
@@ -464,6 +506,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         L.total_ops += T.ops;
         L.total_bytes += T.bytes;
     }
+    clk.mark("templates", jobs.size());
     // every job goes to one XCC queue (longest-processing-time first on the
     // estimated work: semiring ops plus a fixed cost per task)
     const int nq = std::max(1, std::min(16, device_cu_count(ctx) / 32));
@@ -527,6 +570,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     for (int q = 1; q < nq; q++) L.qbegin[q] = L.qbegin[q - 1] + L.qcount[q - 1];
     if (ctx->profiling) L.host_tasks = sorted;
 
+    clk.mark("queues", jobs.size());
     // ---- one upload: jobs | nodes | tasks | counters, tickets | subtrees |
     // qbegin, qcount | trace; then the weights
     size_t o_jobs = 0;
@@ -574,6 +618,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     L.o_hacc = o_end + wbytes;
     L.o_hticket = a256(L.o_hacc + kAccSlotBytes * jobs.size());
     L.d_accs = dbase + o_accs;
+    clk.mark("tables", jobs.size());
     return TN_OK;
 }
 

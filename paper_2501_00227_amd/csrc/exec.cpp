@@ -30,13 +30,16 @@ void dev_free(tn_ctx* ctx, void* p, size_t bytes) {
 
 tn_status ensure_pinned(tn_ctx* ctx, size_t bytes) {
     if (ctx->pinned_bytes >= bytes) return TN_OK;
+    const size_t had = ctx->pinned_bytes;
     if (ctx->pinned) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipHostFree(ctx->pinned);
         ctx->pinned = nullptr;
         ctx->pinned_bytes = 0;
     }
-    size_t n = std::max<size_t>(bytes, 1 << 16);
+    // grow geometrically: a stream of slightly larger requests reallocates
+    // (a slow pinned allocation) only a logarithmic number of times
+    size_t n = std::max<size_t>(std::max<size_t>(bytes, 1 << 16), 2 * had);
     if (hipHostMalloc(&ctx->pinned, n, hipHostMallocDefault) != hipSuccess)
         return fail(TN_ENOMEM, "hipHostMalloc of the staging buffer failed");
     ctx->pinned_bytes = n;
@@ -54,8 +57,11 @@ void* pinned_acquire(tn_ctx* ctx, size_t bytes) {
         best->busy = true;
         return best->p;
     }
+    // a new buffer rounds up to a power of two, so later launches of a similar
+    // size find it free instead of allocating again
     void* p = nullptr;
-    size_t n = std::max<size_t>(bytes, 1 << 16);
+    size_t n = 1 << 16;
+    while (n < bytes) n <<= 1;
     if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) return nullptr;
     ctx->pinned_pool.push_back({p, n, true});
     return p;
