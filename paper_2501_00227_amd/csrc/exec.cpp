@@ -4,9 +4,12 @@
 #include "exec.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <unordered_set>
 
 namespace tn {
 
@@ -158,16 +161,26 @@ void build_program_host(const Plan& p, ProgramHost& h) {
 // leaves and slice positions, then all compact permutes (uploaded in one
 // copy), then all permute tables, expanded on the device by one launch.
 tn_status get_programs(tn_ctx* ctx, const std::vector<const Plan*>& plans) {
-    std::vector<ProgramHost> todo;
-    std::vector<uint64_t> seen;
-    for (const Plan* p : plans) {
-        if (!p || p->nleaf() == 0 || ctx->progs.count(p->uid)) continue;
-        if (std::find(seen.begin(), seen.end(), p->uid) != seen.end()) continue;
-        seen.push_back(p->uid);
-        todo.emplace_back();
-        build_program_host(*p, todo.back());
+    std::vector<const Plan*> fresh;
+    std::unordered_set<uint64_t> seen;
+    for (const Plan* p : plans)
+        if (p && p->nleaf() > 0 && !ctx->progs.count(p->uid) && seen.insert(p->uid).second) fresh.push_back(p);
+    if (fresh.empty()) return TN_OK;
+    // host tables of each plan (independent: several threads for many plans)
+    std::vector<ProgramHost> todo(fresh.size());
+    const size_t nthreads =
+        fresh.size() >= 32 ? std::min<size_t>(8, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    if (nthreads > 1) {
+        std::atomic<size_t> next{0};
+        std::vector<std::thread> pool;
+        for (size_t w = 0; w < nthreads; w++)
+            pool.emplace_back([&] {
+                for (size_t u = next++; u < fresh.size(); u = next++) build_program_host(*fresh[u], todo[u]);
+            });
+        for (auto& th : pool) th.join();
+    } else {
+        for (size_t u = 0; u < fresh.size(); u++) build_program_host(*fresh[u], todo[u]);
     }
-    if (todo.empty()) return TN_OK;
     size_t off = 0, nperm = 0;
     for (ProgramHost& h : todo) {
         h.o_leaf = off;
