@@ -22,7 +22,7 @@ Also reported in the same JSON line:
                         algebra uniform over tropical int32, counting tropical,
                         float32 partition function): one-at-a-time, batched
                         (persistent launches of 256 jobs) and served
-                        (Poisson arrivals at 0.5, 1 and 2 x the one-at-a-time
+                        (Poisson arrivals at 0.5, 1, 2 and 4 x the one-at-a-time
                         rate; p50/p99 latency submit -> result on the host)
   cpu_baseline          the CPU oracle producing the step's three results
 """
@@ -314,9 +314,9 @@ def job_stream(ctx, njobs, seed=0):
         chunk = jobs[k:k + 256]
         ctx.solve_batch([c[0] for c in chunk], [c[1] for c in chunk], [c[2] for c in chunk])
     res["batched_solves_per_s"] = njobs / (time.perf_counter() - t0)
-    # served: Poisson arrivals at 0.5, 1 and 2 x the one-at-a-time rate
+    # served: Poisson arrivals at 0.5, 1, 2 and 4 x the one-at-a-time rate
     res["served"] = []
-    for mult in (0.5, 1.0, 2.0):
+    for mult in (0.5, 1.0, 2.0, 4.0):
         rate = mult * plain
         arrivals = gg.poisson_arrivals(njobs, rate, seed + 1)
         srv = tn.Server(ctx, 16 << 30, max_slots=512)

@@ -108,6 +108,7 @@ struct InFlight {
     std::vector<uint64_t> ids;
     hipEvent_t ev = nullptr;
     uint64_t bytes = 0;
+    int stream = 0;
 };
 
 struct tn_server {
@@ -172,13 +173,17 @@ static void scheduler(tn_server* s) {
                 ++it;
             }
         }
-        // 2. admit: FIFO while the budget and the slots allow
+        // 2. admit: FIFO while the budget and the slots allow.  At most one
+        // launch per stream is in flight: while all are busy, arrivals wait
+        // in the queue and go out together in the next launch (one launch's
+        // host work then serves many jobs when the device is saturated)
         std::vector<uint64_t> ids;
         uint64_t bytes = 0;
         {
             std::unique_lock<std::mutex> g(s->mu);
             if (s->stop && s->queue.empty() && s->inflight.empty()) break;
-            while (!s->queue.empty()) {
+            const bool busy = s->inflight.size() >= s->streams.size();
+            while (!busy && !s->queue.empty()) {
                 ServerJob& j = s->jobs[s->queue.front()];
                 if (s->running + (int)ids.size() >= s->max_slots) break;
                 if (s->admitted + bytes + j.bytes > s->budget) break;
@@ -214,8 +219,21 @@ static void scheduler(tn_server* s) {
         alloc.alloc = [s](size_t n) { return s->pool.alloc(n); };
         alloc.free = [s](void* p, size_t n) { s->pool.release(p, n); };
         tn_status st;
-        hipStream_t stream = s->streams[s->next_stream];
-        s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+        // a stream with no launch in flight (one exists: admission above
+        // stops while every stream is busy)
+        int si = s->next_stream;
+        for (int k = 0; k < (int)s->streams.size(); k++) {
+            const int c = (s->next_stream + k) % (int)s->streams.size();
+            bool used = false;
+            for (const InFlight& o : s->inflight) used = used || o.stream == c;
+            if (!used) {
+                si = c;
+                break;
+            }
+        }
+        s->next_stream = (si + 1) % (int)s->streams.size();
+        hipStream_t stream = s->streams[si];
+        f.stream = si;
         {
             std::lock_guard<std::mutex> g(s->dev);
             st = batch_prepare(s->ctx, items, f.L, alloc);
