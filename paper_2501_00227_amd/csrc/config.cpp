@@ -7,6 +7,7 @@
 // (the back-tracking reading of the tropical contraction, Sec. 5.1).  Indices
 // that a leaf sums by itself (a vertex seen by one leaf only) are set on the
 // host to the best value of that leaf's factors.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -77,16 +78,37 @@ tn_status single_config_max(tn_ctx* ctx, const Net& net, const Plan& plan, int32
             }
             ord_off[nn] = (int)ord_ids.size();
             std::vector<long long> off(plan.node_off_dag.begin(), plan.node_off_dag.end());
+            // inner nodes by depth from the root: a node's output indices are
+            // fixed once its parent is done, so each level runs in parallel
+            std::vector<int> t_of(nn, -1), depth(ninner, 0);
+            for (int t = 0; t < ninner; t++) t_of[plan.prog[t].node] = t;
+            int nlevels = 0;
+            for (int t = ninner - 1; t >= 0; t--) {  // parents come after their children
+                nlevels = std::max(nlevels, depth[t] + 1);
+                for (int c : {plan.prog[t].a, plan.prog[t].b})
+                    if (t_of[c] >= 0) depth[t_of[c]] = depth[t] + 1;
+            }
+            std::vector<int> lvl_off(nlevels + 1, 0), lvl_nodes(ninner);
+            for (int t = 0; t < ninner; t++) lvl_off[depth[t] + 1]++;
+            for (int l = 0; l < nlevels; l++) lvl_off[l + 1] += lvl_off[l];
+            {
+                std::vector<int> fill(lvl_off.begin(), lvl_off.end() - 1);
+                for (int t = ninner - 1; t >= 0; t--) lvl_nodes[fill[depth[t]]++] = t;
+            }
             const size_t b_nodes = nodes.size() * 4, b_ooff = ord_off.size() * 4, b_oids = ord_ids.size() * 4 + 4,
-                         b_off = off.size() * 8, b_asg = (size_t)net.nv * 4 + 4;
+                         b_off = off.size() * 8, b_loff = lvl_off.size() * 4, b_lnod = lvl_nodes.size() * 4,
+                         b_asg = (size_t)net.nv * 4 + 4;
             const size_t o_ooff = (b_nodes + 15) & ~(size_t)15, o_oids = (o_ooff + b_ooff + 15) & ~(size_t)15,
-                         o_off = (o_oids + b_oids + 15) & ~(size_t)15, o_asg = (o_off + b_off + 15) & ~(size_t)15,
+                         o_off = (o_oids + b_oids + 15) & ~(size_t)15, o_loff = (o_off + b_off + 15) & ~(size_t)15,
+                         o_lnod = (o_loff + b_loff + 15) & ~(size_t)15, o_asg = (o_lnod + b_lnod + 15) & ~(size_t)15,
                          o_stat = (o_asg + b_asg + 15) & ~(size_t)15, total = o_stat + 16;
             std::vector<unsigned char> host(total, 0);
             std::memcpy(host.data(), nodes.data(), b_nodes);
             std::memcpy(host.data() + o_ooff, ord_off.data(), b_ooff);
             if (!ord_ids.empty()) std::memcpy(host.data() + o_oids, ord_ids.data(), ord_ids.size() * 4);
             std::memcpy(host.data() + o_off, off.data(), b_off);
+            std::memcpy(host.data() + o_loff, lvl_off.data(), b_loff);
+            std::memcpy(host.data() + o_lnod, lvl_nodes.data(), b_lnod);
             std::memset(host.data() + o_asg, 0xff, (size_t)net.nv * 4);  // -1: unset
             unsigned char* d = nullptr;
             if (hipMalloc(&d, total) != hipSuccess) {
@@ -96,7 +118,8 @@ tn_status single_config_max(tn_ctx* ctx, const Net& net, const Plan& plan, int32
                 hipStream_t s = ctx->stream;
                 if (hipMemcpyAsync(d, host.data(), total, hipMemcpyHostToDevice, s) != hipSuccess ||
                     launch_backtrace((const float*)L.job_arena0[0], (const int*)d, ninner, (const int*)(d + o_ooff),
-                                     (const int*)(d + o_oids), (const long long*)(d + o_off), (int*)(d + o_asg),
+                                     (const int*)(d + o_oids), (const long long*)(d + o_off),
+                                     (const int*)(d + o_loff), (const int*)(d + o_lnod), nlevels, (int*)(d + o_asg),
                                      (int*)(d + o_stat), nn, (int)ord_ids.size(), net.nv, s) != hipSuccess ||
                     hipMemcpyAsync(host.data() + o_asg, d + o_asg, total - o_asg, hipMemcpyDeviceToHost, s) != hipSuccess ||
                     hipStreamSynchronize(s) != hipSuccess) {

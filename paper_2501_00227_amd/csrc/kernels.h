@@ -127,13 +127,15 @@ int accumulator_bytes(int dsr);
 // down, each inner node's summed indices are set to the first assignment
 // whose A + B reproduces the node's stored value.  nodes: 3 ints (node,
 // left, right) per inner node in execution order; the storage order of node
-// x is ord_ids[ord_off[x] .. ord_off[x+1]) (index ids = vertex ids).  assign
-// (nv ints, -1 = unset) receives every index value; status: 0 ok, 1 no
-// matching assignment, 2 too many summed indices, 3 an output index unset.
-// nn: all nodes; nids: entries of ord_ids; the tables are staged in LDS when
-// they fit in 48 KB.
+// x is ord_ids[ord_off[x] .. ord_off[x+1]) (index ids = vertex ids).  The
+// inner nodes by depth from the root: level l holds lvl_nodes[lvl_off[l] ..
+// lvl_off[l+1]) (positions in nodes).  assign (nv ints, -1 = unset) receives
+// every index value; status: 0 ok, 1 no matching assignment, 2 too many
+// summed indices, 3 an output index unset.  nn: all nodes; nids: entries of
+// ord_ids; the tables are staged in LDS when they fit in 40 KB.
 hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, const int* ord_off, const int* ord_ids,
-                            const long long* off, int* assign, int* status, int nn, int nids, int nv, hipStream_t s);
+                            const long long* off, const int* lvl_off, const int* lvl_nodes, int nlevels, int* assign,
+                            int* status, int nn, int nids, int nv, hipStream_t s);
 
 // Choose tile shape for a GEMM node (heuristic; the autotuner may override).
 GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);

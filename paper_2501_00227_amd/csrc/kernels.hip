@@ -566,134 +566,171 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(Planes part, Planes C
 }
 
 // ---------------------------------------------------------- back-trace --
-// One workgroup walks the tree from the root: thread 0 reads the node's value
-// at its (already assigned) output indices and lists the summed indices; all
-// threads then scan the assignments of the summed indices, in chunks, for the
-// smallest one whose A + B equals that value.  The GEMM formed the value as
-// the maximum of exactly these float sums, so the equality is exact.
-__global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, const int* g_nodes, int ninner,
-                                                        const int* g_ord_off, const int* g_ord_ids,
-                                                        const long long* g_off, int* g_assign, int* status, int nn,
-                                                        int nids, int nv, int use_lds) {
-    // the tables and the assignment live in LDS when they fit (the walk is
-    // serial in thread 0, so their latency is on the critical path)
+// One workgroup walks the tree from the root, one depth level at a time (a
+// node's output indices are fixed once its parent is done, and nodes of one
+// level sum disjoint index sets, so they are independent).  Within a level
+// each wave takes whole nodes: lane 0 reads the node's value at its assigned
+// output indices and lists the summed indices, then the 64 lanes scan the
+// assignments of the summed indices in increasing order, 64 at a time, for
+// the first one whose A + B equals that value.  The GEMM formed the value as
+// the maximum of exactly these float sums, so the equality is exact, and the
+// first match is the smallest assignment, whatever the waves' timing.
+constexpr int kBtWaves = 8;
+
+// the lanes of one wave see each other's LDS writes after this point
+__device__ inline void bt_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(64 * kBtWaves) void backtrace_kernel(
+    const float* arena, const int* g_nodes, int ninner, const int* g_ord_off, const int* g_ord_ids,
+    const long long* g_off, const int* g_lvl_off, const int* g_lvl_nodes, int nlevels, int* g_assign, int* status,
+    int nn, int nids, int nv, int use_lds) {
+    // the tables and the assignment live in LDS when they fit
     extern __shared__ __align__(16) unsigned char bt_lds[];
     const int* nodes = g_nodes;
     const int* ord_off = g_ord_off;
     const int* ord_ids = g_ord_ids;
     const long long* off = g_off;
+    const int* lvl_off = g_lvl_off;
+    const int* lvl_nodes = g_lvl_nodes;
     int* assign = g_assign;
     if (use_lds) {
         long long* s_off = (long long*)bt_lds;
         int* s_nodes = (int*)(s_off + nn);
         int* s_oo = s_nodes + 3 * ninner;
         int* s_oi = s_oo + nn + 1;
-        int* s_as = s_oi + nids;
+        int* s_lo = s_oi + nids;
+        int* s_ln = s_lo + nlevels + 1;
+        int* s_as = s_ln + ninner;
         for (int i = threadIdx.x; i < nn; i += blockDim.x) s_off[i] = g_off[i];
         for (int i = threadIdx.x; i < 3 * ninner; i += blockDim.x) s_nodes[i] = g_nodes[i];
         for (int i = threadIdx.x; i <= nn; i += blockDim.x) s_oo[i] = g_ord_off[i];
         for (int i = threadIdx.x; i < nids; i += blockDim.x) s_oi[i] = g_ord_ids[i];
+        for (int i = threadIdx.x; i <= nlevels; i += blockDim.x) s_lo[i] = g_lvl_off[i];
+        for (int i = threadIdx.x; i < ninner; i += blockDim.x) s_ln[i] = g_lvl_nodes[i];
         for (int i = threadIdx.x; i < nv; i += blockDim.x) s_as[i] = g_assign[i];
         nodes = s_nodes;
         ord_off = s_oo;
         ord_ids = s_oi;
         off = s_off;
+        lvl_off = s_lo;
+        lvl_nodes = s_ln;
         assign = s_as;
     }
     constexpr int kMaxFree = 30, kMaxRank = 62;
-    constexpr unsigned long long kChunk = 1ull << 16;
-    __shared__ int sfree[kMaxFree];
-    __shared__ int nfree;
-    __shared__ long long taddr;  // the node's entry at its assigned output indices
-    __shared__ unsigned long long best;
-    __shared__ int mapA[kMaxRank], mapB[kMaxRank];  // >= 0: position in sfree; < 0: -1 - fixed value
-    __shared__ int rankA, rankB;
+    // per wave: the summed indices of its node, and where each operand index
+    // takes its bit from (>= 0: position among the summed indices; < 0:
+    // -1 - the fixed value)
+    __shared__ int w_free[kBtWaves][kMaxFree];
+    __shared__ int w_mapA[kBtWaves][kMaxRank], w_mapB[kBtWaves][kMaxRank];
+    __shared__ int w_nfree[kBtWaves], w_rankA[kBtWaves], w_rankB[kBtWaves], w_err[kBtWaves];
+    __shared__ long long w_taddr[kBtWaves];
     __shared__ int stop;
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     if (threadIdx.x == 0) stop = 0;
     __syncthreads();
-    // Shared state is written by thread 0 only between the barrier pairs that
-    // separate it from every read by the other threads.
-    for (int t = ninner - 1; t >= 0; t--) {
-        const int x = nodes[3 * t], a = nodes[3 * t + 1], b = nodes[3 * t + 2];
-        if (threadIdx.x == 0 && !stop) {
-            long long addr = 0;
-            const int rc = ord_off[x + 1] - ord_off[x];
-            if (rc > kMaxRank) stop = 2;
-            for (int q = 0; q < rc && !stop; q++) {
-                const int v = assign[ord_ids[ord_off[x] + q]];
-                if (v < 0) stop = 3;  // an output index left unset
-                addr |= (long long)(v & 1) << q;
+    for (int lv = 0; lv < nlevels; lv++) {
+        for (int i = lvl_off[lv] + wave; i < lvl_off[lv + 1]; i += kBtWaves) {
+            const int t = lvl_nodes[i];
+            const int x = nodes[3 * t], a = nodes[3 * t + 1], b = nodes[3 * t + 2];
+            if (lane == 0) {
+                int err = 0;
+                long long addr = 0;
+                const int rc = ord_off[x + 1] - ord_off[x];
+                if (rc > kMaxRank) err = 2;
+                for (int q = 0; q < rc && !err; q++) {
+                    const int v = assign[ord_ids[ord_off[x] + q]];
+                    if (v < 0) err = 3;  // an output index left unset
+                    addr |= (long long)(v & 1) << q;
+                }
+                w_taddr[wave] = err ? 0 : off[x] + addr;
+                int nfree = 0;
+                for (int side = 0; side < 2 && !err; side++) {
+                    const int y = side ? b : a;
+                    int* map = side ? w_mapB[wave] : w_mapA[wave];
+                    const int r = ord_off[y + 1] - ord_off[y];
+                    if (side) w_rankB[wave] = r;
+                    else w_rankA[wave] = r;
+                    if (r > kMaxRank) {
+                        err = 2;
+                        break;
+                    }
+                    for (int q = 0; q < r; q++) {
+                        const int id = ord_ids[ord_off[y] + q];
+                        const int cur = assign[id];
+                        if (cur >= 0) {
+                            map[q] = -1 - (cur & 1);
+                            continue;
+                        }
+                        // a summed index already listed for this node is marked
+                        // -2 - position until the node's values are written
+                        int pos = cur <= -2 ? -2 - cur : -1;
+                        if (pos < 0) {
+                            if (nfree == kMaxFree) {
+                                err = 2;
+                                break;
+                            }
+                            pos = nfree;
+                            w_free[wave][nfree++] = id;
+                            assign[id] = -2 - pos;
+                        }
+                        map[q] = pos;
+                    }
+                }
+                w_nfree[wave] = nfree;
+                w_err[wave] = err;
+                if (err) {
+                    *status = err;
+                    stop = err;
+                }
             }
-            if (!stop) taddr = off[x] + addr;
-            nfree = 0;
-            for (int side = 0; side < 2 && !stop; side++) {
-                const int y = side ? b : a;
-                int* map = side ? mapB : mapA;
-                const int r = ord_off[y + 1] - ord_off[y];
-                if (side) rankB = r;
-                else rankA = r;
-                if (r > kMaxRank) {
-                    stop = 2;
+            bt_wave_sync();
+            if (w_err[wave]) break;
+            const int nf = w_nfree[wave], ra = w_rankA[wave], rb = w_rankB[wave];
+            const int* mapA = w_mapA[wave];
+            const int* mapB = w_mapB[wave];
+            const float target = arena[w_taddr[wave]];
+            const long long baseA = off[a], baseB = off[b];
+            const unsigned long long total = 1ull << nf;
+            long long found = -1;
+            for (unsigned long long s0 = 0; s0 < total; s0 += 64) {
+                const unsigned long long sv = s0 + (unsigned long long)lane;
+                bool hit = false;
+                if (sv < total) {
+                    long long addrA = 0, addrB = 0;
+                    for (int q = 0; q < ra; q++) {
+                        const int m = mapA[q];
+                        addrA |= (long long)(m >= 0 ? (int)((sv >> m) & 1) : -1 - m) << q;
+                    }
+                    for (int q = 0; q < rb; q++) {
+                        const int m = mapB[q];
+                        addrB |= (long long)(m >= 0 ? (int)((sv >> m) & 1) : -1 - m) << q;
+                    }
+                    hit = arena[baseA + addrA] + arena[baseB + addrB] == target;
+                }
+                const unsigned long long mask = __ballot(hit);
+                if (mask) {
+                    found = (long long)(s0 + (unsigned long long)__builtin_ctzll(mask));
                     break;
                 }
-                for (int q = 0; q < r; q++) {
-                    const int id = ord_ids[ord_off[y] + q];
-                    const int cur = assign[id];
-                    if (cur >= 0) {
-                        map[q] = -1 - (cur & 1);
-                        continue;
-                    }
-                    // a summed index already listed for this node is marked
-                    // -2 - position until the node's values are written
-                    int pos = cur <= -2 ? -2 - cur : -1;
-                    if (pos < 0) {
-                        if (nfree == kMaxFree) {
-                            stop = 2;
-                            break;
-                        }
-                        pos = nfree;
-                        sfree[nfree++] = id;
-                        assign[id] = -2 - pos;
-                    }
-                    map[q] = pos;
+            }
+            if (lane == 0) {
+                if (found < 0) {
+                    *status = 1;
+                    stop = 1;
+                } else {
+                    for (int f = 0; f < nf; f++) assign[w_free[wave][f]] = (int)((found >> f) & 1);
                 }
             }
-            if (stop) *status = stop;
-            best = ~0ull;
+            bt_wave_sync();  // the wave's tables are rewritten for its next node
+            if (found < 0) break;
         }
         __syncthreads();
         const int halt = stop;
-        const unsigned long long total = 1ull << nfree;
         __syncthreads();
         if (halt) break;
-        const float target = arena[taddr];  // every thread: one round trip with the scan's loads
-        for (unsigned long long c0 = 0; c0 < total; c0 += kChunk) {
-            const unsigned long long c1 = c0 + kChunk < total ? c0 + kChunk : total;
-            for (unsigned long long s = c0 + threadIdx.x; s < c1; s += blockDim.x) {
-                long long addrA = 0, addrB = 0;
-                for (int q = 0; q < rankA; q++) {
-                    const int m = mapA[q];
-                    addrA |= (long long)(m >= 0 ? (int)((s >> m) & 1) : -1 - m) << q;
-                }
-                for (int q = 0; q < rankB; q++) {
-                    const int m = mapB[q];
-                    addrB |= (long long)(m >= 0 ? (int)((s >> m) & 1) : -1 - m) << q;
-                }
-                if (arena[off[a] + addrA] + arena[off[b] + addrB] == target) atomicMin(&best, s);
-            }
-            __syncthreads();
-            const bool found = best != ~0ull;
-            __syncthreads();
-            if (found) break;
-        }
-        if (threadIdx.x == 0) {
-            if (best == ~0ull) {
-                *status = 1;
-                stop = 1;
-            } else {
-                for (int f = 0; f < nfree; f++) assign[sfree[f]] = (int)((best >> f) & 1);
-            }
-        }
     }
     if (use_lds) {
         __syncthreads();
@@ -702,11 +739,14 @@ __global__ __launch_bounds__(256) void backtrace_kernel(const float* arena, cons
 }
 
 hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, const int* ord_off, const int* ord_ids,
-                            const long long* off, int* assign, int* status, int nn, int nids, int nv, hipStream_t s) {
-    const size_t bytes = 8 * (size_t)nn + 4 * (3 * (size_t)ninner + (size_t)nn + 1 + (size_t)nids + (size_t)nv);
-    const int use_lds = bytes <= 48 * 1024 ? 1 : 0;
-    backtrace_kernel<<<1, 256, use_lds ? bytes : 0, s>>>(arena, nodes, ninner, ord_off, ord_ids, off, assign, status,
-                                                         nn, nids, nv, use_lds);
+                            const long long* off, const int* lvl_off, const int* lvl_nodes, int nlevels, int* assign,
+                            int* status, int nn, int nids, int nv, hipStream_t s) {
+    const size_t bytes = 8 * (size_t)nn + 4 * (3 * (size_t)ninner + (size_t)nn + 1 + (size_t)nids + (size_t)nlevels +
+                                               1 + (size_t)ninner + (size_t)nv);
+    const int use_lds = bytes <= 40 * 1024 ? 1 : 0;
+    backtrace_kernel<<<1, 64 * kBtWaves, use_lds ? bytes : 0, s>>>(arena, nodes, ninner, ord_off, ord_ids, off, lvl_off,
+                                                                   lvl_nodes, nlevels, assign, status, nn, nids, nv,
+                                                                   use_lds);
     return hipGetLastError();
 }
 
