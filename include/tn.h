@@ -436,19 +436,21 @@ tn_status tn_solve_size_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* pla
  * largest value.  Computed in one contraction over truncated polynomials
  * (per tensor entry the four highest-order terms c_d x^(m - d) of the
  * polynomial whose exponents are configuration values; (+) aligns two such
- * lists by their top exponent, (x) adds exponents and convolves the counts)
- * on the per-node executor, sliced plans included.  Counts are modulo 2^64
- * (as TN_COUNTING_TROPICAL); a value in between that no configuration takes
- * has count 0.
- *   k       1 .. 4
- *   top     out: the largest value; INT32_MIN if no configuration satisfies
- *           the fixed vertices (then every count is 0)
- *   counts  caller memory of k uint64: counts[d] at value top - d
- * Synchronous.  Errors: TN_EINVAL (k out of range, non-integer weights,
- * plan with open vertices or built for another network), TN_ENOMEM,
- * TN_EDEVICE. */
-tn_status tn_solve_counting_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t* top,
-                                  uint64_t* counts);
+ * lists by their top exponent, (x) adds exponents and convolves the counts).
+ * Counts are modulo 2^64 (as TN_COUNTING_TROPICAL); a value in between that
+ * no configuration takes has count 0.
+ *   k         1 .. 4
+ *   executor  as for tn_solve_size_max_k: 0 auto (persistent for unsliced
+ *             trees with sc <= 14), 1 per-node launches (sliced plans too),
+ *             2 persistent (unsliced plans only)
+ *   top       out: the largest value; INT32_MIN if no configuration
+ *             satisfies the fixed vertices (then every count is 0)
+ *   counts    caller memory of k uint64: counts[d] at value top - d
+ * Synchronous.  Errors: TN_EINVAL (k or executor out of range, non-integer
+ * weights, plan with open vertices or built for another network, executor 2
+ * with a sliced plan), TN_ENOMEM, TN_EDEVICE. */
+tn_status tn_solve_counting_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t k, int32_t executor,
+                                  int32_t* top, uint64_t* counts);
 
 /* One maximum configuration (SingleConfigMax of the Sec. 5 table): an
  * independent set of largest total weight, or for a spin-glass network a

@@ -141,7 +141,8 @@ SIGNATURES = [
     ("tn_net_condition", ctypes.c_int, [_VP, ctypes.c_int32, c_int32_p, c_int32_p, _P(_VP)]),
     ("tn_solve_open", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), ctypes.c_int64, _P(tn_result)]),
     ("tn_solve_size_max_k", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_float)]),
-    ("tn_solve_counting_max_k", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, c_int32_p, _P(ctypes.c_uint64)]),
+    ("tn_solve_counting_max_k", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, c_int32_p,
+                                               _P(ctypes.c_uint64)]),
     ("tn_solve_single_config_max", ctypes.c_int, [_VP, _VP, _VP, c_int32_p, _P(ctypes.c_float)]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
@@ -533,12 +534,13 @@ class Context:
         _check(lib().tn_solve_size_max_k(self.h, net.h, plan.h, int(k), int(ex), out))
         return [float(x) for x in out]
 
-    def solve_counting_max_k(self, net: Net, plan: Plan, k: int) -> Dict:
+    def solve_counting_max_k(self, net: Net, plan: Plan, k: int, executor="auto") -> Dict:
         """CountingMax(k) for integer weights (k <= 4): {"top": the largest
         value (or -inf), "counts": {top - d: count mod 2^64}}."""
         top = ctypes.c_int32(0)
         cnt = (ctypes.c_uint64 * int(k))()
-        _check(lib().tn_solve_counting_max_k(self.h, net.h, plan.h, int(k), ctypes.byref(top), cnt))
+        ex = EXECUTOR.get(executor, executor) if isinstance(executor, str) else int(executor)
+        _check(lib().tn_solve_counting_max_k(self.h, net.h, plan.h, int(k), int(ex), ctypes.byref(top), cnt))
         if top.value == -2 ** 31:
             return {"top": float("-inf"), "counts": {}}
         return {"top": top.value, "counts": {top.value - d: int(cnt[d]) for d in range(int(k))}}

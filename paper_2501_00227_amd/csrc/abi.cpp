@@ -582,27 +582,43 @@ tn_status tn_solve_size_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int3
     TN_GUARD_END
 }
 
-tn_status tn_solve_counting_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, int32_t* top,
-                                  uint64_t* counts) {
+tn_status tn_solve_counting_max_k(tn_ctx* c, const tn_net* n, const tn_plan* p, int32_t k, int32_t executor,
+                                  int32_t* top, uint64_t* counts) {
     TN_GUARD_BEGIN
     if (!c || !n || !p || !top || !counts || k < 1 || k > 4)
         return fail(TN_EINVAL, "invalid arguments (k in 1..4, top and counts required)");
+    if (executor < 0 || executor > 2) return fail(TN_EINVAL, "executor must be 0, 1 or 2");
+    if (executor == 2 && !p->plan.sliced.empty())
+        return fail(TN_EINVAL, "the persistent executor runs unsliced plans only");
     if (p->plan.fingerprint != n->net.fingerprint || p->plan.nv != n->net.nv)
         return fail(TN_EINVAL, "plan was built for a different network");
     if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
-    tn_solve_opts o;
-    tn_solve_opts_default(&o);
-    o.semiring = kSemiringTPoly4;
-    o.executor = 1;
-    tn_result r;
-    std::vector<unsigned char> raw;
-    tn_status st = solve_one(c, n->net, p->plan, o, r, nullptr, &raw);
-    if (st != TN_OK) return st;
     if (p->plan.nleaf() == 0) {  // the empty network: one configuration of value 0
         *top = 0;
         counts[0] = 1;
         for (int d = 1; d < k; d++) counts[d] = 0;
         return TN_OK;
+    }
+    std::vector<unsigned char> raw;
+    // auto: one persistent launch for small trees only (as for SizeMax(k))
+    const bool small = p->plan.sliced.empty() && p->plan.max_rank <= 14;
+    if (executor == 2 || (executor == 0 && small)) {
+        if (!p->plan.open.empty()) return fail(TN_EINVAL, "the plan has open vertices");
+        if (!n->net.integer_weights) return fail(TN_EINVAL, "CountingMax(k) needs integer weights (|w| <= 65536)");
+        std::vector<PassSpec> passes(1);
+        passes[0].dsr = DSR_TPOLY;
+        std::vector<std::array<unsigned char, kAccSlotBytes>> accs;
+        tn_status st = run_passes_sync(c, n->net, p->plan, passes, accs);
+        if (st != TN_OK) return st;
+        raw.assign(accs[0].begin(), accs[0].end());
+    } else {
+        tn_solve_opts o;
+        tn_solve_opts_default(&o);
+        o.semiring = kSemiringTPoly4;
+        o.executor = 1;
+        tn_result r;
+        tn_status st = solve_one(c, n->net, p->plan, o, r, nullptr, &raw);
+        if (st != TN_OK) return st;
     }
     int32_t m;
     uint64_t cnt[4];

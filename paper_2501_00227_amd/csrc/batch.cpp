@@ -39,8 +39,9 @@ int small_rank(size_t njobs, int nworkgroups) {
     return (int)njobs >= nworkgroups / 4 ? 12 : 0;
 }
 // a large node is cut into at most this many tasks (each loops over tiles);
-// the eight-largest algebra's GEMM tiles cost some twenty times a 4-byte
-// tile, so its GEMMs get one task per resident workgroup (two per CU)
+// the wide-entry algebras' GEMM tiles (eight-lists, truncated polynomials)
+// cost some twenty times a 4-byte tile, so their GEMMs get one task per
+// resident workgroup (two per CU)
 constexpr int64_t kMaxTasksPerNode = 64;
 constexpr int64_t kMaxTasksPerNodeTop8 = 512;
 
@@ -217,6 +218,7 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
             // 32-byte entries move as eight 4-byte words: three more bits, kept lowest
             const int wide = jp.dsr == DSR_TOPK ? 3 : 0;
             N.pp[side] = (wide ? jp.dp->perms_wide : jp.dp->perms) + slot;
+            N.pp1[side] = jp.dsr == DSR_TPOLY ? jp.dp->perms_wide + slot : nullptr;
             N.psrc[side] = p.node_off_dag[child];
             N.pdst[side] = side ? np.dag_b_tmp : np.dag_a_tmp;
             N.prank[side] = rank + wide;
@@ -255,17 +257,26 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
                 ready[side] = final_of[child];
                 continue;
             }
-            int64_t ntiles = (int64_t)1 << (N.prank[side] - N.ptile_bits[side]);
-            int64_t per = chunk(ntiles);
-            int64_t ntask = ntiles / per;
-            Counter c{T.ncounters++, (int)(ntask * npl), final_of[child].level + 1};
+            // tiles per plane (the truncated polynomial's count plane moves as
+            // 4-byte words of rank + 3)
+            int64_t per_pl[2], ntask_pl[2], ntask_all = 0;
+            for (int pl = 0; pl < npl; pl++) {
+                const int r = (jp.dsr == DSR_TPOLY && pl == 1) ? N.prank[side] + 3 : N.prank[side];
+                const int64_t ntiles = (int64_t)1 << (r - perm_tile_bits(r));
+                per_pl[pl] = chunk(ntiles);
+                ntask_pl[pl] = ntiles / per_pl[pl];
+                ntask_all += ntask_pl[pl];
+            }
+            Counter c{T.ncounters++, (int)ntask_all, final_of[child].level + 1};
             for (int pl = 0; pl < npl; pl++)
-                for (int64_t k = 0; k < ntask; k++)
-                    add(BT_PERM, nidx, side * 2 + pl, k * per, final_of[child], Counter(), c.id, c.level, (int)per);
+                for (int64_t k = 0; k < ntask_pl[pl]; k++)
+                    add(BT_PERM, nidx, side * 2 + pl, k * per_pl[pl], final_of[child], Counter(), c.id, c.level,
+                        (int)per_pl[pl]);
             ready[side] = c;
         }
         int64_t nblocks = (int64_t)1 << ((N.g.lb - N.g.tb) + (N.g.li - N.g.ti) + (N.g.lj - N.g.tj) + N.g.lsplit);
-        int64_t per = chunk(nblocks, jp.dsr == DSR_TOPK ? kMaxTasksPerNodeTop8 : kMaxTasksPerNode);
+        const bool wide_entry = jp.dsr == DSR_TOPK || jp.dsr == DSR_TPOLY;
+        int64_t per = chunk(nblocks, wide_entry ? kMaxTasksPerNodeTop8 : kMaxTasksPerNode);
         Counter gdone{T.ncounters++, (int)(nblocks / per), std::max(ready[0].level, ready[1].level) + 1};
         for (int64_t k = 0; k < nblocks / per; k++)
             add(BT_GEMM, nidx, 0, k * per, ready[0], ready[1], gdone.id, gdone.level, (int)per);
@@ -363,8 +374,6 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             st.passes = *it.passes;
         else
             s = make_passes(*it.net, it.opts, st.passes);
-        for (const PassSpec& ps : st.passes)
-            if (ps.dsr == DSR_TPOLY) s = fail(TN_EINVAL, "the truncated-polynomial algebra runs on the per-node executor only");
         if (s != TN_OK) {
             st.status = s;
             continue;
@@ -373,7 +382,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         if (it.plan->nleaf() > 0) {
             s = get_program(ctx, *it.plan, dp);
             for (const PassSpec& ps : st.passes)
-                if (s == TN_OK && ps.dsr == DSR_TOPK) s = ensure_wide_perms(ctx, *it.plan, *dp);
+                if (s == TN_OK && (ps.dsr == DSR_TOPK || ps.dsr == DSR_TPOLY)) s = ensure_wide_perms(ctx, *it.plan, *dp);
             if (s != TN_OK) {
                 st.status = s;
                 continue;
@@ -408,6 +417,13 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     }
     L.njobs = (int)jobs.size();
     if (jobs.empty()) return TN_OK;
+    {  // one kernel instance serves the wide-entry algebras, another the rest
+        int nwide = 0;
+        for (const JobPlan& jp : jobs) nwide += (jp.dsr == DSR_TOPK || jp.dsr == DSR_TPOLY) ? 1 : 0;
+        if (nwide > 0 && nwide < (int)jobs.size())
+            return fail(TN_EINVAL, "a persistent launch cannot mix the wide-entry algebras with the others");
+        L.wide = nwide > 0 ? 1 : 0;
+    }
     // every job's root accumulator slot, side by side: one read-back
     const size_t o_accs = data;
     for (size_t ji = 0; ji < jobs.size(); ji++) jobs[ji].o_acc = o_accs + kAccSlotBytes * ji;
@@ -639,7 +655,7 @@ tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
         int shape[4] = {0, 0, 0, 0};
         ProfScope ps(ctx, TN_K_BATCH, -1, -1, shape, L.total_bytes, L.total_ops);
         e = launch_batch(L.d_tasks, L.d_qbegin, L.d_qcount, L.nq, L.d_jobs, L.d_nodes, L.d_subtree, L.d_counters,
-                         L.d_ticket, nwg, L.d_trace, s);
+                         L.d_ticket, nwg, L.d_trace, L.wide, s);
     }
     // the tickets come back with the roots: a queue whose tickets did not all
     // go out was not served, and its jobs' results are not valid

@@ -38,6 +38,9 @@ struct BNode {  // one inner node; jobs of the same plan and algebra share it (o
     int64_t a_off, b_off, c_off;  // effective operand offsets (after permutes)
     int ma, mb, mc;
     const PermTables* pp[2];
+    // the truncated-polynomial algebra's 32-byte count plane: the same permute
+    // over 4-byte words (rank + 3, three lowest bits in place); else null
+    const PermTables* pp1[2];
     int64_t psrc[2], pdst[2];
     int prank[2], ptile_bits[2];
     int64_t part_off;     // this node's split-K partials inside the job's partial buffer
@@ -61,9 +64,11 @@ struct BTask {
 // [qbegin[q], qbegin[q] + qcount[q]) in level order, served by the
 // workgroups running on XCC q (hardware id modulo nq) with ticket tickets[q].
 // trace: NULL, or 4 x ntasks timestamps (start, ready, end, xcc) per task.
+// wide: the launch's jobs use the wide-entry algebras (eight-lists,
+// truncated polynomials; a launch holds either these or the others only).
 hipError_t launch_batch(const BTask* tasks, const int* qbegin, const int* qcount, int nq, const BJob* jobs,
                         const BNode* nodes, const int* subtree, int* counters, int* tickets, int nworkgroups,
-                        unsigned long long* trace, hipStream_t s);
+                        unsigned long long* trace, int wide, hipStream_t s);
 size_t batch_lds_bytes();
 
 }  // namespace tn

@@ -37,6 +37,7 @@ struct DevAllocFn {
 struct BatchLaunch {
     std::vector<ItemState> items;
     int njobs = 0, ntasks = 0;
+    int wide = 0;  // the jobs use the wide-entry algebras (a separate kernel instance)
     void* data = nullptr;    // arenas, partials, meta, accumulators, weights
     size_t data_bytes = 0;
     void* tables = nullptr;  // jobs, nodes, tasks, counters

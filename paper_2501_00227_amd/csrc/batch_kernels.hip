@@ -71,7 +71,7 @@ __device__ __attribute__((always_inline)) void run_gemm(const BJob& j, const BNo
     g.mb = nd.mb;
     g.mc = nd.mc;
     const int rm = nd.g.rm, rn = nd.g.rn;
-    if constexpr (D == DSR_TOPK) {  // 32-byte entries: one output per thread only
+    if constexpr (D == DSR_TOPK || D == DSR_TPOLY) {  // wide entries: one output per thread only
         gemm_tile<D, 1, 1>(g, (u64)tile, smem);
     } else {
         if (nd.g.mode == GEMM_THIN) {
@@ -124,20 +124,24 @@ template <int D>
 __device__ void run_perm(const BJob& j, const BNode& nd, int side, int plane, i64 first, int count,
                          unsigned char* smem) {
     PermLds* tabs = (PermLds*)smem;
-    perm_load_tables(tabs, nd.pp[side]);
+    // the truncated polynomial's count plane moves as 4-byte words of rank + 3
+    const bool wide1 = D == DSR_TPOLY && plane == 1;
+    perm_load_tables(tabs, wide1 ? nd.pp1[side] : nd.pp[side]);
     __syncthreads();
     const int pb = plane_bytes_dev<D>(plane);
     unsigned char* base = (unsigned char*)(plane ? j.arena.p1 : j.arena.p0);
     unsigned char* tile = smem + ((sizeof(PermLds) + 255) & ~(size_t)255);
-    const int nt = nd.prank[side] - nd.ptile_bits[side];
+    const int rank = wide1 ? nd.prank[side] + 3 : nd.prank[side];
+    const int tbits = rank < kPermTileBits ? rank : kPermTileBits;
+    const int nt = rank - tbits;
     for (int k = 0; k < count; k++) {
         if (pb == 4 || pb == 32)  // 32-byte entries: their 4-byte words, by the host's widened tables
             permute_tile<unsigned int>((const unsigned int*)(base + nd.psrc[side] * pb),
                                        (unsigned int*)(base + nd.pdst[side] * pb), tabs, (unsigned int*)tile,
-                                       nd.ptile_bits[side], nt, first + k);
+                                       tbits, nt, first + k);
         else
             permute_tile<u64>((const u64*)(base + nd.psrc[side] * 8), (u64*)(base + nd.pdst[side] * 8), tabs,
-                              (u64*)tile, nd.ptile_bits[side], nt, first + k);
+                              (u64*)tile, tbits, nt, first + k);
     }
 }
 
@@ -156,7 +160,7 @@ __device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count,
         return;
     }
     const int S = 1 << nd.g.lsplit;
-    if constexpr (D == DSR_TOPK) {  // 32-byte entries: one unit at a time
+    if constexpr (D == DSR_TOPK || D == DSR_TPOLY) {  // wide entries: one unit at a time
         for (int k = 0; k < count; k++) {
             const i64 o = (first + k) * 256 + threadIdx.x;
             if (o < nd.nout) A::store(C, o, split_sum<D>(P, nd.nout, o, S, j.ap));
@@ -213,8 +217,11 @@ __device__ void run_node_whole(const BJob& j, const BNode& nd, unsigned char* sm
     bool any = false;
     for (int side = 0; side < 2; side++) {
         if (!nd.pp[side]) continue;
-        const int ntiles = 1 << (nd.prank[side] - nd.ptile_bits[side]);
-        for (int pl = 0; pl < npl; pl++) run_perm<D>(j, nd, side, pl, 0, ntiles, smem);
+        for (int pl = 0; pl < npl; pl++) {
+            const int rank = (D == DSR_TPOLY && pl == 1) ? nd.prank[side] + 3 : nd.prank[side];
+            const int ntiles = 1 << (rank - (rank < kPermTileBits ? rank : kPermTileBits));
+            run_perm<D>(j, nd, side, pl, 0, ntiles, smem);
+        }
         any = true;
     }
     if (any) local_step_sync();
@@ -281,7 +288,12 @@ __device__ inline unsigned int hw_xcc_id() {
 }
 
 // At least two waves per SIMD (registers capped at 256 per lane): the grid of
-// two workgroups per CU is then resident at once.
+// two workgroups per CU is then resident at once.  WIDE selects the algebras
+// one instance serves: the 4-byte ones (and counting tropical), or the
+// wide-entry ones (eight-lists, truncated polynomials), so that the wide
+// algebras' task routines do not enlarge the kernel the common algebras run
+// in (that cost the 4-byte launches some 5%).
+template <bool WIDE>
 __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__ tasks, const int* __restrict__ qbegin,
                                                     const int* __restrict__ qcount, int nq,
                                                     const BJob* __restrict__ jobs, const BNode* __restrict__ nodes,
@@ -303,15 +315,22 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
         wait_counters(counters, t.dep0, t.need0, t.dep1, t.need1);
         const unsigned long long t_ready = trace ? wall_clock64() : 0ull;
         const BJob& j = jobs[t.job];
-        switch (j.dsr) {
-        case DSR_TROP_I32: run_task<DSR_TROP_I32>(t, j, nodes, subtree, smem); break;
-        case DSR_TROP_F32: run_task<DSR_TROP_F32>(t, j, nodes, subtree, smem); break;
-        case DSR_CTROP: run_task<DSR_CTROP>(t, j, nodes, subtree, smem); break;
-        case DSR_MODP: run_task<DSR_MODP>(t, j, nodes, subtree, smem); break;
-        case DSR_Z_F32: run_task<DSR_Z_F32>(t, j, nodes, subtree, smem); break;
-        case DSR_Z_BF16: run_task<DSR_Z_BF16>(t, j, nodes, subtree, smem); break;
-        case DSR_TOPK: run_task<DSR_TOPK>(t, j, nodes, subtree, smem); break;
-        default: break;
+        if constexpr (WIDE) {
+            switch (j.dsr) {
+            case DSR_TOPK: run_task<DSR_TOPK>(t, j, nodes, subtree, smem); break;
+            case DSR_TPOLY: run_task<DSR_TPOLY>(t, j, nodes, subtree, smem); break;
+            default: break;
+            }
+        } else {
+            switch (j.dsr) {
+            case DSR_TROP_I32: run_task<DSR_TROP_I32>(t, j, nodes, subtree, smem); break;
+            case DSR_TROP_F32: run_task<DSR_TROP_F32>(t, j, nodes, subtree, smem); break;
+            case DSR_CTROP: run_task<DSR_CTROP>(t, j, nodes, subtree, smem); break;
+            case DSR_MODP: run_task<DSR_MODP>(t, j, nodes, subtree, smem); break;
+            case DSR_Z_F32: run_task<DSR_Z_F32>(t, j, nodes, subtree, smem); break;
+            case DSR_Z_BF16: run_task<DSR_Z_BF16>(t, j, nodes, subtree, smem); break;
+            default: break;
+            }
         }
         signal_counter(counters, t.signal);
         if (trace && threadIdx.x == 0) {
@@ -325,10 +344,14 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
 
 hipError_t launch_batch(const BTask* tasks, const int* qbegin, const int* qcount, int nq, const BJob* jobs,
                         const BNode* nodes, const int* subtree, int* counters, int* tickets, int nworkgroups,
-                        unsigned long long* trace, hipStream_t s) {
+                        unsigned long long* trace, int wide, hipStream_t s) {
     if (nworkgroups <= 0) return hipSuccess;
-    batch_kernel<<<nworkgroups, 256, kBatchLds, s>>>(tasks, qbegin, qcount, nq, jobs, nodes, subtree, counters,
-                                                     tickets, trace);
+    if (wide)
+        batch_kernel<true><<<nworkgroups, 256, kBatchLds, s>>>(tasks, qbegin, qcount, nq, jobs, nodes, subtree,
+                                                               counters, tickets, trace);
+    else
+        batch_kernel<false><<<nworkgroups, 256, kBatchLds, s>>>(tasks, qbegin, qcount, nq, jobs, nodes, subtree,
+                                                                counters, tickets, trace);
     return hipGetLastError();
 }
 

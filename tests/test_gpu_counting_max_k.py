@@ -1,6 +1,6 @@
 """GPU tests of CountingMax(k) for integer weights (Sec. 5 table; Sec. 5.3
 prints the Petersen value): one contraction over truncated polynomials (the
-four highest-order terms per tensor entry) on the per-node executor.  Checked
+four highest-order terms per tensor entry) on both executors.  Checked
 against the paper's Petersen and buckyball values, the oracle's enumeration
 (weighted independent sets, spin glasses, fixed vertices, a sliced plan) and,
 for unit weights at n = 60 and 100, the oracle's independence polynomial."""
@@ -45,8 +45,12 @@ def test_paper_values(ctx):
     assert r["counts"][-e - 1] == r["counts"][-e - 3] == 0
 
 
+EXECUTORS = ("stream", "persistent")
+
+
+@pytest.mark.parametrize("ex", EXECUTORS)
 @pytest.mark.parametrize("weights", ["unit", "integer"])
-def test_random_graphs_vs_enumeration(ctx, weights):
+def test_random_graphs_vs_enumeration(ctx, weights, ex):
     rng = random.Random({"unit": 11, "integer": 12}[weights])
     for t in range(12):
         n = rng.randint(1, 18)
@@ -56,10 +60,11 @@ def test_random_graphs_vs_enumeration(ctx, weights):
         net = tn.Net.from_graph(g)
         plan = tn.Plan.create(net, seed=t)
         for k in (1, 2, 4):
-            assert ctx.solve_counting_max_k(net, plan, k) == _mod(oracle.brute_force_counting_max_k(g, k)), (t, k)
+            assert ctx.solve_counting_max_k(net, plan, k, ex) == _mod(oracle.brute_force_counting_max_k(g, k)), (t, k)
 
 
-def test_spin_glasses_and_fixed_vertices(ctx):
+@pytest.mark.parametrize("ex", EXECUTORS)
+def test_spin_glasses_and_fixed_vertices(ctx, ex):
     rng = random.Random(13)
     for t in range(8):
         n = rng.randint(3, 16)
@@ -68,15 +73,15 @@ def test_spin_glasses_and_fixed_vertices(ctx):
         h = [float(rng.randint(-1, 1)) for _ in range(n)]
         net = tn.Net.spin_glass(g, J, h)
         plan = tn.Plan.create(net, seed=t)
-        assert ctx.solve_counting_max_k(net, plan, 4) == _mod(oracle.spin_glass_counting_max_k(g, 4, J, h)), t
+        assert ctx.solve_counting_max_k(net, plan, 4, ex) == _mod(oracle.spin_glass_counting_max_k(g, 4, J, h)), t
         fixed = {v: rng.randint(0, 1) for v in rng.sample(range(n), 2)}
-        got = ctx.solve_counting_max_k(net.condition(fixed), plan, 3)
+        got = ctx.solve_counting_max_k(net.condition(fixed), plan, 3, ex)
         assert got == _mod(oracle.spin_glass_counting_max_k(g, 3, J, h, fixed)), t
         gw = g.with_weights(gg.integer_weights(n, 1600 + t, 1, 4))
         wnet = tn.Net.from_graph(gw)
         wplan = tn.Plan.create(wnet, seed=t)
         fixed = {v: 0 for v in rng.sample(range(n), 2)}
-        got = ctx.solve_counting_max_k(wnet.condition(fixed), wplan, 4)
+        got = ctx.solve_counting_max_k(wnet.condition(fixed), wplan, 4, ex)
         assert got == _mod(oracle.brute_force_counting_max_k(gw, 4, fixed)), t
 
 
@@ -86,6 +91,9 @@ def test_sliced_plan(ctx):
     plan = tn.Plan.create(net, method="treesa", ntrials=1, niters=3, sc_target=3, nslices=4, seed=5)
     assert plan.info()["nsliced"] > 0
     assert ctx.solve_counting_max_k(net, plan, 4) == _mod(oracle.brute_force_counting_max_k(g, 4))
+    with pytest.raises(tn.TnError) as ei:
+        ctx.solve_counting_max_k(net, plan, 4, "persistent")
+    assert ei.value.code == tn.TN_EINVAL
 
 
 @pytest.mark.parametrize("n,seed", [(60, 0), (100, 1)])
@@ -95,31 +103,34 @@ def test_unit_weights_agree_with_the_polynomial(ctx, n, seed):
     alpha = len(poly) - 1
     net = tn.Net.from_graph(g)
     plan = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=seed)
-    r = ctx.solve_counting_max_k(net, plan, 4)
-    assert r == {"top": alpha, "counts": {alpha - d: poly[alpha - d] % M64 for d in range(4)}}
+    for ex in EXECUTORS:
+        r = ctx.solve_counting_max_k(net, plan, 4, ex)
+        assert r == {"top": alpha, "counts": {alpha - d: poly[alpha - d] % M64 for d in range(4)}}, ex
     assert ctx.solve_max_k(net, plan, 4)["counting_max_k"] == {alpha - d: poly[alpha - d] for d in range(4)}
 
 
 def test_rejections_and_edge_cases(ctx):
     net = tn.Net.from_graph(gg.path(5))
     plan = tn.Plan.create(net)
-    for k in (0, 5):
+    for k, ex in ((0, "auto"), (5, "auto"), (2, 3), (2, -1)):
         with pytest.raises(tn.TnError) as ei:
-            ctx.solve_counting_max_k(net, plan, k)
+            ctx.solve_counting_max_k(net, plan, k, ex)
         assert ei.value.code == tn.TN_EINVAL
     frac = tn.Net.from_graph(gg.path(5).with_weights(gg.dyadic_weights(5, 0)))
-    with pytest.raises(tn.TnError) as ei:
-        ctx.solve_counting_max_k(frac, tn.Plan.create(frac), 2)
-    assert ei.value.code == tn.TN_EINVAL
-    with pytest.raises(tn.TnError) as ei:
-        ctx.solve_counting_max_k(net, tn.Plan.create(net, open=[1]), 2)
-    assert ei.value.code == tn.TN_EINVAL
+    for ex in EXECUTORS:
+        with pytest.raises(tn.TnError) as ei:
+            ctx.solve_counting_max_k(frac, tn.Plan.create(frac), 2, ex)
+        assert ei.value.code == tn.TN_EINVAL
+        with pytest.raises(tn.TnError) as ei:
+            ctx.solve_counting_max_k(net, tn.Plan.create(net, open=[1]), 2, ex)
+        assert ei.value.code == tn.TN_EINVAL
     with pytest.raises(tn.TnError) as ei:
         ctx.solve_counting_max_k(net, tn.Plan.create(tn.Net.from_graph(gg.path(6))), 2)
     assert ei.value.code == tn.TN_EINVAL
     e = tn.Net.from_graph(gg.empty(0))
     assert ctx.solve_counting_max_k(e, tn.Plan.create(e), 3) == {"top": 0, "counts": {0: 1, -1: 0, -2: 0}}
     bad = net.condition({1: 1, 2: 1})  # both ends of an edge in the set
-    assert ctx.solve_counting_max_k(bad, plan, 2) == {"top": float("-inf"), "counts": {}}
     iso = tn.Net.from_graph(gg.empty(7))  # 2^7 sets: C(7, s) at size s
-    assert ctx.solve_counting_max_k(iso, tn.Plan.create(iso), 4) == {"top": 7, "counts": {7: 1, 6: 7, 5: 21, 4: 35}}
+    for ex in EXECUTORS:
+        assert ctx.solve_counting_max_k(bad, plan, 2, ex) == {"top": float("-inf"), "counts": {}}
+        assert ctx.solve_counting_max_k(iso, tn.Plan.create(iso), 4, ex) == {"top": 7, "counts": {7: 1, 6: 7, 5: 21, 4: 35}}
