@@ -177,6 +177,19 @@ def square_lattice(L: int) -> Graph:
     return _make(L * L, pairs, f"square{L}")
 
 
+def grid(rows: int, cols: int) -> Graph:
+    """Full rows x cols grid, vertex (r, c) -> r*cols + c, 4-neighbour edges."""
+    pairs = []
+    for r in range(rows):
+        for c in range(cols):
+            v = r * cols + c
+            if c + 1 < cols:
+                pairs.append((v, v + 1))
+            if r + 1 < rows:
+                pairs.append((v, v + cols))
+    return _make(rows * cols, pairs, f"grid{rows}x{cols}")
+
+
 def fullerene() -> Graph:
     """The C60 buckyball of the Sec. 6.4 example: the 60 vertices of a truncated
     icosahedron (all cyclic coordinate rotations and sign changes of

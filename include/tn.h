@@ -305,9 +305,10 @@ typedef struct {
     int32_t semiring;          /* tn_semiring */
     double beta;               /* inverse temperature for TN_PARTITION_* (x = e^beta) */
     int32_t nprimes;           /* TN_COUNT_EXACT: residue primes incl. one check prime,
-                                  2..8 (0 = default: enough CRT primes for an
+                                  2..16 (0 = default: enough CRT primes for an
                                   upper bound on the count, at least two, plus
-                                  one check; at most 7 CRT primes, range 2^209) */
+                                  one check; at most 15 CRT primes, range 2^449;
+                                  counts above 2^512 are TN_EOVERFLOW) */
     const uint32_t* primes;    /* NULL = default primes (largest primes below 2^30) */
     int64_t slice_begin;       /* run slices [slice_begin, slice_end) only; slice s */
     int64_t slice_end;         /* fixes sliced index k to bit k of s; 0,0 = all */
@@ -335,8 +336,8 @@ typedef struct {
     float size_f32;
     int32_t size_is_neg_inf;
     uint64_t count_mod_2_64;
-    uint32_t residues[8];
-    uint32_t primes[8];
+    uint32_t residues[16];
+    uint32_t primes[16];
     int32_t nresidues;
     uint32_t count_limbs[16];
     int32_t count_nlimbs;

@@ -12,8 +12,10 @@ first.  A missing library raises ``LibraryMissing``: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -82,7 +84,7 @@ class tn_solve_opts(ctypes.Structure):
 class tn_result(ctypes.Structure):
     _fields_ = [("semiring", ctypes.c_int32), ("size_i32", ctypes.c_int32), ("size_f32", ctypes.c_float),
                 ("size_is_neg_inf", ctypes.c_int32), ("count_mod_2_64", ctypes.c_uint64),
-                ("residues", ctypes.c_uint32 * 8), ("primes", ctypes.c_uint32 * 8), ("nresidues", ctypes.c_int32),
+                ("residues", ctypes.c_uint32 * 16), ("primes", ctypes.c_uint32 * 16), ("nresidues", ctypes.c_int32),
                 ("count_limbs", ctypes.c_uint32 * 16), ("count_nlimbs", ctypes.c_int32),
                 ("z_mant", ctypes.c_double), ("z_exp2", ctypes.c_int64), ("log_z", ctypes.c_double),
                 ("z", ctypes.c_double), ("seconds", ctypes.c_double)]
@@ -153,6 +155,23 @@ SIGNATURES = [
 ]
 
 _lib = None
+# Contexts and servers still open at interpreter exit are released by an exit
+# handler (servers first), while torch's allocator they free into still works.
+# The handler is registered when the first context is made, after torch has
+# been imported, so that it runs before any exit handler torch registered.
+_live: "weakref.WeakSet" = weakref.WeakSet()
+_live_servers: "weakref.WeakSet" = weakref.WeakSet()
+_exit_hook = False
+
+
+def _release_all() -> None:
+    for s in list(_live_servers):
+        try:
+            s.close()
+        except Exception:
+            pass
+    for c in list(_live):
+        c.close()
 
 
 def lib():
@@ -432,15 +451,18 @@ class Context:
 
             torch.cuda.set_device(device)
             dev = device
+            # bound now: the callbacks must not look torch up at interpreter
+            # teardown, when module globals may already be gone
+            t_alloc, t_free = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
 
             def _alloc(nbytes, user, stream_ptr):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream_ptr or 0))
+                    return t_alloc(int(nbytes), dev, int(stream_ptr or 0))
                 except Exception:
                     return None
 
             def _free(ptr, nbytes, user, stream_ptr):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                t_free(int(ptr))
 
             a_cb, f_cb = ALLOC_FN(_alloc), FREE_FN(_free)
             self._cb = (a_cb, f_cb)
@@ -451,6 +473,11 @@ class Context:
         _check(lib().tn_ctx_create(int(device), ctypes.c_void_p(stream) if stream else None,
                                    ctypes.byref(alloc) if alloc is not None else None, ctypes.byref(h)))
         self.h = h
+        global _exit_hook
+        if not _exit_hook:
+            atexit.register(_release_all)
+            _exit_hook = True
+        _live.add(self)
 
     def set_profiling(self, on: bool = True) -> None:
         _check(lib().tn_ctx_set_profiling(self.h, 1 if on else 0))
@@ -553,10 +580,14 @@ class Context:
         _check(lib().tn_solve_single_config_max(self.h, net.h, plan.h, cfg, ctypes.byref(val)))
         return {"config": [int(cfg[v]) for v in range(net.nv)], "value": float(val.value)}
 
-    def __del__(self):
+    def close(self) -> None:
+        """Release the context (and the device memory it holds) now."""
         if getattr(self, "h", None) and _lib is not None:
             _lib.tn_ctx_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 class Server:
@@ -568,6 +599,7 @@ class Server:
         _check(lib().tn_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
         self.h = h
         self._keep = {}
+        _live_servers.add(self)
 
     def submit(self, net: Net, plan: Plan, semiring, beta: float = 0.0) -> int:
         o = solve_opts(semiring, beta)

@@ -3,6 +3,7 @@
 #include <atomic>
 #include <new>
 
+#include <chrono>
 #include "batch_host.h"
 #include "exec.h"
 

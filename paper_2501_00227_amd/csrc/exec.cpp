@@ -331,8 +331,9 @@ AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval
 
 // the largest primes below 2^30 (residues then admit one Montgomery
 // reduction per four products: 4 p^2 < p 2^32)
-static const uint32_t kDefaultPrimes[8] = {1073741789u, 1073741783u, 1073741741u, 1073741723u,
-                                           1073741719u, 1073741717u, 1073741689u, 1073741671u};
+static const uint32_t kDefaultPrimes[kMaxPrimes] = {
+    1073741789u, 1073741783u, 1073741741u, 1073741723u, 1073741719u, 1073741717u, 1073741689u, 1073741671u,
+    1073741663u, 1073741651u, 1073741621u, 1073741567u, 1073741561u, 1073741527u, 1073741503u, 1073741477u};
 
 static bool is_prime(uint32_t p) {
     if (p < 2) return false;
@@ -380,8 +381,10 @@ tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSp
         // default: enough CRT primes (each above 2^29.99) for the bound on the
         // count, plus one check prime
         int np = o.nprimes;
-        if (np <= 0) np = std::min(8, std::max(2, (int)std::ceil((count_bound_bits(net) + 2.0) / 29.0) + 1));
-        if (np < 2 || np > 8) return fail(TN_EINVAL, "nprimes must be in [2, 8] (CRT primes + one check prime)");
+        if (np <= 0)
+            np = std::min(kMaxPrimes, std::max(2, (int)std::ceil((count_bound_bits(net) + 2.0) / 29.0) + 1));
+        if (np < 2 || np > kMaxPrimes)
+            return fail(TN_EINVAL, "nprimes must be in [2, 16] (CRT primes + one check prime)");
         for (int k = 0; k < np; k++) {
             uint32_t p = o.primes ? o.primes[k] : kDefaultPrimes[k];
             if (p >= (1u << 30) || p < 3 || !is_prime(p)) return fail(TN_EINVAL, "residue moduli must be odd primes below 2^30");
@@ -525,72 +528,67 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
 // ------------------------------------------------------------------ solve --
 static int64_t node_entries(const Plan& p, int node) { return (int64_t)1 << p.order[node].size(); }
 
-tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res,
-                    std::vector<tn_result>* tensor, std::vector<unsigned char>* raw) {
-    auto t0 = std::chrono::steady_clock::now();
+// Check the plan against the network and the slice range against the plan.
+tn_status check_solve(const Net& net, const Plan& plan, const tn_solve_opts& o, int64_t& sb, int64_t& se) {
     if (plan.fingerprint != net.fingerprint || plan.nv != net.nv)
         return fail(TN_EINVAL, "plan was built for a different network");
-    if (!plan.open.empty() && !tensor) return fail(TN_EINVAL, "the plan has open vertices: use tn_solve_open");
-    std::vector<PassSpec> passes;
-    tn_status st = make_passes(net, o, passes);
-    if (st != TN_OK) return st;
-    hipStream_t s = ctx->stream;
-    const int nleaf = plan.nleaf();
-    const int nn = (int)plan.nodes.size();
-    int ns = (int)plan.sliced.size();
+    const int ns = (int)plan.sliced.size();
     if (ns > 62) return fail(TN_EINVAL, "too many sliced indices");
-    int64_t nslices = (int64_t)1 << ns;
-    int64_t sb = o.slice_begin, se = o.slice_end;
+    const int64_t nslices = (int64_t)1 << ns;
+    sb = o.slice_begin;
+    se = o.slice_end;
     if (sb == 0 && se == 0) se = nslices;
     if (sb < 0 || se > nslices || sb >= se) return fail(TN_EINVAL, "slice range out of bounds");
+    return TN_OK;
+}
 
-    DevProgram* dp = nullptr;
-    if (nleaf > 0) {
-        st = get_program(ctx, plan, dp);
-        if (st != TN_OK) return st;
-        for (auto& ps : passes)
-            if (plane_bytes(ps.dsr, 0) == 32 || plane_bytes(ps.dsr, 1) == 32) {
-                st = ensure_wide_perms(ctx, plan, *dp);
-                if (st != TN_OK) return st;
-            }
-    }
-    // one allocation: arena planes, split partials, meta, weights, accumulator
-    size_t need = 0;
-    int64_t E = std::max<int64_t>(plan.arena_entries, 64);
+// Offsets (bytes from the solve buffer's base) of the arena planes, split
+// partials, Z bookkeeping, weights and root accumulators of one solve.
+SolveLayout solve_layout(const Net& net, const Plan& plan, const std::vector<PassSpec>& passes, DevProgram* dp,
+                         bool tensor_root) {
+    SolveLayout L;
+    const int nn = (int)plan.nodes.size();
+    const int64_t E = std::max<int64_t>(plan.arena_entries, 64);
     int64_t Pe = 0;
-    for (auto& ps : passes) {
+    for (auto& ps : passes)
         if (dp) {
             node_launches(*dp, plan, ps.dsr);
             Pe = std::max(Pe, dp->part_entries[ps.dsr]);
         }
-    }
-    int pb0 = 0, pb1 = 0;
     for (auto& ps : passes) {
-        pb0 = std::max(pb0, plane_bytes(ps.dsr, 0));
-        pb1 = std::max(pb1, plane_bytes(ps.dsr, 1));
+        L.pb0 = std::max(L.pb0, plane_bytes(ps.dsr, 0));
+        L.pb1 = std::max(L.pb1, plane_bytes(ps.dsr, 1));
     }
-    size_t o_a0 = 0;
-    size_t o_a1 = align256(o_a0 + (size_t)E * pb0);
-    size_t o_p0 = align256(o_a1 + (size_t)E * pb1);
-    size_t o_p1 = align256(o_p0 + (size_t)Pe * pb0);
-    size_t o_meta = align256(o_p1 + (size_t)Pe * pb1);
-    size_t o_w = align256(o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
+    L.o_a0 = 0;
+    L.o_a1 = align256(L.o_a0 + (size_t)E * L.pb0);
+    L.o_p0 = align256(L.o_a1 + (size_t)E * L.pb1);
+    L.o_p1 = align256(L.o_p0 + (size_t)Pe * L.pb0);
+    L.o_meta = align256(L.o_p1 + (size_t)Pe * L.pb1);
+    L.o_w = align256(L.o_meta + sizeof(TensorMeta) * (size_t)std::max(nn, 1));
     // root entries: 2^|open| for plans with open vertices, else one
-    const int64_t nent = (nleaf > 0 && tensor) ? (int64_t)1 << plan.order[nn - 1].size() : 1;
-    const size_t acc_bytes = kAccSlotBytes * (size_t)nent * passes.size();
-    size_t o_acc = align256(o_w + sizeof(float) * std::max<size_t>(net.wdev.size(), 1));
-    need = align256(o_acc + acc_bytes);
-    unsigned char* base = (unsigned char*)dev_alloc(ctx, need);
-    if (!base) return fail(TN_ENOMEM, "device allocation of " + std::to_string(need) + " bytes failed");
-    Planes arena{base + o_a0, pb1 ? base + o_a1 : nullptr};
-    Planes part{base + o_p0, pb1 ? base + o_p1 : nullptr};
-    TensorMeta* meta = (TensorMeta*)(base + o_meta);
-    float* wdev = net.wdev.empty() ? nullptr : (float*)(base + o_w);
-    st = ensure_pinned(ctx, std::max<size_t>(acc_bytes, sizeof(float) * net.wdev.size()) + 64);
-    if (st != TN_OK) {
-        dev_free(ctx, base, need);
-        return st;
-    }
+    L.nent = (plan.nleaf() > 0 && tensor_root) ? (int64_t)1 << plan.order[nn - 1].size() : 1;
+    L.acc_bytes = kAccSlotBytes * (size_t)L.nent * passes.size();
+    L.o_acc = align256(L.o_w + sizeof(float) * std::max<size_t>(net.wdev.size(), 1));
+    L.need = align256(L.o_acc + L.acc_bytes);
+    return L;
+}
+
+// Every pass over slices [sb, se) on the context stream, in the solve buffer
+// at base (laid out by L); stage: host memory of at least
+// max(L.acc_bytes, weight bytes) for the weight upload and the result copy.
+// all receives the accumulators of every pass.
+tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o,
+                    const std::vector<PassSpec>& passes, DevProgram* dp, unsigned char* base, const SolveLayout& L,
+                    int64_t sb, int64_t se, void* stage, std::vector<unsigned char>& all) {
+    hipStream_t s = ctx->stream;
+    const int nleaf = plan.nleaf();
+    const int nn = (int)plan.nodes.size();
+    const int pb1 = L.pb1;
+    Planes arena{base + L.o_a0, pb1 ? base + L.o_a1 : nullptr};
+    Planes part{base + L.o_p0, pb1 ? base + L.o_p1 : nullptr};
+    TensorMeta* meta = (TensorMeta*)(base + L.o_meta);
+    float* wdev = net.wdev.empty() ? nullptr : (float*)(base + L.o_w);
+    const int64_t nent = L.nent;
     hipError_t herr = hipSuccess;
     const char* herr_at = "";
     auto chk = [&](hipError_t e, const char* at) {
@@ -601,8 +599,8 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
     };
     if (wdev) {
         chk(hipStreamSynchronize(s), "sync before weights");
-        std::memcpy(ctx->pinned, net.wdev.data(), sizeof(float) * net.wdev.size());
-        chk(hipMemcpyAsync(wdev, ctx->pinned, sizeof(float) * net.wdev.size(), hipMemcpyHostToDevice, s), "weights upload");
+        std::memcpy(stage, net.wdev.data(), sizeof(float) * net.wdev.size());
+        chk(hipMemcpyAsync(wdev, stage, sizeof(float) * net.wdev.size(), hipMemcpyHostToDevice, s), "weights upload");
         chk(hipStreamSynchronize(s), "weights sync");  // staging is reused for the results below
     }
     auto plane_at = [&](Planes pl, int dsr, int64_t off) {
@@ -615,7 +613,7 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
         const int dsr = passes[pi].dsr;
         AlgebraParams ap = algebra_params(dsr, passes[pi].prime, o.beta, passes[pi].xval);
         ap.fix_off = net.fix_off;
-        void* acc = base + o_acc + kAccSlotBytes * (size_t)nent * pi;
+        void* acc = base + L.o_acc + kAccSlotBytes * (size_t)nent * pi;
         const int eb = plane_bytes(dsr, 0) + plane_bytes(dsr, 1);
         const bool is_z = dsr == DSR_Z_F32 || dsr == DSR_Z_BF16;
         if (nleaf == 0) {
@@ -693,22 +691,62 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                 "root accumulate");
         }
     }
-    std::vector<unsigned char> all(acc_bytes);
+    all.assign(L.acc_bytes, 0);
     if (herr == hipSuccess) {
-        chk(hipMemcpyAsync(ctx->pinned, base + o_acc, acc_bytes, hipMemcpyDeviceToHost, s), "result copy");
+        chk(hipMemcpyAsync(stage, base + L.o_acc, L.acc_bytes, hipMemcpyDeviceToHost, s), "result copy");
         chk(hipStreamSynchronize(s), "result sync");
-        std::memcpy(all.data(), ctx->pinned, acc_bytes);
+        std::memcpy(all.data(), stage, L.acc_bytes);
     }
-    dev_free(ctx, base, need);
     if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error at ") + herr_at + ": " + hipGetErrorString(herr));
+    return TN_OK;
+}
+
+tn_status decode_root(const tn_solve_opts& o, const std::vector<PassSpec>& passes, const std::vector<unsigned char>& all,
+                      int64_t nent, int64_t addr, tn_result& r) {
+    std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
+    for (size_t k = 0; k < passes.size(); k++)
+        std::memcpy(accs[k].data(), all.data() + kAccSlotBytes * ((size_t)nent * k + (size_t)addr), 16);
+    return decode_result(o, passes, accs, r);
+}
+
+tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res,
+                    std::vector<tn_result>* tensor, std::vector<unsigned char>* raw) {
+    auto t0 = std::chrono::steady_clock::now();
+    int64_t sb = 0, se = 0;
+    tn_status st = check_solve(net, plan, o, sb, se);
+    if (st != TN_OK) return st;
+    if (!plan.open.empty() && !tensor) return fail(TN_EINVAL, "the plan has open vertices: use tn_solve_open");
+    std::vector<PassSpec> passes;
+    st = make_passes(net, o, passes);
+    if (st != TN_OK) return st;
+    const int nleaf = plan.nleaf();
+    const int nn = (int)plan.nodes.size();
+
+    DevProgram* dp = nullptr;
+    if (nleaf > 0) {
+        st = get_program(ctx, plan, dp);
+        if (st != TN_OK) return st;
+        for (auto& ps : passes)
+            if (plane_bytes(ps.dsr, 0) == 32 || plane_bytes(ps.dsr, 1) == 32) {
+                st = ensure_wide_perms(ctx, plan, *dp);
+                if (st != TN_OK) return st;
+            }
+    }
+    // one allocation: arena planes, split partials, meta, weights, accumulator
+    const SolveLayout L = solve_layout(net, plan, passes, dp, tensor != nullptr);
+    unsigned char* base = (unsigned char*)dev_alloc(ctx, L.need);
+    if (!base) return fail(TN_ENOMEM, "device allocation of " + std::to_string(L.need) + " bytes failed");
+    st = ensure_pinned(ctx, std::max<size_t>(L.acc_bytes, sizeof(float) * net.wdev.size()) + 64);
+    if (st != TN_OK) {
+        dev_free(ctx, base, L.need);
+        return st;
+    }
+    std::vector<unsigned char> all;
+    st = run_solve(ctx, net, plan, o, passes, dp, base, L, sb, se, ctx->pinned, all);
+    dev_free(ctx, base, L.need);
+    if (st != TN_OK) return st;
     if (raw) raw->assign(all.begin(), all.begin() + kAccSlotBytes);
-    // decode root entry addr (storage order of the root) from every pass
-    auto decode_entry = [&](int64_t addr, tn_result& r) {
-        std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
-        for (size_t k = 0; k < passes.size(); k++)
-            std::memcpy(accs[k].data(), all.data() + kAccSlotBytes * ((size_t)nent * k + (size_t)addr), 16);
-        return decode_result(o, passes, accs, r);
-    };
+    const int64_t nent = L.nent;
     const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (tensor) {
         // result entry bit q = open vertex plan.open[q]; find its bit in the root
@@ -723,14 +761,14 @@ tn_status solve_one(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
         for (int64_t e = 0; e < ((int64_t)1 << k); e++) {
             int64_t addr = 0;
             for (int q = 0; q < k; q++) addr |= ((e >> q) & 1) << pos[q];
-            tn_status s2 = decode_entry(addr, (*tensor)[e]);
+            tn_status s2 = decode_root(o, passes, all, nent, addr, (*tensor)[e]);
             if (s2 != TN_OK) return s2;
             (*tensor)[e].seconds = sec;
         }
         res = (*tensor)[0];
         return TN_OK;
     }
-    st = decode_entry(0, res);
+    st = decode_root(o, passes, all, nent, 0, res);
     res.seconds = sec;
     return st;
 }

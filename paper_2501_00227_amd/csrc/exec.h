@@ -116,6 +116,14 @@ struct ProfScope {
     ~ProfScope();
 };
 
+// Device-memory layout of one solve (bytes from the base of its buffer).
+struct SolveLayout {
+    size_t o_a0 = 0, o_a1 = 0, o_p0 = 0, o_p1 = 0, o_meta = 0, o_w = 0, o_acc = 0, need = 0, acc_bytes = 0;
+    int64_t nent = 1;  // root entries per pass
+    int pb0 = 0, pb1 = 0;
+};
+struct PassSpec;
+
 // tensor: for plans with open vertices, receives the 2^nopen results (entry
 // bits = open vertices in the plan's order); res then holds entry 0.
 // raw: receives the first pass's accumulator slot (kAccSlotBytes).
@@ -132,11 +140,24 @@ struct PassSpec {
 // the eight largest values (SizeMax(k), k <= 8) and the truncated polynomial
 // of the four highest orders (CountingMax(k), k <= 4; per-node executor).
 constexpr int kSemiringTop8 = 100;
+// residue primes of an exact count (CRT primes plus one check prime)
+constexpr int kMaxPrimes = 16;
 constexpr int kSemiringTPoly4 = 101;
 tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes);
 AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval = 1);
 // Decode the accumulators of all passes into the result struct.
 tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& passes,
                         const std::vector<std::vector<unsigned char>>& acc, tn_result& res);
+
+// The pieces of solve_one, for callers that bring their own device memory.
+// check_solve: plan/network match and the slice range [sb, se).
+tn_status check_solve(const Net& net, const Plan& plan, const tn_solve_opts& o, int64_t& sb, int64_t& se);
+SolveLayout solve_layout(const Net& net, const Plan& plan, const std::vector<PassSpec>& passes, DevProgram* dp,
+                         bool tensor_root);
+tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o,
+                    const std::vector<PassSpec>& passes, DevProgram* dp, unsigned char* base, const SolveLayout& L,
+                    int64_t sb, int64_t se, void* stage, std::vector<unsigned char>& all);
+tn_status decode_root(const tn_solve_opts& o, const std::vector<PassSpec>& passes, const std::vector<unsigned char>& all,
+                      int64_t nent, int64_t addr, tn_result& r);
 
 }  // namespace tn

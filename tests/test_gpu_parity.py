@@ -180,15 +180,15 @@ def test_integer_algebra_rejects_fractional_weights(ctx):
 def test_exact_count_range_and_overflow(ctx):
     """Counts are exact below the product of the CRT primes and flagged above
     it by the check prime.  By default the number of primes follows an upper
-    bound on the count (at most eight primes, seven of them for CRT, about
-    2^209); given primes set the range.  The empty graph on n vertices has
-    2^n independent sets."""
-    for n in (140, 160, 200):
+    bound on the count (at most sixteen primes, fifteen of them for CRT,
+    about 2^449); given primes set the range.  The empty graph on n vertices
+    has 2^n independent sets."""
+    for n in (140, 160, 200, 300, 440):
         net = tn.Net.from_graph(gg.empty(n))
         r = ctx.solve(net, tn.Plan.create(net), "count_exact")
         assert r["count"] == 2 ** n and r["count_mod_2_64"] == 0
         assert len(r["primes"]) >= (n + 29) // 30 + 1
-    net = tn.Net.from_graph(gg.empty(300))
+    net = tn.Net.from_graph(gg.empty(480))
     with pytest.raises(tn.TnError) as ei:
         ctx.solve(net, tn.Plan.create(net), "count_exact")
     assert ei.value.code == tn.TN_EOVERFLOW

@@ -221,3 +221,37 @@ def test_open_vertices_stay_to_the_root_and_are_never_sliced():
         with pytest.raises(tn.TnError) as ei:
             tn.Plan.create(net, open=bad)
         assert ei.value.code == tn.TN_EINVAL
+
+
+def test_wide_tree_reaches_2_30_entries_on_the_register_tiled_kernels():
+    """The explicit tree of the full-size parity tests (3 x 29 grid): its
+    largest tensors have 2^30 entries, every node's launch shape is one the
+    kernels accept, the 2^35-operation node runs on the register-tiled VALU
+    kernels (matrix cores for Z), and the oracle's plan follower accepts the
+    tree's index lists on a narrower grid built the same way."""
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from wide_trees import three_row_gemm_tree
+
+    g = gg.grid(3, 29)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.from_tree(net, *three_row_gemm_tree(29, 5, g.edges))
+    info = plan.info()
+    assert info["max_rank"] == 30 and info["nsliced"] == 0
+    for sr, kind in (("tropical_i32", "gemm_big"), ("tropical_f32", "gemm_big"), ("counting_tropical", "gemm_big"),
+                     ("count_exact", "gemm_big"), ("partition_f32", "gemm_mfma")):
+        rows = plan.gemm_shapes(sr)
+        assert all(r["valid"] for r in rows)
+        big = [r for r in rows if r["lb"] + r["li"] + r["lj"] + r["lk"] == 35]
+        assert len(big) == 1 and big[0]["kind"] == kind, (sr, big)
+        assert (big[0]["li"], big[0]["lj"], big[0]["lk"]) == (24, 6, 5)
+    # the same construction on a 3 x 9 grid: O3 follows the exported tree and
+    # agrees with brute force
+    g9 = gg.grid(3, 9)
+    p9 = tn.Plan.from_tree(tn.Net.from_graph(g9), *three_row_gemm_tree(9, 3, g9.edges))
+    assert p9.info()["max_rank"] == 10
+    tree = p9.export()
+    bf = oracle.brute_force(g9)
+    ct = oracle.follow_plan(g9, tree, "counting_tropical")
+    assert (ct["size"], ct["count"]) == (bf["size_max"], bf["count_max"])
+    assert oracle.follow_plan(g9, tree, "count")["count"] == bf["count_all"]

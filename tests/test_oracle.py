@@ -79,6 +79,20 @@ def test_square20_partition_function_matches_paper():
     assert abs(r["z"] - want) / want < 1e-14
 
 
+def test_square20_stored_values_match_paper():
+    """The stored exact count of the 20x20 grid (tests/golden/square20.json,
+    written by the oracle's elimination) rounds to the Float64 value printed
+    in Sec. 5.1, and its ln Z(0) is the log of that count."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "square20.json")))
+    want = GOLD["square20"]["partition_beta0"]["value"]
+    count = int(gold["count"])
+    assert abs(count - want) / want < 1e-15
+    assert count.bit_length() == 240  # about 2^239: beyond 7 CRT primes below 2^30
+    assert gold["log_z"]["0.0"] == pytest.approx(math.log(count), rel=1e-14)
+    # the checkerboards are the two largest sets of an even grid
+    assert gold["counting_tropical"] == [200.0, "2"]
+
+
 def _transfer_matrix_count(L):
     """Independent sets of the L x L grid by rows: a row is a mask with no two
     adjacent ones, consecutive rows must not share a one."""
@@ -375,6 +389,64 @@ def test_follow_plan_slicing_every_subset_agrees():
         t["sliced"] = list(range(k))
         r = oracle.follow_plan(g, t, "counting_tropical")
         assert r == ref
+
+
+def _oplus(sr, a, b):
+    """The algebra's (+) of two O3 results (max-plus, counting tropical, counts, Z)."""
+    if sr == "tropical":
+        return {"size": max(a["size"], b["size"])}
+    if sr == "counting_tropical":
+        if a["size"] != b["size"]:
+            return a if a["size"] > b["size"] else b
+        return {"size": a["size"], "count": a["count"] + b["count"]}
+    if sr == "count":
+        return {"count": a["count"] + b["count"]}
+    return {"z": a["z"] + b["z"]}
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_follow_plan_slice_ranges(seed):
+    """O3's slice-range path (slice s fixes sliced[k] to bit k of s, Sec. 4.2
+    slicing): every single slice equals the brute force conditioned on those
+    fixed values, and the (+) of the results over any partition of the slice
+    range into contiguous ranges equals the whole contraction."""
+    g = [gg.random_regular(12, 3, seed), gg.kings_subgraph(3, 0.9, seed), gg.gnp(11, 0.35, seed)][seed % 3]
+    if seed % 2:
+        g = g.with_weights(gg.dyadic_weights(g.nv, seed))
+    ns = 3 + seed % 2
+    tree = random_tree(g, 100 + seed, absorb=bool(seed % 4 >= 2), nsliced=ns)
+    sl = tree["sliced"]
+    beta = 0.6
+    whole = {sr: oracle.follow_plan(g, tree, sr, beta) for sr in SEMIRINGS}
+    bf = oracle.brute_force(g, [beta])
+    assert whole["count"]["count"] == bf["count_all"]
+    for s in range(1 << ns):
+        fixed = {sl[k]: (s >> k) & 1 for k in range(ns)}
+        ref = oracle.brute_force(g, [beta], fixed=fixed)
+        one = {sr: oracle.follow_plan(g, tree, sr, beta, slices=(s, s + 1)) for sr in SEMIRINGS}
+        assert one["count"]["count"] == ref["count_all"], (s, fixed)
+        if ref["count_all"] == 0:
+            assert one["tropical"]["size"] == float("-inf")
+            assert one["counting_tropical"] == {"size": float("-inf"), "count": 0}
+            assert one["partition"]["z"] == 0.0
+            continue
+        assert one["tropical"]["size"] == ref["size_max"]
+        assert (one["counting_tropical"]["size"], one["counting_tropical"]["count"]) == (ref["size_max"],
+                                                                                       ref["count_max"])
+        assert one["partition"]["z"] == pytest.approx(ref["z"][0], rel=1e-13)
+    rng = random.Random(seed)
+    for _ in range(3):
+        cuts = sorted(rng.sample(range(1, 1 << ns), rng.randint(1, (1 << ns) - 1)))
+        bounds = [0] + cuts + [1 << ns]
+        for sr in SEMIRINGS:
+            acc = None
+            for a, b in zip(bounds[:-1], bounds[1:]):
+                r = oracle.follow_plan(g, tree, sr, beta, slices=(a, b))
+                acc = r if acc is None else _oplus(sr, acc, r)
+            if sr == "partition":
+                assert acc["z"] == pytest.approx(whole[sr]["z"], rel=1e-13)
+            else:
+                assert {k: acc[k] for k in whole[sr]} == {k: whole[sr][k] for k in whole[sr]}, (sr, bounds)
 
 
 # ---------------------------------------------------- independence polynomial
