@@ -355,6 +355,25 @@ typedef struct {
 tn_status tn_solve(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts,
                    tn_result* out);
 
+/* The contraction of tn_solve (per-node launches, opts->executor 0 or 1;
+ * sliced plans too, opts->slice_begin/slice_end as there) for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Every device buffer of the call
+ * (the plan's program tables, the arena of live intermediates, split-K
+ * partials, partition-function bookkeeping, weights and root accumulators)
+ * lives in one fixed 256 MiB device array of the library, one copy per GPU,
+ * held until the process ends; the call makes no device or pinned-host
+ * allocation (host-side temporaries only) and no profiling records.  The
+ * array keeps the last call's contents; a call sets up everything it reads.
+ * Calls that overlap on one GPU (several contexts or threads on the same
+ * device) race on the array: the caller serialises them.  Same result as
+ * tn_solve with executor 1.  Errors as tn_solve, plus TN_ETOOBIG when the
+ * solve needs more than the array (tn_plan_peak_bytes plus the program
+ * tables), TN_EINVAL for plans with open vertices or executor 2, TN_EDEVICE
+ * when the array could not be located on the device. */
+tn_status tn_solve_noalloc(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts,
+                           tn_result* out);
+
 /* Many networks in one persistent launch: a device task table of
  * (job, node, tile) entries with dependency counters; workgroups pop ready
  * tiles until every job's root is done.  Tile shapes come from the

@@ -135,6 +135,7 @@ SIGNATURES = [
     ("tn_net_flat_complexity", ctypes.c_int, [_VP, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double)]),
     ("tn_solve_opts_default", None, [_P(tn_solve_opts)]),
     ("tn_solve", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(tn_result)]),
+    ("tn_solve_noalloc", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_batch", ctypes.c_int, [_VP, ctypes.c_int32, _P(_VP), _P(_VP), _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_polynomial", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_uint32), _P(ctypes.c_int32)]),
     ("tn_solve_max_k", ctypes.c_int,
@@ -509,6 +510,14 @@ class Context:
         o = solve_opts(semiring, beta, primes, slices, executor)
         r = tn_result()
         _check(lib().tn_solve(self.h, net.h, plan.h, ctypes.byref(o), ctypes.byref(r)))
+        return decode(r)
+
+    def solve_noalloc(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None) -> Dict:
+        """tn_solve_noalloc: as solve(..., executor="stream"), every device
+        buffer inside the library's fixed scratch array (no allocation)."""
+        o = solve_opts(semiring, beta, primes, slices, "stream")
+        r = tn_result()
+        _check(lib().tn_solve_noalloc(self.h, net.h, plan.h, ctypes.byref(o), ctypes.byref(r)))
         return decode(r)
 
     def solve_open(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None) -> List[Dict]:

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libtn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["net.cpp", "optimize.cpp", "plan.cpp", "exec.cpp", "batch.cpp", "polynomial.cpp", "config.cpp", "server.cpp", "abi.cpp",
-           "kernels.hip", "batch_kernels.hip"]
+           "kernels.hip", "batch_kernels.hip", "noalloc.hip"]
 HEADERS = ["common.h", "plan.h", "kernels.h", "kernels_dev.h", "exec.h", "batch.h", "batch_host.h"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

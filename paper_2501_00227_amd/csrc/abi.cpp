@@ -41,6 +41,7 @@ tn_status tn_ctx_create(int device, void* stream, const tn_allocator* alloc, tn_
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(TN_EDEVICE, "no HIP device available");
     if (device < 0 || device >= n) return fail(TN_EINVAL, "device id out of range");
     if (hipSetDevice(device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    noalloc_init_device(device);  // with the device current
     auto* c = new tn_ctx();
     c->device = device;
     if (alloc) {
@@ -461,6 +462,19 @@ tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_
         return st;
     }
     return solve_one(c, n->net, p->plan, *o, *out);
+    TN_GUARD_END
+}
+
+tn_status tn_solve_noalloc(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_opts* o, tn_result* out) {
+    TN_GUARD_BEGIN
+    if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");
+    if (!public_semiring(o->semiring)) return fail(TN_EINVAL, "unknown semiring");
+    if (o->executor != 0 && o->executor != 1) return fail(TN_EINVAL, "the scratch-free solve runs per-node launches only");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    auto t0 = std::chrono::steady_clock::now();
+    tn_status st = solve_noalloc(c, n->net, p->plan, *o, *out);
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
     TN_GUARD_END
 }
 

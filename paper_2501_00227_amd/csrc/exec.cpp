@@ -229,6 +229,50 @@ tn_status get_programs(tn_ctx* ctx, const std::vector<const Plan*>& plans) {
     return TN_OK;
 }
 
+// Offsets of one program's pieces in its device region.
+struct ProgramOffsets {
+    size_t o_leaf, o_spos, o_perm, o_tab, total;
+};
+
+static ProgramOffsets program_offsets(const ProgramHost& h) {
+    ProgramOffsets q;
+    q.o_leaf = 0;
+    q.o_spos = align256(sizeof(LeafDev) * h.leaves.size());
+    q.o_perm = align256(q.o_spos + sizeof(int) * h.spos.size());
+    q.o_tab = align256(q.o_perm + sizeof(PermParams) * h.perms.size());
+    q.total = align256(q.o_tab + sizeof(PermTables) * h.perms.size());
+    return q;
+}
+
+size_t program_bytes(const Plan& p) {
+    if (p.nleaf() == 0) return 0;
+    ProgramHost h;
+    build_program_host(p, h);
+    return program_offsets(h).total;
+}
+
+tn_status program_into(tn_ctx* ctx, const Plan& p, unsigned char* dev, DevProgram& dp) {
+    ProgramHost h;
+    build_program_host(p, h);
+    const ProgramOffsets q = program_offsets(h);
+    std::vector<unsigned char> img(q.o_tab, 0);  // pageable: the copy below waits for it
+    std::memcpy(img.data() + q.o_leaf, h.leaves.data(), sizeof(LeafDev) * h.leaves.size());
+    std::memcpy(img.data() + q.o_spos, h.spos.data(), sizeof(int) * h.spos.size());
+    if (!h.perms.empty()) std::memcpy(img.data() + q.o_perm, h.perms.data(), sizeof(PermParams) * h.perms.size());
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(dev, img.data(), q.o_tab, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (!h.perms.empty() && launch_expand_perms((const PermParams*)(dev + q.o_perm), (PermTables*)(dev + q.o_tab),
+                                                 (int)h.perms.size(), s) != hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(TN_EDEVICE, "upload of the plan program failed");
+    dp = std::move(h.dp);
+    dp.leaves = (LeafDev*)(dev + q.o_leaf);
+    dp.slice_pos = (int*)(dev + q.o_spos);
+    dp.perms = (PermTables*)(dev + q.o_tab);
+    dp.nperms = (int)h.perms.size();
+    return TN_OK;
+}
+
 tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out) {
     auto it = ctx->progs.find(p.uid);
     if (it == ctx->progs.end()) {

@@ -159,5 +159,20 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                     int64_t sb, int64_t se, void* stage, std::vector<unsigned char>& all);
 tn_status decode_root(const tn_solve_opts& o, const std::vector<PassSpec>& passes, const std::vector<unsigned char>& all,
                       int64_t nent, int64_t addr, tn_result& r);
+// Bytes of device memory the program of a plan takes (leaves, slice
+// positions, compact and expanded permute tables).
+size_t program_bytes(const Plan& p);
+// Write the program of a plan into dev (at least program_bytes(p) bytes, 256-
+// byte aligned) with copies from pageable host memory on the context stream
+// and expand its permute tables there; dp receives pointers into dev.  Waits
+// for the copies.  No allocation of device or pinned memory.
+tn_status program_into(tn_ctx* ctx, const Plan& p, unsigned char* dev, DevProgram& dp);
+
+// Scratch-free solve (noalloc.hip): the fixed device array is looked up once
+// per device at context creation; solve_noalloc runs tn_solve's per-node
+// contraction entirely inside it.
+void noalloc_init_device(int device);
+size_t noalloc_scratch_bytes();
+tn_status solve_noalloc(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o, tn_result& res);
 
 }  // namespace tn
