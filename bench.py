@@ -1,37 +1,46 @@
 """Benchmark of the hot path on one MI355X.
 
-Headline (``value``): one step = the three contractions of the seeded
-3-regular n=120 network (unit weights, TreeSA order), run as one persistent
-launch: max independent-set size (int32 max-plus), exact independent-set
-count (residues mod primes below 2^30, as many as a bound on the count
-needs (3 at n = 120), + a check prime, CRT) and the
-partition function at x = 1 (float32, per-tensor power-of-two exponents).
-Leaf data and plan tables are resident on the device before timing; planning
-is host-side and untimed.  value = 3 x 2^tc semiring ops / seconds per step,
-tc the plan's time complexity (Sec. 4.1).
+Headline (``value``): one step = the 240-vertex 3-regular network (seed 0,
+unit weights) contracted over all its slices in two algebras, tropical
+float32 (SizeMax) and counting tropical (CountingMax: int32 size, uint64
+count), on per-node launches.  The contraction order is TreeSA with
+sc_target 30 and slicing, so the largest intermediates hold 2^30 entries.
+value = 2 x 2^tc semiring ops / seconds per step (tc: the plan's total time
+complexity over all slices, Sec. 4.1).  Planning is host-side and untimed;
+the network's leaves are built on the device inside the step.
 
-Also reported in the same JSON line:
-  roofline              the dominant kernel of the timed step (HIP events on
-                        the context stream), algorithmic bytes per launch over
-                        its average launch duration, against HBM peak
-  largest_intermediate  one slice of the 240-vertex 3-regular network planned
-                        to a largest intermediate of 2^30 entries: the GEMM
-                        node with the most semiring ops and the largest permute,
-                        against the VALU peak of their algebra / HBM peak
-  batched / served      a stream of 3-regular jobs (n even in [40, 120],
-                        algebra uniform over tropical int32, counting tropical,
-                        float32 partition function): one-at-a-time, batched
-                        (persistent launches of 256 jobs) and served
-                        (Poisson arrivals at 0.5, 1, 2 and 4 x the one-at-a-time
-                        rate; p50/p99 latency submit -> result on the host)
-  cpu_baseline          the CPU oracle producing the step's three results
+In the same JSON line:
+  roofline       the kernel with the most device time in the timed steps
+                 (HIP events around every launch, on the context stream):
+                 semiring ops (or algorithmic bytes) per launch over its
+                 average launch time, against the engine peak of its algebra
+                 (VALU instruction rate / instructions per op, matrix cores)
+                 or HBM; plus the time-weighted fraction of every launch of
+                 the step against its own roofline min(P_engine, I x B)
+  per_node       the step's longest launches with their bound and fraction
+  tuned          the step with the committed launch-shape table and with the
+                 heuristic shapes only; the same for the 120-vertex step
+  k2_step        the 120-vertex network's three contractions (max-plus int32,
+                 exact count, Z at x = 1) as one persistent launch
+  k3             King's subgraph 24 x 24 at 0.8, weights k/2^14: tropical
+                 float32 and Z(beta) for beta in {0.5, 1, 2, 4} on matrix
+                 cores (float32 and bfloat16 inputs), error against the
+                 oracle's extended-precision values (tests/golden/k3.json)
+  batched        a job stream: plain, batched and served solves/s, p50/p99
+  widened rows   polynomial, spin glass, SingleConfigMax, SizeMax(8),
+                 CountingMax(4), conditioning
+  cpu_baseline   the oracle's plan follower on the same network and
+                 algebras (a finer-sliced plan, a bounded sample of slices,
+                 one process per host core)
 """
 from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import hashlib
 import json
 import math
+import multiprocessing as mp
 import os
 import sys
 import threading
@@ -40,118 +49,287 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_GBS = 8000.0
-# VALU peak from the published FP32 vector rate: 157.3 TFLOP/s = 78.6 T lane
-# FMAs / s, i.e. 78.6 T 32-bit lane instructions / s (256 CUs x 2.4 GHz x 128
-# lanes per clock).
-LANE_TOPS = 157.3 / 2.0
-# Fewest VALU instructions one semiring op can take on gfx950: max-plus is one
-# add per product plus one three-input max per two products; counting
-# tropical is a saturating add, a 64-bit product (one 32x32->64 multiply-add,
-# two 32-bit multiplies, one three-input add), two compares, four selects, a
-# 64-bit add and a max.
-INSTR_PER_OP = {"tropical_i32": 1.5, "tropical_f32": 1.5, "counting_tropical": 13.0}
+HBM = 8000e9  # bytes / s
+# VALU: the published FP32 vector rate, 157.3 TFLOP/s = 78.65 T lane FMAs / s,
+# taken as 78.65 T 32-bit lane instructions / s (256 CUs x 2.4 GHz x 128).
+LANE = 78.65e12
+# Fewest VALU instructions per semiring op on gfx950: max-plus one add per
+# product plus one three-input max per two products (1.5); counting tropical
+# a saturating add, a 64-bit product (one 32x32->64 multiply-add, two 32-bit
+# multiplies, one three-input add), two compares, four selects, a 64-bit add
+# and a max (13); counts mod p a 32x32->64 multiply-add per product plus one
+# Montgomery reduction (two multiplies, an add, a min) per four (2.5).
+ENGINE = {"tropical_i32": LANE / 1.5, "tropical_f32": LANE / 1.5, "counting_tropical": LANE / 13.0,
+          "count_exact": LANE / 2.5,
+          # the real algebra on matrix cores: one multiply-add per op;
+          # 157.3 TFLOP/s float32, 2.5 PFLOP/s bfloat16 inputs (dense)
+          "partition_f32": 157.3e12 / 2, "partition_bf16": 2.5e15 / 2}
+ENGINE_BOUND = {"partition_f32": "mfma", "partition_bf16": "mfma"}
 SR_NAME = {0: "tropical_i32", 1: "tropical_f32", 2: "counting_tropical", 3: "count_exact", 4: "partition_f32",
            5: "partition_bf16", -1: "mixed"}
-MFMA_F32_TFLOPS = 157.3
+TABLE = os.path.join(ROOT, "paper_2501_00227_amd", "mi355x_tiles.tune")
 
-STEP = (("tropical_i32", 0.0), ("count_exact", 0.0), ("partition_f32", 0.0))
+K5_PLAN = dict(method="treesa", ntrials=16, niters=50, rw_weight=0.5, sc_target=30, nslices=30, seed=0)
+K5_STEP = ("tropical_f32", "counting_tropical")
+K2_STEP = (("tropical_i32", 0.0), ("count_exact", 0.0), ("partition_f32", 0.0))
+CPU_PLAN = dict(method="treesa", ntrials=4, niters=5, sc_target=16, nslices=40, seed=0)
 
 
-def build_k2(seed):
+def build_k5(seed=0):
+    import graphgen as gg
+    import paper_2501_00227_amd as tn
+
+    g = gg.random_regular(240, 3, seed)
+    net = tn.Net.from_graph(g)
+    return g, net, tn.Plan.create(net, **K5_PLAN)
+
+
+def build_k2(seed=0):
     import graphgen as gg
     import paper_2501_00227_amd as tn
 
     g = gg.random_regular(120, 3, seed)
     net = tn.Net.from_graph(g)
-    plan = tn.Plan.create(net, method="treesa", ntrials=8, niters=20, seed=seed)
-    return g, net, plan
+    return g, net, tn.Plan.create(net, method="treesa", ntrials=8, niters=20, seed=seed)
 
 
-def run_step(ctx, net, plan, executor="persistent"):
-    """The three contractions of one step: one persistent launch, or (for
-    comparison) per-node stream launches, one contraction after the other."""
-    if executor == "stream":
-        return [ctx.solve(net, plan, s, beta=b, executor="stream") for s, b in STEP]
-    return ctx.solve_batch([net] * len(STEP), [plan] * len(STEP), [s for s, _ in STEP], [b for _, b in STEP])
+def build_k3(seed=0):
+    import graphgen as gg
+    import paper_2501_00227_amd as tn
+
+    g = gg.kings_subgraph(24, 0.8, seed)
+    g = g.with_weights(gg.dyadic_weights(g.nv, seed))
+    net = tn.Net.from_graph(g)
+    return g, net, tn.Plan.create(net, seed=seed)
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if the kernel is unchanged since."""
-    import hashlib
+def k5_step(ctx, net, plan):
+    return [ctx.solve(net, plan, sr, executor="stream") for sr in K5_STEP]
 
-    path = os.path.join(ROOT, "profiles", "k2_step_persistent_traffic.json")
+
+def k2_step(ctx, net, plan):
+    return ctx.solve_batch([net] * len(K2_STEP), [plan] * len(K2_STEP), [s for s, _ in K2_STEP],
+                           [b for _, b in K2_STEP])
+
+
+# ------------------------------------------------------------- roofline --
+def launch_roofline(r):
+    """One launch against its own roofline: GEMMs against min(P_engine,
+    I x B_HBM), I = ops / algorithmic bytes; every other kernel against HBM."""
+    t = r["ms"] * 1e-3
+    sr = SR_NAME.get(r["semiring"], "mixed")
+    if r["ops"] > 0 and sr in ENGINE and t > 0:
+        intensity = r["ops"] / r["alg_bytes"]
+        pe = ENGINE[sr]
+        roof = min(pe, intensity * HBM)
+        bound = ENGINE_BOUND.get(sr, "alu") if pe <= intensity * HBM else "hbm"
+        return {"bound": bound, "achieved_ops": r["ops"] / t, "roof_ops": roof, "frac": r["ops"] / t / roof}
+    gbs = r["alg_bytes"] / t if t > 0 else 0.0
+    return {"bound": "hbm", "achieved_bytes": gbs, "frac": gbs / HBM}
+
+
+def profile_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy's readings), if
+    the kernel sources are unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    srcs = ["paper_2501_00227_amd/csrc/batch_kernels.hip", "paper_2501_00227_amd/csrc/kernels_dev.h"]
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in srcs)).hexdigest()[:16]
-    if h != rec.get("kernel_source_sha256_16"):
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec["batch_kernel"]["traffic_bytes_per_launch"]
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("traffic_bytes_per_launch")
 
 
-def group(recs):
-    groups = {}
+def kernel_source_hash():
+    srcs = ["paper_2501_00227_amd/csrc/kernels.hip", "paper_2501_00227_amd/csrc/kernels_dev.h",
+            "paper_2501_00227_amd/csrc/batch_kernels.hip"]
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in srcs)).hexdigest()[:16]
+
+
+def dominant_roofline(recs):
+    """Roofline of the kernel with the most device time, and the
+    time-weighted fraction of all launches against their own rooflines."""
+    by = {}
+    tw_num = tw_den = 0.0
     for r in recs:
-        key = (r["kind"], r["semiring"])
-        g = groups.setdefault(key, {"ms": 0.0, "n": 0, "ops": 0.0, "bytes": 0.0})
-        g["ms"] += r["ms"]
-        g["n"] += 1
-        g["ops"] += r["ops"]
-        g["bytes"] += r["alg_bytes"]
-    return groups
+        b = by.setdefault(r["kernel"] or r["kind"], {"ms": 0.0, "n": 0, "ops": 0.0, "bytes": 0.0, "sr": set()})
+        b["ms"] += r["ms"]
+        b["n"] += 1
+        b["ops"] += r["ops"]
+        b["bytes"] += r["alg_bytes"]
+        b["sr"].add(SR_NAME.get(r["semiring"], "mixed"))
+        lr = launch_roofline(r)
+        tw_num += r["ms"] * lr["frac"]
+        tw_den += r["ms"]
+    name = max(by, key=lambda k: by[k]["ms"])
+    b = by[name]
+    avg_s = b["ms"] / b["n"] * 1e-3
+    sr = sorted(b["sr"])[0]
+    per_launch_ops, per_launch_bytes = b["ops"] / b["n"], b["bytes"] / b["n"]
+    intensity = per_launch_ops / per_launch_bytes if per_launch_bytes else 0.0
+    if per_launch_ops > 0 and sr in ENGINE and ENGINE[sr] <= intensity * HBM:
+        bound, achieved, peak, unit = ENGINE_BOUND.get(sr, "alu"), per_launch_ops / avg_s / 1e12, ENGINE[sr] / 1e12, \
+            "TOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", per_launch_bytes / avg_s / 1e9, HBM / 1e9, "GB/s"
+    total_ms = sum(x["ms"] for x in by.values())
+    kernels = sorted(((k, v["ms"], v["n"]) for k, v in by.items()), key=lambda x: -x[1])
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": profile_traffic(name), "kernel": name, "semiring": sr, "launches": b["n"],
+            "avg_launch_ms": b["ms"] / b["n"], "ops_per_launch": per_launch_ops,
+            "alg_bytes_per_launch": per_launch_bytes, "share_of_device_time": b["ms"] / total_ms,
+            "time_weighted_frac_all_launches": tw_num / tw_den,
+            "device_time_by_kernel_ms": {k: round(ms, 3) for k, ms, n in kernels[:12]}}
 
 
-def cpu_baseline(g, ops_per_step):
+def per_node_table(recs, top=16):
+    rows = []
+    for r in sorted(recs, key=lambda r: -r["ms"])[:top]:
+        lr = launch_roofline(r)
+        row = {"kernel": r["kernel"], "semiring": SR_NAME.get(r["semiring"], "mixed"), "node": r["node"],
+               "shape_log2": r["shape"], "ms": round(r["ms"], 4), "bound": lr["bound"], "frac": round(lr["frac"], 4)}
+        if "achieved_ops" in lr:
+            row["TOP_per_s"] = round(lr["achieved_ops"] / 1e12, 3)
+            row["roof_TOP_per_s"] = round(lr["roof_ops"] / 1e12, 3)
+        else:
+            row["GB_per_s"] = round(lr["achieved_bytes"] / 1e9, 1)
+        rows.append(row)
+    return rows
+
+
+# ------------------------------------------------------------ measurement --
+def timed_steps(step, steps, warmup, ctx, profile=True):
+    import torch
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.synchronize()
+    if profile:
+        ctx.profile(clear=True)
+        ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    recs = []
+    if profile:
+        recs = ctx.profile(clear=True)
+        ctx.set_profiling(False)
+    return dt, res, recs
+
+
+def tuned_vs_heuristic(ctx, step, reps=1):
+    import paper_2501_00227_amd as tn
+
+    out = {}
+    for mode in ("heuristic", "tuned"):
+        tn.tune_clear()
+        if mode == "tuned" and os.path.exists(TABLE):
+            tn.tune_load(TABLE)
+        step()
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        ctx.synchronize()
+        out[mode + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+    return out
+
+
+def k3_record(ctx):
+    """King's subgraph 24 x 24 at 0.8: tropical f32 and Z(beta) on matrix
+    cores against the oracle's stored values, with the Z nodes' rooflines."""
+    g, net, plan = build_k3(0)
+    gold = next(c for c in json.load(open(os.path.join(ROOT, "tests", "golden", "k3.json")))["cases"]
+                if c["seed"] == 0)
+    tc, sc, rwc = plan.complexity()
+    out = {"workload": "King's subgraph 24x24 p=0.8 seed 0 (%d vertices, %d edges), weights k/2^14" % (g.nv, g.ne),
+           "tc_log2": tc, "sc_log2": sc}
+    ctx.solve(net, plan, "tropical_f32")
+    t0 = time.perf_counter()
+    r = ctx.solve(net, plan, "tropical_f32")
+    out["tropical_f32"] = {"ms": (time.perf_counter() - t0) * 1e3, "size": r["size"],
+                           "exact": r["size"] == gold["size_max"]}
+    out["partition"] = []
+    for beta, want in gold["log_z"].items():
+        row = {"beta": float(beta)}
+        for sr in ("partition_f32", "partition_bf16"):
+            ctx.solve(net, plan, sr, beta=float(beta))
+            ctx.set_profiling(True)
+            t0 = time.perf_counter()
+            r = ctx.solve(net, plan, sr, beta=float(beta))
+            dt = time.perf_counter() - t0
+            recs = ctx.profile(clear=True)
+            ctx.set_profiling(False)
+            mf = [x for x in recs if x["kind"] == "gemm_mfma"]
+            key = sr.split("_")[1]
+            row[key] = {"ms": dt * 1e3, "log_z": r["log_z"], "abs_err_log_z": abs(r["log_z"] - want),
+                        "rel_err_z": abs(math.expm1(r["log_z"] - want)), "GOP_per_s": 2.0 ** tc / dt / 1e9}
+            if mf:
+                big = max(mf, key=lambda x: x["ops"])
+                lr = launch_roofline(big)
+                row[key]["largest_mfma_node"] = {"shape_log2": big["shape"], "ms": big["ms"],
+                                                 "TFLOP_per_s": 2 * big["ops"] / big["ms"] / 1e9,
+                                                 "bound": lr["bound"], "frac": lr["frac"]}
+                row[key]["mfma_share_of_device_time"] = sum(x["ms"] for x in mf) / sum(x["ms"] for x in recs)
+        out["partition"].append(row)
+    out["fp32_max_rel_err_z"] = max(x["f32"]["rel_err_z"] for x in out["partition"])
+    out["bf16_max_rel_err_z"] = max(x["bf16"]["rel_err_z"] for x in out["partition"])
+    return out
+
+
+# ---------------------------------------------------------- cpu baseline --
+def _o3_slice(args):
+    import graphgen as gg
     import oracle
 
+    tree, s = args
+    g = gg.random_regular(240, 3, 0)
     t0 = time.perf_counter()
-    oracle.eliminate(g, "tropical")
-    oracle.eliminate(g, "count")
-    oracle.eliminate(g, "partition", 0.0)
-    dt = time.perf_counter() - t0
-    return {"value": ops_per_step / dt / 1e9, "unit": "GOP/s", "cores": 1, "kind": "oracle",
-            "sample": "one full step (the same three results) by the oracle's variable elimination, "
-                      "single-threaded; work counted as the GPU plan's 3 x 2^tc semiring ops",
-            "seconds": dt}
+    a = oracle.follow_plan(g, tree, "tropical", slices=(s, s + 1))
+    b = oracle.follow_plan(g, tree, "counting_tropical", slices=(s, s + 1))
+    return time.perf_counter() - t0, a, b
 
 
-def largest_intermediate(ctx):
-    """One slice of the n=240 network planned to sc = 30, per-node timings."""
+def cpu_baseline():
+    """The oracle's plan follower (O3) on the headline network and algebras:
+    the same graph planned to 2^16-entry intermediates, one slice per host
+    core, tropical then counting tropical, all cores in parallel."""
     import graphgen as gg
     import paper_2501_00227_amd as tn
 
     g = gg.random_regular(240, 3, 0)
     net = tn.Net.from_graph(g)
-    plan = tn.Plan.create(net, method="treesa", ntrials=8, niters=10, sc_target=30, nslices=30, seed=0)
-    tc, sc, rwc = plan.complexity()
+    plan = tn.Plan.create(net, **CPU_PLAN)
     info = plan.info()
-    out = {"workload": "3-regular n=240 seed 0, TreeSA sc_target 30: slice 0 of %d" % (1 << info["nsliced"]),
-           "tc_log2_per_slice": tc - info["nsliced"], "sc_log2": sc, "nsliced": info["nsliced"]}
-    for sr in ("tropical_f32", "counting_tropical"):
-        ctx.solve(net, plan, sr, slices=(0, 1))  # warm
-        ctx.set_profiling(True)
-        t0 = time.perf_counter()
-        ctx.solve(net, plan, sr, slices=(0, 1))
-        dt = time.perf_counter() - t0
-        recs = ctx.profile()
-        ctx.set_profiling(False)
-        gem = max((r for r in recs if r["kind"].startswith("gemm")), key=lambda r: r["ops"])
-        perm = max((r for r in recs if r["kind"] == "permute"), key=lambda r: r["alg_bytes"])
-        peak = LANE_TOPS / INSTR_PER_OP[sr]
-        tops = gem["ops"] / gem["ms"] / 1e9
-        gbs = perm["alg_bytes"] / perm["ms"] / 1e6
-        out[sr] = {
-            "slice_seconds": dt,
-            "slice_GOPs": 2.0 ** (tc - info["nsliced"]) / dt / 1e9,
-            "largest_gemm": {"shape_log2_bikj": gem["shape"], "ms": gem["ms"], "achieved": tops, "unit": "TOP/s",
-                             "peak": peak, "bound": "alu", "frac": tops / peak},
-            "largest_permute": {"rank": perm["shape"][0], "ms": perm["ms"], "achieved": gbs, "unit": "GB/s",
-                                "peak": HBM_GBS, "bound": "hbm", "frac": gbs / HBM_GBS},
-        }
-    return out
+    tree = plan.export()
+    tc_slice = info["tc_log2"] - info["nsliced"]
+    cores = min(16, len(os.sched_getaffinity(0)))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_o3_slice, [(tree, s) for s in range(cores)])
+    wall = time.perf_counter() - t0
+    ops = cores * 2 * 2.0 ** tc_slice
+    return {"value": ops / wall / 1e9, "unit": "GOP/s", "cores": cores, "kind": "oracle",
+            "sample": "3-regular n=240 seed 0 (the headline network), tropical + counting tropical by the oracle's plan "
+                      "follower on a TreeSA plan sliced to 2^%d-entry intermediates (%d slices of 2^%.2f ops each): "
+                      "slices 0..%d, one process per core" % (info["max_rank"], 1 << info["nsliced"], tc_slice,
+                                                              cores - 1),
+            "seconds": wall, "per_slice_seconds_mean": sum(r[0] for r in res) / len(res),
+            "nproc": os.cpu_count(), "cpu_model": model}
 
 
 def independence_polynomial(ctx, net, plan, tc):
@@ -349,17 +527,39 @@ def job_stream(ctx, njobs, seed=0):
     return res
 
 
+def tune_workloads(ctx, path):
+    """Tune the launch shapes of the benchmark workloads' large nodes and
+    write the table (the committed table is made this way)."""
+    import paper_2501_00227_amd as tn
+
+    tn.tune_clear()
+    _, _, p5 = build_k5()
+    _, _, p2 = build_k2()
+    _, _, p3 = build_k3()
+    work = [(p5, "tropical_f32", 28), (p5, "counting_tropical", 28),
+            (p2, "tropical_i32", 16), (p2, "count_exact", 16), (p2, "partition_f32", 16),
+            (p3, "tropical_f32", 20), (p3, "partition_f32", 20), (p3, "partition_bf16", 20)]
+    for plan, sr, lo in work:
+        t0 = time.perf_counter()
+        n = ctx.tune_plan(plan, sr, min_log2_ops=lo, reps=2)
+        print(json.dumps({"tuned": sr, "min_log2_ops": lo, "keys": n, "seconds": time.perf_counter() - t0}),
+              flush=True)
+    n = tn.tune_save(path)
+    recs = tn.tune_records()
+    print(json.dumps({"table": path, "entries": n, "records": recs}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--jobs", type=int, default=2000, help="jobs in the batched / served stream")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline step only")
-    ap.add_argument("--executor", default="persistent", choices=["persistent", "stream"],
-                    help="persistent launch per step (default) or per-node stream launches")
+    ap.add_argument("--heuristic", action="store_true", help="heuristic launch shapes only (no tuning table)")
+    ap.add_argument("--tune-out", help="tune the workloads' large nodes, write the table to this path, exit")
     ap.add_argument("--widened", action="store_true",
                     help="only the polynomial, spin-glass, maximum-configuration, SizeMax(8), CountingMax(4) and "
                          "conditioning lines")
@@ -370,6 +570,10 @@ def main():
         print("bench.py measures one GPU only: several GPUs would share slices and jobs with one final "
               "(+)-reduction of a scalar root, which is not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    # the oracle runs first, in forked processes, before anything touches the GPU
+    cpu = None
+    if not (args.no_cpu or args.tune_out or args.widened or args.calibrate_copy):
+        cpu = cpu_baseline()
 
     import torch
     import paper_2501_00227_amd as tn
@@ -383,48 +587,34 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "copies": 3}))
         return
-    g, net, plan = build_k2(args.seed)
-    tc, sc, rwc = plan.complexity()
     ctx = tn.Context(0)
+    if args.tune_out:
+        tune_workloads(ctx, args.tune_out)
+        return
+    tn.tune_clear()
+    if not args.heuristic and os.path.exists(TABLE):
+        tn.tune_load(TABLE)
     if args.widened:
+        g, net, plan = build_k2(args.seed)
+        tc = plan.complexity()[0]
         print(json.dumps({"independence_polynomial": independence_polynomial(ctx, net, plan, tc),
                           "spin_glass_buckyball": buckyball(ctx), "single_config_max": single_config(ctx, net, plan),
                           "size_max_8_weighted": size_max_8_weighted(ctx, g, plan, tc),
                           "counting_max_4": counting_max_4(ctx, net, plan, tc),
                           "conditioned": conditioned_batch(ctx, g, plan)}))
         return
-    for _ in range(args.warmup):
-        run_step(ctx, net, plan, args.executor)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = run_step(ctx, net, plan, args.executor)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    ops_per_step = len(STEP) * 2.0 ** tc
-    value = ops_per_step / dt / 1e9
 
-    # profiled steps: HIP events around every launch on the context stream
-    ctx.set_profiling(True)
-    for _ in range(5):
-        run_step(ctx, net, plan, args.executor)
-    recs = ctx.profile(clear=True)
-    ctx.set_profiling(False)
-    groups = group(recs)
-    (kind, sr) = max(groups, key=lambda k: groups[k]["ms"])
-    grp = groups[(kind, sr)]
-    avg_ms = grp["ms"] / grp["n"]
-    achieved = grp["bytes"] / grp["n"] / (avg_ms * 1e-3) / 1e9
-    kname = "batch_kernel (persistent: %s)" % SR_NAME.get(sr, sr) if kind == "batch" else "%s/%s" % (kind, SR_NAME.get(sr, sr))
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s", "frac": achieved / HBM_GBS,
-            "traffic": measured_traffic() if kind == "batch" else None, "kernel": kname,
-            "avg_launch_ms": avg_ms, "launches": grp["n"],
-            "alg_bytes_per_launch": grp["bytes"] / grp["n"], "ops_per_launch": grp["ops"] / grp["n"],
-            "share_of_device_time": grp["ms"] / sum(x["ms"] for x in groups.values())}
-
+    g5, net5, plan5 = build_k5(args.seed)
+    info5 = plan5.info()
+    tc5, sc5, rwc5 = plan5.complexity()
+    step5 = lambda: k5_step(ctx, net5, plan5)  # noqa: E731
+    dt, res, recs = timed_steps(step5, args.steps, args.warmup, ctx)
+    ops_per_step = len(K5_STEP) * 2.0 ** tc5
+    per_step = len(recs) // max(args.steps, 1)
+    roof = dominant_roofline(recs)
     out = {
         "metric": "semiring GOP/s & % roofline at largest intermediate; batched solves/s + p50/p99",
-        "value": value,
+        "value": ops_per_step / dt / 1e9,
         "unit": "GOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -433,27 +623,46 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i32+u32+f32",
+        "dtype": "f32+i32+u64",
         "data": "synthetic",
-        "config": {"workload": "3-regular n=120 seed %d, unit weights: tropical int32 + exact count (3 + 1 "
-                               "primes below 2^30, CRT) + Z(x=1) fp32, %s" % (args.seed, "one persistent launch per step"
-                                                                   if args.executor == "persistent"
-                                                                   else "per-node stream launches"),
-                   "tc_log2": tc, "sc_log2": sc, "rwc_log2": rwc},
+        "config": {"workload": "K5: 3-regular n=240 seed %d, unit weights; tropical float32 + counting tropical "
+                               "(int32 size, uint64 count), each over all %d slices of a TreeSA plan with sc_target 30 "
+                               "(largest intermediate 2^%d entries), per-node launches" %
+                               (args.seed, 1 << info5["nsliced"], info5["max_rank"]),
+                   "tc_log2": tc5, "sc_log2": sc5, "rwc_log2": rwc5, "nsliced": info5["nsliced"],
+                   "launch_shapes": "heuristic" if args.heuristic or not os.path.exists(TABLE)
+                   else "tuned table " + os.path.relpath(TABLE, ROOT)},
         "roofline": roof,
-        "results": {"size_max": res[0]["size"], "count_all": str(res[1]["count"]), "log_z": res[2]["log_z"]},
+        "per_node": per_node_table(recs[-per_step:]),
+        "results": {"size_max": res[0]["size"], "counting_max": [res[1]["size"], res[1]["count_mod_2_64"]],
+                    "seconds_per_algebra": [r["seconds"] for r in res]},
     }
     if not args.quick:
-        out["largest_intermediate"] = largest_intermediate(ctx)
-        out["independence_polynomial"] = independence_polynomial(ctx, net, plan, tc)
+        g2, net2, plan2 = build_k2(args.seed)
+        tc2, sc2, rwc2 = plan2.complexity()
+        step2 = lambda: k2_step(ctx, net2, plan2)  # noqa: E731
+        if not args.heuristic and os.path.exists(TABLE):
+            out["tuned"] = {"table": os.path.relpath(TABLE, ROOT),
+                            "k5_step": tuned_vs_heuristic(ctx, step5),
+                            "k2_step": tuned_vs_heuristic(ctx, step2, reps=200)}
+        dt2, res2, recs2 = timed_steps(step2, 1000, 200, ctx)
+        out["k2_step"] = {"workload": "3-regular n=120 seed %d, unit weights: tropical int32 + exact count (3 + 1 "
+                                      "primes below 2^30, CRT) + Z(x=1) fp32, one persistent launch per step" % args.seed,
+                          "tc_log2": tc2, "sc_log2": sc2, "ms_per_step": dt2 * 1e3,
+                          "GOP_per_s": len(K2_STEP) * 2.0 ** tc2 / dt2 / 1e9, "roofline": dominant_roofline(recs2),
+                          "results": {"size_max": res2[0]["size"], "count_all": str(res2[1]["count"]),
+                                      "log_z": res2[2]["log_z"]}}
+        out["k3"] = k3_record(ctx)
+        g, net, plan = g2, net2, plan2
+        out["independence_polynomial"] = independence_polynomial(ctx, net, plan, tc2)
         out["spin_glass_buckyball"] = buckyball(ctx)
         out["single_config_max"] = single_config(ctx, net, plan)
-        out["size_max_8_weighted"] = size_max_8_weighted(ctx, g, plan, tc)
-        out["counting_max_4"] = counting_max_4(ctx, net, plan, tc)
+        out["size_max_8_weighted"] = size_max_8_weighted(ctx, g, plan, tc2)
+        out["counting_max_4"] = counting_max_4(ctx, net, plan, tc2)
         out["conditioned"] = conditioned_batch(ctx, g, plan)
         out["batched"] = job_stream(ctx, args.jobs, args.seed)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, ops_per_step)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -126,6 +126,8 @@ typedef struct {
     float ms;           /* measured duration */
     double alg_bytes;   /* algorithmic bytes of the launch */
     double ops;         /* semiring ops of the launch (GEMM) */
+    char kernel[64];    /* the kernel (template instance) launched, as profilers name it,
+                           e.g. "gemm_ct_big_kernel<7, 6>" */
 } tn_kernel_record;
 
 tn_status tn_ctx_set_profiling(tn_ctx* ctx, int enabled);
@@ -376,9 +378,10 @@ tn_status tn_solve_noalloc(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, 
 
 /* Many networks in one persistent launch: a device task table of
  * (job, node, tile) entries with dependency counters; workgroups pop ready
- * tiles until every job's root is done.  Tile shapes come from the
- * autotuner table keyed by each job's own shapes, so a job's result does not
- * depend on the other jobs in the batch.  n jobs; opts and out have n
+ * tiles until every job's root is done.  Launch shapes come from the tuning
+ * table (or the heuristic) keyed by each node's own shape (see the
+ * autotuner below), so a job's result does not depend on the other jobs in
+ * the batch.  n jobs; opts and out have n
  * entries.  Jobs must not be sliced.  Per-job failures are reported in
  * out[i].semiring = -1 and the call returns the first failure. */
 tn_status tn_solve_batch(tn_ctx* ctx, int32_t n, const tn_net* const* nets,
@@ -492,6 +495,56 @@ tn_status tn_solve_counting_max_k(tn_ctx* ctx, const tn_net* net, const tn_plan*
  * reproduces a node's value). */
 tn_status tn_solve_single_config_max(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, int32_t* config,
                                      float* value);
+
+/* ----------------------------------------------------------- autotuner --- */
+
+/* Launch shapes (kernel family, tile, K step, K splits) of the batched
+ * semiring GEMMs come from a process-wide table keyed by the node's own
+ * shape: device algebra, log2 batch / M / N / K and operand orders.  Keys not
+ * in the table use a fixed heuristic.  The key holds nothing but the node's
+ * shape, so a job runs the same launches alone and in any batch.
+ *
+ * tn_tune_plan times, for every inner node of the plan with at least
+ * 2^min_log2_ops semiring operations whose key is not yet in the table, each
+ * candidate shape the kernels accept on seeded operands of the node's size
+ * (best of reps launches, split reduction included) and stores the fastest.
+ * A candidate whose result differs from the heuristic shape's (any bit in
+ * the exact algebras, more than 1e-4 relative per entry for the real one,
+ * whose sums change order with the tile) is rejected.
+ * Each semiring tunes the device algebras it runs (TN_COUNT_EXACT: the mod-p
+ * kernels).  Device memory for the node's operands comes from the context's
+ * allocator.  *ntuned receives the number of keys added.  Plans run after
+ * the call use the new entries.  Errors: TN_EINVAL (NULL arguments, unknown
+ * semiring), TN_ENOMEM, TN_EDEVICE. */
+typedef struct {
+    int32_t dsr;             /* device algebra: 0 max-plus int32, 1 max-plus float32, 2 counting
+                                tropical, 3 counts mod p, 4 real float32, 5 real bfloat16 inputs */
+    int32_t lb, li, lj, lk;  /* log2 batch, M, N, K */
+    int32_t a_t, b_t;        /* operand orders: A [b][k][i], B [b][j][k] when set */
+    int32_t ncand;           /* candidate shapes tried */
+    int32_t nrejected;       /* candidates whose result differed */
+    float heuristic_ms;      /* the heuristic shape's time */
+    float best_ms;           /* the winner's time */
+    int32_t shape[10];       /* winner: mode (0 tiled, 1 thin, 2 long-K), log2 tile batch / M / N,
+                                log2 K step, rows / columns per thread, log2 K splits, matrix
+                                cores, 0 */
+} tn_tune_record;
+
+tn_status tn_tune_plan(tn_ctx* ctx, const tn_plan* plan, int32_t semiring, double min_log2_ops, int32_t reps,
+                       int32_t* ntuned);
+/* Write the table as text (one line per key); *nentries (NULL allowed)
+ * receives the entry count.  TN_EINVAL if the file cannot be written. */
+tn_status tn_tune_save(const char* path, int32_t* nentries);
+/* Merge a table file into the table.  Every line must be an entry the
+ * kernels accept for its key, else nothing of the file is taken
+ * (TN_EINVAL).  The file named by the environment variable TN_TUNE_FILE is
+ * loaded at the first tn_ctx_create of the process. */
+tn_status tn_tune_load(const char* path, int32_t* nentries);
+/* Empty the table (every node back on the heuristic) and the records. */
+void tn_tune_clear(void);
+/* Records of the keys tuned since the last clear: copies up to cap; *n
+ * receives the number available. */
+tn_status tn_tune_records(tn_tune_record* recs, int32_t cap, int32_t* n);
 
 /* -------------------------------------------------------------- server --- */
 

@@ -93,7 +93,7 @@ class tn_result(ctypes.Structure):
 class tn_kernel_record(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("node", ctypes.c_int32), ("semiring", ctypes.c_int32),
                 ("shape", ctypes.c_int32 * 4), ("ms", ctypes.c_float), ("alg_bytes", ctypes.c_double),
-                ("ops", ctypes.c_double)]
+                ("ops", ctypes.c_double), ("kernel", ctypes.c_char * 64)]
 
 
 class tn_task_record(ctypes.Structure):
@@ -105,6 +105,13 @@ class tn_server_stats_t(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("peak_admitted_bytes", ctypes.c_uint64),
                 ("peak_running", ctypes.c_int32)]
+
+
+class tn_tune_record(ctypes.Structure):
+    _fields_ = [("dsr", ctypes.c_int32), ("lb", ctypes.c_int32), ("li", ctypes.c_int32), ("lj", ctypes.c_int32),
+                ("lk", ctypes.c_int32), ("a_t", ctypes.c_int32), ("b_t", ctypes.c_int32), ("ncand", ctypes.c_int32),
+                ("nrejected", ctypes.c_int32), ("heuristic_ms", ctypes.c_float), ("best_ms", ctypes.c_float),
+                ("shape", ctypes.c_int32 * 10)]
 
 
 # (name, restype, argtypes) of every exported symbol of include/tn.h
@@ -147,6 +154,11 @@ SIGNATURES = [
     ("tn_solve_counting_max_k", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, c_int32_p,
                                                _P(ctypes.c_uint64)]),
     ("tn_solve_single_config_max", ctypes.c_int, [_VP, _VP, _VP, c_int32_p, _P(ctypes.c_float)]),
+    ("tn_tune_plan", ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, c_int32_p]),
+    ("tn_tune_save", ctypes.c_int, [ctypes.c_char_p, c_int32_p]),
+    ("tn_tune_load", ctypes.c_int, [ctypes.c_char_p, c_int32_p]),
+    ("tn_tune_clear", None, []),
+    ("tn_tune_records", ctypes.c_int, [_P(tn_tune_record), ctypes.c_int32, c_int32_p]),
     ("tn_server_create", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int32, _P(_VP)]),
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
     ("tn_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _P(tn_result), c_int32_p, _P(ctypes.c_double)]),
@@ -435,6 +447,44 @@ def decode(r: tn_result) -> Dict:
     return out
 
 
+# ---------------------------------------------------------------- autotuner --
+
+TUNE_SHAPE_FIELDS = ("mode", "tb", "ti", "tj", "tk", "rm", "rn", "lsplit", "mfma")
+
+
+def tune_save(path: str) -> int:
+    """Write the process's launch-shape table; returns its entry count."""
+    n = ctypes.c_int32()
+    _check(lib().tn_tune_save(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_load(path: str) -> int:
+    """Merge a table file into the process's table; returns the entry count."""
+    n = ctypes.c_int32()
+    _check(lib().tn_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_clear() -> None:
+    """Every node back on the heuristic launch shapes."""
+    lib().tn_tune_clear()
+
+
+def tune_records() -> List[Dict]:
+    """One dict per key tuned since the last clear."""
+    n = ctypes.c_int32()
+    _check(lib().tn_tune_records(None, 0, ctypes.byref(n)))
+    recs = (tn_tune_record * max(n.value, 1))()
+    _check(lib().tn_tune_records(recs, n.value, ctypes.byref(n)))
+    out = []
+    for r in recs[: n.value]:
+        d = {f: getattr(r, f) for f, _ in r._fields_ if f != "shape"}
+        d["shape"] = dict(zip(TUNE_SHAPE_FIELDS, list(r.shape)[:9]))
+        out.append(d)
+    return out
+
+
 # ------------------------------------------------------------------ context --
 
 class Context:
@@ -489,7 +539,8 @@ class Context:
         recs = (tn_kernel_record * max(n.value, 1))()
         _check(lib().tn_ctx_profile(self.h, recs, n.value, ctypes.byref(n), 1 if clear else 0))
         return [{"kind": KERNEL_KIND.get(r.kind, r.kind), "node": r.node, "semiring": r.semiring,
-                 "shape": list(r.shape), "ms": r.ms, "alg_bytes": r.alg_bytes, "ops": r.ops}
+                 "shape": list(r.shape), "ms": r.ms, "alg_bytes": r.alg_bytes, "ops": r.ops,
+                 "kernel": r.kernel.decode(errors="replace")}
                 for r in recs[: n.value]]
 
     def task_trace(self, clear: bool = True) -> np.ndarray:
@@ -511,6 +562,13 @@ class Context:
         r = tn_result()
         _check(lib().tn_solve(self.h, net.h, plan.h, ctypes.byref(o), ctypes.byref(r)))
         return decode(r)
+
+    def tune_plan(self, plan: Plan, semiring, min_log2_ops: float = 20.0, reps: int = 3) -> int:
+        """Tune the launch shapes of the plan's nodes with at least
+        2^min_log2_ops semiring ops (tn_tune_plan); returns the keys added."""
+        n = ctypes.c_int32()
+        _check(lib().tn_tune_plan(self.h, plan.h, _sr(semiring), float(min_log2_ops), int(reps), ctypes.byref(n)))
+        return n.value
 
     def solve_noalloc(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None) -> Dict:
         """tn_solve_noalloc: as solve(..., executor="stream"), every device

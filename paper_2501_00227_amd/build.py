@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["net.cpp", "optimize.cpp", "plan.cpp", "exec.cpp", "batch.cpp", "polynomial.cpp", "config.cpp", "server.cpp", "abi.cpp",
+SOURCES = ["net.cpp", "optimize.cpp", "plan.cpp", "exec.cpp", "batch.cpp", "polynomial.cpp", "config.cpp", "server.cpp", "tune.cpp", "abi.cpp",
            "kernels.hip", "batch_kernels.hip", "noalloc.hip"]
 HEADERS = ["common.h", "plan.h", "kernels.h", "kernels_dev.h", "exec.h", "batch.h", "batch_host.h"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

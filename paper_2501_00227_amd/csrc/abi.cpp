@@ -1,5 +1,6 @@
 // extern "C" entry points (include/tn.h).  No exception crosses this file:
 // every call is wrapped and reports a tn_status plus a thread-local message.
+#include <algorithm>
 #include <atomic>
 #include <new>
 
@@ -42,6 +43,10 @@ tn_status tn_ctx_create(int device, void* stream, const tn_allocator* alloc, tn_
     if (device < 0 || device >= n) return fail(TN_EINVAL, "device id out of range");
     if (hipSetDevice(device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
     noalloc_init_device(device);  // with the device current
+    {
+        tn_status ts = tune_env_load();  // TN_TUNE_FILE, once per process
+        if (ts != TN_OK) return ts;
+    }
     auto* c = new tn_ctx();
     c->device = device;
     if (alloc) {
@@ -462,6 +467,57 @@ tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_
         return st;
     }
     return solve_one(c, n->net, p->plan, *o, *out);
+    TN_GUARD_END
+}
+
+tn_status tn_tune_plan(tn_ctx* c, const tn_plan* p, int32_t semiring, double min_log2_ops, int32_t reps,
+                       int32_t* ntuned) {
+    TN_GUARD_BEGIN
+    if (!c || !p) return fail(TN_EINVAL, "NULL argument");
+    if (!public_semiring(semiring)) return fail(TN_EINVAL, "unknown semiring");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    tn_net dummy;  // make_passes reads only the network's weights and kind
+    dummy.net.integer_weights = true;
+    tn_solve_opts o;
+    tn_solve_opts_default(&o);
+    o.semiring = semiring;
+    o.nprimes = 2;
+    std::vector<PassSpec> passes;
+    tn_status st = make_passes(dummy.net, o, passes);
+    if (st != TN_OK) return st;
+    std::vector<int> dsrs;
+    for (auto& ps : passes)
+        if (std::find(dsrs.begin(), dsrs.end(), ps.dsr) == dsrs.end()) dsrs.push_back(ps.dsr);
+    return tune_plan(c, p->plan, dsrs, min_log2_ops, reps, ntuned);
+    TN_GUARD_END
+}
+
+tn_status tn_tune_save(const char* path, int32_t* nentries) {
+    TN_GUARD_BEGIN
+    if (!path) return fail(TN_EINVAL, "NULL path");
+    return tune_save(path, nentries);
+    TN_GUARD_END
+}
+
+tn_status tn_tune_load(const char* path, int32_t* nentries) {
+    TN_GUARD_BEGIN
+    if (!path) return fail(TN_EINVAL, "NULL path");
+    return tune_load(path, nentries);
+    TN_GUARD_END
+}
+
+void tn_tune_clear(void) {
+    try {
+        tune_clear();
+    } catch (...) {
+    }
+}
+
+tn_status tn_tune_records(tn_tune_record* recs, int32_t cap, int32_t* n) {
+    TN_GUARD_BEGIN
+    if (!n || cap < 0 || (cap > 0 && !recs)) return fail(TN_EINVAL, "bad arguments");
+    *n = tune_records(recs, cap);
+    return TN_OK;
     TN_GUARD_END
 }
 

@@ -130,7 +130,7 @@ struct JobPlan {
     int dsr;
     uint32_t prime, xval;
     DevProgram* dp;
-    const std::vector<NodeLaunch>* nl;
+    const LaunchSet* ls;
     int64_t E, Pe;
     size_t o_arena0, o_arena1, o_part0, o_part1, o_meta, o_acc;
 };
@@ -196,7 +196,7 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
     const int bn0 = 0;
     for (int t = 0; t < ninner; t++) {
         const NodeProg& np = p.prog[t];
-        const NodeLaunch& nl = (*jp.nl)[t];
+        const NodeLaunch& nl = jp.ls->nodes[t];
         BNode N{};
         N.g = nl.shape;
         N.ma = np.a;
@@ -207,7 +207,7 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
         N.c_off = np.dag_c_off;
         N.nout = (int64_t)1 << (N.g.lb + N.g.li + N.g.lj);
         N.reduce_per_block = N.nout < 1024 ? 1 : 0;
-        N.part_off = jp.dp->part_off_dag.at(jp.dsr)[t];  // a lookup: templates build concurrently
+        N.part_off = jp.ls->part_off_dag[t];
         for (int side = 0; side < 2; side++) {
             int child = side ? np.b : np.a;
             bool perm = side ? np.perm_b : np.perm_a;
@@ -397,9 +397,9 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             jp.prime = st.passes[p].prime;
             jp.xval = st.passes[p].xval;
             jp.dp = dp;
-            jp.nl = dp ? &node_launches(*dp, *it.plan, jp.dsr) : nullptr;
+            jp.ls = dp ? &node_launches(*dp, *it.plan, jp.dsr) : nullptr;
             jp.E = std::max<int64_t>(it.plan->arena_entries_dag, 64);
-            jp.Pe = dp ? dp->part_entries_dag[jp.dsr] : 0;
+            jp.Pe = dp ? jp.ls->part_entries_dag : 0;
             int pb0 = plane_bytes(jp.dsr, 0), pb1 = plane_bytes(jp.dsr, 1);
             jp.o_arena0 = data;
             data = a256(data + (size_t)jp.E * pb0);
@@ -653,7 +653,8 @@ tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
     int nwg = device_cu_count(ctx) * 2;
     if (e == hipSuccess) {
         int shape[4] = {0, 0, 0, 0};
-        ProfScope ps(ctx, TN_K_BATCH, -1, -1, shape, L.total_bytes, L.total_ops);
+        ProfScope ps(ctx, TN_K_BATCH, -1, -1, shape, L.total_bytes, L.total_ops,
+                     L.wide ? "batch_kernel<true>" : "batch_kernel<false>");
         e = launch_batch(L.d_tasks, L.d_qbegin, L.d_qcount, L.nq, L.d_jobs, L.d_nodes, L.d_subtree, L.d_counters,
                          L.d_ticket, nwg, L.d_trace, L.wide, s);
     }

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <thread>
 #include <unordered_set>
@@ -77,7 +78,8 @@ void pinned_release(tn_ctx* ctx, void* p) {
 }
 
 // ------------------------------------------------------------- profiling --
-ProfScope::ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops)
+ProfScope::ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops,
+                     const char* kernel)
     : ctx(c), on(c->profiling) {
     if (!on) return;
     auto get = [&]() {
@@ -99,6 +101,8 @@ ProfScope::ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], 
     pr.rec.ms = 0;
     pr.rec.alg_bytes = bytes;
     pr.rec.ops = ops;
+    std::memset(pr.rec.kernel, 0, sizeof pr.rec.kernel);
+    std::strncpy(pr.rec.kernel, kernel ? kernel : "", sizeof pr.rec.kernel - 1);
     (void)hipEventRecord(pr.start, ctx->stream);
 }
 
@@ -324,27 +328,24 @@ tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp) {
     return TN_OK;
 }
 
-const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr) {
-    const int key = dsr;
-    auto it = dp.launches.find(key);
-    if (it != dp.launches.end()) return it->second;
-    std::vector<NodeLaunch> v(p.prog.size());
-    int64_t part = 0, part_dag = 0;
-    std::vector<int64_t> part_off(p.prog.size(), 0);
+const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr) {
+    const int64_t key = (int64_t)(tune_generation() << 8) | dsr;
+    auto it = dp.launch_sets.find(key);
+    if (it != dp.launch_sets.end()) return it->second;
+    LaunchSet ls;
+    ls.nodes.resize(p.prog.size());
+    ls.part_off_dag.assign(p.prog.size(), 0);
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
-        v[t].shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
-        if (v[t].shape.lsplit > 0)
-            v[t].part_entries = (int64_t)1 << (v[t].shape.lsplit + np.lb + np.li + np.lj);
-        part = std::max(part, v[t].part_entries);
+        NodeLaunch& v = ls.nodes[t];
+        v.shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+        if (v.shape.lsplit > 0) v.part_entries = (int64_t)1 << (v.shape.lsplit + np.lb + np.li + np.lj);
+        ls.part_entries = std::max(ls.part_entries, v.part_entries);
         // concurrent nodes of the dependency-graph executor need separate partials
-        part_off[t] = part_dag;
-        part_dag += (v[t].part_entries + 63) & ~(int64_t)63;
+        ls.part_off_dag[t] = ls.part_entries_dag;
+        ls.part_entries_dag += (v.part_entries + 63) & ~(int64_t)63;
     }
-    dp.part_entries[key] = part;
-    dp.part_off_dag[key] = part_off;
-    dp.part_entries_dag[key] = part_dag;
-    return dp.launches.emplace(key, std::move(v)).first->second;
+    return dp.launch_sets.emplace(key, std::move(ls)).first->second;
 }
 
 // --------------------------------------------------------------- algebra --
@@ -595,10 +596,7 @@ SolveLayout solve_layout(const Net& net, const Plan& plan, const std::vector<Pas
     const int64_t E = std::max<int64_t>(plan.arena_entries, 64);
     int64_t Pe = 0;
     for (auto& ps : passes)
-        if (dp) {
-            node_launches(*dp, plan, ps.dsr);
-            Pe = std::max(Pe, dp->part_entries[ps.dsr]);
-        }
+        if (dp) Pe = std::max(Pe, node_launches(*dp, plan, ps.dsr).part_entries);
     for (auto& ps : passes) {
         L.pb0 = std::max(L.pb0, plane_bytes(ps.dsr, 0));
         L.pb1 = std::max(L.pb1, plane_bytes(ps.dsr, 1));
@@ -664,11 +662,13 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
             chk(launch_set_one(dsr, acc, ap, s), "set one");
             continue;
         }
-        const auto& launches = node_launches(*dp, plan, dsr);
+        const auto& launches = node_launches(*dp, plan, dsr).nodes;
         for (int64_t sl = sb; sl < se && herr == hipSuccess; sl++) {
             if (is_z) chk(launch_meta_init(meta, nn, s), "meta init");
             {
-                ProfScope ps(ctx, TN_K_LEAF, -1, o.semiring, nullptr, (double)plan.leaf_entries * eb, 0);
+                char kn[64];
+                snprintf(kn, sizeof kn, "leaf_kernel<%d>", dsr);
+                ProfScope ps(ctx, TN_K_LEAF, -1, o.semiring, nullptr, (double)plan.leaf_entries * eb, 0, kn);
                 chk(launch_leaves(dsr, dp->leaves, nleaf, wdev, dp->slice_pos, (unsigned long long)sl, arena, ap,
                                   meta, s),
                     "leaves");
@@ -692,7 +692,8 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                         int pbytes = plane_bytes(dsr, pl);
                         if (!pbytes) continue;
                         ProfScope ps(ctx, TN_K_PERMUTE, np.node, o.semiring, shp,
-                                     2.0 * (double)node_entries(plan, src_node) * pbytes, 0);
+                                     2.0 * (double)node_entries(plan, src_node) * pbytes, 0,
+                                     pbytes == 8 ? "permute_kernel<unsigned long long>" : "permute_kernel<unsigned int>");
                         if (pbytes == 32)  // 32-byte entries: 4-byte words, the three lowest bits in place
                             chk(launch_permute(4, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms_wide + slot,
                                                rank + 3, perm_tile_bits(rank + 3), s),
@@ -718,14 +719,17 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                                      : g.mfma             ? TN_K_GEMM_MFMA
                                      : g.rm == 8          ? TN_K_GEMM_BIG
                                                           : TN_K_GEMM;
+                    char kn[64];
                     ProfScope ps(ctx, kind, np.node, o.semiring, shp, ent * eb,
-                                 std::exp2((double)(g.lb + g.li + g.lj + g.lk)));
+                                 std::exp2((double)(g.lb + g.li + g.lj + g.lk)), gemm_kernel_name(dsr, g, kn, sizeof kn));
                     chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s), "gemm");
                 }
                 if (g.lsplit > 0) {
                     int64_t nout = (int64_t)1 << (g.lb + g.li + g.lj);
+                    char kn[64];
+                    snprintf(kn, sizeof kn, "split_reduce_kernel<%d>", dsr);
                     ProfScope ps(ctx, TN_K_ACCUM, np.node, o.semiring, shp,
-                                 (double)(nout << g.lsplit) * eb + (double)nout * eb, 0);
+                                 (double)(nout << g.lsplit) * eb + (double)nout * eb, 0, kn);
                     chk(launch_split_reduce(dsr, part, Cp, nout, g.lsplit, ap, meta, np.node, s), "split reduce");
                 }
             }

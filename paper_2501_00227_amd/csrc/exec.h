@@ -28,6 +28,15 @@ struct NodeLaunch {
     int64_t part_entries = 0;  // split-K partial buffer entries (0 if none)
 };
 
+// Launch shapes of every node of a plan for one device algebra, with the
+// split-K partial sizes they imply.
+struct LaunchSet {
+    std::vector<NodeLaunch> nodes;
+    int64_t part_entries = 0;              // largest node's partials (one node at a time)
+    std::vector<int64_t> part_off_dag;     // each split node's own partials (dependency-graph layout)
+    int64_t part_entries_dag = 0;          // sum over split nodes
+};
+
 // Device-resident constant data of one plan: leaf descriptors, permute
 // tables and slice positions.  Uploaded once per (context, plan).
 struct DevProgram {  // device tables of one plan (in a buffer that ctx->prog_bufs owns)
@@ -42,10 +51,9 @@ struct DevProgram {  // device tables of one plan (in a buffer that ctx->prog_bu
     size_t wide_bytes = 0;
     int* slice_pos = nullptr;     // nv entries: position in the sliced list or -1
     std::vector<int> perm_slot_a, perm_slot_b;  // per inner node, -1 if none
-    std::map<int, std::vector<NodeLaunch>> launches;  // per device algebra
-    std::map<int, int64_t> part_entries;              // per device algebra (largest node)
-    std::map<int, std::vector<int64_t>> part_off_dag; // per algebra: each split node's own partials
-    std::map<int, int64_t> part_entries_dag;          // per algebra: sum over split nodes
+    // launch shapes per (tuning-table generation, device algebra): a new
+    // table makes new entries, so references handed out stay valid
+    std::map<int64_t, LaunchSet> launch_sets;
 };
 
 struct PendingRec {
@@ -104,15 +112,27 @@ tn_status get_program(tn_ctx* ctx, const Plan& p, DevProgram*& out);
 tn_status get_programs(tn_ctx* ctx, const std::vector<const Plan*>& plans);
 // The widened permute tables of a program (no-op once built).
 tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp);
-// Tile shapes of every node for one device algebra (cached in dp).
-const std::vector<NodeLaunch>& node_launches(DevProgram& dp, const Plan& p, int dsr);
+// Launch shapes of every node for one device algebra under the current
+// tuning table (cached in dp; the reference stays valid while dp lives).
+const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr);
+// Tuning table (tune.cpp): generation (bumped by every change), tuning of a
+// plan's nodes, table file I/O.
+uint64_t tune_generation();
+tn_status tune_plan(tn_ctx* ctx, const Plan& plan, const std::vector<int>& dsrs, double min_log2_ops, int reps,
+                    int32_t* ntuned);
+tn_status tune_save(const char* path, int32_t* nentries);
+tn_status tune_load(const char* path, int32_t* nentries);
+void tune_clear();
+int32_t tune_records(tn_tune_record* recs, int32_t cap);
+tn_status tune_env_load();
 
 // Profiling bracket around one launch (no-op unless profiling is on).
 struct ProfScope {
     tn_ctx* ctx;
     PendingRec pr;
     bool on;
-    ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops);
+    ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops,
+              const char* kernel = "");
     ~ProfScope();
 };
 

@@ -137,8 +137,22 @@ hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, co
                             const long long* off, const int* lvl_off, const int* lvl_nodes, int nlevels, int* assign,
                             int* status, int nn, int nids, int nv, hipStream_t s);
 
-// Choose tile shape for a GEMM node (heuristic; the autotuner may override).
+// Launch shape of a GEMM node: the entry of the tuning table for this node
+// shape if there is one (tune.cpp), else the fixed heuristic.  Either way the
+// shape depends on the node alone, never on the other work of a launch.
 GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);
+GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);
 bool gemm_shape_valid(int dsr, const GemmShape& g);
+size_t gemm_lds_bytes(int dsr, const GemmShape& g);
+// Name of the kernel (template instance) a launch of shape g runs, as in
+// profiler listings, e.g. "gemm_ct_big_kernel<7, 6>".
+const char* gemm_kernel_name(int dsr, const GemmShape& g, char* buf, size_t cap);
+
+// Tuning helpers: seeded operand data for an algebra, and a device-side
+// count of the entries where two results differ (bit patterns for the exact
+// algebras, relative rtol for the real ones), added to *bad.
+hipError_t launch_fill_tune(int dsr, Planes p, int64_t n, unsigned long long seed, unsigned int prime, hipStream_t s);
+hipError_t launch_compare_tune(int dsr, Planes x, Planes y, int64_t n, float rtol, unsigned long long* bad,
+                               hipStream_t s);
 
 }  // namespace tn

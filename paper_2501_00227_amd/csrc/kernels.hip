@@ -13,6 +13,7 @@
 // slice accumulation (Sec. 4.2 slicing).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -273,7 +274,7 @@ static long long tiled_lds_bytes(int dsr, int tb, int ti, int tj, int tk) {
     return (1ll << (tb + tk)) * (pad_dim(1 << ti) + pad_dim(1 << tj)) * lds_elem_bytes(dsr);
 }
 
-GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
+GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
     GemmShape g{};
     g.lb = lb;
     g.li = li;
@@ -836,5 +837,65 @@ hipError_t launch_set_one(int dsr, void* acc, const AlgebraParams& ap, hipStream
 }
 
 int accumulator_bytes(int) { return 16; }
+
+// ------------------------------------------------------ tuning helpers --
+// Seeded operand data for timing and checking candidate launch shapes: a
+// SplitMix64-style hash of (seed, index) mapped into each algebra's values
+// (small sizes, full 64-bit counts, residues below p, positive reals).
+__device__ inline u64 mix64(u64 z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void fill_tune_kernel(int dsr, Planes p, i64 n, u64 seed, unsigned int prime) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        const u64 h = mix64(seed ^ mix64((u64)i));
+        switch (dsr) {
+        case DSR_TROP_I32: ((int*)p.p0)[i] = (int)(h & 15); break;
+        case DSR_TROP_F32: ((float*)p.p0)[i] = (float)(h & 255) * 0.0625f; break;
+        case DSR_CTROP:
+            ((int*)p.p0)[i] = (int)(h & 3);
+            ((u64*)p.p1)[i] = mix64(h);
+            break;
+        case DSR_MODP: ((unsigned int*)p.p0)[i] = (unsigned int)((h >> 16) % prime); break;
+        default: ((float*)p.p0)[i] = 0.5f + (float)(h & 0xffff) * (0.5f / 65536.0f); break;
+        }
+    }
+}
+
+hipError_t launch_fill_tune(int dsr, Planes p, i64 n, u64 seed, unsigned int prime, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const i64 blocks = std::min<i64>((n + 255) / 256, 8192);
+    fill_tune_kernel<<<(unsigned)blocks, 256, 0, s>>>(dsr, p, n, seed, prime);
+    return hipGetLastError();
+}
+
+// Entries of x and y that differ: bit patterns for the exact algebras, and
+// more than rtol relative for the real ones.
+__global__ void compare_tune_kernel(int dsr, Planes x, Planes y, i64 n, float rtol, unsigned long long* bad) {
+    unsigned long long local = 0;
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        bool diff;
+        if (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) {
+            const float a = ((const float*)x.p0)[i], b = ((const float*)y.p0)[i];
+            diff = !(fabsf(a - b) <= rtol * fmaxf(fabsf(a), fabsf(b)));
+        } else {
+            diff = ((const unsigned int*)x.p0)[i] != ((const unsigned int*)y.p0)[i];
+            if (dsr == DSR_CTROP) diff = diff || ((const u64*)x.p1)[i] != ((const u64*)y.p1)[i];
+        }
+        local += diff ? 1 : 0;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+hipError_t launch_compare_tune(int dsr, Planes x, Planes y, i64 n, float rtol, unsigned long long* bad,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const i64 blocks = std::min<i64>((n + 255) / 256, 8192);
+    compare_tune_kernel<<<(unsigned)blocks, 256, 0, s>>>(dsr, x, y, n, rtol, bad);
+    return hipGetLastError();
+}
 
 }  // namespace tn

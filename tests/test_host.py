@@ -255,3 +255,57 @@ def test_wide_tree_reaches_2_30_entries_on_the_register_tiled_kernels():
     ct = oracle.follow_plan(g9, tree, "counting_tropical")
     assert (ct["size"], ct["count"]) == (bf["size_max"], bf["count_max"])
     assert oracle.follow_plan(g9, tree, "count")["count"] == bf["count_all"]
+
+
+def test_tuning_table_file_overrides_the_heuristic(tmp_path):
+    """A table entry (tn_tune_load) replaces the heuristic launch shape of
+    exactly its node shape; entries the kernels do not accept are refused
+    with nothing of the file taken; save / clear / load round-trip."""
+    tn.tune_clear()
+    net = tn.Net.from_graph(gg.random_regular(120, 3, 0))
+    plan = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=0)
+    rows = plan.gemm_shapes("tropical_f32")
+    rows_i32 = plan.gemm_shapes("tropical_i32")
+    big = [r for r in rows if r["kind"] == "gemm_big" and r["tk"] >= 2]
+    assert big, "the n=120 plan has a register-tiled node"
+    r0 = big[0]
+    key = (1, r0["lb"], r0["li"], r0["lj"], r0["lk"], r0["a_t"], r0["b_t"])
+    entry = "%d %d %d %d %d %d %d : 0 0 %d %d %d 8 8 0 0\n" % (key + (r0["ti"], r0["tj"], r0["tk"] - 1))
+    path = tmp_path / "tiles.tune"
+    path.write_text("# comment\n" + entry)
+    assert tn.tune_load(str(path)) == 1
+    same = lambda r: (1, r["lb"], r["li"], r["lj"], r["lk"], r["a_t"], r["b_t"]) == key
+    for r in plan.gemm_shapes("tropical_f32"):
+        want_tk = r0["tk"] - 1 if same(r) else next(x for x in rows if x["node"] == r["node"])["tk"]
+        assert r["tk"] == want_tk and r["valid"] == 1
+    # the other algebras keep the heuristic
+    assert plan.gemm_shapes("tropical_i32") == rows_i32
+    out = tmp_path / "saved.tune"
+    assert tn.tune_save(str(out)) == 1
+    assert entry.split(":")[1].split() == out.read_text().splitlines()[1].split(":")[1].split()
+    # unusable entries: a tile larger than the node, a K step beyond K, garbage
+    for bad in ("%d %d %d %d %d %d %d : 0 0 %d %d %d 8 8 0 0\n" % (key + (8, 8, 5)),
+                "%d %d %d %d %d %d %d : 0 0 %d %d %d 8 8 0 0\n" % (key + (r0["ti"], r0["tj"], r0["lk"] + 1)),
+                "1 2 3 : 0\n"):
+        p2 = tmp_path / "bad.tune"
+        p2.write_text(entry + bad)
+        tn.tune_clear()
+        with pytest.raises(tn.TnError) as ei:
+            tn.tune_load(str(p2))
+        assert ei.value.code == tn.TN_EINVAL
+        assert plan.gemm_shapes("tropical_f32") == rows  # nothing taken
+    tn.tune_clear()
+    assert plan.gemm_shapes("tropical_f32") == rows
+    assert tn.tune_load(str(out)) == 1
+    tn.tune_clear()
+
+
+def test_committed_tuning_table_loads():
+    """The table the benchmark uses (written by bench.py --tune-out on an
+    MI355X) holds only entries the kernels accept."""
+    path = os.path.join(ROOT, "paper_2501_00227_amd", "mi355x_tiles.tune")
+    tn.tune_clear()
+    n = tn.tune_load(path)
+    lines = [l for l in open(path) if l.strip() and not l.startswith("#")]
+    assert n == len(lines) > 50
+    tn.tune_clear()
