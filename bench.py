@@ -563,6 +563,8 @@ def main():
     ap.add_argument("--widened", action="store_true",
                     help="only the polynomial, spin-glass, maximum-configuration, SizeMax(8), CountingMax(4) and "
                          "conditioning lines")
+    ap.add_argument("--k3", action="store_true", help="only the King's-subgraph partition-function line")
+    ap.add_argument("--k2", action="store_true", help="only the 120-vertex persistent step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (for scaling hardware byte counters) and exit")
     args = ap.parse_args()
@@ -572,7 +574,7 @@ def main():
         sys.exit(2)
     # the oracle runs first, in forked processes, before anything touches the GPU
     cpu = None
-    if not (args.no_cpu or args.tune_out or args.widened or args.calibrate_copy):
+    if not (args.no_cpu or args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2):
         cpu = cpu_baseline()
 
     import torch
@@ -594,6 +596,16 @@ def main():
     tn.tune_clear()
     if not args.heuristic and os.path.exists(TABLE):
         tn.tune_load(TABLE)
+    if args.k3:
+        print(json.dumps({"k3": k3_record(ctx)}))
+        return
+    if args.k2:
+        g2, net2, plan2 = build_k2(args.seed)
+        tc2 = plan2.complexity()[0]
+        dt2, res2, recs2 = timed_steps(lambda: k2_step(ctx, net2, plan2), args.steps, args.warmup, ctx)
+        print(json.dumps({"k2_step": {"ms_per_step": dt2 * 1e3, "GOP_per_s": len(K2_STEP) * 2.0 ** tc2 / dt2 / 1e9,
+                                      "roofline": dominant_roofline(recs2)}}))
+        return
     if args.widened:
         g, net, plan = build_k2(args.seed)
         tc = plan.complexity()[0]

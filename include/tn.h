@@ -53,6 +53,7 @@ typedef enum {
 /* Element algebra of the contraction (Sec. 5 property table).
  *   TN_TROPICAL_I32      SizeMax     max-plus over int32, -inf = INT32_MIN with
  *                                    saturating add; integer weights only
+ *                                    (|w| <= 65536 and sum |w| <= 2^28)
  *   TN_TROPICAL_F32      SizeMax     max-plus over float32, -inf = -INFINITY
  *   TN_COUNTING_TROPICAL CountingMax (int32 size, uint64 count): larger size wins,
  *                                    equal sizes add counts; the count is exact

@@ -977,18 +977,28 @@ __device__ inline bool gemm_tile_big_any(const GemmArgs& g, u64 tile, unsigned c
 // in LDS (counts first for 8-byte alignment), each thread owning 8 x 4 (or
 // 4 x 8) outputs in groups of four rows / columns as above.  Tiles 128 x 64,
 // 64 x 128, 256 x 32, 32 x 256.
+//
+// Each K step runs in two passes.  The first takes, for every output, the
+// largest size a + b over the step's k (plain max-plus: two adds and one
+// three-input max per two k); outputs whose size grows drop the counts they
+// had.  The second adds the count products of exactly the terms whose size
+// equals the output's size, through a select on the B count and one
+// 64-bit multiply-add.  Sizes are staged clamped at -2^30, so sums of two
+// never overflow int32 (-inf = INT32_MIN outside); an output whose size stays
+// below -2^29 is -inf (count 0) when stored.  Real sizes satisfy |s| <= 2^28.
 __host__ __device__ constexpr bool ct_tile_shape(int ti, int tj) {
     return (ti == 7 && tj == 6) || (ti == 6 && tj == 7) || (ti == 8 && tj == 5) || (ti == 5 && tj == 8);
 }
 
-// acc (+)= (an + bn, ac * bc): the larger size wins, equal sizes add counts
-__device__ inline void ct_mac(int& n, u64& c, int an, u64 ac, int bn, u64 bc) {
-    const int s = __builtin_elementwise_add_sat(an, bn);
-    const u64 p = ac * bc;
-    const u64 keep = n >= s ? c : 0ull;
-    const u64 add = s >= n ? p : 0ull;
-    c = keep + add;
-    n = max(n, s);
+constexpr int kCtNegInf = -(1 << 30);        // staged -inf
+constexpr int kCtNegInfBelow = -(1 << 29);   // results below this are -inf
+
+// acc += a * (bhi : blo) mod 2^64, with one 32 x 32 -> 64 multiply-add for
+// the low words and two 32-bit multiplies for the cross terms
+__device__ inline u64 mad_u64_mod(u64 acc, unsigned alo, unsigned ahi, unsigned blo, unsigned bhi) {
+    const unsigned cross = alo * bhi + ahi * blo;
+    const u64 t = (u64)alo * blo + acc;
+    return t + ((u64)cross << 32);
 }
 
 template <int LTM, int LTN>
@@ -1028,7 +1038,7 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                 k = idx >> LTM;
                 addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
             }
-            An[k * TMP + i] = ((const int*)g.A.p0)[addr];
+            An[k * TMP + i] = max(((const int*)g.A.p0)[addr], kCtNegInf);
             Ac[k * TMP + i] = ((const u64*)g.A.p1)[addr];
         }
         for (int idx = tid; idx < nb; idx += 256) {
@@ -1043,16 +1053,55 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                 j = idx >> g.tk;
                 addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
             }
-            Bn[k * TNP + j] = ((const int*)g.B.p0)[addr];
+            Bn[k * TNP + j] = max(((const int*)g.B.p0)[addr], kCtNegInf);
             Bc[k * TNP + j] = ((const u64*)g.B.p1)[addr];
         }
         __syncthreads();
-        for (int k = 0; k < TK; k++) {
+        // pass 1: the step's largest size per output
+        int m[RMT][RNT];
+#pragma unroll
+        for (int r = 0; r < RMT; r++)
+#pragma unroll
+            for (int c = 0; c < RNT; c++) m[r][c] = accn[r][c];
+        auto load_sizes = [&](int k, int* an, int* bn) {
+#pragma unroll
+            for (int h = 0; h < RMT / 4; h++) lds_load4(An + k * TMP + h * (TM / 2) + ty * 4, an + 4 * h);
+#pragma unroll
+            for (int h = 0; h < RNT / 4; h++) lds_load4(Bn + k * TNP + h * (TN / 2) + tx * 4, bn + 4 * h);
+        };
+        int k = 0;
+        for (; k + 1 < TK; k += 2) {
+            int a0[RMT], a1[RMT], b0[RNT], b1[RNT];
+            load_sizes(k, a0, b0);
+            load_sizes(k + 1, a1, b1);
+#pragma unroll
+            for (int r = 0; r < RMT; r++)
+#pragma unroll
+                for (int c = 0; c < RNT; c++) m[r][c] = max(m[r][c], max(a0[r] + b0[c], a1[r] + b1[c]));
+        }
+        if (k < TK) {
+            int a0[RMT], b0[RNT];
+            load_sizes(k, a0, b0);
+#pragma unroll
+            for (int r = 0; r < RMT; r++)
+#pragma unroll
+                for (int c = 0; c < RNT; c++) m[r][c] = max(m[r][c], a0[r] + b0[c]);
+        }
+        // outputs whose size grew drop the counts of the smaller size
+#pragma unroll
+        for (int r = 0; r < RMT; r++)
+#pragma unroll
+            for (int c = 0; c < RNT; c++) {
+                accc[r][c] = m[r][c] > accn[r][c] ? 0ull : accc[r][c];
+                accn[r][c] = m[r][c];
+            }
+        // pass 2: count products of the terms at the output's size
+        for (k = 0; k < TK; k++) {
             int an[RMT], bn[RNT];
             u64 ac[RMT], bc[RNT];
+            load_sizes(k, an, bn);
 #pragma unroll
             for (int h = 0; h < RMT / 4; h++) {
-                lds_load4(An + k * TMP + h * (TM / 2) + ty * 4, an + 4 * h);
                 const uint4 u0 = *(const uint4*)(Ac + k * TMP + h * (TM / 2) + ty * 4);
                 const uint4 u1 = *(const uint4*)(Ac + k * TMP + h * (TM / 2) + ty * 4 + 2);
                 ac[4 * h + 0] = ((u64)u0.y << 32) | u0.x;
@@ -1062,7 +1111,6 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
             }
 #pragma unroll
             for (int h = 0; h < RNT / 4; h++) {
-                lds_load4(Bn + k * TNP + h * (TN / 2) + tx * 4, bn + 4 * h);
                 const uint4 u0 = *(const uint4*)(Bc + k * TNP + h * (TN / 2) + tx * 4);
                 const uint4 u1 = *(const uint4*)(Bc + k * TNP + h * (TN / 2) + tx * 4 + 2);
                 bc[4 * h + 0] = ((u64)u0.y << 32) | u0.x;
@@ -1073,7 +1121,11 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
 #pragma unroll
             for (int r = 0; r < RMT; r++)
 #pragma unroll
-                for (int c = 0; c < RNT; c++) ct_mac(accn[r][c], accc[r][c], an[r], ac[r], bn[c], bc[c]);
+                for (int c = 0; c < RNT; c++) {
+                    const bool eq = an[r] + bn[c] == accn[r][c];
+                    const unsigned blo = eq ? (unsigned)bc[c] : 0u, bhi = eq ? (unsigned)(bc[c] >> 32) : 0u;
+                    accc[r][c] = mad_u64_mod(accc[r][c], (unsigned)ac[r], (unsigned)(ac[r] >> 32), blo, bhi);
+                }
         }
         __syncthreads();
     }
@@ -1082,6 +1134,14 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
     const i64 sbase = g.lsplit ? (i64)p.split * nout : 0;
     int* dn = (int*)dst.p0 + sbase;
     u64* dc = (u64*)dst.p1 + sbase;
+#pragma unroll
+    for (int r = 0; r < RMT; r++)
+#pragma unroll
+        for (int c = 0; c < RNT; c++)
+            if (accn[r][c] < kCtNegInfBelow) {
+                accn[r][c] = INT_MIN;
+                accc[r][c] = 0ull;
+            }
 #pragma unroll
     for (int r = 0; r < RMT; r++) {
         const int row = (r / 4) * (TM / 2) + ty * 4 + (r & 3);

@@ -6,6 +6,18 @@
 
 namespace tn {
 
+// The integer algebras (max-plus int32, counting tropical) need every size a
+// configuration can reach within |size| <= 2^28: the sum of |weights| (of
+// |couplings| and |fields| for a spin glass) bounds it.
+static constexpr double kIntSizeBound = 268435456.0;
+
+static double abs_sum(const std::vector<float>& w) {
+    double s = 0;
+    for (float x : w) s += std::fabs((double)x);
+    return s;
+}
+
+
 static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -49,6 +61,7 @@ tn_status make_net(int nv, int ne, const int32_t* edges, const float* weights, N
             if (out.w[v] != std::nearbyint(out.w[v]) || std::fabs(out.w[v]) > 65536.0f)
                 out.integer_weights = false;
         }
+        if (abs_sum(out.w) > kIntSizeBound) out.integer_weights = false;
     }
     // FNV-1a over the structure, so a plan can check it belongs to this network
     uint64_t h = 1469598103934665603ull;
@@ -112,6 +125,7 @@ tn_status make_spin_glass(int nv, int ne, const int32_t* edges, const float* J, 
         if (!std::isfinite(x)) return fail(TN_EINVAL, "non-finite coupling or field");
         if (x != std::nearbyint(x) || std::fabs(x) > 65536.0f) out.integer_weights = false;
     }
+    if (abs_sum(out.w) > kIntSizeBound) out.integer_weights = false;
     out.fingerprint = out.fingerprint * 1099511628211ull ^ 0x5397u;  // a spin glass differs from an IS network
     set_dev_weights(out);
     return TN_OK;
