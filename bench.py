@@ -185,11 +185,22 @@ def dominant_roofline(recs):
 
 
 def per_node_table(recs, top=16):
+    """The step's nodes with the most device time (launches of one node,
+    kernel and algebra summed over the slices), each against its roofline."""
+    groups = {}
+    for r in recs:
+        key = (r["kernel"], r["semiring"], r["node"], tuple(r["shape"]))
+        g = groups.setdefault(key, dict(r, ms=0.0, ops=0.0, alg_bytes=0.0, launches=0))
+        g["ms"] += r["ms"]
+        g["ops"] += r["ops"]
+        g["alg_bytes"] += r["alg_bytes"]
+        g["launches"] += 1
     rows = []
-    for r in sorted(recs, key=lambda r: -r["ms"])[:top]:
+    for r in sorted(groups.values(), key=lambda r: -r["ms"])[:top]:
         lr = launch_roofline(r)
         row = {"kernel": r["kernel"], "semiring": SR_NAME.get(r["semiring"], "mixed"), "node": r["node"],
-               "shape_log2": r["shape"], "ms": round(r["ms"], 4), "bound": lr["bound"], "frac": round(lr["frac"], 4)}
+               "shape_log2": r["shape"], "launches": r["launches"], "ms": round(r["ms"], 3), "bound": lr["bound"],
+               "frac": round(lr["frac"], 4)}
         if "achieved_ops" in lr:
             row["TOP_per_s"] = round(lr["achieved_ops"] / 1e12, 3)
             row["roof_TOP_per_s"] = round(lr["roof_ops"] / 1e12, 3)

@@ -149,6 +149,14 @@ typedef struct {
 } tn_task_record;
 tn_status tn_ctx_task_trace(tn_ctx* ctx, tn_task_record* recs, int32_t cap, int32_t* n, int clear);
 
+/* Longest dependency wait of a persistent launch (tn_solve_batch, the
+ * persistent executor of tn_solve, the server, and the passes of the
+ * polynomial / max-k / configuration calls), default 10 s.  A workgroup whose
+ * wait for an input exceeds it sets the launch's abort flag; every workgroup
+ * then leaves the launch, the kernel ends, and the call returns TN_EDEVICE
+ * for every job of that launch.  Errors: TN_EINVAL (seconds not positive). */
+tn_status tn_ctx_set_wait_limit(tn_ctx* ctx, double seconds);
+
 /* ------------------------------------------------------------- network --- */
 
 /* Independent-set network of a graph (Sec. 3.2): one index per vertex, an
@@ -566,10 +574,20 @@ tn_status tn_server_poll(tn_server* s, uint64_t job_id, tn_result* out, int32_t*
 /* Block until all submitted jobs are done. */
 tn_status tn_server_drain(tn_server* s);
 
+/* Cancel a job still in the queue: its poll then returns TN_ECANCELED.
+ * Errors: TN_EBUSY (the job is already on the device), TN_EINVAL (unknown
+ * or finished job).  Thread-safe. */
+tn_status tn_server_cancel(tn_server* s, uint64_t job_id);
+
 typedef struct {
     uint64_t submitted, completed, failed, launches;
-    uint64_t peak_admitted_bytes;   /* never above the budget */
-    int32_t peak_running;
+    uint64_t peak_admitted_bytes;   /* largest sum of admitted jobs' device bytes (never above the budget) */
+    int32_t peak_running;           /* most jobs on the device at once */
+    int32_t peak_inflight;          /* most persistent launches in flight at once */
+    uint64_t peak_pool_bytes;       /* high-water mark of the server's device pool (jobs and task tables) */
+    uint64_t rejected;              /* submits refused with TN_ETOOBIG */
+    uint64_t canceled;              /* jobs cancelled in the queue */
+    uint64_t requeued;              /* admissions put back because the pool could not hold them */
 } tn_server_stats_t;
 tn_status tn_server_stats(tn_server* s, tn_server_stats_t* st);
 tn_status tn_server_destroy(tn_server* s); /* drains first */

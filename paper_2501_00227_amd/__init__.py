@@ -104,7 +104,9 @@ class tn_task_record(ctypes.Structure):
 class tn_server_stats_t(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("peak_admitted_bytes", ctypes.c_uint64),
-                ("peak_running", ctypes.c_int32)]
+                ("peak_running", ctypes.c_int32), ("peak_inflight", ctypes.c_int32),
+                ("peak_pool_bytes", ctypes.c_uint64), ("rejected", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+                ("requeued", ctypes.c_uint64)]
 
 
 class tn_tune_record(ctypes.Structure):
@@ -124,6 +126,7 @@ SIGNATURES = [
     ("tn_ctx_set_profiling", ctypes.c_int, [_VP, ctypes.c_int]),
     ("tn_ctx_profile", ctypes.c_int, [_VP, _P(tn_kernel_record), ctypes.c_int32, c_int32_p, ctypes.c_int]),
     ("tn_ctx_synchronize", ctypes.c_int, [_VP]),
+    ("tn_ctx_set_wait_limit", ctypes.c_int, [_VP, ctypes.c_double]),
     ("tn_ctx_task_trace", ctypes.c_int, [_VP, _P(tn_task_record), ctypes.c_int32, c_int32_p, ctypes.c_int]),
     ("tn_net_independent_set", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, c_int32_p, _P(ctypes.c_float), _P(_VP)]),
     ("tn_net_spin_glass", ctypes.c_int,
@@ -163,6 +166,7 @@ SIGNATURES = [
     ("tn_server_submit", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
     ("tn_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _P(tn_result), c_int32_p, _P(ctypes.c_double)]),
     ("tn_server_drain", ctypes.c_int, [_VP]),
+    ("tn_server_cancel", ctypes.c_int, [_VP, ctypes.c_uint64]),
     ("tn_server_stats", ctypes.c_int, [_VP, _P(tn_server_stats_t)]),
     ("tn_server_destroy", ctypes.c_int, [_VP]),
 ]
@@ -553,6 +557,10 @@ class Context:
                        ("t_start", np.float32), ("t_ready", np.float32), ("t_end", np.float32)])
         return np.frombuffer(bytes(recs)[: n.value * dt.itemsize], dtype=dt).copy()
 
+    def set_wait_limit(self, seconds: float) -> None:
+        """Longest dependency wait of a persistent launch (tn_ctx_set_wait_limit)."""
+        _check(lib().tn_ctx_set_wait_limit(self.h, float(seconds)))
+
     def synchronize(self) -> None:
         _check(lib().tn_ctx_synchronize(self.h))
 
@@ -691,6 +699,10 @@ class Server:
 
     def drain(self) -> None:
         _check(lib().tn_server_drain(self.h))
+
+    def cancel(self, job_id: int) -> None:
+        """Cancel a job still in the queue (its poll then raises TN_ECANCELED)."""
+        _check(lib().tn_server_cancel(self.h, int(job_id)))
 
     def stats(self) -> Dict:
         s = tn_server_stats_t()

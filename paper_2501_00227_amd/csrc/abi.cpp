@@ -1,6 +1,7 @@
 // extern "C" entry points (include/tn.h).  No exception crosses this file:
 // every call is wrapped and reports a tn_status plus a thread-local message.
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <new>
 
@@ -467,6 +468,14 @@ tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_
         return st;
     }
     return solve_one(c, n->net, p->plan, *o, *out);
+    TN_GUARD_END
+}
+
+tn_status tn_ctx_set_wait_limit(tn_ctx* c, double seconds) {
+    TN_GUARD_BEGIN
+    if (!c || !(seconds > 0) || !std::isfinite(seconds)) return fail(TN_EINVAL, "the wait limit must be a positive time");
+    c->wait_limit_s = seconds;
+    return TN_OK;
     TN_GUARD_END
 }
 

@@ -593,8 +593,8 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     size_t o_nodes = a256(o_jobs + sizeof(BJob) * bj.size());
     size_t o_tasks = a256(o_nodes + sizeof(BNode) * std::max<size_t>(bn.size(), 1));
     size_t o_cnt = a256(o_tasks + sizeof(BTask) * sorted.size());
-    size_t o_tick = o_cnt + sizeof(int) * (size_t)ncounters;  // counters and tickets: zero at every launch
-    size_t o_sub = a256(o_tick + sizeof(int) * (size_t)nq);
+    size_t o_tick = o_cnt + sizeof(int) * (size_t)ncounters;  // counters, tickets, abort flag: zero at every launch
+    size_t o_sub = a256(o_tick + sizeof(int) * (size_t)(nq + 1));
     size_t o_q = a256(o_sub + sizeof(int) * std::max<size_t>(L.subtree_list.size(), 1));
     size_t o_trace = a256(o_q + sizeof(int) * 2 * (size_t)nq);
     size_t o_end = ctx->profiling ? a256(o_trace + 32 * sorted.size()) : o_trace;
@@ -602,9 +602,9 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     L.tables = alloc.alloc(L.table_bytes);
     if (!L.tables) return fail(TN_ENOMEM, "device allocation of the task table failed");
     size_t wbytes = weights_end;
-    L.host_bytes = o_end + wbytes + kAccSlotBytes * jobs.size() + sizeof(int) * nq + 1024;
+    L.host_bytes = o_end + wbytes + kAccSlotBytes * jobs.size() + sizeof(int) * (nq + 1) + 1024;
     L.o_reset = o_cnt;
-    L.reset_bytes = o_tick + sizeof(int) * (size_t)nq - o_cnt;
+    L.reset_bytes = o_tick + sizeof(int) * (size_t)(nq + 1) - o_cnt;
     L.host = pinned_acquire(ctx, L.host_bytes);
     L.ctx = ctx;
     if (!L.host) return fail(TN_ENOMEM, "pinned staging allocation failed");
@@ -638,6 +638,18 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     return TN_OK;
 }
 
+// The context's wait limit in ticks of the device's constant wall clock.
+long long wait_limit_ticks(tn_ctx* ctx) {
+    if (ctx->wall_khz <= 0) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
+            khz = 100000;  // the 100 MHz clock of CDNA parts
+        ctx->wall_khz = khz;
+    }
+    const double t = ctx->wait_limit_s * 1e3 * (double)ctx->wall_khz;
+    return t < 1.0 ? 1 : (t > 9e18 ? (long long)9e18 : (long long)t);
+}
+
 tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
     if (L.njobs == 0) return TN_OK;
     hipError_t e = hipSuccess;
@@ -656,12 +668,13 @@ tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
         ProfScope ps(ctx, TN_K_BATCH, -1, -1, shape, L.total_bytes, L.total_ops,
                      L.wide ? "batch_kernel<true>" : "batch_kernel<false>");
         e = launch_batch(L.d_tasks, L.d_qbegin, L.d_qcount, L.nq, L.d_jobs, L.d_nodes, L.d_subtree, L.d_counters,
-                         L.d_ticket, nwg, L.d_trace, L.wide, s);
+                         L.d_ticket, nwg, L.d_trace, L.wide, wait_limit_ticks(ctx), s);
     }
     // the tickets come back with the roots: a queue whose tickets did not all
     // go out was not served, and its jobs' results are not valid
     if (e == hipSuccess)
-        e = hipMemcpyAsync((unsigned char*)L.host + L.o_hticket, L.d_ticket, sizeof(int) * L.nq, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync((unsigned char*)L.host + L.o_hticket, L.d_ticket, sizeof(int) * (L.nq + 1),
+                           hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync((unsigned char*)L.host + L.o_hacc, L.d_accs, kAccSlotBytes * (size_t)L.njobs, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return fail(TN_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
@@ -671,6 +684,11 @@ tn_status batch_launch(tn_ctx* ctx, BatchLaunch& L, hipStream_t s) {
 tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out) {
     out.assign(L.items.size(), tn_result{});
     tn_status first = TN_OK;
+    if (L.njobs > 0 && ((const int*)((unsigned char*)L.host + L.o_hticket))[L.nq] != 0)
+        for (auto& st : L.items)
+            if (st.status == TN_OK)
+                st.status = fail(TN_EDEVICE, "a dependency wait of the persistent launch exceeded the context's wait "
+                                             "limit; the launch was abandoned");
     for (int q = 0; q < L.nq && L.njobs > 0; q++) {
         int served = ((const int*)((unsigned char*)L.host + L.o_hticket))[q];
         if (L.qcount[q] > 0 && served < L.qcount[q]) {

@@ -66,9 +66,11 @@ struct BTask {
 // trace: NULL, or 4 x ntasks timestamps (start, ready, end, xcc) per task.
 // wide: the launch's jobs use the wide-entry algebras (eight-lists,
 // truncated polynomials; a launch holds either these or the others only).
+// tickets has nq + 1 entries: one per queue, then the abort flag a wait sets
+// when it exceeds wait_limit ticks of the constant wall clock.
 hipError_t launch_batch(const BTask* tasks, const int* qbegin, const int* qcount, int nq, const BJob* jobs,
                         const BNode* nodes, const int* subtree, int* counters, int* tickets, int nworkgroups,
-                        unsigned long long* trace, int wide, hipStream_t s);
+                        unsigned long long* trace, int wide, long long wait_limit, hipStream_t s);
 size_t batch_lds_bytes();
 
 }  // namespace tn

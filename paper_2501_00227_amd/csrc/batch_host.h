@@ -68,6 +68,7 @@ struct BatchLaunch {
 };
 
 int device_cu_count(tn_ctx* ctx);
+long long wait_limit_ticks(tn_ctx* ctx);
 // Build and upload nothing yet: lay out memory, allocate, fill the staging.
 tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch& L, const DevAllocFn& alloc);
 // Enqueue upload, the persistent kernel and the root read-back on stream s.

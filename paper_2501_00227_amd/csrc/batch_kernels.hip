@@ -2,6 +2,8 @@
 // passes in one launch (see batch.h for the task model).
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "batch.h"
 #include "kernels_dev.h"
 
@@ -20,17 +22,37 @@ static_assert(((sizeof(PermLds) + 255) & ~(size_t)255) + kPermTile * 8 <= kBatch
 // visible to the next task once its stores have reached L2 (vmcnt drained)
 // and the consumer's CU has dropped its L1 lines.  The counters themselves
 // are device-scope atomics.
-__device__ inline void wait_counters(const int* counters, int d0, int n0, int d1, int n1) {
+//
+// Every wait is bounded: a wait longer than `limit` ticks of the constant
+// wall clock, or any wait while the launch's abort flag is set, sets the flag
+// and gives up; the workgroup then leaves the launch and every other
+// workgroup leaves at its next ticket or wait, so the kernel always ends and
+// the host reports the launch as failed.  Returns false on giving up.
+__device__ inline bool wait_counters(const int* counters, int d0, int n0, int d1, int n1, int* abort_flag,
+                                     long long limit) {
+    __shared__ int s_ok;
     if (threadIdx.x == 0) {
-        if (d0 >= 0)
-            while (__hip_atomic_load(&counters[d0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n0)
+        int ok = 1;
+        const long long t0 = wall_clock64();
+        const int dep[2] = {d0, d1}, need[2] = {n0, n1};
+        for (int u = 0; u < 2 && ok; u++) {
+            if (dep[u] < 0) continue;
+            while (__hip_atomic_load(&counters[dep[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need[u]) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                    wall_clock64() - t0 > limit) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
-        if (d1 >= 0)
-            while (__hip_atomic_load(&counters[d1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n1)
-                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        s_ok = ok;
     }
     __syncthreads();
+    const bool ok = s_ok != 0;
     asm volatile("buffer_inv sc0" ::: "memory");  // this CU's L1: refetch from the XCC's L2
+    return ok;
 }
 
 __device__ inline void signal_counter(int* counters, int c) {
@@ -298,13 +320,17 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
                                                     const int* __restrict__ qcount, int nq,
                                                     const BJob* __restrict__ jobs, const BNode* __restrict__ nodes,
                                                     const int* __restrict__ subtree, int* counters, int* tickets,
-                                                    unsigned long long* trace) {
+                                                    unsigned long long* trace, long long wait_limit) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_task;
     const int q = (int)(hw_xcc_id() % (unsigned)nq);
     const int qb = qbegin[q], qn = qcount[q];
+    int* abort_flag = tickets + nq;  // set when a wait gave up: every workgroup leaves
     for (;;) {
-        if (threadIdx.x == 0) s_task = atomicAdd(&tickets[q], 1);
+        if (threadIdx.x == 0)
+            s_task = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0
+                         ? INT_MAX
+                         : atomicAdd(&tickets[q], 1);
         __syncthreads();
         const int tq = s_task;
         __syncthreads();
@@ -312,7 +338,7 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
         const int ti = qb + tq;
         const unsigned long long t_start = trace ? wall_clock64() : 0ull;
         const BTask t = tasks[ti];
-        wait_counters(counters, t.dep0, t.need0, t.dep1, t.need1);
+        if (!wait_counters(counters, t.dep0, t.need0, t.dep1, t.need1, abort_flag, wait_limit)) break;
         const unsigned long long t_ready = trace ? wall_clock64() : 0ull;
         const BJob& j = jobs[t.job];
         if constexpr (WIDE) {
@@ -344,14 +370,14 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
 
 hipError_t launch_batch(const BTask* tasks, const int* qbegin, const int* qcount, int nq, const BJob* jobs,
                         const BNode* nodes, const int* subtree, int* counters, int* tickets, int nworkgroups,
-                        unsigned long long* trace, int wide, hipStream_t s) {
+                        unsigned long long* trace, int wide, long long wait_limit, hipStream_t s) {
     if (nworkgroups <= 0) return hipSuccess;
     if (wide)
         batch_kernel<true><<<nworkgroups, 256, kBatchLds, s>>>(tasks, qbegin, qcount, nq, jobs, nodes, subtree,
-                                                               counters, tickets, trace);
+                                                               counters, tickets, trace, wait_limit);
     else
         batch_kernel<false><<<nworkgroups, 256, kBatchLds, s>>>(tasks, qbegin, qcount, nq, jobs, nodes, subtree,
-                                                                counters, tickets, trace);
+                                                                counters, tickets, trace, wait_limit);
     return hipGetLastError();
 }
 

@@ -95,6 +95,8 @@ struct tn_ctx {
     std::vector<PinnedBuf> pinned_pool;
     std::mutex pinned_mu;
     std::vector<tn_task_record> task_trace;  // persistent-launch timelines (profiling)
+    double wait_limit_s = 10.0;  // longest dependency wait of a persistent launch
+    int wall_khz = 0;            // the device's constant wall-clock rate (cached)
     // the last synchronous persistent launch, kept for an identical next call
     tn::BatchLaunch* batch_cache = nullptr;
     std::vector<uint64_t> batch_cache_key;

@@ -28,10 +28,12 @@ double now_s() {
 struct Pool {
     unsigned char* base = nullptr;
     uint64_t bytes = 0;
+    uint64_t used = 0, peak = 0;         // bytes handed out now / at most
     std::map<uint64_t, uint64_t> free_;  // offset -> size
     void init(void* b, uint64_t n) {
         base = (unsigned char*)b;
         bytes = n;
+        used = peak = 0;
         free_.clear();
         free_[0] = n;
     }
@@ -42,12 +44,15 @@ struct Pool {
                 uint64_t off = it->first, sz = it->second;
                 free_.erase(it);
                 if (sz > n) free_[off + n] = sz - n;
+                used += n;
+                peak = std::max(peak, used);
                 return base + off;
             }
         return nullptr;
     }
     void release(void* p, uint64_t n) {
         n = (n + 255) & ~(uint64_t)255;
+        used -= n;
         uint64_t off = (uint64_t)((unsigned char*)p - base);
         auto it = free_.emplace(off, n).first;
         auto nx = std::next(it);
@@ -131,6 +136,9 @@ struct tn_server {
     std::list<InFlight> inflight;
     std::thread th;
     bool stop = false;
+    // after the pool could not hold an admission round: admit nothing more
+    // until fewer launches than this are in flight (a completion frees memory)
+    size_t blocked_at = 0;
     tn_server_stats_t stats{};
 };
 
@@ -169,6 +177,8 @@ static void scheduler(tn_server* s) {
                 complete(s, *it);
                 (void)hipEventDestroy(it->ev);
                 it = s->inflight.erase(it);
+                std::lock_guard<std::mutex> g(s->mu);
+                if (s->blocked_at && s->inflight.size() < s->blocked_at) s->blocked_at = 0;
             } else {
                 ++it;
             }
@@ -182,7 +192,7 @@ static void scheduler(tn_server* s) {
         {
             std::unique_lock<std::mutex> g(s->mu);
             if (s->stop && s->queue.empty() && s->inflight.empty()) break;
-            const bool busy = s->inflight.size() >= s->streams.size();
+            const bool busy = s->inflight.size() >= s->streams.size() || s->blocked_at != 0;
             while (!busy && !s->queue.empty()) {
                 ServerJob& j = s->jobs[s->queue.front()];
                 if (s->running + (int)ids.size() >= s->max_slots) break;
@@ -249,6 +259,8 @@ static void scheduler(tn_server* s) {
             }
             s->admitted -= bytes;
             s->running -= (int)ids.size();
+            s->stats.requeued += ids.size();
+            if (!s->inflight.empty()) s->blocked_at = s->inflight.size();  // wait for a completion
             if (s->inflight.empty()) {  // nothing will free memory: fail the head job
                 ServerJob& j = s->jobs[s->queue.front()];
                 s->queue.pop_front();
@@ -283,11 +295,13 @@ static void scheduler(tn_server* s) {
         }
         (void)hipEventCreateWithFlags(&f.ev, hipEventDisableTiming);
         (void)hipEventRecord(f.ev, stream);
+        s->inflight.push_back(std::move(f));
         {
             std::lock_guard<std::mutex> g(s->mu);
             s->stats.launches++;
+            s->stats.peak_inflight = std::max<int32_t>(s->stats.peak_inflight, (int32_t)s->inflight.size());
+            s->stats.peak_pool_bytes = std::max<uint64_t>(s->stats.peak_pool_bytes, s->pool.peak);
         }
-        s->inflight.push_back(std::move(f));
     }
 }
 
@@ -342,7 +356,11 @@ tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
         tn_status st = make_passes(net->net, *o, passes);
         if (st != TN_OK) return st;
         uint64_t bytes = job_device_bytes(net->net, plan->plan, *o);
-        if (bytes > s->budget) return fail(TN_ETOOBIG, "job needs " + std::to_string(bytes) + " device bytes, above the budget");
+        if (bytes > s->budget) {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stats.rejected++;
+            return fail(TN_ETOOBIG, "job needs " + std::to_string(bytes) + " device bytes, above the budget");
+        }
         {
             // upload the plan's device program now, on the caller's thread
             std::lock_guard<std::mutex> g(s->dev);
@@ -386,8 +404,32 @@ tn_status tn_server_poll(tn_server* s, uint64_t job_id, tn_result* out, int32_t*
         if (latency_s) *latency_s = it->second.latency;
         tn_status st = it->second.st;
         s->jobs.erase(it);
+        if (st == TN_ECANCELED) return fail(st, "job was cancelled");
         if (st != TN_OK) return fail(st, "job failed");
     }
+    return TN_OK;
+}
+
+tn_status tn_server_cancel(tn_server* s, uint64_t job_id) {
+    if (!s) return fail(TN_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->jobs.find(job_id);
+    if (it == s->jobs.end()) return fail(TN_EINVAL, "unknown job id");
+    ServerJob& j = it->second;
+    if (j.state == 1) return fail(TN_EBUSY, "the job is already on the device");
+    if (j.state == 2) return fail(TN_EINVAL, "the job has already finished");
+    for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+        if (*q == job_id) {
+            s->queue.erase(q);
+            break;
+        }
+    j.state = 2;
+    j.st = TN_ECANCELED;
+    j.res.semiring = -1;
+    j.latency = now_s() - j.t_submit;
+    s->stats.completed++;
+    s->stats.canceled++;
+    s->done_cv.notify_all();
     return TN_OK;
 }
 

@@ -1,0 +1,178 @@
+"""Served stream and failure handling on the GPU.
+
+* Admission binds: a burst of jobs whose device bytes far exceed the HBM
+  budget is served in several admission rounds whose launches overlap on the
+  device (at least two in flight at once), the admitted bytes never pass the
+  budget, the server's device pool high-water mark stays within the budget
+  plus the task-table reserve, and every result equals the job's result
+  alone and the oracle's.
+* Jobs still queued can be cancelled; a job above the budget is refused.
+* Failures forced from the host end cleanly: a dependency-wait limit so small
+  that the persistent launch gives up (every workgroup leaves, TN_EDEVICE),
+  an allocator that returns NULL (TN_ENOMEM); the same context then solves
+  correctly again.
+"""
+import ctypes
+
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_2501_00227_amd as tn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    tn.lib()
+    c = tn.Context(0)
+    yield c
+    c.set_wait_limit(10.0)
+    c.synchronize()
+
+
+def _key(r):
+    return tuple(r.get(k) for k in ("size", "count_mod_2_64", "count", "z_mant", "z_exp2"))
+
+
+def _jobs(n, seed, n_lo, n_hi):
+    import random
+
+    rng = random.Random(seed)
+    out = []
+    for k in range(n):
+        nv = rng.randrange(n_lo, n_hi + 1, 2)
+        g = gg.random_regular(nv, 3, 1000 * seed + k)
+        net = tn.Net.from_graph(g)
+        plan = tn.Plan.create(net, seed=k)
+        sr = ["tropical_i32", "counting_tropical", "partition_f32"][k % 3]
+        out.append((g, net, plan, sr))
+    return out
+
+
+def test_admission_binds_and_launches_overlap(ctx):
+    jobs = _jobs(48, seed=7, n_lo=60, n_hi=110)
+    sizes = sorted(p.peak_bytes(sr) for _, _, p, sr in jobs)
+    budget = max(4 * sizes[len(sizes) // 2], (3 * sizes[-1]) // 2)  # a few jobs at a time, any job fits
+    total = sum(sizes)
+    print(f"budget {budget} bytes, the burst needs {total} ({total / budget:.1f} x)", flush=True)
+    assert total > 3 * budget
+    alone = [ctx.solve(net, plan, sr, executor="persistent") for _, net, plan, sr in jobs]
+    srv = tn.Server(ctx, budget, max_slots=64)
+    ids = [srv.submit(net, plan, sr) for _, net, plan, sr in jobs]  # one burst
+    srv.drain()
+    res = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    print("server stats", st, flush=True)
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    assert st["launches"] >= 3                      # the budget split the burst
+    assert st["peak_admitted_bytes"] <= budget
+    assert st["peak_inflight"] >= 2                 # launches overlapped on the device
+    assert st["peak_pool_bytes"] <= budget + (64 << 20)
+    for (g, _, _, sr), r, a in zip(jobs, res, alone):
+        assert r is not None and _key(r) == _key(a)
+    # every tropical / counting result against the oracle (n <= 110: elimination)
+    for (g, _, _, sr), r in zip(jobs, res):
+        if sr == "tropical_i32":
+            assert r["size"] == oracle.eliminate(g, "tropical")["size"]
+        elif sr == "counting_tropical":
+            ref = oracle.eliminate(g, "counting_tropical")
+            assert (r["size"], r["count_mod_2_64"]) == (ref["size"], ref["count"] % 2 ** 64)
+
+
+def test_cancel_queued_jobs_and_refuse_oversized(ctx):
+    g = gg.random_regular(150, 3, 3)
+    net = tn.Net.from_graph(g)
+    big = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, sc_target=24, seed=3)
+    small = _jobs(6, seed=8, n_lo=20, n_hi=30)
+    srv = tn.Server(ctx, 32 << 30, max_slots=1)
+    first = srv.submit(net, big, "counting_tropical")
+    queued = [srv.submit(n2, p2, sr) for _, n2, p2, sr in small]
+    cancelled = []
+    for jid in queued[2:]:
+        try:
+            srv.cancel(jid)
+            cancelled.append(jid)
+        except tn.TnError as e:
+            assert e.code == tn.TN_EBUSY
+    srv.drain()
+    assert srv.poll(first) is not None
+    for jid in queued:
+        if jid in cancelled:
+            with pytest.raises(tn.TnError) as ei:
+                srv.poll(jid)
+            assert ei.value.code == tn.TN_ECANCELED
+        else:
+            assert srv.poll(jid) is not None
+    st = srv.stats()
+    assert st["canceled"] == len(cancelled) >= 1
+    srv.close()
+    tiny = tn.Server(ctx, 1 << 16, max_slots=1)
+    with pytest.raises(tn.TnError) as ei:  # a job far above the budget
+        tiny.submit(net, big, "counting_tropical")
+    assert ei.value.code == tn.TN_ETOOBIG
+    assert tiny.stats()["rejected"] == 1
+    tiny.close()
+
+
+def test_wait_limit_abandons_the_launch_and_the_context_recovers(ctx):
+    g = gg.random_regular(120, 3, 0)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, method="treesa", ntrials=2, niters=5, seed=0)
+    want = oracle.eliminate(g, "counting_tropical")
+    ctx.set_wait_limit(1e-8)  # one tick of the wall clock: every dependency wait gives up
+    with pytest.raises(tn.TnError) as ei:
+        ctx.solve_batch([net, net], [plan, plan], ["counting_tropical", "tropical_i32"])
+    assert ei.value.code == tn.TN_EDEVICE
+    ctx.set_wait_limit(10.0)
+    r = ctx.solve_batch([net, net], [plan, plan], ["counting_tropical", "tropical_i32"])
+    assert (r[0]["size"], r[0]["count_mod_2_64"]) == (want["size"], want["count"] % 2 ** 64)
+    assert r[1]["size"] == want["size"]
+    with pytest.raises(tn.TnError):
+        ctx.set_wait_limit(0.0)
+
+
+def test_allocator_failure_is_reported_and_the_next_solve_succeeds():
+    import torch
+
+    torch.cuda.set_device(0)
+    state = {"fail": False, "calls": 0}
+    t_alloc, t_free = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
+
+    def _alloc(nbytes, user, stream):
+        state["calls"] += 1
+        if state["fail"]:
+            return None
+        return t_alloc(int(nbytes), 0, int(stream or 0))
+
+    def _free(ptr, nbytes, user, stream):
+        t_free(int(ptr))
+
+    a_cb, f_cb = tn.ALLOC_FN(_alloc), tn.FREE_FN(_free)
+    alloc = tn.tn_allocator(ctypes.cast(a_cb, ctypes.c_void_p), ctypes.cast(f_cb, ctypes.c_void_p), None)
+    h = ctypes.c_void_p()
+    tn._check(tn.lib().tn_ctx_create(0, ctypes.c_void_p(torch.cuda.current_stream(0).cuda_stream),
+                                     ctypes.byref(alloc), ctypes.byref(h)))
+    c = tn.Context.__new__(tn.Context)
+    c._cb = (a_cb, f_cb)
+    c.h = h
+    tn._live.add(c)
+    g = gg.random_regular(60, 3, 1)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net)
+    want = oracle.eliminate(g, "count")["count"]
+    state["fail"] = True
+    for ex in ("stream", "persistent"):
+        with pytest.raises(tn.TnError) as ei:
+            c.solve(net, plan, "count_exact", executor=ex)
+        assert ei.value.code == tn.TN_ENOMEM
+    with pytest.raises(tn.TnError) as ei:
+        tn.Server(c, 1 << 20)
+    assert ei.value.code == tn.TN_ENOMEM
+    state["fail"] = False
+    for ex in ("stream", "persistent"):
+        assert c.solve(net, plan, "count_exact", executor=ex)["count"] == want
+    c.synchronize()
+    c.close()
