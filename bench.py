@@ -471,14 +471,50 @@ def buckyball(ctx):
     return out
 
 
-def job_stream(ctx, njobs, seed=0):
-    """Batched and served throughput on a stream of small 3-regular jobs."""
+K4_N = (40, 200)
+K4_BUDGET = 2 << 30
+
+
+def k4_expected(njobs, seed):
+    """Expected results of the served jobs with n <= 130 (the oracle's
+    elimination, stored by tests/golden/make_golden_k4.py for the default
+    stream), or None when the stream differs from the stored one."""
+    path = os.path.join(ROOT, "tests", "golden", "k4_jobs.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec["njobs"] != njobs or rec["seed"] != seed or rec["n_range"] != list(K4_N):
+        return None
+    out = {}
+    for k, v in rec["expected"].items():
+        if v is None:
+            continue
+        out[int(k)] = [v[0], int(v[1])] if isinstance(v, list) else v
+    return out
+
+
+def _k4_matches(sr, r, want):
+    if sr == "tropical_i32":
+        return r["size"] == want
+    if sr == "counting_tropical":
+        return [r["size"], r["count_mod_2_64"]] == want
+    return abs(r["log_z"] - want) <= 1e-5
+
+
+def job_stream(ctx, njobs, seed=0, expected=None):
+    """The served workload: 3-regular jobs with n uniform over even values in
+    [40, 200], algebra uniform over tropical int32, counting tropical and
+    float32 Z at x = 1; jobs above the 2 GiB device budget are refused
+    (TN_ETOOBIG) and counted.  Plain one-at-a-time, batched (persistent
+    launches of 256 jobs) and served (Poisson arrivals at 0.5, 1, 2 and 4 x
+    the plain rate, p50/p99 latency submit -> result on the host), every job
+    with n <= 130 checked against the oracle."""
     import numpy as np
 
     import graphgen as gg
     import paper_2501_00227_amd as tn
 
-    mix = gg.job_mix(njobs, seed, 40, 120)
+    mix = gg.job_mix(njobs, seed, *K4_N)
 
     def mk(j):
         n, gseed, sr = j
@@ -489,28 +525,47 @@ def job_stream(ctx, njobs, seed=0):
     with cf.ThreadPoolExecutor(8) as ex:
         jobs = list(ex.map(mk, mix))
     plan_s = time.perf_counter() - t0
-    res = {"jobs": njobs, "n_range": [40, 120], "planning_seconds_8_threads": plan_s}
-    # one at a time (a sample), each tn_solve synchronous
-    sample = jobs[: min(300, njobs)]
-    for net, plan, sr in sample[:20]:
-        ctx.solve(net, plan, sr)
+    # the jobs that fit the budget (the server refuses the others)
+    keep = [k for k, (net, plan, sr) in enumerate(jobs) if tn.server_job_bytes(net, plan, sr) <= K4_BUDGET]
+    res = {"workload": "K4: %d 3-regular jobs, n uniform over even values in [%d, %d], algebra uniform over tropical "
+                       "int32 / counting tropical / Z(x=1) fp32, device budget %d GiB" %
+                       (njobs, K4_N[0], K4_N[1], K4_BUDGET >> 30),
+           "jobs": njobs, "admissible": len(keep), "planning_seconds_8_threads": plan_s,
+           "largest_admissible_n": max(mix[k][0] for k in keep)}
+    mism = 0
+    checked = 0
+
+    def check(k, r):
+        nonlocal mism, checked
+        if expected is not None and k in expected:
+            checked += 1
+            if not _k4_matches(mix[k][2], r, expected[k]):
+                mism += 1
+
+    # one at a time (a sample of the admissible jobs), each tn_solve synchronous
+    sample = keep[: min(300, len(keep))]
+    for k in sample[:20]:
+        ctx.solve(*jobs[k])
     t0 = time.perf_counter()
-    for net, plan, sr in sample:
-        ctx.solve(net, plan, sr)
+    for k in sample:
+        ctx.solve(*jobs[k])
     plain = len(sample) / (time.perf_counter() - t0)
     res["plain_solves_per_s"] = plain
     # batched: persistent launches of 256 jobs
     t0 = time.perf_counter()
-    for k in range(0, njobs, 256):
-        chunk = jobs[k:k + 256]
-        ctx.solve_batch([c[0] for c in chunk], [c[1] for c in chunk], [c[2] for c in chunk])
-    res["batched_solves_per_s"] = njobs / (time.perf_counter() - t0)
-    # served: Poisson arrivals at 0.5, 1, 2 and 4 x the one-at-a-time rate
+    for q in range(0, len(keep), 256):
+        chunk = keep[q:q + 256]
+        out = ctx.solve_batch([jobs[k][0] for k in chunk], [jobs[k][1] for k in chunk], [jobs[k][2] for k in chunk])
+        for k, r in zip(chunk, out):
+            check(k, r)
+    res["batched_solves_per_s"] = len(keep) / (time.perf_counter() - t0)
+    # served: Poisson arrivals at 0.5, 1, 2 and 4 x the one-at-a-time rate;
+    # every job is submitted, the ones above the budget are refused
     res["served"] = []
     for mult in (0.5, 1.0, 2.0, 4.0):
         rate = mult * plain
         arrivals = gg.poisson_arrivals(njobs, rate, seed + 1)
-        srv = tn.Server(ctx, 16 << 30, max_slots=512)
+        srv = tn.Server(ctx, K4_BUDGET, max_slots=512)
         ids = [None] * njobs
         t_start = time.perf_counter()
 
@@ -519,22 +574,39 @@ def job_stream(ctx, njobs, seed=0):
                 dt = arrivals[i] - (time.perf_counter() - t_start)
                 if dt > 0:
                     time.sleep(dt)
-                ids[i] = srv.submit(net, plan, sr)
+                try:
+                    ids[i] = srv.submit(net, plan, sr)
+                except tn.TnError as e:
+                    if e.code != tn.TN_ETOOBIG:
+                        raise
 
         th = threading.Thread(target=producer)
         th.start()
         th.join()
         srv.drain()
         t_end = time.perf_counter()
-        lat = np.array([srv.poll(i)["latency_s"] for i in ids])
+        lat = []
+        for k, jid in enumerate(ids):
+            if jid is None:
+                continue
+            r = srv.poll(jid)
+            lat.append(r["latency_s"])
+            if mult == 1.0:
+                check(k, r)
+        lat = np.array(lat)
         st = srv.stats()
         srv.close()
         res["served"].append({"arrival_rate_per_s": rate, "rate_over_plain": mult,
-                              "solves_per_s": njobs / (t_end - t_start),
+                              "solves_per_s": len(lat) / (t_end - t_start),
                               "p50_ms": float(np.percentile(lat, 50) * 1e3),
                               "p99_ms": float(np.percentile(lat, 99) * 1e3),
                               "launches": st["launches"], "peak_running": st["peak_running"],
-                              "peak_admitted_bytes": st["peak_admitted_bytes"], "budget_bytes": 16 << 30})
+                              "peak_inflight": st["peak_inflight"], "rejected": st["rejected"],
+                              "requeued": st["requeued"], "peak_admitted_bytes": st["peak_admitted_bytes"],
+                              "peak_pool_bytes": st["peak_pool_bytes"], "budget_bytes": K4_BUDGET})
+    res["oracle_checked"] = checked
+    res["oracle_mismatches"] = mism
+    res["oracle_stored_jobs"] = len(expected) if expected else 0
     return res
 
 
@@ -585,7 +657,8 @@ def main():
         sys.exit(2)
     # the oracle runs first, in forked processes, before anything touches the GPU
     cpu = None
-    if not (args.no_cpu or args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2):
+    only = args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2
+    if not (args.no_cpu or only):
         cpu = cpu_baseline()
 
     import torch
@@ -683,7 +756,7 @@ def main():
         out["size_max_8_weighted"] = size_max_8_weighted(ctx, g, plan, tc2)
         out["counting_max_4"] = counting_max_4(ctx, net, plan, tc2)
         out["conditioned"] = conditioned_batch(ctx, g, plan)
-        out["batched"] = job_stream(ctx, args.jobs, args.seed)
+        out["batched"] = job_stream(ctx, args.jobs, args.seed, k4_expected(args.jobs, args.seed))
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

@@ -574,6 +574,11 @@ tn_status tn_server_poll(tn_server* s, uint64_t job_id, tn_result* out, int32_t*
 /* Block until all submitted jobs are done. */
 tn_status tn_server_drain(tn_server* s);
 
+/* Device bytes a job takes in a server (the admission measure: every tensor
+ * of every pass in its own region, as the persistent launch lays them out);
+ * a server refuses a job above its budget.  No device access. */
+tn_status tn_server_job_bytes(const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts, uint64_t* bytes);
+
 /* Cancel a job still in the queue: its poll then returns TN_ECANCELED.
  * Errors: TN_EBUSY (the job is already on the device), TN_EINVAL (unknown
  * or finished job).  Thread-safe. */

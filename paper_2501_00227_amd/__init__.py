@@ -167,6 +167,7 @@ SIGNATURES = [
     ("tn_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _P(tn_result), c_int32_p, _P(ctypes.c_double)]),
     ("tn_server_drain", ctypes.c_int, [_VP]),
     ("tn_server_cancel", ctypes.c_int, [_VP, ctypes.c_uint64]),
+    ("tn_server_job_bytes", ctypes.c_int, [_VP, _VP, _P(tn_solve_opts), _P(ctypes.c_uint64)]),
     ("tn_server_stats", ctypes.c_int, [_VP, _P(tn_server_stats_t)]),
     ("tn_server_destroy", ctypes.c_int, [_VP]),
 ]
@@ -663,6 +664,14 @@ class Context:
 
     def __del__(self):
         self.close()
+
+
+def server_job_bytes(net: Net, plan: Plan, semiring, beta: float = 0.0) -> int:
+    """Device bytes the job takes in a server (tn_server_job_bytes)."""
+    o = solve_opts(semiring, beta)
+    b = ctypes.c_uint64()
+    _check(lib().tn_server_job_bytes(net.h, plan.h, ctypes.byref(o), ctypes.byref(b)))
+    return b.value
 
 
 class Server:

@@ -410,6 +410,19 @@ tn_status tn_server_poll(tn_server* s, uint64_t job_id, tn_result* out, int32_t*
     return TN_OK;
 }
 
+tn_status tn_server_job_bytes(const tn_net* net, const tn_plan* plan, const tn_solve_opts* o, uint64_t* bytes) {
+    try {
+        if (!net || !plan || !o || !bytes) return fail(TN_EINVAL, "NULL argument");
+        std::vector<PassSpec> passes;
+        tn_status st = make_passes(net->net, *o, passes);
+        if (st != TN_OK) return st;
+        *bytes = job_device_bytes(net->net, plan->plan, *o);
+        return TN_OK;
+    } catch (...) {
+        return fail(TN_ENOMEM, "job size failed");
+    }
+}
+
 tn_status tn_server_cancel(tn_server* s, uint64_t job_id) {
     if (!s) return fail(TN_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> g(s->mu);
