@@ -324,7 +324,9 @@ typedef struct {
     int64_t slice_begin;       /* run slices [slice_begin, slice_end) only; slice s */
     int64_t slice_end;         /* fixes sliced index k to bit k of s; 0,0 = all */
     int32_t executor;          /* 0 auto: one persistent launch for unsliced trees with
-                                  sc <= 22, per-node stream launches otherwise;
+                                  sc <= 22 and at most 2^27 semiring ops per pass
+                                  (a persistent launch keeps a job on one chiplet),
+                                  per-node stream launches otherwise;
                                   1 per-node stream launches; 2 persistent launch
                                   (unsliced plans only) */
 } tn_solve_opts;
@@ -387,7 +389,9 @@ tn_status tn_solve_noalloc(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, 
 
 /* Many networks in one persistent launch: a device task table of
  * (job, node, tile) entries with dependency counters; workgroups pop ready
- * tiles until every job's root is done.  Launch shapes come from the tuning
+ * tiles until every job's root is done.  Jobs the auto executor of tn_solve
+ * sends to per-node launches (trees with much work) run one after the other
+ * on per-node launches over the whole chip instead.  Launch shapes come from the tuning
  * table (or the heuristic) keyed by each node's own shape (see the
  * autotuner below), so a job's result does not depend on the other jobs in
  * the batch.  n jobs; opts and out have n
@@ -557,11 +561,14 @@ tn_status tn_tune_records(tn_tune_record* recs, int32_t cap, int32_t* n);
 
 /* -------------------------------------------------------------- server --- */
 
-/* Continuous-batching server on one context.  Jobs are admitted while the sum
- * of their device bytes (tn_plan_peak_bytes) stays within hbm_budget_bytes and
- * fewer than max_slots run; admitted jobs are merged into the next persistent
- * launch while earlier launches may still run; each job's latency is
- * result-on-host minus submit time.  The server owns a scheduler thread. */
+/* Continuous-batching server on one context.  Jobs are admitted in arrival
+ * order while the sum of their device bytes (tn_server_job_bytes) stays
+ * within hbm_budget_bytes and fewer than max_slots run; admitted jobs are
+ * merged into the next persistent launch (on one of three streams) while
+ * earlier launches may still run; a job the auto executor of tn_solve sends to
+ * per-node launches goes out alone on per-node launches, asynchronously on
+ * its own stream.  Each job's latency is result-on-host minus submit time.
+ * The server owns a scheduler thread. */
 tn_status tn_server_create(tn_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots,
                            tn_server** out);
 /* Thread-safe.  The net and plan must stay alive until the job is done.

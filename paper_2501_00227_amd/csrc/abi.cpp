@@ -548,15 +548,38 @@ tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const 
     TN_GUARD_BEGIN
     if (!c || n < 0 || (n > 0 && (!nets || !plans || !opts || !out))) return fail(TN_EINVAL, "NULL argument");
     if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
+    // jobs the auto executor sends to per-node launches (trees with much
+    // work: a persistent launch keeps a job on one chiplet) run one after the
+    // other over the whole chip; the rest share one persistent launch.  The
+    // route depends on the job alone, as for tn_solve.
     std::vector<BatchItem> items;
+    std::vector<int32_t> in_batch, alone;
     for (int32_t i = 0; i < n; i++) {
         if (!nets[i] || !plans[i]) return fail(TN_EINVAL, "NULL network or plan in the batch");
         if (!public_semiring(opts[i].semiring)) return fail(TN_EINVAL, "unknown semiring");
-        items.push_back({&nets[i]->net, &plans[i]->plan, opts[i]});
+        const Plan& pl = plans[i]->plan;
+        const bool per_node = pl.sliced.empty() && opts[i].slice_begin == 0 && opts[i].slice_end == 0 &&
+                              (opts[i].executor == 1 || (opts[i].executor == 0 && !use_persistent(pl)));
+        if (per_node) {
+            alone.push_back(i);
+        } else {
+            in_batch.push_back(i);
+            items.push_back({&nets[i]->net, &pl, opts[i]});
+        }
     }
-    std::vector<tn_result> res;
-    tn_status st = solve_batch_sync(c, items, res);
-    for (int32_t i = 0; i < n && i < (int32_t)res.size(); i++) out[i] = res[i];
+    tn_status st = TN_OK;
+    if (!items.empty()) {
+        std::vector<tn_result> res;
+        st = solve_batch_sync(c, items, res);
+        for (size_t k = 0; k < in_batch.size() && k < res.size(); k++) out[in_batch[k]] = res[k];
+    }
+    for (int32_t i : alone) {
+        tn_status s2 = solve_one(c, nets[i]->net, plans[i]->plan, opts[i], out[i]);
+        if (s2 != TN_OK) {
+            out[i].semiring = -1;
+            if (st == TN_OK) st = s2;
+        }
+    }
     return st;
     TN_GUARD_END
 }

@@ -890,7 +890,11 @@ bool use_persistent(const Plan& p) {
     }
     if (!p.sliced.empty()) return false;
     if (mode >= 0) return mode == 1;
-    return p.max_rank <= 22;  // small trees: launch overhead dominates the per-node path
+    // small trees: launch overhead dominates the per-node path.  A job of a
+    // persistent launch runs on one chiplet, so trees with much work (more
+    // than 2^27 semiring ops per pass) take the per-node path over the whole
+    // chip instead.
+    return p.max_rank <= 22 && p.tc <= 27.0;
 }
 
 }  // namespace tn

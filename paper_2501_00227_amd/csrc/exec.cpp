@@ -79,8 +79,8 @@ void pinned_release(tn_ctx* ctx, void* p) {
 
 // ------------------------------------------------------------- profiling --
 ProfScope::ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops,
-                     const char* kernel)
-    : ctx(c), on(c->profiling) {
+                     const char* kernel, bool enable)
+    : ctx(c), on(c->profiling && enable) {
     if (!on) return;
     auto get = [&]() {
         hipEvent_t e;
@@ -622,7 +622,14 @@ SolveLayout solve_layout(const Net& net, const Plan& plan, const std::vector<Pas
 tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o,
                     const std::vector<PassSpec>& passes, DevProgram* dp, unsigned char* base, const SolveLayout& L,
                     int64_t sb, int64_t se, void* stage, std::vector<unsigned char>& all) {
-    hipStream_t s = ctx->stream;
+    return run_solve_on(ctx, ctx->stream, false, net, plan, o, passes, dp, base, L, sb, se, stage, &all);
+}
+
+tn_status run_solve_on(tn_ctx* ctx, hipStream_t s, bool async, const Net& net, const Plan& plan,
+                       const tn_solve_opts& o, const std::vector<PassSpec>& passes, DevProgram* dp,
+                       unsigned char* base, const SolveLayout& L, int64_t sb, int64_t se, void* stage,
+                       std::vector<unsigned char>* all) {
+    const bool prof = !async;  // launches of another thread's stream are not profiled
     const int nleaf = plan.nleaf();
     const int nn = (int)plan.nodes.size();
     const int pb1 = L.pb1;
@@ -640,10 +647,11 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
         }
     };
     if (wdev) {
-        chk(hipStreamSynchronize(s), "sync before weights");
+        if (!async) chk(hipStreamSynchronize(s), "sync before weights");
         std::memcpy(stage, net.wdev.data(), sizeof(float) * net.wdev.size());
         chk(hipMemcpyAsync(wdev, stage, sizeof(float) * net.wdev.size(), hipMemcpyHostToDevice, s), "weights upload");
-        chk(hipStreamSynchronize(s), "weights sync");  // staging is reused for the results below
+        // the staging is reused for the results: in order on the stream
+        if (!async) chk(hipStreamSynchronize(s), "weights sync");
     }
     auto plane_at = [&](Planes pl, int dsr, int64_t off) {
         Planes r;
@@ -668,7 +676,7 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
             {
                 char kn[64];
                 snprintf(kn, sizeof kn, "leaf_kernel<%d>", dsr);
-                ProfScope ps(ctx, TN_K_LEAF, -1, o.semiring, nullptr, (double)plan.leaf_entries * eb, 0, kn);
+                ProfScope ps(ctx, TN_K_LEAF, -1, o.semiring, nullptr, (double)plan.leaf_entries * eb, 0, kn, prof);
                 chk(launch_leaves(dsr, dp->leaves, nleaf, wdev, dp->slice_pos, (unsigned long long)sl, arena, ap,
                                   meta, s),
                     "leaves");
@@ -693,7 +701,8 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                         if (!pbytes) continue;
                         ProfScope ps(ctx, TN_K_PERMUTE, np.node, o.semiring, shp,
                                      2.0 * (double)node_entries(plan, src_node) * pbytes, 0,
-                                     pbytes == 8 ? "permute_kernel<unsigned long long>" : "permute_kernel<unsigned int>");
+                                     pbytes == 8 ? "permute_kernel<unsigned long long>" : "permute_kernel<unsigned int>",
+                                     prof);
                         if (pbytes == 32)  // 32-byte entries: 4-byte words, the three lowest bits in place
                             chk(launch_permute(4, pl ? src.p1 : src.p0, pl ? dst.p1 : dst.p0, dp->perms_wide + slot,
                                                rank + 3, perm_tile_bits(rank + 3), s),
@@ -721,7 +730,8 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                                                           : TN_K_GEMM;
                     char kn[64];
                     ProfScope ps(ctx, kind, np.node, o.semiring, shp, ent * eb,
-                                 std::exp2((double)(g.lb + g.li + g.lj + g.lk)), gemm_kernel_name(dsr, g, kn, sizeof kn));
+                                 std::exp2((double)(g.lb + g.li + g.lj + g.lk)), gemm_kernel_name(dsr, g, kn, sizeof kn),
+                                 prof);
                     chk(launch_gemm(dsr, Ap, Bp, Cp, part, g, ap, meta, np.a, np.b, np.node, s), "gemm");
                 }
                 if (g.lsplit > 0) {
@@ -729,7 +739,7 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                     char kn[64];
                     snprintf(kn, sizeof kn, "split_reduce_kernel<%d>", dsr);
                     ProfScope ps(ctx, TN_K_ACCUM, np.node, o.semiring, shp,
-                                 (double)(nout << g.lsplit) * eb + (double)nout * eb, 0, kn);
+                                 (double)(nout << g.lsplit) * eb + (double)nout * eb, 0, kn, prof);
                     chk(launch_split_reduce(dsr, part, Cp, nout, g.lsplit, ap, meta, np.node, s), "split reduce");
                 }
             }
@@ -739,11 +749,13 @@ tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solv
                 "root accumulate");
         }
     }
-    all.assign(L.acc_bytes, 0);
-    if (herr == hipSuccess) {
-        chk(hipMemcpyAsync(stage, base + L.o_acc, L.acc_bytes, hipMemcpyDeviceToHost, s), "result copy");
-        chk(hipStreamSynchronize(s), "result sync");
-        std::memcpy(all.data(), stage, L.acc_bytes);
+    if (herr == hipSuccess) chk(hipMemcpyAsync(stage, base + L.o_acc, L.acc_bytes, hipMemcpyDeviceToHost, s), "result copy");
+    if (!async) {
+        all->assign(L.acc_bytes, 0);
+        if (herr == hipSuccess) {
+            chk(hipStreamSynchronize(s), "result sync");
+            std::memcpy(all->data(), stage, L.acc_bytes);
+        }
     }
     if (herr != hipSuccess) return fail(TN_EDEVICE, std::string("HIP error at ") + herr_at + ": " + hipGetErrorString(herr));
     return TN_OK;

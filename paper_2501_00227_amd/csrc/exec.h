@@ -134,7 +134,7 @@ struct ProfScope {
     PendingRec pr;
     bool on;
     ProfScope(tn_ctx* c, int kind, int node, int sr, const int shape[4], double bytes, double ops,
-              const char* kernel = "");
+              const char* kernel = "", bool enable = true);
     ~ProfScope();
 };
 
@@ -179,6 +179,14 @@ SolveLayout solve_layout(const Net& net, const Plan& plan, const std::vector<Pas
 tn_status run_solve(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_solve_opts& o,
                     const std::vector<PassSpec>& passes, DevProgram* dp, unsigned char* base, const SolveLayout& L,
                     int64_t sb, int64_t se, void* stage, std::vector<unsigned char>& all);
+// run_solve on stream s; async: nothing waits (the weights go up from and
+// the accumulators come back into stage, in stream order), and the caller
+// reads the accumulators from stage once the stream has passed; launches
+// are not profiled.  all may be NULL when async.
+tn_status run_solve_on(tn_ctx* ctx, hipStream_t s, bool async, const Net& net, const Plan& plan,
+                       const tn_solve_opts& o, const std::vector<PassSpec>& passes, DevProgram* dp,
+                       unsigned char* base, const SolveLayout& L, int64_t sb, int64_t se, void* stage,
+                       std::vector<unsigned char>* all);
 tn_status decode_root(const tn_solve_opts& o, const std::vector<PassSpec>& passes, const std::vector<unsigned char>& all,
                       int64_t nent, int64_t addr, tn_result& r);
 // Bytes of device memory the program of a plan takes (leaves, slice

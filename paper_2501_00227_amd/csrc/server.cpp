@@ -101,6 +101,12 @@ struct ServerJob {
     const Plan* plan = nullptr;
     tn_solve_opts opts{};
     uint64_t bytes = 0;
+    // a tree with much work runs alone on per-node launches over the whole
+    // chip (a persistent launch keeps each job on one chiplet)
+    bool large = false;
+    DevProgram* dp = nullptr;
+    std::vector<PassSpec> passes;
+    SolveLayout layout;
     double t_submit = 0;
     int state = 0;  // 0 queued, 1 running, 2 done
     tn_result res{};
@@ -114,6 +120,10 @@ struct InFlight {
     hipEvent_t ev = nullptr;
     uint64_t bytes = 0;
     int stream = 0;
+    // a large job's per-node launches: its buffer in the pool, pinned staging
+    bool large = false;
+    unsigned char* base = nullptr;
+    void* stage = nullptr;
 };
 
 struct tn_server {
@@ -146,17 +156,36 @@ static const uint64_t kTableReserve = 64ull << 20;  // task tables of in-flight 
 
 static void complete(tn_server* s, InFlight& f) {
     std::vector<tn_result> res;
-    batch_finish(f.L, res);
-    double t = now_s();
-    {
+    std::vector<tn_status> sts;
+    if (f.large) {
+        tn_solve_opts o;
+        std::vector<PassSpec> passes;
+        SolveLayout L;
+        {
+            std::lock_guard<std::mutex> g(s->mu);  // the job table may rehash while submits come in
+            const ServerJob& j = s->jobs[f.ids[0]];
+            o = j.opts;
+            passes = j.passes;
+            L = j.layout;
+        }
+        std::vector<unsigned char> all((unsigned char*)f.stage, (unsigned char*)f.stage + L.acc_bytes);
+        res.assign(1, tn_result{});
+        sts.push_back(decode_root(o, passes, all, L.nent, 0, res[0]));
+        std::lock_guard<std::mutex> g(s->dev);
+        s->pool.release(f.base, L.need);
+        pinned_release(s->ctx, f.stage);
+    } else {
+        batch_finish(f.L, res);
+        for (auto& it : f.L.items) sts.push_back(it.status);
         std::lock_guard<std::mutex> g(s->dev);
         batch_release(f.L);
     }
+    double t = now_s();
     std::lock_guard<std::mutex> g(s->mu);
     for (size_t k = 0; k < f.ids.size(); k++) {
         ServerJob& j = s->jobs[f.ids[k]];
         j.res = res[k];
-        j.st = f.L.items[k].status;
+        j.st = sts[k];
         j.res.seconds = t - j.t_submit;
         j.latency = t - j.t_submit;
         j.state = 2;
@@ -197,9 +226,11 @@ static void scheduler(tn_server* s) {
                 ServerJob& j = s->jobs[s->queue.front()];
                 if (s->running + (int)ids.size() >= s->max_slots) break;
                 if (s->admitted + bytes + j.bytes > s->budget) break;
+                if (j.large && !ids.empty()) break;  // a large job goes out alone
                 bytes += j.bytes;
                 ids.push_back(j.id);
                 s->queue.pop_front();
+                if (j.large) break;
             }
             if (ids.empty()) {
                 // nothing admissible: sleep until a submit or a completion poll
@@ -213,18 +244,26 @@ static void scheduler(tn_server* s) {
             if (s->running > s->stats.peak_running) s->stats.peak_running = s->running;
             for (auto id : ids) s->jobs[id].state = 1;
         }
-        // 3. one persistent launch for this admission round
+        // 3. one persistent launch for this admission round (or a large job's
+        // per-node launches)
         std::vector<BatchItem> items;
+        ServerJob lj;  // a copy of the large job's launch data (the table may rehash)
+        bool is_large = false;
         {
             std::lock_guard<std::mutex> g(s->mu);
             for (auto id : ids) {
                 ServerJob& j = s->jobs[id];
                 items.push_back({j.net, j.plan, j.opts});
+                if (j.large) {
+                    lj = j;
+                    is_large = true;
+                }
             }
         }
         InFlight f;
         f.ids = ids;
         f.bytes = bytes;
+        f.large = is_large;
         DevAllocFn alloc;
         alloc.alloc = [s](size_t n) { return s->pool.alloc(n); };
         alloc.free = [s](void* p, size_t n) { s->pool.release(p, n); };
@@ -246,8 +285,24 @@ static void scheduler(tn_server* s) {
         f.stream = si;
         {
             std::lock_guard<std::mutex> g(s->dev);
-            st = batch_prepare(s->ctx, items, f.L, alloc);
-            if (st == TN_OK) st = batch_launch(s->ctx, f.L, stream);
+            if (is_large) {
+                const SolveLayout& L = lj.layout;
+                f.base = (unsigned char*)s->pool.alloc(L.need);
+                f.stage = f.base ? pinned_acquire(s->ctx, std::max<size_t>(L.acc_bytes, sizeof(float) *
+                                                                                         lj.net->wdev.size()) + 64)
+                                 : nullptr;
+                if (!f.base || !f.stage) {
+                    if (f.base) s->pool.release(f.base, L.need);
+                    f.base = nullptr;
+                    st = TN_ENOMEM;
+                } else {
+                    st = run_solve_on(s->ctx, stream, true, *lj.net, *lj.plan, lj.opts, lj.passes, lj.dp, f.base, L,
+                                      0, 1, f.stage, nullptr);
+                }
+            } else {
+                st = batch_prepare(s->ctx, items, f.L, alloc);
+                if (st == TN_OK) st = batch_launch(s->ctx, f.L, stream);
+            }
         }
         if (st == TN_ENOMEM) {  // pool fragmented: requeue at the front, retry after completions
             std::lock_guard<std::mutex> g(s->dev);
@@ -278,6 +333,8 @@ static void scheduler(tn_server* s) {
                 std::lock_guard<std::mutex> g(s->dev);
                 (void)hipStreamSynchronize(stream);
                 batch_release(f.L);
+                if (f.base) s->pool.release(f.base, lj.layout.need);
+                if (f.stage) pinned_release(s->ctx, f.stage);
             }
             std::lock_guard<std::mutex> g(s->mu);
             for (auto id : ids) {
@@ -355,21 +412,24 @@ tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
         std::vector<PassSpec> passes;
         tn_status st = make_passes(net->net, *o, passes);
         if (st != TN_OK) return st;
-        uint64_t bytes = job_device_bytes(net->net, plan->plan, *o);
-        if (bytes > s->budget) {
-            std::lock_guard<std::mutex> g(s->mu);
-            s->stats.rejected++;
-            return fail(TN_ETOOBIG, "job needs " + std::to_string(bytes) + " device bytes, above the budget");
-        }
+        const bool large = !use_persistent(plan->plan);
+        DevProgram* dp = nullptr;
+        SolveLayout layout;
         {
             // upload the plan's device program now, on the caller's thread
             std::lock_guard<std::mutex> g(s->dev);
-            DevProgram* dp = nullptr;
             if (plan->plan.nleaf() > 0) {
                 st = get_program(s->ctx, plan->plan, dp);
                 if (st != TN_OK) return st;
                 for (auto& ps : passes) node_launches(*dp, plan->plan, ps.dsr);
             }
+            if (large) layout = solve_layout(net->net, plan->plan, passes, dp, false);
+        }
+        uint64_t bytes = large ? layout.need : job_device_bytes(net->net, plan->plan, *o);
+        if (bytes > s->budget) {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stats.rejected++;
+            return fail(TN_ETOOBIG, "job needs " + std::to_string(bytes) + " device bytes, above the budget");
         }
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stop) return fail(TN_ECANCELED, "server is shutting down");
@@ -381,6 +441,10 @@ tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
         j.opts.primes = nullptr;  // the default primes; caller arrays may not outlive the call
         if (o->primes) return fail(TN_EINVAL, "served jobs use the default primes");
         j.bytes = bytes;
+        j.large = large;
+        j.dp = dp;
+        j.passes = passes;
+        j.layout = layout;
         j.t_submit = now_s();
         s->jobs[j.id] = j;
         s->queue.push_back(j.id);
@@ -416,7 +480,12 @@ tn_status tn_server_job_bytes(const tn_net* net, const tn_plan* plan, const tn_s
         std::vector<PassSpec> passes;
         tn_status st = make_passes(net->net, *o, passes);
         if (st != TN_OK) return st;
-        *bytes = job_device_bytes(net->net, plan->plan, *o);
+        if (use_persistent(plan->plan)) {
+            *bytes = job_device_bytes(net->net, plan->plan, *o);
+        } else {
+            DevProgram host_only;  // launch shapes only: nothing goes to the device
+            *bytes = solve_layout(net->net, plan->plan, passes, plan->plan.nleaf() > 0 ? &host_only : nullptr, false).need;
+        }
         return TN_OK;
     } catch (...) {
         return fail(TN_ENOMEM, "job size failed");

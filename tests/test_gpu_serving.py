@@ -98,7 +98,9 @@ def test_cancel_queued_jobs_and_refuse_oversized(ctx):
         except tn.TnError as e:
             assert e.code == tn.TN_EBUSY
     srv.drain()
-    assert srv.poll(first) is not None
+    r = srv.poll(first)  # a large tree: served alone on per-node launches
+    want = ctx.solve(net, big, "counting_tropical")
+    assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count_mod_2_64"])
     for jid in queued:
         if jid in cancelled:
             with pytest.raises(tn.TnError) as ei:
@@ -115,6 +117,35 @@ def test_cancel_queued_jobs_and_refuse_oversized(ctx):
     assert ei.value.code == tn.TN_ETOOBIG
     assert tiny.stats()["rejected"] == 1
     tiny.close()
+
+
+def test_large_trees_leave_the_persistent_launch(ctx):
+    """Trees with more than 2^27 ops per pass run on per-node launches in a
+    batch and in the server, with the same results as alone; small ones
+    share the persistent launch."""
+    small = _jobs(6, seed=9, n_lo=30, n_hi=60)
+    bigs = []
+    for n in (140, 150):
+        g = gg.random_regular(n, 3, n)
+        net = tn.Net.from_graph(g)
+        plan = tn.Plan.create(net, seed=1)
+        assert plan.complexity()[0] > 27
+        bigs.append((g, net, plan, "tropical_i32"))
+    jobs = small[:3] + bigs[:1] + small[3:] + bigs[1:]
+    alone = [ctx.solve(net, plan, sr) for _, net, plan, sr in jobs]
+    mixed = ctx.solve_batch([j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs])
+    for a, m in zip(alone, mixed):
+        assert _key(a) == _key(m)
+    srv = tn.Server(ctx, 8 << 30, max_slots=16)
+    ids = [srv.submit(net, plan, sr) for _, net, plan, sr in jobs]
+    srv.drain()
+    for jid, a in zip(ids, alone):
+        assert _key(srv.poll(jid)) == _key(a)
+    st = srv.stats()
+    srv.close()
+    assert st["launches"] >= 3  # the large ones went out alone
+    for (g, _, _, sr), a in zip(bigs, alone[3:4] + alone[-1:]):
+        assert a["size"] == oracle.eliminate(g, "tropical", max_width=26)["size"]
 
 
 def test_wait_limit_abandons_the_launch_and_the_context_recovers(ctx):
