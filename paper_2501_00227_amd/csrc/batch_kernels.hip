@@ -105,6 +105,10 @@ __device__ __attribute__((always_inline)) void run_gemm(const BJob& j, const BNo
             return;
         }
         if constexpr (is_z<D>()) {
+            if (nd.g.mfma == 2) {
+                gemm_tile_mfma128<D>(g, (u64)tile, smem);
+                return;
+            }
             if (nd.g.mfma) {
                 gemm_tile_mfma<D>(g, (u64)tile, smem);
                 return;

@@ -268,6 +268,12 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g) {
     gemm_tile_mfma<D>(g, blockIdx.x, smem);
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void gemm_mfma128_kernel(GemmArgs g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    gemm_tile_mfma128<D>(g, blockIdx.x, smem);
+}
+
 // Dynamic LDS of the LDS-staged tile kernel: the A and B tiles of one K step
 // (rows padded as the kernel pads them).
 static long long tiled_lds_bytes(int dsr, int tb, int ti, int tj, int tk) {
@@ -346,6 +352,13 @@ GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t,
         // four workgroups' operand tiles fit in one CU's LDS
         const int tkmax = (bti == 8 || btj == 8) ? 4 : 5;
         g.tk = lk < tkmax ? lk : tkmax;
+    } else if ((dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) && li >= 7 && lj >= 7 && lk >= (dsr == DSR_Z_BF16 ? 5 : 4)) {
+        // partition function on the matrix cores, 128 x 128 tiles
+        g.rm = g.rn = 4;
+        g.ti = g.tj = 7;
+        g.tb = 0;
+        g.tk = dsr == DSR_Z_BF16 ? 5 : 4;
+        g.mfma = 2;
     } else if (!topk && li >= 6 && lj >= 6 && lk >= 4) {
         // contraction-heavy node: 64x64 tile, 4x4 per thread (or one 32x32
         // matrix-core block per wave for the partition function)
@@ -421,8 +434,13 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
         if (g.tk < 1 || g.tk > 5 || g.tk + g.lsplit > g.lk || g.li < g.ti || g.lj < g.tj) return false;
         return true;
     }
-    if (g.mfma) {
+    if (g.mfma == 2) {  // 128 x 128 matrix-core tiles, fixed K step
         if (dsr != DSR_Z_F32 && dsr != DSR_Z_BF16) return false;
+        return g.ti == 7 && g.tj == 7 && g.tb == 0 && g.rm == 4 && g.rn == 4 && g.li >= 7 && g.lj >= 7 &&
+               g.tk == (dsr == DSR_Z_BF16 ? 5 : 4) && g.lsplit >= 0 && g.tk + g.lsplit <= g.lk;
+    }
+    if (g.mfma) {
+        if (g.mfma != 1 || (dsr != DSR_Z_F32 && dsr != DSR_Z_BF16)) return false;
         if (g.ti != 6 || g.tj != 6 || g.tb != 0) return false;
         if (g.tk < (dsr == DSR_Z_BF16 ? 4 : 1)) return false;
     }
@@ -438,6 +456,7 @@ bool gemm_shape_valid(int dsr, const GemmShape& g) {
 
 size_t gemm_lds_bytes(int dsr, const GemmShape& g) {
     if (g.mode == GEMM_DOT) return 256 * (size_t)lds_elem_bytes(dsr);
+    if (g.mfma == 2) return dsr == DSR_Z_BF16 ? Mfma128<DSR_Z_BF16>::LDS : Mfma128<DSR_Z_F32>::LDS;
     if (g.mode == GEMM_THIN) return ((size_t)1 << (g.lk + g.lj)) * lds_elem_bytes(dsr);
     if (g.rm == 8)
         return (size_t)(1 << g.tk) * (((1 << g.ti) + 4) + ((1 << g.tj) + 4)) * (dsr == DSR_CTROP ? 12 : 4);
@@ -515,6 +534,13 @@ hipError_t launch_gemm(int dsr, Planes Ap, Planes Bp, Planes Cp, Planes part, co
         if (dsr == DSR_TROP_I32) return gemm_big_go<DSR_TROP_I32>(a, lds, blocks, s);
         if (dsr == DSR_TROP_F32) return gemm_big_go<DSR_TROP_F32>(a, lds, blocks, s);
         return gemm_big_go<DSR_MODP>(a, lds, blocks, s);
+    }
+    if (g.mfma == 2) {
+        if (dsr == DSR_Z_F32)
+            gemm_mfma128_kernel<DSR_Z_F32><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        else
+            gemm_mfma128_kernel<DSR_Z_BF16><<<dim3((unsigned)blocks), dim3(256), lds, s>>>(a);
+        return hipGetLastError();
     }
     if (g.mfma) {
         if (dsr == DSR_Z_F32)

@@ -1236,6 +1236,180 @@ __device__ void gemm_tile_mfma(const GemmArgs& g, u64 tile, unsigned char* smem)
     z_epilogue<D>(g, tile, lmax);
 }
 
+// Partition function on the matrix cores, large tiles: a 128 x 128 output
+// tile, four waves in a 2 x 2 grid, each wave 64 x 64 as 2 x 2 blocks of
+// 32 x 32 (so every A fragment serves two B fragments and back).  Operand
+// tiles sit in LDS with k contiguous per row (A as [i][k], B as [j][k], rows
+// padded by 16 bytes), written once per K step from 16-byte global loads that
+// were issued before the previous step's MFMAs (two LDS buffers, one barrier
+// per step).  The sum over k may take any order as long as A and B agree: in
+// float32 (TK = 16, v_mfma_f32_32x32x2f32) lane half h feeds k = h*8 + s to
+// step s, so a lane reads its eight k of a step block with two 16-byte LDS
+// loads; in bfloat16 (TK = 32, v_mfma_f32_32x32x16_bf16, values rounded and
+// packed to 16 bits when staged) lane half h feeds k = h*16 + 8*s .. +7 to
+// step s, one 16-byte load per step.
+template <int D>
+struct Mfma128 {
+    static constexpr bool kBf16 = D == DSR_Z_BF16;
+    static constexpr int TK = kBf16 ? 32 : 16;            // k per LDS step
+    static constexpr int EB = kBf16 ? 2 : 4;              // bytes per staged value
+    static constexpr int ROW = TK * EB + 16;               // padded row bytes
+    static constexpr int OPB = 128 * ROW;                  // one operand tile
+    static constexpr int BUF = 2 * OPB;                    // A and B
+    static constexpr int LDS = 2 * BUF;                    // two buffers
+    static constexpr int NV = 128 * TK / 4 / 256;          // float4 loads per thread per operand
+};
+
+__device__ inline unsigned int bf16_bits(float x) { return __float_as_uint(x) >> 16; }
+
+template <int D>
+__device__ void gemm_tile_mfma128(const GemmArgs& g, u64 tile, unsigned char* smem) {
+    static_assert(is_z<D>(), "matrix cores serve the real algebra only");
+    using M = Mfma128<D>;
+    using A = Alg<D>;
+    constexpr int TK = M::TK, NV = M::NV;
+    const TilePos p = tile_pos(g, tile);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1, half = lane >> 5, l32 = lane & 31;
+    const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    // global -> register prefetch of one K step: NV float4 per operand per
+    // thread; element e = tid + 256 v of the 128 x TK tile, 4 values each
+    float4 ra[NV], rb[NV];
+    auto fetch = [&](i64 k0) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int e = tid + 256 * v;
+            i64 addr;
+            if (!g.a_t) {  // (b, i, k): 4 consecutive k of row i
+                const int i = e / (TK / 4), k = 4 * (e % (TK / 4));
+                addr = (((p.b0 << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
+            } else {  // (b, k, i): 4 consecutive rows at one k
+                const int k = e / 32, i = 4 * (e % 32);
+                addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
+            }
+            ra[v] = *(const float4*)((const float*)g.A.p0 + addr);
+            if (!g.b_t) {  // (b, k, j): 4 consecutive columns at one k
+                const int k = e / 32, j = 4 * (e % 32);
+                addr = (((p.b0 << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
+            } else {  // (b, j, k): 4 consecutive k of column j
+                const int j = e / (TK / 4), k = 4 * (e % (TK / 4));
+                addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
+            }
+            rb[v] = *(const float4*)((const float*)g.B.p0 + addr);
+        }
+    };
+    // registers -> LDS buffer `buf` ([row][k], k contiguous), scaled (and
+    // rounded to bfloat16 and packed)
+    auto put = [&](int buf) {
+        unsigned char* As = smem + buf * M::BUF;
+        unsigned char* Bs = As + M::OPB;
+        auto put4 = [&](unsigned char* base, bool along_k, int e, float4 x, float s) {
+            const float v[4] = {A::prescale(x.x, s), A::prescale(x.y, s), A::prescale(x.z, s), A::prescale(x.w, s)};
+            if (along_k) {
+                const int r = e / (TK / 4), k = 4 * (e % (TK / 4));
+                unsigned char* q = base + r * M::ROW + k * M::EB;
+                if constexpr (M::kBf16) {
+                    uint2 u;
+                    u.x = bf16_bits(v[0]) | (bf16_bits(v[1]) << 16);
+                    u.y = bf16_bits(v[2]) | (bf16_bits(v[3]) << 16);
+                    *(uint2*)q = u;
+                } else {
+                    *(float4*)q = make_float4(v[0], v[1], v[2], v[3]);
+                }
+            } else {
+                const int k = e / 32, r = 4 * (e % 32);
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    unsigned char* q = base + (r + t) * M::ROW + k * M::EB;
+                    if constexpr (M::kBf16)
+                        *(unsigned short*)q = (unsigned short)bf16_bits(v[t]);
+                    else
+                        *(float*)q = v[t];
+                }
+            }
+        };
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int e = tid + 256 * v;
+            put4(As, !g.a_t, e, ra[v], sA);
+            put4(Bs, g.b_t != 0, e, rb[v], sB);
+        }
+    };
+    tn_v16f acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[bi][bj][r] = 0.0f;
+    const int nsteps = p.Kc / TK;
+    fetch(p.kbeg);
+    put(0);
+    __syncthreads();
+    for (int st = 0; st < nsteps; st++) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) fetch(p.kbeg + (i64)(st + 1) * TK);  // in flight during the MFMAs below
+        const unsigned char* As = smem + buf * M::BUF;
+        const unsigned char* Bs = As + M::OPB;
+        if constexpr (M::kBf16) {
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                tn_v8s a[2], b[2];
+#pragma unroll
+                for (int x = 0; x < 2; x++) {
+                    a[x] = *(const tn_v8s*)(As + (wr * 64 + x * 32 + l32) * M::ROW + (half * 16 + 8 * s) * 2);
+                    b[x] = *(const tn_v8s*)(Bs + (wc * 64 + x * 32 + l32) * M::ROW + (half * 16 + 8 * s) * 2);
+                }
+#pragma unroll
+                for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+                    for (int bj = 0; bj < 2; bj++)
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+            }
+        } else {
+            float4 a[2][2], b[2][2];  // [block][two float4 = eight k]
+#pragma unroll
+            for (int x = 0; x < 2; x++)
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    a[x][q] = *(const float4*)(As + (wr * 64 + x * 32 + l32) * M::ROW + (half * 8 + 4 * q) * 4);
+                    b[x][q] = *(const float4*)(Bs + (wc * 64 + x * 32 + l32) * M::ROW + (half * 8 + 4 * q) * 4);
+                }
+#pragma unroll
+            for (int s = 0; s < 8; s++) {
+#pragma unroll
+                for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+                    for (int bj = 0; bj < 2; bj++) {
+                        const float4& av = a[bi][s >> 2];
+                        const float4& bv = b[bj][s >> 2];
+                        const float ax = (s & 3) == 0 ? av.x : (s & 3) == 1 ? av.y : (s & 3) == 2 ? av.z : av.w;
+                        const float bx = (s & 3) == 0 ? bv.x : (s & 3) == 1 ? bv.y : (s & 3) == 2 ? bv.z : bv.w;
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(ax, bx, acc[bi][bj], 0, 0, 0);
+                    }
+            }
+        }
+        if (st + 1 < nsteps) put(buf ^ 1);  // the other buffer: last read before the previous barrier
+        __syncthreads();
+    }
+    const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
+    float* dst = (float*)(g.lsplit ? g.P.p0 : g.C.p0) + (g.lsplit ? (i64)p.split * nout : 0);
+    float lmax = 0.0f;
+#pragma unroll
+    for (int bi = 0; bi < 2; bi++)
+#pragma unroll
+        for (int bj = 0; bj < 2; bj++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int row = wr * 64 + bi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                const int col = wc * 64 + bj * 32 + l32;
+                const i64 o = (((p.b0 << g.li) | (p.i0 + row)) << g.lj) | (p.j0 + col);
+                dst[o] = acc[bi][bj][r];
+                lmax = fmaxf(lmax, acc[bi][bj][r]);
+            }
+    z_epilogue<D>(g, tile, lmax);
+}
+
 // ----------------------------------------------------- thin / dot GEMM --
 // Thin node (GEMM_THIN): a tile is 2^ti (>= 1024) consecutive rows of one
 // batch; B (K x N <= 32 entries) is staged in LDS.  Each thread takes four

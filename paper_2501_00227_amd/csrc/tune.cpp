@@ -80,6 +80,7 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 const char* gemm_kernel_name(int dsr, const GemmShape& g, char* buf, size_t cap) {
     if (g.mode == GEMM_THIN) snprintf(buf, cap, "gemm_thin_kernel<%d>", dsr);
     else if (g.mode == GEMM_DOT) snprintf(buf, cap, "gemm_dot_kernel<%d>", dsr);
+    else if (g.mfma == 2) snprintf(buf, cap, "gemm_mfma128_kernel<%d>", dsr);
     else if (g.mfma) snprintf(buf, cap, "gemm_mfma_kernel<%d>", dsr);
     else if (g.rm == 8 && dsr == DSR_CTROP) snprintf(buf, cap, "gemm_ct_big_kernel<%d, %d>", g.ti, g.tj);
     else if (g.rm == 8) snprintf(buf, cap, "gemm_big_kernel<%d, %d, %d>", dsr, g.ti, g.tj);
@@ -135,7 +136,18 @@ std::vector<GemmShape> tune_candidates(int dsr, int lb, int li, int lj, int lk, 
                 g.lsplit = ls;
                 push(g);
             }
-    // matrix cores (real algebra)
+    // matrix cores (real algebra): 128 x 128 tiles, then 64 x 64
+    if (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16)
+        for (int ls : lsplits) {
+            GemmShape g{};
+            g.mode = GEMM_TILED;
+            g.mfma = 2;
+            g.rm = g.rn = 4;
+            g.ti = g.tj = 7;
+            g.tk = dsr == DSR_Z_BF16 ? 5 : 4;
+            g.lsplit = ls;
+            push(g);
+        }
     if (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16)
         for (int tk = 1; tk <= 5; tk++)
             for (int ls : lsplits) {
