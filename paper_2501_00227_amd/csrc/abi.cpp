@@ -383,7 +383,7 @@ tn_status tn_plan_peak_bytes(const tn_plan* p, tn_semiring sr, uint64_t* bytes) 
     const bool dag = use_persistent(pl);  // the dependency-graph executor keeps every partial separate
     uint64_t part = 0;
     for (auto& np : pl.prog) {
-        GemmShape g = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+        GemmShape g = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t, dag);
         if (!g.lsplit) continue;
         uint64_t n = 1ull << (g.lsplit + np.lb + np.li + np.lj);
         part = dag ? part + ((n + 63) & ~63ull) : std::max<uint64_t>(part, n);

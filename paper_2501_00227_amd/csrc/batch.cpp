@@ -79,20 +79,27 @@ double task_cost(const BTask& t, const std::vector<BNode>& bn, const std::vector
     }
 }
 
-// Rank of every task in a critical-path-first topological order (tasks are
-// created in a topological order: every producer before its consumers).
-std::vector<int> critical_path_order(const std::vector<BTask>& bt, const std::vector<BNode>& bn,
-                                     const std::vector<int>& subtree, int ncounters) {
+// Rank of every task in an earliest-start-first order: a simulation of
+// `workers` workgroups that each take the next ticket when free, as the
+// device does.  A task enters the candidates once all its producers hold
+// tickets (so producers always precede consumers), with an estimated ready
+// time (its counters' last producer end plus a signalling latency); the free
+// workgroup takes, among the candidates ready by then, the one with the
+// largest bottom level, else the one ready first.  Unlike a plain
+// critical-path order, a task whose inputs are still far off does not hold a
+// workgroup (and the tickets behind it) while work that could run waits.
+std::vector<int> earliest_start_order(const std::vector<BTask>& bt, const std::vector<BNode>& bn,
+                                      const std::vector<int>& subtree, int ncounters, int workers) {
+    constexpr double kSignalLatency = 2.0;  // microseconds from a producer's end to a waiter's start
     const int n = (int)bt.size();
-    std::vector<double> blevel(n, 0.0), cblevel(ncounters, 0.0);
-    for (int k = n - 1; k >= 0; k--) {  // consumers first
+    std::vector<double> cost(n), blevel(n, 0.0), cblevel(ncounters, 0.0);
+    for (int k = n - 1; k >= 0; k--) {
         const BTask& t = bt[k];
-        blevel[k] = task_cost(t, bn, subtree) + (t.signal >= 0 ? cblevel[t.signal] : 0.0);
+        cost[k] = task_cost(t, bn, subtree);
+        blevel[k] = cost[k] + (t.signal >= 0 ? cblevel[t.signal] : 0.0);
         for (int d : {t.dep0, t.dep1})
             if (d >= 0) cblevel[d] = std::max(cblevel[d], blevel[k]);
     }
-    // Kahn's algorithm over counters: a task is ready once each of its
-    // counters has had all its producers emitted
     std::vector<int> producers_left(ncounters, 0), waiting(n, 0);
     std::vector<std::vector<int>> waiters(ncounters);
     for (int k = 0; k < n; k++) {
@@ -104,20 +111,40 @@ std::vector<int> critical_path_order(const std::vector<BTask>& bt, const std::ve
                 waiting[k]++;
             }
     }
-    auto cmp = [&](int a, int b) { return blevel[a] != blevel[b] ? blevel[a] < blevel[b] : a > b; };
-    std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
+    std::vector<double> cdone(ncounters, 0.0);
+    using RK = std::pair<double, int>;
+    std::priority_queue<RK, std::vector<RK>, std::greater<RK>> pending;  // (estimated ready, task)
+    std::priority_queue<RK> avail;                                        // (bottom level, -task)
+    std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+    for (int w = 0; w < std::max(workers, 1); w++) free_at.push(0.0);
     for (int k = 0; k < n; k++)
-        if (!waiting[k]) ready.push(k);
+        if (!waiting[k]) pending.push({0.0, k});
     std::vector<int> rank(n, 0);
     int next = 0;
-    while (!ready.empty()) {
-        const int k = ready.top();
-        ready.pop();
+    while (!pending.empty() || !avail.empty()) {
+        double start = free_at.top();
+        if (avail.empty() && pending.top().first > start) start = pending.top().first;
+        while (!pending.empty() && pending.top().first <= start) {
+            avail.push({blevel[pending.top().second], -pending.top().second});
+            pending.pop();
+        }
+        const int k = -avail.top().second;
+        avail.pop();
+        free_at.pop();
+        const double end = start + cost[k];
+        free_at.push(end);
         rank[k] = next++;
         const int c = bt[k].signal;
-        if (c >= 0 && --producers_left[c] == 0)
+        if (c < 0) continue;
+        cdone[c] = std::max(cdone[c], end);
+        if (--producers_left[c] == 0)
             for (int w : waiters[c])
-                if (--waiting[w] == 0) ready.push(w);
+                if (--waiting[w] == 0) {
+                    double r = 0.0;
+                    for (int d : {bt[w].dep0, bt[w].dep1})
+                        if (d >= 0) r = std::max(r, cdone[d] + kSignalLatency);
+                    pending.push({r, w});
+                }
     }
     for (int k = 0; k < n; k++)  // unreachable with a well-formed table; keep every task in a valid place
         if (waiting[k]) rank[k] = next++;
@@ -146,7 +173,7 @@ struct JobTemplate {
     std::vector<int> subtree;
     int ncounters = 0;
     double ops = 0, bytes = 0, work = 0;
-    std::vector<int> order;  // task indices in critical-path-first order
+    std::vector<int> order;  // task indices in earliest-start-first order
     int bn0 = -1, sub0 = 0;  // where the launch holds its nodes and subtree lists (shared by its jobs)
 };
 
@@ -198,7 +225,7 @@ void build_template(const JobPlan& jp, int fuse_rank, JobTemplate& T) {
         const NodeProg& np = p.prog[t];
         const NodeLaunch& nl = jp.ls->nodes[t];
         BNode N{};
-        N.g = nl.shape;
+        N.g = nl.shape;  // chiplet-scope shape: never the 128 x 128 matrix-core tiles
         N.ma = np.a;
         N.mb = np.b;
         N.mc = np.node;
@@ -397,7 +424,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
             jp.prime = st.passes[p].prime;
             jp.xval = st.passes[p].xval;
             jp.dp = dp;
-            jp.ls = dp ? &node_launches(*dp, *it.plan, jp.dsr) : nullptr;
+            jp.ls = dp ? &node_launches(*dp, *it.plan, jp.dsr, true) : nullptr;
             jp.E = std::max<int64_t>(it.plan->arena_entries_dag, 64);
             jp.Pe = dp ? jp.ls->part_entries_dag : 0;
             int pb0 = plane_bytes(jp.dsr, 0), pb1 = plane_bytes(jp.dsr, 1);
@@ -440,6 +467,11 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
     std::vector<BTask> bt;
     int ncounters = 0;
     const int fuse_rank = small_rank(jobs.size(), device_cu_count(ctx) * 2);
+    // workgroups one job template's tasks share in the schedule simulation:
+    // one chiplet's, divided among the jobs its queue holds
+    const int nq_sched = std::max(1, std::min(16, device_cu_count(ctx) / 32));
+    const int jobs_per_q = (int)((jobs.size() + (size_t)nq_sched - 1) / (size_t)nq_sched);
+    const int order_workers = std::max(1, device_cu_count(ctx) * 2 / nq_sched / std::max(1, jobs_per_q));
     // one template per (plan, algebra); the templates are independent of each
     // other, so a large launch builds them on several host threads
     std::map<std::pair<const Plan*, int>, JobTemplate> templates;
@@ -452,7 +484,7 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         auto build = [&](size_t u) {
             JobTemplate& T = *todo[u].first;
             build_template(jobs[todo[u].second], fuse_rank, T);
-            const std::vector<int> rank = critical_path_order(T.bt, T.bn, T.subtree, T.ncounters);
+            const std::vector<int> rank = earliest_start_order(T.bt, T.bn, T.subtree, T.ncounters, order_workers);
             T.order.assign(T.bt.size(), 0);
             for (size_t k = 0; k < rank.size(); k++) T.order[(size_t)rank[k]] = (int)k;
             T.work = 2.0e4 * (double)T.bt.size();
@@ -537,10 +569,11 @@ tn_status batch_prepare(tn_ctx* ctx, std::vector<BatchItem>& items, BatchLaunch&
         qload[best] += job_tmpl[j]->work;
     }
     // ticket order inside a queue.  Each job's tasks follow its template's
-    // critical-path-first order: every task has a rough cost (per-workgroup
+    // earliest-start-first order: every task has a rough cost (per-workgroup
     // rates) and a bottom level (its cost plus the longest chain of dependent
-    // tasks after it), and the order always takes the ready task with the
-    // largest bottom level.  The jobs of a queue are interleaved position by
+    // tasks after it); a simulation of the queue's workgroups hands the next
+    // ticket to the task that can start first, the largest bottom level
+    // among those ready.  The jobs of a queue are interleaved position by
     // position in proportion to their lengths, so every producer precedes its
     // consumers and a waiting workgroup only waits on smaller tickets of its
     // queue.

@@ -49,16 +49,18 @@ struct BNode {  // one inner node; jobs of the same plan and algebra share it (o
 };
 
 struct BTask {
+    // the dependencies first: one aligned 16-byte load on the device
+    int dep0, need0;  // wait until counters[dep0] >= need0 (dep0 < 0: none)
+    int dep1, need1;
     int kind;
     int job;
     int node;    // index into the BNode table (GEMM/PERM/REDUCE); SUBTREE: offset in the subtree list
     int aux;     // PERM: side*2 + plane; SUBTREE: number of nodes
     int64_t tile;  // first tile (GEMM/PERM) or reduction unit; ACCUM: root arena offset
-    int dep0, dep1;
-    int need0, need1;
     int signal;  // counter to bump when done (-1: none)
     int count;   // tiles / units this task runs, from `tile` on
 };
+static_assert(sizeof(BTask) == 48, "three 16-byte loads per task");
 
 // Tasks are grouped into one queue per XCC (chiplet): queue q holds tasks
 // [qbegin[q], qbegin[q] + qcount[q]) in level order, served by the

@@ -25,29 +25,45 @@ static_assert(((sizeof(PermLds) + 255) & ~(size_t)255) + kPermTile * 8 <= kBatch
 //
 // Every wait is bounded: a wait longer than `limit` ticks of the constant
 // wall clock, or any wait while the launch's abort flag is set, sets the flag
-// and gives up; the workgroup then leaves the launch and every other
-// workgroup leaves at its next ticket or wait, so the kernel always ends and
-// the host reports the launch as failed.  Returns false on giving up.
-__device__ inline bool wait_counters(const int* counters, int d0, int n0, int d1, int n1, int* abort_flag,
+// and gives up; the workgroup then leaves the launch.  Every other workgroup
+// either runs its next tasks (their inputs are complete) or reaches a wait
+// that sees the flag and leaves too, so the kernel always ends and the host
+// reports the launch as failed.  The flag and the clock are read only once a
+// counter has been found short, and then every 16th poll, so a dependency
+// that is already met costs one load.  The first wave polls with the
+// counter's value made wave-uniform, so the loop branches on scalars.
+__device__ inline bool wait_one(const int* counters, int d, int need, int* abort_flag, long long limit) {
+    if (d < 0) return true;
+    auto have = [&] {
+        return __builtin_amdgcn_readfirstlane(
+                   __hip_atomic_load(&counters[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >= need;
+    };
+    if (have()) return true;
+    const long long t0 = wall_clock64();
+    for (int poll = 1;; poll++) {
+        __builtin_amdgcn_s_sleep(1);
+        if (have()) return true;
+        if ((poll & 15) == 0 &&
+            (__builtin_amdgcn_readfirstlane(__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0 ||
+             wall_clock64() - t0 > limit)) {
+            if ((threadIdx.x & 63) == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+}
+
+// Returns false on giving up.  Out of line: the task loop keeps its values
+// in registers that calls preserve, and inlined there the poll loop reloaded
+// spilled values from scratch on every poll.
+__attribute__((noinline)) __device__ bool wait_counters(const int* counters, int d0, int n0, int d1, int n1, int* abort_flag,
                                      long long limit) {
     __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const long long t0 = wall_clock64();
-        const int dep[2] = {d0, d1}, need[2] = {n0, n1};
-        for (int u = 0; u < 2 && ok; u++) {
-            if (dep[u] < 0) continue;
-            while (__hip_atomic_load(&counters[dep[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need[u]) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                    wall_clock64() - t0 > limit) {
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        s_ok = ok;
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x) < 64) {  // the first wave (a wave-uniform branch)
+        // wave-uniform arguments (the call passes them in vector registers)
+        d0 = __builtin_amdgcn_readfirstlane(d0), n0 = __builtin_amdgcn_readfirstlane(n0);
+        d1 = __builtin_amdgcn_readfirstlane(d1), n1 = __builtin_amdgcn_readfirstlane(n1);
+        const bool ok = wait_one(counters, d0, n0, abort_flag, limit) && wait_one(counters, d1, n1, abort_flag, limit);
+        if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
     }
     __syncthreads();
     const bool ok = s_ok != 0;
@@ -104,11 +120,7 @@ __device__ __attribute__((always_inline)) void run_gemm(const BJob& j, const BNo
             gemm_tile_dot<D>(g, (u64)tile, smem);
             return;
         }
-        if constexpr (is_z<D>()) {
-            if (nd.g.mfma == 2) {
-                gemm_tile_mfma128<D>(g, (u64)tile, smem);
-                return;
-            }
+        if constexpr (is_z<D>()) {  // 64 x 64 matrix-core tiles only (the host never picks 128 x 128 here)
             if (nd.g.mfma) {
                 gemm_tile_mfma<D>(g, (u64)tile, smem);
                 return;
@@ -329,15 +341,13 @@ __global__ __launch_bounds__(256, 2) void batch_kernel(const BTask* __restrict__
     __shared__ int s_task;
     const int q = (int)(hw_xcc_id() % (unsigned)nq);
     const int qb = qbegin[q], qn = qcount[q];
-    int* abort_flag = tickets + nq;  // set when a wait gave up: every workgroup leaves
+    int* abort_flag = tickets + nq;  // set when a wait gave up: every workgroup leaves at its next wait
     for (;;) {
-        if (threadIdx.x == 0)
-            s_task = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0
-                         ? INT_MAX
-                         : atomicAdd(&tickets[q], 1);
+        if (threadIdx.x == 0) s_task = atomicAdd(&tickets[q], 1);
         __syncthreads();
-        const int tq = s_task;
-        __syncthreads();
+        // no second barrier: thread 0 writes s_task again only after the
+        // task's last barrier, which every wave passes after reading it here
+        const int tq = __builtin_amdgcn_readfirstlane(s_task);
         if (tq >= qn) break;  // every workgroup leaves once its queue's tickets run out
         const int ti = qb + tq;
         const unsigned long long t_start = trace ? wall_clock64() : 0ull;

@@ -328,8 +328,8 @@ tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp) {
     return TN_OK;
 }
 
-const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr) {
-    const int64_t key = (int64_t)(tune_generation() << 8) | dsr;
+const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr, bool chiplet) {
+    const int64_t key = chiplet ? -1 - (int64_t)dsr : (int64_t)(tune_generation() << 8) | dsr;
     auto it = dp.launch_sets.find(key);
     if (it != dp.launch_sets.end()) return it->second;
     LaunchSet ls;
@@ -338,7 +338,7 @@ const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr) {
     for (size_t t = 0; t < p.prog.size(); t++) {
         const NodeProg& np = p.prog[t];
         NodeLaunch& v = ls.nodes[t];
-        v.shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+        v.shape = choose_gemm_shape(dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t, chiplet);
         if (v.shape.lsplit > 0) v.part_entries = (int64_t)1 << (v.shape.lsplit + np.lb + np.li + np.lj);
         ls.part_entries = std::max(ls.part_entries, v.part_entries);
         // concurrent nodes of the dependency-graph executor need separate partials
@@ -596,7 +596,7 @@ SolveLayout solve_layout(const Net& net, const Plan& plan, const std::vector<Pas
     const int64_t E = std::max<int64_t>(plan.arena_entries, 64);
     int64_t Pe = 0;
     for (auto& ps : passes)
-        if (dp) Pe = std::max(Pe, node_launches(*dp, plan, ps.dsr).part_entries);
+        if (dp) Pe = std::max(Pe, node_launches(*dp, plan, ps.dsr, false).part_entries);
     for (auto& ps : passes) {
         L.pb0 = std::max(L.pb0, plane_bytes(ps.dsr, 0));
         L.pb1 = std::max(L.pb1, plane_bytes(ps.dsr, 1));
@@ -670,7 +670,7 @@ tn_status run_solve_on(tn_ctx* ctx, hipStream_t s, bool async, const Net& net, c
             chk(launch_set_one(dsr, acc, ap, s), "set one");
             continue;
         }
-        const auto& launches = node_launches(*dp, plan, dsr).nodes;
+        const auto& launches = node_launches(*dp, plan, dsr, false).nodes;
         for (int64_t sl = sb; sl < se && herr == hipSuccess; sl++) {
             if (is_z) chk(launch_meta_init(meta, nn, s), "meta init");
             {

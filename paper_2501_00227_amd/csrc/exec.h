@@ -116,7 +116,7 @@ tn_status get_programs(tn_ctx* ctx, const std::vector<const Plan*>& plans);
 tn_status ensure_wide_perms(tn_ctx* ctx, const Plan& p, DevProgram& dp);
 // Launch shapes of every node for one device algebra under the current
 // tuning table (cached in dp; the reference stays valid while dp lives).
-const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr);
+const LaunchSet& node_launches(DevProgram& dp, const Plan& p, int dsr, bool chiplet);
 // Tuning table (tune.cpp): generation (bumped by every change), tuning of a
 // plan's nodes, table file I/O.
 uint64_t tune_generation();

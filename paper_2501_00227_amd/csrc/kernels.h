@@ -137,11 +137,16 @@ hipError_t launch_backtrace(const float* arena, const int* nodes, int ninner, co
                             const long long* off, const int* lvl_off, const int* lvl_nodes, int nlevels, int* assign,
                             int* status, int nn, int nids, int nv, hipStream_t s);
 
-// Launch shape of a GEMM node: the entry of the tuning table for this node
-// shape if there is one (tune.cpp), else the fixed heuristic.  Either way the
-// shape depends on the node alone, never on the other work of a launch.
-GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);
-GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t);
+// Launch shape of a GEMM node.  For a per-node launch over the whole chip:
+// the entry of the tuning table for this node shape if there is one
+// (tune.cpp), else the fixed heuristic.  For a task of the persistent launch
+// (chiplet = true: the node's tiles share one chiplet's 32 CUs with the
+// job's other nodes) always the heuristic, without the 128 x 128
+// matrix-core tiles, which leave too few tiles to go round there; the table
+// was timed over the whole chip and does not apply.  Either way the shape
+// depends on the node alone, never on the other work of a launch.
+GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, bool chiplet = false);
+GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, bool mfma128 = true);
 bool gemm_shape_valid(int dsr, const GemmShape& g);
 size_t gemm_lds_bytes(int dsr, const GemmShape& g);
 // Name of the kernel (template instance) a launch of shape g runs, as in

@@ -280,7 +280,7 @@ static long long tiled_lds_bytes(int dsr, int tb, int ti, int tj, int tk) {
     return (1ll << (tb + tk)) * (pad_dim(1 << ti) + pad_dim(1 << tj)) * lds_elem_bytes(dsr);
 }
 
-GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
+GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, bool mfma128) {
     GemmShape g{};
     g.lb = lb;
     g.li = li;
@@ -352,7 +352,8 @@ GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t,
         // four workgroups' operand tiles fit in one CU's LDS
         const int tkmax = (bti == 8 || btj == 8) ? 4 : 5;
         g.tk = lk < tkmax ? lk : tkmax;
-    } else if ((dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) && li >= 7 && lj >= 7 && lk >= (dsr == DSR_Z_BF16 ? 5 : 4)) {
+    } else if (mfma128 && (dsr == DSR_Z_F32 || dsr == DSR_Z_BF16) && li >= 7 && lj >= 7 &&
+               lk >= (dsr == DSR_Z_BF16 ? 5 : 4)) {
         // partition function on the matrix cores, 128 x 128 tiles
         g.rm = g.rn = 4;
         g.ti = g.tj = 7;

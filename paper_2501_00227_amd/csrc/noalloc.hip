@@ -73,7 +73,7 @@ tn_status solve_noalloc(tn_ctx* ctx, const Net& net, const Plan& plan, const tn_
     if (dpp) {
         st = program_into(ctx, plan, base, dp);
         if (st != TN_OK) return st;
-        for (auto& ps : passes) node_launches(dp, plan, ps.dsr);
+        for (auto& ps : passes) node_launches(dp, plan, ps.dsr, false);
     }
     std::vector<unsigned char> stage(std::max<size_t>(L.acc_bytes, sizeof(float) * net.wdev.size()) + 64);
     std::vector<unsigned char> all;

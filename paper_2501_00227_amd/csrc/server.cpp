@@ -83,7 +83,7 @@ uint64_t job_device_bytes(const Net& net, const Plan& plan, const tn_solve_opts&
         uint64_t E = (uint64_t)std::max<int64_t>(plan.arena_entries_dag, 64);
         uint64_t Pe = 0;  // every split node has its own partials in the dependency-graph executor
         for (auto& np : plan.prog) {
-            GemmShape g = choose_gemm_shape(ps.dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t);
+            GemmShape g = choose_gemm_shape(ps.dsr, np.lb, np.li, np.lj, np.lk, np.a_t, np.b_t, true);
             if (g.lsplit) Pe += ((1ull << (g.lsplit + np.lb + np.li + np.lj)) + 63) & ~63ull;
         }
         total += a(E * pb0) + a(E * pb1) + a(Pe * pb0) + a(Pe * pb1) + a(sizeof(TensorMeta) * plan.nodes.size()) + a(16);
@@ -421,7 +421,7 @@ tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
             if (plan->plan.nleaf() > 0) {
                 st = get_program(s->ctx, plan->plan, dp);
                 if (st != TN_OK) return st;
-                for (auto& ps : passes) node_launches(*dp, plan->plan, ps.dsr);
+                for (auto& ps : passes) node_launches(*dp, plan->plan, ps.dsr, !large);
             }
             if (large) layout = solve_layout(net->net, plan->plan, passes, dp, false);
         }

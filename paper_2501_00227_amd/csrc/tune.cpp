@@ -68,7 +68,8 @@ uint64_t tune_generation() {
     return g_generation;
 }
 
-GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t) {
+GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, bool chiplet) {
+    if (chiplet) return heuristic_gemm_shape(dsr, lb, li, lj, lk, a_t, b_t, false);
     {
         std::lock_guard<std::mutex> l(g_mu);
         auto it = g_table.find(TuneKey{dsr, lb, li, lj, lk, a_t, b_t});
