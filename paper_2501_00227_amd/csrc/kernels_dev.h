@@ -996,9 +996,9 @@ constexpr int kCtNegInfBelow = -(1 << 29);   // results below this are -inf
 // acc += a * (bhi : blo) mod 2^64, with one 32 x 32 -> 64 multiply-add for
 // the low words and two 32-bit multiplies for the cross terms
 __device__ inline u64 mad_u64_mod(u64 acc, unsigned alo, unsigned ahi, unsigned blo, unsigned bhi) {
-    const unsigned cross = alo * bhi + ahi * blo;
     const u64 t = (u64)alo * blo + acc;
-    return t + ((u64)cross << 32);
+    const unsigned hi = (unsigned)(t >> 32) + alo * bhi + ahi * blo;  // cross terms touch the high word only
+    return ((u64)hi << 32) | (unsigned)t;
 }
 
 template <int LTM, int LTN>
