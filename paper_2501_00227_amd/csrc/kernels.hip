@@ -233,7 +233,7 @@ static hipError_t gemm_mode_go(const GemmArgs& a, int mode, size_t lds, u64 bloc
 }
 
 template <int LTM, int LTN>
-__global__ __launch_bounds__(256, 3) void gemm_ct_big_kernel(GemmArgs g) {
+__global__ __launch_bounds__(256, 2) void gemm_ct_big_kernel(GemmArgs g) {
     extern __shared__ __align__(16) unsigned char smem[];
     gemm_tile_ct_big<LTM, LTN>(g, blockIdx.x, smem);
 }

@@ -983,7 +983,12 @@ __device__ inline bool gemm_tile_big_any(const GemmArgs& g, u64 tile, unsigned c
 // three-input max per two k); outputs whose size grows drop the counts they
 // had.  The second adds the count products of exactly the terms whose size
 // equals the output's size, through a select on the B count and one
-// 64-bit multiply-add.  Sizes are staged clamped at -2^30, so sums of two
+// 64-bit multiply-add.  When no staged count of the step (A or B) reaches
+// 2^32 (the usual case: counts of optimal configurations are small) the
+// product's cross terms vanish and the second pass takes a 32 x 32 -> 64
+// multiply-add per term only; the staging loop ORs the high words and the
+// tile's waves agree on the path through a flag in LDS.  Sizes are staged
+// clamped at -2^30, so sums of two
 // never overflow int32 (-inf = INT32_MIN outside); an output whose size stays
 // below -2^29 is -inf (count 0) when stored.  Real sizes satisfy |s| <= 2^28.
 __host__ __device__ constexpr bool ct_tile_shape(int ti, int tj) {
@@ -1008,10 +1013,14 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
     constexpr int CTH = TN / RNT, TMP = TM + 4, TNP = TN + 4;
     static_assert((TM / RMT) * CTH == 256, "256 threads per tile");
     const int TK = 1 << g.tk;
-    u64* Ac = (u64*)smem;                    // [TK][TMP]
-    u64* Bc = Ac + (size_t)TK * TMP;         // [TK][TNP]
-    int* An = (int*)(Bc + (size_t)TK * TNP);  // [TK][TMP]
-    int* Bn = An + (size_t)TK * TMP;          // [TK][TNP]
+    // counts as separate low- and high-word planes, so that the usual
+    // (32-bit) path reads low words only, four per 16-byte LDS load
+    unsigned* Acl = (unsigned*)smem;               // [TK][TMP]
+    unsigned* Ach = Acl + (size_t)TK * TMP;        // [TK][TMP]
+    unsigned* Bcl = Ach + (size_t)TK * TMP;        // [TK][TNP]
+    unsigned* Bch = Bcl + (size_t)TK * TNP;        // [TK][TNP]
+    int* An = (int*)(Bch + (size_t)TK * TNP);      // [TK][TMP]
+    int* Bn = An + (size_t)TK * TMP;               // [TK][TNP]
     const TilePos p = tile_pos(g, tile);
     const int tid = threadIdx.x, tx = tid % CTH, ty = tid / CTH;
     int accn[RMT][RNT];
@@ -1024,8 +1033,17 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
             accc[r][c] = 0ull;
         }
     const int na = TM * TK, nb = TN * TK;
-    for (int kk = 0; kk < p.Kc; kk += TK) {
+    // per K step (two alternating slots): set when a staged count has a
+    // nonzero high word; a slot is cleared one step ahead, after the barrier
+    // that ends the last step reading it
+    __shared__ int s_wide[2];
+    if (tid == 0) s_wide[0] = s_wide[1] = 0;
+    __syncthreads();
+    int step = 0;
+    for (int kk = 0; kk < p.Kc; kk += TK, step ^= 1) {
         const i64 k0 = p.kbeg + kk;
+        if (tid == 0) s_wide[step ^ 1] = 0;
+        unsigned hi_or = 0;
         for (int idx = tid; idx < na; idx += 256) {
             int i, k;
             i64 addr;
@@ -1039,7 +1057,10 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                 addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
             }
             An[k * TMP + i] = max(((const int*)g.A.p0)[addr], kCtNegInf);
-            Ac[k * TMP + i] = ((const u64*)g.A.p1)[addr];
+            const u64 c = ((const u64*)g.A.p1)[addr];
+            hi_or |= (unsigned)(c >> 32);
+            Acl[k * TMP + i] = (unsigned)c;
+            Ach[k * TMP + i] = (unsigned)(c >> 32);
         }
         for (int idx = tid; idx < nb; idx += 256) {
             int j, k;
@@ -1054,9 +1075,14 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                 addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
             }
             Bn[k * TNP + j] = max(((const int*)g.B.p0)[addr], kCtNegInf);
-            Bc[k * TNP + j] = ((const u64*)g.B.p1)[addr];
+            const u64 c = ((const u64*)g.B.p1)[addr];
+            hi_or |= (unsigned)(c >> 32);
+            Bcl[k * TNP + j] = (unsigned)c;
+            Bch[k * TNP + j] = (unsigned)(c >> 32);
         }
+        if (__any(hi_or != 0) && (tid & 63) == 0) s_wide[step] = 1;
         __syncthreads();
+        const bool wide = s_wide[step] != 0;
         // pass 1: the step's largest size per output
         int m[RMT][RNT];
 #pragma unroll
@@ -1096,35 +1122,46 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                 accn[r][c] = m[r][c];
             }
         // pass 2: count products of the terms at the output's size
+        if (!wide) {  // every count of the step below 2^32: low words only
+            for (k = 0; k < TK; k++) {
+                int an[RMT], bn[RNT];
+                unsigned ac[RMT], bc[RNT];
+                load_sizes(k, an, bn);
+#pragma unroll
+                for (int h = 0; h < RMT / 4; h++) lds_load4(Acl + k * TMP + h * (TM / 2) + ty * 4, ac + 4 * h);
+#pragma unroll
+                for (int h = 0; h < RNT / 4; h++) lds_load4(Bcl + k * TNP + h * (TN / 2) + tx * 4, bc + 4 * h);
+#pragma unroll
+                for (int r = 0; r < RMT; r++)
+#pragma unroll
+                    for (int c = 0; c < RNT; c++) {
+                        const unsigned b = an[r] + bn[c] == accn[r][c] ? bc[c] : 0u;
+                        accc[r][c] += (u64)ac[r] * b;
+                    }
+            }
+            __syncthreads();
+            continue;
+        }
         for (k = 0; k < TK; k++) {
             int an[RMT], bn[RNT];
-            u64 ac[RMT], bc[RNT];
+            unsigned al[RMT], ah[RMT], bl[RNT], bh[RNT];
             load_sizes(k, an, bn);
 #pragma unroll
             for (int h = 0; h < RMT / 4; h++) {
-                const uint4 u0 = *(const uint4*)(Ac + k * TMP + h * (TM / 2) + ty * 4);
-                const uint4 u1 = *(const uint4*)(Ac + k * TMP + h * (TM / 2) + ty * 4 + 2);
-                ac[4 * h + 0] = ((u64)u0.y << 32) | u0.x;
-                ac[4 * h + 1] = ((u64)u0.w << 32) | u0.z;
-                ac[4 * h + 2] = ((u64)u1.y << 32) | u1.x;
-                ac[4 * h + 3] = ((u64)u1.w << 32) | u1.z;
+                lds_load4(Acl + k * TMP + h * (TM / 2) + ty * 4, al + 4 * h);
+                lds_load4(Ach + k * TMP + h * (TM / 2) + ty * 4, ah + 4 * h);
             }
 #pragma unroll
             for (int h = 0; h < RNT / 4; h++) {
-                const uint4 u0 = *(const uint4*)(Bc + k * TNP + h * (TN / 2) + tx * 4);
-                const uint4 u1 = *(const uint4*)(Bc + k * TNP + h * (TN / 2) + tx * 4 + 2);
-                bc[4 * h + 0] = ((u64)u0.y << 32) | u0.x;
-                bc[4 * h + 1] = ((u64)u0.w << 32) | u0.z;
-                bc[4 * h + 2] = ((u64)u1.y << 32) | u1.x;
-                bc[4 * h + 3] = ((u64)u1.w << 32) | u1.z;
+                lds_load4(Bcl + k * TNP + h * (TN / 2) + tx * 4, bl + 4 * h);
+                lds_load4(Bch + k * TNP + h * (TN / 2) + tx * 4, bh + 4 * h);
             }
 #pragma unroll
             for (int r = 0; r < RMT; r++)
 #pragma unroll
                 for (int c = 0; c < RNT; c++) {
                     const bool eq = an[r] + bn[c] == accn[r][c];
-                    const unsigned blo = eq ? (unsigned)bc[c] : 0u, bhi = eq ? (unsigned)(bc[c] >> 32) : 0u;
-                    accc[r][c] = mad_u64_mod(accc[r][c], (unsigned)ac[r], (unsigned)(ac[r] >> 32), blo, bhi);
+                    accc[r][c] = mad_u64_mod(accc[r][c], al[r], ah[r], eq ? bl[c] : 0u, eq ? bh[c] : 0u);
                 }
         }
         __syncthreads();

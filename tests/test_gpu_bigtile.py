@@ -264,3 +264,48 @@ def test_square_tile_on_a_hand_made_tree(ctx):
     assert (r["size"], r["count_mod_2_64"]) == (bf_u["size_max"], bf_u["count_max"])
     r = ctx.solve(net, plan, "tropical_i32", executor="persistent")
     assert r["size"] == bf_u["size_max"]
+
+
+def _with_pendant_paths(g, two, three):
+    """g with a pendant path of two vertices hung on every vertex in `two`
+    and one of three vertices on every vertex in `three`.  A path v-a-b adds
+    one to any maximum set (b with v, else a or b: two ways when v is out); a
+    path v-a-b-c adds two (one way when v is out, two when v is in), so the
+    number of maximum sets is the sum over the base graph's maximum sets S of
+    2^(|two \\ S| + |three & S|): counts of 2^40 and more, also in the large
+    intermediate tensors."""
+    e = [tuple(x) for x in g.edges.tolist()]
+    nv = g.nv
+    for v in two:
+        e += [(v, nv), (nv, nv + 1)]
+        nv += 2
+    for v in three:
+        e += [(v, nv), (nv, nv + 1), (nv + 1, nv + 2)]
+        nv += 3
+    es = sorted({(min(u, v), max(u, v)) for u, v in e})
+    return gg.Graph(nv, np.array(es, np.int32).reshape(-1, 2), None, g.name + "+paths")
+
+
+@pytest.mark.parametrize("base", ["lattice14", "rr120"])
+def test_counting_tropical_big_tiles_with_counts_above_2_32(ctx, base):
+    """The counting-tropical tiles take a 32-bit product path when every
+    count of a K step is below 2^32 and the full 64-bit product otherwise;
+    pendant paths make the counts of the large nodes exceed 2^32."""
+    g0 = gg.square_lattice(14) if base == "lattice14" else gg.random_regular(120, 3, 5)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(g0.nv)
+    two, three = sorted(perm[: g0.nv // 2].tolist()), sorted(perm[g0.nv // 2: g0.nv // 2 + g0.nv // 4].tolist())
+    g = _with_pendant_paths(g0, two, three)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, seed=0)
+    want = oracle.eliminate(g, "counting_tropical")
+    print(f"{base}+paths: {g.nv} vertices, complexity {plan.complexity()}, size {want['size']}, "
+          f"count 2^{float(np.log2(float(want['count']))):.1f}", flush=True)
+    assert want["count"] > 2 ** 48
+    r, recs = _solve_profiled(ctx, net, plan, "counting_tropical")
+    ran = {_ct_tile(x["shape"]) for x in recs if x["kind"] == "gemm_big"}
+    print(f"  tiles {sorted(ran, key=str)}: {r['size']}, {r['count_mod_2_64']}", flush=True)
+    assert ran - {None}
+    assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count"] % 2 ** 64)
+    rp = ctx.solve(net, plan, "counting_tropical", executor="persistent")
+    assert (rp["size"], rp["count_mod_2_64"]) == (want["size"], want["count"] % 2 ** 64)
