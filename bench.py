@@ -651,6 +651,7 @@ def main():
                          "conditioning lines")
     ap.add_argument("--k3", action="store_true", help="only the King's-subgraph partition-function line")
     ap.add_argument("--k2", action="store_true", help="only the 120-vertex persistent step")
+    ap.add_argument("--k4", action="store_true", help="only the served workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (for scaling hardware byte counters) and exit")
     args = ap.parse_args()
@@ -660,7 +661,7 @@ def main():
         sys.exit(2)
     # the oracle runs first, in forked processes, before anything touches the GPU
     cpu = None
-    only = args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2
+    only = args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2 or args.k4
     if not (args.no_cpu or only):
         cpu = cpu_baseline()
 
@@ -685,6 +686,9 @@ def main():
         tn.tune_load(TABLE)
     if args.k3:
         print(json.dumps({"k3": k3_record(ctx)}))
+        return
+    if args.k4:
+        print(json.dumps({"batched": job_stream(ctx, args.jobs, args.seed, k4_expected(args.jobs, args.seed))}))
         return
     if args.k2:
         g2, net2, plan2 = build_k2(args.seed)

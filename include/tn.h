@@ -213,6 +213,10 @@ tn_status tn_net_condition(const tn_net* src, int32_t n, const int32_t* vertices
  *            + rw_weight * rwc (all log2), Metropolis acceptance, inverse
  *            temperatures beta_start:beta_step:beta_stop, niters sweeps per
  *            temperature, best of ntrials (trials run on host threads).
+ *   method 2 automatic: the greedy tree; when it needs more than 2^26
+ *            semiring ops, TreeSA with the same options as well, and the
+ *            tree of lower TreeSA cost is kept (cheap planning for small
+ *            networks, annealed trees for the large ones).
  *   nslices  upper bound on sliced indices; indices are sliced (Sec. 4.2)
  *            while sc > sc_target.  0 = never slice.
  *   absorb_vertices  fold each vertex tensor into one incident edge tensor

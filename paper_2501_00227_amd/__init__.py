@@ -300,7 +300,7 @@ def plan_opts(**kw) -> tn_plan_opts:
     lib().tn_plan_opts_default(ctypes.byref(o))
     method = kw.pop("method", None)
     if method is not None:
-        o.method = {"greedy": 0, "treesa": 1}.get(method, method)
+        o.method = {"greedy": 0, "treesa": 1, "auto": 2}.get(method, method)
     opn = kw.pop("open", None)
     if opn:
         o._open_buf = _i32(list(opn))
@@ -322,7 +322,7 @@ class Plan:
 
     @classmethod
     def create(cls, net: Net, **kw) -> "Plan":
-        """Plan options as keywords (method="greedy" | "treesa", seed, ntrials,
+        """Plan options as keywords (method="greedy" | "treesa" | "auto", seed, ntrials,
         niters, sc_target, nslices, ..., open=[vertices])."""
         o = plan_opts(**kw)
         h = ctypes.c_void_p()

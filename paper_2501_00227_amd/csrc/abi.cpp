@@ -256,10 +256,10 @@ static tn_status to_options(const tn_plan_opts* o, PlanOptions& p) {
     if (o->nopen < 0 || o->nopen > kMaxOpen || (o->nopen > 0 && !o->open))
         return fail(TN_EINVAL, "nopen must be 0 .. 16, with open given");
     p.open.assign(o->open, o->open + o->nopen);
-    if (p.method != 0 && p.method != 1) return fail(TN_EINVAL, "method must be 0 (greedy) or 1 (TreeSA)");
+    if (p.method < 0 || p.method > 2) return fail(TN_EINVAL, "method must be 0 (greedy), 1 (TreeSA) or 2 (automatic)");
     if (p.temperature < 0 || p.nrepeat < 0 || p.ntrials < 0 || p.niters < 0 || p.nslices < 0)
         return fail(TN_EINVAL, "negative optimizer parameter");
-    if (p.method == 1 && (p.beta_step <= 0 || p.beta_stop < p.beta_start))
+    if (p.method != 0 && (p.beta_step <= 0 || p.beta_stop < p.beta_start))
         return fail(TN_EINVAL, "TreeSA needs beta_step > 0 and beta_stop >= beta_start");
     return TN_OK;
 }

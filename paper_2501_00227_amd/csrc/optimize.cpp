@@ -495,23 +495,47 @@ tn_status optimize_w(const Net& net, const std::vector<Leaf>& leaves, const Plan
             best = a.tree();
         }
     } else {
-        int nt = std::max(1, o.ntrials);
-        std::vector<SAResult<W>> res(nt);
-        int nth = o.nthreads > 0 ? o.nthreads : (int)std::thread::hardware_concurrency();
-        nth = std::max(1, std::min(nth, nt));
-        std::atomic<int> next{0};
-        std::vector<std::thread> pool;
-        for (int th = 0; th < nth; th++)
-            pool.emplace_back([&]() {
-                for (int k; (k = next.fetch_add(1)) < nt;)
-                    res[k] = treesa_trial<W>(leaf_ix, net.nv, o, o.seed * 7919ull + (uint64_t)k, open);
-            });
-        for (auto& th : pool) th.join();
-        int bi = 0;
-        for (int k = 1; k < nt; k++)
-            if (res[k].cost < res[bi].cost) bi = k;
-        best = res[bi].tree;
-        sliced = res[bi].sliced;
+        auto anneal = [&]() {  // best of ntrials TreeSA trials, on host threads
+            int nt = std::max(1, o.ntrials);
+            std::vector<SAResult<W>> res(nt);
+            int nth = o.nthreads > 0 ? o.nthreads : (int)std::thread::hardware_concurrency();
+            nth = std::max(1, std::min(nth, nt));
+            std::atomic<int> next{0};
+            std::vector<std::thread> pool;
+            for (int th = 0; th < nth; th++)
+                pool.emplace_back([&]() {
+                    for (int k; (k = next.fetch_add(1)) < nt;)
+                        res[k] = treesa_trial<W>(leaf_ix, net.nv, o, o.seed * 7919ull + (uint64_t)k, open);
+                });
+            for (auto& th : pool) th.join();
+            int bi = 0;
+            for (int k = 1; k < nt; k++)
+                if (res[k].cost < res[bi].cost) bi = k;
+            return res[bi];
+        };
+        if (o.method == 1) {
+            SAResult<W> r = anneal();
+            best = r.tree;
+            sliced = r.sliced;
+        } else {
+            // automatic: the greedy tree, and when it needs more than 2^26
+            // semiring ops TreeSA as well; the tree of lower annealing cost
+            // (tc, sc above the target, read-write) wins
+            best = greedy<W>(leaf_ix, net.nv, o.alpha, o.temperature, o.nrepeat, o.seed, open);
+            Annealer<W> a;
+            a.sc_target = o.sc_target;
+            a.ws = o.sc_weight;
+            a.wrw = o.rw_weight;
+            a.open = open;
+            a.load(best, leaf_ix);
+            if (std::log2(a.TC) > 26.0) {
+                SAResult<W> r = anneal();
+                if (r.cost < a.cost(a.TC, a.RW, a.sc())) {
+                    best = r.tree;
+                    sliced = r.sliced;
+                }
+            }
+        }
     }
     L = best.L;
     R = best.R;

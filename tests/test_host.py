@@ -140,6 +140,28 @@ def test_treesa_never_worse_than_its_greedy_start():
     assert c(sa) <= c(gr) + 1e-9
 
 
+def test_automatic_planner_keeps_greedy_for_small_and_anneals_large_networks():
+    """method "auto": the greedy tree below 2^26 semiring ops, else the better
+    (by the TreeSA cost) of the greedy tree and TreeSA's."""
+    small = tn.Net.from_graph(gg.random_regular(60, 3, 1))
+    a = tn.Plan.create(small, method="auto", ntrials=2, niters=4, seed=3)
+    gr = tn.Plan.create(small, seed=3)
+    assert a.export() == gr.export() and a.complexity()[0] <= 26
+    g = gg.random_regular(170, 3, 170)
+    net = tn.Net.from_graph(g)
+    gr = tn.Plan.create(net, seed=1, sc_target=22)
+    au = tn.Plan.create(net, method="auto", ntrials=2, niters=10, seed=1, sc_target=22)
+    assert gr.complexity()[0] > 26
+    cost = lambda p: p.complexity()[0] + max(0.0, p.complexity()[1] - 22) + 0.2 * p.complexity()[2]
+    assert cost(au) <= cost(gr) + 1e-9
+    assert au.complexity()[0] < gr.complexity()[0]  # here annealing wins: 2^31.1 against 2^35.0 ops
+    t = au.export()
+    sub = tn.Plan.create(tn.Net.from_graph(gg.random_regular(24, 3, 0)), method="auto", seed=0)
+    bf = oracle.brute_force(gg.random_regular(24, 3, 0), [1.0])
+    assert oracle.follow_plan(gg.random_regular(24, 3, 0), sub.export(), "count")["count"] == bf["count_all"]
+    assert len(t["left"]) == len(t["right"]) > 0
+
+
 def test_slicing_reaches_the_space_target():
     g = gg.random_regular(40, 3, 2)
     net = tn.Net.from_graph(g)
