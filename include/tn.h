@@ -393,9 +393,13 @@ tn_status tn_solve_noalloc(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, 
 
 /* Many networks in one persistent launch: a device task table of
  * (job, node, tile) entries with dependency counters; workgroups pop ready
- * tiles until every job's root is done.  Jobs the auto executor of tn_solve
- * sends to per-node launches (trees with much work) run one after the other
- * on per-node launches over the whole chip instead.  Launch shapes come from the tuning
+ * tiles until every job's root is done.  Jobs with much work run one after
+ * the other on per-node launches over the whole chip instead: trees the auto
+ * executor of tn_solve sends to per-node launches, except that in the exact
+ * algebras (all but the partition function) trees of up to 2^31 semiring ops
+ * per pass with intermediates of at most 2^24 entries stay in the shared
+ * launch, where several of them fill the chiplets side by side (their
+ * results do not depend on the route).  Launch shapes come from the tuning
  * table (or the heuristic) keyed by each node's own shape (see the
  * autotuner below), so a job's result does not depend on the other jobs in
  * the batch.  n jobs; opts and out have n
@@ -569,8 +573,8 @@ tn_status tn_tune_records(tn_tune_record* recs, int32_t cap, int32_t* n);
  * order while the sum of their device bytes (tn_server_job_bytes) stays
  * within hbm_budget_bytes and fewer than max_slots run; admitted jobs are
  * merged into the next persistent launch (on one of three streams) while
- * earlier launches may still run; a job the auto executor of tn_solve sends to
- * per-node launches goes out alone on per-node launches, asynchronously on
+ * earlier launches may still run; a job tn_solve_batch would run on per-node
+ * launches (see there) goes out alone on per-node launches, asynchronously on
  * its own stream.  Each job's latency is result-on-host minus submit time.
  * The server owns a scheduler thread. */
 tn_status tn_server_create(tn_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_slots,

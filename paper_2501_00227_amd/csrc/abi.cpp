@@ -548,10 +548,11 @@ tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const 
     TN_GUARD_BEGIN
     if (!c || n < 0 || (n > 0 && (!nets || !plans || !opts || !out))) return fail(TN_EINVAL, "NULL argument");
     if (hipSetDevice(c->device) != hipSuccess) return fail(TN_EDEVICE, "hipSetDevice failed");
-    // jobs the auto executor sends to per-node launches (trees with much
-    // work: a persistent launch keeps a job on one chiplet) run one after the
-    // other over the whole chip; the rest share one persistent launch.  The
-    // route depends on the job alone, as for tn_solve.
+    // jobs with much work run one after the other on per-node launches over
+    // the whole chip (a persistent launch keeps a job on one chiplet); the
+    // rest share one persistent launch (use_persistent_shared: the small trees
+    // of tn_solve's rule, and mid-size trees of the exact algebras, whose
+    // results do not depend on the route).
     std::vector<BatchItem> items;
     std::vector<int32_t> in_batch, alone;
     for (int32_t i = 0; i < n; i++) {
@@ -559,7 +560,8 @@ tn_status tn_solve_batch(tn_ctx* c, int32_t n, const tn_net* const* nets, const 
         if (!public_semiring(opts[i].semiring)) return fail(TN_EINVAL, "unknown semiring");
         const Plan& pl = plans[i]->plan;
         const bool per_node = pl.sliced.empty() && opts[i].slice_begin == 0 && opts[i].slice_end == 0 &&
-                              (opts[i].executor == 1 || (opts[i].executor == 0 && !use_persistent(pl)));
+                              (opts[i].executor == 1 ||
+                               (opts[i].executor == 0 && !use_persistent_shared(pl, opts[i].semiring)));
         if (per_node) {
             alone.push_back(i);
         } else {

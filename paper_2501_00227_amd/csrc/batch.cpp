@@ -915,19 +915,36 @@ tn_status run_passes_keep(tn_ctx* ctx, const Net& net, const Plan& plan, const s
     return st;
 }
 
-bool use_persistent(const Plan& p) {
-    static int mode = -2;
-    if (mode == -2) {
+static int exec_mode() {  // TN_EXEC=stream | persistent forces a route (tests); -1: automatic
+    static const int mode = [] {
         const char* e = std::getenv("TN_EXEC");
-        mode = !e ? -1 : (std::strcmp(e, "stream") == 0 ? 0 : (std::strcmp(e, "persistent") == 0 ? 1 : -1));
-    }
+        return !e ? -1 : (std::strcmp(e, "stream") == 0 ? 0 : (std::strcmp(e, "persistent") == 0 ? 1 : -1));
+    }();
+    return mode;
+}
+
+bool use_persistent(const Plan& p) {
     if (!p.sliced.empty()) return false;
-    if (mode >= 0) return mode == 1;
+    if (exec_mode() >= 0) return exec_mode() == 1;
     // small trees: launch overhead dominates the per-node path.  A job of a
     // persistent launch runs on one chiplet, so trees with much work (more
     // than 2^27 semiring ops per pass) take the per-node path over the whole
     // chip instead.
     return p.max_rank <= 22 && p.tc <= 27.0;
+}
+
+bool use_persistent_shared(const Plan& p, int semiring) {
+    if (use_persistent(p)) return true;
+    if (exec_mode() >= 0 || !p.sliced.empty()) return false;
+    // jobs launched together: mid-size trees of the exact algebras fill the
+    // chiplets side by side (on the served mix, 2^27-2^29-op jobs ran three
+    // times faster than one after the other on per-node launches, and
+    // 2^29-2^31-op jobs 2.6 times faster), and their results do not depend on the
+    // route: integer, modular and max-plus arithmetic are exact under any
+    // tiling.  The real algebra keeps the single-job rule, so a Z job's sums
+    // run in the same order alone and in any mix.
+    const bool exact = semiring != TN_PARTITION_F32 && semiring != TN_PARTITION_BF16;
+    return exact && p.max_rank <= 24 && p.tc <= 31.0;
 }
 
 }  // namespace tn

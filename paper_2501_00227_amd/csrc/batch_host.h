@@ -95,5 +95,8 @@ tn_status solve_polynomial(tn_ctx* ctx, const Net& net, const Plan& plan, int li
 void batch_cache_drop(tn_ctx* ctx);
 // Route a single unsliced small tree through the persistent launch.
 bool use_persistent(const Plan& p);
+// The route of a job launched together with others (tn_solve_batch, the
+// server): use_persistent, or a mid-size tree in an exact algebra.
+bool use_persistent_shared(const Plan& p, int semiring);
 
 }  // namespace tn

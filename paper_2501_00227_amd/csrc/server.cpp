@@ -412,7 +412,7 @@ tn_status tn_server_submit(tn_server* s, const tn_net* net, const tn_plan* plan,
         std::vector<PassSpec> passes;
         tn_status st = make_passes(net->net, *o, passes);
         if (st != TN_OK) return st;
-        const bool large = !use_persistent(plan->plan);
+        const bool large = !use_persistent_shared(plan->plan, o->semiring);
         DevProgram* dp = nullptr;
         SolveLayout layout;
         {
@@ -480,7 +480,7 @@ tn_status tn_server_job_bytes(const tn_net* net, const tn_plan* plan, const tn_s
         std::vector<PassSpec> passes;
         tn_status st = make_passes(net->net, *o, passes);
         if (st != TN_OK) return st;
-        if (use_persistent(plan->plan)) {
+        if (use_persistent_shared(plan->plan, o->semiring)) {
             *bytes = job_device_bytes(net->net, plan->plan, *o);
         } else {
             DevProgram host_only;  // launch shapes only: nothing goes to the device

@@ -119,19 +119,43 @@ def test_cancel_queued_jobs_and_refuse_oversized(ctx):
     tiny.close()
 
 
-def test_large_trees_leave_the_persistent_launch(ctx):
-    """Trees with more than 2^27 ops per pass run on per-node launches in a
-    batch and in the server, with the same results as alone; small ones
-    share the persistent launch."""
+def _kinds(ctx, fn):
+    ctx.set_profiling(True)
+    try:
+        ctx.profile(clear=True)
+        out = fn()
+        kinds = {r["kind"] for r in ctx.profile(clear=True)}
+    finally:
+        ctx.set_profiling(False)
+    return out, kinds
+
+
+def test_routes_of_large_trees(ctx):
+    """Alone, trees with more than 2^27 ops per pass run on per-node launches.
+    Launched together (a batch, the server), mid-size trees of the exact
+    algebras (2^27 to 2^31 ops, intermediates up to 2^24 entries) share the
+    persistent launch; the real algebra's large trees and trees above 2^31
+    ops go out on per-node launches.  Every route gives the job's result
+    alone."""
     small = _jobs(6, seed=9, n_lo=30, n_hi=60)
-    bigs = []
+    nets = {}
     for n in (140, 150):
         g = gg.random_regular(n, 3, n)
         net = tn.Net.from_graph(g)
-        plan = tn.Plan.create(net, seed=1)
-        assert plan.complexity()[0] > 27
-        bigs.append((g, net, plan, "tropical_i32"))
-    jobs = small[:3] + bigs[:1] + small[3:] + bigs[1:]
+        nets[n] = (g, net, tn.Plan.create(net, seed=1))
+    tc140, tc150 = nets[140][2].complexity()[0], nets[150][2].complexity()[0]
+    assert 27 < tc140 <= 31 and nets[140][2].info()["max_rank"] <= 24 and tc150 > 31
+    mids = [nets[140] + ("tropical_i32",), nets[140] + ("counting_tropical",)]
+    bigs = [nets[150] + ("tropical_i32",), nets[140] + ("partition_f32",)]
+    for _, net, plan, sr in mids:
+        _, kinds = _kinds(ctx, lambda: ctx.solve(net, plan, sr))
+        assert "batch" not in kinds  # alone: per-node launches
+        _, kinds = _kinds(ctx, lambda: ctx.solve_batch([net], [plan], [sr]))
+        assert kinds == {"batch"}  # launched together: the shared persistent launch
+    for _, net, plan, sr in bigs:
+        _, kinds = _kinds(ctx, lambda: ctx.solve_batch([net], [plan], [sr]))
+        assert "batch" not in kinds
+    jobs = small[:3] + mids[:1] + bigs[:1] + small[3:] + mids[1:] + bigs[1:]
     alone = [ctx.solve(net, plan, sr) for _, net, plan, sr in jobs]
     mixed = ctx.solve_batch([j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs])
     for a, m in zip(alone, mixed):
@@ -143,9 +167,12 @@ def test_large_trees_leave_the_persistent_launch(ctx):
         assert _key(srv.poll(jid)) == _key(a)
     st = srv.stats()
     srv.close()
-    assert st["launches"] >= 3  # the large ones went out alone
-    for (g, _, _, sr), a in zip(bigs, alone[3:4] + alone[-1:]):
-        assert a["size"] == oracle.eliminate(g, "tropical", max_width=26)["size"]
+    assert st["launches"] >= 3  # the per-node jobs went out alone
+    want140 = oracle.eliminate(nets[140][0], "counting_tropical", max_width=26)
+    want150 = oracle.eliminate(nets[150][0], "tropical", max_width=26)
+    assert alone[3]["size"] == want140["size"]
+    assert (alone[8]["size"], alone[8]["count_mod_2_64"]) == (want140["size"], want140["count"] % 2 ** 64)
+    assert alone[4]["size"] == want150["size"]
 
 
 def test_wait_limit_abandons_the_launch_and_the_context_recovers(ctx):
