@@ -114,3 +114,25 @@ def test_k5_full_size_slices_cross_algebra(ctx):
         print(f"  slice {s}: {a['size']} {b['size']} {c['size']} count {c['count_mod_2_64']}", flush=True)
         assert a["size"] == b["size"] == c["size"]
         assert c["count_mod_2_64"] == c2["count_mod_2_64"] > 0
+
+
+def test_k5_all_slices_agree_across_plans(ctx):
+    """The 240-vertex network over all slices of its 2^30-entry plan (the
+    benchmark's) and of a differently annealed plan sliced to 2^26 entries
+    (another tree, other sliced indices, permutes and launch shapes): the same
+    maximum size in both max-plus algebras and the same size and count of
+    maximum sets in the counting-tropical one."""
+    g = _k5()
+    net = tn.Net.from_graph(g)
+    p30 = tn.Plan.create(net, method="treesa", ntrials=16, niters=50, rw_weight=0.5, sc_target=30, nslices=30, seed=0)
+    p26 = tn.Plan.create(net, method="treesa", ntrials=8, niters=20, sc_target=26, nslices=40, seed=5)
+    i30, i26 = p30.info(), p26.info()
+    print("plans", p30.complexity(), i30["nsliced"], p26.complexity(), i26["nsliced"], flush=True)
+    assert i30["max_rank"] == 30 and i26["max_rank"] <= 26 and i26["nsliced"] > i30["nsliced"]
+    a = ctx.solve(net, p30, "counting_tropical")
+    b = ctx.solve(net, p26, "counting_tropical")
+    print("counting tropical", a["size"], a["count_mod_2_64"], b["size"], b["count_mod_2_64"], flush=True)
+    assert (a["size"], a["count_mod_2_64"]) == (b["size"], b["count_mod_2_64"])
+    assert a["count_mod_2_64"] > 0
+    for sr in ("tropical_i32", "tropical_f32"):
+        assert ctx.solve(net, p30, sr)["size"] == ctx.solve(net, p26, sr)["size"] == a["size"]
