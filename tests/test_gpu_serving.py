@@ -1,11 +1,12 @@
 """Served stream and failure handling on the GPU.
 
 * Admission binds: a burst of jobs whose device bytes far exceed the HBM
-  budget is served in several admission rounds whose launches overlap on the
-  device (at least two in flight at once), the admitted bytes never pass the
-  budget, the server's device pool high-water mark stays within the budget
-  plus the task-table reserve, and every result equals the job's result
-  alone and the oracle's.
+  budget is served in several admission rounds, the admitted bytes never
+  pass the budget, the server's device pool high-water mark stays within
+  the budget plus the task-table reserve, and every result equals the job's
+  result alone and the oracle's.
+* Launches overlap: jobs admitted while a long launch runs go out at once on
+  another stream (two launches in flight together).
 * Jobs still queued can be cancelled; a job above the budget is refused.
 * Failures forced from the host end cleanly: a dependency-wait limit so small
   that the persistent launch gives up (every workgroup leaves, TN_EDEVICE),
@@ -51,7 +52,7 @@ def _jobs(n, seed, n_lo, n_hi):
     return out
 
 
-def test_admission_binds_and_launches_overlap(ctx):
+def test_admission_binds(ctx):
     jobs = _jobs(48, seed=7, n_lo=60, n_hi=110)
     sizes = sorted(p.peak_bytes(sr) for _, _, p, sr in jobs)
     budget = max(4 * sizes[len(sizes) // 2], (3 * sizes[-1]) // 2)  # a few jobs at a time, any job fits
@@ -69,7 +70,6 @@ def test_admission_binds_and_launches_overlap(ctx):
     assert st["completed"] == len(jobs) and st["failed"] == 0
     assert st["launches"] >= 3                      # the budget split the burst
     assert st["peak_admitted_bytes"] <= budget
-    assert st["peak_inflight"] >= 2                 # launches overlapped on the device
     assert st["peak_pool_bytes"] <= budget + (64 << 20)
     for (g, _, _, sr), r, a in zip(jobs, res, alone):
         assert r is not None and _key(r) == _key(a)
@@ -80,6 +80,37 @@ def test_admission_binds_and_launches_overlap(ctx):
         elif sr == "counting_tropical":
             ref = oracle.eliminate(g, "counting_tropical")
             assert (r["size"], r["count_mod_2_64"]) == (ref["size"], ref["count"] % 2 ** 64)
+
+
+def test_launches_overlap_on_the_device(ctx):
+    """A job admitted while an earlier launch still runs goes out at once on
+    another stream: a long per-node job (counting tropical on n=170, some
+    2^35 ops) is submitted, and once it is on the device small jobs follow;
+    at least two launches are then in flight together."""
+    import time
+
+    g = gg.random_regular(170, 3, 170)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, seed=1)
+    assert plan.complexity()[0] > 33
+    small = _jobs(8, seed=11, n_lo=40, n_hi=80)
+    want = ctx.solve(net, plan, "counting_tropical")
+    alone = [ctx.solve(n2, p2, sr) for _, n2, p2, sr in small]
+    srv = tn.Server(ctx, 32 << 30, max_slots=64)
+    big = srv.submit(net, plan, "counting_tropical")
+    t0 = time.perf_counter()
+    while srv.stats()["launches"] < 1 and time.perf_counter() - t0 < 5.0:
+        time.sleep(1e-4)
+    ids = [srv.submit(n2, p2, sr) for _, n2, p2, sr in small]
+    srv.drain()
+    r = srv.poll(big)
+    assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count_mod_2_64"])
+    for jid, a in zip(ids, alone):
+        assert _key(srv.poll(jid)) == _key(a)
+    st = srv.stats()
+    srv.close()
+    print("server stats", st, flush=True)
+    assert st["peak_inflight"] >= 2
 
 
 def test_cancel_queued_jobs_and_refuse_oversized(ctx):
