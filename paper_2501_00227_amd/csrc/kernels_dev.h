@@ -637,9 +637,11 @@ __device__ inline TilePos tile_pos(const GemmArgs& g, u64 tile) {
 // Stage the A tile as As[batch][k][row] and the B tile as Bs[batch][k][col]
 // for k in [k0, k0 + TK), reading global memory in its own order.
 template <int D>
-__device__ inline void gemm_stage(const GemmArgs& g, const TilePos& p, i64 k0, typename Alg<D>::V* As,
-                                  typename Alg<D>::V* Bs, float sA, float sB) {
+__device__ inline unsigned gemm_stage(const GemmArgs& g, const TilePos& p, i64 k0, typename Alg<D>::V* As,
+                                      typename Alg<D>::V* Bs, float sA, float sB) {
+    // returns, for counting tropical, the OR of the staged counts' high words
     using A = Alg<D>;
+    unsigned hi = 0;
     const int TB = 1 << g.tb, TM = 1 << g.ti, TN = 1 << g.tj, TK = 1 << g.tk;
     const int TMp = pad_dim(TM), TNp = pad_dim(TN);
     const int tid = threadIdx.x;
@@ -658,7 +660,9 @@ __device__ inline void gemm_stage(const GemmArgs& g, const TilePos& p, i64 k0, t
             bb = idx >> (g.tk + g.ti);
             addr = ((((p.b0 + bb) << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
         }
-        As[(bb * TK + k) * TMp + i] = A::prescale(A::load(g.A, addr), sA);
+        const typename A::V v = A::load(g.A, addr);
+        if constexpr (D == DSR_CTROP) hi |= (unsigned)(v.c >> 32);
+        As[(bb * TK + k) * TMp + i] = A::prescale(v, sA);
     }
     for (int idx = tid; idx < nb; idx += 256) {
         int bb, j, k;
@@ -674,8 +678,11 @@ __device__ inline void gemm_stage(const GemmArgs& g, const TilePos& p, i64 k0, t
             bb = idx >> (g.tk + g.tj);
             addr = ((((p.b0 + bb) << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
         }
-        Bs[(bb * TK + k) * TNp + j] = A::prescale(A::load(g.B, addr), sB);
+        const typename A::V v = A::load(g.B, addr);
+        if constexpr (D == DSR_CTROP) hi |= (unsigned)(v.c >> 32);
+        Bs[(bb * TK + k) * TNp + j] = A::prescale(v, sB);
     }
+    return hi;
 }
 
 // Partition function: the exponent of C (first tile only) and the running
@@ -718,13 +725,56 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
 #pragma unroll
         for (int c = 0; c < RN; c++) acc[r][c] = A::zero(g.ap);
 
-    for (int kk = 0; kk < p.Kc; kk += TK) {
-        gemm_stage<D>(g, p, p.kbeg + kk, As, Bs, sA, sB);
+    // counting tropical: per K step (two alternating slots, each cleared one
+    // step ahead) whether a staged count reaches 2^32; if none does, count
+    // products take one 32 x 32 -> 64 multiply
+    __shared__ int s_wide[2];
+    if constexpr (D == DSR_CTROP) {
+        if (tid == 0) s_wide[0] = s_wide[1] = 0;
+        __syncthreads();
+    }
+    int step = 0;
+    for (int kk = 0; kk < p.Kc; kk += TK, step ^= 1) {
+        if constexpr (D == DSR_CTROP)
+            if (tid == 0) s_wide[step ^ 1] = 0;
+        const unsigned hi = gemm_stage<D>(g, p, p.kbeg + kk, As, Bs, sA, sB);
+        if constexpr (D == DSR_CTROP)
+            if (__any(hi != 0) && (tid & 63) == 0) s_wide[step] = 1;
         __syncthreads();
         if (tid < active) {
             const V* ap_ = As + (size_t)z * TK * TMp + y;
             const V* bp_ = Bs + (size_t)z * TK * TNp + x;
             int k = 0;
+            if constexpr (D == DSR_CTROP) {
+                if (s_wide[step] == 0) {
+                    for (; k < TK; k++) {
+                        int an[RM], bn[RN];
+                        unsigned ac[RM], bc[RN];
+#pragma unroll
+                        for (int r = 0; r < RM; r++) {
+                            const V v = ap_[k * TMp + r * TMt];
+                            an[r] = v.n;
+                            ac[r] = (unsigned)v.c;
+                        }
+#pragma unroll
+                        for (int c = 0; c < RN; c++) {
+                            const V v = bp_[k * TNp + c * TNt];
+                            bn[c] = v.n;
+                            bc[c] = (unsigned)v.c;
+                        }
+#pragma unroll
+                        for (int r = 0; r < RM; r++)
+#pragma unroll
+                            for (int c = 0; c < RN; c++) {
+                                const int sz = __builtin_elementwise_add_sat(an[r], bn[c]);
+                                const u64 prod = (u64)ac[r] * bc[c];
+                                const int n = max(acc[r][c].n, sz);
+                                acc[r][c].c = (acc[r][c].n == n ? acc[r][c].c : 0ull) + (sz == n ? prod : 0ull);
+                                acc[r][c].n = n;
+                            }
+                    }
+                }
+            }
             if constexpr (D == DSR_MODP) {  // four k steps per Montgomery reduction, then two
                 for (; k + 3 < TK; k += 4) {
                     V av[4][RM], bv[4][RN];
