@@ -479,14 +479,16 @@ K4_BUDGET = 2 << 30
 
 
 def k4_expected(njobs, seed):
-    """Expected results of the served jobs with n <= 130 (the oracle's
-    elimination, stored by tests/golden/make_golden_k4.py for the default
-    stream), or None when the stream differs from the stored one."""
+    """Expected results of the served jobs with n <= 130 among the first
+    stored ones (the oracle's elimination, stored by
+    tests/golden/make_golden_k4.py for the first 2000 jobs of the stream), or
+    None when the stream does not start with the stored one."""
     path = os.path.join(ROOT, "tests", "golden", "k4_jobs.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec["njobs"] != njobs or rec["seed"] != seed or rec["n_range"] != list(K4_N):
+    # job_mix draws job after job, so a longer stream starts with the stored one
+    if rec["njobs"] > njobs or rec["seed"] != seed or rec["n_range"] != list(K4_N):
         return None
     out = {}
     for k, v in rec["expected"].items():
@@ -511,7 +513,8 @@ def job_stream(ctx, njobs, seed=0, expected=None):
     (TN_ETOOBIG) and counted.  Plain one-at-a-time, batched (persistent
     launches of 256 jobs) and served (Poisson arrivals at 0.5, 1, 2 and 4 x
     the plain rate, p50/p99 latency submit -> result on the host), every job
-    with n <= 130 checked against the oracle."""
+    with n <= 130 among the first 2000 checked against the oracle's stored
+    values."""
     import numpy as np
 
     import graphgen as gg
@@ -641,7 +644,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--jobs", type=int, default=2000, help="jobs in the batched / served stream")
+    ap.add_argument("--jobs", type=int, default=10000, help="jobs in the batched / served stream")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline step only")
     ap.add_argument("--heuristic", action="store_true", help="heuristic launch shapes only (no tuning table)")
