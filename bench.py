@@ -283,7 +283,8 @@ def k3_record(ctx):
             mf = [x for x in recs if x["kind"] == "gemm_mfma"]
             key = sr.split("_")[1]
             row[key] = {"ms": dt * 1e3, "log_z": r["log_z"], "abs_err_log_z": abs(r["log_z"] - want),
-                        "rel_err_z": abs(math.expm1(r["log_z"] - want)), "GOP_per_s": 2.0 ** tc / dt / 1e9}
+                        "rel_err_z": abs(math.expm1(r["log_z"] - want)), "GOP_per_s": 2.0 ** tc / dt / 1e9,
+                        "z_range_log2": r["z_range_log2"]}
             if mf:
                 big = max(mf, key=lambda x: x["ops"])
                 lr = launch_roofline(big)

@@ -346,7 +346,15 @@ void tn_solve_opts_default(tn_solve_opts* opts);
  *              count_nlimbs of them); TN_EOVERFLOW if the check prime
  *              disagrees with the CRT value.
  *   Partition function: Z = z_mant * 2^z_exp2 (z_mant in [1,2) or 0),
- *              log_z = ln Z, z = Z as a double (inf if above DBL_MAX). */
+ *              log_z = ln Z, z = Z as a double (inf if above DBL_MAX);
+ *              z_range_log2 = the largest, over the contraction tree, of a
+ *              tensor's log2(max / smallest nonzero entry) as stored (float32
+ *              entries under one power-of-two exponent per tensor, Sec. 3.1
+ *              rescaled) and of the sum of a product's two operand ranges
+ *              (the span of the products it forms): terms more than about
+ *              2^126 below a tensor's maximum flush to zero, so values above
+ *              100 mean the result may have lost such terms; 0 for the
+ *              other semirings. */
 typedef struct {
     int32_t semiring;
     int32_t size_i32;
@@ -363,6 +371,7 @@ typedef struct {
     double log_z;
     double z;
     double seconds;            /* wall time of the call */
+    double z_range_log2;       /* partition function: dynamic range of the tree's tensors (see above) */
 } tn_result;
 
 /* Contract the network along the plan on the context's stream and wait for

@@ -87,7 +87,7 @@ class tn_result(ctypes.Structure):
                 ("residues", ctypes.c_uint32 * 16), ("primes", ctypes.c_uint32 * 16), ("nresidues", ctypes.c_int32),
                 ("count_limbs", ctypes.c_uint32 * 16), ("count_nlimbs", ctypes.c_int32),
                 ("z_mant", ctypes.c_double), ("z_exp2", ctypes.c_int64), ("log_z", ctypes.c_double),
-                ("z", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("z", ctypes.c_double), ("seconds", ctypes.c_double), ("z_range_log2", ctypes.c_double)]
 
 
 class tn_kernel_record(ctypes.Structure):
@@ -448,7 +448,7 @@ def decode(r: tn_result) -> Dict:
         out["residues"] = [int(r.residues[k]) for k in range(r.nresidues)]
         out["primes"] = [int(r.primes[k]) for k in range(r.nresidues)]
     if sr in (TN_PARTITION_F32, TN_PARTITION_BF16):
-        out.update(z=r.z, log_z=r.log_z, z_mant=r.z_mant, z_exp2=int(r.z_exp2))
+        out.update(z=r.z, log_z=r.log_z, z_mant=r.z_mant, z_exp2=int(r.z_exp2), z_range_log2=r.z_range_log2)
     return out
 
 

@@ -739,8 +739,8 @@ tn_status batch_finish(BatchLaunch& L, std::vector<tn_result>& out) {
         if (s == TN_OK) {
             std::vector<std::vector<unsigned char>> accs;
             for (int j : st.job_ids) {
-                std::vector<unsigned char> a(16);
-                std::memcpy(a.data(), (unsigned char*)L.host + L.o_hacc + kAccSlotBytes * j, 16);
+                std::vector<unsigned char> a(kAccSlotBytes);
+                std::memcpy(a.data(), (unsigned char*)L.host + L.o_hacc + kAccSlotBytes * j, kAccSlotBytes);
                 accs.push_back(a);
             }
             s = decode_result(st.opts, st.passes, accs, out[i]);

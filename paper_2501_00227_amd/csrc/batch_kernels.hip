@@ -205,7 +205,7 @@ __device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count,
         }
         return;
     }
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
     for (int k = 0; k < count; k += 4) {
         // four units per pass: with at most 4 splits all their loads are in
         // flight together (a unit is one output per thread)
@@ -239,13 +239,10 @@ __device__ void run_reduce(const BJob& j, const BNode& nd, i64 first, int count,
         for (int u = 0; u < 4; u++)
             if (ok[u]) {
                 A::store(C, o[u], acc[u]);
-                if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc[u]);
+                if constexpr (is_z<D>()) z_track(acc[u], lmax, lmin);
             }
     }
-    if constexpr (is_z<D>()) {
-        for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
-        if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(j.meta, nd.mc, __float_as_uint(lmax));
-    }
+    if constexpr (is_z<D>()) z_meta_block(j.meta, nd.mc, lmax, lmin);
 }
 
 // one inner node, start to end, by this workgroup alone
@@ -309,6 +306,7 @@ __attribute__((noinline)) __device__ void run_task(const BTask& t, const BJob& j
             r.p1 = plane_bytes_dev<D>(1) ? (unsigned char*)j.arena.p1 + off * plane_bytes_dev<D>(1) : nullptr;
             accumulate_one<D>(r, j.root, j.meta, j.acc, 1, j.ap);
         }
+        if constexpr (is_z<D>()) z_range_block(j.meta, j.nnode, j.acc, 1, (float*)smem);
         break;
     }
     case BT_ONE: {

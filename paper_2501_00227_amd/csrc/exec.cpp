@@ -561,6 +561,11 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
         res.z_exp2 = m == 0.0 ? 0 : e;
         res.log_z = m == 0.0 ? -INFINITY : std::log(m) + (double)e * std::log(2.0);
         res.z = m == 0.0 ? 0.0 : (e > 1100 ? INFINITY : std::ldexp(m, (int)std::max<int64_t>(e, -2000)));
+        if (acc[0].size() >= (size_t)kZRangeOffset + 4) {
+            float r;
+            std::memcpy(&r, a0 + kZRangeOffset, 4);
+            res.z_range_log2 = r;
+        }
         break;
     }
     case kSemiringTop8:
@@ -747,6 +752,7 @@ tn_status run_solve_on(tn_ctx* ctx, hipStream_t s, bool async, const Net& net, c
             chk(launch_accumulate(dsr, plane_at(arena, dsr, plan.node_off[root]), root, meta, acc, sl == sb ? 1 : 0,
                                   ap, s, nent),
                 "root accumulate");
+            if (is_z) chk(launch_z_range(meta, nn, acc, sl == sb ? 1 : 0, s), "z range");
         }
     }
     if (herr == hipSuccess) chk(hipMemcpyAsync(stage, base + L.o_acc, L.acc_bytes, hipMemcpyDeviceToHost, s), "result copy");
@@ -763,9 +769,12 @@ tn_status run_solve_on(tn_ctx* ctx, hipStream_t s, bool async, const Net& net, c
 
 tn_status decode_root(const tn_solve_opts& o, const std::vector<PassSpec>& passes, const std::vector<unsigned char>& all,
                       int64_t nent, int64_t addr, tn_result& r) {
-    std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(16));
-    for (size_t k = 0; k < passes.size(); k++)
-        std::memcpy(accs[k].data(), all.data() + kAccSlotBytes * ((size_t)nent * k + (size_t)addr), 16);
+    std::vector<std::vector<unsigned char>> accs(passes.size(), std::vector<unsigned char>(kAccSlotBytes));
+    for (size_t k = 0; k < passes.size(); k++) {
+        std::memcpy(accs[k].data(), all.data() + kAccSlotBytes * ((size_t)nent * k + (size_t)addr), kAccSlotBytes);
+        // the Z dynamic range belongs to the whole contraction: entry 0's slot
+        std::memcpy(accs[k].data() + kZRangeOffset, all.data() + kAccSlotBytes * ((size_t)nent * k) + kZRangeOffset, 4);
+    }
     return decode_result(o, passes, accs, r);
 }
 

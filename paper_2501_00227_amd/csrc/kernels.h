@@ -33,7 +33,9 @@ struct Planes {
 // is stored * 2^exp; maxbits is the float bit pattern of max|stored|.
 struct TensorMeta {
     long long exp;
-    unsigned int maxbits;
+    unsigned int maxbits;    // bits of the largest stored entry (a non-negative float)
+    unsigned int minnz_inv;  // complement of the bits of the smallest nonzero stored entry; 0: none yet
+    float operand_range;     // inner nodes: log2 range of A plus that of B (what a product spans)
     unsigned int pad;
 };
 
@@ -116,6 +118,11 @@ hipError_t launch_split_reduce(int dsr, Planes part, Planes C, int64_t nout, int
 // != 0 copies.  For the partition function a slot is {double mantissa, int64
 // exponent}.
 constexpr int kAccSlotBytes = 48;
+// The partition function's dynamic range (the largest log2(max / smallest
+// nonzero) of a stored tensor, or of the two operands of a product added):
+// a float at this byte of the pass's first accumulator slot.
+constexpr int kZRangeOffset = 32;
+hipError_t launch_z_range(const TensorMeta* meta, int n, void* acc, int first, hipStream_t s);
 hipError_t launch_accumulate(int dsr, Planes root, int mroot, TensorMeta* meta, void* acc, int first,
                              const AlgebraParams& ap, hipStream_t s, long long nent = 1);
 // The device-side identity element of a whole (empty) network.

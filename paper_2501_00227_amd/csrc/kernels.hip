@@ -41,6 +41,18 @@ static int lds_elem_bytes(int dsr) {
     }
 }
 
+// ----------------------------------------------------- Z dynamic range --
+__global__ __launch_bounds__(256) void z_range_kernel(const TensorMeta* meta, int n, void* acc, int first) {
+    __shared__ float red[256];
+    z_range_block(meta, n, acc, first, red);
+}
+
+hipError_t launch_z_range(const TensorMeta* meta, int n, void* acc, int first, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    z_range_kernel<<<1, 256, 0, s>>>(meta, n, acc, first);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ meta init --
 __global__ void meta_init_kernel(TensorMeta* meta, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -580,17 +592,14 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(Planes part, Planes C
         return;
     }
     const int S = 1 << lsplit;
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
     i64 o = (i64)blockIdx.x * 256 + threadIdx.x;
     if (o < nout) {
         const V acc = split_sum<D>(part, nout, o, S, ap);
         A::store(C, o, acc);
-        if constexpr (is_z<D>()) lmax = acc;
+        if constexpr (is_z<D>()) z_track(acc, lmax, lmin);
     }
-    if constexpr (is_z<D>()) {
-        for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
-        if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(meta, mc, __float_as_uint(lmax));
-    }
+    if constexpr (is_z<D>()) z_meta_block(meta, mc, lmax, lmin);
 }
 
 // ---------------------------------------------------------- back-trace --

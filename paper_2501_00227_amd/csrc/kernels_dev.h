@@ -346,12 +346,78 @@ __device__ inline long long meta_exp(const TensorMeta* m, int i) {
 __device__ inline void meta_set(TensorMeta* m, int i, long long e, unsigned int bits) {
     __hip_atomic_store(&m[i].exp, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&m[i].maxbits, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&m[i].minnz_inv, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&m[i].operand_range, 0.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned int meta_minnz_inv(const TensorMeta* m, int i) {
+    return __hip_atomic_load(&m[i].minnz_inv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// log2(max / smallest nonzero) from a tensor's record (0 when empty)
+__device__ inline float bits_range(unsigned mx, unsigned mn_inv) {
+    return (mx != 0u && mn_inv != 0u) ? log2f(__uint_as_float(mx)) - log2f(__uint_as_float(~mn_inv)) : 0.0f;
+}
+__device__ inline float meta_range(const TensorMeta* m, int i) {
+    return bits_range(meta_maxbits(m, i), meta_minnz_inv(m, i));
 }
 __device__ inline void meta_set_exp(TensorMeta* m, int i, long long e) {
     __hip_atomic_store(&m[i].exp, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void meta_max(TensorMeta* m, int i, unsigned int bits) {
     __hip_atomic_fetch_max(&m[i].maxbits, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// the smallest nonzero entry, as the complement of its bits under an atomic
+// maximum (positive floats order as their bits)
+__device__ inline void meta_min_nonzero(TensorMeta* m, int i, float v) {
+    if (v > 0.0f && v < INFINITY)
+        __hip_atomic_fetch_max(&m[i].minnz_inv, ~__float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The dynamic range of the stored partition-function entries: the largest
+// and the smallest nonzero value seen by a thread.
+__device__ inline void z_track(float v, float& lmax, float& lmin) {
+    lmax = fmaxf(lmax, v);
+    if (v > 0.0f) lmin = fminf(lmin, v);
+}
+// A workgroup barrier that orders LDS only: __syncthreads() would also wait
+// for the workgroup's global stores to complete, a round trip on the tail of
+// a launch that no LDS exchange needs.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+// The extremes of a tensor's stored entries, added to its record.  Atomics
+// on one record serialise where its line lives: a large launch first reduces
+// over the workgroup (one atomic pair per workgroup); a small one, whose
+// cost is the latency of its tail, lets each wave add its own pair.  Every
+// thread of the workgroup calls (the branch is uniform over the launch);
+// every launch that calls has 256-thread workgroups (reading blockDim would
+// cost a vector load, whose wait also waits for the tile's stores).
+constexpr unsigned kZWaveAtomicGrid = 64;
+constexpr int kZWaves = 4;
+__device__ inline void z_meta_block(TensorMeta* m, int i, float lmax, float lmin) {
+    __shared__ float2 ext[kZWaves];
+    for (int off = 32; off > 0; off >>= 1) {
+        lmax = fmaxf(lmax, __shfl_xor(lmax, off));
+        lmin = fminf(lmin, __shfl_xor(lmin, off));
+    }
+    if (gridDim.x > kZWaveAtomicGrid) {
+        if ((threadIdx.x & 63) == 0) ext[threadIdx.x >> 6] = make_float2(lmax, lmin);
+        lds_barrier();
+        // wave 0: lane w takes wave w's pair
+        const float2 e = (int)threadIdx.x < kZWaves ? ext[threadIdx.x] : make_float2(0.0f, INFINITY);
+        lds_barrier();  // ext is free for the workgroup's next call
+        if (threadIdx.x >= 64) return;
+        lmax = e.x;
+        lmin = e.y;
+        for (int off = kZWaves / 2; off > 0; off >>= 1) {
+            lmax = fmaxf(lmax, __shfl_xor(lmax, off));
+            lmin = fminf(lmin, __shfl_xor(lmin, off));
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (lmax > 0.0f) meta_max(m, i, __float_as_uint(lmax));
+        meta_min_nonzero(m, i, lmin);
+    }
 }
 
 // exponent m with 2^m <= max < 2^(m+1) of a non-negative float given by its bits
@@ -450,13 +516,14 @@ __device__ inline void leaf_one_z(const LeafDev& d, int leaf_id, const float* w,
         mx = fmax(mx, acc);
     }
     int ex = mx > 0.0 ? ilogb(mx) : 0;
-    float fmx = 0.0f;
+    float fmx = 0.0f, fmn = INFINITY;
     for (int e = 0; e < nent; e++) {
         float f = (float)ldexp(val[e], -ex);
-        fmx = fmaxf(fmx, f);
+        z_track(f, fmx, fmn);
         ((float*)arena.p0)[d.off + e] = f;
     }
     meta_set(meta, leaf_id, ex, __float_as_uint(fmx));
+    meta_min_nonzero(meta, leaf_id, fmn);
 }
 
 template <int D>
@@ -685,20 +752,54 @@ __device__ inline unsigned gemm_stage(const GemmArgs& g, const TilePos& p, i64 k
     return hi;
 }
 
-// Partition function: the exponent of C (first tile only) and the running
-// maximum of the stored entries (one atomic per wave).
+// Partition function.  The first tile reads its operands' records when it
+// starts (sharing the round trip of the input scales), derives C's exponent
+// and the operands' ranges added once its own operand loads have landed
+// (before it stores: a wait there is free, after the stores it would wait for
+// them too), and writes both at its end; every tile adds the extremes of
+// what it stored (split partials leave them to the split reduction).
+struct ZOperands {
+    long long ea, eb;
+    unsigned xa, xb, na, nb;
+};
+struct ZDerived {
+    long long exp;
+    float range;
+};
 template <int D>
-__device__ inline void z_epilogue(const GemmArgs& g, u64 first_tile, float lmax) {
+__device__ inline ZOperands z_prologue(const GemmArgs& g, u64 tile) {
+    ZOperands z{};
     if constexpr (is_z<D>()) {
-        if (first_tile == 0 && threadIdx.x == 0) {
-            meta_set_exp(g.meta, g.mc,
-                         meta_exp(g.meta, g.ma) + max_exponent(meta_maxbits(g.meta, g.ma)) + meta_exp(g.meta, g.mb) +
-                             max_exponent(meta_maxbits(g.meta, g.mb)));
+        if (tile == 0) {
+            z.ea = meta_exp(g.meta, g.ma);
+            z.eb = meta_exp(g.meta, g.mb);
+            z.xa = meta_maxbits(g.meta, g.ma);
+            z.xb = meta_maxbits(g.meta, g.mb);
+            z.na = meta_minnz_inv(g.meta, g.ma);
+            z.nb = meta_minnz_inv(g.meta, g.mb);
         }
-        if (!g.lsplit) {
-            for (int off = 32; off > 0; off >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, off));
-            if ((threadIdx.x & 63) == 0 && lmax > 0.0f) meta_max(g.meta, g.mc, __float_as_uint(lmax));
+    }
+    return z;
+}
+template <int D>
+__device__ inline ZDerived z_derive(u64 tile, const ZOperands& z) {
+    ZDerived d{0, 0.0f};
+    if constexpr (is_z<D>()) {
+        if (tile == 0) {
+            d.exp = z.ea + max_exponent(z.xa) + z.eb + max_exponent(z.xb);
+            d.range = bits_range(z.xa, z.na) + bits_range(z.xb, z.nb);
         }
+    }
+    return d;
+}
+template <int D>
+__device__ inline void z_epilogue(const GemmArgs& g, u64 tile, const ZDerived& z, float lmax, float lmin) {
+    if constexpr (is_z<D>()) {
+        if (tile == 0 && threadIdx.x == 0) {
+            meta_set_exp(g.meta, g.mc, z.exp);
+            __hip_atomic_store(&g.meta[g.mc].operand_range, z.range, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!g.lsplit) z_meta_block(g.meta, g.mc, lmax, lmin);
     }
 }
 
@@ -718,6 +819,7 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
     const int x = tid % TNt, y = (tid / TNt) % TMt, z = tid / (TNt * TMt);
 
     const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    const ZOperands zo = z_prologue<D>(g, tile);
 
     V acc[RM][RN];
 #pragma unroll
@@ -827,7 +929,8 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
         __syncthreads();
     }
 
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
+    const ZDerived zd = z_derive<D>(tile, zo);
     if (tid < active) {
         const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
         const Planes dst = g.lsplit ? g.P : g.C;
@@ -838,10 +941,10 @@ __device__ void gemm_tile(const GemmArgs& g, u64 tile, unsigned char* smem) {
             for (int c = 0; c < RN; c++) {
                 i64 o = ((((p.b0 + z) << g.li) | (p.i0 + y + r * TMt)) << g.lj) | (p.j0 + x + c * TNt);
                 A::store(dst, base + o, acc[r][c]);
-                if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc[r][c]);
+                if constexpr (is_z<D>()) z_track(acc[r][c], lmax, lmin);
             }
     }
-    z_epilogue<D>(g, tile, lmax);
+    z_epilogue<D>(g, tile, zd, lmax, lmin);
 }
 
 // Register-tiled GEMM of the 4-byte VALU algebras (max-plus int32/f32, counts
@@ -1284,6 +1387,7 @@ __device__ void gemm_tile_mfma(const GemmArgs& g, u64 tile, unsigned char* smem)
     const int wr = w >> 1, wc = w & 1;
     const int half = lane >> 5, l32 = lane & 31;
     const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    const ZOperands zo = z_prologue<D>(g, tile);
     tn_v16f acc;
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[r] = 0.0f;
@@ -1312,15 +1416,16 @@ __device__ void gemm_tile_mfma(const GemmArgs& g, u64 tile, unsigned char* smem)
     }
     const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
     float* dst = (float*)(g.lsplit ? g.P.p0 : g.C.p0) + (g.lsplit ? (i64)p.split * nout : 0);
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
+    const ZDerived zd = z_derive<D>(tile, zo);
 #pragma unroll
     for (int r = 0; r < 16; r++) {
         const int row = 8 * (r >> 2) + 4 * half + (r & 3);
         const i64 o = (((p.b0 << g.li) | (p.i0 + wr * 32 + row)) << g.lj) | (p.j0 + wc * 32 + l32);
         dst[o] = acc[r];
-        lmax = fmaxf(lmax, acc[r]);
+        z_track(acc[r], lmax, lmin);
     }
-    z_epilogue<D>(g, tile, lmax);
+    z_epilogue<D>(g, tile, zd, lmax, lmin);
 }
 
 // Partition function on the matrix cores, large tiles: a 128 x 128 output
@@ -1359,6 +1464,7 @@ __device__ void gemm_tile_mfma128(const GemmArgs& g, u64 tile, unsigned char* sm
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1, half = lane >> 5, l32 = lane & 31;
     const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    const ZOperands zo = z_prologue<D>(g, tile);
     // global -> register prefetch of one K step: NV float4 per operand per
     // thread; element e = tid + 256 v of the 128 x TK tile, 4 values each
     float4 ra[NV], rb[NV];
@@ -1481,7 +1587,8 @@ __device__ void gemm_tile_mfma128(const GemmArgs& g, u64 tile, unsigned char* sm
     }
     const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
     float* dst = (float*)(g.lsplit ? g.P.p0 : g.C.p0) + (g.lsplit ? (i64)p.split * nout : 0);
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
+    const ZDerived zd = z_derive<D>(tile, zo);
 #pragma unroll
     for (int bi = 0; bi < 2; bi++)
 #pragma unroll
@@ -1492,9 +1599,9 @@ __device__ void gemm_tile_mfma128(const GemmArgs& g, u64 tile, unsigned char* sm
                 const int col = wc * 64 + bj * 32 + l32;
                 const i64 o = (((p.b0 << g.li) | (p.i0 + row)) << g.lj) | (p.j0 + col);
                 dst[o] = acc[bi][bj][r];
-                lmax = fmaxf(lmax, acc[bi][bj][r]);
+                z_track(acc[bi][bj][r], lmax, lmin);
             }
-    z_epilogue<D>(g, tile, lmax);
+    z_epilogue<D>(g, tile, zd, lmax, lmin);
 }
 
 // ----------------------------------------------------- thin / dot GEMM --
@@ -1513,13 +1620,15 @@ __device__ void gemm_tile_thin(const GemmArgs& g, u64 tile, unsigned char* smem)
     const TilePos p = tile_pos(g, tile);
     const int K = 1 << g.lk, N = 1 << g.lj;
     const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    const ZOperands zo = z_prologue<D>(g, tile);
     for (int q = threadIdx.x; q < K * N; q += 256) {
         const int k = q >> g.lj, j = q & (N - 1);
         const i64 addr = g.b_t ? (((p.b0 << g.lj) | j) << g.lk) | k : (((p.b0 << g.lk) | k) << g.lj) | j;
         Bs[q] = A::prescale(A::load(g.B, addr), sB);
     }
     __syncthreads();
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
+    const ZDerived zd = z_derive<D>(tile, zo);
     const int rows = 1 << g.ti;
     for (int r0 = 0; r0 < rows; r0 += 256 * RQ) {
         V av[RQ][KMAX];
@@ -1542,11 +1651,11 @@ __device__ void gemm_tile_thin(const GemmArgs& g, u64 tile, unsigned char* smem)
                 for (int k = 0; k < KMAX; k++)
                     if (k < K) acc = A::add(acc, A::mul(A::prescale(av[q][k], sA), Bs[(k << g.lj) | j], g.ap), g.ap);
                 A::store(g.C, obase | j, acc);
-                if constexpr (is_z<D>()) lmax = fmaxf(lmax, acc);
+                if constexpr (is_z<D>()) z_track(acc, lmax, lmin);
             }
         }
     }
-    z_epilogue<D>(g, tile, lmax);
+    z_epilogue<D>(g, tile, zd, lmax, lmin);
 }
 
 // One output per batch (GEMM_DOT): a tile is one (batch, K-split) pair; the
@@ -1559,6 +1668,7 @@ __device__ void gemm_tile_dot(const GemmArgs& g, u64 tile, unsigned char* smem) 
     V* red = (V*)smem;
     const TilePos p = tile_pos(g, tile);
     const float sA = input_scale<D>(g, g.ma), sB = input_scale<D>(g, g.mb);
+    const ZOperands zo = z_prologue<D>(g, tile);
     V acc = A::zero(g.ap);
     const i64 base = p.b0 << g.lk;
     for (i64 k = p.kbeg + threadIdx.x; k < p.kbeg + p.Kc; k += 256)
@@ -1570,16 +1680,17 @@ __device__ void gemm_tile_dot(const GemmArgs& g, u64 tile, unsigned char* smem) 
         if ((int)threadIdx.x < w) red[threadIdx.x] = A::add(red[threadIdx.x], red[threadIdx.x + w], g.ap);
         __syncthreads();
     }
-    float lmax = 0.0f;
+    float lmax = 0.0f, lmin = INFINITY;
+    const ZDerived zd = z_derive<D>(tile, zo);
     if (threadIdx.x == 0) {
         const i64 nout = (i64)1 << g.lb;
         if (g.lsplit)
             A::store(g.P, (i64)p.split * nout + p.b0, red[0]);
         else
             A::store(g.C, p.b0, red[0]);
-        if constexpr (is_z<D>()) lmax = red[0];
+        if constexpr (is_z<D>()) z_track(red[0], lmax, lmin);
     }
-    z_epilogue<D>(g, tile, lmax);
+    z_epilogue<D>(g, tile, zd, lmax, lmin);
     __syncthreads();
 }
 
@@ -1622,7 +1733,33 @@ __device__ void split_reduce_one(Planes part, Planes C, i64 nout, int lsplit, co
         A::store(C, o, red[0]);
         if constexpr (is_z<D>()) {
             if (red[0] > 0.0f) meta_max(meta, mc, __float_as_uint(red[0]));
+            meta_min_nonzero(meta, mc, red[0]);
         }
+    }
+    __syncthreads();
+}
+
+// The partition function's dynamic range: over the n tensors of a
+// contraction, the largest log2(max / smallest nonzero) of the stored
+// float32 entries, or of the two operands of a product added together (the
+// span a product of their entries needs; past the float32 exponent range the
+// smallest products underflow), by one workgroup (every thread calls); written as a float
+// at byte kZRangeOffset of the pass's accumulator slot, or raised to it when
+// first is 0 (later slices).
+__device__ inline void z_range_block(const TensorMeta* m, int n, void* acc, int first, float* red) {
+    float best = 0.0f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        best = fmaxf(best, fmaxf(meta_range(m, i),
+                                 __hip_atomic_load(&m[i].operand_range, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float* slot = (float*)((char*)acc + kZRangeOffset);
+        *slot = first ? red[0] : fmaxf(*slot, red[0]);
     }
     __syncthreads();
 }
