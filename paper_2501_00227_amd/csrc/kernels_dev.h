@@ -1139,8 +1139,10 @@ __device__ inline bool gemm_tile_big_any(const GemmArgs& g, u64 tile, unsigned c
 // 64-bit multiply-add.  When no staged count of the step (A or B) reaches
 // 2^32 (the usual case: counts of optimal configurations are small) the
 // product's cross terms vanish and the second pass takes a 32 x 32 -> 64
-// multiply-add per term only; the staging loop ORs the high words and the
-// tile's waves agree on the path through a flag in LDS.  Sizes are staged
+// multiply-add per term only; when none reaches 2^floor((32 - tk) / 2) the
+// step's products and their sum fit 32 bits, and it takes a 24-bit
+// multiply-add into a 32-bit partial per output.  The staging loop ORs the
+// words and the tile's waves agree on the path through flags in LDS.  Sizes are staged
 // clamped at -2^30, so sums of two
 // never overflow int32 (-inf = INT32_MIN outside); an output whose size stays
 // below -2^29 is -inf (count 0) when stored.  Real sizes satisfy |s| <= 2^28.
@@ -1186,17 +1188,20 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
             accc[r][c] = 0ull;
         }
     const int na = TM * TK, nb = TN * TK;
-    // per K step (two alternating slots): set when a staged count has a
-    // nonzero high word; a slot is cleared one step ahead, after the barrier
-    // that ends the last step reading it
-    __shared__ int s_wide[2];
-    if (tid == 0) s_wide[0] = s_wide[1] = 0;
+    // per K step (two alternating slots): s_wide is set when a staged count
+    // has a nonzero high word, s_big when one reaches small_lim; a slot is
+    // cleared one step ahead, after the barrier that ends the last step
+    // reading it.  Below small_lim the step's products and their sum over
+    // the step fit 32 bits: TK (small_lim - 1)^2 < 2^32.
+    __shared__ int s_wide[2], s_big[2];
+    const unsigned small_lim = 1u << ((32 - g.tk) / 2);
+    if (tid == 0) s_wide[0] = s_wide[1] = s_big[0] = s_big[1] = 0;
     __syncthreads();
     int step = 0;
     for (int kk = 0; kk < p.Kc; kk += TK, step ^= 1) {
         const i64 k0 = p.kbeg + kk;
-        if (tid == 0) s_wide[step ^ 1] = 0;
-        unsigned hi_or = 0;
+        if (tid == 0) s_wide[step ^ 1] = s_big[step ^ 1] = 0;
+        unsigned hi_or = 0, lo_or = 0;
         for (int idx = tid; idx < na; idx += 256) {
             int i, k;
             i64 addr;
@@ -1212,6 +1217,7 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
             An[k * TMP + i] = max(((const int*)g.A.p0)[addr], kCtNegInf);
             const u64 c = ((const u64*)g.A.p1)[addr];
             hi_or |= (unsigned)(c >> 32);
+            lo_or |= (unsigned)c;
             Acl[k * TMP + i] = (unsigned)c;
             Ach[k * TMP + i] = (unsigned)(c >> 32);
         }
@@ -1230,12 +1236,17 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
             Bn[k * TNP + j] = max(((const int*)g.B.p0)[addr], kCtNegInf);
             const u64 c = ((const u64*)g.B.p1)[addr];
             hi_or |= (unsigned)(c >> 32);
+            lo_or |= (unsigned)c;
             Bcl[k * TNP + j] = (unsigned)c;
             Bch[k * TNP + j] = (unsigned)(c >> 32);
         }
-        if (__any(hi_or != 0) && (tid & 63) == 0) s_wide[step] = 1;
+        const bool any_hi = __any(hi_or != 0), any_big = __any(lo_or >= small_lim);
+        if ((tid & 63) == 0) {
+            if (any_hi) s_wide[step] = 1;
+            if (any_big) s_big[step] = 1;
+        }
         __syncthreads();
-        const bool wide = s_wide[step] != 0;
+        const bool wide = s_wide[step] != 0, small = !wide && s_big[step] == 0;
         // pass 1: the step's largest size per output
         int m[RMT][RNT];
 #pragma unroll
@@ -1275,6 +1286,35 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                 accn[r][c] = m[r][c];
             }
         // pass 2: count products of the terms at the output's size
+        if (small) {  // 24-bit multiply-adds into a 32-bit partial per output
+            unsigned part[RMT][RNT];
+#pragma unroll
+            for (int r = 0; r < RMT; r++)
+#pragma unroll
+                for (int c = 0; c < RNT; c++) part[r][c] = 0u;
+            for (k = 0; k < TK; k++) {
+                int an[RMT], bn[RNT];
+                unsigned ac[RMT], bc[RNT];
+                load_sizes(k, an, bn);
+#pragma unroll
+                for (int h = 0; h < RMT / 4; h++) lds_load4(Acl + k * TMP + h * (TM / 2) + ty * 4, ac + 4 * h);
+#pragma unroll
+                for (int h = 0; h < RNT / 4; h++) lds_load4(Bcl + k * TNP + h * (TN / 2) + tx * 4, bc + 4 * h);
+#pragma unroll
+                for (int r = 0; r < RMT; r++)
+#pragma unroll
+                    for (int c = 0; c < RNT; c++) {
+                        const unsigned b = an[r] + bn[c] == accn[r][c] ? bc[c] : 0u;
+                        part[r][c] = __umul24(ac[r], b) + part[r][c];
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < RMT; r++)
+#pragma unroll
+                for (int c = 0; c < RNT; c++) accc[r][c] += part[r][c];
+            __syncthreads();
+            continue;
+        }
         if (!wide) {  // every count of the step below 2^32: low words only
             for (k = 0; k < TK; k++) {
                 int an[RMT], bn[RNT];
