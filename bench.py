@@ -50,17 +50,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM = 8000e9  # bytes / s
-# VALU: the published FP32 vector rate, 157.3 TFLOP/s = 78.65 T lane FMAs / s,
-# taken as 78.65 T 32-bit lane instructions / s (256 CUs x 2.4 GHz x 128).
-LANE = 78.65e12
-# Fewest VALU instructions per semiring op on gfx950: max-plus one add per
-# product plus one three-input max per two products (1.5); counting tropical
-# a saturating add, a 64-bit product (one 32x32->64 multiply-add, two 32-bit
-# multiplies, one three-input add), two compares, four selects, a 64-bit add
-# and a max (13); counts mod p a 32x32->64 multiply-add per product plus one
+# VALU issue, 256 CUs x 2.4 GHz: FP32 instructions 128 lanes per CU-clock
+# (the published 157.3 TFLOP/s = 78.65 T lane FMAs / s); integer instructions
+# (adds, three-input max, compares, selects, multiply-adds) one wave of 64
+# lanes per CU-clock, 39.3 T lane instructions / s, the rate the integer
+# kernels' VALU counters saturate at.
+LANE_F32 = 78.65e12
+LANE_INT = 256 * 2.4e9 * 64
+# Fewest VALU instructions per semiring op: max-plus one add per product plus
+# one three-input max per two products (1.5); counting tropical in two
+# passes, 1.5 for the sizes plus add, compare, select and multiply-add for the
+# counts (5.5); counts mod p a 32x32->64 multiply-add per product plus one
 # Montgomery reduction (two multiplies, an add, a min) per four (2.5).
-ENGINE = {"tropical_i32": LANE / 1.5, "tropical_f32": LANE / 1.5, "counting_tropical": LANE / 13.0,
-          "count_exact": LANE / 2.5,
+ENGINE = {"tropical_i32": LANE_INT / 1.5, "tropical_f32": LANE_F32 / 1.5, "counting_tropical": LANE_INT / 5.5,
+          "count_exact": LANE_INT / 2.5,
           # the real algebra on matrix cores: one multiply-add per op;
           # 157.3 TFLOP/s float32, 2.5 PFLOP/s bfloat16 inputs (dense)
           "partition_f32": 157.3e12 / 2, "partition_bf16": 2.5e15 / 2}
