@@ -301,6 +301,49 @@ def k3_record(ctx):
     return out
 
 
+def k1_graphs():
+    import graphgen as gg
+
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "k1.json")))["cases"]
+    return [gg.random_regular(20, 3, c["seed"]) for c in gold], gold
+
+
+def k1_record(ctx, reps=20):
+    """Twenty 3-regular 20-vertex graphs (seeds 0..19), counting tropical:
+    solves per second one at a time (both executors) and as one batch, every
+    result against the oracle's stored values.  Intermediates of a few KB:
+    launch latency, not a roofline, sets the rate."""
+    import paper_2501_00227_amd as tn
+
+    graphs, gold = k1_graphs()
+    nets = [tn.Net.from_graph(g) for g in graphs]
+    plans = [tn.Plan.create(n, seed=c["seed"]) for n, c in zip(nets, gold)]
+    want = [(c["size_max"], c["count_max"]) for c in gold]
+    out = {"workload": "K1: 3-regular n=20 seeds 0..19, unit weights, counting tropical (int32 size, uint64 count), "
+                       "greedy plans", "jobs": len(nets),
+           "sc_log2_max": max(p.complexity()[1] for p in plans)}
+
+    def check(rs):
+        return all((r["size"], r["count_mod_2_64"]) == w for r, w in zip(rs, want))
+
+    for ex in ("stream", "persistent"):
+        one = lambda: [ctx.solve(n, p, "counting_tropical", executor=ex) for n, p in zip(nets, plans)]  # noqa: E731
+        ok = check(one())
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ok = check(one()) and ok
+        dt = time.perf_counter() - t0
+        out["one_at_a_time_" + ex] = {"solves_per_s": reps * len(nets) / dt, "exact": ok}
+    batch = lambda: ctx.solve_batch(nets, plans, "counting_tropical")  # noqa: E731
+    ok = check(batch())
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ok = check(batch()) and ok
+    dt = time.perf_counter() - t0
+    out["batched"] = {"solves_per_s": reps * len(nets) / dt, "exact": ok, "launches_per_batch": 1}
+    return out
+
+
 # ---------------------------------------------------------- cpu baseline --
 def _o3_slice(args):
     import graphgen as gg
@@ -341,13 +384,22 @@ def cpu_baseline():
         res = pool.map(_o3_slice, [(tree, s) for s in range(cores)])
     wall = time.perf_counter() - t0
     ops = cores * 2 * 2.0 ** tc_slice
+    # beside K1: the oracle's brute force over all 2^20 subsets, one core
+    import oracle
+
+    graphs, _ = k1_graphs()
+    t1 = time.perf_counter()
+    for g1 in graphs:
+        oracle.brute_force(g1)
+    k1 = {"solves_per_s": len(graphs) / (time.perf_counter() - t1), "cores": 1,
+          "sample": "the twenty K1 graphs (3-regular n=20), brute force over all 2^20 subsets"}
     return {"value": ops / wall / 1e9, "unit": "GOP/s", "cores": cores, "kind": "oracle",
             "sample": "3-regular n=240 seed 0 (the headline network), tropical + counting tropical by the oracle's plan "
                       "follower on a TreeSA plan sliced to 2^%d-entry intermediates (%d slices of 2^%.2f ops each): "
                       "slices 0..%d, one process per core" % (info["max_rank"], 1 << info["nsliced"], tc_slice,
                                                               cores - 1),
             "seconds": wall, "per_slice_seconds_mean": sum(r[0] for r in res) / len(res),
-            "nproc": os.cpu_count(), "cpu_model": model}
+            "nproc": os.cpu_count(), "cpu_model": model, "k1_brute_force": k1}
 
 
 def independence_polynomial(ctx, net, plan, tc):
@@ -659,6 +711,7 @@ def main():
     ap.add_argument("--k3", action="store_true", help="only the King's-subgraph partition-function line")
     ap.add_argument("--k2", action="store_true", help="only the 120-vertex persistent step")
     ap.add_argument("--k4", action="store_true", help="only the served workload")
+    ap.add_argument("--k1", action="store_true", help="only the twenty 20-vertex graphs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy (for scaling hardware byte counters) and exit")
     args = ap.parse_args()
@@ -668,7 +721,7 @@ def main():
         sys.exit(2)
     # the oracle runs first, in forked processes, before anything touches the GPU
     cpu = None
-    only = args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2 or args.k4
+    only = args.tune_out or args.widened or args.calibrate_copy or args.k3 or args.k2 or args.k4 or args.k1
     if not (args.no_cpu or only):
         cpu = cpu_baseline()
 
@@ -693,6 +746,9 @@ def main():
         tn.tune_load(TABLE)
     if args.k3:
         print(json.dumps({"k3": k3_record(ctx)}))
+        return
+    if args.k1:
+        print(json.dumps({"k1": k1_record(ctx)}))
         return
     if args.k4:
         print(json.dumps({"batched": job_stream(ctx, args.jobs, args.seed, k4_expected(args.jobs, args.seed))}))
@@ -769,6 +825,7 @@ def main():
                           "results": {"size_max": res2[0]["size"], "count_all": str(res2[1]["count"]),
                                       "log_z": res2[2]["log_z"]}}
         out["k3"] = k3_record(ctx)
+        out["k1"] = k1_record(ctx)
         g, net, plan = g2, net2, plan2
         out["independence_polynomial"] = independence_polynomial(ctx, net, plan, tc2)
         out["spin_glass_buckyball"] = buckyball(ctx)
