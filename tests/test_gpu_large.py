@@ -116,19 +116,24 @@ def test_k5_full_size_slices_cross_algebra(ctx):
         assert c["count_mod_2_64"] == c2["count_mod_2_64"] > 0
 
 
-def test_k5_all_slices_agree_across_plans(ctx):
-    """The 240-vertex network over all slices of its 2^30-entry plan (the
-    benchmark's) and of a differently annealed plan sliced to 2^26 entries
-    (another tree, other sliced indices, permutes and launch shapes): the same
-    maximum size in both max-plus algebras and the same size and count of
-    maximum sets in the counting-tropical one."""
-    g = _k5()
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_k5_all_slices_agree_across_plans(ctx, seed):
+    """The 240-vertex networks (seeds 0..2) over all slices of a plan with
+    2^30-entry intermediates (seed 0: the benchmark's) and of a differently
+    annealed plan sliced to 2^26 entries (another tree, other sliced indices,
+    permutes and launch shapes): the same maximum size in both max-plus
+    algebras and the same size and count of maximum sets in the
+    counting-tropical one."""
+    g = gg.random_regular(240, 3, seed)
     net = tn.Net.from_graph(g)
-    p30 = tn.Plan.create(net, method="treesa", ntrials=16, niters=50, rw_weight=0.5, sc_target=30, nslices=30, seed=0)
-    p26 = tn.Plan.create(net, method="treesa", ntrials=8, niters=20, sc_target=26, nslices=40, seed=5)
+    p30 = tn.Plan.create(net, method="treesa", ntrials=16, niters=50, rw_weight=0.5, sc_target=30, nslices=30,
+                         seed=seed)
+    p26 = tn.Plan.create(net, method="treesa", ntrials=8, niters=20, sc_target=26, nslices=40, seed=5 + seed)
     i30, i26 = p30.info(), p26.info()
-    print("plans", p30.complexity(), i30["nsliced"], p26.complexity(), i26["nsliced"], flush=True)
-    assert i30["max_rank"] == 30 and i26["max_rank"] <= 26 and i26["nsliced"] > i30["nsliced"]
+    print("seed", seed, "plans", p30.complexity(), i30["nsliced"], p26.complexity(), i26["nsliced"], flush=True)
+    assert 28 <= i30["max_rank"] <= 30 and i26["max_rank"] <= 26 and i26["nsliced"] > i30["nsliced"]
+    if seed == 0:
+        assert i30["max_rank"] == 30
     a = ctx.solve(net, p30, "counting_tropical")
     b = ctx.solve(net, p26, "counting_tropical")
     print("counting tropical", a["size"], a["count_mod_2_64"], b["size"], b["count_mod_2_64"], flush=True)
