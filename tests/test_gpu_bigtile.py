@@ -309,3 +309,27 @@ def test_counting_tropical_big_tiles_with_counts_above_2_32(ctx, base):
     assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count"] % 2 ** 64)
     rp = ctx.solve(net, plan, "counting_tropical", executor="persistent")
     assert (rp["size"], rp["count_mod_2_64"]) == (want["size"], want["count"] % 2 ** 64)
+
+
+@pytest.mark.parametrize("ntwo,nthree", [(8, 4), (12, 6), (16, 8)])
+def test_counting_tropical_big_tiles_with_counts_around_2_14(ctx, ntwo, nthree):
+    """Below 2^floor((32 - tk) / 2) (2^14 for the tiles' K step of 16) a K
+    step's counts take the 24-bit path, up to 2^32 the 32-bit one: a few
+    pendant paths on the 120-vertex graph put the number of maximum sets at
+    2^13.9, 2^18.1 and 2^21.3, so the large nodes hold counts on both sides
+    of the line and their tiles switch paths from step to step."""
+    g0 = gg.random_regular(120, 3, 5)
+    perm = np.random.default_rng(4).permutation(g0.nv)
+    two, three = sorted(perm[:ntwo].tolist()), sorted(perm[ntwo:ntwo + nthree].tolist())
+    g = _with_pendant_paths(g0, two, three)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net, seed=0)
+    want = oracle.eliminate(g, "counting_tropical")
+    print(f"rr120+{ntwo}+{nthree}: complexity {plan.complexity()}, size {want['size']}, "
+          f"count 2^{float(np.log2(float(want['count']))):.1f}", flush=True)
+    assert 2 ** 13 < want["count"] < 2 ** 32
+    r, recs = _solve_profiled(ctx, net, plan, "counting_tropical")
+    assert {_ct_tile(x["shape"]) for x in recs if x["kind"] == "gemm_big"} - {None}
+    assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count"])
+    rp = ctx.solve(net, plan, "counting_tropical", executor="persistent")
+    assert (rp["size"], rp["count_mod_2_64"]) == (want["size"], want["count"])
