@@ -156,8 +156,13 @@ GemmShape choose_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, in
 GemmShape heuristic_gemm_shape(int dsr, int lb, int li, int lj, int lk, int a_t, int b_t, bool mfma128 = true);
 bool gemm_shape_valid(int dsr, const GemmShape& g);
 size_t gemm_lds_bytes(int dsr, const GemmShape& g);
+// Counting-tropical register tiles whose next K step is read into LDS while
+// the current one computes (128 x 64 and 64 x 128 tiles, 4 <= TK <= 16).
+constexpr bool ct_ahead_shape(int ti, int tj, int tk) {
+    return ((ti == 7 && tj == 6) || (ti == 6 && tj == 7)) && tk >= 2 && tk <= 4;
+}
 // Name of the kernel (template instance) a launch of shape g runs, as in
-// profiler listings, e.g. "gemm_ct_big_kernel<7, 6>".
+// profiler listings, e.g. "gemm_ct_big_kernel<7, 6, true>".
 const char* gemm_kernel_name(int dsr, const GemmShape& g, char* buf, size_t cap);
 
 // Tuning helpers: seeded operand data for an algebra, and a device-side

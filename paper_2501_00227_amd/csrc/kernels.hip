@@ -244,18 +244,21 @@ static hipError_t gemm_mode_go(const GemmArgs& a, int mode, size_t lds, u64 bloc
     return hipGetLastError();
 }
 
-template <int LTM, int LTN>
+template <int LTM, int LTN, bool AHEAD>
 __global__ __launch_bounds__(256, 2) void gemm_ct_big_kernel(GemmArgs g) {
     extern __shared__ __align__(16) unsigned char smem[];
-    gemm_tile_ct_big<LTM, LTN>(g, blockIdx.x, smem);
+    gemm_tile_ct_big<LTM, LTN, AHEAD>(g, blockIdx.x, smem);
 }
 
 static hipError_t gemm_ct_big_go(const GemmArgs& a, size_t lds, u64 blocks, hipStream_t s) {
     const dim3 grid((unsigned)blocks), block(256);
-    if (a.ti == 7 && a.tj == 6) gemm_ct_big_kernel<7, 6><<<grid, block, lds, s>>>(a);
-    else if (a.ti == 6 && a.tj == 7) gemm_ct_big_kernel<6, 7><<<grid, block, lds, s>>>(a);
-    else if (a.ti == 8 && a.tj == 5) gemm_ct_big_kernel<8, 5><<<grid, block, lds, s>>>(a);
-    else if (a.ti == 5 && a.tj == 8) gemm_ct_big_kernel<5, 8><<<grid, block, lds, s>>>(a);
+    const bool ahead = ct_ahead_shape(a.ti, a.tj, a.tk);
+    if (a.ti == 7 && a.tj == 6 && ahead) gemm_ct_big_kernel<7, 6, true><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 6 && a.tj == 7 && ahead) gemm_ct_big_kernel<6, 7, true><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 7 && a.tj == 6) gemm_ct_big_kernel<7, 6, false><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 6 && a.tj == 7) gemm_ct_big_kernel<6, 7, false><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 8 && a.tj == 5) gemm_ct_big_kernel<8, 5, false><<<grid, block, lds, s>>>(a);
+    else if (a.ti == 5 && a.tj == 8) gemm_ct_big_kernel<5, 8, false><<<grid, block, lds, s>>>(a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

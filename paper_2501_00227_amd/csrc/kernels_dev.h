@@ -1161,7 +1161,27 @@ __device__ inline u64 mad_u64_mod(u64 acc, unsigned alo, unsigned ahi, unsigned 
     return ((u64)hi << 32) | (unsigned)t;
 }
 
-template <int LTM, int LTN>
+// Operand tiles of a K step read ahead into LDS (the 128 x 64 and 64 x 128
+// tiles, 4 <= TK <= 16): the next step's sizes and counts travel from global
+// memory into a raw staging area while the current step computes, by
+// global-to-LDS loads that hold no registers; the planes are then filled
+// from LDS.  raw holds, in global-memory order, the A sizes, A counts,
+// B sizes and B counts of one step, 16 bytes per load.
+constexpr int kCtRawSlots = 3 * (128 + 64) * 16 / 4;
+// s_waitcnt vmcnt(0): this thread's vector memory operations, global-to-LDS
+// loads included, have completed
+__device__ inline void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// One 16-byte global-to-LDS load: the wave's 64 lanes fill 64 consecutive
+// 16-byte slots from LDS address lds_base (wave-uniform).  Written in asm so
+// that the compiler does not make every LDS read of the other buffers wait
+// for it (it cannot tell them apart); it has no register result, and the
+// caller waits for it (vm_wait_all) and synchronises before reading the
+// slots.
+__device__ inline void global_to_lds16(const void* src, unsigned lds_base) {
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(lds_base) : "memory", "m0");
+}
+
+template <int LTM, int LTN, bool AHEAD = false>
 __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* smem) {
     constexpr int TM = 1 << LTM, TN = 1 << LTN;
     constexpr int RMT = LTM >= LTN ? 8 : 4, RNT = LTM >= LTN ? 4 : 8;
@@ -1195,7 +1215,71 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
     // the step fit 32 bits: TK (small_lim - 1)^2 < 2^32.
     __shared__ int s_wide[2], s_big[2];
     const unsigned small_lim = 1u << ((32 - g.tk) / 2);
+    // element idx of a staged operand (the staging order is global-memory
+    // order) and its address in the operand's planes
+    auto a_pos = [&](int idx, i64 k0, int& i, int& k) -> i64 {
+        if (!g.a_t) {
+            k = idx & (TK - 1);
+            i = idx >> g.tk;
+            return (((p.b0 << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
+        }
+        i = idx & (TM - 1);
+        k = idx >> LTM;
+        return (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
+    };
+    auto b_pos = [&](int idx, i64 k0, int& j, int& k) -> i64 {
+        if (!g.b_t) {
+            j = idx & (TN - 1);
+            k = idx >> LTN;
+            return (((p.b0 << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
+        }
+        k = idx & (TK - 1);
+        j = idx >> g.tk;
+        return (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
+    };
+    [[maybe_unused]] const int nraw = 3 * (na + nb) / 4;  // 16-byte loads per step
+    [[maybe_unused]] unsigned char* raw = nullptr;
+    [[maybe_unused]] unsigned raw_base = 0;  // its LDS address
+    if constexpr (AHEAD) {
+        __shared__ __align__(16) unsigned char raw_lds[kCtRawSlots * 16];
+        raw = raw_lds;
+        raw_base = (unsigned)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)raw_lds;
+    }
+    // one step's operands into raw: load q of this thread fills 16-byte slot
+    // q * 256 + tid (a wave's 64 lanes fill 64 consecutive slots, as the
+    // global-to-LDS load writes them); 4 sizes or 2 counts per slot, each
+    // run contiguous in global memory (TK >= 4, rows of 2^tk or more)
+    [[maybe_unused]] auto read_ahead = [&](i64 k0) {
+        const int wave_base = tid & ~63;
+        for (int q = 0; q * 256 < nraw; q++) {
+            const int slot = q * 256 + tid;
+            if (q * 256 + wave_base >= nraw) break;  // uniform per wave: nraw is a multiple of 64
+            int r0, r1;
+            const void* src;
+            if (slot < na / 4) {
+                src = (const int*)g.A.p0 + a_pos(4 * slot, k0, r0, r1);
+            } else if (slot < 3 * na / 4) {
+                src = (const u64*)g.A.p1 + a_pos(2 * (slot - na / 4), k0, r0, r1);
+            } else if (slot < 3 * na / 4 + nb / 4) {
+                src = (const int*)g.B.p0 + b_pos(4 * (slot - 3 * na / 4), k0, r0, r1);
+            } else {
+                src = (const u64*)g.B.p1 + b_pos(2 * (slot - 3 * na / 4 - nb / 4), k0, r0, r1);
+            }
+            global_to_lds16(src, __builtin_amdgcn_readfirstlane(raw_base + (q * 256 + wave_base) * 16));
+        }
+    };
+    // the barrier that ends a step; with read-ahead it first waits for this
+    // thread's loads of the next step (its own wait, not the barrier's: the
+    // compiler does not see them)
+    auto end_step = [&]() {
+        if constexpr (AHEAD) vm_wait_all();
+        __syncthreads();
+    };
     if (tid == 0) s_wide[0] = s_wide[1] = s_big[0] = s_big[1] = 0;
+    if constexpr (AHEAD) {
+        read_ahead(p.kbeg);
+        vm_wait_all();
+    }
     __syncthreads();
     int step = 0;
     for (int kk = 0; kk < p.Kc; kk += TK, step ^= 1) {
@@ -1204,18 +1288,17 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
         unsigned hi_or = 0, lo_or = 0;
         for (int idx = tid; idx < na; idx += 256) {
             int i, k;
-            i64 addr;
-            if (!g.a_t) {
-                k = idx & (TK - 1);
-                i = idx >> g.tk;
-                addr = (((p.b0 << g.li) | (p.i0 + i)) << g.lk) | (k0 + k);
+            const i64 addr = a_pos(idx, k0, i, k);
+            int sz;
+            u64 c;
+            if constexpr (AHEAD) {
+                sz = ((const int*)raw)[idx];
+                c = ((const u64*)(raw + na * 4))[idx];
             } else {
-                i = idx & (TM - 1);
-                k = idx >> LTM;
-                addr = (((p.b0 << g.lk) | (k0 + k)) << g.li) | (p.i0 + i);
+                sz = ((const int*)g.A.p0)[addr];
+                c = ((const u64*)g.A.p1)[addr];
             }
-            An[k * TMP + i] = max(((const int*)g.A.p0)[addr], kCtNegInf);
-            const u64 c = ((const u64*)g.A.p1)[addr];
+            An[k * TMP + i] = max(sz, kCtNegInf);
             hi_or |= (unsigned)(c >> 32);
             lo_or |= (unsigned)c;
             Acl[k * TMP + i] = (unsigned)c;
@@ -1223,18 +1306,17 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
         }
         for (int idx = tid; idx < nb; idx += 256) {
             int j, k;
-            i64 addr;
-            if (!g.b_t) {
-                j = idx & (TN - 1);
-                k = idx >> LTN;
-                addr = (((p.b0 << g.lk) | (k0 + k)) << g.lj) | (p.j0 + j);
+            const i64 addr = b_pos(idx, k0, j, k);
+            int sz;
+            u64 c;
+            if constexpr (AHEAD) {
+                sz = ((const int*)(raw + na * 12))[idx];
+                c = ((const u64*)(raw + na * 12 + nb * 4))[idx];
             } else {
-                k = idx & (TK - 1);
-                j = idx >> g.tk;
-                addr = (((p.b0 << g.lj) | (p.j0 + j)) << g.lk) | (k0 + k);
+                sz = ((const int*)g.B.p0)[addr];
+                c = ((const u64*)g.B.p1)[addr];
             }
-            Bn[k * TNP + j] = max(((const int*)g.B.p0)[addr], kCtNegInf);
-            const u64 c = ((const u64*)g.B.p1)[addr];
+            Bn[k * TNP + j] = max(sz, kCtNegInf);
             hi_or |= (unsigned)(c >> 32);
             lo_or |= (unsigned)c;
             Bcl[k * TNP + j] = (unsigned)c;
@@ -1247,6 +1329,11 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
         }
         __syncthreads();
         const bool wide = s_wide[step] != 0, small = !wide && s_big[step] == 0;
+        // raw is free (every wave has staged from it): the next step's loads
+        // run during this one, and the barrier ending this step waits for them
+        if constexpr (AHEAD) {
+            if (kk + TK < p.Kc) read_ahead(k0 + TK);
+        }
         // pass 1: the step's largest size per output
         int m[RMT][RNT];
 #pragma unroll
@@ -1312,7 +1399,7 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
             for (int r = 0; r < RMT; r++)
 #pragma unroll
                 for (int c = 0; c < RNT; c++) accc[r][c] += part[r][c];
-            __syncthreads();
+            end_step();
             continue;
         }
         if (!wide) {  // every count of the step below 2^32: low words only
@@ -1332,7 +1419,7 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                         accc[r][c] += (u64)ac[r] * b;
                     }
             }
-            __syncthreads();
+            end_step();
             continue;
         }
         for (k = 0; k < TK; k++) {
@@ -1357,7 +1444,7 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
                     accc[r][c] = mad_u64_mod(accc[r][c], al[r], ah[r], eq ? bl[c] : 0u, eq ? bh[c] : 0u);
                 }
         }
-        __syncthreads();
+        end_step();
     }
     const i64 nout = (i64)1 << (g.lb + g.li + g.lj);
     const Planes dst = g.lsplit ? g.P : g.C;

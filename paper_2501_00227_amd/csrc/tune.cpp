@@ -83,7 +83,8 @@ const char* gemm_kernel_name(int dsr, const GemmShape& g, char* buf, size_t cap)
     else if (g.mode == GEMM_DOT) snprintf(buf, cap, "gemm_dot_kernel<%d>", dsr);
     else if (g.mfma == 2) snprintf(buf, cap, "gemm_mfma128_kernel<%d>", dsr);
     else if (g.mfma) snprintf(buf, cap, "gemm_mfma_kernel<%d>", dsr);
-    else if (g.rm == 8 && dsr == DSR_CTROP) snprintf(buf, cap, "gemm_ct_big_kernel<%d, %d>", g.ti, g.tj);
+    else if (g.rm == 8 && dsr == DSR_CTROP)
+        snprintf(buf, cap, "gemm_ct_big_kernel<%d, %d, %s>", g.ti, g.tj, ct_ahead_shape(g.ti, g.tj, g.tk) ? "true" : "false");
     else if (g.rm == 8) snprintf(buf, cap, "gemm_big_kernel<%d, %d, %d>", dsr, g.ti, g.tj);
     else snprintf(buf, cap, "gemm_kernel<%d, %d, %d>", dsr, g.rm, g.rn);
     return buf;
