@@ -1286,41 +1286,70 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
         const i64 k0 = p.kbeg + kk;
         if (tid == 0) s_wide[step ^ 1] = s_big[step ^ 1] = 0;
         unsigned hi_or = 0, lo_or = 0;
-        for (int idx = tid; idx < na; idx += 256) {
-            int i, k;
-            const i64 addr = a_pos(idx, k0, i, k);
-            int sz;
-            u64 c;
-            if constexpr (AHEAD) {
-                sz = ((const int*)raw)[idx];
-                c = ((const u64*)(raw + na * 4))[idx];
-            } else {
-                sz = ((const int*)g.A.p0)[addr];
-                c = ((const u64*)g.A.p1)[addr];
+        if constexpr (AHEAD) {
+            // four consecutive entries of raw per thread (one 16-byte read of
+            // sizes, two of counts); along the planes' fast index they are one
+            // 16-byte write per plane, across it four 4-byte writes
+            auto put4 = [&](int* n, unsigned* cl, unsigned* ch, int base, int stride, const unsigned char* rs,
+                            const unsigned char* rc, int g4) {
+                int sz[4];
+                unsigned cw[8];
+                lds_load4((const int*)rs + 4 * g4, sz);
+                lds_load4((const unsigned*)rc + 8 * g4, cw);
+                lds_load4((const unsigned*)rc + 8 * g4 + 4, cw + 4);
+                unsigned lo[4], hi[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    sz[u] = max(sz[u], kCtNegInf);
+                    lo[u] = cw[2 * u];
+                    hi[u] = cw[2 * u + 1];
+                    lo_or |= lo[u];
+                    hi_or |= hi[u];
+                }
+                if (stride == 1) {
+                    global_store4(n + base, sz);  // (a plain 16-byte store, here into LDS)
+                    global_store4(cl + base, lo);
+                    global_store4(ch + base, hi);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        n[base + u * stride] = sz[u];
+                        cl[base + u * stride] = lo[u];
+                        ch[base + u * stride] = hi[u];
+                    }
+                }
+            };
+            for (int g4 = tid; g4 < na / 4; g4 += 256) {
+                int i, k;
+                a_pos(4 * g4, k0, i, k);  // the first of the four: along k (A) or i (A transposed)
+                put4(An, Acl, Ach, k * TMP + i, g.a_t ? 1 : TMP, raw, raw + na * 4, g4);
             }
-            An[k * TMP + i] = max(sz, kCtNegInf);
-            hi_or |= (unsigned)(c >> 32);
-            lo_or |= (unsigned)c;
-            Acl[k * TMP + i] = (unsigned)c;
-            Ach[k * TMP + i] = (unsigned)(c >> 32);
-        }
-        for (int idx = tid; idx < nb; idx += 256) {
-            int j, k;
-            const i64 addr = b_pos(idx, k0, j, k);
-            int sz;
-            u64 c;
-            if constexpr (AHEAD) {
-                sz = ((const int*)(raw + na * 12))[idx];
-                c = ((const u64*)(raw + na * 12 + nb * 4))[idx];
-            } else {
-                sz = ((const int*)g.B.p0)[addr];
-                c = ((const u64*)g.B.p1)[addr];
+            for (int g4 = tid; g4 < nb / 4; g4 += 256) {
+                int j, k;
+                b_pos(4 * g4, k0, j, k);  // along j (B) or k (B transposed)
+                put4(Bn, Bcl, Bch, k * TNP + j, g.b_t ? TNP : 1, raw + na * 12, raw + na * 12 + nb * 4, g4);
             }
-            Bn[k * TNP + j] = max(sz, kCtNegInf);
-            hi_or |= (unsigned)(c >> 32);
-            lo_or |= (unsigned)c;
-            Bcl[k * TNP + j] = (unsigned)c;
-            Bch[k * TNP + j] = (unsigned)(c >> 32);
+        } else {
+            for (int idx = tid; idx < na; idx += 256) {
+                int i, k;
+                const i64 addr = a_pos(idx, k0, i, k);
+                An[k * TMP + i] = max(((const int*)g.A.p0)[addr], kCtNegInf);
+                const u64 c = ((const u64*)g.A.p1)[addr];
+                hi_or |= (unsigned)(c >> 32);
+                lo_or |= (unsigned)c;
+                Acl[k * TMP + i] = (unsigned)c;
+                Ach[k * TMP + i] = (unsigned)(c >> 32);
+            }
+            for (int idx = tid; idx < nb; idx += 256) {
+                int j, k;
+                const i64 addr = b_pos(idx, k0, j, k);
+                Bn[k * TNP + j] = max(((const int*)g.B.p0)[addr], kCtNegInf);
+                const u64 c = ((const u64*)g.B.p1)[addr];
+                hi_or |= (unsigned)(c >> 32);
+                lo_or |= (unsigned)c;
+                Bcl[k * TNP + j] = (unsigned)c;
+                Bch[k * TNP + j] = (unsigned)(c >> 32);
+            }
         }
         const bool any_hi = __any(hi_or != 0), any_big = __any(lo_or >= small_lim);
         if ((tid & 63) == 0) {
