@@ -978,6 +978,27 @@ __device__ inline void global_store4(V* p, const V* v) {
     *(uint4*)p = u;
 }
 
+// Four consecutive entries i..i+3 (i a multiple of 4) of an algebra's planes
+// by 16-byte stores.
+template <int D>
+__device__ inline void store4(const Planes& p, i64 i, const typename Alg<D>::V* v) {
+    using V = typename Alg<D>::V;
+    if constexpr (D == DSR_CTROP) {
+        const int n[4] = {v[0].n, v[1].n, v[2].n, v[3].n};
+        global_store4((int*)p.p0 + i, n);
+        uint4 c0, c1;
+        c0.x = (unsigned)v[0].c, c0.y = (unsigned)(v[0].c >> 32), c0.z = (unsigned)v[1].c, c0.w = (unsigned)(v[1].c >> 32);
+        c1.x = (unsigned)v[2].c, c1.y = (unsigned)(v[2].c >> 32), c1.z = (unsigned)v[3].c, c1.w = (unsigned)(v[3].c >> 32);
+        *(uint4*)((u64*)p.p1 + i) = c0;
+        *(uint4*)((u64*)p.p1 + i + 2) = c1;
+    } else if constexpr (sizeof(V) == 4) {
+        global_store4((V*)p.p0 + i, v);
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; u++) Alg<D>::store(p, i + u, v[u]);
+    }
+}
+
 template <int D>
 __device__ inline typename Alg<D>::V big_mac2(typename Alg<D>::V acc, typename Alg<D>::V a0, typename Alg<D>::V b0,
                                               typename Alg<D>::V a1, typename Alg<D>::V b1, const AlgebraParams& ap) {
@@ -1786,6 +1807,44 @@ __device__ void gemm_tile_thin(const GemmArgs& g, u64 tile, unsigned char* smem)
     float lmax = 0.0f, lmin = INFINITY;
     const ZDerived zd = z_derive<D>(tile, zo);
     const int rows = 1 << g.ti;
+    if constexpr (D != DSR_TOPK && D != DSR_TPOLY) {
+        if (g.lj >= 2) {
+            // N >= 4: N / 4 lanes per row, four consecutive outputs each, so
+            // that a wave's stores cover one contiguous run of rows (16-byte
+            // stores per lane; the lanes of a row read the same A entries)
+            const int llpr = g.lj - 2, rpp = 256 >> llpr;  // rows per pass
+            const int rl = threadIdx.x >> llpr, j0 = (threadIdx.x & ((1 << llpr) - 1)) * 4;
+            for (int r0 = 0; r0 < rows; r0 += rpp * RQ) {
+                V av[RQ][KMAX];
+#pragma unroll
+                for (int q = 0; q < RQ; q++) {
+                    const i64 i = p.i0 + r0 + q * rpp + rl;
+#pragma unroll
+                    for (int k = 0; k < KMAX; k++)
+                        if (k < K) {
+                            const i64 addr =
+                                g.a_t ? (((p.b0 << g.lk) | k) << g.li) | i : (((p.b0 << g.li) | i) << g.lk) | k;
+                            av[q][k] = A::prescale(A::load(g.A, addr), sA);
+                        }
+                }
+#pragma unroll
+                for (int q = 0; q < RQ; q++) {
+                    V acc[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        acc[u] = A::zero(g.ap);
+#pragma unroll
+                        for (int k = 0; k < KMAX; k++)
+                            if (k < K) acc[u] = A::add(acc[u], A::mul(av[q][k], Bs[(k << g.lj) | (j0 + u)], g.ap), g.ap);
+                        if constexpr (is_z<D>()) z_track(acc[u], lmax, lmin);
+                    }
+                    store4<D>(g.C, (((p.b0 << g.li) | (p.i0 + r0 + q * rpp + rl)) << g.lj) | j0, acc);
+                }
+            }
+            z_epilogue<D>(g, tile, zd, lmax, lmin);
+            return;
+        }
+    }
     for (int r0 = 0; r0 < rows; r0 += 256 * RQ) {
         V av[RQ][KMAX];
 #pragma unroll
