@@ -333,3 +333,40 @@ def test_counting_tropical_big_tiles_with_counts_around_2_14(ctx, ntwo, nthree):
     assert (r["size"], r["count_mod_2_64"]) == (want["size"], want["count"])
     rp = ctx.solve(net, plan, "counting_tropical", executor="persistent")
     assert (rp["size"], rp["count_mod_2_64"]) == (want["size"], want["count"])
+
+
+def test_thin_nodes_with_four_or_more_columns_every_algebra(ctx):
+    """A sliced plan of the 120-vertex graph has thin nodes (M >= 2^10,
+    N * K <= 32) with N >= 4, which store four consecutive outputs per lane:
+    every algebra against the oracle (per-node launches: the persistent
+    executor takes unsliced plans only)."""
+    executor = "stream"
+    g = gg.random_regular(120, 3, 0)
+    gw = g.with_weights(gg.dyadic_weights(g.nv, 0))
+    net, netw = tn.Net.from_graph(g), tn.Net.from_graph(gw)
+    kw = dict(method="treesa", ntrials=4, niters=10, sc_target=14, nslices=20, seed=0)
+    plan, planw = tn.Plan.create(net, **kw), tn.Plan.create(netw, **kw)
+    for sr in ("tropical_f32", "counting_tropical"):
+        thin = [d for d in plan.gemm_shapes(sr) if d["kind"] == "gemm_thin" and d["lj"] >= 2]
+        print(sr, "thin nodes with N >= 4:", [(d["lb"], d["li"], d["lj"], d["lk"]) for d in thin], flush=True)
+        assert thin
+    ct = oracle.eliminate(g, "counting_tropical")
+    kinds = set()
+
+    def run(n, p, sr, **k):
+        if executor == "stream":
+            r, recs = _solve_profiled(ctx, n, p, sr, **k)
+            kinds.update(x["kind"] for x in recs)
+            return r
+        return ctx.solve(n, p, sr, executor="persistent", **k)
+
+    r = run(net, plan, "counting_tropical")
+    assert (r["size"], r["count_mod_2_64"]) == (ct["size"], ct["count"] % 2 ** 64)
+    assert run(net, plan, "tropical_i32")["size"] == ct["size"]
+    assert run(netw, planw, "tropical_f32")["size"] == oracle.eliminate(gw, "tropical")["size"]
+    assert run(net, plan, "count_exact")["count"] == oracle.eliminate(g, "count")["count"]
+    want = oracle.eliminate(gw, "partition", beta=1.0)["log_z"]
+    assert abs(run(netw, planw, "partition_f32", beta=1.0)["log_z"] - want) <= 1e-5
+    assert abs(run(netw, planw, "partition_bf16", beta=1.0)["log_z"] - want) <= 0.05
+    if executor == "stream":
+        assert "gemm_thin" in kinds
