@@ -756,3 +756,31 @@ def test_count_top_rejects_fractional_weights_and_reports_infeasible():
     with pytest.raises(oracle.OracleError):
         oracle.brute_force_counting_max_k(g, 2)
     assert oracle.brute_force_counting_max_k(gg.path(2), 2, fixed={0: 1, 1: 1}) == {"top": float("-inf"), "counts": {}}
+
+
+def test_served_stream_stored_values_reproduce():
+    """tests/golden/k4_jobs.json: the stream it names, every job with n <= 130
+    present, the sample drawn only from the larger ones, and a few stored
+    values recomputed by the oracle (a check of the file, not a pin of the
+    oracle)."""
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "k4_jobs.json")))
+    mix = gg.job_mix(rec["njobs"], rec["seed"], *rec["n_range"])
+    small = {k for k, j in enumerate(mix) if j[0] <= rec["check_n"]}
+    large = [k for k, j in enumerate(mix) if j[0] > rec["check_n"]]
+    sample = set(rec["sample"]["jobs"])
+    assert sample <= set(large) and len(sample) == round(rec["sample"]["fraction"] * len(large))
+    assert {int(k) for k in rec["expected"]} == small | sample
+    checked = 0
+    for k in sorted(small, key=lambda k: mix[k][0])[:6]:
+        n, gseed, sr = mix[k]
+        g = gg.random_regular(n, 3, gseed)
+        want = rec["expected"][str(k)]
+        if sr == "tropical_i32":
+            assert oracle.eliminate(g, "tropical")["size"] == want
+        elif sr == "counting_tropical":
+            r = oracle.eliminate(g, "counting_tropical")
+            assert [r["size"], str(r["count"] % 2 ** 64)] == want
+        else:
+            assert abs(oracle.eliminate(g, "partition", 0.0)["log_z"] - want) <= 1e-12 * abs(want)
+        checked += 1
+    assert checked == 6
