@@ -381,6 +381,20 @@ typedef struct {
 tn_status tn_solve(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts,
                    tn_result* out);
 
+/* Checkpoint and resume of sliced contractions (Sec. 4.2: the contraction is
+ * the (+)-sum of its slices).  out = a (+) b for two results of one network,
+ * plan and options over disjoint slice ranges (tn_solve with
+ * opts->slice_begin / slice_end): a long run can store a tn_result (plain
+ * bytes, owned by the caller) with the next slice index and continue later.
+ * Host-side only; out may alias a or b.  Per semiring: tropical, the larger
+ * size; counting tropical, the larger size with its count, the counts added
+ * (mod 2^64) when the sizes are equal; exact count, the residues added per
+ * prime and the CRT value and its check prime recomputed (TN_EOVERFLOW as in
+ * tn_solve); partition function, Z_a + Z_b in float64 mantissa and exponent,
+ * z_range_log2 the larger.  seconds: the sum.  TN_EINVAL for NULL pointers,
+ * different semirings or primes, or another semiring. */
+tn_status tn_result_combine(const tn_result* a, const tn_result* b, tn_result* out);
+
 /* The contraction of tn_solve (per-node launches, opts->executor 0 or 1;
  * sliced plans too, opts->slice_begin/slice_end as there) for callers that
  * cannot allocate device memory: code under HIP graph capture, tight serving

@@ -145,6 +145,7 @@ SIGNATURES = [
     ("tn_net_flat_complexity", ctypes.c_int, [_VP, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double)]),
     ("tn_solve_opts_default", None, [_P(tn_solve_opts)]),
     ("tn_solve", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(tn_result)]),
+    ("tn_result_combine", ctypes.c_int, [_P(tn_result), _P(tn_result), _P(tn_result)]),
     ("tn_solve_noalloc", ctypes.c_int, [_VP, _VP, _VP, _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_batch", ctypes.c_int, [_VP, ctypes.c_int32, _P(_VP), _P(_VP), _P(tn_solve_opts), _P(tn_result)]),
     ("tn_solve_polynomial", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _P(ctypes.c_uint32), _P(ctypes.c_int32)]),
@@ -452,6 +453,15 @@ def decode(r: tn_result) -> Dict:
     return out
 
 
+def result_combine(a: tn_result, b: tn_result) -> tn_result:
+    """tn_result_combine: a (+) b for results of disjoint slice ranges (the
+    raw results of Context.solve_result; bytes(r) stores one, and
+    tn_result.from_buffer_copy reads it back)."""
+    out = tn_result()
+    _check(lib().tn_result_combine(ctypes.byref(a), ctypes.byref(b), ctypes.byref(out)))
+    return out
+
+
 # ---------------------------------------------------------------- autotuner --
 
 TUNE_SHAPE_FIELDS = ("mode", "tb", "ti", "tj", "tk", "rm", "rn", "lsplit", "mfma")
@@ -567,10 +577,15 @@ class Context:
 
     def solve(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None,
               executor="auto") -> Dict:
+        return decode(self.solve_result(net, plan, semiring, beta, primes, slices, executor))
+
+    def solve_result(self, net: Net, plan: Plan, semiring, beta: float = 0.0, primes=None, slices=None,
+                     executor="auto") -> tn_result:
+        """As solve, the raw tn_result (for result_combine and decode)."""
         o = solve_opts(semiring, beta, primes, slices, executor)
         r = tn_result()
         _check(lib().tn_solve(self.h, net.h, plan.h, ctypes.byref(o), ctypes.byref(r)))
-        return decode(r)
+        return r
 
     def tune_plan(self, plan: Plan, semiring, min_log2_ops: float = 20.0, reps: int = 3) -> int:
         """Tune the launch shapes of the plan's nodes with at least

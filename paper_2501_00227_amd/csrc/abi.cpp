@@ -451,6 +451,16 @@ void tn_solve_opts_default(tn_solve_opts* o) {
 
 static bool public_semiring(int s) { return s >= TN_TROPICAL_I32 && s <= TN_PARTITION_BF16; }
 
+tn_status tn_result_combine(const tn_result* a, const tn_result* b, tn_result* out) {
+    TN_GUARD_BEGIN
+    if (!a || !b || !out) return fail(TN_EINVAL, "NULL argument");
+    tn_result r;
+    tn_status st = combine_results(*a, *b, r);
+    if (st == TN_OK) *out = r;
+    return st;
+    TN_GUARD_END
+}
+
 tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_opts* o, tn_result* out) {
     TN_GUARD_BEGIN
     if (!c || !n || !p || !o || !out) return fail(TN_EINVAL, "NULL argument");

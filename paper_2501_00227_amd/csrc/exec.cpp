@@ -485,6 +485,96 @@ struct BigU {
     }
 };
 
+// The exact count from res.residues / res.primes (nresidues of them): Garner
+// over all primes but the last, which checks the value.
+static tn_status crt_decode(tn_result& res) {
+    const int np = res.nresidues;
+    BigU x, M;
+    x.d = {res.residues[0]};
+    M.d = {res.primes[0]};
+    for (int k = 1; k < np - 1; k++) {
+        uint32_t p = res.primes[k];
+        uint32_t xm = x.mod_small(p), mm = M.mod_small(p);
+        uint32_t t = (uint32_t)((uint64_t)((res.residues[k] + (uint64_t)p - xm) % p) * powmod(mm, p - 2, p) % p);
+        BigU add = M;
+        add.mul_small(t);
+        x.add(add);
+        M.mul_small(p);
+    }
+    x.trim();
+    if (x.d.size() > 16) return fail(TN_EOVERFLOW, "exact count needs more than 512 bits");
+    res.count_nlimbs = (int)x.d.size();
+    for (size_t k = 0; k < 16; k++) res.count_limbs[k] = k < x.d.size() ? x.d[k] : 0;
+    res.count_mod_2_64 = (x.d.size() > 0 ? (uint64_t)x.d[0] : 0) | (x.d.size() > 1 ? (uint64_t)x.d[1] << 32 : 0);
+    uint32_t pc = res.primes[np - 1];
+    if (x.mod_small(pc) != res.residues[np - 1])
+        return fail(TN_EOVERFLOW, "exact count exceeds the CRT range: the check prime disagrees");
+    return TN_OK;
+}
+
+tn_status combine_results(const tn_result& a, const tn_result& b, tn_result& out) {
+    if (a.semiring != b.semiring) return fail(TN_EINVAL, "results of different semirings");
+    tn_result r = a;
+    r.seconds = a.seconds + b.seconds;
+    switch (a.semiring) {
+    case TN_TROPICAL_I32:
+    case TN_COUNTING_TROPICAL: {
+        const bool ca = !a.size_is_neg_inf, cb = !b.size_is_neg_inf;
+        if (!ca || (cb && b.size_i32 > a.size_i32)) {
+            r.size_i32 = b.size_i32;
+            r.size_f32 = b.size_f32;
+            r.size_is_neg_inf = b.size_is_neg_inf;
+            r.count_mod_2_64 = b.count_mod_2_64;
+        } else if (ca && cb && b.size_i32 == a.size_i32) {
+            r.count_mod_2_64 = a.count_mod_2_64 + b.count_mod_2_64;  // mod 2^64
+        }
+        if (a.semiring == TN_TROPICAL_I32) r.count_mod_2_64 = 0;
+        break;
+    }
+    case TN_TROPICAL_F32:
+        if (b.size_f32 > a.size_f32 || a.size_is_neg_inf) {
+            r.size_f32 = b.size_f32;
+            r.size_i32 = b.size_i32;
+            r.size_is_neg_inf = b.size_is_neg_inf;
+        }
+        break;
+    case TN_COUNT_EXACT: {
+        if (a.nresidues != b.nresidues || a.nresidues < 2 || a.nresidues > 16)
+            return fail(TN_EINVAL, "exact counts with different prime sets");
+        for (int k = 0; k < a.nresidues; k++) {
+            if (a.primes[k] != b.primes[k] || a.primes[k] < 2) return fail(TN_EINVAL, "exact counts with different primes");
+            r.residues[k] = (uint32_t)(((uint64_t)a.residues[k] + b.residues[k]) % a.primes[k]);
+        }
+        tn_status st = crt_decode(r);
+        if (st != TN_OK) return st;
+        break;
+    }
+    case TN_PARTITION_F32:
+    case TN_PARTITION_BF16: {
+        // z = mant * 2^exp with mant in [1, 2) or 0
+        const bool za = a.z_mant == 0.0, zb = b.z_mant == 0.0;
+        if (za) {
+            r = b;
+            r.seconds = a.seconds + b.seconds;
+        } else if (!zb) {
+            const int64_t e = std::max(a.z_exp2, b.z_exp2);
+            const int64_t da = std::max<int64_t>(a.z_exp2 - e, -2000), db = std::max<int64_t>(b.z_exp2 - e, -2000);
+            int k = 0;
+            const double f = std::frexp(std::ldexp(a.z_mant, (int)da) + std::ldexp(b.z_mant, (int)db), &k);
+            r.z_mant = 2.0 * f;
+            r.z_exp2 = e + k - 1;
+            r.log_z = std::log(r.z_mant) + (double)r.z_exp2 * std::log(2.0);
+            r.z = r.z_exp2 > 1100 ? INFINITY : std::ldexp(r.z_mant, (int)std::max<int64_t>(r.z_exp2, -2000));
+        }
+        r.z_range_log2 = std::max(a.z_range_log2, b.z_range_log2);
+        break;
+    }
+    default: return fail(TN_EINVAL, "no combination for this semiring");
+    }
+    out = r;
+    return TN_OK;
+}
+
 tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& passes,
                         const std::vector<std::vector<unsigned char>>& acc, tn_result& res) {
     std::memset(&res, 0, sizeof res);
@@ -528,27 +618,8 @@ tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& pas
             res.residues[k] = (uint32_t)((uint64_t)xm * rinv % p);
             res.primes[k] = p;
         }
-        // Garner over p_1 .. p_{np-1}; p_np checks the result
-        BigU x, M;
-        x.d = {res.residues[0]};
-        M.d = {res.primes[0]};
-        for (int k = 1; k < np - 1; k++) {
-            uint32_t p = res.primes[k];
-            uint32_t xm = x.mod_small(p), mm = M.mod_small(p);
-            uint32_t t = (uint32_t)((uint64_t)((res.residues[k] + (uint64_t)p - xm) % p) * powmod(mm, p - 2, p) % p);
-            BigU add = M;
-            add.mul_small(t);
-            x.add(add);
-            M.mul_small(p);
-        }
-        x.trim();
-        if (x.d.size() > 16) return fail(TN_EOVERFLOW, "exact count needs more than 512 bits");
-        res.count_nlimbs = (int)x.d.size();
-        for (size_t k = 0; k < x.d.size(); k++) res.count_limbs[k] = x.d[k];
-        res.count_mod_2_64 = (x.d.size() > 0 ? (uint64_t)x.d[0] : 0) | (x.d.size() > 1 ? (uint64_t)x.d[1] << 32 : 0);
-        uint32_t pc = res.primes[np - 1];
-        if (x.mod_small(pc) != res.residues[np - 1])
-            return fail(TN_EOVERFLOW, "exact count exceeds the CRT range: the check prime disagrees");
+        tn_status st = crt_decode(res);
+        if (st != TN_OK) return st;
         break;
     }
     case TN_PARTITION_F32:

@@ -168,6 +168,8 @@ constexpr int kSemiringTPoly4 = 101;
 tn_status make_passes(const Net& net, const tn_solve_opts& o, std::vector<PassSpec>& passes);
 AlgebraParams algebra_params(int dsr, uint32_t prime, double beta, uint32_t xval = 1);
 // Decode the accumulators of all passes into the result struct.
+// out = a (+) b for results of disjoint slice ranges (tn_result_combine).
+tn_status combine_results(const tn_result& a, const tn_result& b, tn_result& out);
 tn_status decode_result(const tn_solve_opts& o, const std::vector<PassSpec>& passes,
                         const std::vector<std::vector<unsigned char>>& acc, tn_result& res);
 
