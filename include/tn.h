@@ -377,7 +377,10 @@ typedef struct {
 /* Contract the network along the plan on the context's stream and wait for
  * the root.  Errors: TN_EINVAL (semiring needs integer weights, plan built
  * for another network), TN_ENOMEM (allocator returned NULL), TN_EDEVICE,
- * TN_EOVERFLOW (exact count). */
+ * TN_EOVERFLOW (exact count).  With the environment variable TN_LOG naming a
+ * file, each call appends one JSON line to it (status, semiring, executor,
+ * the plan's tc/sc/rwc, slice range, wall time and the result's key
+ * values). */
 tn_status tn_solve(tn_ctx* ctx, const tn_net* net, const tn_plan* plan, const tn_solve_opts* opts,
                    tn_result* out);
 

@@ -6,6 +6,9 @@
 #include <new>
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
 #include "batch_host.h"
 #include "exec.h"
 
@@ -451,6 +454,46 @@ void tn_solve_opts_default(tn_solve_opts* o) {
 
 static bool public_semiring(int s) { return s >= TN_TROPICAL_I32 && s <= TN_PARTITION_BF16; }
 
+// TN_LOG=<path>: one JSON line per tn_solve appended to the file: the plan's
+// complexity, the slice range, the executor, the status, the result's key
+// values and the call's wall time (the variable is read at every call).
+static void log_solve(const tn_plan* p, const tn_solve_opts& o, bool persistent, tn_status st, const tn_result& r) {
+    const char* path = std::getenv("TN_LOG");
+    if (!path || !*path) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f,
+                 "{\"call\": \"tn_solve\", \"status\": %d, \"semiring\": %d, \"executor\": \"%s\", "
+                 "\"tc_log2\": %.4f, \"sc_log2\": %.4f, \"rwc_log2\": %.4f, \"nsliced\": %d, "
+                 "\"slice_begin\": %lld, \"slice_end\": %lld",
+                 (int)st, (int)o.semiring, persistent ? "persistent" : "per-node", p->plan.tc, p->plan.sc, p->plan.rwc,
+                 (int)p->plan.sliced.size(), (long long)o.slice_begin, (long long)o.slice_end);
+    if (st == TN_OK) {
+        std::fprintf(f, ", \"seconds\": %.6g", r.seconds);
+        switch (o.semiring) {
+        case TN_TROPICAL_I32: std::fprintf(f, ", \"size\": %d", r.size_i32); break;
+        case TN_TROPICAL_F32: std::fprintf(f, ", \"size\": %.9g", (double)r.size_f32); break;
+        case TN_COUNTING_TROPICAL:
+            std::fprintf(f, ", \"size\": %d, \"count_mod_2_64\": %llu", r.size_i32,
+                         (unsigned long long)r.count_mod_2_64);
+            break;
+        case TN_COUNT_EXACT:
+            std::fprintf(f, ", \"count_mod_2_64\": %llu, \"count_limbs\": %d", (unsigned long long)r.count_mod_2_64,
+                         r.count_nlimbs);
+            break;
+        case TN_PARTITION_F32:
+        case TN_PARTITION_BF16:
+            std::fprintf(f, ", \"log_z\": %.17g, \"z_range_log2\": %.6g", r.log_z, r.z_range_log2);
+            break;
+        default: break;
+        }
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+}
+
 tn_status tn_result_combine(const tn_result* a, const tn_result* b, tn_result* out) {
     TN_GUARD_BEGIN
     if (!a || !b || !out) return fail(TN_EINVAL, "NULL argument");
@@ -470,14 +513,18 @@ tn_status tn_solve(tn_ctx* c, const tn_net* n, const tn_plan* p, const tn_solve_
     bool persistent = o->executor == 2 || (o->executor == 0 && use_persistent(p->plan));
     if (o->executor == 2 && (!p->plan.sliced.empty() || o->slice_begin || o->slice_end))
         return fail(TN_EINVAL, "the persistent executor runs unsliced plans only");
+    tn_status st;
     if (persistent && o->slice_begin == 0 && o->slice_end == 0) {
         std::vector<BatchItem> items{{&n->net, &p->plan, *o}};
         std::vector<tn_result> res;
-        tn_status st = solve_batch_sync(c, items, res);
+        st = solve_batch_sync(c, items, res);
         if (!res.empty()) *out = res[0];
-        return st;
+    } else {
+        persistent = false;
+        st = solve_one(c, n->net, p->plan, *o, *out);
     }
-    return solve_one(c, n->net, p->plan, *o, *out);
+    log_solve(p, *o, persistent, st, *out);
+    return st;
     TN_GUARD_END
 }
 

@@ -201,3 +201,26 @@ def test_exact_count_range_and_overflow(ctx):
     r = ctx.solve(net, plan, "count_exact", primes=primes)
     assert r["count"] == 2 ** 40
     assert r["primes"] == primes and all(res == pow(2, 40, p) for res, p in zip(r["residues"], primes))
+
+
+def test_solve_log_lines(ctx, tmp_path, monkeypatch):
+    """TN_LOG: one JSON line per tn_solve with the plan's complexity, the
+    executor and the result's key values."""
+    path = tmp_path / "solves.jsonl"
+    monkeypatch.setenv("TN_LOG", str(path))
+    g = gg.random_regular(20, 3, 0)
+    net = tn.Net.from_graph(g)
+    plan = tn.Plan.create(net)
+    ref = oracle.brute_force(g, [0.5])
+    r1 = ctx.solve(net, plan, "counting_tropical", executor="stream")
+    r2 = ctx.solve(net, plan, "partition_f32", beta=0.5, executor="persistent")
+    monkeypatch.delenv("TN_LOG")
+    ctx.solve(net, plan, "tropical_i32")  # not logged
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert len(lines) == 2
+    tc, sc, rwc = plan.complexity()
+    assert lines[0]["status"] == 0 and lines[0]["executor"] == "per-node"
+    assert (lines[0]["size"], lines[0]["count_mod_2_64"]) == (r1["size"], r1["count_mod_2_64"]) == \
+        (ref["size_max"], ref["count_max"])
+    assert lines[1]["executor"] == "persistent" and abs(lines[1]["log_z"] - r2["log_z"]) < 1e-12
+    assert all(abs(x["tc_log2"] - tc) < 1e-3 and abs(x["sc_log2"] - sc) < 1e-3 for x in lines)
