@@ -1271,22 +1271,23 @@ __device__ void gemm_tile_ct_big(const GemmArgs& g, u64 tile, unsigned char* sme
     // global-to-LDS load writes them); 4 sizes or 2 counts per slot, each
     // run contiguous in global memory (TK >= 4, rows of 2^tk or more)
     [[maybe_unused]] auto read_ahead = [&](i64 k0) {
-        const int wave_base = tid & ~63;
-        for (int q = 0; q * 256 < nraw; q++) {
-            const int slot = q * 256 + tid;
-            if (q * 256 + wave_base >= nraw) break;  // uniform per wave: nraw is a multiple of 64
+        // the wave's first slot of each load is uniform (an SGPR), and so is
+        // the region it falls in: nraw and the region bounds are multiples of 64
+        const int lane = tid & 63;
+        for (int s0 = __builtin_amdgcn_readfirstlane(tid & ~63); s0 < nraw; s0 += 256) {
+            const int slot = s0 + lane;
             int r0, r1;
             const void* src;
-            if (slot < na / 4) {
+            if (s0 < na / 4) {
                 src = (const int*)g.A.p0 + a_pos(4 * slot, k0, r0, r1);
-            } else if (slot < 3 * na / 4) {
+            } else if (s0 < 3 * na / 4) {
                 src = (const u64*)g.A.p1 + a_pos(2 * (slot - na / 4), k0, r0, r1);
-            } else if (slot < 3 * na / 4 + nb / 4) {
+            } else if (s0 < 3 * na / 4 + nb / 4) {
                 src = (const int*)g.B.p0 + b_pos(4 * (slot - 3 * na / 4), k0, r0, r1);
             } else {
                 src = (const u64*)g.B.p1 + b_pos(2 * (slot - 3 * na / 4 - nb / 4), k0, r0, r1);
             }
-            global_to_lds16(src, __builtin_amdgcn_readfirstlane(raw_base + (q * 256 + wave_base) * 16));
+            global_to_lds16(src, raw_base + s0 * 16);
         }
     };
     // the barrier that ends a step; with read-ahead it first waits for this
