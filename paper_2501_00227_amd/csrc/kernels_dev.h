@@ -1195,7 +1195,8 @@ __device__ inline void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // One 16-byte global-to-LDS load: the wave's 64 lanes fill 64 consecutive
 // 16-byte slots from LDS address lds_base (wave-uniform).  Written in asm so
 // that the compiler does not make every LDS read of the other buffers wait
-// for it (it cannot tell them apart); it has no register result, and the
+// for it (it cannot tell them apart).  It has no register result (the data
+// goes to LDS; its address registers are read when it issues), and the
 // caller waits for it (vm_wait_all) and synchronises before reading the
 // slots.
 __device__ inline void global_to_lds16(const void* src, unsigned lds_base) {
